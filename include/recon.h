@@ -1,0 +1,159 @@
+/*
+ * recon.h -- C ABI of the MI355X (gfx950) iterative Fourier-space reconstruction
+ * with wide-angle redshift-space distortions of Burden, Percival & Howlett,
+ * "Reconstruction in Fourier space" (arXiv:1504.02591).
+ *
+ * Method, as implemented (section / equation names refer to the paper):
+ *   paint    -- galaxies and randoms are binned onto an N^3 mesh (Sec. 3.1, Sec. 3.2);
+ *               here with a deterministic integer fixed-point cloud-in-cell stencil.
+ *   solve    -- Gaussian smoothing S(k) = exp(-k^2 R^2/2) in Fourier space (Sec. 3.1),
+ *               galaxy and random densities smoothed separately, overdensity
+ *               delta = (rho - rho_bar)/rho_bar (Sec. 2) formed against the randoms and
+ *               zeroed outside a binary survey mask (Sec. 3.2), then the starting
+ *               displacement: the Zel'dovich solve Psi(k) = i k delta(k)/(b k^2)
+ *               (Sec. 2, eq. Zeldovich) or the approximate RSD-corrected starts of
+ *               eq. (approx1) / eq. (approx2).
+ *   iterate  -- the iterative removal of the non-parallel RSD term (Sec. 5.1,
+ *               eq. iterative): D_{n+1} = D_s + f div[(Psi_n . r) r] with r the unit
+ *               vector from the observer to each cell, Psi_{n+1} = i k D_{n+1}/(b k^2);
+ *               the fixed point solves eq. (Nusser) with the RSD term scaled by
+ *               beta = f/b.
+ *   shift    -- galaxies and randoms are moved back along the displacement
+ *               (Sec. 1): -Psi - f (Psi . r) r for galaxies, -Psi for randoms.
+ *
+ * Conventions: grid node (ix,iy,iz) sits at box_origin + (L/N)(ix,iy,iz); real fields
+ * are [iz][iy][ix] float32 (x fastest); the box is periodic.  Positions are float32
+ * [n][3] (x,y,z); weights float32 [n] with 0 <= w < 64 (NULL means 1).
+ *
+ * Ownership: every pointer argument named "device" is device memory owned by the
+ * caller, who keeps it alive until the plan's stream has completed the call.  The
+ * workspace passed to recon_plan is caller-owned device memory that the plan uses
+ * exclusively until recon_destroy.  The plan owns only host-side metadata.
+ *
+ * Ordering: calls are asynchronous on the plan's stream except where noted (the
+ * solve reads totals back once; iterate reads one convergence norm per pass).
+ * The state machine is paint(GAL) [, paint(RAN)] -> solve -> iterate (repeatable)
+ * -> shift / get_psi; recon_set_delta replaces the paint steps.
+ *
+ * Errors: every call returns RECON_OK (0), a positive warning, or a negative error
+ * code; recon_strerror names the code and recon_last_error returns the plan's last
+ * message.  No C++ exception crosses this interface.
+ */
+#ifndef RECON_H
+#define RECON_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* return codes */
+#define RECON_OK 0
+#define RECON_NOTCONVERGED 1   /* warning: max_iter reached before the tolerance */
+#define RECON_EINVAL (-1)      /* invalid argument or invalid input data (NaN position, bad weight, ...) */
+#define RECON_ENOMEM (-2)      /* workspace too small */
+#define RECON_EDEVICE (-3)     /* a HIP runtime call or kernel launch failed */
+#define RECON_ESTATE (-4)      /* call out of order */
+#define RECON_EDIVERGED (-5)   /* eps non-finite, rising on two consecutive passes, or ||Psi_n|| > 100 ||Psi_1|| */
+
+/* catalogue selector */
+#define RECON_GAL 0
+#define RECON_RAN 1
+
+/* starting displacement */
+#define RECON_START_PLAIN 0    /* Psi_0 from the redshift-space overdensity (Sec. 5.2, first start) */
+#define RECON_START_FFTA1 1    /* eq. (approx1):  Psi_p - beta/(1+beta) (Psi_p . r) r            */
+#define RECON_START_FFTA2 2    /* eq. (approx2):  Psi_p - 3 beta/(7+3 beta) (Psi_p . r) r        */
+#define RECON_START_LEARNED 3  /* Psi_p + Delta r with Delta predicted by a small 3D CNN        */
+
+/* plan flags */
+#define RECON_NO_RANDOMS 1u        /* mean-density mode: delta = rho/rho_bar - 1, no randoms, no mask */
+#define RECON_KEEP_DELTA 2u        /* keep the smoothed overdensity delta_s in configuration space     */
+#define RECON_START_BUFFERS 4u     /* allocate the start-correction field (needed by FFTA / learned)   */
+
+/* paint flags */
+#define RECON_PAINT_ACCUMULATE 1u  /* add to the grid instead of replacing it */
+
+typedef struct recon_plan_s recon_plan_t;
+
+typedef struct {
+  int32_t n;               /* cells per side, power of two in [8, 1024]                                  */
+  int32_t batch;           /* independent realisations sharing this geometry (>= 1)                      */
+  double box_len;          /* L > 0 [Mpc/h]                                                              */
+  double box_origin[3];    /* lower corner of the periodic box                                           */
+  double observer[3];      /* observer position, same frame (Sec. 3.1: r points away from the observer)  */
+  double bias;             /* b > 0 (Sec. 3.2: delta_g = b delta)                                         */
+  double growth;           /* f >= 0 (eq. Nusser)                                                        */
+  double smooth_r;         /* R >= 0 [Mpc/h] (Sec. 3.1 smoothing)                                        */
+  double mask_tau;         /* mask threshold as a fraction of the mean 27-cell random sum (>= 0)          */
+  uint32_t flags;          /* RECON_NO_RANDOMS | RECON_KEEP_DELTA | RECON_START_BUFFERS                  */
+} recon_params_t;
+
+/* Device bytes the workspace must provide for these parameters (0 if the parameters are invalid). */
+size_t recon_workspace_bytes(const recon_params_t* params);
+
+/* Create a plan.  workspace: device memory of at least recon_workspace_bytes bytes, 256-byte aligned,
+ * caller-owned.  stream: a hipStream_t (NULL = default stream).  Returns EINVAL for invalid parameters,
+ * ENOMEM when workspace_bytes is too small. */
+int recon_plan(recon_plan_t** out, const recon_params_t* params, void* workspace, size_t workspace_bytes,
+               void* stream);
+
+/* Deposit a catalogue (Sec. 3.1 / 3.2 binning; cloud-in-cell in integer fixed point, units 2^-32 of
+ * weight, periodic wrap).  pos: device float32 [n][3]; w: device float32 [n] or NULL; offsets: device
+ * int64 [batch+1] giving each realisation's object range (NULL when batch == 1).  Objects with a
+ * non-finite position, a position more than 2^30 cells from the box, or a weight outside [0, 64) are
+ * skipped and make the next recon_solve return EINVAL.  The grid is bit-identical for any object order. */
+int recon_paint(recon_plan_t* plan, int which, const float* pos, const float* w, int64_t n,
+                const int64_t* offsets, uint32_t flags);
+
+/* Totals, smoothing, mask, overdensity and its spectrum D_s, and the starting displacement (a
+ * synchronisation point: totals are read back).  start: RECON_START_*; net: device pointer to the
+ * learned-start network parameters (RECON_START_LEARNED only, layout in recon_cnn.h), else NULL.
+ * EINVAL when a painted object was invalid or the total random weight is zero. */
+int recon_solve(recon_plan_t* plan, int start, const void* net);
+
+/* Run correction passes (Sec. 5.1) until eps_n = ||Psi_n - Psi_{n-1}|| / ||Psi_n|| <= tol for every
+ * realisation, or max_iter passes in this call.  tol <= 0 runs exactly max_iter passes.  Synchronises
+ * once per pass.  iters_out: host int32 [batch], total passes of each realisation (may be NULL);
+ * eps_out: host double [batch * max_iter], eps of each pass of this call, NaN-padded (may be NULL).
+ * Returns OK, NOTCONVERGED, or EDIVERGED.  May be called again to continue. */
+int recon_iterate(recon_plan_t* plan, int max_iter, double tol, int32_t* iters_out, double* eps_out);
+
+/* Move a catalogue back along the displacement (Sec. 1).  disp_out: device float32 [n][3]
+ * (galaxies: -Psi - f (Psi.r) r, randoms: -Psi, Psi interpolated with the deposit's stencil);
+ * pos_out: device float32 [n][3] receiving pos + disp, or NULL. */
+int recon_shift(recon_plan_t* plan, int which, const float* pos, int64_t n, const int64_t* offsets,
+                float* disp_out, float* pos_out);
+
+/* Copy the current displacement Psi (device float32 [batch][3][N^3], [iz][iy][ix]). */
+int recon_get_psi(recon_plan_t* plan, float* psi_out);
+
+/* Copy a deposit grid (device int64 [batch][N^3], units 2^-32 of weight). */
+int recon_get_grid(recon_plan_t* plan, int which, int64_t* out);
+
+/* Copy the smoothed masked overdensity delta_s (device float32 [batch][N^3]); needs RECON_KEEP_DELTA. */
+int recon_get_delta(recon_plan_t* plan, float* out);
+
+/* Test hook: supply delta_s directly (device float32 [batch][N^3]), replacing paint and smoothing. */
+int recon_set_delta(recon_plan_t* plan, const float* delta_s);
+
+/* Instrumentation (not part of the method): while enabled, every kernel launched by the plan is
+ * bracketed by HIP events on the plan's stream.  recon_profile_stop synchronises the stream, writes the
+ * launch count and summed duration (ms) of each kernel kind into counts[k] / total_ms[k] for
+ * k < min(cap, kinds), clears the record and returns the number of kernel kinds; names come from
+ * recon_profile_kernel_name(k). */
+int recon_profile_start(recon_plan_t* plan);
+int recon_profile_stop(recon_plan_t* plan, int32_t* counts, double* total_ms, int cap);
+const char* recon_profile_kernel_name(int kind);
+
+void recon_destroy(recon_plan_t* plan);
+const char* recon_strerror(int code);
+const char* recon_last_error(const recon_plan_t* plan);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RECON_H */

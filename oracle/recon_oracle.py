@@ -49,6 +49,9 @@ R10 Line of sight r = (x - O)/|x - O| per grid node, r = 0 at the observer.
 R11 The correction term is not re-smoothed (delta_s is already smoothed).
 R12 Convergence: eps_n = ||Psi_n - Psi_{n-1}|| / ||Psi_n|| over all cells and the
     three components; the pass count n counts correction passes (n = 0 is the start).
+    Divergence: eps_n non-finite, eps rising on two consecutive passes, or
+    ||Psi_n|| above 100 ||Psi_1|| (the iteration only converges for beta mu^2 < 1,
+    eq. (itpsi) and the remark after it).
 R13 Shift: galaxies move by -Psi - f (Psi.r) r, randoms by -Psi, with Psi
     interpolated to the object by the same CIC stencil.
 R14 FFTA starts with beta in place of f: c = beta/(1+beta) (eq. approx1) or
@@ -56,8 +59,13 @@ R14 FFTA starts with beta in place of f: c = beta/(1+beta) (eq. approx1) or
 """
 from __future__ import annotations
 
+import os
+
 import numpy as np
 import scipy.fft as sfft
+
+# FFT threads: the host cores this process may use, capped at 16 (one GPU's share of a box)
+WORKERS = int(os.environ.get("ORACLE_WORKERS", min(16, len(os.sched_getaffinity(0)))))
 
 FRAC_BITS = 16          # per-axis CIC fraction quantum is 2^-16
 WEIGHT_BITS = 32        # weights are stored as integers in units of 2^-32
@@ -113,12 +121,12 @@ def wavenumbers(n, box_len):
 
 def fwd(f):
     """Forward real-to-complex transform, exp(-i k.x) convention (R1)."""
-    return sfft.rfftn(np.asarray(f, dtype=np.float64), axes=(0, 1, 2), workers=-1)
+    return sfft.rfftn(np.asarray(f, dtype=np.float64), axes=(0, 1, 2), workers=WORKERS)
 
 
 def inv(fk, n):
     """Inverse complex-to-real transform with the 1/N^3 factor (R1)."""
-    return sfft.irfftn(fk, s=(n, n, n), axes=(0, 1, 2), workers=-1)
+    return sfft.irfftn(fk, s=(n, n, n), axes=(0, 1, 2), workers=WORKERS)
 
 
 # ---------------------------------------------------------------------------
@@ -341,6 +349,7 @@ def reconstruct_field(delta_s, box_len, origin, observer, bias, growth,
     eps_hist = []
     passes = 0
     diverged = False
+    norm1 = None
     dk = d_s
     limit = n_passes if n_passes is not None else max_iter
     while passes < limit:
@@ -353,10 +362,14 @@ def reconstruct_field(delta_s, box_len, origin, observer, bias, growth,
         psi = psi_new
         passes += 1
         eps_hist.append(float(eps))
+        norm1 = den if norm1 is None else norm1
         if not np.isfinite(eps):
             diverged = True
             break
         if len(eps_hist) >= 3 and eps_hist[-1] > eps_hist[-2] > eps_hist[-3]:
+            diverged = True
+            break
+        if passes >= 2 and den > 100.0 * norm1:
             diverged = True
             break
         if n_passes is None and tol is not None and eps <= tol:

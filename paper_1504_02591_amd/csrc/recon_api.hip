@@ -1,0 +1,866 @@
+// Host orchestration and C ABI of the reconstruction library.
+//
+// One plan owns a caller-provided device workspace carved into the buffers of
+// the pipeline; all kernels run on the plan's stream.  The iteration keeps
+// three complex work arrays (W0..W2) that cycle through
+//   state X (x-inverse output of P_n)  --y_fanout-->  state Y (three displacement
+//   spectra, inverse-transformed along y)  --z_iter, y_fanin, x_iter-->  state X,
+// plus D_s and D_n.  Convergence norms come back as one small device-to-host
+// copy per pass.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/recon.h"
+#include "recon_kernels.hpp"
+
+using namespace recon;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+enum PlanState { ST_EMPTY = 0, ST_PAINTED = 1, ST_DELTA = 2, ST_SOLVED = 3 };
+
+struct Layout {
+  size_t grid_g = 0, grid_r = 0, mask = 0, w0 = 0, w1 = 0, w2 = 0, ds = 0, dn = 0, psi = 0, delta = 0,
+         corr = 0, tw = 0, partials = 0, red = 0, totals = 0, thr = 0, dscal = 0, act = 0, err = 0, total = 0;
+};
+
+bool valid_params(const recon_params_t* p, std::string* why) {
+  auto fail = [&](const char* m) { if (why) *why = m; return false; };
+  if (!p) return fail("params is NULL");
+  if (p->n < 8 || p->n > 1024 || (p->n & (p->n - 1))) return fail("n must be a power of two in [8, 1024]");
+  if (p->batch < 1) return fail("batch must be >= 1");
+  if (!(p->box_len > 0.0) || !std::isfinite(p->box_len)) return fail("box_len must be positive and finite");
+  for (int a = 0; a < 3; ++a)
+    if (!std::isfinite(p->box_origin[a]) || !std::isfinite(p->observer[a])) return fail("origin/observer must be finite");
+  if (!(p->bias > 0.0) || !std::isfinite(p->bias)) return fail("bias must be positive and finite");
+  if (!(p->growth >= 0.0) || !std::isfinite(p->growth)) return fail("growth must be >= 0 and finite");
+  if (!(p->smooth_r >= 0.0) || !std::isfinite(p->smooth_r)) return fail("smooth_r must be >= 0 and finite");
+  if (!(p->mask_tau >= 0.0) || !std::isfinite(p->mask_tau)) return fail("mask_tau must be >= 0 and finite");
+  if (p->flags & ~(RECON_NO_RANDOMS | RECON_KEEP_DELTA | RECON_START_BUFFERS)) return fail("unknown flag");
+  return true;
+}
+
+long long max_partial_blocks(int n) {
+  // x passes use 8 rows per block; z passes use 2*wz columns per block
+  long long xb = (long long)(n / 2 + 1) * n / 8;
+  long long zb = (long long)n * n / 2;   // upper bound (wz >= 1)
+  return xb > zb ? xb : zb;
+}
+
+Layout make_layout(const recon_params_t* p) {
+  Layout L;
+  const long long n = p->n, b = p->batch;
+  const long long n3 = n * n * n, cn = (n / 2 + 1) * n * n;
+  const bool randoms = !(p->flags & RECON_NO_RANDOMS);
+  size_t off = 0;
+  auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return o; };
+  L.grid_g = take(b * n3 * 8);
+  L.grid_r = randoms ? take(b * n3 * 8) : 0;
+  L.mask = randoms ? take(b * n3) : 0;
+  L.w0 = take(b * cn * 8);
+  L.w1 = take(b * cn * 8);
+  L.w2 = take(b * cn * 8);
+  L.ds = take(b * cn * 8);
+  L.dn = take(b * cn * 8);
+  L.psi = take(b * 3 * n3 * 4);
+  L.delta = (p->flags & RECON_KEEP_DELTA) ? take(b * n3 * 4) : 0;
+  L.corr = (p->flags & RECON_START_BUFFERS) ? take(b * n3 * 4) : 0;
+  L.tw = take(n * 8);
+  L.partials = take((size_t)b * max_partial_blocks((int)n) * 2 * 8);
+  L.red = take(b * 2 * 8 * 2);
+  L.totals = take(b * 3 * 8);
+  L.thr = take(b * 8);
+  L.dscal = take(b * sizeof(DeltaScal));
+  L.act = take(b * 4 * 4);
+  L.err = take(16);
+  L.total = off;
+  return L;
+}
+
+// Per-kernel event timing on the plan's stream (instrumentation; off by default).
+enum KernelId {
+  KP_FILL, KP_PAINT, KP_TOTALS, KP_MASK, KP_Z_FWD_GRID, KP_Y_FWD, KP_X_SMOOTH, KP_Y_INV, KP_Z_DELTA, KP_X_START,
+  KP_Z_FWD_REAL, KP_Y_FANOUT, KP_Z_ITER, KP_Y_FANIN, KP_X_ITER, KP_REDUCE, KP_Z_FINAL, KP_SHIFT, KP_COUNT
+};
+const char* const kKernelNames[KP_COUNT] = {
+    "fill", "paint", "totals", "mask", "z_fwd_grid", "y_fwd", "x_smooth", "y_inv", "z_delta", "x_start",
+    "z_fwd_real", "y_fanout", "z_iter", "y_fanin", "x_iter", "reduce", "z_final", "shift"};
+
+struct Profiler {
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  std::vector<std::pair<int, size_t>> recs;
+};
+
+}  // namespace
+
+struct recon_plan_s {
+  recon_params_t p{};
+  hipStream_t stream = nullptr;
+  char* ws = nullptr;
+  Layout L;
+  int n = 0, batch = 1;
+  long long n3 = 0, cn = 0;
+  bool randoms = true;
+  long long *grid_g = nullptr, *grid_r = nullptr;
+  unsigned char* mask = nullptr;
+  float2 *w0 = nullptr, *w1 = nullptr, *w2 = nullptr, *ds = nullptr, *dn = nullptr, *tw = nullptr;
+  float *psi = nullptr, *delta = nullptr, *corr = nullptr;
+  double *partials = nullptr, *red = nullptr;
+  unsigned long long* totals = nullptr;
+  long long* thr = nullptr;
+  DeltaScal* dscal = nullptr;
+  int *act_fan = nullptr, *act_fin = nullptr, *act_it = nullptr, *err = nullptr;
+  Geo geo{};
+  CicGeo cic{};
+  bool painted_g = false, painted_r = false;
+  int state = ST_EMPTY;
+  int start = RECON_START_PLAIN;
+  std::vector<int> passes, done, psi_valid, st_y, pending1, diverged;
+  std::vector<double> num0, den0, s1, s2, norm1;
+  std::vector<std::vector<double>> hist;
+  std::vector<int> h_fan, h_fin, h_it;
+  std::vector<double> h_red, h_red2;
+  std::string msg;
+  Profiler prof;
+  ~recon_plan_s() {
+    for (hipEvent_t e : prof.pool) (void)hipEventDestroy(e);
+  }
+};
+
+namespace {
+
+int fail(recon_plan_t* pl, int code, const std::string& m) {
+  if (pl) pl->msg = m;
+  return code;
+}
+
+int check_launch(recon_plan_t* pl, const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(pl, RECON_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+  return RECON_OK;
+}
+
+struct ProfScope {
+  recon_plan_t* pl;
+  size_t idx = 0;
+  bool live = false;
+  ProfScope(recon_plan_t* p, int id) : pl(p) {
+    Profiler& pr = pl->prof;
+    if (!pr.on) return;
+    while (pr.pool.size() < pr.used + 2) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return;
+      pr.pool.push_back(e);
+    }
+    idx = pr.used;
+    pr.used += 2;
+    (void)hipEventRecord(pr.pool[idx], pl->stream);
+    pr.recs.emplace_back(id, idx);
+    live = true;
+  }
+  ~ProfScope() {
+    if (live) (void)hipEventRecord(pl->prof.pool[idx + 1], pl->stream);
+  }
+};
+#define PROF_CAT2(a, b) a##b
+#define PROF_CAT(a, b) PROF_CAT2(a, b)
+#define PROF(pl, id) ProfScope PROF_CAT(prof_scope_, __LINE__)(pl, id)
+
+#define RECON_TRY(expr)          \
+  do {                           \
+    int rc_ = (expr);            \
+    if (rc_ != RECON_OK) return rc_; \
+  } while (0)
+
+#define HIP_TRY(pl, call)                                                           \
+  do {                                                                              \
+    hipError_t e_ = (call);                                                         \
+    if (e_ != hipSuccess) return fail(pl, RECON_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// Per-size launchers
+// ---------------------------------------------------------------------------
+struct Ops {
+  int (*setup)(recon_plan_t*);             // z/y/x/y/z/y/x chain from the painted grids to D_s and state X
+  int (*setup_delta)(recon_plan_t*, const float*);
+  int (*fanout)(recon_plan_t*, const int*);
+  int (*ziter)(recon_plan_t*, int mode, const int*);
+  int (*fanin_xiter)(recon_plan_t*, bool first, const int*);
+  int (*zfinal)(recon_plan_t*, float* psi, float* u, bool cross, const int*);
+  int nb_x, nb_z;
+};
+
+template <int N>
+struct SizeOps {
+  static constexpr int WZ = wz<N>(), WY = wy<N>(), WX = wx<N>();
+  static dim3 gz(const recon_plan_t* pl) { return dim3(N * (N / (2 * WZ)), pl->batch); }
+  static dim3 gy(const recon_plan_t* pl) { return dim3((N / 2 + 1) * (N / WY), pl->batch); }
+  static dim3 gx(const recon_plan_t* pl) { return dim3((N / 2 + 1) * N / WX, pl->batch); }
+
+  static int setup(recon_plan_t* pl) {
+    hipStream_t s = pl->stream;
+    const dim3 blk(kThreads);
+    if (pl->randoms) {
+      {
+        PROF(pl, KP_Z_FWD_GRID);
+        k_z_fwd_grid<N, 2><<<gz(pl), blk, 0, s>>>(pl->grid_g, pl->grid_r, pl->w0, pl->w1, pl->tw);
+      }
+      RECON_TRY(check_launch(pl, "z forward (grids)"));
+      {
+        PROF(pl, KP_Y_FWD);
+        k_y_plain<N, 2, false><<<gy(pl), blk, 0, s>>>(pl->w0, pl->w1, pl->tw);
+      }
+      RECON_TRY(check_launch(pl, "y forward"));
+      {
+        PROF(pl, KP_X_SMOOTH);
+        k_x_smooth<N, 2><<<gx(pl), blk, 0, s>>>(pl->w0, pl->w1, pl->geo, pl->tw);
+      }
+      RECON_TRY(check_launch(pl, "x smooth"));
+      {
+        PROF(pl, KP_Y_INV);
+        k_y_plain<N, 2, true><<<gy(pl), blk, 0, s>>>(pl->w0, pl->w1, pl->tw);
+      }
+      RECON_TRY(check_launch(pl, "y inverse"));
+      {
+        PROF(pl, KP_Z_DELTA);
+        k_z_delta<N, 2><<<gz(pl), blk, 0, s>>>(pl->w0, pl->w1, pl->mask, pl->dscal, pl->delta, pl->tw);
+      }
+      RECON_TRY(check_launch(pl, "z delta"));
+    } else {
+      {
+        PROF(pl, KP_Z_FWD_GRID);
+        k_z_fwd_grid<N, 1><<<gz(pl), blk, 0, s>>>(pl->grid_g, nullptr, pl->w0, nullptr, pl->tw);
+      }
+      RECON_TRY(check_launch(pl, "z forward (grid)"));
+      {
+        PROF(pl, KP_Y_FWD);
+        k_y_plain<N, 1, false><<<gy(pl), blk, 0, s>>>(pl->w0, nullptr, pl->tw);
+      }
+      RECON_TRY(check_launch(pl, "y forward"));
+      {
+        PROF(pl, KP_X_SMOOTH);
+        k_x_smooth<N, 1><<<gx(pl), blk, 0, s>>>(pl->w0, nullptr, pl->geo, pl->tw);
+      }
+      RECON_TRY(check_launch(pl, "x smooth"));
+      {
+        PROF(pl, KP_Y_INV);
+        k_y_plain<N, 1, true><<<gy(pl), blk, 0, s>>>(pl->w0, nullptr, pl->tw);
+      }
+      RECON_TRY(check_launch(pl, "y inverse"));
+      {
+        PROF(pl, KP_Z_DELTA);
+        k_z_delta<N, 1><<<gz(pl), blk, 0, s>>>(pl->w0, nullptr, nullptr, pl->dscal, pl->delta, pl->tw);
+      }
+      RECON_TRY(check_launch(pl, "z delta"));
+    }
+    return finish_start(pl);
+  }
+
+  static int finish_start(recon_plan_t* pl) {
+    hipStream_t s = pl->stream;
+    {
+      PROF(pl, KP_Y_FWD);
+      k_y_plain<N, 1, false><<<gy(pl), dim3(kThreads), 0, s>>>(pl->w0, nullptr, pl->tw);
+    }
+    RECON_TRY(check_launch(pl, "y forward (delta)"));
+    {
+      PROF(pl, KP_X_START);
+      k_x_start<N><<<gx(pl), dim3(kThreads), 0, s>>>(pl->w0, pl->w1, pl->ds, pl->geo, pl->tw);
+    }
+    return check_launch(pl, "x start");
+  }
+
+  static int setup_delta(recon_plan_t* pl, const float* d) {
+    {
+      PROF(pl, KP_Z_FWD_REAL);
+      k_z_fwd_real<N><<<gz(pl), dim3(kThreads), 0, pl->stream>>>(d, pl->w0, pl->tw);
+    }
+    RECON_TRY(check_launch(pl, "z forward (delta)"));
+    return finish_start(pl);
+  }
+
+  static int fanout(recon_plan_t* pl, const int* act) {
+    {
+      PROF(pl, KP_Y_FANOUT);
+      k_y_fanout<N><<<gy(pl), dim3(kThreads), 0, pl->stream>>>(pl->w0, pl->w1, pl->w2, pl->geo, act, pl->tw);
+    }
+    return check_launch(pl, "y fan-out");
+  }
+
+  static int ziter(recon_plan_t* pl, int mode, const int* act) {
+    hipStream_t s = pl->stream;
+    {
+      PROF(pl, KP_Z_ITER);
+      if (mode == ZI_FFTA)
+        k_z_iter<N, ZI_FFTA><<<gz(pl), dim3(kThreads), 0, s>>>(pl->w0, pl->w1, pl->w2, pl->geo, pl->corr,
+                                                               pl->partials, act, pl->tw);
+      else if (mode == ZI_LEARNED)
+        k_z_iter<N, ZI_LEARNED><<<gz(pl), dim3(kThreads), 0, s>>>(pl->w0, pl->w1, pl->w2, pl->geo, pl->corr,
+                                                                  pl->partials, act, pl->tw);
+      else
+        k_z_iter<N, ZI_PLAIN><<<gz(pl), dim3(kThreads), 0, s>>>(pl->w0, pl->w1, pl->w2, pl->geo, nullptr,
+                                                                nullptr, act, pl->tw);
+    }
+    RECON_TRY(check_launch(pl, "z iteration"));
+    if (mode != ZI_PLAIN) {
+      {
+        PROF(pl, KP_REDUCE);
+        k_reduce_pairs<<<pl->batch, kThreads, 0, s>>>(pl->partials, (int)gz(pl).x, pl->red + 2 * pl->batch);
+      }
+      RECON_TRY(check_launch(pl, "reduce (start sums)"));
+    }
+    return RECON_OK;
+  }
+
+  static int fanin_xiter(recon_plan_t* pl, bool first, const int* act) {
+    hipStream_t s = pl->stream;
+    {
+      PROF(pl, KP_Y_FANIN);
+      k_y_fanin<N><<<gy(pl), dim3(kThreads), 0, s>>>(pl->w0, pl->w1, pl->w2, pl->geo, act, pl->tw);
+    }
+    RECON_TRY(check_launch(pl, "y fan-in"));
+    {
+      PROF(pl, KP_X_ITER);
+      k_x_iter<N><<<gx(pl), dim3(kThreads), 0, s>>>(pl->w0, pl->w1, pl->ds, first ? pl->ds : pl->dn, pl->dn,
+                                                     pl->geo, pl->partials, act, pl->tw);
+    }
+    RECON_TRY(check_launch(pl, "x iteration"));
+    {
+      PROF(pl, KP_REDUCE);
+      k_reduce_pairs<<<pl->batch, kThreads, 0, s>>>(pl->partials, (int)gx(pl).x, pl->red);
+    }
+    return check_launch(pl, "reduce (norm)");
+  }
+
+  static int zfinal(recon_plan_t* pl, float* psi, float* u, bool cross, const int* act) {
+    hipStream_t s = pl->stream;
+    {
+      PROF(pl, KP_Z_FINAL);
+      k_z_final<N><<<gz(pl), dim3(kThreads), 0, s>>>(pl->w0, pl->w1, pl->w2, pl->geo, psi, u,
+                                                      cross ? pl->corr : nullptr, pl->partials, act, pl->tw);
+    }
+    RECON_TRY(check_launch(pl, "z final"));
+    if (cross) {
+      {
+        PROF(pl, KP_REDUCE);
+        k_reduce_pairs<<<pl->batch, kThreads, 0, s>>>(pl->partials, (int)gz(pl).x, pl->red + 2 * pl->batch);
+      }
+      RECON_TRY(check_launch(pl, "reduce (cross sum)"));
+    }
+    return RECON_OK;
+  }
+
+  static const Ops* table() {
+    static const Ops ops = {setup, setup_delta, fanout, ziter, fanin_xiter, zfinal,
+                            (int)((N / 2 + 1) * N / WX), (int)(N * (N / (2 * WZ)))};
+    return &ops;
+  }
+};
+
+const Ops* ops_for(int n) {
+  switch (n) {
+    case 8: return SizeOps<8>::table();
+    case 16: return SizeOps<16>::table();
+    case 32: return SizeOps<32>::table();
+    case 64: return SizeOps<64>::table();
+    case 128: return SizeOps<128>::table();
+    case 256: return SizeOps<256>::table();
+    case 512: return SizeOps<512>::table();
+    case 1024: return SizeOps<1024>::table();
+    default: return nullptr;
+  }
+}
+
+int launch_fill_u64(recon_plan_t* pl, void* p, long long count) {
+  long long blocks = (count + kThreads - 1) / kThreads;
+  if (blocks > 65536) blocks = 65536;
+  if (blocks < 1) blocks = 1;
+  {
+    PROF(pl, KP_FILL);
+    k_fill_u64<<<(unsigned)blocks, kThreads, 0, pl->stream>>>((unsigned long long*)p, count);
+  }
+  return check_launch(pl, "fill");
+}
+
+int upload_mask(recon_plan_t* pl, int* dev, std::vector<int>& host) {
+  HIP_TRY(pl, hipMemcpyAsync(dev, host.data(), sizeof(int) * host.size(), hipMemcpyHostToDevice, pl->stream));
+  return RECON_OK;
+}
+
+double ffta_c(int start, double beta) {
+  if (start == RECON_START_FFTA1) return beta / (1.0 + beta);
+  if (start == RECON_START_FFTA2) return 3.0 * beta / (7.0 + 3.0 * beta);
+  return 0.0;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+size_t recon_workspace_bytes(const recon_params_t* params) {
+  if (!valid_params(params, nullptr)) return 0;
+  return make_layout(params).total;
+}
+
+const char* recon_strerror(int code) {
+  switch (code) {
+    case RECON_OK: return "ok";
+    case RECON_NOTCONVERGED: return "not converged within max_iter";
+    case RECON_EINVAL: return "invalid argument";
+    case RECON_ENOMEM: return "workspace too small";
+    case RECON_EDEVICE: return "device error";
+    case RECON_ESTATE: return "call out of order";
+    case RECON_EDIVERGED: return "iteration diverged";
+    default: return "unknown error";
+  }
+}
+
+const char* recon_last_error(const recon_plan_t* plan) { return plan ? plan->msg.c_str() : "plan is NULL"; }
+
+int recon_plan(recon_plan_t** out, const recon_params_t* params, void* workspace, size_t workspace_bytes,
+               void* stream) {
+  if (!out) return RECON_EINVAL;
+  *out = nullptr;
+  std::string why;
+  if (!valid_params(params, &why)) return RECON_EINVAL;
+  if (!workspace || ((uintptr_t)workspace % kAlign)) return RECON_EINVAL;
+  Layout L = make_layout(params);
+  if (workspace_bytes < L.total) return RECON_ENOMEM;
+  recon_plan_t* pl = new (std::nothrow) recon_plan_t();
+  if (!pl) return RECON_ENOMEM;
+  pl->p = *params;
+  pl->stream = (hipStream_t)stream;
+  pl->ws = (char*)workspace;
+  pl->L = L;
+  pl->n = params->n;
+  pl->batch = params->batch;
+  pl->n3 = (long long)pl->n * pl->n * pl->n;
+  pl->cn = (long long)(pl->n / 2 + 1) * pl->n * pl->n;
+  pl->randoms = !(params->flags & RECON_NO_RANDOMS);
+  char* w = pl->ws;
+  pl->grid_g = (long long*)(w + L.grid_g);
+  pl->grid_r = pl->randoms ? (long long*)(w + L.grid_r) : nullptr;
+  pl->mask = pl->randoms ? (unsigned char*)(w + L.mask) : nullptr;
+  pl->w0 = (float2*)(w + L.w0);
+  pl->w1 = (float2*)(w + L.w1);
+  pl->w2 = (float2*)(w + L.w2);
+  pl->ds = (float2*)(w + L.ds);
+  pl->dn = (float2*)(w + L.dn);
+  pl->psi = (float*)(w + L.psi);
+  pl->delta = (params->flags & RECON_KEEP_DELTA) ? (float*)(w + L.delta) : nullptr;
+  pl->corr = (params->flags & RECON_START_BUFFERS) ? (float*)(w + L.corr) : nullptr;
+  pl->tw = (float2*)(w + L.tw);
+  pl->partials = (double*)(w + L.partials);
+  pl->red = (double*)(w + L.red);
+  pl->totals = (unsigned long long*)(w + L.totals);
+  pl->thr = (long long*)(w + L.thr);
+  pl->dscal = (DeltaScal*)(w + L.dscal);
+  pl->act_fan = (int*)(w + L.act);
+  pl->act_fin = pl->act_fan + pl->batch;
+  pl->act_it = pl->act_fan + 2 * pl->batch;
+  pl->err = (int*)(w + L.err);
+
+  const int n = pl->n;
+  const double L0 = params->box_len, h = L0 / n;
+  // line-of-sight scale: a power of two >= every |origin - observer| and L, so scaling is exact
+  double m = L0;
+  for (int a = 0; a < 3; ++a) m = std::fmax(m, std::fabs(params->box_origin[a] - params->observer[a]));
+  const double r0 = std::ldexp(1.0, (int)std::ceil(std::log2(m)));
+  pl->geo.kf = (float)(2.0 * M_PI / L0);
+  pl->geo.hs = (float)(h / r0);
+  for (int a = 0; a < 3; ++a) pl->geo.ds[a] = (float)((params->box_origin[a] - params->observer[a]) / r0);
+  pl->geo.growth = (float)params->growth;
+  pl->geo.inv_bn3 = (float)(1.0 / (params->bias * (double)n * n * n));
+  pl->geo.smooth_c = (float)(0.5 * params->smooth_r * params->smooth_r);
+  pl->geo.inv_n3 = (float)(1.0 / ((double)n * n * n));
+  pl->geo.start_scale = 1.0f;
+  pl->cic.n = n;
+  pl->cic.s = (float)((double)n / L0);
+  for (int a = 0; a < 3; ++a) pl->cic.o[a] = (float)params->box_origin[a];
+  pl->passes.assign(pl->batch, 0);
+  pl->done.assign(pl->batch, 0);
+  pl->psi_valid.assign(pl->batch, 0);
+  pl->st_y.assign(pl->batch, 0);
+  pl->pending1.assign(pl->batch, 0);
+  pl->diverged.assign(pl->batch, 0);
+  pl->num0.assign(pl->batch, 0.0);
+  pl->den0.assign(pl->batch, 0.0);
+  pl->s1.assign(pl->batch, 0.0);
+  pl->s2.assign(pl->batch, 0.0);
+  pl->norm1.assign(pl->batch, 0.0);
+  pl->hist.assign(pl->batch, {});
+  pl->h_fan.assign(pl->batch, 0);
+  pl->h_fin.assign(pl->batch, 0);
+  pl->h_it.assign(pl->batch, 0);
+  pl->h_red.assign(2 * pl->batch, 0.0);
+  pl->h_red2.assign(2 * pl->batch, 0.0);
+
+  // twiddles exp(-2 pi i m / N), rounded once from double
+  std::vector<float2> tw(n);
+  for (int i = 0; i < n; ++i) {
+    const double ang = -2.0 * M_PI * (double)i / (double)n;
+    tw[i] = make_float2((float)std::cos(ang), (float)std::sin(ang));
+  }
+  if (hipMemcpyAsync(pl->tw, tw.data(), sizeof(float2) * n, hipMemcpyHostToDevice, pl->stream) != hipSuccess ||
+      hipStreamSynchronize(pl->stream) != hipSuccess) {
+    delete pl;
+    return RECON_EDEVICE;
+  }
+  *out = pl;
+  return RECON_OK;
+}
+
+void recon_destroy(recon_plan_t* plan) { delete plan; }
+
+int recon_paint(recon_plan_t* pl, int which, const float* pos, const float* w, int64_t n, const int64_t* offsets,
+                uint32_t flags) {
+  if (!pl) return RECON_EINVAL;
+  if (which != RECON_GAL && which != RECON_RAN) return fail(pl, RECON_EINVAL, "which must be RECON_GAL or RECON_RAN");
+  if (which == RECON_RAN && !pl->randoms) return fail(pl, RECON_EINVAL, "plan was created with RECON_NO_RANDOMS");
+  if (n < 0 || (n > 0 && !pos)) return fail(pl, RECON_EINVAL, "bad catalogue pointer or count");
+  if (pl->batch > 1 && !offsets && n > 0) return fail(pl, RECON_EINVAL, "offsets are required when batch > 1");
+  if (flags & ~RECON_PAINT_ACCUMULATE) return fail(pl, RECON_EINVAL, "unknown paint flag");
+  long long* grid = which == RECON_GAL ? pl->grid_g : pl->grid_r;
+  const bool first = which == RECON_GAL ? !pl->painted_g : !pl->painted_r;
+  int* errc = pl->err + which;   // invalid-object counter of this grid
+  if (!(flags & RECON_PAINT_ACCUMULATE) || first) {
+    RECON_TRY(launch_fill_u64(pl, grid, pl->n3 * pl->batch));
+    HIP_TRY(pl, hipMemsetAsync(errc, 0, sizeof(int), pl->stream));
+  }
+  if (n > 0) {
+    long long blocks = (n + kThreads - 1) / kThreads;
+    if (blocks > 8192) blocks = 8192;
+    {
+      PROF(pl, KP_PAINT);
+      k_paint<<<(unsigned)blocks, kThreads, 0, pl->stream>>>(pos, w, n, (const long long*)offsets, pl->batch,
+                                                             (unsigned long long*)grid, pl->cic, errc);
+    }
+    RECON_TRY(check_launch(pl, "paint"));
+  }
+  if (which == RECON_GAL) pl->painted_g = true; else pl->painted_r = true;
+  pl->state = ST_PAINTED;
+  return RECON_OK;
+}
+
+int recon_set_delta(recon_plan_t* pl, const float* delta_s) {
+  if (!pl) return RECON_EINVAL;
+  if (!delta_s) return fail(pl, RECON_EINVAL, "delta_s is NULL");
+  const Ops* ops = ops_for(pl->n);
+  if (pl->delta) {
+    HIP_TRY(pl, hipMemcpyAsync(pl->delta, delta_s, sizeof(float) * pl->n3 * pl->batch, hipMemcpyDeviceToDevice,
+                               pl->stream));
+  }
+  RECON_TRY(ops->setup_delta(pl, delta_s));
+  pl->state = ST_DELTA;
+  return RECON_OK;
+}
+
+int recon_solve(recon_plan_t* pl, int start, const void* net) {
+  if (!pl) return RECON_EINVAL;
+  if (start < RECON_START_PLAIN || start > RECON_START_LEARNED) return fail(pl, RECON_EINVAL, "unknown start");
+  if (start != RECON_START_PLAIN && !pl->corr)
+    return fail(pl, RECON_EINVAL, "non-plain starts need a plan created with RECON_START_BUFFERS");
+  if (start == RECON_START_LEARNED)
+    return fail(pl, RECON_EINVAL, "learned start needs the network library (not linked in this build)");
+  (void)net;
+  const Ops* ops = ops_for(pl->n);
+  if (pl->state == ST_PAINTED) {
+    if (!pl->painted_g) return fail(pl, RECON_ESTATE, "galaxies were not painted");
+    if (pl->randoms && !pl->painted_r) return fail(pl, RECON_ESTATE, "randoms were not painted");
+    RECON_TRY(launch_fill_u64(pl, pl->totals, 3LL * pl->batch));
+    {
+      long long blocks = (pl->n3 + kThreads - 1) / kThreads;
+      if (blocks > 2048) blocks = 2048;
+      PROF(pl, KP_TOTALS);
+      k_totals<<<dim3((unsigned)blocks, pl->batch), kThreads, 0, pl->stream>>>(pl->grid_g, pl->grid_r, pl->n3,
+                                                                               pl->totals);
+      RECON_TRY(check_launch(pl, "totals"));
+    }
+    std::vector<unsigned long long> tot(3 * pl->batch);
+    int errs[2] = {0, 0};
+    HIP_TRY(pl, hipMemcpyAsync(tot.data(), pl->totals, 8 * tot.size(), hipMemcpyDeviceToHost, pl->stream));
+    HIP_TRY(pl, hipMemcpyAsync(errs, pl->err, 2 * sizeof(int), hipMemcpyDeviceToHost, pl->stream));
+    HIP_TRY(pl, hipStreamSynchronize(pl->stream));
+    const int errcount = errs[0] + (pl->randoms ? errs[1] : 0);
+    if (errcount) return fail(pl, RECON_EINVAL, std::to_string(errcount) + " objects had invalid positions or weights");
+    std::vector<DeltaScal> sc(pl->batch);
+    std::vector<long long> thr(pl->batch, 0);
+    for (int b = 0; b < pl->batch; ++b) {
+      const long long wg = (long long)tot[3 * b], wr = (long long)tot[3 * b + 1], occ = (long long)tot[3 * b + 2];
+      if (wg <= 0) return fail(pl, RECON_EINVAL, "total galaxy weight is zero");
+      sc[b].inv_rhobar = (float)((double)pl->n3 / ((double)wg * 2.3283064365386963e-10));
+      sc[b].alpha = 0.f;
+      if (pl->randoms) {
+        if (wr <= 0 || occ <= 0) return fail(pl, RECON_EINVAL, "total random weight is zero");
+        sc[b].alpha = (float)((double)wg / (double)wr);
+        thr[b] = (long long)std::floor(pl->p.mask_tau * 27.0 * (double)wr / (double)occ);
+      }
+    }
+    HIP_TRY(pl, hipMemcpyAsync(pl->dscal, sc.data(), sizeof(DeltaScal) * pl->batch, hipMemcpyHostToDevice, pl->stream));
+    if (pl->randoms) {
+      HIP_TRY(pl, hipMemcpyAsync(pl->thr, thr.data(), 8 * pl->batch, hipMemcpyHostToDevice, pl->stream));
+      long long blocks = (pl->n3 + kThreads - 1) / kThreads;
+      if (blocks > 65536) blocks = 65536;
+      {
+        PROF(pl, KP_MASK);
+        k_mask<<<dim3((unsigned)blocks, pl->batch), kThreads, 0, pl->stream>>>(pl->grid_r, pl->n, pl->thr, pl->mask);
+      }
+      RECON_TRY(check_launch(pl, "mask"));
+    }
+    RECON_TRY(ops->setup(pl));
+    HIP_TRY(pl, hipStreamSynchronize(pl->stream));
+  } else if (pl->state != ST_DELTA && pl->state != ST_SOLVED) {
+    return fail(pl, RECON_ESTATE, "paint or set_delta must precede solve");
+  } else if (pl->state == ST_SOLVED) {
+    return fail(pl, RECON_ESTATE, "already solved; paint or set_delta again");
+  }
+  pl->start = start;
+  const double beta = pl->p.growth / pl->p.bias;
+  pl->geo.start_scale = (float)(1.0 - ffta_c(start, beta));
+  for (int b = 0; b < pl->batch; ++b) {
+    pl->passes[b] = 0;
+    pl->done[b] = 0;
+    pl->psi_valid[b] = 0;
+    pl->st_y[b] = 0;
+    pl->pending1[b] = 0;
+    pl->diverged[b] = 0;
+    pl->hist[b].clear();
+  }
+  pl->state = ST_SOLVED;
+  return RECON_OK;
+}
+
+int recon_iterate(recon_plan_t* pl, int max_iter, double tol, int32_t* iters_out, double* eps_out) {
+  if (!pl) return RECON_EINVAL;
+  if (pl->state != ST_SOLVED) return fail(pl, RECON_ESTATE, "solve must precede iterate");
+  if (max_iter < 0) return fail(pl, RECON_EINVAL, "max_iter must be >= 0");
+  const Ops* ops = ops_for(pl->n);
+  const int B = pl->batch;
+  const bool fixed = !(tol > 0.0);
+  const double norm_k = 1.0 / (pl->p.bias * pl->p.bias * (double)pl->n3);   // Parseval + 1/b^2
+  std::vector<std::vector<double>> call_eps(B);
+  for (int b = 0; b < B; ++b) pl->done[b] = pl->diverged[b] ? 1 : 0;
+
+  // norm2 = ||Psi_n||^2.  Divergence: non-finite eps, eps rising twice in a row, or
+  // ||Psi_n|| > 100 ||Psi_1||.
+  auto record = [&](int b, double e, double norm2) {
+    call_eps[b].push_back(e);
+    pl->hist[b].push_back(e);
+    const auto& h = pl->hist[b];
+    const size_t k = h.size();
+    const double nrm = std::sqrt(std::fmax(norm2, 0.0));
+    if (k == 1) pl->norm1[b] = nrm;
+    if (!std::isfinite(e) || !std::isfinite(nrm) || (k >= 3 && h[k - 1] > h[k - 2] && h[k - 2] > h[k - 3]) ||
+        (k >= 2 && nrm > 100.0 * pl->norm1[b])) {
+      pl->diverged[b] = 1;
+      pl->done[b] = 1;
+    } else if (!fixed && e <= tol) {
+      pl->done[b] = 1;
+    }
+  };
+
+  // resolve eps_1 of a non-gradient start: needs the state-Y fan-out of D_1
+  auto resolve_pending = [&](bool write_psi) -> int {
+    bool any = false;
+    for (int b = 0; b < B; ++b) {
+      pl->h_fan[b] = (pl->pending1[b] && !pl->st_y[b]) ? 1 : 0;
+      pl->h_fin[b] = pl->pending1[b];
+      any = any || pl->pending1[b];
+    }
+    if (!any) return RECON_OK;
+    RECON_TRY(upload_mask(pl, pl->act_fan, pl->h_fan));
+    RECON_TRY(ops->fanout(pl, pl->act_fan));
+    RECON_TRY(upload_mask(pl, pl->act_fin, pl->h_fin));
+    RECON_TRY(ops->zfinal(pl, pl->psi, nullptr, true, pl->act_fin));
+    HIP_TRY(pl, hipMemcpyAsync(pl->h_red2.data(), pl->red + 2 * B, 16 * B, hipMemcpyDeviceToHost, pl->stream));
+    HIP_TRY(pl, hipStreamSynchronize(pl->stream));
+    for (int b = 0; b < B; ++b) {
+      if (!pl->pending1[b]) continue;
+      pl->st_y[b] = 1;
+      pl->psi_valid[b] = 1;
+      pl->pending1[b] = 0;
+      const double s3 = pl->h_red2[2 * b];
+      const double diff2 = pl->num0[b] - 2.0 * (s3 - pl->s1[b]) + pl->s2[b];
+      const double e = pl->den0[b] > 0 ? std::sqrt(std::fmax(diff2, 0.0) / pl->den0[b]) : 0.0;
+      record(b, e, pl->den0[b]);
+    }
+    (void)write_psi;
+    return RECON_OK;
+  };
+
+  for (int it = 0; it < max_iter; ++it) {
+    bool any = false;
+    for (int b = 0; b < B; ++b) any = any || !pl->done[b];
+    if (!any) break;
+    // pending eps_1 first (it also fans out those realisations)
+    RECON_TRY(resolve_pending(true));
+    any = false;
+    for (int b = 0; b < B; ++b) {
+      pl->h_it[b] = pl->done[b] ? 0 : 1;
+      pl->h_fan[b] = (!pl->done[b] && !pl->st_y[b]) ? 1 : 0;
+      any = any || pl->h_it[b];
+    }
+    if (!any) break;
+    int first_pass = -1;
+    for (int b = 0; b < B; ++b)
+      if (pl->h_it[b]) { first_pass = pl->passes[b]; break; }
+    RECON_TRY(upload_mask(pl, pl->act_fan, pl->h_fan));
+    RECON_TRY(ops->fanout(pl, pl->act_fan));
+    RECON_TRY(upload_mask(pl, pl->act_it, pl->h_it));
+    const bool start_pass = first_pass == 0 && pl->start != RECON_START_PLAIN;
+    const int mode = start_pass ? (pl->start == RECON_START_LEARNED ? ZI_LEARNED : ZI_FFTA) : ZI_PLAIN;
+    RECON_TRY(ops->ziter(pl, mode, pl->act_it));
+    RECON_TRY(ops->fanin_xiter(pl, first_pass == 0, pl->act_it));
+    HIP_TRY(pl, hipMemcpyAsync(pl->h_red.data(), pl->red, 16 * B, hipMemcpyDeviceToHost, pl->stream));
+    if (start_pass) {
+      HIP_TRY(pl, hipMemcpyAsync(pl->h_red2.data(), pl->red + 2 * B, 16 * B, hipMemcpyDeviceToHost, pl->stream));
+    }
+    HIP_TRY(pl, hipStreamSynchronize(pl->stream));
+    for (int b = 0; b < B; ++b) {
+      if (!pl->h_it[b]) continue;
+      pl->st_y[b] = 0;
+      pl->psi_valid[b] = 0;
+      pl->passes[b] += 1;
+      const double num = pl->h_red[2 * b], den = pl->h_red[2 * b + 1];
+      if (start_pass) {
+        pl->num0[b] = num * norm_k;
+        pl->den0[b] = den * norm_k;
+        pl->s1[b] = pl->h_red2[2 * b];
+        pl->s2[b] = pl->h_red2[2 * b + 1];
+        pl->pending1[b] = 1;
+      } else {
+        record(b, den > 0 ? std::sqrt(num / den) : 0.0, den * norm_k);
+      }
+    }
+  }
+  RECON_TRY(resolve_pending(true));
+  // displacement of every realisation whose Psi buffer is stale
+  bool need = false;
+  for (int b = 0; b < B; ++b) {
+    pl->h_fin[b] = pl->psi_valid[b] ? 0 : 1;
+    pl->h_fan[b] = (pl->h_fin[b] && !pl->st_y[b]) ? 1 : 0;
+    need = need || pl->h_fin[b];
+  }
+  if (need) {
+    RECON_TRY(upload_mask(pl, pl->act_fan, pl->h_fan));
+    RECON_TRY(ops->fanout(pl, pl->act_fan));
+    RECON_TRY(upload_mask(pl, pl->act_fin, pl->h_fin));
+    RECON_TRY(ops->zfinal(pl, pl->psi, nullptr, false, pl->act_fin));
+    for (int b = 0; b < B; ++b)
+      if (pl->h_fin[b]) { pl->psi_valid[b] = 1; pl->st_y[b] = 1; }
+  }
+  HIP_TRY(pl, hipStreamSynchronize(pl->stream));
+  bool div = false, notconv = false;
+  for (int b = 0; b < B; ++b) {
+    if (iters_out) iters_out[b] = pl->passes[b];
+    if (eps_out)
+      for (int i = 0; i < max_iter; ++i)
+        eps_out[(size_t)b * max_iter + i] = i < (int)call_eps[b].size() ? call_eps[b][i] : NAN;
+    div = div || pl->diverged[b];
+    if (!fixed && !pl->diverged[b]) {
+      const auto& h = pl->hist[b];
+      if (h.empty() || !(h.back() <= tol)) notconv = true;
+    }
+  }
+  if (div) return fail(pl, RECON_EDIVERGED, "convergence norm rose twice in a row or became non-finite");
+  return notconv ? RECON_NOTCONVERGED : RECON_OK;
+}
+
+int recon_shift(recon_plan_t* pl, int which, const float* pos, int64_t n, const int64_t* offsets, float* disp_out,
+                float* pos_out) {
+  if (!pl) return RECON_EINVAL;
+  if (which != RECON_GAL && which != RECON_RAN) return fail(pl, RECON_EINVAL, "which must be RECON_GAL or RECON_RAN");
+  if (pl->state != ST_SOLVED) return fail(pl, RECON_ESTATE, "iterate must precede shift");
+  for (int b = 0; b < pl->batch; ++b)
+    if (!pl->psi_valid[b]) return fail(pl, RECON_ESTATE, "displacement not computed; call iterate");
+  if (n < 0 || (n > 0 && (!pos || !disp_out))) return fail(pl, RECON_EINVAL, "bad catalogue pointers");
+  if (pl->batch > 1 && !offsets && n > 0) return fail(pl, RECON_EINVAL, "offsets are required when batch > 1");
+  if (n == 0) return RECON_OK;
+  HIP_TRY(pl, hipMemsetAsync(pl->err + 2, 0, sizeof(int), pl->stream));
+  long long blocks = (n + kThreads - 1) / kThreads;
+  if (blocks > 8192) blocks = 8192;
+  {
+    PROF(pl, KP_SHIFT);
+    k_shift<<<(unsigned)blocks, kThreads, 0, pl->stream>>>(
+        pos, n, (const long long*)offsets, pl->batch, pl->psi, pl->cic, (float)pl->p.observer[0],
+        (float)pl->p.observer[1], (float)pl->p.observer[2], (float)pl->p.growth, which == RECON_GAL ? 1 : 0,
+        disp_out, pos_out, pl->err + 2);
+  }
+  return check_launch(pl, "shift");
+}
+
+int recon_get_psi(recon_plan_t* pl, float* psi_out) {
+  if (!pl || !psi_out) return RECON_EINVAL;
+  if (pl->state != ST_SOLVED) return fail(pl, RECON_ESTATE, "no displacement yet");
+  for (int b = 0; b < pl->batch; ++b)
+    if (!pl->psi_valid[b]) return fail(pl, RECON_ESTATE, "displacement not computed; call iterate");
+  HIP_TRY(pl, hipMemcpyAsync(psi_out, pl->psi, sizeof(float) * 3 * pl->n3 * pl->batch, hipMemcpyDeviceToDevice,
+                             pl->stream));
+  return RECON_OK;
+}
+
+int recon_get_grid(recon_plan_t* pl, int which, int64_t* out) {
+  if (!pl || !out) return RECON_EINVAL;
+  if (which != RECON_GAL && which != RECON_RAN) return fail(pl, RECON_EINVAL, "which must be RECON_GAL or RECON_RAN");
+  const long long* g = which == RECON_GAL ? pl->grid_g : pl->grid_r;
+  if (!g || !(which == RECON_GAL ? pl->painted_g : pl->painted_r)) return fail(pl, RECON_ESTATE, "grid not painted");
+  HIP_TRY(pl, hipMemcpyAsync(out, g, sizeof(int64_t) * pl->n3 * pl->batch, hipMemcpyDeviceToDevice, pl->stream));
+  return RECON_OK;
+}
+
+int recon_get_delta(recon_plan_t* pl, float* out) {
+  if (!pl || !out) return RECON_EINVAL;
+  if (!pl->delta) return fail(pl, RECON_EINVAL, "plan was created without RECON_KEEP_DELTA");
+  if (pl->state != ST_SOLVED && pl->state != ST_DELTA) return fail(pl, RECON_ESTATE, "no overdensity yet");
+  HIP_TRY(pl, hipMemcpyAsync(out, pl->delta, sizeof(float) * pl->n3 * pl->batch, hipMemcpyDeviceToDevice, pl->stream));
+  return RECON_OK;
+}
+
+int recon_profile_start(recon_plan_t* pl) {
+  if (!pl) return RECON_EINVAL;
+  pl->prof.on = true;
+  pl->prof.used = 0;
+  pl->prof.recs.clear();
+  return RECON_OK;
+}
+
+int recon_profile_stop(recon_plan_t* pl, int32_t* counts, double* total_ms, int cap) {
+  if (!pl) return RECON_EINVAL;
+  pl->prof.on = false;
+  HIP_TRY(pl, hipStreamSynchronize(pl->stream));
+  std::vector<int32_t> c(KP_COUNT, 0);
+  std::vector<double> t(KP_COUNT, 0.0);
+  for (const auto& r : pl->prof.recs) {
+    float ms = 0.f;
+    HIP_TRY(pl, hipEventElapsedTime(&ms, pl->prof.pool[r.second], pl->prof.pool[r.second + 1]));
+    c[r.first] += 1;
+    t[r.first] += ms;
+  }
+  pl->prof.recs.clear();
+  pl->prof.used = 0;
+  for (int k = 0; k < KP_COUNT && k < cap; ++k) {
+    if (counts) counts[k] = c[k];
+    if (total_ms) total_ms[k] = t[k];
+  }
+  return KP_COUNT;
+}
+
+const char* recon_profile_kernel_name(int id) {
+  return (id >= 0 && id < KP_COUNT) ? kKernelNames[id] : "";
+}
+
+}  // extern "C"

@@ -1,0 +1,1000 @@
+// Kernels of the reconstruction hot path.
+//
+// Memory layout (per realisation, b-th block of each buffer):
+//   real field      [z][y][x]              N^3 float, x fastest
+//   int64 grid      [z][y][x]              N^3 int64 (units of 2^-32 weight)
+//   spectrum C      [kz][ky][kx]           (N/2+1) N N float2; kz is the halved axis
+// Forward 3D transforms run z (real-to-complex, two real columns packed per
+// complex column), then y, then x; inverse transforms run x, y, z.  Every
+// k-space multiplier is applied inside the pass where its wavenumber index is
+// known, so the fan-out Psi_j = i k'_j P and the fan-in div = sum_j i k'_j V_j
+// are staged across passes instead of transforming three fields end to end.
+#pragma once
+
+#include "recon_device.hpp"
+
+namespace recon {
+
+// Geometry and physics constants shared by the transform kernels.
+struct Geo {
+  float kf;          // fundamental wavenumber 2 pi / L
+  float hs;          // cell size divided by the line-of-sight scale R0 (a power of two)
+  float ds[3];       // (box origin - observer) / R0, per axis
+  float growth;      // f
+  float inv_bn3;     // 1 / (b N^3): Zel'dovich solve including the inverse-transform factor
+  float smooth_c;    // R^2 / 2
+  float inv_n3;      // 1 / N^3
+  float start_scale; // u_0 = start_scale * u_p for the FFTA starts
+};
+
+// Per-realisation scalars of the overdensity step.
+struct DeltaScal {
+  float alpha;       // W_g / W_r
+  float inv_rhobar;  // N^3 / W_g (mean-density mode)
+};
+
+// Cloud-in-cell frame: u = fl32(fl32(x - o) * s), s = fl32(N / L).
+struct CicGeo {
+  int n;
+  float s;
+  float o[3];
+};
+
+enum ZIterMode { ZI_PLAIN = 0, ZI_FFTA = 1, ZI_LEARNED = 2 };
+
+template <int N> constexpr int wz() { return N >= 1024 ? 8 : (N / 2 < 16 ? N / 2 : 16); }   // packed z columns
+template <int N> constexpr int wy() { return N >= 1024 ? 8 : (N < 16 ? N : 16); }           // y-pass columns
+template <int N> constexpr int wx() { return 8; }                                             // x-pass rows
+
+__device__ __forceinline__ long long ceil_div_ll(long long a, long long b) { return (a + b - 1) / b; }
+
+// ---------------------------------------------------------------------------
+// Fill, deposit, totals, mask
+// ---------------------------------------------------------------------------
+__global__ void k_fill_u64(unsigned long long* p, long long count) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < count;
+       i += (long long)gridDim.x * blockDim.x)
+    p[i] = 0ull;
+}
+
+__global__ void k_fill_i32(int* p, long long count, int v) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < count;
+       i += (long long)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+__device__ __forceinline__ int find_realisation(const long long* __restrict__ off, int batch, long long i) {
+  int lo = 0, hi = batch - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= i) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Integer fixed-point CIC deposit.  Seven corners get floor(W_Q c / 2^48) and
+// corner (1,1,1) the remainder, so every object deposits exactly W_Q; integer
+// atomics make the grid independent of the order of the objects.
+__global__ void __launch_bounds__(256) k_paint(const float* __restrict__ pos, const float* __restrict__ w,
+                                               long long n, const long long* __restrict__ off, int batch,
+                                               unsigned long long* __restrict__ grid, CicGeo g,
+                                               int* __restrict__ err) {
+  const long long n3 = (long long)g.n * g.n * g.n;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    bool ok = true;
+    float uu[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      float d = __fsub_rn(pos[3 * i + a], g.o[a]);
+      uu[a] = __fmul_rn(d, g.s);
+      ok = ok && (fabsf(uu[a]) < 1073741824.0f);   // false for NaN / inf too
+    }
+    float wv = w ? w[i] : 1.0f;
+    ok = ok && (wv >= 0.0f) && (wv < 64.0f);
+    if (!ok) { atomicAdd(err, 1); continue; }
+    int ii[3];
+    unsigned long long tau[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      float fl = floorf(uu[a]);
+      float t = __fsub_rn(uu[a], fl);
+      tau[a] = (unsigned long long)floorf(t * 65536.0f);
+      ii[a] = ((int)fl) & (g.n - 1);
+    }
+    const unsigned long long wq = w ? (unsigned long long)__double2ll_rn((double)wv * 4294967296.0)
+                                    : (1ull << 32);
+    const int b = off ? find_realisation(off, batch, i) : 0;
+    unsigned long long* gb = grid + (long long)b * n3;
+    unsigned long long acc = 0;
+#pragma unroll
+    for (int cnr = 0; cnr < 8; ++cnr) {
+      const int dx = cnr & 1, dy = (cnr >> 1) & 1, dz = cnr >> 2;
+      const long long ix = (ii[0] + dx) & (g.n - 1);
+      const long long iy = (ii[1] + dy) & (g.n - 1);
+      const long long iz = (ii[2] + dz) & (g.n - 1);
+      unsigned long long share;
+      if (cnr < 7) {
+        const unsigned long long ax = dx ? tau[0] : 65536ull - tau[0];
+        const unsigned long long ay = dy ? tau[1] : 65536ull - tau[1];
+        const unsigned long long az = dz ? tau[2] : 65536ull - tau[2];
+        const unsigned long long c = ax * ay * az;
+        const unsigned long long chi = c >> 24, clo = c & 0xFFFFFFull;
+        share = (wq * chi + ((wq * clo) >> 24)) >> 24;
+        acc += share;
+      } else {
+        share = wq - acc;
+      }
+      if (share) atomicAdd(gb + (iz * g.n + iy) * g.n + ix, share);
+    }
+  }
+}
+
+// Exact totals per realisation: out[b] = {sum I_g, sum I_r, #cells with I_r != 0}.
+__global__ void __launch_bounds__(256) k_totals(const long long* __restrict__ gg, const long long* __restrict__ gr,
+                                                long long n3, unsigned long long* __restrict__ out) {
+  const int b = blockIdx.y;
+  gg += (long long)b * n3;
+  if (gr) gr += (long long)b * n3;
+  unsigned long long sg = 0, sr = 0, occ = 0;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n3;
+       i += (long long)gridDim.x * blockDim.x) {
+    sg += (unsigned long long)gg[i];
+    if (gr) {
+      long long v = gr[i];
+      sr += (unsigned long long)v;
+      occ += (v != 0);
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    sg += __shfl_xor(sg, o, 64);
+    sr += __shfl_xor(sr, o, 64);
+    occ += __shfl_xor(occ, o, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    atomicAdd(out + 3 * b + 0, sg);
+    if (gr) {
+      atomicAdd(out + 3 * b + 1, sr);
+      atomicAdd(out + 3 * b + 2, occ);
+    }
+  }
+}
+
+// Binary survey mask: the cell is inside when the exact 3x3x3 periodic sum of the
+// random grid exceeds thr[b].
+__global__ void __launch_bounds__(256) k_mask(const long long* __restrict__ gr, int n,
+                                              const long long* __restrict__ thr, unsigned char* __restrict__ mask) {
+  const int b = blockIdx.y;
+  const long long n3 = (long long)n * n * n;
+  gr += (long long)b * n3;
+  mask += (long long)b * n3;
+  const long long t = thr[b];
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n3;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int x = (int)(i % n), y = (int)((i / n) % n), z = (int)(i / ((long long)n * n));
+    long long s = 0;
+    for (int dz = -1; dz <= 1; ++dz) {
+      const long long zz = (z + dz) & (n - 1);
+      for (int dy = -1; dy <= 1; ++dy) {
+        const long long row = (zz * n + ((y + dy) & (n - 1))) * n;
+#pragma unroll
+        for (int dx = -1; dx <= 1; ++dx) s += gr[row + ((x + dx) & (n - 1))];
+      }
+    }
+    mask[i] = s > t ? 1 : 0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// z passes (real <-> half spectrum along z, two real columns per complex column)
+// Tile: one y row, 2*WP consecutive x.  LDS holds [N][WP+1] packed columns.
+// ---------------------------------------------------------------------------
+template <int N, int WP>
+__device__ __forceinline__ void z_tile_coords(int& y, int& x0) {
+  constexpr int TPR = N / (2 * WP);
+  y = blockIdx.x / TPR;
+  x0 = (blockIdx.x % TPR) * 2 * WP;
+}
+
+// Load a half-spectrum column tile and expand it Hermitian-wise into packed full columns.
+template <int N, int WP>
+__device__ __forceinline__ void z_load_pack(float2* buf, const float2* __restrict__ a, int y, int x0) {
+  constexpr int LD = WP + 1;
+  for (int e = threadIdx.x; e < (N / 2 + 1) * WP; e += kThreads) {
+    const int p = e % WP, kz = e / WP;
+    const long long base = ((long long)kz * N + y) * N + x0 + p;
+    const float2 A = a[base], B = a[base + WP];
+    if (kz == 0 || kz == N / 2) {
+      buf[kz * LD + p] = make_float2(A.x, B.x);
+    } else {
+      buf[kz * LD + p] = make_float2(A.x - B.y, A.y + B.x);
+      buf[(N - kz) * LD + p] = make_float2(A.x + B.y, B.x - A.y);
+    }
+  }
+}
+
+// Split a transformed packed tile into the half spectra of its two real columns and store.
+// MULK: multiply by i k'_z.
+template <int N, int WP, bool MULK>
+__device__ __forceinline__ void z_unpack_store(const float2* buf, float2* __restrict__ out, int y, int x0, float kf) {
+  constexpr int LD = WP + 1;
+  for (int e = threadIdx.x; e < (N / 2 + 1) * WP; e += kThreads) {
+    const int p = e % WP, kz = e / WP;
+    const float2 Z = buf[kz * LD + p];
+    const float2 M = buf[((N - kz) & (N - 1)) * LD + p];
+    float2 A = make_float2(0.5f * (Z.x + M.x), 0.5f * (Z.y - M.y));
+    float2 B = make_float2(0.5f * (Z.y + M.y), 0.5f * (M.x - Z.x));
+    if (MULK) {
+      const float k = kf * deriv_mode<N>(kz);
+      A = mul_i(A) * k;
+      B = mul_i(B) * k;
+    }
+    const long long base = ((long long)kz * N + y) * N + x0 + p;
+    out[base] = A;
+    out[base + WP] = B;
+  }
+}
+
+// Forward z transform of int64 grids (units 2^-32) into half spectra.
+template <int N, int NA>
+__global__ void __launch_bounds__(256) k_z_fwd_grid(const long long* __restrict__ g0, const long long* __restrict__ g1,
+                                                    float2* __restrict__ o0, float2* __restrict__ o1,
+                                                    const float2* __restrict__ twg) {
+  constexpr int WP = wz<N>(), LD = WP + 1;
+  __shared__ float2 buf[N * LD];
+  __shared__ float2 tw[N];
+  stage_twiddles<N>(tw, twg);
+  int y, x0;
+  z_tile_coords<N, WP>(y, x0);
+  const long long n3 = (long long)N * N * N, cn = (long long)(N / 2 + 1) * N * N;
+  const int b = blockIdx.y;
+  const float unit = 2.3283064365386963e-10f;   // 2^-32
+#pragma unroll
+  for (int a = 0; a < NA; ++a) {
+    const long long* g = (a == 0 ? g0 : g1) + b * n3;
+    float2* o = (a == 0 ? o0 : o1) + b * cn;
+    for (int e = threadIdx.x; e < N * WP; e += kThreads) {
+      const int p = e % WP, z = e / WP;
+      const long long base = ((long long)z * N + y) * N + x0 + p;
+      buf[z * LD + p] = make_float2((float)g[base] * unit, (float)g[base + WP] * unit);
+    }
+    __syncthreads();
+    tile_fft<N, WP, false>(buf, tw);
+    z_unpack_store<N, WP, false>(buf, o, y, x0, 0.f);
+    __syncthreads();
+  }
+}
+
+// Forward z transform of one real field.
+template <int N>
+__global__ void __launch_bounds__(256) k_z_fwd_real(const float* __restrict__ f, float2* __restrict__ o,
+                                                    const float2* __restrict__ twg) {
+  constexpr int WP = wz<N>(), LD = WP + 1;
+  __shared__ float2 buf[N * LD];
+  __shared__ float2 tw[N];
+  stage_twiddles<N>(tw, twg);
+  int y, x0;
+  z_tile_coords<N, WP>(y, x0);
+  const long long n3 = (long long)N * N * N, cn = (long long)(N / 2 + 1) * N * N;
+  const int b = blockIdx.y;
+  f += b * n3;
+  o += b * cn;
+  for (int e = threadIdx.x; e < N * WP; e += kThreads) {
+    const int p = e % WP, z = e / WP;
+    const long long base = ((long long)z * N + y) * N + x0 + p;
+    buf[z * LD + p] = make_float2(f[base], f[base + WP]);
+  }
+  __syncthreads();
+  tile_fft<N, WP, false>(buf, tw);
+  z_unpack_store<N, WP, false>(buf, o, y, x0, 0.f);
+}
+
+// Inverse z transform of the smoothed galaxy (and random) densities, overdensity in
+// configuration space, forward z transform of the overdensity (written over arr0).
+//   with randoms:  delta = m (G - alpha R) / (alpha R), 0 outside the mask or where R <= 0
+//   mean density:  delta = G / rho_bar - 1
+template <int N, int NA>
+__global__ void __launch_bounds__(256) k_z_delta(float2* __restrict__ a0, const float2* __restrict__ a1,
+                                                 const unsigned char* __restrict__ mask,
+                                                 const DeltaScal* __restrict__ sc, float* __restrict__ delta_out,
+                                                 const float2* __restrict__ twg) {
+  constexpr int WP = wz<N>(), LD = WP + 1;
+  constexpr int EPT = (N * WP + kThreads - 1) / kThreads;
+  __shared__ float2 buf[N * LD];
+  __shared__ float2 tw[N];
+  stage_twiddles<N>(tw, twg);
+  int y, x0;
+  z_tile_coords<N, WP>(y, x0);
+  const long long n3 = (long long)N * N * N, cn = (long long)(N / 2 + 1) * N * N;
+  const int b = blockIdx.y;
+  a0 += b * cn;
+  if (NA == 2) a1 += b * cn;
+  const DeltaScal s = sc[b];
+  float2 gv[EPT];
+  z_load_pack<N, WP>(buf, a0, y, x0);
+  __syncthreads();
+  tile_fft<N, WP, true>(buf, tw);
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int e = threadIdx.x + i * kThreads;
+    if (e < N * WP) gv[i] = buf[(e / WP) * LD + e % WP];
+  }
+  __syncthreads();
+  if constexpr (NA == 2) {
+    z_load_pack<N, WP>(buf, a1, y, x0);
+    __syncthreads();
+    tile_fft<N, WP, true>(buf, tw);
+  }
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int e = threadIdx.x + i * kThreads;
+    if (e < N * WP) {
+      const int p = e % WP, z = e / WP;
+      const long long cell = ((long long)z * N + y) * N + x0 + p;
+      float d0, d1;
+      if constexpr (NA == 2) {
+        const float2 rv = buf[z * LD + p];
+        const unsigned char* m = mask + b * n3;
+        const float ar0 = s.alpha * rv.x, ar1 = s.alpha * rv.y;
+        d0 = (m[cell] && ar0 > 0.f) ? (gv[i].x - ar0) / ar0 : 0.f;
+        d1 = (m[cell + WP] && ar1 > 0.f) ? (gv[i].y - ar1) / ar1 : 0.f;
+      } else {
+        d0 = gv[i].x * s.inv_rhobar - 1.f;
+        d1 = gv[i].y * s.inv_rhobar - 1.f;
+      }
+      gv[i] = make_float2(d0, d1);
+      if (delta_out) {
+        delta_out[b * n3 + cell] = d0;
+        delta_out[b * n3 + cell + WP] = d1;
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int e = threadIdx.x + i * kThreads;
+    if (e < N * WP) buf[(e / WP) * LD + e % WP] = gv[i];
+  }
+  __syncthreads();
+  tile_fft<N, WP, false>(buf, tw);
+  z_unpack_store<N, WP, false>(buf, a0, y, x0, 0.f);
+}
+
+// Scaled line-of-sight vector of a node: r = (origin + H i - observer) / R0.
+__device__ __forceinline__ float los_comp(const Geo& g, int a, int i) { return fmaf(g.hs, (float)i, g.ds[a]); }
+
+// One iteration's configuration-space step (step A tail + step B head):
+//   inverse z of the three displacement spectra -> s = sum_j r_j Psi_j
+//   V_j = u r_hat_j = s r_j / |r|^2 -> forward z; the z component is multiplied by i k'_z.
+// Arrays are updated in place.  Start modes (first pass only):
+//   ZI_FFTA:    u_0 = start_scale * u_p, Delta = u_0 - u_p stored in corr
+//   ZI_LEARNED: u_0 = u_p + corr
+// and both accumulate S1 = sum Delta u_p, S2 = sum Delta^2 into partials.
+template <int N, int MODE>
+__global__ void __launch_bounds__(256) k_z_iter(float2* __restrict__ a0, float2* __restrict__ a1,
+                                                float2* __restrict__ a2, Geo g, float* __restrict__ corr,
+                                                double* __restrict__ partials, const int* __restrict__ active,
+                                                const float2* __restrict__ twg) {
+  constexpr int WP = wz<N>(), LD = WP + 1;
+  constexpr int EPT = (N * WP + kThreads - 1) / kThreads;
+  const int b = blockIdx.y;
+  if (active && !active[b]) return;
+  __shared__ float2 buf[N * LD];
+  __shared__ float2 tw[N];
+  stage_twiddles<N>(tw, twg);
+  int y, x0;
+  z_tile_coords<N, WP>(y, x0);
+  const long long n3 = (long long)N * N * N, cn = (long long)(N / 2 + 1) * N * N;
+  float2* arr[3] = {a0 + b * cn, a1 + b * cn, a2 + b * cn};
+  float s0[EPT], s1[EPT];
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) { s0[i] = 0.f; s1[i] = 0.f; }
+  const float ry = los_comp(g, 1, y);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    z_load_pack<N, WP>(buf, arr[a], y, x0);
+    __syncthreads();
+    tile_fft<N, WP, true>(buf, tw);
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      const int e = threadIdx.x + i * kThreads;
+      if (e < N * WP) {
+        const int p = e % WP, z = e / WP;
+        const float2 v = buf[z * LD + p];
+        float r0, r1;
+        if (a == 0) { r0 = los_comp(g, 0, x0 + p); r1 = los_comp(g, 0, x0 + p + WP); }
+        else if (a == 1) { r0 = ry; r1 = ry; }
+        else { r0 = los_comp(g, 2, z); r1 = r0; }
+        s0[i] = fmaf(r0, v.x, s0[i]);
+        s1[i] = fmaf(r1, v.y, s1[i]);
+      }
+    }
+    __syncthreads();
+  }
+  // s -> q = u_0 / |r|, so that V_j = q * r_j
+  double acc1 = 0.0, acc2 = 0.0;
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int e = threadIdx.x + i * kThreads;
+    if (e < N * WP) {
+      const int p = e % WP, z = e / WP;
+      const float rz = los_comp(g, 2, z);
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const float rx = los_comp(g, 0, x0 + p + h * WP);
+        const float r2 = rx * rx + ry * ry + rz * rz;
+        const float ir = r2 > 0.f ? rsqrtf(r2) : 0.f;
+        const float up = (h ? s1[i] : s0[i]) * ir;        // u_p = s / |r|
+        float u0 = up;
+        if (MODE != ZI_PLAIN) {
+          const long long cell = b * n3 + ((long long)z * N + y) * N + x0 + p + h * WP;
+          float dlt;
+          if (MODE == ZI_FFTA) {
+            u0 = g.start_scale * up;
+            dlt = u0 - up;
+            corr[cell] = dlt;
+          } else {
+            dlt = corr[cell];
+            u0 = up + dlt;
+          }
+          acc1 += (double)dlt * (double)up;
+          acc2 += (double)dlt * (double)dlt;
+        }
+        const float q = u0 * ir;
+        if (h) s1[i] = q; else s0[i] = q;
+      }
+    }
+  }
+  if (MODE != ZI_PLAIN) {
+    double t1, t2;
+    block_sum2(acc1, acc2, &t1, &t2);
+    if (threadIdx.x == 0) {
+      const long long nb = gridDim.x;
+      partials[2 * (b * nb + blockIdx.x) + 0] = t1;
+      partials[2 * (b * nb + blockIdx.x) + 1] = t2;
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      const int e = threadIdx.x + i * kThreads;
+      if (e < N * WP) {
+        const int p = e % WP, z = e / WP;
+        float r0, r1;
+        if (a == 0) { r0 = los_comp(g, 0, x0 + p); r1 = los_comp(g, 0, x0 + p + WP); }
+        else if (a == 1) { r0 = ry; r1 = ry; }
+        else { r0 = los_comp(g, 2, z); r1 = r0; }
+        buf[z * LD + p] = make_float2(s0[i] * r0, s1[i] * r1);
+      }
+    }
+    __syncthreads();
+    tile_fft<N, WP, false>(buf, tw);
+    if (a == 2) z_unpack_store<N, WP, true>(buf, arr[a], y, x0, g.kf);
+    else z_unpack_store<N, WP, false>(buf, arr[a], y, x0, g.kf);
+    __syncthreads();
+  }
+}
+
+// Inverse z of the three displacement spectra: writes Psi_j (when psi != null),
+// u = Psi.r_hat (when u_out != null) and accumulates S3 = sum corr * u (when corr != null).
+template <int N>
+__global__ void __launch_bounds__(256) k_z_final(const float2* __restrict__ a0, const float2* __restrict__ a1,
+                                                 const float2* __restrict__ a2, Geo g, float* __restrict__ psi,
+                                                 float* __restrict__ u_out, const float* __restrict__ corr,
+                                                 double* __restrict__ partials, const int* __restrict__ active,
+                                                 const float2* __restrict__ twg) {
+  constexpr int WP = wz<N>(), LD = WP + 1;
+  constexpr int EPT = (N * WP + kThreads - 1) / kThreads;
+  const int b = blockIdx.y;
+  if (active && !active[b]) return;
+  __shared__ float2 buf[N * LD];
+  __shared__ float2 tw[N];
+  stage_twiddles<N>(tw, twg);
+  int y, x0;
+  z_tile_coords<N, WP>(y, x0);
+  const long long n3 = (long long)N * N * N, cn = (long long)(N / 2 + 1) * N * N;
+  const float2* arr[3] = {a0 + b * cn, a1 + b * cn, a2 + b * cn};
+  float s0[EPT], s1[EPT];
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) { s0[i] = 0.f; s1[i] = 0.f; }
+  const float ry = los_comp(g, 1, y);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    z_load_pack<N, WP>(buf, arr[a], y, x0);
+    __syncthreads();
+    tile_fft<N, WP, true>(buf, tw);
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      const int e = threadIdx.x + i * kThreads;
+      if (e < N * WP) {
+        const int p = e % WP, z = e / WP;
+        const float2 v = buf[z * LD + p];
+        const long long cell = ((long long)z * N + y) * N + x0 + p;
+        if (psi) {
+          float* pa = psi + (b * 3 + a) * n3;
+          pa[cell] = v.x;
+          pa[cell + WP] = v.y;
+        }
+        float r0, r1;
+        if (a == 0) { r0 = los_comp(g, 0, x0 + p); r1 = los_comp(g, 0, x0 + p + WP); }
+        else if (a == 1) { r0 = ry; r1 = ry; }
+        else { r0 = los_comp(g, 2, z); r1 = r0; }
+        s0[i] = fmaf(r0, v.x, s0[i]);
+        s1[i] = fmaf(r1, v.y, s1[i]);
+      }
+    }
+    __syncthreads();
+  }
+  if (!u_out && !corr) return;
+  double acc = 0.0;
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int e = threadIdx.x + i * kThreads;
+    if (e < N * WP) {
+      const int p = e % WP, z = e / WP;
+      const float rz = los_comp(g, 2, z);
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const float rx = los_comp(g, 0, x0 + p + h * WP);
+        const float r2 = rx * rx + ry * ry + rz * rz;
+        const float ir = r2 > 0.f ? rsqrtf(r2) : 0.f;
+        const float u = (h ? s1[i] : s0[i]) * ir;
+        const long long cell = b * n3 + ((long long)z * N + y) * N + x0 + p + h * WP;
+        if (u_out) u_out[cell] = u;
+        if (corr) acc += (double)corr[cell] * (double)u;
+      }
+    }
+  }
+  if (corr) {
+    double t1, t2;
+    block_sum2(acc, 0.0, &t1, &t2);
+    if (threadIdx.x == 0) partials[2 * ((long long)b * gridDim.x + blockIdx.x)] = t1,
+                          partials[2 * ((long long)b * gridDim.x + blockIdx.x) + 1] = 0.0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// y passes.  Tile: one kz plane, W consecutive x, all N rows.
+// ---------------------------------------------------------------------------
+template <int N, int W>
+__device__ __forceinline__ void y_tile_coords(int& p, int& x0) {
+  p = blockIdx.x / (N / W);
+  x0 = (blockIdx.x % (N / W)) * W;
+}
+
+template <int N, int W>
+__device__ __forceinline__ void y_load(float2* buf, const float2* __restrict__ a, int p, int x0) {
+  constexpr int LD = W + 1;
+  for (int e = threadIdx.x; e < N * W; e += kThreads) {
+    const int c = e % W, j = e / W;
+    buf[j * LD + c] = a[((long long)p * N + j) * N + x0 + c];
+  }
+}
+
+template <int N, int W>
+__device__ __forceinline__ void y_store(const float2* buf, float2* __restrict__ a, int p, int x0) {
+  constexpr int LD = W + 1;
+  for (int e = threadIdx.x; e < N * W; e += kThreads) {
+    const int c = e % W, j = e / W;
+    a[((long long)p * N + j) * N + x0 + c] = buf[j * LD + c];
+  }
+}
+
+template <int N, int NA, bool INV>
+__global__ void __launch_bounds__(256) k_y_plain(float2* __restrict__ a0, float2* __restrict__ a1,
+                                                 const float2* __restrict__ twg) {
+  constexpr int W = wy<N>(), LD = W + 1;
+  __shared__ float2 buf[N * LD];
+  __shared__ float2 tw[N];
+  stage_twiddles<N>(tw, twg);
+  int p, x0;
+  y_tile_coords<N, W>(p, x0);
+  const long long cn = (long long)(N / 2 + 1) * N * N;
+  const int b = blockIdx.y;
+#pragma unroll
+  for (int a = 0; a < NA; ++a) {
+    float2* arr = (a == 0 ? a0 : a1) + b * cn;
+    y_load<N, W>(buf, arr, p, x0);
+    __syncthreads();
+    tile_fft<N, W, INV>(buf, tw);
+    y_store<N, W>(buf, arr, p, x0);
+    __syncthreads();
+  }
+}
+
+// Inverse y with the displacement fan-out:
+//   a0 <- Y^-1[a0]                    (x component, i k'_x applied in the x pass)
+//   a1 <- Y^-1[i k'_y a1]             (y component)
+//   a2 <- i k'_z Y^-1[a1]             (z component)
+template <int N>
+__global__ void __launch_bounds__(256) k_y_fanout(float2* __restrict__ a0, float2* __restrict__ a1,
+                                                  float2* __restrict__ a2, Geo g, const int* __restrict__ active,
+                                                  const float2* __restrict__ twg) {
+  constexpr int W = wy<N>(), LD = W + 1;
+  constexpr int EPT = (N * W + kThreads - 1) / kThreads;
+  const int b = blockIdx.y;
+  if (active && !active[b]) return;
+  __shared__ float2 buf[N * LD];
+  __shared__ float2 tw[N];
+  stage_twiddles<N>(tw, twg);
+  int p, x0;
+  y_tile_coords<N, W>(p, x0);
+  const long long cn = (long long)(N / 2 + 1) * N * N;
+  a0 += b * cn; a1 += b * cn; a2 += b * cn;
+  y_load<N, W>(buf, a0, p, x0);
+  __syncthreads();
+  tile_fft<N, W, true>(buf, tw);
+  y_store<N, W>(buf, a0, p, x0);
+  __syncthreads();
+  float2 r[EPT];
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int e = threadIdx.x + i * kThreads;
+    if (e < N * W) {
+      const int c = e % W, j = e / W;
+      r[i] = a1[((long long)p * N + j) * N + x0 + c];
+      buf[j * LD + c] = mul_i(r[i]) * (g.kf * deriv_mode<N>(j));
+    }
+  }
+  __syncthreads();
+  tile_fft<N, W, true>(buf, tw);
+  y_store<N, W>(buf, a1, p, x0);
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int e = threadIdx.x + i * kThreads;
+    if (e < N * W) buf[(e / W) * LD + e % W] = r[i];
+  }
+  __syncthreads();
+  tile_fft<N, W, true>(buf, tw);
+  const float kz = g.kf * deriv_mode<N>(p);     // p in [0, N/2]; N/2 is the Nyquist plane
+  for (int e = threadIdx.x; e < N * W; e += kThreads) {
+    const int c = e % W, j = e / W;
+    a2[((long long)p * N + j) * N + x0 + c] = mul_i(buf[j * LD + c]) * kz;
+  }
+}
+
+// Forward y with the divergence fan-in:
+//   a0 <- Y[a0]                       (x component; i k'_x applied in the x pass)
+//   a1 <- i k'_y Y[a1] + Y[a2]        (y component plus the z component, already times i k'_z)
+template <int N>
+__global__ void __launch_bounds__(256) k_y_fanin(float2* __restrict__ a0, float2* __restrict__ a1,
+                                                 const float2* __restrict__ a2, Geo g,
+                                                 const int* __restrict__ active, const float2* __restrict__ twg) {
+  constexpr int W = wy<N>(), LD = W + 1;
+  constexpr int EPT = (N * W + kThreads - 1) / kThreads;
+  const int b = blockIdx.y;
+  if (active && !active[b]) return;
+  __shared__ float2 buf[N * LD];
+  __shared__ float2 tw[N];
+  stage_twiddles<N>(tw, twg);
+  int p, x0;
+  y_tile_coords<N, W>(p, x0);
+  const long long cn = (long long)(N / 2 + 1) * N * N;
+  a0 += b * cn; a1 += b * cn; a2 += b * cn;
+  y_load<N, W>(buf, a0, p, x0);
+  __syncthreads();
+  tile_fft<N, W, false>(buf, tw);
+  y_store<N, W>(buf, a0, p, x0);
+  __syncthreads();
+  y_load<N, W>(buf, a1, p, x0);
+  __syncthreads();
+  tile_fft<N, W, false>(buf, tw);
+  float2 r[EPT];
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int e = threadIdx.x + i * kThreads;
+    if (e < N * W) {
+      const int c = e % W, j = e / W;
+      r[i] = mul_i(buf[j * LD + c]) * (g.kf * deriv_mode<N>(j));
+    }
+  }
+  __syncthreads();
+  y_load<N, W>(buf, a2, p, x0);
+  __syncthreads();
+  tile_fft<N, W, false>(buf, tw);
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int e = threadIdx.x + i * kThreads;
+    if (e < N * W) {
+      const int c = e % W, j = e / W;
+      a1[((long long)p * N + j) * N + x0 + c] = r[i] + buf[j * LD + c];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// x passes.  Tile: W consecutive rows (row = kz * N + ky), all N x.
+// Element ownership e -> (j = e % N, c = e / N): contiguous global rows.
+// ---------------------------------------------------------------------------
+template <int N, int W>
+__device__ __forceinline__ void x_load(float2* buf, const float2* __restrict__ a, long long r0) {
+  constexpr int LD = W + 1;
+  for (int e = threadIdx.x; e < N * W; e += kThreads) {
+    const int j = e % N, c = e / N;
+    buf[j * LD + c] = a[(r0 + c) * N + j];
+  }
+}
+
+template <int N, int W>
+__device__ __forceinline__ void x_store(const float2* buf, float2* __restrict__ a, long long r0) {
+  constexpr int LD = W + 1;
+  for (int e = threadIdx.x; e < N * W; e += kThreads) {
+    const int j = e % N, c = e / N;
+    a[(r0 + c) * N + j] = buf[j * LD + c];
+  }
+}
+
+// k^2 and the derivative components of element (row, j) of an x tile.
+template <int N>
+__device__ __forceinline__ void x_wavenumbers(long long row, int j, float kf, float& k2, float& dx, float& dy,
+                                              float& dz, int& kzi) {
+  const int ky = (int)(row % N);
+  kzi = (int)(row / N);
+  const float mx = signed_mode<N>(j), my = signed_mode<N>(ky), mz = (float)kzi;
+  k2 = kf * kf * (mx * mx + my * my + mz * mz);
+  dx = kf * deriv_mode<N>(j);
+  dy = kf * deriv_mode<N>(ky);
+  dz = kzi == N / 2 ? 0.f : kf * mz;
+}
+
+// Forward x, Gaussian smoothing S(k) = exp(-k^2 R^2 / 2) with the 1/N^3 of the inverse, inverse x.
+template <int N, int NA>
+__global__ void __launch_bounds__(256) k_x_smooth(float2* __restrict__ a0, float2* __restrict__ a1, Geo g,
+                                                  const float2* __restrict__ twg) {
+  constexpr int W = wx<N>(), LD = W + 1;
+  __shared__ float2 buf[N * LD];
+  __shared__ float2 tw[N];
+  stage_twiddles<N>(tw, twg);
+  const long long cn = (long long)(N / 2 + 1) * N * N;
+  const long long r0 = (long long)blockIdx.x * W;
+  const int b = blockIdx.y;
+#pragma unroll
+  for (int a = 0; a < NA; ++a) {
+    float2* arr = (a == 0 ? a0 : a1) + b * cn;
+    x_load<N, W>(buf, arr, r0);
+    __syncthreads();
+    tile_fft<N, W, false>(buf, tw);
+    for (int e = threadIdx.x; e < N * W; e += kThreads) {
+      const int j = e % N, c = e / N;
+      float k2, dx, dy, dz;
+      int kzi;
+      x_wavenumbers<N>(r0 + c, j, g.kf, k2, dx, dy, dz, kzi);
+      buf[j * LD + c] = buf[j * LD + c] * (expf(-k2 * g.smooth_c) * g.inv_n3);
+    }
+    __syncthreads();
+    tile_fft<N, W, true>(buf, tw);
+    x_store<N, W>(buf, arr, r0);
+    __syncthreads();
+  }
+}
+
+// Forward x of the overdensity -> D_s (stored); P = D_s / (b k^2 N^3);
+// a0 <- X^-1[i k'_x P], a1 <- X^-1[P].
+template <int N>
+__global__ void __launch_bounds__(256) k_x_start(float2* __restrict__ a0, float2* __restrict__ a1,
+                                                 float2* __restrict__ ds, Geo g, const float2* __restrict__ twg) {
+  constexpr int W = wx<N>(), LD = W + 1;
+  constexpr int EPT = (N * W + kThreads - 1) / kThreads;
+  __shared__ float2 buf[N * LD];
+  __shared__ float2 tw[N];
+  stage_twiddles<N>(tw, twg);
+  const long long cn = (long long)(N / 2 + 1) * N * N;
+  const long long r0 = (long long)blockIdx.x * W;
+  const int b = blockIdx.y;
+  a0 += b * cn; a1 += b * cn; ds += b * cn;
+  x_load<N, W>(buf, a0, r0);
+  __syncthreads();
+  tile_fft<N, W, false>(buf, tw);
+  float2 pr[EPT];
+  float kxd[EPT];
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int e = threadIdx.x + i * kThreads;
+    if (e < N * W) {
+      const int j = e % N, c = e / N;
+      const float2 d = buf[j * LD + c];
+      ds[(r0 + c) * N + j] = d;
+      float k2, dx, dy, dz;
+      int kzi;
+      x_wavenumbers<N>(r0 + c, j, g.kf, k2, dx, dy, dz, kzi);
+      pr[i] = k2 > 0.f ? d * (g.inv_bn3 / k2) : make_float2(0.f, 0.f);
+      kxd[i] = dx;
+      buf[j * LD + c] = mul_i(pr[i]) * dx;
+    }
+  }
+  __syncthreads();
+  tile_fft<N, W, true>(buf, tw);
+  x_store<N, W>(buf, a0, r0);
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int e = threadIdx.x + i * kThreads;
+    if (e < N * W) buf[(e % N) * LD + e / N] = pr[i];
+  }
+  __syncthreads();
+  tile_fft<N, W, true>(buf, tw);
+  x_store<N, W>(buf, a1, r0);
+}
+
+// One iteration's k-space step:
+//   div = i k'_x X[a0] + X[a1];  D_{n+1} = D_s + f div  (stored to dnext)
+//   partial sums of  sum w k'^2 |D_{n+1} - D_n|^2 / k^4  and  sum w k'^2 |D_{n+1}|^2 / k^4
+//   (w = 2 inside the halved kz axis) -> convergence norm by Parseval
+//   P = D_{n+1} / (b k^2 N^3);  a0 <- X^-1[i k'_x P],  a1 <- X^-1[P]
+// dprev and dnext may be the same buffer (element-wise in place).
+template <int N>
+__global__ void __launch_bounds__(256) k_x_iter(float2* __restrict__ a0, float2* __restrict__ a1,
+                                                const float2* __restrict__ ds, const float2* dprev,
+                                                float2* dnext, Geo g, double* __restrict__ partials,
+                                                const int* __restrict__ active, const float2* __restrict__ twg) {
+  constexpr int W = wx<N>(), LD = W + 1;
+  constexpr int EPT = (N * W + kThreads - 1) / kThreads;
+  const int b = blockIdx.y;
+  if (active && !active[b]) return;
+  __shared__ float2 buf[N * LD];
+  __shared__ float2 tw[N];
+  stage_twiddles<N>(tw, twg);
+  const long long cn = (long long)(N / 2 + 1) * N * N;
+  const long long r0 = (long long)blockIdx.x * W;
+  a0 += b * cn; a1 += b * cn; ds += b * cn; dprev += b * cn; dnext += b * cn;
+  x_load<N, W>(buf, a0, r0);
+  __syncthreads();
+  tile_fft<N, W, false>(buf, tw);
+  float2 r[EPT];
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int e = threadIdx.x + i * kThreads;
+    if (e < N * W) r[i] = buf[(e % N) * LD + e / N];
+  }
+  __syncthreads();
+  x_load<N, W>(buf, a1, r0);
+  __syncthreads();
+  tile_fft<N, W, false>(buf, tw);
+  double num = 0.0, den = 0.0;
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int e = threadIdx.x + i * kThreads;
+    if (e < N * W) {
+      const int j = e % N, c = e / N;
+      float k2, dx, dy, dz;
+      int kzi;
+      x_wavenumbers<N>(r0 + c, j, g.kf, k2, dx, dy, dz, kzi);
+      const float2 div = mul_i(r[i]) * dx + buf[j * LD + c];
+      const long long idx = (r0 + c) * N + j;
+      const float2 dsv = ds[idx];
+      const float2 dn = make_float2(fmaf(g.growth, div.x, dsv.x), fmaf(g.growth, div.y, dsv.y));
+      const float2 dp = dprev[idx];
+      dnext[idx] = dn;
+      if (k2 > 0.f) {
+        const float wgt = (kzi == 0 || kzi == N / 2) ? 1.f : 2.f;
+        const float kd2 = dx * dx + dy * dy + dz * dz;
+        const float f = wgt * kd2 / (k2 * k2);
+        const float ex = dn.x - dp.x, ey = dn.y - dp.y;
+        num += (double)(f * (ex * ex + ey * ey));
+        den += (double)(f * (dn.x * dn.x + dn.y * dn.y));
+        r[i] = dn * (g.inv_bn3 / k2);
+      } else {
+        r[i] = make_float2(0.f, 0.f);
+      }
+    }
+  }
+  __syncthreads();
+  {
+    double t1, t2;
+    block_sum2(num, den, &t1, &t2);
+    if (threadIdx.x == 0) {
+      partials[2 * ((long long)b * gridDim.x + blockIdx.x) + 0] = t1;
+      partials[2 * ((long long)b * gridDim.x + blockIdx.x) + 1] = t2;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int e = threadIdx.x + i * kThreads;
+    if (e < N * W) {
+      const int j = e % N;
+      buf[j * LD + e / N] = mul_i(r[i]) * (g.kf * deriv_mode<N>(j));
+    }
+  }
+  __syncthreads();
+  tile_fft<N, W, true>(buf, tw);
+  x_store<N, W>(buf, a0, r0);
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int e = threadIdx.x + i * kThreads;
+    if (e < N * W) buf[(e % N) * LD + e / N] = r[i];
+  }
+  __syncthreads();
+  tile_fft<N, W, true>(buf, tw);
+  x_store<N, W>(buf, a1, r0);
+}
+
+// Fixed-order reduction of per-block partial pairs: out[b] = sum over blocks.
+__global__ void __launch_bounds__(256) k_reduce_pairs(const double* __restrict__ partials, int nblk,
+                                                      double* __restrict__ out) {
+  const int b = blockIdx.x;
+  double s0 = 0.0, s1 = 0.0;
+  for (int i = threadIdx.x; i < nblk; i += kThreads) {
+    s0 += partials[2 * ((long long)b * nblk + i)];
+    s1 += partials[2 * ((long long)b * nblk + i) + 1];
+  }
+  double t0, t1;
+  block_sum2(s0, s1, &t0, &t1);
+  if (threadIdx.x == 0) { out[2 * b] = t0; out[2 * b + 1] = t1; }
+}
+
+// ---------------------------------------------------------------------------
+// Shift: CIC interpolation of Psi at each object with the deposit's stencil.
+//   galaxies: disp = -Psi - f (Psi . r_hat) r_hat;  randoms: disp = -Psi
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_shift(const float* __restrict__ pos, long long n,
+                                               const long long* __restrict__ off, int batch,
+                                               const float* __restrict__ psi, CicGeo cg, float ox, float oy,
+                                               float oz, float growth, int galaxies, float* __restrict__ disp,
+                                               float* __restrict__ pos_out, int* __restrict__ err) {
+  const long long n3 = (long long)cg.n * cg.n * cg.n;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    float uu[3];
+    bool ok = true;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      float d = __fsub_rn(pos[3 * i + a], cg.o[a]);
+      uu[a] = __fmul_rn(d, cg.s);
+      ok = ok && (fabsf(uu[a]) < 1073741824.0f);
+    }
+    if (!ok) {
+      atomicAdd(err, 1);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) disp[3 * i + a] = 0.f;
+      continue;
+    }
+    int ii[3];
+    float t[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      float fl = floorf(uu[a]);
+      t[a] = __fsub_rn(uu[a], fl);
+      ii[a] = ((int)fl) & (cg.n - 1);
+    }
+    const int b = off ? find_realisation(off, batch, i) : 0;
+    const float* pb = psi + (long long)b * 3 * n3;
+    float p0 = 0.f, p1 = 0.f, p2 = 0.f;
+#pragma unroll
+    for (int cnr = 0; cnr < 8; ++cnr) {
+      const int dx = cnr & 1, dy = (cnr >> 1) & 1, dz = cnr >> 2;
+      const float wgt = (dx ? t[0] : 1.f - t[0]) * (dy ? t[1] : 1.f - t[1]) * (dz ? t[2] : 1.f - t[2]);
+      const long long idx = (((long long)((ii[2] + dz) & (cg.n - 1)) * cg.n + ((ii[1] + dy) & (cg.n - 1))) * cg.n) +
+                            ((ii[0] + dx) & (cg.n - 1));
+      p0 = fmaf(wgt, pb[idx], p0);
+      p1 = fmaf(wgt, pb[n3 + idx], p1);
+      p2 = fmaf(wgt, pb[2 * n3 + idx], p2);
+    }
+    float d0 = -p0, d1 = -p1, d2 = -p2;
+    if (galaxies && growth != 0.f) {
+      const float rx = pos[3 * i] - ox, ry = pos[3 * i + 1] - oy, rz = pos[3 * i + 2] - oz;
+      const float r2 = rx * rx + ry * ry + rz * rz;
+      if (r2 > 0.f) {
+        const float ir = rsqrtf(r2);
+        const float hx = rx * ir, hy = ry * ir, hz = rz * ir;
+        const float u = growth * (p0 * hx + p1 * hy + p2 * hz);
+        d0 -= u * hx;
+        d1 -= u * hy;
+        d2 -= u * hz;
+      }
+    }
+    disp[3 * i] = d0;
+    disp[3 * i + 1] = d1;
+    disp[3 * i + 2] = d2;
+    if (pos_out) {
+      pos_out[3 * i] = pos[3 * i] + d0;
+      pos_out[3 * i + 1] = pos[3 * i + 1] + d1;
+      pos_out[3 * i + 2] = pos[3 * i + 2] + d2;
+    }
+  }
+}
+
+}  // namespace recon

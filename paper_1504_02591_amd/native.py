@@ -1,0 +1,235 @@
+"""ctypes binding of the C ABI in include/recon.h (argument marshalling only).
+
+Every step of the reconstruction runs in the HIP library; this module only
+checks shapes and dtypes, passes device pointers and the current HIP stream,
+and turns return codes into exceptions.  PyTorch provides device memory and
+the stream.  Loading fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_NAME = "librecon.so"
+
+RECON_OK, RECON_NOTCONVERGED = 0, 1
+RECON_EINVAL, RECON_ENOMEM, RECON_EDEVICE, RECON_ESTATE, RECON_EDIVERGED = -1, -2, -3, -4, -5
+GAL, RAN = 0, 1
+START_PLAIN, START_FFTA1, START_FFTA2, START_LEARNED = 0, 1, 2, 3
+NO_RANDOMS, KEEP_DELTA, START_BUFFERS = 1, 2, 4
+PAINT_ACCUMULATE = 1
+
+EXPORTED = ("recon_workspace_bytes", "recon_plan", "recon_paint", "recon_solve", "recon_iterate",
+            "recon_shift", "recon_get_psi", "recon_get_grid", "recon_get_delta", "recon_set_delta",
+            "recon_destroy", "recon_strerror", "recon_last_error", "recon_profile_start",
+            "recon_profile_stop", "recon_profile_kernel_name")
+
+
+class ReconError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"recon error {code}: {msg}")
+        self.code = code
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("batch", ctypes.c_int32), ("box_len", ctypes.c_double),
+                ("box_origin", ctypes.c_double * 3), ("observer", ctypes.c_double * 3),
+                ("bias", ctypes.c_double), ("growth", ctypes.c_double), ("smooth_r", ctypes.c_double),
+                ("mask_tau", ctypes.c_double), ("flags", ctypes.c_uint32)]
+
+
+_LIB = None
+
+
+def lib_path():
+    return os.path.join(_HERE, LIB_NAME)
+
+
+def load(path=None):
+    """Load the built HIP library (raises if it has not been built)."""
+    global _LIB
+    if _LIB is not None and path is None:
+        return _LIB
+    p = path or lib_path()
+    if not os.path.exists(p):
+        raise RuntimeError(f"HIP library {p} is missing; build it with __graft_entry__.build()")
+    lib = ctypes.CDLL(p)
+    vp, i64, i32, u32, dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint32, ctypes.c_double
+    lib.recon_workspace_bytes.argtypes = [ctypes.POINTER(Params)]
+    lib.recon_workspace_bytes.restype = ctypes.c_size_t
+    lib.recon_plan.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(Params), vp, ctypes.c_size_t, vp]
+    lib.recon_paint.argtypes = [vp, ctypes.c_int, vp, vp, i64, vp, u32]
+    lib.recon_solve.argtypes = [vp, ctypes.c_int, vp]
+    lib.recon_iterate.argtypes = [vp, ctypes.c_int, dbl, ctypes.POINTER(i32), ctypes.POINTER(dbl)]
+    lib.recon_shift.argtypes = [vp, ctypes.c_int, vp, i64, vp, vp, vp]
+    lib.recon_get_psi.argtypes = [vp, vp]
+    lib.recon_get_grid.argtypes = [vp, ctypes.c_int, vp]
+    lib.recon_get_delta.argtypes = [vp, vp]
+    lib.recon_set_delta.argtypes = [vp, vp]
+    lib.recon_destroy.argtypes = [vp]
+    lib.recon_destroy.restype = None
+    lib.recon_strerror.argtypes = [ctypes.c_int]
+    lib.recon_strerror.restype = ctypes.c_char_p
+    lib.recon_last_error.argtypes = [vp]
+    lib.recon_last_error.restype = ctypes.c_char_p
+    lib.recon_profile_start.argtypes = [vp]
+    lib.recon_profile_stop.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(dbl), ctypes.c_int]
+    lib.recon_profile_kernel_name.argtypes = [ctypes.c_int]
+    lib.recon_profile_kernel_name.restype = ctypes.c_char_p
+    for name in ("recon_profile_start", "recon_profile_stop", "recon_plan", "recon_paint", "recon_solve", "recon_iterate", "recon_shift",
+                 "recon_get_psi", "recon_get_grid", "recon_get_delta", "recon_set_delta"):
+        getattr(lib, name).restype = ctypes.c_int
+    if path is None:
+        _LIB = lib
+    return lib
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _check_dev(t, dtype, shape_tail, name, device):
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.device != device:
+        raise ValueError(f"{name} must live on {device}")
+    if shape_tail is not None and tuple(t.shape[1:]) != tuple(shape_tail):
+        raise ValueError(f"{name} must have shape [n, {shape_tail}]")
+
+
+class Plan:
+    """A reconstruction plan: workspace, geometry, and the C-ABI calls on the current stream."""
+
+    def __init__(self, n, box_len, observer, bias, growth, smooth_r, origin=(0.0, 0.0, 0.0), batch=1,
+                 mask_tau=0.1, randoms=True, keep_delta=False, start_buffers=False, device=None):
+        self.lib = load()
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        flags = (0 if randoms else NO_RANDOMS) | (KEEP_DELTA if keep_delta else 0) | \
+                (START_BUFFERS if start_buffers else 0)
+        p = Params()
+        p.n, p.batch, p.box_len = int(n), int(batch), float(box_len)
+        for a in range(3):
+            p.box_origin[a] = float(origin[a])
+            p.observer[a] = float(observer[a])
+        p.bias, p.growth, p.smooth_r, p.mask_tau, p.flags = float(bias), float(growth), float(smooth_r), \
+            float(mask_tau), flags
+        self.params = p
+        self.n, self.batch, self.randoms = int(n), int(batch), randoms
+        nbytes = self.lib.recon_workspace_bytes(ctypes.byref(p))
+        if nbytes == 0:
+            raise ReconError(RECON_EINVAL, "invalid parameters")
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        rc = self.lib.recon_plan(ctypes.byref(h), ctypes.byref(p), _ptr(self.workspace), nbytes,
+                                 ctypes.c_void_p(self.stream.cuda_stream))
+        if rc != RECON_OK:
+            raise ReconError(rc, self.lib.recon_strerror(rc).decode())
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            torch.cuda.synchronize(self.device)
+            self.lib.recon_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _rc(self, rc, allow=(RECON_OK,)):
+        if rc in allow:
+            return rc
+        msg = self.lib.recon_last_error(self.handle).decode()
+        raise ReconError(rc, msg or self.lib.recon_strerror(rc).decode())
+
+    def paint(self, which, pos, w=None, offsets=None, accumulate=False):
+        _check_dev(pos, torch.float32, (3,), "pos", self.device)
+        if w is not None:
+            _check_dev(w, torch.float32, None, "w", self.device)
+            if w.numel() != pos.shape[0]:
+                raise ValueError("w must have one entry per object")
+        if offsets is not None:
+            _check_dev(offsets, torch.int64, None, "offsets", self.device)
+            if offsets.numel() != self.batch + 1:
+                raise ValueError("offsets must have batch + 1 entries")
+        return self._rc(self.lib.recon_paint(self.handle, which, _ptr(pos), _ptr(w), pos.shape[0], _ptr(offsets),
+                                             PAINT_ACCUMULATE if accumulate else 0))
+
+    def set_delta(self, delta):
+        _check_dev(delta, torch.float32, None, "delta", self.device)
+        if delta.numel() != self.batch * self.n ** 3:
+            raise ValueError("delta must hold batch * n^3 values")
+        return self._rc(self.lib.recon_set_delta(self.handle, _ptr(delta)))
+
+    def solve(self, start=START_PLAIN, net=None):
+        return self._rc(self.lib.recon_solve(self.handle, int(start), _ptr(net)))
+
+    def iterate(self, max_iter, tol):
+        """Returns (code, passes per realisation, eps history [batch][<=max_iter])."""
+        iters = (ctypes.c_int32 * self.batch)()
+        eps = (ctypes.c_double * (self.batch * max(max_iter, 1)))()
+        rc = self._rc(self.lib.recon_iterate(self.handle, int(max_iter), float(tol), iters, eps),
+                      allow=(RECON_OK, RECON_NOTCONVERGED))
+        hist = []
+        for b in range(self.batch):
+            row = [eps[b * max_iter + i] for i in range(max_iter)]
+            hist.append([e for e in row if not math.isnan(e)])
+        return rc, list(iters), hist
+
+    def shift(self, which, pos, offsets=None, want_pos=False, out_disp=None, out_pos=None):
+        _check_dev(pos, torch.float32, (3,), "pos", self.device)
+        disp = torch.empty_like(pos) if out_disp is None else out_disp
+        out = (torch.empty_like(pos) if out_pos is None else out_pos) if want_pos else None
+        _check_dev(disp, torch.float32, (3,), "out_disp", self.device)
+        if disp.shape != pos.shape or (out is not None and out.shape != pos.shape):
+            raise ValueError("output buffers must match pos")
+        self._rc(self.lib.recon_shift(self.handle, which, _ptr(pos), pos.shape[0], _ptr(offsets), _ptr(disp),
+                                      _ptr(out)))
+        return (disp, out) if want_pos else disp
+
+    def profile_start(self):
+        return self._rc(self.lib.recon_profile_start(self.handle))
+
+    def profile_stop(self):
+        """Per-kernel {name: (launches, total_ms)} recorded since profile_start."""
+        cap = 64
+        counts = (ctypes.c_int32 * cap)()
+        tot = (ctypes.c_double * cap)()
+        k = self.lib.recon_profile_stop(self.handle, counts, tot, cap)
+        if k < 0:
+            self._rc(k)
+        out = {}
+        for i in range(min(k, cap)):
+            if counts[i]:
+                out[self.lib.recon_profile_kernel_name(i).decode()] = (int(counts[i]), float(tot[i]))
+        return out
+
+    def psi(self):
+        out = torch.empty((self.batch, 3, self.n, self.n, self.n), dtype=torch.float32, device=self.device)
+        self._rc(self.lib.recon_get_psi(self.handle, _ptr(out)))
+        return out
+
+    def grid(self, which):
+        out = torch.empty((self.batch, self.n, self.n, self.n), dtype=torch.int64, device=self.device)
+        self._rc(self.lib.recon_get_grid(self.handle, which, _ptr(out)))
+        return out
+
+    def delta(self):
+        out = torch.empty((self.batch, self.n, self.n, self.n), dtype=torch.float32, device=self.device)
+        self._rc(self.lib.recon_get_delta(self.handle, _ptr(out)))
+        return out
+
+
+def plan_for(cat, **kw):
+    """Plan matching a synthetic catalogue's geometry."""
+    return Plan(cat.n, cat.box_len, cat.observer, cat.bias, cat.growth, cat.smooth_r, origin=cat.origin,
+                mask_tau=cat.mask_tau, randoms=cat.ran_pos is not None, **kw)

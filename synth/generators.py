@@ -15,6 +15,7 @@ sight, and uniform randoms inside the survey geometry.
 from __future__ import annotations
 
 import math
+import os
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -23,6 +24,7 @@ from scipy import integrate
 
 SIGMA8 = 0.8
 K_TURN = 0.02
+WORKERS = min(16, len(os.sched_getaffinity(0)))
 
 
 @dataclass
@@ -71,7 +73,7 @@ def linear_field(n, box_len, seed, want_psi=True, dtype=np.float64):
     rng = np.random.default_rng(seed)
     ctype = np.complex128 if dtype == np.float64 else np.complex64
     wn = rng.standard_normal((n, n, n), dtype=dtype)
-    fk = sfft.rfftn(wn, workers=-1).astype(ctype, copy=False)
+    fk = sfft.rfftn(wn, workers=WORKERS).astype(ctype, copy=False)
     del wn
     amp = power_amplitude()
     mf = np.fft.fftfreq(n, d=1.0 / n)
@@ -85,7 +87,7 @@ def linear_field(n, box_len, seed, want_psi=True, dtype=np.float64):
         scale = np.sqrt(amp * _shape_pk(kk) * n ** 3 / box_len ** 3)
     scale[0, 0, 0] = 0.0
     fk *= scale.astype(dtype)
-    delta = sfft.irfftn(fk, s=(n, n, n), workers=-1).astype(dtype, copy=False)
+    delta = sfft.irfftn(fk, s=(n, n, n), workers=WORKERS).astype(dtype, copy=False)
     psi = None
     if want_psi:
         k2 = kx * kx + ky * ky + kz * kz
@@ -95,7 +97,7 @@ def linear_field(n, box_len, seed, want_psi=True, dtype=np.float64):
         dx = np.where(mh == n // 2, 0.0, mh * sc).reshape(1, 1, n // 2 + 1)
         psi = np.empty((3, n, n, n), dtype=dtype)
         for j, d in enumerate((dx, dy, dz)):
-            psi[j] = sfft.irfftn(fk * (1j * d / k2).astype(ctype), s=(n, n, n), workers=-1)
+            psi[j] = sfft.irfftn(fk * (1j * d / k2).astype(ctype), s=(n, n, n), workers=WORKERS)
     return delta, psi
 
 

@@ -1,0 +1,330 @@
+"""GPU path vs the FP64 oracle, element by element, through the C ABI.
+
+Bars: int64 deposit grids bit-exact; Psi within 1e-5 relative L2 (all cells,
+three components); displacements within 1e-4 Mpc/h max-abs; convergence norms
+within 1e-5 absolute.  Parity runs use fixed pass counts.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import recon_oracle as O
+from synth import generators as G
+
+pytestmark = pytest.mark.gpu
+
+PSI_TOL = 1e-5
+DISP_TOL = 1e-4
+
+
+def dev():
+    return torch.device("cuda", 0)
+
+
+def to_dev(a):
+    return None if a is None else torch.from_numpy(np.ascontiguousarray(a)).to(dev())
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / np.linalg.norm(b))
+
+
+def gpu_catalogue_run(native, cat, n_passes, start=0, keep_delta=True, tol=0.0):
+    plan = native.plan_for(cat, keep_delta=keep_delta, start_buffers=start != 0)
+    gal, ran = to_dev(cat.gal_pos), to_dev(cat.ran_pos)
+    plan.paint(native.GAL, gal, to_dev(cat.gal_w))
+    if ran is not None:
+        plan.paint(native.RAN, ran, to_dev(cat.ran_w))
+    plan.solve(start)
+    rc, iters, eps = plan.iterate(n_passes, tol)
+    out = dict(rc=rc, iters=iters[0], eps=eps[0], psi=plan.psi()[0].cpu().numpy(),
+               grid_g=plan.grid(native.GAL)[0].cpu().numpy(),
+               disp_g=plan.shift(native.GAL, gal).cpu().numpy())
+    if ran is not None:
+        out["grid_r"] = plan.grid(native.RAN)[0].cpu().numpy()
+        out["disp_r"] = plan.shift(native.RAN, ran).cpu().numpy()
+    if keep_delta:
+        out["delta"] = plan.delta()[0].cpu().numpy()
+    plan.close()
+    return out
+
+
+def oracle_catalogue_run(cat, n_passes, start=0):
+    return O.reconstruct(cat.gal_pos, cat.gal_w, cat.ran_pos, cat.ran_w, cat.n, cat.box_len, cat.origin,
+                         cat.observer, cat.bias, cat.growth, cat.smooth_r, cat.mask_tau, n_passes=n_passes,
+                         start=start)
+
+
+def compare_full(g, r, label):
+    assert np.array_equal(g["grid_g"], r["grid_g"]), f"{label}: galaxy grid not bit-exact"
+    if "grid_r" in g and r["grid_r"] is not None:
+        assert np.array_equal(g["grid_r"], r["grid_r"]), f"{label}: random grid not bit-exact"
+    e_psi = rel_l2(g["psi"], r["psi"])
+    e_dg = float(np.abs(g["disp_g"] - r["disp_g"]).max())
+    print(f"{label}: psi relL2={e_psi:.2e} disp_g max={e_dg:.2e}", flush=True)
+    assert e_psi <= PSI_TOL, f"{label}: psi rel L2 {e_psi}"
+    assert e_dg <= DISP_TOL, f"{label}: galaxy displacement {e_dg}"
+    if "disp_r" in g and "disp_r" in r:
+        e_dr = float(np.abs(g["disp_r"] - r["disp_r"]).max())
+        assert e_dr <= DISP_TOL, f"{label}: random displacement {e_dr}"
+    if "delta" in g:
+        e_d = rel_l2(g["delta"], r["delta_s"])
+        assert e_d <= PSI_TOL, f"{label}: delta rel L2 {e_d}"
+    ge, re_ = np.array(g["eps"]), np.array(r["eps"])
+    assert ge.shape == re_.shape
+    np.testing.assert_allclose(ge, re_, rtol=1e-4, atol=1e-6)
+
+
+# ---------------------------------------------------------------------------
+# Deposit
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("n", [8, 32, 128])
+def test_paint_bitexact_with_weights_wrap_and_order(gpu_lib, n):
+    from paper_1504_02591_amd import native
+    rng = np.random.default_rng(100 + n)
+    box = 300.0
+    m = 40000
+    pos = (rng.random((m, 3)) * 1.4 * box - 0.2 * box).astype(np.float32)
+    pos[:5] = [[0, 0, 0], [box, box, box], [-1e-3, 0, 0], [box * 0.5, 0, box - 1e-4], [1e-7, 1e-7, 1e-7]]
+    w = (rng.random(m) * 10).astype(np.float32)
+    w[:3] = [0.0, np.float32(2.0 ** -40), np.float32(63.999)]
+    plan = native.Plan(n, box, (-100.0, 0.0, 0.0), 1.0, 0.5, 10.0, randoms=True)
+    plan.paint(native.GAL, to_dev(pos), to_dev(w))
+    perm = rng.permutation(m)
+    plan.paint(native.RAN, to_dev(pos[perm]), to_dev(w[perm]))
+    gg = plan.grid(native.GAL)[0].cpu().numpy()
+    gr = plan.grid(native.RAN)[0].cpu().numpy()
+    ref = O.paint(pos, w, n, box, (0.0, 0.0, 0.0))
+    assert np.array_equal(gg, ref)
+    assert np.array_equal(gr, ref)
+    assert int(gg.sum()) == int(O.quantise_weights(w, m).sum())
+    plan.close()
+
+
+def test_paint_accumulate_equals_single_call(gpu_lib):
+    from paper_1504_02591_amd import native
+    rng = np.random.default_rng(7)
+    pos = (rng.random((10000, 3)) * 100).astype(np.float32)
+    plan = native.Plan(16, 100.0, (50.0, 50.0, 50.0), 1.0, 0.5, 10.0, randoms=False)
+    plan.paint(native.GAL, to_dev(pos[:3000]))
+    plan.paint(native.GAL, to_dev(pos[3000:]), accumulate=True)
+    g = plan.grid(native.GAL)[0].cpu().numpy()
+    assert np.array_equal(g, O.paint(pos, None, 16, 100.0, (0, 0, 0)))
+    plan.close()
+
+
+# ---------------------------------------------------------------------------
+# Transforms and the iteration, fed through the delta hook
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("n", [8, 16, 32, 64])
+def test_plane_wave_displacement_gpu(gpu_lib, n):
+    from paper_1504_02591_amd import native
+    box, amp, ph, b = 400.0, 0.3, 0.7, 1.7
+    for modes in [(1, 0, 0), (0, 1, 2), (n // 2 - 1, -2, 1), (3, -1, n // 2 - 1)]:
+        delta, k0 = G.plane_wave(n, box, modes, amp, ph)
+        plan = native.Plan(n, box, (-1e4, 0, 0), b, 0.0, 0.0, randoms=False)
+        plan.set_delta(to_dev(delta.astype(np.float32)))
+        plan.solve()
+        plan.iterate(1, 0.0)
+        psi = plan.psi()[0].cpu().numpy()
+        plan.close()
+        h = box / n
+        i = np.arange(n) * h
+        z, y, x = np.meshgrid(i, i, i, indexing="ij")
+        arg = k0[0] * x + k0[1] * y + k0[2] * z + ph
+        expect = np.stack([-(amp / (b * float(k0 @ k0))) * k0[j] * np.sin(arg) for j in range(3)])
+        assert rel_l2(psi, expect) < PSI_TOL, modes
+
+
+@pytest.mark.parametrize("n,observer", [(8, (31.3, 47.9, 52.1)), (16, (-80.0, 130.0, 60.0)),
+                                        (32, (150.0, 150.0, 150.0)), (64, (-300.0, 100.0, 250.0)),
+                                        (128, (200.0, 200.0, 200.0))])
+def test_random_field_iterates_match_oracle(gpu_lib, n, observer):
+    from paper_1504_02591_amd import native
+    box, b, f = 400.0, 1.5, 0.6
+    rng = np.random.default_rng(200 + n)
+    delta = O.smooth(rng.standard_normal((n, n, n)), box, 2.5 * box / n)
+    for npass in (1, 3):
+        plan = native.Plan(n, box, observer, b, f, 0.0, randoms=False)
+        plan.set_delta(to_dev(delta.astype(np.float32)))
+        plan.solve()
+        rc, iters, eps = plan.iterate(npass, 0.0)
+        psi = plan.psi()[0].cpu().numpy()
+        plan.close()
+        ref = O.reconstruct_field(delta.astype(np.float32).astype(np.float64), box, (0, 0, 0), observer, b, f,
+                                  n_passes=npass)
+        e = rel_l2(psi, ref["psi"])
+        print(f"n={n} passes={npass} relL2={e:.2e}", flush=True)
+        assert iters[0] == npass
+        assert e < PSI_TOL
+        np.testing.assert_allclose(eps[0], ref["eps"], rtol=1e-4, atol=1e-6)
+
+
+@pytest.mark.parametrize("axis", [0, 2])
+def test_distant_observer_closed_form_gpu(gpu_lib, axis):
+    from paper_1504_02591_amd import native
+    n, box, b, f = 32, 400.0, 2.0, 0.74
+    beta = f / b
+    rng = np.random.default_rng(31 + axis)
+    delta = O.smooth(rng.standard_normal((n, n, n)), box, 30.0).astype(np.float32)
+    obs = [box / 2] * 3
+    obs[axis] -= 1e9 * box
+    plan = native.Plan(n, box, obs, b, f, 0.0, randoms=False)
+    plan.set_delta(to_dev(delta))
+    plan.solve()
+    plan.iterate(4, 0.0)
+    psi = plan.psi()[0].cpu().numpy()
+    plan.close()
+    d = delta.astype(np.float64)
+    m = np.fft.fftfreq(n, d=1.0 / n)
+    kk = [(2 * np.pi / box) * m.reshape(1, 1, -1), (2 * np.pi / box) * m.reshape(1, -1, 1),
+          (2 * np.pi / box) * m.reshape(-1, 1, 1)]
+    mm = [m.reshape(1, 1, -1), m.reshape(1, -1, 1), m.reshape(-1, 1, 1)]
+    dk = [np.where(np.abs(a) == n // 2, 0.0, k) for a, k in zip(mm, kk)]
+    k2 = kk[0] ** 2 + kk[1] ** 2 + kk[2] ** 2
+    with np.errstate(invalid="ignore", divide="ignore"):
+        mu2 = np.where(k2 > 0, dk[axis] ** 2 / k2, 0.0)
+        dn = np.fft.fftn(d) * (1 - (-beta * mu2) ** 5) / (1 + beta * mu2)
+        pot = np.where(k2 > 0, dn / (b * k2), 0.0)
+    expect = np.stack([np.real(np.fft.ifftn(1j * dk[j] * pot)) for j in range(3)])
+    assert rel_l2(psi, expect) < PSI_TOL
+
+
+# ---------------------------------------------------------------------------
+# End to end on catalogues
+# ---------------------------------------------------------------------------
+def test_config1_end_to_end(gpu_lib):
+    from paper_1504_02591_amd import native
+    cat = G.config1()
+    g = gpu_catalogue_run(native, cat, 6)
+    r = oracle_catalogue_run(cat, 6)
+    compare_full(g, r, "config1")
+
+
+def test_survey_cone_small(gpu_lib):
+    from paper_1504_02591_amd import native
+    cat = G.config2(n=128, scale=0.25)
+    g = gpu_catalogue_run(native, cat, 5)
+    r = oracle_catalogue_run(cat, 5)
+    compare_full(g, r, "survey128")
+
+
+def test_mean_density_mode(gpu_lib):
+    from paper_1504_02591_amd import native
+    cat = G.config3(n=64)
+    g = gpu_catalogue_run(native, cat, 4)
+    r = oracle_catalogue_run(cat, 4)
+    compare_full(g, r, "meandensity64")
+
+
+@pytest.mark.parametrize("start", [1, 2])
+def test_ffta_starts(gpu_lib, start):
+    from paper_1504_02591_amd import native
+    cat = G.lattice_box(32, 500.0, (-500.0, 250.0, 250.0), 0.7, 21, 22, ran_factor=3, bias=1.2, smooth_r=20.0)
+    for npass in (1, 2, 4):
+        g = gpu_catalogue_run(native, cat, npass, start=start)
+        r = oracle_catalogue_run(cat, npass, start=start)
+        compare_full(g, r, f"ffta{start}-{npass}")
+
+
+def test_batched_matches_single_realisations(gpu_lib):
+    from paper_1504_02591_amd import native
+    cats = [G.lattice_box(32, 500.0, (-500.0, 250.0, 250.0), 0.7, 30 + i, 40 + i, ran_factor=2, bias=1.0,
+                          smooth_r=20.0, n_part=24 + 4 * i) for i in range(3)]
+    gal = np.concatenate([c.gal_pos for c in cats])
+    ran = np.concatenate([c.ran_pos for c in cats])
+    goff = np.cumsum([0] + [c.gal_pos.shape[0] for c in cats]).astype(np.int64)
+    roff = np.cumsum([0] + [c.ran_pos.shape[0] for c in cats]).astype(np.int64)
+    c0 = cats[0]
+    plan = native.Plan(32, 500.0, c0.observer, 1.0, 0.7, 20.0, batch=3)
+    plan.paint(native.GAL, to_dev(gal), offsets=to_dev(goff))
+    plan.paint(native.RAN, to_dev(ran), offsets=to_dev(roff))
+    plan.solve()
+    rc, iters, eps = plan.iterate(3, 0.0)
+    psi = plan.psi().cpu().numpy()
+    disp = plan.shift(native.GAL, to_dev(gal), offsets=to_dev(goff)).cpu().numpy()
+    grids = plan.grid(native.GAL).cpu().numpy()
+    plan.close()
+    for i, c in enumerate(cats):
+        r = oracle_catalogue_run(c, 3)
+        assert np.array_equal(grids[i], r["grid_g"])
+        assert rel_l2(psi[i], r["psi"]) < PSI_TOL
+        assert np.abs(disp[goff[i]:goff[i + 1]] - r["disp_g"]).max() < DISP_TOL
+        np.testing.assert_allclose(eps[i], r["eps"], rtol=1e-4, atol=1e-6)
+
+
+# ---------------------------------------------------------------------------
+# Tolerance mode, divergence and errors
+# ---------------------------------------------------------------------------
+def test_tolerance_mode_counts_passes(gpu_lib):
+    from paper_1504_02591_amd import native
+    cat = G.lattice_box(32, 500.0, (-500.0, 250.0, 250.0), 0.5, 51, 52, ran_factor=2, bias=1.0, smooth_r=20.0)
+    g = gpu_catalogue_run(native, cat, 40, tol=1e-3)
+    r = O.reconstruct(cat.gal_pos, None, cat.ran_pos, None, cat.n, cat.box_len, cat.origin, cat.observer,
+                      cat.bias, cat.growth, cat.smooth_r, cat.mask_tau, tol=1e-3, max_iter=40)
+    assert g["rc"] == 0
+    assert abs(g["iters"] - r["passes"]) <= 1
+    assert g["eps"][-1] <= 1e-3
+
+
+def test_not_converged_and_resume(gpu_lib):
+    from paper_1504_02591_amd import native
+    cat = G.lattice_box(32, 500.0, (-500.0, 250.0, 250.0), 0.7, 53, 54, ran_factor=2, bias=1.0, smooth_r=20.0)
+    plan = native.plan_for(cat)
+    plan.paint(native.GAL, to_dev(cat.gal_pos))
+    plan.paint(native.RAN, to_dev(cat.ran_pos))
+    plan.solve()
+    rc, iters, eps = plan.iterate(2, 1e-9)
+    assert rc == native.RECON_NOTCONVERGED and iters[0] == 2
+    rc, iters, eps = plan.iterate(2, 1e-9)
+    assert iters[0] == 4
+    psi = plan.psi()[0].cpu().numpy()
+    plan.close()
+    r = oracle_catalogue_run(cat, 4)
+    assert rel_l2(psi, r["psi"]) < PSI_TOL
+
+
+def test_divergence_detected(gpu_lib):
+    from paper_1504_02591_amd import native
+    n, box = 16, 300.0
+    rng = np.random.default_rng(3)
+    delta = O.smooth(rng.standard_normal((n, n, n)), box, 30.0).astype(np.float32)
+    plan = native.Plan(n, box, (150.0, 150.0, -3e9), 1.0, 2.5, 0.0, randoms=False)
+    plan.set_delta(to_dev(delta))
+    plan.solve()
+    with pytest.raises(native.ReconError) as ei:
+        plan.iterate(30, 1e-6)
+    assert ei.value.code == native.RECON_EDIVERGED
+    plan.close()
+
+
+def test_invalid_inputs_and_order(gpu_lib):
+    from paper_1504_02591_amd import native
+    plan = native.Plan(16, 100.0, (50.0, 50.0, 50.0), 1.0, 0.5, 10.0)
+    with pytest.raises(native.ReconError) as ei:
+        plan.solve()
+    assert ei.value.code == native.RECON_ESTATE
+    with pytest.raises(native.ReconError) as ei:
+        plan.iterate(1, 0.0)
+    assert ei.value.code == native.RECON_ESTATE
+    pos = np.random.default_rng(1).random((100, 3)).astype(np.float32) * 100
+    bad = pos.copy()
+    bad[17, 1] = np.nan
+    plan.paint(native.GAL, to_dev(bad))
+    plan.paint(native.RAN, to_dev(pos))
+    with pytest.raises(native.ReconError) as ei:
+        plan.solve()
+    assert ei.value.code == native.RECON_EINVAL
+    plan.paint(native.GAL, to_dev(pos), to_dev(np.full(100, -1.0, np.float32)))
+    plan.paint(native.RAN, to_dev(pos))
+    with pytest.raises(native.ReconError) as ei:
+        plan.solve()
+    assert ei.value.code == native.RECON_EINVAL
+    plan.paint(native.GAL, to_dev(pos))
+    plan.paint(native.RAN, to_dev(pos), to_dev(np.zeros(100, np.float32)))
+    with pytest.raises(native.ReconError) as ei:
+        plan.solve()
+    assert ei.value.code == native.RECON_EINVAL
+    plan.close()

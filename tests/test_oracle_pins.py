@@ -407,3 +407,14 @@ def test_bad_inputs_rejected():
         O.paint(np.zeros((1, 3), np.float32), np.array([-1.0], np.float32), 8, 8.0, (0, 0, 0))
     with pytest.raises(ValueError):
         O.overdensity(np.ones((8, 8, 8), np.int64), np.zeros((8, 8, 8), np.int64), 8.0, 1.0)
+
+
+def test_divergence_beyond_beta_one():
+    """Plane-parallel iterates grow as (beta mu^2)^n when beta mu^2 > 1 (remark after eq. (itpsi))."""
+    n, box = 16, 300.0
+    rng = np.random.default_rng(3)
+    delta = O.smooth(rng.standard_normal((n, n, n)), box, 30.0)
+    res = O.reconstruct_field(delta, box, (0, 0, 0), (150.0, 150.0, -3e9), 1.0, 2.5, tol=1e-6, max_iter=30)
+    assert res["diverged"]
+    ok = O.reconstruct_field(delta, box, (0, 0, 0), (150.0, 150.0, -3e9), 1.0, 0.9, tol=1e-6, max_iter=400)
+    assert not ok["diverged"] and ok["eps"][-1] <= 1e-6
