@@ -70,7 +70,7 @@ Layout make_layout(const recon_params_t* p) {
   L.w2 = take(b * cn * 8);
   L.ds = take(b * cn * 8);
   L.dn = take(b * cn * 8);
-  L.psi = take(b * 3 * n3 * 4);
+  L.psi = take(b * n3 * 16);
   L.delta = (p->flags & RECON_KEEP_DELTA) ? take(b * n3 * 4) : 0;
   L.corr = (p->flags & RECON_START_BUFFERS) ? take(b * n3 * 4) : 0;
   L.tw = take(n * 8);
@@ -114,7 +114,8 @@ struct recon_plan_s {
   long long *grid_g = nullptr, *grid_r = nullptr;
   unsigned char* mask = nullptr;
   float2 *w0 = nullptr, *w1 = nullptr, *w2 = nullptr, *ds = nullptr, *dn = nullptr, *tw = nullptr;
-  float *psi = nullptr, *delta = nullptr, *corr = nullptr;
+  float4* psi = nullptr;
+  float *delta = nullptr, *corr = nullptr;
   double *partials = nullptr, *red = nullptr;
   unsigned long long* totals = nullptr;
   long long* thr = nullptr;
@@ -197,70 +198,70 @@ struct Ops {
   int (*fanout)(recon_plan_t*, const int*);
   int (*ziter)(recon_plan_t*, int mode, const int*);
   int (*fanin_xiter)(recon_plan_t*, bool first, const int*);
-  int (*zfinal)(recon_plan_t*, float* psi, float* u, bool cross, const int*);
+  int (*zfinal)(recon_plan_t*, float4* psi, float* u, bool cross, const int*);
   int nb_x, nb_z;
 };
 
 template <int N>
 struct SizeOps {
   static constexpr int WZ = wz<N>(), WY = wy<N>(), WX = wx<N>();
+  static constexpr int TZ = ntz<N>(), TY = nty<N>(), TX = ntx<N>();
   static dim3 gz(const recon_plan_t* pl) { return dim3(N * (N / (2 * WZ)), pl->batch); }
   static dim3 gy(const recon_plan_t* pl) { return dim3((N / 2 + 1) * (N / WY), pl->batch); }
   static dim3 gx(const recon_plan_t* pl) { return dim3((N / 2 + 1) * N / WX, pl->batch); }
 
   static int setup(recon_plan_t* pl) {
     hipStream_t s = pl->stream;
-    const dim3 blk(kThreads);
     if (pl->randoms) {
       {
         PROF(pl, KP_Z_FWD_GRID);
-        k_z_fwd_grid<N, 2><<<gz(pl), blk, 0, s>>>(pl->grid_g, pl->grid_r, pl->w0, pl->w1, pl->tw);
+        k_z_fwd_grid<N, 2><<<gz(pl), dim3(TZ), 0, s>>>(pl->grid_g, pl->grid_r, pl->w0, pl->w1, pl->tw);
       }
       RECON_TRY(check_launch(pl, "z forward (grids)"));
       {
         PROF(pl, KP_Y_FWD);
-        k_y_plain<N, 2, false><<<gy(pl), blk, 0, s>>>(pl->w0, pl->w1, pl->tw);
+        k_y_plain<N, 2, false><<<gy(pl), dim3(TY), 0, s>>>(pl->w0, pl->w1, pl->tw);
       }
       RECON_TRY(check_launch(pl, "y forward"));
       {
         PROF(pl, KP_X_SMOOTH);
-        k_x_smooth<N, 2><<<gx(pl), blk, 0, s>>>(pl->w0, pl->w1, pl->geo, pl->tw);
+        k_x_smooth<N, 2><<<gx(pl), dim3(TX), 0, s>>>(pl->w0, pl->w1, pl->geo, pl->tw);
       }
       RECON_TRY(check_launch(pl, "x smooth"));
       {
         PROF(pl, KP_Y_INV);
-        k_y_plain<N, 2, true><<<gy(pl), blk, 0, s>>>(pl->w0, pl->w1, pl->tw);
+        k_y_plain<N, 2, true><<<gy(pl), dim3(TY), 0, s>>>(pl->w0, pl->w1, pl->tw);
       }
       RECON_TRY(check_launch(pl, "y inverse"));
       {
         PROF(pl, KP_Z_DELTA);
-        k_z_delta<N, 2><<<gz(pl), blk, 0, s>>>(pl->w0, pl->w1, pl->mask, pl->dscal, pl->delta, pl->tw);
+        k_z_delta<N, 2><<<gz(pl), dim3(TZ), 0, s>>>(pl->w0, pl->w1, pl->mask, pl->dscal, pl->delta, pl->tw);
       }
       RECON_TRY(check_launch(pl, "z delta"));
     } else {
       {
         PROF(pl, KP_Z_FWD_GRID);
-        k_z_fwd_grid<N, 1><<<gz(pl), blk, 0, s>>>(pl->grid_g, nullptr, pl->w0, nullptr, pl->tw);
+        k_z_fwd_grid<N, 1><<<gz(pl), dim3(TZ), 0, s>>>(pl->grid_g, nullptr, pl->w0, nullptr, pl->tw);
       }
       RECON_TRY(check_launch(pl, "z forward (grid)"));
       {
         PROF(pl, KP_Y_FWD);
-        k_y_plain<N, 1, false><<<gy(pl), blk, 0, s>>>(pl->w0, nullptr, pl->tw);
+        k_y_plain<N, 1, false><<<gy(pl), dim3(TY), 0, s>>>(pl->w0, nullptr, pl->tw);
       }
       RECON_TRY(check_launch(pl, "y forward"));
       {
         PROF(pl, KP_X_SMOOTH);
-        k_x_smooth<N, 1><<<gx(pl), blk, 0, s>>>(pl->w0, nullptr, pl->geo, pl->tw);
+        k_x_smooth<N, 1><<<gx(pl), dim3(TX), 0, s>>>(pl->w0, nullptr, pl->geo, pl->tw);
       }
       RECON_TRY(check_launch(pl, "x smooth"));
       {
         PROF(pl, KP_Y_INV);
-        k_y_plain<N, 1, true><<<gy(pl), blk, 0, s>>>(pl->w0, nullptr, pl->tw);
+        k_y_plain<N, 1, true><<<gy(pl), dim3(TY), 0, s>>>(pl->w0, nullptr, pl->tw);
       }
       RECON_TRY(check_launch(pl, "y inverse"));
       {
         PROF(pl, KP_Z_DELTA);
-        k_z_delta<N, 1><<<gz(pl), blk, 0, s>>>(pl->w0, nullptr, nullptr, pl->dscal, pl->delta, pl->tw);
+        k_z_delta<N, 1><<<gz(pl), dim3(TZ), 0, s>>>(pl->w0, nullptr, nullptr, pl->dscal, pl->delta, pl->tw);
       }
       RECON_TRY(check_launch(pl, "z delta"));
     }
@@ -271,12 +272,12 @@ struct SizeOps {
     hipStream_t s = pl->stream;
     {
       PROF(pl, KP_Y_FWD);
-      k_y_plain<N, 1, false><<<gy(pl), dim3(kThreads), 0, s>>>(pl->w0, nullptr, pl->tw);
+      k_y_plain<N, 1, false><<<gy(pl), dim3(TY), 0, s>>>(pl->w0, nullptr, pl->tw);
     }
     RECON_TRY(check_launch(pl, "y forward (delta)"));
     {
       PROF(pl, KP_X_START);
-      k_x_start<N><<<gx(pl), dim3(kThreads), 0, s>>>(pl->w0, pl->w1, pl->ds, pl->geo, pl->tw);
+      k_x_start<N><<<gx(pl), dim3(TX), 0, s>>>(pl->w0, pl->w1, pl->ds, pl->geo, pl->tw);
     }
     return check_launch(pl, "x start");
   }
@@ -284,7 +285,7 @@ struct SizeOps {
   static int setup_delta(recon_plan_t* pl, const float* d) {
     {
       PROF(pl, KP_Z_FWD_REAL);
-      k_z_fwd_real<N><<<gz(pl), dim3(kThreads), 0, pl->stream>>>(d, pl->w0, pl->tw);
+      k_z_fwd_real<N><<<gz(pl), dim3(TZ), 0, pl->stream>>>(d, pl->w0, pl->tw);
     }
     RECON_TRY(check_launch(pl, "z forward (delta)"));
     return finish_start(pl);
@@ -293,7 +294,7 @@ struct SizeOps {
   static int fanout(recon_plan_t* pl, const int* act) {
     {
       PROF(pl, KP_Y_FANOUT);
-      k_y_fanout<N><<<gy(pl), dim3(kThreads), 0, pl->stream>>>(pl->w0, pl->w1, pl->w2, pl->geo, act, pl->tw);
+      k_y_fanout<N><<<gy(pl), dim3(TY), 0, pl->stream>>>(pl->w0, pl->w1, pl->w2, pl->geo, act, pl->tw);
     }
     return check_launch(pl, "y fan-out");
   }
@@ -303,13 +304,13 @@ struct SizeOps {
     {
       PROF(pl, KP_Z_ITER);
       if (mode == ZI_FFTA)
-        k_z_iter<N, ZI_FFTA><<<gz(pl), dim3(kThreads), 0, s>>>(pl->w0, pl->w1, pl->w2, pl->geo, pl->corr,
+        k_z_iter<N, ZI_FFTA><<<gz(pl), dim3(TZ), 0, s>>>(pl->w0, pl->w1, pl->w2, pl->geo, pl->corr,
                                                                pl->partials, act, pl->tw);
       else if (mode == ZI_LEARNED)
-        k_z_iter<N, ZI_LEARNED><<<gz(pl), dim3(kThreads), 0, s>>>(pl->w0, pl->w1, pl->w2, pl->geo, pl->corr,
+        k_z_iter<N, ZI_LEARNED><<<gz(pl), dim3(TZ), 0, s>>>(pl->w0, pl->w1, pl->w2, pl->geo, pl->corr,
                                                                   pl->partials, act, pl->tw);
       else
-        k_z_iter<N, ZI_PLAIN><<<gz(pl), dim3(kThreads), 0, s>>>(pl->w0, pl->w1, pl->w2, pl->geo, nullptr,
+        k_z_iter<N, ZI_PLAIN><<<gz(pl), dim3(TZ), 0, s>>>(pl->w0, pl->w1, pl->w2, pl->geo, nullptr,
                                                                 nullptr, act, pl->tw);
     }
     RECON_TRY(check_launch(pl, "z iteration"));
@@ -327,12 +328,12 @@ struct SizeOps {
     hipStream_t s = pl->stream;
     {
       PROF(pl, KP_Y_FANIN);
-      k_y_fanin<N><<<gy(pl), dim3(kThreads), 0, s>>>(pl->w0, pl->w1, pl->w2, pl->geo, act, pl->tw);
+      k_y_fanin<N><<<gy(pl), dim3(TY), 0, s>>>(pl->w0, pl->w1, pl->w2, pl->geo, act, pl->tw);
     }
     RECON_TRY(check_launch(pl, "y fan-in"));
     {
       PROF(pl, KP_X_ITER);
-      k_x_iter<N><<<gx(pl), dim3(kThreads), 0, s>>>(pl->w0, pl->w1, pl->ds, first ? pl->ds : pl->dn, pl->dn,
+      k_x_iter<N><<<gx(pl), dim3(TX), 0, s>>>(pl->w0, pl->w1, pl->ds, first ? pl->ds : pl->dn, pl->dn,
                                                      pl->geo, pl->partials, act, pl->tw);
     }
     RECON_TRY(check_launch(pl, "x iteration"));
@@ -343,11 +344,11 @@ struct SizeOps {
     return check_launch(pl, "reduce (norm)");
   }
 
-  static int zfinal(recon_plan_t* pl, float* psi, float* u, bool cross, const int* act) {
+  static int zfinal(recon_plan_t* pl, float4* psi, float* u, bool cross, const int* act) {
     hipStream_t s = pl->stream;
     {
       PROF(pl, KP_Z_FINAL);
-      k_z_final<N><<<gz(pl), dim3(kThreads), 0, s>>>(pl->w0, pl->w1, pl->w2, pl->geo, psi, u,
+      k_z_final<N><<<gz(pl), dim3(TZ), 0, s>>>(pl->w0, pl->w1, pl->w2, pl->geo, psi, u,
                                                       cross ? pl->corr : nullptr, pl->partials, act, pl->tw);
     }
     RECON_TRY(check_launch(pl, "z final"));
@@ -460,7 +461,7 @@ int recon_plan(recon_plan_t** out, const recon_params_t* params, void* workspace
   pl->w2 = (float2*)(w + L.w2);
   pl->ds = (float2*)(w + L.ds);
   pl->dn = (float2*)(w + L.dn);
-  pl->psi = (float*)(w + L.psi);
+  pl->psi = (float4*)(w + L.psi);
   pl->delta = (params->flags & RECON_KEEP_DELTA) ? (float*)(w + L.delta) : nullptr;
   pl->corr = (params->flags & RECON_START_BUFFERS) ? (float*)(w + L.corr) : nullptr;
   pl->tw = (float2*)(w + L.tw);
@@ -808,9 +809,10 @@ int recon_get_psi(recon_plan_t* pl, float* psi_out) {
   if (pl->state != ST_SOLVED) return fail(pl, RECON_ESTATE, "no displacement yet");
   for (int b = 0; b < pl->batch; ++b)
     if (!pl->psi_valid[b]) return fail(pl, RECON_ESTATE, "displacement not computed; call iterate");
-  HIP_TRY(pl, hipMemcpyAsync(psi_out, pl->psi, sizeof(float) * 3 * pl->n3 * pl->batch, hipMemcpyDeviceToDevice,
-                             pl->stream));
-  return RECON_OK;
+  long long blocks = (pl->n3 * pl->batch + kThreads - 1) / kThreads;
+  if (blocks > 65536) blocks = 65536;
+  k_psi_planar<<<(unsigned)blocks, kThreads, 0, pl->stream>>>(pl->psi, pl->n3, pl->batch, psi_out);
+  return check_launch(pl, "psi copy");
 }
 
 int recon_get_grid(recon_plan_t* pl, int which, int64_t* out) {

@@ -84,16 +84,16 @@ __device__ __forceinline__ void dftR(float2* v) {
 
 // One self-sorting Stockham pass of radix R on a [N][LD] LDS tile holding W columns.
 // NS is the length of the sub-transforms already completed by earlier passes.
-template <int N, int W, int R, int NS, bool INV>
+template <int N, int W, int NT, int R, int NS, bool INV>
 __device__ __forceinline__ void stockham_pass(float2* buf, const float2* tw) {
   constexpr int LD = W + 1;
   constexpr int NB = (N / R) * W;
-  constexpr int PER = (NB + kThreads - 1) / kThreads;
+  constexpr int PER = (NB + NT - 1) / NT;
   float2 v[PER][R];
 #pragma unroll
   for (int it = 0; it < PER; ++it) {
-    const int b = threadIdx.x + it * kThreads;
-    if (NB % kThreads == 0 || b < NB) {
+    const int b = threadIdx.x + it * NT;
+    if (NB % NT == 0 || b < NB) {
       const int c = b % W, j = b / W;
 #pragma unroll
       for (int r = 0; r < R; ++r) v[it][r] = buf[(j + r * (N / R)) * LD + c];
@@ -102,8 +102,8 @@ __device__ __forceinline__ void stockham_pass(float2* buf, const float2* tw) {
   __syncthreads();
 #pragma unroll
   for (int it = 0; it < PER; ++it) {
-    const int b = threadIdx.x + it * kThreads;
-    if (NB % kThreads == 0 || b < NB) {
+    const int b = threadIdx.x + it * NT;
+    if (NB % NT == 0 || b < NB) {
       const int c = b % W, j = b / W;
       const int k = j % NS;
       if constexpr (NS > 1) {
@@ -123,33 +123,33 @@ __device__ __forceinline__ void stockham_pass(float2* buf, const float2* tw) {
   __syncthreads();
 }
 
-template <int N, int W, int NS, bool INV>
+template <int N, int W, int NT, int NS, bool INV>
 __device__ __forceinline__ void radix8_passes(float2* buf, const float2* tw) {
   if constexpr (NS < N) {
-    stockham_pass<N, W, 8, NS, INV>(buf, tw);
-    radix8_passes<N, W, NS * 8, INV>(buf, tw);
+    stockham_pass<N, W, NT, 8, NS, INV>(buf, tw);
+    radix8_passes<N, W, NT, NS * 8, INV>(buf, tw);
   }
 }
 
 // In-place length-N FFT of the W columns of an [N][W+1] LDS tile.  The caller
 // must have issued a barrier after filling the tile; the function ends with one.
-template <int N, int W, bool INV>
+template <int N, int W, int NT, bool INV>
 __device__ __forceinline__ void tile_fft(float2* buf, const float2* tw) {
   constexpr int REM = ilog2(N) % 3;
   if constexpr (REM == 1) {
-    stockham_pass<N, W, 2, 1, INV>(buf, tw);
-    radix8_passes<N, W, 2, INV>(buf, tw);
+    stockham_pass<N, W, NT, 2, 1, INV>(buf, tw);
+    radix8_passes<N, W, NT, 2, INV>(buf, tw);
   } else if constexpr (REM == 2) {
-    stockham_pass<N, W, 4, 1, INV>(buf, tw);
-    radix8_passes<N, W, 4, INV>(buf, tw);
+    stockham_pass<N, W, NT, 4, 1, INV>(buf, tw);
+    radix8_passes<N, W, NT, 4, INV>(buf, tw);
   } else {
-    radix8_passes<N, W, 1, INV>(buf, tw);
+    radix8_passes<N, W, NT, 1, INV>(buf, tw);
   }
 }
 
-template <int N>
+template <int N, int NT>
 __device__ __forceinline__ void stage_twiddles(float2* tw_lds, const float2* __restrict__ tw) {
-  for (int i = threadIdx.x; i < N; i += kThreads) tw_lds[i] = tw[i];
+  for (int i = threadIdx.x; i < N; i += NT) tw_lds[i] = tw[i];
 }
 
 // Wavenumber index m in [0, N) -> signed mode m' (Nyquist as -N/2).
@@ -160,8 +160,9 @@ template <int N>
 __device__ __forceinline__ float deriv_mode(int m) { return m == N / 2 ? 0.f : signed_mode<N>(m); }
 
 // Deterministic block reduction of two doubles (fixed shuffle tree, then fixed LDS order).
+template <int NT>
 __device__ __forceinline__ void block_sum2(double a, double b, double* out_a, double* out_b) {
-  __shared__ double red[2][kThreads / 64];
+  __shared__ double red[2][NT / 64];
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
     a += __shfl_xor(a, off, 64);
@@ -173,7 +174,7 @@ __device__ __forceinline__ void block_sum2(double a, double b, double* out_a, do
   if (threadIdx.x == 0) {
     double sa = 0.0, sb = 0.0;
 #pragma unroll
-    for (int w = 0; w < kThreads / 64; ++w) { sa += red[0][w]; sb += red[1][w]; }
+    for (int w = 0; w < NT / 64; ++w) { sa += red[0][w]; sb += red[1][w]; }
     *out_a = sa;
     *out_b = sb;
   }

@@ -45,6 +45,10 @@ enum ZIterMode { ZI_PLAIN = 0, ZI_FFTA = 1, ZI_LEARNED = 2 };
 template <int N> constexpr int wz() { return N >= 1024 ? 8 : (N / 2 < 16 ? N / 2 : 16); }   // packed z columns
 template <int N> constexpr int wy() { return N >= 1024 ? 8 : (N < 16 ? N : 16); }           // y-pass columns
 template <int N> constexpr int wx() { return 8; }                                             // x-pass rows
+// threads per block of the z, y and x passes
+template <int N> constexpr int ntz() { return N >= 256 ? 512 : 256; }
+template <int N> constexpr int nty() { return N >= 256 ? 512 : 256; }
+template <int N> constexpr int ntx() { return 256; }
 
 __device__ __forceinline__ long long ceil_div_ll(long long a, long long b) { return (a + b - 1) / b; }
 
@@ -198,10 +202,10 @@ __device__ __forceinline__ void z_tile_coords(int& y, int& x0) {
 }
 
 // Load a half-spectrum column tile and expand it Hermitian-wise into packed full columns.
-template <int N, int WP>
+template <int N, int WP, int NT>
 __device__ __forceinline__ void z_load_pack(float2* buf, const float2* __restrict__ a, int y, int x0) {
   constexpr int LD = WP + 1;
-  for (int e = threadIdx.x; e < (N / 2 + 1) * WP; e += kThreads) {
+  for (int e = threadIdx.x; e < (N / 2 + 1) * WP; e += NT) {
     const int p = e % WP, kz = e / WP;
     const long long base = ((long long)kz * N + y) * N + x0 + p;
     const float2 A = a[base], B = a[base + WP];
@@ -216,10 +220,10 @@ __device__ __forceinline__ void z_load_pack(float2* buf, const float2* __restric
 
 // Split a transformed packed tile into the half spectra of its two real columns and store.
 // MULK: multiply by i k'_z.
-template <int N, int WP, bool MULK>
+template <int N, int WP, int NT, bool MULK>
 __device__ __forceinline__ void z_unpack_store(const float2* buf, float2* __restrict__ out, int y, int x0, float kf) {
   constexpr int LD = WP + 1;
-  for (int e = threadIdx.x; e < (N / 2 + 1) * WP; e += kThreads) {
+  for (int e = threadIdx.x; e < (N / 2 + 1) * WP; e += NT) {
     const int p = e % WP, kz = e / WP;
     const float2 Z = buf[kz * LD + p];
     const float2 M = buf[((N - kz) & (N - 1)) * LD + p];
@@ -238,13 +242,14 @@ __device__ __forceinline__ void z_unpack_store(const float2* buf, float2* __rest
 
 // Forward z transform of int64 grids (units 2^-32) into half spectra.
 template <int N, int NA>
-__global__ void __launch_bounds__(256) k_z_fwd_grid(const long long* __restrict__ g0, const long long* __restrict__ g1,
+__global__ void __launch_bounds__(ntz<N>()) __attribute__((amdgpu_waves_per_eu(4))) k_z_fwd_grid(const long long* __restrict__ g0, const long long* __restrict__ g1,
                                                     float2* __restrict__ o0, float2* __restrict__ o1,
                                                     const float2* __restrict__ twg) {
+  constexpr int NT = ntz<N>();
   constexpr int WP = wz<N>(), LD = WP + 1;
   __shared__ float2 buf[N * LD];
   __shared__ float2 tw[N];
-  stage_twiddles<N>(tw, twg);
+  stage_twiddles<N, NT>(tw, twg);
   int y, x0;
   z_tile_coords<N, WP>(y, x0);
   const long long n3 = (long long)N * N * N, cn = (long long)(N / 2 + 1) * N * N;
@@ -254,40 +259,41 @@ __global__ void __launch_bounds__(256) k_z_fwd_grid(const long long* __restrict_
   for (int a = 0; a < NA; ++a) {
     const long long* g = (a == 0 ? g0 : g1) + b * n3;
     float2* o = (a == 0 ? o0 : o1) + b * cn;
-    for (int e = threadIdx.x; e < N * WP; e += kThreads) {
+    for (int e = threadIdx.x; e < N * WP; e += NT) {
       const int p = e % WP, z = e / WP;
       const long long base = ((long long)z * N + y) * N + x0 + p;
       buf[z * LD + p] = make_float2((float)g[base] * unit, (float)g[base + WP] * unit);
     }
     __syncthreads();
-    tile_fft<N, WP, false>(buf, tw);
-    z_unpack_store<N, WP, false>(buf, o, y, x0, 0.f);
+    tile_fft<N, WP, NT, false>(buf, tw);
+    z_unpack_store<N, WP, NT, false>(buf, o, y, x0, 0.f);
     __syncthreads();
   }
 }
 
 // Forward z transform of one real field.
 template <int N>
-__global__ void __launch_bounds__(256) k_z_fwd_real(const float* __restrict__ f, float2* __restrict__ o,
+__global__ void __launch_bounds__(ntz<N>()) __attribute__((amdgpu_waves_per_eu(4))) k_z_fwd_real(const float* __restrict__ f, float2* __restrict__ o,
                                                     const float2* __restrict__ twg) {
+  constexpr int NT = ntz<N>();
   constexpr int WP = wz<N>(), LD = WP + 1;
   __shared__ float2 buf[N * LD];
   __shared__ float2 tw[N];
-  stage_twiddles<N>(tw, twg);
+  stage_twiddles<N, NT>(tw, twg);
   int y, x0;
   z_tile_coords<N, WP>(y, x0);
   const long long n3 = (long long)N * N * N, cn = (long long)(N / 2 + 1) * N * N;
   const int b = blockIdx.y;
   f += b * n3;
   o += b * cn;
-  for (int e = threadIdx.x; e < N * WP; e += kThreads) {
+  for (int e = threadIdx.x; e < N * WP; e += NT) {
     const int p = e % WP, z = e / WP;
     const long long base = ((long long)z * N + y) * N + x0 + p;
     buf[z * LD + p] = make_float2(f[base], f[base + WP]);
   }
   __syncthreads();
-  tile_fft<N, WP, false>(buf, tw);
-  z_unpack_store<N, WP, false>(buf, o, y, x0, 0.f);
+  tile_fft<N, WP, NT, false>(buf, tw);
+  z_unpack_store<N, WP, NT, false>(buf, o, y, x0, 0.f);
 }
 
 // Inverse z transform of the smoothed galaxy (and random) densities, overdensity in
@@ -295,15 +301,16 @@ __global__ void __launch_bounds__(256) k_z_fwd_real(const float* __restrict__ f,
 //   with randoms:  delta = m (G - alpha R) / (alpha R), 0 outside the mask or where R <= 0
 //   mean density:  delta = G / rho_bar - 1
 template <int N, int NA>
-__global__ void __launch_bounds__(256) k_z_delta(float2* __restrict__ a0, const float2* __restrict__ a1,
+__global__ void __launch_bounds__(ntz<N>()) __attribute__((amdgpu_waves_per_eu(4))) k_z_delta(float2* __restrict__ a0, const float2* __restrict__ a1,
                                                  const unsigned char* __restrict__ mask,
                                                  const DeltaScal* __restrict__ sc, float* __restrict__ delta_out,
                                                  const float2* __restrict__ twg) {
+  constexpr int NT = ntz<N>();
   constexpr int WP = wz<N>(), LD = WP + 1;
-  constexpr int EPT = (N * WP + kThreads - 1) / kThreads;
+  constexpr int EPT = (N * WP + NT - 1) / NT;
   __shared__ float2 buf[N * LD];
   __shared__ float2 tw[N];
-  stage_twiddles<N>(tw, twg);
+  stage_twiddles<N, NT>(tw, twg);
   int y, x0;
   z_tile_coords<N, WP>(y, x0);
   const long long n3 = (long long)N * N * N, cn = (long long)(N / 2 + 1) * N * N;
@@ -312,23 +319,23 @@ __global__ void __launch_bounds__(256) k_z_delta(float2* __restrict__ a0, const 
   if (NA == 2) a1 += b * cn;
   const DeltaScal s = sc[b];
   float2 gv[EPT];
-  z_load_pack<N, WP>(buf, a0, y, x0);
+  z_load_pack<N, WP, NT>(buf, a0, y, x0);
   __syncthreads();
-  tile_fft<N, WP, true>(buf, tw);
+  tile_fft<N, WP, NT, true>(buf, tw);
 #pragma unroll
   for (int i = 0; i < EPT; ++i) {
-    const int e = threadIdx.x + i * kThreads;
+    const int e = threadIdx.x + i * NT;
     if (e < N * WP) gv[i] = buf[(e / WP) * LD + e % WP];
   }
   __syncthreads();
   if constexpr (NA == 2) {
-    z_load_pack<N, WP>(buf, a1, y, x0);
+    z_load_pack<N, WP, NT>(buf, a1, y, x0);
     __syncthreads();
-    tile_fft<N, WP, true>(buf, tw);
+    tile_fft<N, WP, NT, true>(buf, tw);
   }
 #pragma unroll
   for (int i = 0; i < EPT; ++i) {
-    const int e = threadIdx.x + i * kThreads;
+    const int e = threadIdx.x + i * NT;
     if (e < N * WP) {
       const int p = e % WP, z = e / WP;
       const long long cell = ((long long)z * N + y) * N + x0 + p;
@@ -353,12 +360,12 @@ __global__ void __launch_bounds__(256) k_z_delta(float2* __restrict__ a0, const 
   __syncthreads();
 #pragma unroll
   for (int i = 0; i < EPT; ++i) {
-    const int e = threadIdx.x + i * kThreads;
+    const int e = threadIdx.x + i * NT;
     if (e < N * WP) buf[(e / WP) * LD + e % WP] = gv[i];
   }
   __syncthreads();
-  tile_fft<N, WP, false>(buf, tw);
-  z_unpack_store<N, WP, false>(buf, a0, y, x0, 0.f);
+  tile_fft<N, WP, NT, false>(buf, tw);
+  z_unpack_store<N, WP, NT, false>(buf, a0, y, x0, 0.f);
 }
 
 // Scaled line-of-sight vector of a node: r = (origin + H i - observer) / R0.
@@ -372,17 +379,18 @@ __device__ __forceinline__ float los_comp(const Geo& g, int a, int i) { return f
 //   ZI_LEARNED: u_0 = u_p + corr
 // and both accumulate S1 = sum Delta u_p, S2 = sum Delta^2 into partials.
 template <int N, int MODE>
-__global__ void __launch_bounds__(256) k_z_iter(float2* __restrict__ a0, float2* __restrict__ a1,
+__global__ void __launch_bounds__(ntz<N>()) __attribute__((amdgpu_waves_per_eu(4))) k_z_iter(float2* __restrict__ a0, float2* __restrict__ a1,
                                                 float2* __restrict__ a2, Geo g, float* __restrict__ corr,
                                                 double* __restrict__ partials, const int* __restrict__ active,
                                                 const float2* __restrict__ twg) {
+  constexpr int NT = ntz<N>();
   constexpr int WP = wz<N>(), LD = WP + 1;
-  constexpr int EPT = (N * WP + kThreads - 1) / kThreads;
+  constexpr int EPT = (N * WP + NT - 1) / NT;
   const int b = blockIdx.y;
   if (active && !active[b]) return;
   __shared__ float2 buf[N * LD];
   __shared__ float2 tw[N];
-  stage_twiddles<N>(tw, twg);
+  stage_twiddles<N, NT>(tw, twg);
   int y, x0;
   z_tile_coords<N, WP>(y, x0);
   const long long n3 = (long long)N * N * N, cn = (long long)(N / 2 + 1) * N * N;
@@ -393,12 +401,12 @@ __global__ void __launch_bounds__(256) k_z_iter(float2* __restrict__ a0, float2*
   const float ry = los_comp(g, 1, y);
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    z_load_pack<N, WP>(buf, arr[a], y, x0);
+    z_load_pack<N, WP, NT>(buf, arr[a], y, x0);
     __syncthreads();
-    tile_fft<N, WP, true>(buf, tw);
+    tile_fft<N, WP, NT, true>(buf, tw);
 #pragma unroll
     for (int i = 0; i < EPT; ++i) {
-      const int e = threadIdx.x + i * kThreads;
+      const int e = threadIdx.x + i * NT;
       if (e < N * WP) {
         const int p = e % WP, z = e / WP;
         const float2 v = buf[z * LD + p];
@@ -416,7 +424,7 @@ __global__ void __launch_bounds__(256) k_z_iter(float2* __restrict__ a0, float2*
   double acc1 = 0.0, acc2 = 0.0;
 #pragma unroll
   for (int i = 0; i < EPT; ++i) {
-    const int e = threadIdx.x + i * kThreads;
+    const int e = threadIdx.x + i * NT;
     if (e < N * WP) {
       const int p = e % WP, z = e / WP;
       const float rz = los_comp(g, 2, z);
@@ -448,7 +456,7 @@ __global__ void __launch_bounds__(256) k_z_iter(float2* __restrict__ a0, float2*
   }
   if (MODE != ZI_PLAIN) {
     double t1, t2;
-    block_sum2(acc1, acc2, &t1, &t2);
+    block_sum2<NT>(acc1, acc2, &t1, &t2);
     if (threadIdx.x == 0) {
       const long long nb = gridDim.x;
       partials[2 * (b * nb + blockIdx.x) + 0] = t1;
@@ -459,7 +467,7 @@ __global__ void __launch_bounds__(256) k_z_iter(float2* __restrict__ a0, float2*
   for (int a = 0; a < 3; ++a) {
 #pragma unroll
     for (int i = 0; i < EPT; ++i) {
-      const int e = threadIdx.x + i * kThreads;
+      const int e = threadIdx.x + i * NT;
       if (e < N * WP) {
         const int p = e % WP, z = e / WP;
         float r0, r1;
@@ -470,52 +478,56 @@ __global__ void __launch_bounds__(256) k_z_iter(float2* __restrict__ a0, float2*
       }
     }
     __syncthreads();
-    tile_fft<N, WP, false>(buf, tw);
-    if (a == 2) z_unpack_store<N, WP, true>(buf, arr[a], y, x0, g.kf);
-    else z_unpack_store<N, WP, false>(buf, arr[a], y, x0, g.kf);
+    tile_fft<N, WP, NT, false>(buf, tw);
+    if (a == 2) z_unpack_store<N, WP, NT, true>(buf, arr[a], y, x0, g.kf);
+    else z_unpack_store<N, WP, NT, false>(buf, arr[a], y, x0, g.kf);
     __syncthreads();
   }
 }
 
-// Inverse z of the three displacement spectra: writes Psi_j (when psi != null),
-// u = Psi.r_hat (when u_out != null) and accumulates S3 = sum corr * u (when corr != null).
+// Inverse z of the three displacement spectra: writes Psi interleaved as float4
+// (x, y, z, 0) per cell (when psi4 != null), u = Psi.r_hat (when u_out != null) and
+// accumulates S3 = sum corr * u (when corr != null).
 template <int N>
-__global__ void __launch_bounds__(256) k_z_final(const float2* __restrict__ a0, const float2* __restrict__ a1,
-                                                 const float2* __restrict__ a2, Geo g, float* __restrict__ psi,
-                                                 float* __restrict__ u_out, const float* __restrict__ corr,
-                                                 double* __restrict__ partials, const int* __restrict__ active,
-                                                 const float2* __restrict__ twg) {
+__global__ void __launch_bounds__(ntz<N>()) __attribute__((amdgpu_waves_per_eu(4))) k_z_final(const float2* __restrict__ a0, const float2* __restrict__ a1,
+                                                      const float2* __restrict__ a2, Geo g, float4* __restrict__ psi4,
+                                                      float* __restrict__ u_out, const float* __restrict__ corr,
+                                                      double* __restrict__ partials, const int* __restrict__ active,
+                                                      const float2* __restrict__ twg) {
+  constexpr int NT = ntz<N>();
   constexpr int WP = wz<N>(), LD = WP + 1;
-  constexpr int EPT = (N * WP + kThreads - 1) / kThreads;
+  constexpr int EPT = (N * WP + NT - 1) / NT;
   const int b = blockIdx.y;
   if (active && !active[b]) return;
   __shared__ float2 buf[N * LD];
   __shared__ float2 tw[N];
-  stage_twiddles<N>(tw, twg);
+  stage_twiddles<N, NT>(tw, twg);
   int y, x0;
   z_tile_coords<N, WP>(y, x0);
   const long long n3 = (long long)N * N * N, cn = (long long)(N / 2 + 1) * N * N;
   const float2* arr[3] = {a0 + b * cn, a1 + b * cn, a2 + b * cn};
   float s0[EPT], s1[EPT];
+  float2 px[EPT], py[EPT];
 #pragma unroll
   for (int i = 0; i < EPT; ++i) { s0[i] = 0.f; s1[i] = 0.f; }
   const float ry = los_comp(g, 1, y);
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    z_load_pack<N, WP>(buf, arr[a], y, x0);
+    z_load_pack<N, WP, NT>(buf, arr[a], y, x0);
     __syncthreads();
-    tile_fft<N, WP, true>(buf, tw);
+    tile_fft<N, WP, NT, true>(buf, tw);
 #pragma unroll
     for (int i = 0; i < EPT; ++i) {
-      const int e = threadIdx.x + i * kThreads;
+      const int e = threadIdx.x + i * NT;
       if (e < N * WP) {
         const int p = e % WP, z = e / WP;
         const float2 v = buf[z * LD + p];
-        const long long cell = ((long long)z * N + y) * N + x0 + p;
-        if (psi) {
-          float* pa = psi + (b * 3 + a) * n3;
-          pa[cell] = v.x;
-          pa[cell + WP] = v.y;
+        if (a == 0) px[i] = v;
+        else if (a == 1) py[i] = v;
+        else if (psi4) {
+          const long long cell = b * n3 + ((long long)z * N + y) * N + x0 + p;
+          psi4[cell] = make_float4(px[i].x, py[i].x, v.x, 0.f);
+          psi4[cell + WP] = make_float4(px[i].y, py[i].y, v.y, 0.f);
         }
         float r0, r1;
         if (a == 0) { r0 = los_comp(g, 0, x0 + p); r1 = los_comp(g, 0, x0 + p + WP); }
@@ -531,7 +543,7 @@ __global__ void __launch_bounds__(256) k_z_final(const float2* __restrict__ a0, 
   double acc = 0.0;
 #pragma unroll
   for (int i = 0; i < EPT; ++i) {
-    const int e = threadIdx.x + i * kThreads;
+    const int e = threadIdx.x + i * NT;
     if (e < N * WP) {
       const int p = e % WP, z = e / WP;
       const float rz = los_comp(g, 2, z);
@@ -549,9 +561,25 @@ __global__ void __launch_bounds__(256) k_z_final(const float2* __restrict__ a0, 
   }
   if (corr) {
     double t1, t2;
-    block_sum2(acc, 0.0, &t1, &t2);
-    if (threadIdx.x == 0) partials[2 * ((long long)b * gridDim.x + blockIdx.x)] = t1,
-                          partials[2 * ((long long)b * gridDim.x + blockIdx.x) + 1] = 0.0;
+    block_sum2<NT>(acc, 0.0, &t1, &t2);
+    if (threadIdx.x == 0) {
+      partials[2 * ((long long)b * gridDim.x + blockIdx.x)] = t1;
+      partials[2 * ((long long)b * gridDim.x + blockIdx.x) + 1] = 0.0;
+    }
+  }
+}
+
+// Interleaved displacement (float4 per cell) -> planar [b][3][N^3].
+__global__ void __launch_bounds__(256) k_psi_planar(const float4* __restrict__ psi4, long long n3, int batch,
+                                                    float* __restrict__ out) {
+  const long long total = n3 * batch;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
+       i += (long long)gridDim.x * blockDim.x) {
+    const float4 v = psi4[i];
+    const long long b = i / n3, c = i - b * n3;
+    out[(b * 3 + 0) * n3 + c] = v.x;
+    out[(b * 3 + 1) * n3 + c] = v.y;
+    out[(b * 3 + 2) * n3 + c] = v.z;
   }
 }
 
@@ -564,31 +592,32 @@ __device__ __forceinline__ void y_tile_coords(int& p, int& x0) {
   x0 = (blockIdx.x % (N / W)) * W;
 }
 
-template <int N, int W>
+template <int N, int W, int NT>
 __device__ __forceinline__ void y_load(float2* buf, const float2* __restrict__ a, int p, int x0) {
   constexpr int LD = W + 1;
-  for (int e = threadIdx.x; e < N * W; e += kThreads) {
+  for (int e = threadIdx.x; e < N * W; e += NT) {
     const int c = e % W, j = e / W;
     buf[j * LD + c] = a[((long long)p * N + j) * N + x0 + c];
   }
 }
 
-template <int N, int W>
+template <int N, int W, int NT>
 __device__ __forceinline__ void y_store(const float2* buf, float2* __restrict__ a, int p, int x0) {
   constexpr int LD = W + 1;
-  for (int e = threadIdx.x; e < N * W; e += kThreads) {
+  for (int e = threadIdx.x; e < N * W; e += NT) {
     const int c = e % W, j = e / W;
     a[((long long)p * N + j) * N + x0 + c] = buf[j * LD + c];
   }
 }
 
 template <int N, int NA, bool INV>
-__global__ void __launch_bounds__(256) k_y_plain(float2* __restrict__ a0, float2* __restrict__ a1,
+__global__ void __launch_bounds__(nty<N>()) __attribute__((amdgpu_waves_per_eu(4))) k_y_plain(float2* __restrict__ a0, float2* __restrict__ a1,
                                                  const float2* __restrict__ twg) {
+  constexpr int NT = nty<N>();
   constexpr int W = wy<N>(), LD = W + 1;
   __shared__ float2 buf[N * LD];
   __shared__ float2 tw[N];
-  stage_twiddles<N>(tw, twg);
+  stage_twiddles<N, NT>(tw, twg);
   int p, x0;
   y_tile_coords<N, W>(p, x0);
   const long long cn = (long long)(N / 2 + 1) * N * N;
@@ -596,10 +625,10 @@ __global__ void __launch_bounds__(256) k_y_plain(float2* __restrict__ a0, float2
 #pragma unroll
   for (int a = 0; a < NA; ++a) {
     float2* arr = (a == 0 ? a0 : a1) + b * cn;
-    y_load<N, W>(buf, arr, p, x0);
+    y_load<N, W, NT>(buf, arr, p, x0);
     __syncthreads();
-    tile_fft<N, W, INV>(buf, tw);
-    y_store<N, W>(buf, arr, p, x0);
+    tile_fft<N, W, NT, INV>(buf, tw);
+    y_store<N, W, NT>(buf, arr, p, x0);
     __syncthreads();
   }
 }
@@ -609,29 +638,30 @@ __global__ void __launch_bounds__(256) k_y_plain(float2* __restrict__ a0, float2
 //   a1 <- Y^-1[i k'_y a1]             (y component)
 //   a2 <- i k'_z Y^-1[a1]             (z component)
 template <int N>
-__global__ void __launch_bounds__(256) k_y_fanout(float2* __restrict__ a0, float2* __restrict__ a1,
+__global__ void __launch_bounds__(nty<N>()) __attribute__((amdgpu_waves_per_eu(4))) k_y_fanout(float2* __restrict__ a0, float2* __restrict__ a1,
                                                   float2* __restrict__ a2, Geo g, const int* __restrict__ active,
                                                   const float2* __restrict__ twg) {
+  constexpr int NT = nty<N>();
   constexpr int W = wy<N>(), LD = W + 1;
-  constexpr int EPT = (N * W + kThreads - 1) / kThreads;
+  constexpr int EPT = (N * W + NT - 1) / NT;
   const int b = blockIdx.y;
   if (active && !active[b]) return;
   __shared__ float2 buf[N * LD];
   __shared__ float2 tw[N];
-  stage_twiddles<N>(tw, twg);
+  stage_twiddles<N, NT>(tw, twg);
   int p, x0;
   y_tile_coords<N, W>(p, x0);
   const long long cn = (long long)(N / 2 + 1) * N * N;
   a0 += b * cn; a1 += b * cn; a2 += b * cn;
-  y_load<N, W>(buf, a0, p, x0);
+  y_load<N, W, NT>(buf, a0, p, x0);
   __syncthreads();
-  tile_fft<N, W, true>(buf, tw);
-  y_store<N, W>(buf, a0, p, x0);
+  tile_fft<N, W, NT, true>(buf, tw);
+  y_store<N, W, NT>(buf, a0, p, x0);
   __syncthreads();
   float2 r[EPT];
 #pragma unroll
   for (int i = 0; i < EPT; ++i) {
-    const int e = threadIdx.x + i * kThreads;
+    const int e = threadIdx.x + i * NT;
     if (e < N * W) {
       const int c = e % W, j = e / W;
       r[i] = a1[((long long)p * N + j) * N + x0 + c];
@@ -639,18 +669,18 @@ __global__ void __launch_bounds__(256) k_y_fanout(float2* __restrict__ a0, float
     }
   }
   __syncthreads();
-  tile_fft<N, W, true>(buf, tw);
-  y_store<N, W>(buf, a1, p, x0);
+  tile_fft<N, W, NT, true>(buf, tw);
+  y_store<N, W, NT>(buf, a1, p, x0);
   __syncthreads();
 #pragma unroll
   for (int i = 0; i < EPT; ++i) {
-    const int e = threadIdx.x + i * kThreads;
+    const int e = threadIdx.x + i * NT;
     if (e < N * W) buf[(e / W) * LD + e % W] = r[i];
   }
   __syncthreads();
-  tile_fft<N, W, true>(buf, tw);
+  tile_fft<N, W, NT, true>(buf, tw);
   const float kz = g.kf * deriv_mode<N>(p);     // p in [0, N/2]; N/2 is the Nyquist plane
-  for (int e = threadIdx.x; e < N * W; e += kThreads) {
+  for (int e = threadIdx.x; e < N * W; e += NT) {
     const int c = e % W, j = e / W;
     a2[((long long)p * N + j) * N + x0 + c] = mul_i(buf[j * LD + c]) * kz;
   }
@@ -660,44 +690,45 @@ __global__ void __launch_bounds__(256) k_y_fanout(float2* __restrict__ a0, float
 //   a0 <- Y[a0]                       (x component; i k'_x applied in the x pass)
 //   a1 <- i k'_y Y[a1] + Y[a2]        (y component plus the z component, already times i k'_z)
 template <int N>
-__global__ void __launch_bounds__(256) k_y_fanin(float2* __restrict__ a0, float2* __restrict__ a1,
+__global__ void __launch_bounds__(nty<N>()) __attribute__((amdgpu_waves_per_eu(4))) k_y_fanin(float2* __restrict__ a0, float2* __restrict__ a1,
                                                  const float2* __restrict__ a2, Geo g,
                                                  const int* __restrict__ active, const float2* __restrict__ twg) {
+  constexpr int NT = nty<N>();
   constexpr int W = wy<N>(), LD = W + 1;
-  constexpr int EPT = (N * W + kThreads - 1) / kThreads;
+  constexpr int EPT = (N * W + NT - 1) / NT;
   const int b = blockIdx.y;
   if (active && !active[b]) return;
   __shared__ float2 buf[N * LD];
   __shared__ float2 tw[N];
-  stage_twiddles<N>(tw, twg);
+  stage_twiddles<N, NT>(tw, twg);
   int p, x0;
   y_tile_coords<N, W>(p, x0);
   const long long cn = (long long)(N / 2 + 1) * N * N;
   a0 += b * cn; a1 += b * cn; a2 += b * cn;
-  y_load<N, W>(buf, a0, p, x0);
+  y_load<N, W, NT>(buf, a0, p, x0);
   __syncthreads();
-  tile_fft<N, W, false>(buf, tw);
-  y_store<N, W>(buf, a0, p, x0);
+  tile_fft<N, W, NT, false>(buf, tw);
+  y_store<N, W, NT>(buf, a0, p, x0);
   __syncthreads();
-  y_load<N, W>(buf, a1, p, x0);
+  y_load<N, W, NT>(buf, a1, p, x0);
   __syncthreads();
-  tile_fft<N, W, false>(buf, tw);
+  tile_fft<N, W, NT, false>(buf, tw);
   float2 r[EPT];
 #pragma unroll
   for (int i = 0; i < EPT; ++i) {
-    const int e = threadIdx.x + i * kThreads;
+    const int e = threadIdx.x + i * NT;
     if (e < N * W) {
       const int c = e % W, j = e / W;
       r[i] = mul_i(buf[j * LD + c]) * (g.kf * deriv_mode<N>(j));
     }
   }
   __syncthreads();
-  y_load<N, W>(buf, a2, p, x0);
+  y_load<N, W, NT>(buf, a2, p, x0);
   __syncthreads();
-  tile_fft<N, W, false>(buf, tw);
+  tile_fft<N, W, NT, false>(buf, tw);
 #pragma unroll
   for (int i = 0; i < EPT; ++i) {
-    const int e = threadIdx.x + i * kThreads;
+    const int e = threadIdx.x + i * NT;
     if (e < N * W) {
       const int c = e % W, j = e / W;
       a1[((long long)p * N + j) * N + x0 + c] = r[i] + buf[j * LD + c];
@@ -709,19 +740,19 @@ __global__ void __launch_bounds__(256) k_y_fanin(float2* __restrict__ a0, float2
 // x passes.  Tile: W consecutive rows (row = kz * N + ky), all N x.
 // Element ownership e -> (j = e % N, c = e / N): contiguous global rows.
 // ---------------------------------------------------------------------------
-template <int N, int W>
+template <int N, int W, int NT>
 __device__ __forceinline__ void x_load(float2* buf, const float2* __restrict__ a, long long r0) {
   constexpr int LD = W + 1;
-  for (int e = threadIdx.x; e < N * W; e += kThreads) {
+  for (int e = threadIdx.x; e < N * W; e += NT) {
     const int j = e % N, c = e / N;
     buf[j * LD + c] = a[(r0 + c) * N + j];
   }
 }
 
-template <int N, int W>
+template <int N, int W, int NT>
 __device__ __forceinline__ void x_store(const float2* buf, float2* __restrict__ a, long long r0) {
   constexpr int LD = W + 1;
-  for (int e = threadIdx.x; e < N * W; e += kThreads) {
+  for (int e = threadIdx.x; e < N * W; e += NT) {
     const int j = e % N, c = e / N;
     a[(r0 + c) * N + j] = buf[j * LD + c];
   }
@@ -742,22 +773,23 @@ __device__ __forceinline__ void x_wavenumbers(long long row, int j, float kf, fl
 
 // Forward x, Gaussian smoothing S(k) = exp(-k^2 R^2 / 2) with the 1/N^3 of the inverse, inverse x.
 template <int N, int NA>
-__global__ void __launch_bounds__(256) k_x_smooth(float2* __restrict__ a0, float2* __restrict__ a1, Geo g,
+__global__ void __launch_bounds__(ntx<N>()) k_x_smooth(float2* __restrict__ a0, float2* __restrict__ a1, Geo g,
                                                   const float2* __restrict__ twg) {
+  constexpr int NT = ntx<N>();
   constexpr int W = wx<N>(), LD = W + 1;
   __shared__ float2 buf[N * LD];
   __shared__ float2 tw[N];
-  stage_twiddles<N>(tw, twg);
+  stage_twiddles<N, NT>(tw, twg);
   const long long cn = (long long)(N / 2 + 1) * N * N;
   const long long r0 = (long long)blockIdx.x * W;
   const int b = blockIdx.y;
 #pragma unroll
   for (int a = 0; a < NA; ++a) {
     float2* arr = (a == 0 ? a0 : a1) + b * cn;
-    x_load<N, W>(buf, arr, r0);
+    x_load<N, W, NT>(buf, arr, r0);
     __syncthreads();
-    tile_fft<N, W, false>(buf, tw);
-    for (int e = threadIdx.x; e < N * W; e += kThreads) {
+    tile_fft<N, W, NT, false>(buf, tw);
+    for (int e = threadIdx.x; e < N * W; e += NT) {
       const int j = e % N, c = e / N;
       float k2, dx, dy, dz;
       int kzi;
@@ -765,8 +797,8 @@ __global__ void __launch_bounds__(256) k_x_smooth(float2* __restrict__ a0, float
       buf[j * LD + c] = buf[j * LD + c] * (expf(-k2 * g.smooth_c) * g.inv_n3);
     }
     __syncthreads();
-    tile_fft<N, W, true>(buf, tw);
-    x_store<N, W>(buf, arr, r0);
+    tile_fft<N, W, NT, true>(buf, tw);
+    x_store<N, W, NT>(buf, arr, r0);
     __syncthreads();
   }
 }
@@ -774,25 +806,26 @@ __global__ void __launch_bounds__(256) k_x_smooth(float2* __restrict__ a0, float
 // Forward x of the overdensity -> D_s (stored); P = D_s / (b k^2 N^3);
 // a0 <- X^-1[i k'_x P], a1 <- X^-1[P].
 template <int N>
-__global__ void __launch_bounds__(256) k_x_start(float2* __restrict__ a0, float2* __restrict__ a1,
+__global__ void __launch_bounds__(ntx<N>()) k_x_start(float2* __restrict__ a0, float2* __restrict__ a1,
                                                  float2* __restrict__ ds, Geo g, const float2* __restrict__ twg) {
+  constexpr int NT = ntx<N>();
   constexpr int W = wx<N>(), LD = W + 1;
-  constexpr int EPT = (N * W + kThreads - 1) / kThreads;
+  constexpr int EPT = (N * W + NT - 1) / NT;
   __shared__ float2 buf[N * LD];
   __shared__ float2 tw[N];
-  stage_twiddles<N>(tw, twg);
+  stage_twiddles<N, NT>(tw, twg);
   const long long cn = (long long)(N / 2 + 1) * N * N;
   const long long r0 = (long long)blockIdx.x * W;
   const int b = blockIdx.y;
   a0 += b * cn; a1 += b * cn; ds += b * cn;
-  x_load<N, W>(buf, a0, r0);
+  x_load<N, W, NT>(buf, a0, r0);
   __syncthreads();
-  tile_fft<N, W, false>(buf, tw);
+  tile_fft<N, W, NT, false>(buf, tw);
   float2 pr[EPT];
   float kxd[EPT];
 #pragma unroll
   for (int i = 0; i < EPT; ++i) {
-    const int e = threadIdx.x + i * kThreads;
+    const int e = threadIdx.x + i * NT;
     if (e < N * W) {
       const int j = e % N, c = e / N;
       const float2 d = buf[j * LD + c];
@@ -806,17 +839,17 @@ __global__ void __launch_bounds__(256) k_x_start(float2* __restrict__ a0, float2
     }
   }
   __syncthreads();
-  tile_fft<N, W, true>(buf, tw);
-  x_store<N, W>(buf, a0, r0);
+  tile_fft<N, W, NT, true>(buf, tw);
+  x_store<N, W, NT>(buf, a0, r0);
   __syncthreads();
 #pragma unroll
   for (int i = 0; i < EPT; ++i) {
-    const int e = threadIdx.x + i * kThreads;
+    const int e = threadIdx.x + i * NT;
     if (e < N * W) buf[(e % N) * LD + e / N] = pr[i];
   }
   __syncthreads();
-  tile_fft<N, W, true>(buf, tw);
-  x_store<N, W>(buf, a1, r0);
+  tile_fft<N, W, NT, true>(buf, tw);
+  x_store<N, W, NT>(buf, a1, r0);
 }
 
 // One iteration's k-space step:
@@ -826,37 +859,38 @@ __global__ void __launch_bounds__(256) k_x_start(float2* __restrict__ a0, float2
 //   P = D_{n+1} / (b k^2 N^3);  a0 <- X^-1[i k'_x P],  a1 <- X^-1[P]
 // dprev and dnext may be the same buffer (element-wise in place).
 template <int N>
-__global__ void __launch_bounds__(256) k_x_iter(float2* __restrict__ a0, float2* __restrict__ a1,
+__global__ void __launch_bounds__(ntx<N>()) k_x_iter(float2* __restrict__ a0, float2* __restrict__ a1,
                                                 const float2* __restrict__ ds, const float2* dprev,
                                                 float2* dnext, Geo g, double* __restrict__ partials,
                                                 const int* __restrict__ active, const float2* __restrict__ twg) {
+  constexpr int NT = ntx<N>();
   constexpr int W = wx<N>(), LD = W + 1;
-  constexpr int EPT = (N * W + kThreads - 1) / kThreads;
+  constexpr int EPT = (N * W + NT - 1) / NT;
   const int b = blockIdx.y;
   if (active && !active[b]) return;
   __shared__ float2 buf[N * LD];
   __shared__ float2 tw[N];
-  stage_twiddles<N>(tw, twg);
+  stage_twiddles<N, NT>(tw, twg);
   const long long cn = (long long)(N / 2 + 1) * N * N;
   const long long r0 = (long long)blockIdx.x * W;
   a0 += b * cn; a1 += b * cn; ds += b * cn; dprev += b * cn; dnext += b * cn;
-  x_load<N, W>(buf, a0, r0);
+  x_load<N, W, NT>(buf, a0, r0);
   __syncthreads();
-  tile_fft<N, W, false>(buf, tw);
+  tile_fft<N, W, NT, false>(buf, tw);
   float2 r[EPT];
 #pragma unroll
   for (int i = 0; i < EPT; ++i) {
-    const int e = threadIdx.x + i * kThreads;
+    const int e = threadIdx.x + i * NT;
     if (e < N * W) r[i] = buf[(e % N) * LD + e / N];
   }
   __syncthreads();
-  x_load<N, W>(buf, a1, r0);
+  x_load<N, W, NT>(buf, a1, r0);
   __syncthreads();
-  tile_fft<N, W, false>(buf, tw);
+  tile_fft<N, W, NT, false>(buf, tw);
   double num = 0.0, den = 0.0;
 #pragma unroll
   for (int i = 0; i < EPT; ++i) {
-    const int e = threadIdx.x + i * kThreads;
+    const int e = threadIdx.x + i * NT;
     if (e < N * W) {
       const int j = e % N, c = e / N;
       float k2, dx, dy, dz;
@@ -884,7 +918,7 @@ __global__ void __launch_bounds__(256) k_x_iter(float2* __restrict__ a0, float2*
   __syncthreads();
   {
     double t1, t2;
-    block_sum2(num, den, &t1, &t2);
+    block_sum2<NT>(num, den, &t1, &t2);
     if (threadIdx.x == 0) {
       partials[2 * ((long long)b * gridDim.x + blockIdx.x) + 0] = t1;
       partials[2 * ((long long)b * gridDim.x + blockIdx.x) + 1] = t2;
@@ -892,29 +926,30 @@ __global__ void __launch_bounds__(256) k_x_iter(float2* __restrict__ a0, float2*
   }
 #pragma unroll
   for (int i = 0; i < EPT; ++i) {
-    const int e = threadIdx.x + i * kThreads;
+    const int e = threadIdx.x + i * NT;
     if (e < N * W) {
       const int j = e % N;
       buf[j * LD + e / N] = mul_i(r[i]) * (g.kf * deriv_mode<N>(j));
     }
   }
   __syncthreads();
-  tile_fft<N, W, true>(buf, tw);
-  x_store<N, W>(buf, a0, r0);
+  tile_fft<N, W, NT, true>(buf, tw);
+  x_store<N, W, NT>(buf, a0, r0);
   __syncthreads();
 #pragma unroll
   for (int i = 0; i < EPT; ++i) {
-    const int e = threadIdx.x + i * kThreads;
+    const int e = threadIdx.x + i * NT;
     if (e < N * W) buf[(e % N) * LD + e / N] = r[i];
   }
   __syncthreads();
-  tile_fft<N, W, true>(buf, tw);
-  x_store<N, W>(buf, a1, r0);
+  tile_fft<N, W, NT, true>(buf, tw);
+  x_store<N, W, NT>(buf, a1, r0);
 }
 
 // Fixed-order reduction of per-block partial pairs: out[b] = sum over blocks.
 __global__ void __launch_bounds__(256) k_reduce_pairs(const double* __restrict__ partials, int nblk,
                                                       double* __restrict__ out) {
+  constexpr int NT = kThreads;
   const int b = blockIdx.x;
   double s0 = 0.0, s1 = 0.0;
   for (int i = threadIdx.x; i < nblk; i += kThreads) {
@@ -922,7 +957,7 @@ __global__ void __launch_bounds__(256) k_reduce_pairs(const double* __restrict__
     s1 += partials[2 * ((long long)b * nblk + i) + 1];
   }
   double t0, t1;
-  block_sum2(s0, s1, &t0, &t1);
+  block_sum2<NT>(s0, s1, &t0, &t1);
   if (threadIdx.x == 0) { out[2 * b] = t0; out[2 * b + 1] = t1; }
 }
 
@@ -932,7 +967,7 @@ __global__ void __launch_bounds__(256) k_reduce_pairs(const double* __restrict__
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_shift(const float* __restrict__ pos, long long n,
                                                const long long* __restrict__ off, int batch,
-                                               const float* __restrict__ psi, CicGeo cg, float ox, float oy,
+                                               const float4* __restrict__ psi4, CicGeo cg, float ox, float oy,
                                                float oz, float growth, int galaxies, float* __restrict__ disp,
                                                float* __restrict__ pos_out, int* __restrict__ err) {
   const long long n3 = (long long)cg.n * cg.n * cg.n;
@@ -961,7 +996,7 @@ __global__ void __launch_bounds__(256) k_shift(const float* __restrict__ pos, lo
       ii[a] = ((int)fl) & (cg.n - 1);
     }
     const int b = off ? find_realisation(off, batch, i) : 0;
-    const float* pb = psi + (long long)b * 3 * n3;
+    const float4* pb = psi4 + (long long)b * n3;
     float p0 = 0.f, p1 = 0.f, p2 = 0.f;
 #pragma unroll
     for (int cnr = 0; cnr < 8; ++cnr) {
@@ -969,9 +1004,10 @@ __global__ void __launch_bounds__(256) k_shift(const float* __restrict__ pos, lo
       const float wgt = (dx ? t[0] : 1.f - t[0]) * (dy ? t[1] : 1.f - t[1]) * (dz ? t[2] : 1.f - t[2]);
       const long long idx = (((long long)((ii[2] + dz) & (cg.n - 1)) * cg.n + ((ii[1] + dy) & (cg.n - 1))) * cg.n) +
                             ((ii[0] + dx) & (cg.n - 1));
-      p0 = fmaf(wgt, pb[idx], p0);
-      p1 = fmaf(wgt, pb[n3 + idx], p1);
-      p2 = fmaf(wgt, pb[2 * n3 + idx], p2);
+      const float4 v = pb[idx];
+      p0 = fmaf(wgt, v.x, p0);
+      p1 = fmaf(wgt, v.y, p1);
+      p2 = fmaf(wgt, v.z, p2);
     }
     float d0 = -p0, d1 = -p1, d2 = -p2;
     if (galaxies && growth != 0.f) {
