@@ -89,6 +89,9 @@ typedef struct {
   double smooth_r;         /* R >= 0 [Mpc/h] (Sec. 3.1 smoothing)                                        */
   double mask_tau;         /* mask threshold as a fraction of the mean 27-cell random sum (>= 0)          */
   uint32_t flags;          /* RECON_NO_RANDOMS | RECON_KEEP_DELTA | RECON_START_BUFFERS                  */
+  int64_t max_objects;     /* largest catalogue painted in one call that uses the brick-binned deposit
+                              (workspace holds 16 B per object for it); larger calls fall back to
+                              per-object atomics.  0 disables binning.  Must be < 2^32.                  */
 } recon_params_t;
 
 /* Device bytes the workspace must provide for these parameters (0 if the parameters are invalid). */

@@ -29,7 +29,9 @@ enum PlanState { ST_EMPTY = 0, ST_PAINTED = 1, ST_DELTA = 2, ST_SOLVED = 3 };
 
 struct Layout {
   size_t grid_g = 0, grid_r = 0, mask = 0, w0 = 0, w1 = 0, w2 = 0, ds = 0, dn = 0, psi = 0, delta = 0,
-         corr = 0, tw = 0, partials = 0, red = 0, totals = 0, thr = 0, dscal = 0, act = 0, err = 0, total = 0;
+         corr = 0, tw = 0, partials = 0, red = 0, totals = 0, thr = 0, dscal = 0, act = 0, err = 0, total = 0,
+         sorted = 0, bcount = 0, bstart = 0, bcursor = 0, bsum = 0;
+  long long nbins = 0, nscan = 0;
 };
 
 bool valid_params(const recon_params_t* p, std::string* why) {
@@ -45,6 +47,7 @@ bool valid_params(const recon_params_t* p, std::string* why) {
   if (!(p->smooth_r >= 0.0) || !std::isfinite(p->smooth_r)) return fail("smooth_r must be >= 0 and finite");
   if (!(p->mask_tau >= 0.0) || !std::isfinite(p->mask_tau)) return fail("mask_tau must be >= 0 and finite");
   if (p->flags & ~(RECON_NO_RANDOMS | RECON_KEEP_DELTA | RECON_START_BUFFERS)) return fail("unknown flag");
+  if (p->max_objects < 0 || p->max_objects >= (1LL << 32)) return fail("max_objects must be in [0, 2^32)");
   return true;
 }
 
@@ -81,6 +84,16 @@ Layout make_layout(const recon_params_t* p) {
   L.dscal = take(b * sizeof(DeltaScal));
   L.act = take(b * 4 * 4);
   L.err = take(16);
+  if (p->max_objects > 0) {
+    const long long nbs = (n + kBrick - 1) / kBrick;
+    L.nbins = b * nbs * nbs * nbs;
+    L.nscan = (L.nbins + 256LL * kScanItems - 1) / (256LL * kScanItems);
+    L.sorted = take((size_t)p->max_objects * 16);
+    L.bcount = take((L.nbins + 2) * 4);
+    L.bstart = take((L.nbins + 2) * 4);
+    L.bcursor = take((L.nbins + 2) * 4);
+    L.bsum = take(L.nscan * 4);
+  }
   L.total = off;
   return L;
 }
@@ -88,11 +101,12 @@ Layout make_layout(const recon_params_t* p) {
 // Per-kernel event timing on the plan's stream (instrumentation; off by default).
 enum KernelId {
   KP_FILL, KP_PAINT, KP_TOTALS, KP_MASK, KP_Z_FWD_GRID, KP_Y_FWD, KP_X_SMOOTH, KP_Y_INV, KP_Z_DELTA, KP_X_START,
-  KP_Z_FWD_REAL, KP_Y_FANOUT, KP_Z_ITER, KP_Y_FANIN, KP_X_ITER, KP_REDUCE, KP_Z_FINAL, KP_SHIFT, KP_COUNT
+  KP_Z_FWD_REAL, KP_Y_FANOUT, KP_Z_ITER, KP_Y_FANIN, KP_X_ITER, KP_REDUCE, KP_Z_FINAL, KP_SHIFT, KP_BIN, KP_SCAN,
+  KP_COUNT
 };
 const char* const kKernelNames[KP_COUNT] = {
     "fill", "paint", "totals", "mask", "z_fwd_grid", "y_fwd", "x_smooth", "y_inv", "z_delta", "x_start",
-    "z_fwd_real", "y_fanout", "z_iter", "y_fanin", "x_iter", "reduce", "z_final", "shift"};
+    "z_fwd_real", "y_fanout", "z_iter", "y_fanin", "x_iter", "reduce", "z_final", "shift", "bin", "scan"};
 
 struct Profiler {
   bool on = false;
@@ -121,6 +135,8 @@ struct recon_plan_s {
   long long* thr = nullptr;
   DeltaScal* dscal = nullptr;
   int *act_fan = nullptr, *act_fin = nullptr, *act_it = nullptr, *err = nullptr;
+  float4* sorted = nullptr;
+  unsigned *bcount = nullptr, *bstart = nullptr, *bcursor = nullptr, *bsum = nullptr;
   Geo geo{};
   CicGeo cic{};
   bool painted_g = false, painted_r = false;
@@ -474,6 +490,13 @@ int recon_plan(recon_plan_t** out, const recon_params_t* params, void* workspace
   pl->act_fin = pl->act_fan + pl->batch;
   pl->act_it = pl->act_fan + 2 * pl->batch;
   pl->err = (int*)(w + L.err);
+  if (params->max_objects > 0) {
+    pl->sorted = (float4*)(w + L.sorted);
+    pl->bcount = (unsigned*)(w + L.bcount);
+    pl->bstart = (unsigned*)(w + L.bstart);
+    pl->bcursor = (unsigned*)(w + L.bcursor);
+    pl->bsum = (unsigned*)(w + L.bsum);
+  }
 
   const int n = pl->n;
   const double L0 = params->box_len, h = L0 / n;
@@ -542,7 +565,52 @@ int recon_paint(recon_plan_t* pl, int which, const float* pos, const float* w, i
     RECON_TRY(launch_fill_u64(pl, grid, pl->n3 * pl->batch));
     HIP_TRY(pl, hipMemsetAsync(errc, 0, sizeof(int), pl->stream));
   }
-  if (n > 0) {
+  if (n > 0 && n <= pl->p.max_objects) {
+    // brick-binned deposit: count, scan, scatter into brick order, per-brick LDS accumulation
+    long long blocks = (n + kThreads - 1) / kThreads;
+    if (blocks > 8192) blocks = 8192;
+    const long long nb = pl->L.nbins;
+    RECON_TRY(launch_fill_u64(pl, pl->bcount, (nb + 2) / 2));
+    const long long nbs = (pl->n + kBrick - 1) / kBrick;
+    const bool lds_bins = nbs * nbs * nbs <= kLdsBins;
+    long long lblocks = (n + 16383) / 16384;
+    if (lblocks > 1024) lblocks = 1024;
+    const long long chunk = (n + lblocks - 1) / lblocks;
+    {
+      PROF(pl, KP_BIN);
+      if (lds_bins)
+        k_bin_count_lds<<<(unsigned)lblocks, 256, 0, pl->stream>>>(pos, w, n, chunk, (const long long*)offsets,
+                                                                   pl->batch, pl->cic, pl->bcount, errc);
+      else
+        k_bin_count<<<(unsigned)blocks, kThreads, 0, pl->stream>>>(pos, w, n, (const long long*)offsets, pl->batch,
+                                                                   pl->cic, pl->bcount, errc);
+    }
+    RECON_TRY(check_launch(pl, "bin count"));
+    {
+      PROF(pl, KP_SCAN);
+      k_scan_blocks<<<(unsigned)pl->L.nscan, 256, 0, pl->stream>>>(pl->bcount, nb, pl->bsum);
+      k_scan_top<<<1, 256, 0, pl->stream>>>(pl->bsum, (int)pl->L.nscan);
+      k_scan_apply<<<(unsigned)pl->L.nscan, 256, 0, pl->stream>>>(pl->bcount, nb, pl->bsum, pl->bstart,
+                                                                  pl->bcursor);
+    }
+    RECON_TRY(check_launch(pl, "bin scan"));
+    {
+      PROF(pl, KP_BIN);
+      if (lds_bins)
+        k_bin_scatter_lds<<<(unsigned)lblocks, 256, 0, pl->stream>>>(pos, w, n, chunk, (const long long*)offsets,
+                                                                     pl->batch, pl->cic, pl->bcursor, pl->sorted);
+      else
+        k_bin_scatter<<<(unsigned)blocks, kThreads, 0, pl->stream>>>(pos, w, n, (const long long*)offsets,
+                                                                     pl->batch, pl->cic, pl->bcursor, pl->sorted);
+    }
+    RECON_TRY(check_launch(pl, "bin scatter"));
+    {
+      PROF(pl, KP_PAINT);
+      k_brick_deposit<<<(unsigned)nb, 256, 0, pl->stream>>>(pl->sorted, pl->bstart, pl->cic,
+                                                            (unsigned long long*)grid);
+    }
+    RECON_TRY(check_launch(pl, "brick deposit"));
+  } else if (n > 0) {
     long long blocks = (n + kThreads - 1) / kThreads;
     if (blocks > 8192) blocks = 8192;
     {

@@ -134,6 +134,274 @@ __global__ void __launch_bounds__(256) k_paint(const float* __restrict__ pos, co
   }
 }
 
+// ---------------------------------------------------------------------------
+// Brick-binned deposit: objects are counted per BS^3 brick of their base cell,
+// scattered into brick order, and each brick is accumulated in LDS before a
+// coalesced flush.  Same integer shares as k_paint, so the grid is identical.
+// ---------------------------------------------------------------------------
+constexpr int kBrick = 16;
+constexpr int kLdsBins = 32768;   // bins a block histograms in LDS (128 KB)
+
+// Cell coordinate of an object; false for a non-finite / far position or a bad weight.
+__device__ __forceinline__ bool cic_locate(float px, float py, float pz, float wv, const CicGeo& g, int ii[3],
+                                           unsigned long long tau[3]) {
+  const float pp[3] = {px, py, pz};
+  float uu[3];
+  bool ok = (wv >= 0.0f) && (wv < 64.0f);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    float d = __fsub_rn(pp[a], g.o[a]);
+    uu[a] = __fmul_rn(d, g.s);
+    ok = ok && (fabsf(uu[a]) < 1073741824.0f);
+  }
+  if (!ok) return false;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    float fl = floorf(uu[a]);
+    float t = __fsub_rn(uu[a], fl);
+    tau[a] = (unsigned long long)floorf(t * 65536.0f);
+    ii[a] = ((int)fl) & (g.n - 1);
+  }
+  return true;
+}
+
+__device__ __forceinline__ long long brick_key(const int ii[3], int n, int b) {
+  const int nbs = (n + kBrick - 1) / kBrick;
+  return (long long)b * nbs * nbs * nbs + ((long long)(ii[2] / kBrick) * nbs + ii[1] / kBrick) * nbs + ii[0] / kBrick;
+}
+
+__global__ void __launch_bounds__(256) k_bin_count(const float* __restrict__ pos, const float* __restrict__ w,
+                                                   long long n, const long long* __restrict__ off, int batch,
+                                                   CicGeo g, unsigned* __restrict__ counts, int* __restrict__ err) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    int ii[3];
+    unsigned long long tau[3];
+    if (!cic_locate(pos[3 * i], pos[3 * i + 1], pos[3 * i + 2], w ? w[i] : 1.0f, g, ii, tau)) {
+      atomicAdd(err, 1);
+      continue;
+    }
+    const int b = off ? find_realisation(off, batch, i) : 0;
+    atomicAdd(counts + brick_key(ii, g.n, b), 1u);
+  }
+}
+
+__global__ void __launch_bounds__(256) k_bin_scatter(const float* __restrict__ pos, const float* __restrict__ w,
+                                                     long long n, const long long* __restrict__ off, int batch,
+                                                     CicGeo g, unsigned* __restrict__ cursor,
+                                                     float4* __restrict__ sorted) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    int ii[3];
+    unsigned long long tau[3];
+    const float px = pos[3 * i], py = pos[3 * i + 1], pz = pos[3 * i + 2], wv = w ? w[i] : 1.0f;
+    if (!cic_locate(px, py, pz, wv, g, ii, tau)) continue;
+    const int b = off ? find_realisation(off, batch, i) : 0;
+    const unsigned slot = atomicAdd(cursor + brick_key(ii, g.n, b), 1u);
+    sorted[slot] = make_float4(px, py, pz, wv);
+  }
+}
+
+// Count with a per-block LDS histogram over the bins of the realisation that owns the
+// chunk's first object; one global atomic per (block, non-empty bin).  Objects whose bin
+// lies outside that window (a chunk crossing realisations) use a direct global atomic.
+__global__ void __launch_bounds__(256) k_bin_count_lds(const float* __restrict__ pos, const float* __restrict__ w,
+                                                       long long n, long long chunk,
+                                                       const long long* __restrict__ off, int batch, CicGeo g,
+                                                       unsigned* __restrict__ counts, int* __restrict__ err) {
+  __shared__ unsigned hist[kLdsBins];
+  const long long lo = blockIdx.x * chunk;
+  if (lo >= n) return;
+  const long long hi = lo + chunk < n ? lo + chunk : n;
+  const int nbs = (g.n + kBrick - 1) / kBrick;
+  const long long per = (long long)nbs * nbs * nbs;
+  const long long base = (off ? (long long)find_realisation(off, batch, lo) : 0LL) * per;
+  for (int i = threadIdx.x; i < kLdsBins; i += 256) hist[i] = 0u;
+  __syncthreads();
+  for (long long i = lo + threadIdx.x; i < hi; i += 256) {
+    int ii[3];
+    unsigned long long tau[3];
+    if (!cic_locate(pos[3 * i], pos[3 * i + 1], pos[3 * i + 2], w ? w[i] : 1.0f, g, ii, tau)) {
+      atomicAdd(err, 1);
+      continue;
+    }
+    const int b = off ? find_realisation(off, batch, i) : 0;
+    const long long key = brick_key(ii, g.n, b);
+    const long long rel = key - base;
+    if (rel >= 0 && rel < kLdsBins) atomicAdd(&hist[rel], 1u);
+    else atomicAdd(counts + key, 1u);
+  }
+  __syncthreads();
+  const long long nb_total = per * batch;
+  for (int i = threadIdx.x; i < kLdsBins; i += 256) {
+    const unsigned c = hist[i];
+    if (c && base + i < nb_total) atomicAdd(counts + base + i, c);
+  }
+}
+
+// Scatter into brick order: each block reserves one contiguous slot range per non-empty
+// bin of its window, then ranks its objects inside the range with LDS atomics.
+__global__ void __launch_bounds__(256) k_bin_scatter_lds(const float* __restrict__ pos, const float* __restrict__ w,
+                                                         long long n, long long chunk,
+                                                         const long long* __restrict__ off, int batch, CicGeo g,
+                                                         unsigned* __restrict__ cursor, float4* __restrict__ sorted) {
+  __shared__ unsigned hist[kLdsBins];
+  const long long lo = blockIdx.x * chunk;
+  if (lo >= n) return;
+  const long long hi = lo + chunk < n ? lo + chunk : n;
+  const int nbs = (g.n + kBrick - 1) / kBrick;
+  const long long per = (long long)nbs * nbs * nbs;
+  const long long base = (off ? (long long)find_realisation(off, batch, lo) : 0LL) * per;
+  const long long nb_total = per * batch;
+  for (int i = threadIdx.x; i < kLdsBins; i += 256) hist[i] = 0u;
+  __syncthreads();
+  for (long long i = lo + threadIdx.x; i < hi; i += 256) {
+    int ii[3];
+    unsigned long long tau[3];
+    if (!cic_locate(pos[3 * i], pos[3 * i + 1], pos[3 * i + 2], w ? w[i] : 1.0f, g, ii, tau)) continue;
+    const int b = off ? find_realisation(off, batch, i) : 0;
+    const long long rel = brick_key(ii, g.n, b) - base;
+    if (rel >= 0 && rel < kLdsBins) atomicAdd(&hist[rel], 1u);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < kLdsBins; i += 256) {
+    const unsigned c = hist[i];
+    if (c && base + i < nb_total) hist[i] = atomicAdd(cursor + base + i, c);
+  }
+  __syncthreads();
+  for (long long i = lo + threadIdx.x; i < hi; i += 256) {
+    int ii[3];
+    unsigned long long tau[3];
+    const float px = pos[3 * i], py = pos[3 * i + 1], pz = pos[3 * i + 2], wv = w ? w[i] : 1.0f;
+    if (!cic_locate(px, py, pz, wv, g, ii, tau)) continue;
+    const int b = off ? find_realisation(off, batch, i) : 0;
+    const long long key = brick_key(ii, g.n, b);
+    const long long rel = key - base;
+    const unsigned slot = (rel >= 0 && rel < kLdsBins) ? atomicAdd(&hist[rel], 1u) : atomicAdd(cursor + key, 1u);
+    sorted[slot] = make_float4(px, py, pz, wv);
+  }
+}
+
+// Exclusive scan of uint32 counts in three kernels: block totals, scan of the totals, apply.
+constexpr int kScanItems = 16;
+__global__ void __launch_bounds__(256) k_scan_blocks(const unsigned* __restrict__ in, long long n,
+                                                     unsigned* __restrict__ bsum) {
+  const long long base = (long long)blockIdx.x * 256 * kScanItems;
+  unsigned s = 0;
+  for (int k = 0; k < kScanItems; ++k) {
+    const long long i = base + (long long)k * 256 + threadIdx.x;
+    if (i < n) s += in[i];
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  __shared__ unsigned ws[4];
+  if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) bsum[blockIdx.x] = ws[0] + ws[1] + ws[2] + ws[3];
+}
+
+// In-place exclusive scan of nb block totals by one block.
+__global__ void __launch_bounds__(256) k_scan_top(unsigned* __restrict__ bsum, int nb) {
+  __shared__ unsigned sh[256];
+  unsigned carry = 0;
+  for (int base = 0; base < nb; base += 256) {
+    const int i = base + threadIdx.x;
+    const unsigned v = i < nb ? bsum[i] : 0u;
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = 1; o < 256; o <<= 1) {
+      unsigned t = threadIdx.x >= o ? sh[threadIdx.x - o] : 0u;
+      __syncthreads();
+      sh[threadIdx.x] += t;
+      __syncthreads();
+    }
+    if (i < nb) bsum[i] = carry + sh[threadIdx.x] - v;
+    carry += sh[255];
+    __syncthreads();
+  }
+}
+
+// out[i] = exclusive prefix of in (out has n + 1 entries; out[n] = total); cursor = copy of out[0..n).
+__global__ void __launch_bounds__(256) k_scan_apply(const unsigned* __restrict__ in, long long n,
+                                                    const unsigned* __restrict__ bsum, unsigned* __restrict__ out,
+                                                    unsigned* __restrict__ cursor) {
+  __shared__ unsigned sh[256];
+  const long long base = (long long)blockIdx.x * 256 * kScanItems;
+  unsigned carry = bsum[blockIdx.x];
+  for (int k = 0; k < kScanItems; ++k) {
+    const long long i = base + (long long)k * 256 + threadIdx.x;
+    const unsigned v = i < n ? in[i] : 0u;
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = 1; o < 256; o <<= 1) {
+      unsigned t = threadIdx.x >= o ? sh[threadIdx.x - o] : 0u;
+      __syncthreads();
+      sh[threadIdx.x] += t;
+      __syncthreads();
+    }
+    const unsigned ex = carry + sh[threadIdx.x] - v;
+    if (i < n) { out[i] = ex; cursor[i] = ex; }
+    if (i == n - 1) out[n] = ex + v;
+    carry += sh[255];
+    __syncthreads();
+  }
+}
+
+// One block per brick: LDS accumulation of the (BS+1)^3 footprint, then a flush with
+// 64-bit atomics (bricks overlap by one cell on their upper faces).
+__global__ void __launch_bounds__(256) k_brick_deposit(const float4* __restrict__ sorted,
+                                                       const unsigned* __restrict__ start, CicGeo g,
+                                                       unsigned long long* __restrict__ grid) {
+  constexpr int T = kBrick + 1;
+  __shared__ unsigned long long acc[T * T * T];
+  const long long key = blockIdx.x;
+  const unsigned lo = start[key], hi = start[key + 1];
+  if (lo == hi) return;
+  const int nbs = (g.n + kBrick - 1) / kBrick;
+  const long long per = (long long)nbs * nbs * nbs;
+  const int b = (int)(key / per);
+  const long long kk = key - (long long)b * per;
+  const int bx = (int)(kk % nbs), by = (int)((kk / nbs) % nbs), bz = (int)(kk / ((long long)nbs * nbs));
+  for (int i = threadIdx.x; i < T * T * T; i += 256) acc[i] = 0ull;
+  __syncthreads();
+  for (unsigned j = lo + threadIdx.x; j < hi; j += 256) {
+    const float4 r = sorted[j];
+    int ii[3];
+    unsigned long long tau[3];
+    cic_locate(r.x, r.y, r.z, r.w, g, ii, tau);
+    const unsigned long long wq = (unsigned long long)__double2ll_rn((double)r.w * 4294967296.0);
+    const int lx = ii[0] - bx * kBrick, ly = ii[1] - by * kBrick, lz = ii[2] - bz * kBrick;
+    unsigned long long sum = 0;
+#pragma unroll
+    for (int cnr = 0; cnr < 8; ++cnr) {
+      const int dx = cnr & 1, dy = (cnr >> 1) & 1, dz = cnr >> 2;
+      unsigned long long share;
+      if (cnr < 7) {
+        const unsigned long long ax = dx ? tau[0] : 65536ull - tau[0];
+        const unsigned long long ay = dy ? tau[1] : 65536ull - tau[1];
+        const unsigned long long az = dz ? tau[2] : 65536ull - tau[2];
+        const unsigned long long c = ax * ay * az;
+        const unsigned long long chi = c >> 24, clo = c & 0xFFFFFFull;
+        share = (wq * chi + ((wq * clo) >> 24)) >> 24;
+        sum += share;
+      } else {
+        share = wq - sum;
+      }
+      if (share) atomicAdd(&acc[((lz + dz) * T + (ly + dy)) * T + (lx + dx)], share);
+    }
+  }
+  __syncthreads();
+  unsigned long long* gb = grid + (long long)b * g.n * g.n * g.n;
+  for (int i = threadIdx.x; i < T * T * T; i += 256) {
+    const unsigned long long v = acc[i];
+    if (!v) continue;
+    const int lx = i % T, ly = (i / T) % T, lz = i / (T * T);
+    const long long x = (bx * kBrick + lx) & (g.n - 1), y = (by * kBrick + ly) & (g.n - 1),
+                    z = (bz * kBrick + lz) & (g.n - 1);
+    atomicAdd(gb + (z * g.n + y) * g.n + x, v);
+  }
+}
+
 // Exact totals per realisation: out[b] = {sum I_g, sum I_r, #cells with I_r != 0}.
 __global__ void __launch_bounds__(256) k_totals(const long long* __restrict__ gg, const long long* __restrict__ gr,
                                                 long long n3, unsigned long long* __restrict__ out) {

@@ -39,7 +39,7 @@ class Params(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("batch", ctypes.c_int32), ("box_len", ctypes.c_double),
                 ("box_origin", ctypes.c_double * 3), ("observer", ctypes.c_double * 3),
                 ("bias", ctypes.c_double), ("growth", ctypes.c_double), ("smooth_r", ctypes.c_double),
-                ("mask_tau", ctypes.c_double), ("flags", ctypes.c_uint32)]
+                ("mask_tau", ctypes.c_double), ("flags", ctypes.c_uint32), ("max_objects", ctypes.c_int64)]
 
 
 _LIB = None
@@ -107,7 +107,7 @@ class Plan:
     """A reconstruction plan: workspace, geometry, and the C-ABI calls on the current stream."""
 
     def __init__(self, n, box_len, observer, bias, growth, smooth_r, origin=(0.0, 0.0, 0.0), batch=1,
-                 mask_tau=0.1, randoms=True, keep_delta=False, start_buffers=False, device=None):
+                 mask_tau=0.1, randoms=True, keep_delta=False, start_buffers=False, max_objects=0, device=None):
         self.lib = load()
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
         flags = (0 if randoms else NO_RANDOMS) | (KEEP_DELTA if keep_delta else 0) | \
@@ -119,6 +119,7 @@ class Plan:
             p.observer[a] = float(observer[a])
         p.bias, p.growth, p.smooth_r, p.mask_tau, p.flags = float(bias), float(growth), float(smooth_r), \
             float(mask_tau), flags
+        p.max_objects = int(max_objects)
         self.params = p
         self.n, self.batch, self.randoms = int(n), int(batch), randoms
         nbytes = self.lib.recon_workspace_bytes(ctypes.byref(p))
@@ -230,6 +231,8 @@ class Plan:
 
 
 def plan_for(cat, **kw):
-    """Plan matching a synthetic catalogue's geometry."""
+    """Plan matching a synthetic catalogue's geometry (binned deposit sized for its largest catalogue)."""
+    if "max_objects" not in kw:
+        kw["max_objects"] = max(cat.gal_pos.shape[0], 0 if cat.ran_pos is None else cat.ran_pos.shape[0])
     return Plan(cat.n, cat.box_len, cat.observer, cat.bias, cat.growth, cat.smooth_r, origin=cat.origin,
                 mask_tau=cat.mask_tau, randoms=cat.ran_pos is not None, **kw)

@@ -80,8 +80,9 @@ def compare_full(g, r, label):
 # ---------------------------------------------------------------------------
 # Deposit
 # ---------------------------------------------------------------------------
+@pytest.mark.parametrize("binned", [False, True])
 @pytest.mark.parametrize("n", [8, 32, 128])
-def test_paint_bitexact_with_weights_wrap_and_order(gpu_lib, n):
+def test_paint_bitexact_with_weights_wrap_and_order(gpu_lib, n, binned):
     from paper_1504_02591_amd import native
     rng = np.random.default_rng(100 + n)
     box = 300.0
@@ -90,7 +91,7 @@ def test_paint_bitexact_with_weights_wrap_and_order(gpu_lib, n):
     pos[:5] = [[0, 0, 0], [box, box, box], [-1e-3, 0, 0], [box * 0.5, 0, box - 1e-4], [1e-7, 1e-7, 1e-7]]
     w = (rng.random(m) * 10).astype(np.float32)
     w[:3] = [0.0, np.float32(2.0 ** -40), np.float32(63.999)]
-    plan = native.Plan(n, box, (-100.0, 0.0, 0.0), 1.0, 0.5, 10.0, randoms=True)
+    plan = native.Plan(n, box, (-100.0, 0.0, 0.0), 1.0, 0.5, 10.0, randoms=True, max_objects=m if binned else 0)
     plan.paint(native.GAL, to_dev(pos), to_dev(w))
     perm = rng.permutation(m)
     plan.paint(native.RAN, to_dev(pos[perm]), to_dev(w[perm]))
@@ -103,15 +104,36 @@ def test_paint_bitexact_with_weights_wrap_and_order(gpu_lib, n):
     plan.close()
 
 
-def test_paint_accumulate_equals_single_call(gpu_lib):
+@pytest.mark.parametrize("binned", [False, True])
+def test_paint_accumulate_equals_single_call(gpu_lib, binned):
     from paper_1504_02591_amd import native
     rng = np.random.default_rng(7)
     pos = (rng.random((10000, 3)) * 100).astype(np.float32)
-    plan = native.Plan(16, 100.0, (50.0, 50.0, 50.0), 1.0, 0.5, 10.0, randoms=False)
+    plan = native.Plan(16, 100.0, (50.0, 50.0, 50.0), 1.0, 0.5, 10.0, randoms=False,
+                       max_objects=8000 if binned else 0)
     plan.paint(native.GAL, to_dev(pos[:3000]))
     plan.paint(native.GAL, to_dev(pos[3000:]), accumulate=True)
     g = plan.grid(native.GAL)[0].cpu().numpy()
     assert np.array_equal(g, O.paint(pos, None, 16, 100.0, (0, 0, 0)))
+    plan.close()
+
+
+def test_binned_deposit_clustered_and_invalid(gpu_lib):
+    from paper_1504_02591_amd import native
+    rng = np.random.default_rng(9)
+    n, box = 64, 640.0
+    pos = np.concatenate([(rng.random((200000, 3)) * 25.0 + 100.0),          # one dense clump
+                          rng.random((50000, 3)) * box]).astype(np.float32)
+    w = (rng.random(pos.shape[0]) * 3).astype(np.float32)
+    plan = native.Plan(n, box, (0.0, 0.0, 0.0), 1.0, 0.5, 10.0, randoms=False, max_objects=pos.shape[0])
+    plan.paint(native.GAL, to_dev(pos), to_dev(w))
+    assert np.array_equal(plan.grid(native.GAL)[0].cpu().numpy(), O.paint(pos, w, n, box, (0, 0, 0)))
+    bad = pos.copy()
+    bad[5] = np.inf
+    plan.paint(native.GAL, to_dev(bad), to_dev(w))
+    with pytest.raises(native.ReconError) as ei:
+        plan.solve()
+    assert ei.value.code == native.RECON_EINVAL
     plan.close()
 
 
@@ -238,7 +260,7 @@ def test_batched_matches_single_realisations(gpu_lib):
     goff = np.cumsum([0] + [c.gal_pos.shape[0] for c in cats]).astype(np.int64)
     roff = np.cumsum([0] + [c.ran_pos.shape[0] for c in cats]).astype(np.int64)
     c0 = cats[0]
-    plan = native.Plan(32, 500.0, c0.observer, 1.0, 0.7, 20.0, batch=3)
+    plan = native.Plan(32, 500.0, c0.observer, 1.0, 0.7, 20.0, batch=3, max_objects=ran.shape[0])
     plan.paint(native.GAL, to_dev(gal), offsets=to_dev(goff))
     plan.paint(native.RAN, to_dev(ran), offsets=to_dev(roff))
     plan.solve()
