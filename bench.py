@@ -48,6 +48,26 @@ def algorithmic_bytes(n, n_gal, n_ran, randoms=True, keep_delta=False):
     }
 
 
+COPY_BYTES = 1 << 30
+
+
+def measure_copy_bandwidth(torch, dev, reps=10):
+    """Device-to-device copy of 1 GiB (torch's copy kernel): read + write bytes per second."""
+    a = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device=dev).fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2 * COPY_BYTES * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+    return gbs
+
+
 def time_oracle_pass(n, box_len, observer, bias, growth, seed):
     """Wall time of one FP64 oracle correction pass on an n^3 field (the CPU-baseline sample)."""
     import numpy as np
@@ -90,6 +110,7 @@ def main():
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    copy_gbs = measure_copy_bandwidth(torch, dev)
     t_gen = time.perf_counter()
     cat = G.config2(n=args.n, scale=args.n / 512.0)
     t_gen = time.perf_counter() - t_gen
@@ -181,6 +202,7 @@ def main():
                    "n": args.n, "start": args.start, "tol": args.tol, "passes": passes[-1] if passes else None,
                    "eps": eps_last},
         "roofline": roofline,
+        "copy_GBs": round(copy_gbs, 1),
         "cpu_baseline": cpu,
         "stages": stages,
     }

@@ -52,9 +52,9 @@ bool valid_params(const recon_params_t* p, std::string* why) {
 }
 
 long long max_partial_blocks(int n) {
-  // x passes use 8 rows per block; z passes use 2*wz columns per block
-  long long xb = (long long)(n / 2 + 1) * n / 8;
-  long long zb = (long long)n * n / 2;   // upper bound (wz >= 1)
+  // blocks of the reducing launches: x passes hold RECON_TILE_X rows, z passes >= 2 columns
+  long long xb = (long long)(n / 2 + 1) * n / RECON_TILE_X;
+  long long zb = (long long)n * n / 2;
   return xb > zb ? xb : zb;
 }
 
@@ -533,6 +533,13 @@ int recon_plan(recon_plan_t** out, const recon_params_t* params, void* workspace
   pl->h_red.assign(2 * pl->batch, 0.0);
   pl->h_red2.assign(2 * pl->batch, 0.0);
 
+  {
+    const Ops* ops = ops_for(n);
+    if (!ops || ops->nb_x > max_partial_blocks(n) || ops->nb_z > max_partial_blocks(n)) {
+      delete pl;
+      return RECON_EINVAL;
+    }
+  }
   // twiddles exp(-2 pi i m / N), rounded once from double
   std::vector<float2> tw(n);
   for (int i = 0; i < n; ++i) {

@@ -1,13 +1,9 @@
 // Device helpers for the reconstruction kernels (gfx950, wave64).
 //
 // The 3D transforms are built from one block-level primitive: a length-N
-// complex FFT applied to W independent columns held in LDS as a row-major
-// [N][W+1] tile of float2 (one pad column keeps both the column-wise and the
-// row-wise access patterns free of bank conflicts).  The tile is transformed
-// by self-sorting Stockham passes (a radix-2 or radix-4 pass when log2 N is
-// not a multiple of 3, then radix-8 passes), each pass staging its
-// butterflies through registers: read all inputs, barrier, write all
-// outputs, barrier.  Twiddles come from an FP32 table of exp(-2 pi i m/N)
+// complex FFT of W independent columns, computed by self-sorting Stockham
+// passes on register fragments that exchange through an LDS tile (see the
+// fragment engine below).  Twiddles come from an FP32 table of exp(-2 pi i m/N)
 // rounded once from FP64 on the host and staged into LDS.
 #pragma once
 
@@ -82,68 +78,177 @@ __device__ __forceinline__ void dftR(float2* v) {
   else dft8<INV>(v);
 }
 
-// One self-sorting Stockham pass of radix R on a [N][LD] LDS tile holding W columns.
-// NS is the length of the sub-transforms already completed by earlier passes.
-template <int N, int W, int NT, int R, int NS, bool INV>
-__device__ __forceinline__ void stockham_pass(float2* buf, const float2* tw) {
-  constexpr int LD = W + 1;
-  constexpr int NB = (N / R) * W;
-  constexpr int PER = (NB + NT - 1) / NT;
-  float2 v[PER][R];
+// ---------------------------------------------------------------------------
+// Register-fragment FFT engine.
+//
+// A tile holds W independent length-N columns.  Each of the (N/8) W fragment
+// threads owns one radix-8 butterfly: element r of its fragment v[8] is row
+// i = j + r N/8 of column c.  Two thread layouts exist:
+//   column-fast (JF = false): c = t % W, j = t / W   (tiles whose columns are contiguous in memory)
+//   row-fast    (JF = true):  j = t % (N/8), c = t / (N/8)   (tiles whose rows are contiguous)
+// so that global loads and stores in fragment layout are coalesced either way.
+// The first radix-8 pass (sub-transform length NS = 1) consumes the fragment from
+// registers, the middle passes run LDS to LDS, and the last radix-8 pass
+// (NS = N/8) leaves the result in the same fragment layout in registers, so an
+// N = 512 transform costs two LDS exchanges.  Radix-2/4 passes (log2 N not a
+// multiple of 3) sit in the middle; each fragment thread then handles 8/R of them.
+// LDS layouts: column-fast [N][W+1]; row-fast [W][N + N/16] with one pad slot per
+// 16 rows, both free of bank conflicts for the strided pass accesses.
+// ---------------------------------------------------------------------------
+template <int N, int W, bool JF>
+struct Lay {
+  static constexpr int LDC = W + 1;
+  static constexpr int LDJ = N + N / 16;
+  static constexpr int SIZE = JF ? W * LDJ : N * LDC;
+  static constexpr int NTF = (N / 8) * W;   // fragment threads
+  __device__ __forceinline__ static int at(int i, int c) { return JF ? c * LDJ + i + (i >> 4) : i * LDC + c; }
+};
+
+// Block size that runs one fragment per thread (at least one wave).
+template <int N, int W>
+constexpr int frag_threads() { return (N / 8) * W < 64 ? 64 : (N / 8) * W; }
+
+template <int N, int W, int R, bool JF>
+__device__ __forceinline__ void bfly_coords(int b, int& c, int& j) {
+  if (JF) { j = b % (N / R); c = b / (N / R); }
+  else { c = b % W; j = b / W; }
+}
+
+// Fragment coordinates of this thread (valid when threadIdx.x < NTF).
+template <int N, int W, bool JF>
+__device__ __forceinline__ void frag_coords(int& c, int& j) { bfly_coords<N, W, 8, JF>(threadIdx.x, c, j); }
+
+// Generic LDS-to-LDS Stockham pass (radix R, completed sub-transform length NS).
+template <int N, int W, int R, int NS, bool INV, bool JF>
+__device__ __forceinline__ void lds_pass(float2* buf, const float2* tw) {
+  using L = Lay<N, W, JF>;
+  constexpr int Q = 8 / R;
+  const int t = threadIdx.x;
+  float2 v[Q][R];
+  if (t < L::NTF) {
 #pragma unroll
-  for (int it = 0; it < PER; ++it) {
-    const int b = threadIdx.x + it * NT;
-    if (NB % NT == 0 || b < NB) {
-      const int c = b % W, j = b / W;
+    for (int q = 0; q < Q; ++q) {
+      int c, j;
+      bfly_coords<N, W, R, JF>(t + q * L::NTF, c, j);
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[it][r] = buf[(j + r * (N / R)) * LD + c];
+      for (int r = 0; r < R; ++r) v[q][r] = buf[L::at(j + r * (N / R), c)];
     }
   }
   __syncthreads();
+  if (t < L::NTF) {
 #pragma unroll
-  for (int it = 0; it < PER; ++it) {
-    const int b = threadIdx.x + it * NT;
-    if (NB % NT == 0 || b < NB) {
-      const int c = b % W, j = b / W;
+    for (int q = 0; q < Q; ++q) {
+      int c, j;
+      bfly_coords<N, W, R, JF>(t + q * L::NTF, c, j);
       const int k = j % NS;
       if constexpr (NS > 1) {
 #pragma unroll
         for (int r = 1; r < R; ++r) {
           float2 w = tw[r * k * (N / (NS * R))];
           if (INV) w.y = -w.y;
-          v[it][r] = cmul(v[it][r], w);
+          v[q][r] = cmul(v[q][r], w);
         }
       }
-      dftR<R, INV>(v[it]);
+      dftR<R, INV>(v[q]);
       const int idx = (j / NS) * NS * R + k;
 #pragma unroll
-      for (int r = 0; r < R; ++r) buf[(idx + r * NS) * LD + c] = v[it][r];
+      for (int r = 0; r < R; ++r) buf[L::at(idx + r * NS, c)] = v[q][r];
     }
   }
   __syncthreads();
 }
 
-template <int N, int W, int NT, int NS, bool INV>
-__device__ __forceinline__ void radix8_passes(float2* buf, const float2* tw) {
-  if constexpr (NS < N) {
-    stockham_pass<N, W, NT, 8, NS, INV>(buf, tw);
-    radix8_passes<N, W, NT, NS * 8, INV>(buf, tw);
+// First radix-8 pass from the register fragment into LDS (preceded by a barrier that
+// protects earlier readers of the tile).
+template <int N, int W, bool INV, bool JF>
+__device__ __forceinline__ void first_pass(float2* v, float2* buf) {
+  using L = Lay<N, W, JF>;
+  __syncthreads();
+  if (threadIdx.x < L::NTF) {
+    int c, j;
+    frag_coords<N, W, JF>(c, j);
+    dft8<INV>(v);
+#pragma unroll
+    for (int r = 0; r < 8; ++r) buf[L::at(j * 8 + r, c)] = v[r];
+  }
+  __syncthreads();
+}
+
+// Last radix-8 pass (NS = N/8) from LDS into the register fragment.
+template <int N, int W, bool INV, bool JF>
+__device__ __forceinline__ void last_pass(float2* v, const float2* buf, const float2* tw) {
+  using L = Lay<N, W, JF>;
+  if (threadIdx.x < L::NTF) {
+    int c, j;
+    frag_coords<N, W, JF>(c, j);
+#pragma unroll
+    for (int r = 0; r < 8; ++r) v[r] = buf[L::at(j + r * (N / 8), c)];
+#pragma unroll
+    for (int r = 1; r < 8; ++r) {
+      float2 w = tw[r * j];
+      if (INV) w.y = -w.y;
+      v[r] = cmul(v[r], w);
+    }
+    dft8<INV>(v);
   }
 }
 
-// In-place length-N FFT of the W columns of an [N][W+1] LDS tile.  The caller
-// must have issued a barrier after filling the tile; the function ends with one.
-template <int N, int W, int NT, bool INV>
-__device__ __forceinline__ void tile_fft(float2* buf, const float2* tw) {
-  constexpr int REM = ilog2(N) % 3;
-  if constexpr (REM == 1) {
-    stockham_pass<N, W, NT, 2, 1, INV>(buf, tw);
-    radix8_passes<N, W, NT, 2, INV>(buf, tw);
-  } else if constexpr (REM == 2) {
-    stockham_pass<N, W, NT, 4, 1, INV>(buf, tw);
-    radix8_passes<N, W, NT, 4, INV>(buf, tw);
+// Middle passes between NS = 8 and NS = N/8 (factor N/64 as 2, 4, 8 or 4 x 4).
+template <int N, int W, bool INV, bool JF>
+__device__ __forceinline__ void middle_passes(float2* buf, const float2* tw) {
+  if constexpr (N == 128) lds_pass<N, W, 2, 8, INV, JF>(buf, tw);
+  else if constexpr (N == 256) lds_pass<N, W, 4, 8, INV, JF>(buf, tw);
+  else if constexpr (N == 512) lds_pass<N, W, 8, 8, INV, JF>(buf, tw);
+  else if constexpr (N == 1024) {
+    lds_pass<N, W, 4, 8, INV, JF>(buf, tw);
+    lds_pass<N, W, 4, 32, INV, JF>(buf, tw);
+  }
+}
+
+// Length-N FFT of the tile, register fragment in and out.  The caller must place a
+// barrier before its next write to the tile.
+template <int N, int W, bool INV, bool JF>
+__device__ __forceinline__ void fft_rr(float2* v, float2* buf, const float2* tw) {
+  using L = Lay<N, W, JF>;
+  if constexpr (N == 8) {
+    if (threadIdx.x < L::NTF) dft8<INV>(v);
+  } else if constexpr (N < 64) {
+    first_pass<N, W, INV, JF>(v, buf);
+    lds_pass<N, W, N / 8, 8, INV, JF>(buf, tw);
+    if (threadIdx.x < L::NTF) {
+      int c, j;
+      frag_coords<N, W, JF>(c, j);
+#pragma unroll
+      for (int r = 0; r < 8; ++r) v[r] = buf[L::at(j + r * (N / 8), c)];
+    }
   } else {
-    radix8_passes<N, W, NT, 1, INV>(buf, tw);
+    first_pass<N, W, INV, JF>(v, buf);
+    middle_passes<N, W, INV, JF>(buf, tw);
+    last_pass<N, W, INV, JF>(v, buf, tw);
+  }
+}
+
+// Length-N FFT of the tile, register fragment in, natural order in LDS out (ends with a barrier).
+template <int N, int W, bool INV, bool JF>
+__device__ __forceinline__ void fft_rl(float2* v, float2* buf, const float2* tw) {
+  using L = Lay<N, W, JF>;
+  if constexpr (N == 8) {
+    __syncthreads();
+    if (threadIdx.x < L::NTF) {
+      int c, j;
+      frag_coords<N, W, JF>(c, j);
+      dft8<INV>(v);
+#pragma unroll
+      for (int r = 0; r < 8; ++r) buf[L::at(r, c)] = v[r];
+    }
+    __syncthreads();
+  } else if constexpr (N < 64) {
+    first_pass<N, W, INV, JF>(v, buf);
+    lds_pass<N, W, N / 8, 8, INV, JF>(buf, tw);
+  } else {
+    first_pass<N, W, INV, JF>(v, buf);
+    middle_passes<N, W, INV, JF>(buf, tw);
+    lds_pass<N, W, 8, N / 8, INV, JF>(buf, tw);
   }
 }
 

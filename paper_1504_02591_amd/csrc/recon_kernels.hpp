@@ -42,13 +42,22 @@ struct CicGeo {
 
 enum ZIterMode { ZI_PLAIN = 0, ZI_FFTA = 1, ZI_LEARNED = 2 };
 
-template <int N> constexpr int wz() { return N >= 1024 ? 8 : (N / 2 < 16 ? N / 2 : 16); }   // packed z columns
-template <int N> constexpr int wy() { return N >= 1024 ? 8 : (N < 16 ? N : 16); }           // y-pass columns
-template <int N> constexpr int wx() { return 8; }                                             // x-pass rows
-// threads per block of the z, y and x passes
-template <int N> constexpr int ntz() { return N >= 256 ? 512 : 256; }
-template <int N> constexpr int nty() { return N >= 256 ? 512 : 256; }
-template <int N> constexpr int ntx() { return 256; }
+// Tile shapes (compile-time tuning knobs): packed z columns, y-pass columns, x-pass rows.
+// Each block runs one radix-8 fragment per thread, (N/8) * tile threads.
+#ifndef RECON_TILE_Z
+#define RECON_TILE_Z 16
+#endif
+#ifndef RECON_TILE_Y
+#define RECON_TILE_Y 16
+#endif
+#ifndef RECON_TILE_X
+#define RECON_TILE_X 4
+#endif
+constexpr int cmin(int a, int b) { return a < b ? a : b; }
+template <int N> constexpr int wz() { return N >= 1024 ? 8 : cmin(N / 2, RECON_TILE_Z); }
+template <int N> constexpr int wy() { return N >= 1024 ? 8 : cmin(N, RECON_TILE_Y); }
+template <int N> constexpr int wx() { return RECON_TILE_X; }
+
 
 __device__ __forceinline__ long long ceil_div_ll(long long a, long long b) { return (a + b - 1) / b; }
 
@@ -459,8 +468,9 @@ __global__ void __launch_bounds__(256) k_mask(const long long* __restrict__ gr, 
 }
 
 // ---------------------------------------------------------------------------
-// z passes (real <-> half spectrum along z, two real columns per complex column)
-// Tile: one y row, 2*WP consecutive x.  LDS holds [N][WP+1] packed columns.
+// z passes (real <-> half spectrum along z, two real columns packed per complex
+// column).  Tile: one y row and 2*WP consecutive x; fragment threads are column-fast
+// over the WP packed columns.
 // ---------------------------------------------------------------------------
 template <int N, int WP>
 __device__ __forceinline__ void z_tile_coords(int& y, int& x0) {
@@ -469,32 +479,32 @@ __device__ __forceinline__ void z_tile_coords(int& y, int& x0) {
   x0 = (blockIdx.x % TPR) * 2 * WP;
 }
 
-// Load a half-spectrum column tile and expand it Hermitian-wise into packed full columns.
-template <int N, int WP, int NT>
-__device__ __forceinline__ void z_load_pack(float2* buf, const float2* __restrict__ a, int y, int x0) {
-  constexpr int LD = WP + 1;
-  for (int e = threadIdx.x; e < (N / 2 + 1) * WP; e += NT) {
-    const int p = e % WP, kz = e / WP;
-    const long long base = ((long long)kz * N + y) * N + x0 + p;
+// Packed full-length column element k of the half spectra A (column x0+c) and B
+// (column x0+c+WP): Z(k) = A(k) + i B(k), extended Hermitian-wise for k > N/2; the
+// imaginary parts at k = 0 and N/2 are dropped as for a real inverse transform.
+template <int N, int WP>
+__device__ __forceinline__ void z_pack_frag(float2* v, const float2* __restrict__ a, int y, int x0, int c, int j) {
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    const int k = j + r * (N / 8);
+    const int m = k <= N / 2 ? k : N - k;
+    const long long base = ((long long)m * N + y) * N + x0 + c;
     const float2 A = a[base], B = a[base + WP];
-    if (kz == 0 || kz == N / 2) {
-      buf[kz * LD + p] = make_float2(A.x, B.x);
-    } else {
-      buf[kz * LD + p] = make_float2(A.x - B.y, A.y + B.x);
-      buf[(N - kz) * LD + p] = make_float2(A.x + B.y, B.x - A.y);
-    }
+    if (k == 0 || k == N / 2) v[r] = make_float2(A.x, B.x);
+    else if (k < N / 2) v[r] = make_float2(A.x - B.y, A.y + B.x);
+    else v[r] = make_float2(A.x + B.y, B.x - A.y);
   }
 }
 
-// Split a transformed packed tile into the half spectra of its two real columns and store.
-// MULK: multiply by i k'_z.
+// Split a transformed packed tile (natural order in LDS) into the half spectra of its
+// two real columns and store them.  MULK: multiply by i k'_z.
 template <int N, int WP, int NT, bool MULK>
 __device__ __forceinline__ void z_unpack_store(const float2* buf, float2* __restrict__ out, int y, int x0, float kf) {
-  constexpr int LD = WP + 1;
+  using L = Lay<N, WP, false>;
   for (int e = threadIdx.x; e < (N / 2 + 1) * WP; e += NT) {
     const int p = e % WP, kz = e / WP;
-    const float2 Z = buf[kz * LD + p];
-    const float2 M = buf[((N - kz) & (N - 1)) * LD + p];
+    const float2 Z = buf[L::at(kz, p)];
+    const float2 M = buf[L::at((N - kz) & (N - 1), p)];
     float2 A = make_float2(0.5f * (Z.x + M.x), 0.5f * (Z.y - M.y));
     float2 B = make_float2(0.5f * (Z.y + M.y), 0.5f * (M.x - Z.x));
     if (MULK) {
@@ -508,217 +518,203 @@ __device__ __forceinline__ void z_unpack_store(const float2* buf, float2* __rest
   }
 }
 
+// Scaled line-of-sight vector of a node: r = (origin + H i - observer) / R0.
+__device__ __forceinline__ float los_comp(const Geo& g, int a, int i) { return fmaf(g.hs, (float)i, g.ds[a]); }
+
+template <int N> constexpr int ntz() { return frag_threads<N, wz<N>()>(); }
+template <int N> constexpr int nty() { return frag_threads<N, wy<N>()>(); }
+template <int N> constexpr int ntx() { return frag_threads<N, wx<N>()>(); }
+
 // Forward z transform of int64 grids (units 2^-32) into half spectra.
 template <int N, int NA>
-__global__ void __launch_bounds__(ntz<N>()) __attribute__((amdgpu_waves_per_eu(4))) k_z_fwd_grid(const long long* __restrict__ g0, const long long* __restrict__ g1,
-                                                    float2* __restrict__ o0, float2* __restrict__ o1,
-                                                    const float2* __restrict__ twg) {
-  constexpr int NT = ntz<N>();
-  constexpr int WP = wz<N>(), LD = WP + 1;
-  __shared__ float2 buf[N * LD];
+__global__ void __launch_bounds__(ntz<N>()) k_z_fwd_grid(const long long* __restrict__ g0,
+                                                         const long long* __restrict__ g1, float2* __restrict__ o0,
+                                                         float2* __restrict__ o1, const float2* __restrict__ twg) {
+  constexpr int NT = ntz<N>(), WP = wz<N>();
+  using L = Lay<N, WP, false>;
+  __shared__ float2 buf[L::SIZE];
   __shared__ float2 tw[N];
   stage_twiddles<N, NT>(tw, twg);
-  int y, x0;
+  int y, x0, c, j;
   z_tile_coords<N, WP>(y, x0);
+  frag_coords<N, WP, false>(c, j);
+  const bool act = threadIdx.x < L::NTF;
   const long long n3 = (long long)N * N * N, cn = (long long)(N / 2 + 1) * N * N;
   const int b = blockIdx.y;
   const float unit = 2.3283064365386963e-10f;   // 2^-32
 #pragma unroll
   for (int a = 0; a < NA; ++a) {
-    const long long* g = (a == 0 ? g0 : g1) + b * n3;
-    float2* o = (a == 0 ? o0 : o1) + b * cn;
-    for (int e = threadIdx.x; e < N * WP; e += NT) {
-      const int p = e % WP, z = e / WP;
-      const long long base = ((long long)z * N + y) * N + x0 + p;
-      buf[z * LD + p] = make_float2((float)g[base] * unit, (float)g[base + WP] * unit);
+    const long long* gsrc = (a == 0 ? g0 : g1) + b * n3;
+    float2 v[8];
+    if (act) {
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        const long long base = ((long long)(j + r * (N / 8)) * N + y) * N + x0 + c;
+        v[r] = make_float2((float)gsrc[base] * unit, (float)gsrc[base + WP] * unit);
+      }
     }
-    __syncthreads();
-    tile_fft<N, WP, NT, false>(buf, tw);
-    z_unpack_store<N, WP, NT, false>(buf, o, y, x0, 0.f);
-    __syncthreads();
+    fft_rl<N, WP, false, false>(v, buf, tw);
+    z_unpack_store<N, WP, NT, false>(buf, (a == 0 ? o0 : o1) + b * cn, y, x0, 0.f);
   }
 }
 
 // Forward z transform of one real field.
 template <int N>
-__global__ void __launch_bounds__(ntz<N>()) __attribute__((amdgpu_waves_per_eu(4))) k_z_fwd_real(const float* __restrict__ f, float2* __restrict__ o,
-                                                    const float2* __restrict__ twg) {
-  constexpr int NT = ntz<N>();
-  constexpr int WP = wz<N>(), LD = WP + 1;
-  __shared__ float2 buf[N * LD];
+__global__ void __launch_bounds__(ntz<N>()) k_z_fwd_real(const float* __restrict__ f, float2* __restrict__ o,
+                                                         const float2* __restrict__ twg) {
+  constexpr int NT = ntz<N>(), WP = wz<N>();
+  using L = Lay<N, WP, false>;
+  __shared__ float2 buf[L::SIZE];
   __shared__ float2 tw[N];
   stage_twiddles<N, NT>(tw, twg);
-  int y, x0;
+  int y, x0, c, j;
   z_tile_coords<N, WP>(y, x0);
+  frag_coords<N, WP, false>(c, j);
   const long long n3 = (long long)N * N * N, cn = (long long)(N / 2 + 1) * N * N;
   const int b = blockIdx.y;
   f += b * n3;
-  o += b * cn;
-  for (int e = threadIdx.x; e < N * WP; e += NT) {
-    const int p = e % WP, z = e / WP;
-    const long long base = ((long long)z * N + y) * N + x0 + p;
-    buf[z * LD + p] = make_float2(f[base], f[base + WP]);
+  float2 v[8];
+  if (threadIdx.x < L::NTF) {
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const long long base = ((long long)(j + r * (N / 8)) * N + y) * N + x0 + c;
+      v[r] = make_float2(f[base], f[base + WP]);
+    }
   }
-  __syncthreads();
-  tile_fft<N, WP, NT, false>(buf, tw);
-  z_unpack_store<N, WP, NT, false>(buf, o, y, x0, 0.f);
+  fft_rl<N, WP, false, false>(v, buf, tw);
+  z_unpack_store<N, WP, NT, false>(buf, o + b * cn, y, x0, 0.f);
 }
 
 // Inverse z transform of the smoothed galaxy (and random) densities, overdensity in
-// configuration space, forward z transform of the overdensity (written over arr0).
+// configuration space, forward z transform of the overdensity (written over a0).
 //   with randoms:  delta = m (G - alpha R) / (alpha R), 0 outside the mask or where R <= 0
 //   mean density:  delta = G / rho_bar - 1
 template <int N, int NA>
-__global__ void __launch_bounds__(ntz<N>()) __attribute__((amdgpu_waves_per_eu(4))) k_z_delta(float2* __restrict__ a0, const float2* __restrict__ a1,
-                                                 const unsigned char* __restrict__ mask,
-                                                 const DeltaScal* __restrict__ sc, float* __restrict__ delta_out,
-                                                 const float2* __restrict__ twg) {
-  constexpr int NT = ntz<N>();
-  constexpr int WP = wz<N>(), LD = WP + 1;
-  constexpr int EPT = (N * WP + NT - 1) / NT;
-  __shared__ float2 buf[N * LD];
+__global__ void __launch_bounds__(ntz<N>()) k_z_delta(float2* __restrict__ a0, const float2* __restrict__ a1,
+                                                      const unsigned char* __restrict__ mask,
+                                                      const DeltaScal* __restrict__ sc, float* __restrict__ delta_out,
+                                                      const float2* __restrict__ twg) {
+  constexpr int NT = ntz<N>(), WP = wz<N>();
+  using L = Lay<N, WP, false>;
+  __shared__ float2 buf[L::SIZE];
   __shared__ float2 tw[N];
   stage_twiddles<N, NT>(tw, twg);
-  int y, x0;
+  int y, x0, c, j;
   z_tile_coords<N, WP>(y, x0);
+  frag_coords<N, WP, false>(c, j);
+  const bool act = threadIdx.x < L::NTF;
   const long long n3 = (long long)N * N * N, cn = (long long)(N / 2 + 1) * N * N;
   const int b = blockIdx.y;
   a0 += b * cn;
-  if (NA == 2) a1 += b * cn;
   const DeltaScal s = sc[b];
-  float2 gv[EPT];
-  z_load_pack<N, WP, NT>(buf, a0, y, x0);
-  __syncthreads();
-  tile_fft<N, WP, NT, true>(buf, tw);
-#pragma unroll
-  for (int i = 0; i < EPT; ++i) {
-    const int e = threadIdx.x + i * NT;
-    if (e < N * WP) gv[i] = buf[(e / WP) * LD + e % WP];
-  }
-  __syncthreads();
+  float2 gv[8], v[8];
+  if (act) z_pack_frag<N, WP>(gv, a0, y, x0, c, j);
+  fft_rr<N, WP, true, false>(gv, buf, tw);
   if constexpr (NA == 2) {
-    z_load_pack<N, WP, NT>(buf, a1, y, x0);
-    __syncthreads();
-    tile_fft<N, WP, NT, true>(buf, tw);
+    if (act) z_pack_frag<N, WP>(v, a1 + b * cn, y, x0, c, j);
+    fft_rr<N, WP, true, false>(v, buf, tw);
   }
+  if (act) {
 #pragma unroll
-  for (int i = 0; i < EPT; ++i) {
-    const int e = threadIdx.x + i * NT;
-    if (e < N * WP) {
-      const int p = e % WP, z = e / WP;
-      const long long cell = ((long long)z * N + y) * N + x0 + p;
+    for (int r = 0; r < 8; ++r) {
+      const long long cell = ((long long)(j + r * (N / 8)) * N + y) * N + x0 + c;
       float d0, d1;
       if constexpr (NA == 2) {
-        const float2 rv = buf[z * LD + p];
         const unsigned char* m = mask + b * n3;
-        const float ar0 = s.alpha * rv.x, ar1 = s.alpha * rv.y;
-        d0 = (m[cell] && ar0 > 0.f) ? (gv[i].x - ar0) / ar0 : 0.f;
-        d1 = (m[cell + WP] && ar1 > 0.f) ? (gv[i].y - ar1) / ar1 : 0.f;
+        const float ar0 = s.alpha * v[r].x, ar1 = s.alpha * v[r].y;
+        d0 = (m[cell] && ar0 > 0.f) ? (gv[r].x - ar0) / ar0 : 0.f;
+        d1 = (m[cell + WP] && ar1 > 0.f) ? (gv[r].y - ar1) / ar1 : 0.f;
       } else {
-        d0 = gv[i].x * s.inv_rhobar - 1.f;
-        d1 = gv[i].y * s.inv_rhobar - 1.f;
+        d0 = gv[r].x * s.inv_rhobar - 1.f;
+        d1 = gv[r].y * s.inv_rhobar - 1.f;
       }
-      gv[i] = make_float2(d0, d1);
+      v[r] = make_float2(d0, d1);
       if (delta_out) {
         delta_out[b * n3 + cell] = d0;
         delta_out[b * n3 + cell + WP] = d1;
       }
     }
   }
-  __syncthreads();
-#pragma unroll
-  for (int i = 0; i < EPT; ++i) {
-    const int e = threadIdx.x + i * NT;
-    if (e < N * WP) buf[(e / WP) * LD + e % WP] = gv[i];
-  }
-  __syncthreads();
-  tile_fft<N, WP, NT, false>(buf, tw);
+  fft_rl<N, WP, false, false>(v, buf, tw);
   z_unpack_store<N, WP, NT, false>(buf, a0, y, x0, 0.f);
 }
-
-// Scaled line-of-sight vector of a node: r = (origin + H i - observer) / R0.
-__device__ __forceinline__ float los_comp(const Geo& g, int a, int i) { return fmaf(g.hs, (float)i, g.ds[a]); }
 
 // One iteration's configuration-space step (step A tail + step B head):
 //   inverse z of the three displacement spectra -> s = sum_j r_j Psi_j
 //   V_j = u r_hat_j = s r_j / |r|^2 -> forward z; the z component is multiplied by i k'_z.
 // Arrays are updated in place.  Start modes (first pass only):
 //   ZI_FFTA:    u_0 = start_scale * u_p, Delta = u_0 - u_p stored in corr
-//   ZI_LEARNED: u_0 = u_p + corr
+//   ZI_LEARNED: u_0 = u_p + corr (corr taken as 0 at the observer)
 // and both accumulate S1 = sum Delta u_p, S2 = sum Delta^2 into partials.
 template <int N, int MODE>
-__global__ void __launch_bounds__(ntz<N>()) __attribute__((amdgpu_waves_per_eu(4))) k_z_iter(float2* __restrict__ a0, float2* __restrict__ a1,
-                                                float2* __restrict__ a2, Geo g, float* __restrict__ corr,
-                                                double* __restrict__ partials, const int* __restrict__ active,
-                                                const float2* __restrict__ twg) {
-  constexpr int NT = ntz<N>();
-  constexpr int WP = wz<N>(), LD = WP + 1;
-  constexpr int EPT = (N * WP + NT - 1) / NT;
+__global__ void __launch_bounds__(ntz<N>()) k_z_iter(float2* __restrict__ a0, float2* __restrict__ a1,
+                                                     float2* __restrict__ a2, Geo g, float* __restrict__ corr,
+                                                     double* __restrict__ partials, const int* __restrict__ active,
+                                                     const float2* __restrict__ twg) {
+  constexpr int NT = ntz<N>(), WP = wz<N>();
+  using L = Lay<N, WP, false>;
   const int b = blockIdx.y;
   if (active && !active[b]) return;
-  __shared__ float2 buf[N * LD];
+  __shared__ float2 buf[L::SIZE];
   __shared__ float2 tw[N];
   stage_twiddles<N, NT>(tw, twg);
-  int y, x0;
+  int y, x0, c, j;
   z_tile_coords<N, WP>(y, x0);
+  frag_coords<N, WP, false>(c, j);
+  const bool act = threadIdx.x < L::NTF;
   const long long n3 = (long long)N * N * N, cn = (long long)(N / 2 + 1) * N * N;
   float2* arr[3] = {a0 + b * cn, a1 + b * cn, a2 + b * cn};
-  float s0[EPT], s1[EPT];
-#pragma unroll
-  for (int i = 0; i < EPT; ++i) { s0[i] = 0.f; s1[i] = 0.f; }
   const float ry = los_comp(g, 1, y);
+  const float rx0 = los_comp(g, 0, x0 + c), rx1 = los_comp(g, 0, x0 + c + WP);
+  float s0[8], s1[8];
+#pragma unroll
+  for (int r = 0; r < 8; ++r) { s0[r] = 0.f; s1[r] = 0.f; }
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    z_load_pack<N, WP, NT>(buf, arr[a], y, x0);
-    __syncthreads();
-    tile_fft<N, WP, NT, true>(buf, tw);
+    float2 v[8];
+    if (act) z_pack_frag<N, WP>(v, arr[a], y, x0, c, j);
+    fft_rr<N, WP, true, false>(v, buf, tw);
+    if (act) {
 #pragma unroll
-    for (int i = 0; i < EPT; ++i) {
-      const int e = threadIdx.x + i * NT;
-      if (e < N * WP) {
-        const int p = e % WP, z = e / WP;
-        const float2 v = buf[z * LD + p];
-        float r0, r1;
-        if (a == 0) { r0 = los_comp(g, 0, x0 + p); r1 = los_comp(g, 0, x0 + p + WP); }
-        else if (a == 1) { r0 = ry; r1 = ry; }
-        else { r0 = los_comp(g, 2, z); r1 = r0; }
-        s0[i] = fmaf(r0, v.x, s0[i]);
-        s1[i] = fmaf(r1, v.y, s1[i]);
+      for (int r = 0; r < 8; ++r) {
+        const float rz = los_comp(g, 2, j + r * (N / 8));
+        const float r0 = a == 0 ? rx0 : (a == 1 ? ry : rz);
+        const float r1 = a == 0 ? rx1 : (a == 1 ? ry : rz);
+        s0[r] = fmaf(r0, v[r].x, s0[r]);
+        s1[r] = fmaf(r1, v[r].y, s1[r]);
       }
     }
-    __syncthreads();
   }
-  // s -> q = u_0 / |r|, so that V_j = q * r_j
+  // s -> q = u_0 / |r|, so that V_j = q r_j
   double acc1 = 0.0, acc2 = 0.0;
+  if (act) {
 #pragma unroll
-  for (int i = 0; i < EPT; ++i) {
-    const int e = threadIdx.x + i * NT;
-    if (e < N * WP) {
-      const int p = e % WP, z = e / WP;
+    for (int r = 0; r < 8; ++r) {
+      const int z = j + r * (N / 8);
       const float rz = los_comp(g, 2, z);
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
-        const float rx = los_comp(g, 0, x0 + p + h * WP);
+        const float rx = h ? rx1 : rx0;
         const float r2 = rx * rx + ry * ry + rz * rz;
         const float ir = r2 > 0.f ? rsqrtf(r2) : 0.f;
-        const float up = (h ? s1[i] : s0[i]) * ir;        // u_p = s / |r|
+        const float up = (h ? s1[r] : s0[r]) * ir;     // u_p = s / |r|
         float u0 = up;
         if (MODE != ZI_PLAIN) {
-          const long long cell = b * n3 + ((long long)z * N + y) * N + x0 + p + h * WP;
+          const long long cell = b * n3 + ((long long)z * N + y) * N + x0 + c + h * WP;
           float dlt;
           if (MODE == ZI_FFTA) {
             u0 = g.start_scale * up;
             dlt = u0 - up;
             corr[cell] = dlt;
           } else {
-            dlt = corr[cell];
+            dlt = r2 > 0.f ? corr[cell] : 0.f;
             u0 = up + dlt;
           }
           acc1 += (double)dlt * (double)up;
           acc2 += (double)dlt * (double)dlt;
         }
         const float q = u0 * ir;
-        if (h) s1[i] = q; else s0[i] = q;
+        if (h) s1[r] = q; else s0[r] = q;
       }
     }
   }
@@ -733,23 +729,19 @@ __global__ void __launch_bounds__(ntz<N>()) __attribute__((amdgpu_waves_per_eu(4
   }
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
+    float2 v[8];
+    if (act) {
 #pragma unroll
-    for (int i = 0; i < EPT; ++i) {
-      const int e = threadIdx.x + i * NT;
-      if (e < N * WP) {
-        const int p = e % WP, z = e / WP;
-        float r0, r1;
-        if (a == 0) { r0 = los_comp(g, 0, x0 + p); r1 = los_comp(g, 0, x0 + p + WP); }
-        else if (a == 1) { r0 = ry; r1 = ry; }
-        else { r0 = los_comp(g, 2, z); r1 = r0; }
-        buf[z * LD + p] = make_float2(s0[i] * r0, s1[i] * r1);
+      for (int r = 0; r < 8; ++r) {
+        const float rz = los_comp(g, 2, j + r * (N / 8));
+        const float r0 = a == 0 ? rx0 : (a == 1 ? ry : rz);
+        const float r1 = a == 0 ? rx1 : (a == 1 ? ry : rz);
+        v[r] = make_float2(s0[r] * r0, s1[r] * r1);
       }
     }
-    __syncthreads();
-    tile_fft<N, WP, NT, false>(buf, tw);
+    fft_rl<N, WP, false, false>(v, buf, tw);
     if (a == 2) z_unpack_store<N, WP, NT, true>(buf, arr[a], y, x0, g.kf);
     else z_unpack_store<N, WP, NT, false>(buf, arr[a], y, x0, g.kf);
-    __syncthreads();
   }
 }
 
@@ -757,73 +749,55 @@ __global__ void __launch_bounds__(ntz<N>()) __attribute__((amdgpu_waves_per_eu(4
 // (x, y, z, 0) per cell (when psi4 != null), u = Psi.r_hat (when u_out != null) and
 // accumulates S3 = sum corr * u (when corr != null).
 template <int N>
-__global__ void __launch_bounds__(ntz<N>()) __attribute__((amdgpu_waves_per_eu(4))) k_z_final(const float2* __restrict__ a0, const float2* __restrict__ a1,
+__global__ void __launch_bounds__(ntz<N>()) k_z_final(const float2* __restrict__ a0, const float2* __restrict__ a1,
                                                       const float2* __restrict__ a2, Geo g, float4* __restrict__ psi4,
                                                       float* __restrict__ u_out, const float* __restrict__ corr,
                                                       double* __restrict__ partials, const int* __restrict__ active,
                                                       const float2* __restrict__ twg) {
-  constexpr int NT = ntz<N>();
-  constexpr int WP = wz<N>(), LD = WP + 1;
-  constexpr int EPT = (N * WP + NT - 1) / NT;
+  constexpr int NT = ntz<N>(), WP = wz<N>();
+  using L = Lay<N, WP, false>;
   const int b = blockIdx.y;
   if (active && !active[b]) return;
-  __shared__ float2 buf[N * LD];
+  __shared__ float2 buf[L::SIZE];
   __shared__ float2 tw[N];
   stage_twiddles<N, NT>(tw, twg);
-  int y, x0;
+  int y, x0, c, j;
   z_tile_coords<N, WP>(y, x0);
+  frag_coords<N, WP, false>(c, j);
+  const bool act = threadIdx.x < L::NTF;
   const long long n3 = (long long)N * N * N, cn = (long long)(N / 2 + 1) * N * N;
   const float2* arr[3] = {a0 + b * cn, a1 + b * cn, a2 + b * cn};
-  float s0[EPT], s1[EPT];
-  float2 px[EPT], py[EPT];
-#pragma unroll
-  for (int i = 0; i < EPT; ++i) { s0[i] = 0.f; s1[i] = 0.f; }
+  float2 px[8], py[8], v[8];
+  if (act) z_pack_frag<N, WP>(px, arr[0], y, x0, c, j);
+  fft_rr<N, WP, true, false>(px, buf, tw);
+  if (act) z_pack_frag<N, WP>(py, arr[1], y, x0, c, j);
+  fft_rr<N, WP, true, false>(py, buf, tw);
+  if (act) z_pack_frag<N, WP>(v, arr[2], y, x0, c, j);
+  fft_rr<N, WP, true, false>(v, buf, tw);
   const float ry = los_comp(g, 1, y);
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    z_load_pack<N, WP, NT>(buf, arr[a], y, x0);
-    __syncthreads();
-    tile_fft<N, WP, NT, true>(buf, tw);
-#pragma unroll
-    for (int i = 0; i < EPT; ++i) {
-      const int e = threadIdx.x + i * NT;
-      if (e < N * WP) {
-        const int p = e % WP, z = e / WP;
-        const float2 v = buf[z * LD + p];
-        if (a == 0) px[i] = v;
-        else if (a == 1) py[i] = v;
-        else if (psi4) {
-          const long long cell = b * n3 + ((long long)z * N + y) * N + x0 + p;
-          psi4[cell] = make_float4(px[i].x, py[i].x, v.x, 0.f);
-          psi4[cell + WP] = make_float4(px[i].y, py[i].y, v.y, 0.f);
-        }
-        float r0, r1;
-        if (a == 0) { r0 = los_comp(g, 0, x0 + p); r1 = los_comp(g, 0, x0 + p + WP); }
-        else if (a == 1) { r0 = ry; r1 = ry; }
-        else { r0 = los_comp(g, 2, z); r1 = r0; }
-        s0[i] = fmaf(r0, v.x, s0[i]);
-        s1[i] = fmaf(r1, v.y, s1[i]);
-      }
-    }
-    __syncthreads();
-  }
-  if (!u_out && !corr) return;
+  const float rx0 = los_comp(g, 0, x0 + c), rx1 = los_comp(g, 0, x0 + c + WP);
   double acc = 0.0;
+  if (act) {
 #pragma unroll
-  for (int i = 0; i < EPT; ++i) {
-    const int e = threadIdx.x + i * NT;
-    if (e < N * WP) {
-      const int p = e % WP, z = e / WP;
-      const float rz = los_comp(g, 2, z);
+    for (int r = 0; r < 8; ++r) {
+      const int z = j + r * (N / 8);
+      const long long cell = b * n3 + ((long long)z * N + y) * N + x0 + c;
+      if (psi4) {
+        psi4[cell] = make_float4(px[r].x, py[r].x, v[r].x, 0.f);
+        psi4[cell + WP] = make_float4(px[r].y, py[r].y, v[r].y, 0.f);
+      }
+      if (u_out || corr) {
+        const float rz = los_comp(g, 2, z);
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const float rx = los_comp(g, 0, x0 + p + h * WP);
-        const float r2 = rx * rx + ry * ry + rz * rz;
-        const float ir = r2 > 0.f ? rsqrtf(r2) : 0.f;
-        const float u = (h ? s1[i] : s0[i]) * ir;
-        const long long cell = b * n3 + ((long long)z * N + y) * N + x0 + p + h * WP;
-        if (u_out) u_out[cell] = u;
-        if (corr) acc += (double)corr[cell] * (double)u;
+        for (int h = 0; h < 2; ++h) {
+          const float rx = h ? rx1 : rx0;
+          const float sx = h ? px[r].y : px[r].x, sy = h ? py[r].y : py[r].x, sz = h ? v[r].y : v[r].x;
+          const float r2 = rx * rx + ry * ry + rz * rz;
+          const float ir = r2 > 0.f ? rsqrtf(r2) : 0.f;
+          const float u = (rx * sx + ry * sy + rz * sz) * ir;
+          if (u_out) u_out[cell + h * WP] = u;
+          if (corr) acc += (double)corr[cell + h * WP] * (double)u;
+        }
       }
     }
   }
@@ -852,7 +826,7 @@ __global__ void __launch_bounds__(256) k_psi_planar(const float4* __restrict__ p
 }
 
 // ---------------------------------------------------------------------------
-// y passes.  Tile: one kz plane, W consecutive x, all N rows.
+// y passes.  Tile: one kz plane, W consecutive x, all N rows; column-fast fragments.
 // ---------------------------------------------------------------------------
 template <int N, int W>
 __device__ __forceinline__ void y_tile_coords(int& p, int& x0) {
@@ -860,44 +834,39 @@ __device__ __forceinline__ void y_tile_coords(int& p, int& x0) {
   x0 = (blockIdx.x % (N / W)) * W;
 }
 
-template <int N, int W, int NT>
-__device__ __forceinline__ void y_load(float2* buf, const float2* __restrict__ a, int p, int x0) {
-  constexpr int LD = W + 1;
-  for (int e = threadIdx.x; e < N * W; e += NT) {
-    const int c = e % W, j = e / W;
-    buf[j * LD + c] = a[((long long)p * N + j) * N + x0 + c];
-  }
+template <int N>
+__device__ __forceinline__ void y_load(float2* v, const float2* __restrict__ a, int p, int x0, int c, int j) {
+#pragma unroll
+  for (int r = 0; r < 8; ++r) v[r] = a[((long long)p * N + j + r * (N / 8)) * N + x0 + c];
 }
 
-template <int N, int W, int NT>
-__device__ __forceinline__ void y_store(const float2* buf, float2* __restrict__ a, int p, int x0) {
-  constexpr int LD = W + 1;
-  for (int e = threadIdx.x; e < N * W; e += NT) {
-    const int c = e % W, j = e / W;
-    a[((long long)p * N + j) * N + x0 + c] = buf[j * LD + c];
-  }
+template <int N>
+__device__ __forceinline__ void y_store(const float2* v, float2* __restrict__ a, int p, int x0, int c, int j) {
+#pragma unroll
+  for (int r = 0; r < 8; ++r) a[((long long)p * N + j + r * (N / 8)) * N + x0 + c] = v[r];
 }
 
 template <int N, int NA, bool INV>
-__global__ void __launch_bounds__(nty<N>()) __attribute__((amdgpu_waves_per_eu(4))) k_y_plain(float2* __restrict__ a0, float2* __restrict__ a1,
-                                                 const float2* __restrict__ twg) {
-  constexpr int NT = nty<N>();
-  constexpr int W = wy<N>(), LD = W + 1;
-  __shared__ float2 buf[N * LD];
+__global__ void __launch_bounds__(nty<N>()) k_y_plain(float2* __restrict__ a0, float2* __restrict__ a1,
+                                                      const float2* __restrict__ twg) {
+  constexpr int NT = nty<N>(), W = wy<N>();
+  using L = Lay<N, W, false>;
+  __shared__ float2 buf[L::SIZE];
   __shared__ float2 tw[N];
   stage_twiddles<N, NT>(tw, twg);
-  int p, x0;
+  int p, x0, c, j;
   y_tile_coords<N, W>(p, x0);
+  frag_coords<N, W, false>(c, j);
+  const bool act = threadIdx.x < L::NTF;
   const long long cn = (long long)(N / 2 + 1) * N * N;
   const int b = blockIdx.y;
 #pragma unroll
   for (int a = 0; a < NA; ++a) {
     float2* arr = (a == 0 ? a0 : a1) + b * cn;
-    y_load<N, W, NT>(buf, arr, p, x0);
-    __syncthreads();
-    tile_fft<N, W, NT, INV>(buf, tw);
-    y_store<N, W, NT>(buf, arr, p, x0);
-    __syncthreads();
+    float2 v[8];
+    if (act) y_load<N>(v, arr, p, x0, c, j);
+    fft_rr<N, W, INV, false>(v, buf, tw);
+    if (act) y_store<N>(v, arr, p, x0, c, j);
   }
 }
 
@@ -906,51 +875,39 @@ __global__ void __launch_bounds__(nty<N>()) __attribute__((amdgpu_waves_per_eu(4
 //   a1 <- Y^-1[i k'_y a1]             (y component)
 //   a2 <- i k'_z Y^-1[a1]             (z component)
 template <int N>
-__global__ void __launch_bounds__(nty<N>()) __attribute__((amdgpu_waves_per_eu(4))) k_y_fanout(float2* __restrict__ a0, float2* __restrict__ a1,
-                                                  float2* __restrict__ a2, Geo g, const int* __restrict__ active,
-                                                  const float2* __restrict__ twg) {
-  constexpr int NT = nty<N>();
-  constexpr int W = wy<N>(), LD = W + 1;
-  constexpr int EPT = (N * W + NT - 1) / NT;
+__global__ void __launch_bounds__(nty<N>()) k_y_fanout(float2* __restrict__ a0, float2* __restrict__ a1,
+                                                       float2* __restrict__ a2, Geo g, const int* __restrict__ active,
+                                                       const float2* __restrict__ twg) {
+  constexpr int NT = nty<N>(), W = wy<N>();
+  using L = Lay<N, W, false>;
   const int b = blockIdx.y;
   if (active && !active[b]) return;
-  __shared__ float2 buf[N * LD];
+  __shared__ float2 buf[L::SIZE];
   __shared__ float2 tw[N];
   stage_twiddles<N, NT>(tw, twg);
-  int p, x0;
+  int p, x0, c, j;
   y_tile_coords<N, W>(p, x0);
+  frag_coords<N, W, false>(c, j);
+  const bool act = threadIdx.x < L::NTF;
   const long long cn = (long long)(N / 2 + 1) * N * N;
   a0 += b * cn; a1 += b * cn; a2 += b * cn;
-  y_load<N, W, NT>(buf, a0, p, x0);
-  __syncthreads();
-  tile_fft<N, W, NT, true>(buf, tw);
-  y_store<N, W, NT>(buf, a0, p, x0);
-  __syncthreads();
-  float2 r[EPT];
+  float2 v[8], keep[8];
+  if (act) y_load<N>(v, a0, p, x0, c, j);
+  fft_rr<N, W, true, false>(v, buf, tw);
+  if (act) {
+    y_store<N>(v, a0, p, x0, c, j);
+    y_load<N>(keep, a1, p, x0, c, j);
 #pragma unroll
-  for (int i = 0; i < EPT; ++i) {
-    const int e = threadIdx.x + i * NT;
-    if (e < N * W) {
-      const int c = e % W, j = e / W;
-      r[i] = a1[((long long)p * N + j) * N + x0 + c];
-      buf[j * LD + c] = mul_i(r[i]) * (g.kf * deriv_mode<N>(j));
-    }
+    for (int r = 0; r < 8; ++r) v[r] = mul_i(keep[r]) * (g.kf * deriv_mode<N>(j + r * (N / 8)));
   }
-  __syncthreads();
-  tile_fft<N, W, NT, true>(buf, tw);
-  y_store<N, W, NT>(buf, a1, p, x0);
-  __syncthreads();
+  fft_rr<N, W, true, false>(v, buf, tw);
+  if (act) y_store<N>(v, a1, p, x0, c, j);
+  fft_rr<N, W, true, false>(keep, buf, tw);
+  if (act) {
+    const float kz = g.kf * deriv_mode<N>(p);     // p in [0, N/2]; N/2 is the Nyquist plane
 #pragma unroll
-  for (int i = 0; i < EPT; ++i) {
-    const int e = threadIdx.x + i * NT;
-    if (e < N * W) buf[(e / W) * LD + e % W] = r[i];
-  }
-  __syncthreads();
-  tile_fft<N, W, NT, true>(buf, tw);
-  const float kz = g.kf * deriv_mode<N>(p);     // p in [0, N/2]; N/2 is the Nyquist plane
-  for (int e = threadIdx.x; e < N * W; e += NT) {
-    const int c = e % W, j = e / W;
-    a2[((long long)p * N + j) * N + x0 + c] = mul_i(buf[j * LD + c]) * kz;
+    for (int r = 0; r < 8; ++r) keep[r] = mul_i(keep[r]) * kz;
+    y_store<N>(keep, a2, p, x0, c, j);
   }
 }
 
@@ -958,83 +915,67 @@ __global__ void __launch_bounds__(nty<N>()) __attribute__((amdgpu_waves_per_eu(4
 //   a0 <- Y[a0]                       (x component; i k'_x applied in the x pass)
 //   a1 <- i k'_y Y[a1] + Y[a2]        (y component plus the z component, already times i k'_z)
 template <int N>
-__global__ void __launch_bounds__(nty<N>()) __attribute__((amdgpu_waves_per_eu(4))) k_y_fanin(float2* __restrict__ a0, float2* __restrict__ a1,
-                                                 const float2* __restrict__ a2, Geo g,
-                                                 const int* __restrict__ active, const float2* __restrict__ twg) {
-  constexpr int NT = nty<N>();
-  constexpr int W = wy<N>(), LD = W + 1;
-  constexpr int EPT = (N * W + NT - 1) / NT;
+__global__ void __launch_bounds__(nty<N>()) k_y_fanin(float2* __restrict__ a0, float2* __restrict__ a1,
+                                                      const float2* __restrict__ a2, Geo g,
+                                                      const int* __restrict__ active, const float2* __restrict__ twg) {
+  constexpr int NT = nty<N>(), W = wy<N>();
+  using L = Lay<N, W, false>;
   const int b = blockIdx.y;
   if (active && !active[b]) return;
-  __shared__ float2 buf[N * LD];
+  __shared__ float2 buf[L::SIZE];
   __shared__ float2 tw[N];
   stage_twiddles<N, NT>(tw, twg);
-  int p, x0;
+  int p, x0, c, j;
   y_tile_coords<N, W>(p, x0);
+  frag_coords<N, W, false>(c, j);
+  const bool act = threadIdx.x < L::NTF;
   const long long cn = (long long)(N / 2 + 1) * N * N;
   a0 += b * cn; a1 += b * cn; a2 += b * cn;
-  y_load<N, W, NT>(buf, a0, p, x0);
-  __syncthreads();
-  tile_fft<N, W, NT, false>(buf, tw);
-  y_store<N, W, NT>(buf, a0, p, x0);
-  __syncthreads();
-  y_load<N, W, NT>(buf, a1, p, x0);
-  __syncthreads();
-  tile_fft<N, W, NT, false>(buf, tw);
-  float2 r[EPT];
-#pragma unroll
-  for (int i = 0; i < EPT; ++i) {
-    const int e = threadIdx.x + i * NT;
-    if (e < N * W) {
-      const int c = e % W, j = e / W;
-      r[i] = mul_i(buf[j * LD + c]) * (g.kf * deriv_mode<N>(j));
-    }
+  float2 v[8], keep[8];
+  if (act) y_load<N>(v, a0, p, x0, c, j);
+  fft_rr<N, W, false, false>(v, buf, tw);
+  if (act) {
+    y_store<N>(v, a0, p, x0, c, j);
+    y_load<N>(keep, a1, p, x0, c, j);
   }
-  __syncthreads();
-  y_load<N, W, NT>(buf, a2, p, x0);
-  __syncthreads();
-  tile_fft<N, W, NT, false>(buf, tw);
+  fft_rr<N, W, false, false>(keep, buf, tw);
+  if (act) {
 #pragma unroll
-  for (int i = 0; i < EPT; ++i) {
-    const int e = threadIdx.x + i * NT;
-    if (e < N * W) {
-      const int c = e % W, j = e / W;
-      a1[((long long)p * N + j) * N + x0 + c] = r[i] + buf[j * LD + c];
-    }
+    for (int r = 0; r < 8; ++r) keep[r] = mul_i(keep[r]) * (g.kf * deriv_mode<N>(j + r * (N / 8)));
+    y_load<N>(v, a2, p, x0, c, j);
+  }
+  fft_rr<N, W, false, false>(v, buf, tw);
+  if (act) {
+#pragma unroll
+    for (int r = 0; r < 8; ++r) v[r] = v[r] + keep[r];
+    y_store<N>(v, a1, p, x0, c, j);
   }
 }
 
 // ---------------------------------------------------------------------------
-// x passes.  Tile: W consecutive rows (row = kz * N + ky), all N x.
-// Element ownership e -> (j = e % N, c = e / N): contiguous global rows.
+// x passes.  Tile: W consecutive rows (row = kz * N + ky), all N x; row-fast fragments.
 // ---------------------------------------------------------------------------
-template <int N, int W, int NT>
-__device__ __forceinline__ void x_load(float2* buf, const float2* __restrict__ a, long long r0) {
-  constexpr int LD = W + 1;
-  for (int e = threadIdx.x; e < N * W; e += NT) {
-    const int j = e % N, c = e / N;
-    buf[j * LD + c] = a[(r0 + c) * N + j];
-  }
-}
-
-template <int N, int W, int NT>
-__device__ __forceinline__ void x_store(const float2* buf, float2* __restrict__ a, long long r0) {
-  constexpr int LD = W + 1;
-  for (int e = threadIdx.x; e < N * W; e += NT) {
-    const int j = e % N, c = e / N;
-    a[(r0 + c) * N + j] = buf[j * LD + c];
-  }
-}
-
-// k^2 and the derivative components of element (row, j) of an x tile.
 template <int N>
-__device__ __forceinline__ void x_wavenumbers(long long row, int j, float kf, float& k2, float& dx, float& dy,
+__device__ __forceinline__ void x_load(float2* v, const float2* __restrict__ a, long long row, int j) {
+#pragma unroll
+  for (int r = 0; r < 8; ++r) v[r] = a[row * N + j + r * (N / 8)];
+}
+
+template <int N>
+__device__ __forceinline__ void x_store(const float2* v, float2* __restrict__ a, long long row, int j) {
+#pragma unroll
+  for (int r = 0; r < 8; ++r) a[row * N + j + r * (N / 8)] = v[r];
+}
+
+// k^2 and the derivative components of element (row, kx).
+template <int N>
+__device__ __forceinline__ void x_wavenumbers(long long row, int kx, float kf, float& k2, float& dx, float& dy,
                                               float& dz, int& kzi) {
   const int ky = (int)(row % N);
   kzi = (int)(row / N);
-  const float mx = signed_mode<N>(j), my = signed_mode<N>(ky), mz = (float)kzi;
+  const float mx = signed_mode<N>(kx), my = signed_mode<N>(ky), mz = (float)kzi;
   k2 = kf * kf * (mx * mx + my * my + mz * mz);
-  dx = kf * deriv_mode<N>(j);
+  dx = kf * deriv_mode<N>(kx);
   dy = kf * deriv_mode<N>(ky);
   dz = kzi == N / 2 ? 0.f : kf * mz;
 }
@@ -1042,32 +983,35 @@ __device__ __forceinline__ void x_wavenumbers(long long row, int j, float kf, fl
 // Forward x, Gaussian smoothing S(k) = exp(-k^2 R^2 / 2) with the 1/N^3 of the inverse, inverse x.
 template <int N, int NA>
 __global__ void __launch_bounds__(ntx<N>()) k_x_smooth(float2* __restrict__ a0, float2* __restrict__ a1, Geo g,
-                                                  const float2* __restrict__ twg) {
-  constexpr int NT = ntx<N>();
-  constexpr int W = wx<N>(), LD = W + 1;
-  __shared__ float2 buf[N * LD];
+                                                       const float2* __restrict__ twg) {
+  constexpr int NT = ntx<N>(), W = wx<N>();
+  using L = Lay<N, W, true>;
+  __shared__ float2 buf[L::SIZE];
   __shared__ float2 tw[N];
   stage_twiddles<N, NT>(tw, twg);
+  int c, j;
+  frag_coords<N, W, true>(c, j);
+  const bool act = threadIdx.x < L::NTF;
   const long long cn = (long long)(N / 2 + 1) * N * N;
-  const long long r0 = (long long)blockIdx.x * W;
+  const long long row = (long long)blockIdx.x * W + c;
   const int b = blockIdx.y;
 #pragma unroll
   for (int a = 0; a < NA; ++a) {
     float2* arr = (a == 0 ? a0 : a1) + b * cn;
-    x_load<N, W, NT>(buf, arr, r0);
-    __syncthreads();
-    tile_fft<N, W, NT, false>(buf, tw);
-    for (int e = threadIdx.x; e < N * W; e += NT) {
-      const int j = e % N, c = e / N;
-      float k2, dx, dy, dz;
-      int kzi;
-      x_wavenumbers<N>(r0 + c, j, g.kf, k2, dx, dy, dz, kzi);
-      buf[j * LD + c] = buf[j * LD + c] * (expf(-k2 * g.smooth_c) * g.inv_n3);
+    float2 v[8];
+    if (act) x_load<N>(v, arr, row, j);
+    fft_rr<N, W, false, true>(v, buf, tw);
+    if (act) {
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        float k2, dx, dy, dz;
+        int kzi;
+        x_wavenumbers<N>(row, j + r * (N / 8), g.kf, k2, dx, dy, dz, kzi);
+        v[r] = v[r] * (expf(-k2 * g.smooth_c) * g.inv_n3);
+      }
     }
-    __syncthreads();
-    tile_fft<N, W, NT, true>(buf, tw);
-    x_store<N, W, NT>(buf, arr, r0);
-    __syncthreads();
+    fft_rr<N, W, true, true>(v, buf, tw);
+    if (act) x_store<N>(v, arr, row, j);
   }
 }
 
@@ -1075,49 +1019,37 @@ __global__ void __launch_bounds__(ntx<N>()) k_x_smooth(float2* __restrict__ a0, 
 // a0 <- X^-1[i k'_x P], a1 <- X^-1[P].
 template <int N>
 __global__ void __launch_bounds__(ntx<N>()) k_x_start(float2* __restrict__ a0, float2* __restrict__ a1,
-                                                 float2* __restrict__ ds, Geo g, const float2* __restrict__ twg) {
-  constexpr int NT = ntx<N>();
-  constexpr int W = wx<N>(), LD = W + 1;
-  constexpr int EPT = (N * W + NT - 1) / NT;
-  __shared__ float2 buf[N * LD];
+                                                      float2* __restrict__ ds, Geo g, const float2* __restrict__ twg) {
+  constexpr int NT = ntx<N>(), W = wx<N>();
+  using L = Lay<N, W, true>;
+  __shared__ float2 buf[L::SIZE];
   __shared__ float2 tw[N];
   stage_twiddles<N, NT>(tw, twg);
+  int c, j;
+  frag_coords<N, W, true>(c, j);
+  const bool act = threadIdx.x < L::NTF;
   const long long cn = (long long)(N / 2 + 1) * N * N;
-  const long long r0 = (long long)blockIdx.x * W;
+  const long long row = (long long)blockIdx.x * W + c;
   const int b = blockIdx.y;
   a0 += b * cn; a1 += b * cn; ds += b * cn;
-  x_load<N, W, NT>(buf, a0, r0);
-  __syncthreads();
-  tile_fft<N, W, NT, false>(buf, tw);
-  float2 pr[EPT];
-  float kxd[EPT];
+  float2 v[8], pr[8];
+  if (act) x_load<N>(v, a0, row, j);
+  fft_rr<N, W, false, true>(v, buf, tw);
+  if (act) {
+    x_store<N>(v, ds, row, j);
 #pragma unroll
-  for (int i = 0; i < EPT; ++i) {
-    const int e = threadIdx.x + i * NT;
-    if (e < N * W) {
-      const int j = e % N, c = e / N;
-      const float2 d = buf[j * LD + c];
-      ds[(r0 + c) * N + j] = d;
+    for (int r = 0; r < 8; ++r) {
       float k2, dx, dy, dz;
       int kzi;
-      x_wavenumbers<N>(r0 + c, j, g.kf, k2, dx, dy, dz, kzi);
-      pr[i] = k2 > 0.f ? d * (g.inv_bn3 / k2) : make_float2(0.f, 0.f);
-      kxd[i] = dx;
-      buf[j * LD + c] = mul_i(pr[i]) * dx;
+      x_wavenumbers<N>(row, j + r * (N / 8), g.kf, k2, dx, dy, dz, kzi);
+      pr[r] = k2 > 0.f ? v[r] * (g.inv_bn3 / k2) : make_float2(0.f, 0.f);
+      v[r] = mul_i(pr[r]) * dx;
     }
   }
-  __syncthreads();
-  tile_fft<N, W, NT, true>(buf, tw);
-  x_store<N, W, NT>(buf, a0, r0);
-  __syncthreads();
-#pragma unroll
-  for (int i = 0; i < EPT; ++i) {
-    const int e = threadIdx.x + i * NT;
-    if (e < N * W) buf[(e % N) * LD + e / N] = pr[i];
-  }
-  __syncthreads();
-  tile_fft<N, W, NT, true>(buf, tw);
-  x_store<N, W, NT>(buf, a1, r0);
+  fft_rr<N, W, true, true>(v, buf, tw);
+  if (act) x_store<N>(v, a0, row, j);
+  fft_rr<N, W, true, true>(pr, buf, tw);
+  if (act) x_store<N>(pr, a1, row, j);
 }
 
 // One iteration's k-space step:
@@ -1128,44 +1060,37 @@ __global__ void __launch_bounds__(ntx<N>()) k_x_start(float2* __restrict__ a0, f
 // dprev and dnext may be the same buffer (element-wise in place).
 template <int N>
 __global__ void __launch_bounds__(ntx<N>()) k_x_iter(float2* __restrict__ a0, float2* __restrict__ a1,
-                                                const float2* __restrict__ ds, const float2* dprev,
-                                                float2* dnext, Geo g, double* __restrict__ partials,
-                                                const int* __restrict__ active, const float2* __restrict__ twg) {
-  constexpr int NT = ntx<N>();
-  constexpr int W = wx<N>(), LD = W + 1;
-  constexpr int EPT = (N * W + NT - 1) / NT;
+                                                     const float2* __restrict__ ds, const float2* dprev,
+                                                     float2* dnext, Geo g, double* __restrict__ partials,
+                                                     const int* __restrict__ active, const float2* __restrict__ twg) {
+  constexpr int NT = ntx<N>(), W = wx<N>();
+  using L = Lay<N, W, true>;
   const int b = blockIdx.y;
   if (active && !active[b]) return;
-  __shared__ float2 buf[N * LD];
+  __shared__ float2 buf[L::SIZE];
   __shared__ float2 tw[N];
   stage_twiddles<N, NT>(tw, twg);
+  int c, j;
+  frag_coords<N, W, true>(c, j);
+  const bool act = threadIdx.x < L::NTF;
   const long long cn = (long long)(N / 2 + 1) * N * N;
-  const long long r0 = (long long)blockIdx.x * W;
+  const long long row = (long long)blockIdx.x * W + c;
   a0 += b * cn; a1 += b * cn; ds += b * cn; dprev += b * cn; dnext += b * cn;
-  x_load<N, W, NT>(buf, a0, r0);
-  __syncthreads();
-  tile_fft<N, W, NT, false>(buf, tw);
-  float2 r[EPT];
-#pragma unroll
-  for (int i = 0; i < EPT; ++i) {
-    const int e = threadIdx.x + i * NT;
-    if (e < N * W) r[i] = buf[(e % N) * LD + e / N];
-  }
-  __syncthreads();
-  x_load<N, W, NT>(buf, a1, r0);
-  __syncthreads();
-  tile_fft<N, W, NT, false>(buf, tw);
+  float2 xa[8], v[8];
+  if (act) x_load<N>(xa, a0, row, j);
+  fft_rr<N, W, false, true>(xa, buf, tw);
+  if (act) x_load<N>(v, a1, row, j);
+  fft_rr<N, W, false, true>(v, buf, tw);
   double num = 0.0, den = 0.0;
+  if (act) {
 #pragma unroll
-  for (int i = 0; i < EPT; ++i) {
-    const int e = threadIdx.x + i * NT;
-    if (e < N * W) {
-      const int j = e % N, c = e / N;
+    for (int r = 0; r < 8; ++r) {
+      const int kx = j + r * (N / 8);
       float k2, dx, dy, dz;
       int kzi;
-      x_wavenumbers<N>(r0 + c, j, g.kf, k2, dx, dy, dz, kzi);
-      const float2 div = mul_i(r[i]) * dx + buf[j * LD + c];
-      const long long idx = (r0 + c) * N + j;
+      x_wavenumbers<N>(row, kx, g.kf, k2, dx, dy, dz, kzi);
+      const float2 div = mul_i(xa[r]) * dx + v[r];
+      const long long idx = row * N + kx;
       const float2 dsv = ds[idx];
       const float2 dn = make_float2(fmaf(g.growth, div.x, dsv.x), fmaf(g.growth, div.y, dsv.y));
       const float2 dp = dprev[idx];
@@ -1177,13 +1102,13 @@ __global__ void __launch_bounds__(ntx<N>()) k_x_iter(float2* __restrict__ a0, fl
         const float ex = dn.x - dp.x, ey = dn.y - dp.y;
         num += (double)(f * (ex * ex + ey * ey));
         den += (double)(f * (dn.x * dn.x + dn.y * dn.y));
-        r[i] = dn * (g.inv_bn3 / k2);
+        v[r] = dn * (g.inv_bn3 / k2);
       } else {
-        r[i] = make_float2(0.f, 0.f);
+        v[r] = make_float2(0.f, 0.f);
       }
+      xa[r] = mul_i(v[r]) * dx;
     }
   }
-  __syncthreads();
   {
     double t1, t2;
     block_sum2<NT>(num, den, &t1, &t2);
@@ -1192,26 +1117,10 @@ __global__ void __launch_bounds__(ntx<N>()) k_x_iter(float2* __restrict__ a0, fl
       partials[2 * ((long long)b * gridDim.x + blockIdx.x) + 1] = t2;
     }
   }
-#pragma unroll
-  for (int i = 0; i < EPT; ++i) {
-    const int e = threadIdx.x + i * NT;
-    if (e < N * W) {
-      const int j = e % N;
-      buf[j * LD + e / N] = mul_i(r[i]) * (g.kf * deriv_mode<N>(j));
-    }
-  }
-  __syncthreads();
-  tile_fft<N, W, NT, true>(buf, tw);
-  x_store<N, W, NT>(buf, a0, r0);
-  __syncthreads();
-#pragma unroll
-  for (int i = 0; i < EPT; ++i) {
-    const int e = threadIdx.x + i * NT;
-    if (e < N * W) buf[(e % N) * LD + e / N] = r[i];
-  }
-  __syncthreads();
-  tile_fft<N, W, NT, true>(buf, tw);
-  x_store<N, W, NT>(buf, a1, r0);
+  fft_rr<N, W, true, true>(xa, buf, tw);
+  if (act) x_store<N>(xa, a0, row, j);
+  fft_rr<N, W, true, true>(v, buf, tw);
+  if (act) x_store<N>(v, a1, row, j);
 }
 
 // Fixed-order reduction of per-block partial pairs: out[b] = sum over blocks.

@@ -162,7 +162,7 @@ def test_plane_wave_displacement_gpu(gpu_lib, n):
 
 @pytest.mark.parametrize("n,observer", [(8, (31.3, 47.9, 52.1)), (16, (-80.0, 130.0, 60.0)),
                                         (32, (150.0, 150.0, 150.0)), (64, (-300.0, 100.0, 250.0)),
-                                        (128, (200.0, 200.0, 200.0))])
+                                        (128, (200.0, 200.0, 200.0)), (256, (-50.0, 210.0, 190.0))])
 def test_random_field_iterates_match_oracle(gpu_lib, n, observer):
     from paper_1504_02591_amd import native
     box, b, f = 400.0, 1.5, 0.6
@@ -182,6 +182,26 @@ def test_random_field_iterates_match_oracle(gpu_lib, n, observer):
         assert iters[0] == npass
         assert e < PSI_TOL
         np.testing.assert_allclose(eps[0], ref["eps"], rtol=1e-4, atol=1e-6)
+
+
+def test_full_size_pass_matches_oracle(gpu_lib):
+    """512^3, the benchmarked launch configuration: two passes from a survey-like field vs the oracle."""
+    from paper_1504_02591_amd import native
+    n, box, b, f = 512, 3500.0, 2.0, 0.74
+    obs = (1750.0, 1750.0, 1750.0)
+    delta, _ = G.linear_field(n, box, 77, want_psi=False, dtype=np.float32)
+    delta = delta.astype(np.float32)
+    plan = native.Plan(n, box, obs, b, f, 15.0, randoms=False)
+    plan.set_delta(to_dev(delta))
+    plan.solve()
+    rc, iters, eps = plan.iterate(2, 0.0)
+    psi = plan.psi()[0].cpu().numpy()
+    plan.close()
+    ref = O.reconstruct_field(delta.astype(np.float64), box, (0, 0, 0), obs, b, f, n_passes=2)
+    e = rel_l2(psi, ref["psi"])
+    print(f"512^3 two passes: psi relL2={e:.2e} eps gpu={eps[0]} oracle={ref['eps']}", flush=True)
+    assert e < PSI_TOL
+    np.testing.assert_allclose(eps[0], ref["eps"], rtol=1e-4, atol=1e-6)
 
 
 @pytest.mark.parametrize("axis", [0, 2])
