@@ -49,6 +49,34 @@ def algorithmic_bytes(n, n_gal, n_ran, randoms=True, keep_delta=False):
 
 
 COPY_BYTES = 1 << 30
+PROFILE = os.path.join(ROOT, "profiles", "survey512_kernels.md")
+
+
+def kernel_source_hash():
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_1504_02591_amd", "csrc", "*"))):
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or None when the
+    kernel sources changed after the counters were taken."""
+    try:
+        text = open(PROFILE).read()
+    except OSError:
+        return None
+    block = text.split("```\nsource ")[-1].split("```")[0].split("\n")
+    if block[0].strip() != kernel_source_hash():
+        return None
+    for line in block[1:]:
+        parts = line.split()
+        if len(parts) == 3 and parts[0] == "traffic" and parts[1] == "k_" + kernel:
+            return int(parts[2])
+    return None
 
 
 def measure_copy_bandwidth(torch, dev, reps=10):
@@ -178,7 +206,8 @@ def main():
         avg_s = stages[dom]["avg_launch_ms"] * 1e-3
         ach = ab[dom] / avg_s / 1e9
         roofline = {"kernel": dom, "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                    "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+                    "traffic": measured_traffic(dom) if args.n == 512 else None,
                     "algorithmic_bytes_per_launch": ab[dom], "avg_launch_ms": round(avg_s * 1e3, 4)}
 
     cpu = None
