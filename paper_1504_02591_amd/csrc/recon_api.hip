@@ -30,7 +30,7 @@ enum PlanState { ST_EMPTY = 0, ST_PAINTED = 1, ST_DELTA = 2, ST_SOLVED = 3 };
 struct Layout {
   size_t grid_g = 0, grid_r = 0, mask = 0, w0 = 0, w1 = 0, w2 = 0, ds = 0, dn = 0, psi = 0, delta = 0,
          corr = 0, tw = 0, partials = 0, red = 0, totals = 0, thr = 0, dscal = 0, act = 0, err = 0, total = 0,
-         sorted = 0, bcount = 0, bstart = 0, bcursor = 0, bsum = 0;
+         sorted = 0, bcount = 0, bstart = 0, bcursor = 0, bsum = 0, status = 0, tpart = 0;
   long long nbins = 0, nscan = 0;
 };
 
@@ -81,6 +81,8 @@ Layout make_layout(const recon_params_t* p) {
   L.red = take(b * 2 * 8 * 2);
   L.totals = take(b * 3 * 8);
   L.thr = take(b * 8);
+  L.status = take(b * 4);
+  L.tpart = take((size_t)b * max_partial_blocks((int)n) * 3 * 8);
   L.dscal = take(b * sizeof(DeltaScal));
   L.act = take(b * 4 * 4);
   L.err = take(16);
@@ -132,7 +134,9 @@ struct recon_plan_s {
   float *delta = nullptr, *corr = nullptr;
   double *partials = nullptr, *red = nullptr;
   unsigned long long* totals = nullptr;
+  unsigned long long* tpart = nullptr;
   long long* thr = nullptr;
+  int* status = nullptr;
   DeltaScal* dscal = nullptr;
   int *act_fan = nullptr, *act_fin = nullptr, *act_it = nullptr, *err = nullptr;
   float4* sorted = nullptr;
@@ -218,6 +222,23 @@ struct Ops {
   int nb_x, nb_z;
 };
 
+// Device-side alpha / rho_bar / mask threshold from the totals, then the survey mask.
+int scalars_and_mask(recon_plan_t* pl, int nblk_z) {
+  k_scalars<<<pl->batch, 256, 0, pl->stream>>>(pl->tpart, nblk_z, pl->n3, pl->p.mask_tau, pl->randoms ? 1 : 0,
+                                               pl->totals, pl->dscal, pl->thr, pl->status);
+  RECON_TRY(check_launch(pl, "scalars"));
+  if (pl->randoms) {
+    const int nseg = (pl->n + 61) / 62;
+    const unsigned blocks = (unsigned)(nseg * ((pl->n + 3) / 4));
+    {
+      PROF(pl, KP_MASK);
+      k_mask_win<<<dim3(blocks, pl->batch), 256, 0, pl->stream>>>(pl->grid_r, pl->n, pl->thr, pl->mask);
+    }
+    RECON_TRY(check_launch(pl, "mask"));
+  }
+  return RECON_OK;
+}
+
 template <int N>
 struct SizeOps {
   static constexpr int WZ = wz<N>(), WY = wy<N>(), WX = wx<N>();
@@ -231,7 +252,7 @@ struct SizeOps {
     if (pl->randoms) {
       {
         PROF(pl, KP_Z_FWD_GRID);
-        k_z_fwd_grid<N, 2><<<gz(pl), dim3(TZ), 0, s>>>(pl->grid_g, pl->grid_r, pl->w0, pl->w1, pl->tw);
+        k_z_fwd_grid<N, 2><<<gz(pl), dim3(TZ), 0, s>>>(pl->grid_g, pl->grid_r, pl->w0, pl->w1, pl->tpart, pl->tw);
       }
       RECON_TRY(check_launch(pl, "z forward (grids)"));
       {
@@ -249,6 +270,7 @@ struct SizeOps {
         k_y_plain<N, 2, true><<<gy(pl), dim3(TY), 0, s>>>(pl->w0, pl->w1, pl->tw);
       }
       RECON_TRY(check_launch(pl, "y inverse"));
+      RECON_TRY(scalars_and_mask(pl, (int)gz(pl).x));
       {
         PROF(pl, KP_Z_DELTA);
         k_z_delta<N, 2><<<gz(pl), dim3(TZ), 0, s>>>(pl->w0, pl->w1, pl->mask, pl->dscal, pl->delta, pl->tw);
@@ -257,7 +279,7 @@ struct SizeOps {
     } else {
       {
         PROF(pl, KP_Z_FWD_GRID);
-        k_z_fwd_grid<N, 1><<<gz(pl), dim3(TZ), 0, s>>>(pl->grid_g, nullptr, pl->w0, nullptr, pl->tw);
+        k_z_fwd_grid<N, 1><<<gz(pl), dim3(TZ), 0, s>>>(pl->grid_g, nullptr, pl->w0, nullptr, pl->tpart, pl->tw);
       }
       RECON_TRY(check_launch(pl, "z forward (grid)"));
       {
@@ -275,6 +297,7 @@ struct SizeOps {
         k_y_plain<N, 1, true><<<gy(pl), dim3(TY), 0, s>>>(pl->w0, nullptr, pl->tw);
       }
       RECON_TRY(check_launch(pl, "y inverse"));
+      RECON_TRY(scalars_and_mask(pl, (int)gz(pl).x));
       {
         PROF(pl, KP_Z_DELTA);
         k_z_delta<N, 1><<<gz(pl), dim3(TZ), 0, s>>>(pl->w0, nullptr, nullptr, pl->dscal, pl->delta, pl->tw);
@@ -485,6 +508,8 @@ int recon_plan(recon_plan_t** out, const recon_params_t* params, void* workspace
   pl->red = (double*)(w + L.red);
   pl->totals = (unsigned long long*)(w + L.totals);
   pl->thr = (long long*)(w + L.thr);
+  pl->status = (int*)(w + L.status);
+  pl->tpart = (unsigned long long*)(w + L.tpart);
   pl->dscal = (DeltaScal*)(w + L.dscal);
   pl->act_fan = (int*)(w + L.act);
   pl->act_fin = pl->act_fan + pl->batch;
@@ -657,48 +682,20 @@ int recon_solve(recon_plan_t* pl, int start, const void* net) {
   if (pl->state == ST_PAINTED) {
     if (!pl->painted_g) return fail(pl, RECON_ESTATE, "galaxies were not painted");
     if (pl->randoms && !pl->painted_r) return fail(pl, RECON_ESTATE, "randoms were not painted");
-    RECON_TRY(launch_fill_u64(pl, pl->totals, 3LL * pl->batch));
-    {
-      long long blocks = (pl->n3 + kThreads - 1) / kThreads;
-      if (blocks > 2048) blocks = 2048;
-      PROF(pl, KP_TOTALS);
-      k_totals<<<dim3((unsigned)blocks, pl->batch), kThreads, 0, pl->stream>>>(pl->grid_g, pl->grid_r, pl->n3,
-                                                                               pl->totals);
-      RECON_TRY(check_launch(pl, "totals"));
-    }
-    std::vector<unsigned long long> tot(3 * pl->batch);
+    RECON_TRY(ops->setup(pl));
+    // one read-back: invalid-object counters and the totals status of every realisation
+    std::vector<int> st(pl->batch, 0);
     int errs[2] = {0, 0};
-    HIP_TRY(pl, hipMemcpyAsync(tot.data(), pl->totals, 8 * tot.size(), hipMemcpyDeviceToHost, pl->stream));
     HIP_TRY(pl, hipMemcpyAsync(errs, pl->err, 2 * sizeof(int), hipMemcpyDeviceToHost, pl->stream));
+    HIP_TRY(pl, hipMemcpyAsync(st.data(), pl->status, sizeof(int) * pl->batch, hipMemcpyDeviceToHost, pl->stream));
     HIP_TRY(pl, hipStreamSynchronize(pl->stream));
     const int errcount = errs[0] + (pl->randoms ? errs[1] : 0);
     if (errcount) return fail(pl, RECON_EINVAL, std::to_string(errcount) + " objects had invalid positions or weights");
-    std::vector<DeltaScal> sc(pl->batch);
-    std::vector<long long> thr(pl->batch, 0);
     for (int b = 0; b < pl->batch; ++b) {
-      const long long wg = (long long)tot[3 * b], wr = (long long)tot[3 * b + 1], occ = (long long)tot[3 * b + 2];
-      if (wg <= 0) return fail(pl, RECON_EINVAL, "total galaxy weight is zero");
-      sc[b].inv_rhobar = (float)((double)pl->n3 / ((double)wg * 2.3283064365386963e-10));
-      sc[b].alpha = 0.f;
-      if (pl->randoms) {
-        if (wr <= 0 || occ <= 0) return fail(pl, RECON_EINVAL, "total random weight is zero");
-        sc[b].alpha = (float)((double)wg / (double)wr);
-        thr[b] = (long long)std::floor(pl->p.mask_tau * 27.0 * (double)wr / (double)occ);
-      }
+      if (st[b] & 1) return fail(pl, RECON_EINVAL, "total galaxy weight is zero");
+      if (st[b] & 2) return fail(pl, RECON_EINVAL, "total random weight is zero");
     }
-    HIP_TRY(pl, hipMemcpyAsync(pl->dscal, sc.data(), sizeof(DeltaScal) * pl->batch, hipMemcpyHostToDevice, pl->stream));
-    if (pl->randoms) {
-      HIP_TRY(pl, hipMemcpyAsync(pl->thr, thr.data(), 8 * pl->batch, hipMemcpyHostToDevice, pl->stream));
-      long long blocks = (pl->n3 + kThreads - 1) / kThreads;
-      if (blocks > 65536) blocks = 65536;
-      {
-        PROF(pl, KP_MASK);
-        k_mask<<<dim3((unsigned)blocks, pl->batch), kThreads, 0, pl->stream>>>(pl->grid_r, pl->n, pl->thr, pl->mask);
-      }
-      RECON_TRY(check_launch(pl, "mask"));
-    }
-    RECON_TRY(ops->setup(pl));
-    HIP_TRY(pl, hipStreamSynchronize(pl->stream));
+
   } else if (pl->state != ST_DELTA && pl->state != ST_SOLVED) {
     return fail(pl, RECON_ESTATE, "paint or set_delta must precede solve");
   } else if (pl->state == ST_SOLVED) {

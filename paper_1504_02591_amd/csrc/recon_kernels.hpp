@@ -411,59 +411,94 @@ __global__ void __launch_bounds__(256) k_brick_deposit(const float4* __restrict_
   }
 }
 
-// Exact totals per realisation: out[b] = {sum I_g, sum I_r, #cells with I_r != 0}.
-__global__ void __launch_bounds__(256) k_totals(const long long* __restrict__ gg, const long long* __restrict__ gr,
-                                                long long n3, unsigned long long* __restrict__ out) {
+// Binary survey mask with a sliding window: each wave owns one y row and 64 consecutive x
+// (62 outputs plus one halo lane each side); per z it sums the three y rows, adds the two
+// x neighbours through lane shuffles, and keeps a running three-plane window along z.
+// Sums are exact int64; a cell is inside when the 27-cell sum exceeds thr[b].
+__global__ void __launch_bounds__(256) k_mask_win(const long long* __restrict__ gr, int n,
+                                                  const long long* __restrict__ thr,
+                                                  unsigned char* __restrict__ mask) {
   const int b = blockIdx.y;
-  gg += (long long)b * n3;
-  if (gr) gr += (long long)b * n3;
-  unsigned long long sg = 0, sr = 0, occ = 0;
-  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n3;
-       i += (long long)gridDim.x * blockDim.x) {
-    sg += (unsigned long long)gg[i];
-    if (gr) {
-      long long v = gr[i];
-      sr += (unsigned long long)v;
-      occ += (v != 0);
-    }
-  }
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    sg += __shfl_xor(sg, o, 64);
-    sr += __shfl_xor(sr, o, 64);
-    occ += __shfl_xor(occ, o, 64);
-  }
-  if ((threadIdx.x & 63) == 0) {
-    atomicAdd(out + 3 * b + 0, sg);
-    if (gr) {
-      atomicAdd(out + 3 * b + 1, sr);
-      atomicAdd(out + 3 * b + 2, occ);
-    }
+  const int nseg = (n + 61) / 62;
+  const int seg = blockIdx.x % nseg;
+  const int y = (blockIdx.x / nseg) * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (y >= n) return;                                   // whole wave leaves together
+  const long long n2 = (long long)n * n;
+  const long long* g = gr + (long long)b * n2 * n;
+  unsigned char* m = mask + (long long)b * n2 * n;
+  const long long t = thr[b];
+  const int xs = seg * 62 + lane - 1;                   // may be -1 or >= n: wrapped below
+  const int x = xs & (n - 1);
+  const long long ym = (long long)((y - 1) & (n - 1)) * n, y0 = (long long)y * n,
+                  yp = (long long)((y + 1) & (n - 1)) * n;
+  const bool out = lane >= 1 && lane <= 62 && xs < n;
+  auto plane = [&](int z) -> long long {
+    const long long* gz = g + (long long)z * n2 + x;
+    const long long r = gz[ym] + gz[y0] + gz[yp];
+    const long long l = __shfl(r, (lane + 63) & 63, 64);
+    const long long h = __shfl(r, (lane + 1) & 63, 64);
+    return l + r + h;
+  };
+  const long long first = plane(0);
+  long long prev = plane(n - 1), cur = first;
+  for (int z = 0; z < n; ++z) {
+    const long long next = z + 1 < n ? plane(z + 1) : first;
+    if (out) m[(long long)z * n2 + y0 + xs] = (prev + cur + next) > t ? 1 : 0;
+    prev = cur;
+    cur = next;
   }
 }
 
-// Binary survey mask: the cell is inside when the exact 3x3x3 periodic sum of the
-// random grid exceeds thr[b].
-__global__ void __launch_bounds__(256) k_mask(const long long* __restrict__ gr, int n,
-                                              const long long* __restrict__ thr, unsigned char* __restrict__ mask) {
-  const int b = blockIdx.y;
-  const long long n3 = (long long)n * n * n;
-  gr += (long long)b * n3;
-  mask += (long long)b * n3;
-  const long long t = thr[b];
-  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n3;
-       i += (long long)gridDim.x * blockDim.x) {
-    const int x = (int)(i % n), y = (int)((i / n) % n), z = (int)(i / ((long long)n * n));
-    long long s = 0;
-    for (int dz = -1; dz <= 1; ++dz) {
-      const long long zz = (z + dz) & (n - 1);
-      for (int dy = -1; dy <= 1; ++dy) {
-        const long long row = (zz * n + ((y + dy) & (n - 1))) * n;
+// Per-realisation scalars from the exact totals {W_g, W_r, n_occ}:
+//   alpha = W_g / W_r, 1/rho_bar = N^3 / (W_g 2^-32), mask threshold floor(tau 27 W_r / n_occ);
+// status[b] bit 0: galaxy total is zero, bit 1: random total is zero.
+// One block per realisation: sums the per-tile integer partials (exact, any order), then derives
+// the scalars; tot[b] keeps the totals.
+__global__ void __launch_bounds__(256) k_scalars(const unsigned long long* __restrict__ tpart, int nblk, long long n3,
+                                                 double tau, int randoms, unsigned long long* __restrict__ tot,
+                                                 DeltaScal* __restrict__ sc, long long* __restrict__ thr,
+                                                 int* __restrict__ status) {
+  const int b = blockIdx.x;
+  unsigned long long acc[3] = {0ull, 0ull, 0ull};
+  for (int i = threadIdx.x; i < nblk; i += 256) {
 #pragma unroll
-        for (int dx = -1; dx <= 1; ++dx) s += gr[row + ((x + dx) & (n - 1))];
+    for (int k = 0; k < 3; ++k) acc[k] += tpart[3 * ((long long)b * nblk + i) + k];
+  }
+  __shared__ unsigned long long red[3][4];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) acc[k] += __shfl_xor(acc[k], o, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) red[k][threadIdx.x >> 6] = acc[k];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const long long wg = (long long)(red[0][0] + red[0][1] + red[0][2] + red[0][3]);
+    const long long wr = (long long)(red[1][0] + red[1][1] + red[1][2] + red[1][3]);
+    const long long occ = (long long)(red[2][0] + red[2][1] + red[2][2] + red[2][3]);
+    tot[3 * b] = (unsigned long long)wg;
+    tot[3 * b + 1] = (unsigned long long)wr;
+    tot[3 * b + 2] = (unsigned long long)occ;
+    int st = 0;
+    DeltaScal d;
+    d.inv_rhobar = wg > 0 ? (float)((double)n3 / ((double)wg * 2.3283064365386963e-10)) : 0.f;
+    d.alpha = 0.f;
+    long long th = 0;
+    if (wg <= 0) st |= 1;
+    if (randoms) {
+      if (wr <= 0 || occ <= 0) st |= 2;
+      else {
+        d.alpha = (float)((double)wg / (double)wr);
+        th = (long long)floor(tau * 27.0 * (double)wr / (double)occ);
       }
     }
-    mask[i] = s > t ? 1 : 0;
+    sc[b] = d;
+    thr[b] = th;
+    status[b] = st;
   }
 }
 
@@ -526,10 +561,12 @@ template <int N> constexpr int nty() { return frag_threads<N, wy<N>()>(); }
 template <int N> constexpr int ntx() { return frag_threads<N, wx<N>()>(); }
 
 // Forward z transform of int64 grids (units 2^-32) into half spectra.
+// Also writes the exact totals {sum g0, sum g1, #(g1 != 0)} of the tile to tpart[b][block].
 template <int N, int NA>
 __global__ void __launch_bounds__(ntz<N>()) k_z_fwd_grid(const long long* __restrict__ g0,
                                                          const long long* __restrict__ g1, float2* __restrict__ o0,
-                                                         float2* __restrict__ o1, const float2* __restrict__ twg) {
+                                                         float2* __restrict__ o1, unsigned long long* __restrict__ tpart,
+                                                         const float2* __restrict__ twg) {
   constexpr int NT = ntz<N>(), WP = wz<N>();
   using L = Lay<N, WP, false>;
   __shared__ float2 buf[L::SIZE];
@@ -542,6 +579,7 @@ __global__ void __launch_bounds__(ntz<N>()) k_z_fwd_grid(const long long* __rest
   const long long n3 = (long long)N * N * N, cn = (long long)(N / 2 + 1) * N * N;
   const int b = blockIdx.y;
   const float unit = 2.3283064365386963e-10f;   // 2^-32
+  unsigned long long sums[3] = {0ull, 0ull, 0ull};
 #pragma unroll
   for (int a = 0; a < NA; ++a) {
     const long long* gsrc = (a == 0 ? g0 : g1) + b * n3;
@@ -550,11 +588,30 @@ __global__ void __launch_bounds__(ntz<N>()) k_z_fwd_grid(const long long* __rest
 #pragma unroll
       for (int r = 0; r < 8; ++r) {
         const long long base = ((long long)(j + r * (N / 8)) * N + y) * N + x0 + c;
-        v[r] = make_float2((float)gsrc[base] * unit, (float)gsrc[base + WP] * unit);
+        const long long q0 = gsrc[base], q1 = gsrc[base + WP];
+        sums[a] += (unsigned long long)q0 + (unsigned long long)q1;
+        if (a == 1) sums[2] += (q0 != 0) + (q1 != 0);
+        v[r] = make_float2((float)q0 * unit, (float)q1 * unit);
       }
     }
     fft_rl<N, WP, false, false>(v, buf, tw);
     z_unpack_store<N, WP, NT, false>(buf, (a == 0 ? o0 : o1) + b * cn, y, x0, 0.f);
+  }
+  __shared__ unsigned long long red[3][NT / 64];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) sums[k] += __shfl_xor(sums[k], o, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) red[k][threadIdx.x >> 6] = sums[k];
+  }
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    unsigned long long t = 0;
+    for (int w = 0; w < NT / 64; ++w) t += red[threadIdx.x][w];
+    tpart[3 * ((long long)b * gridDim.x + blockIdx.x) + threadIdx.x] = t;
   }
 }
 
