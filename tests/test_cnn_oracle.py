@@ -1,0 +1,85 @@
+"""Pins of the learned-start network oracle (library routines, adjointness, finite differences)."""
+import numpy as np
+import pytest
+from scipy import ndimage
+
+from oracle import cnn_oracle as C
+from oracle import recon_oracle as O
+
+
+def test_single_channel_conv_is_periodic_correlation():
+    rng = np.random.default_rng(1)
+    x = rng.standard_normal((1, 6, 7, 8))
+    w = rng.standard_normal((1, 27, 1))
+    ker = np.zeros((3, 3, 3))
+    for t, (dx, dy, dz) in enumerate(C.TAPS):
+        ker[dz + 1, dy + 1, dx + 1] = w[0, t, 0]
+    ref = ndimage.correlate(x[0], ker, mode="wrap")
+    np.testing.assert_allclose(C.conv(x, w, np.zeros(1))[0], ref, atol=1e-12)
+
+
+def test_multichannel_conv_sums_channel_correlations():
+    rng = np.random.default_rng(2)
+    x = rng.standard_normal((3, 5, 5, 5))
+    w = rng.standard_normal((2, 27, 3))
+    b = rng.standard_normal(2)
+    out = C.conv(x, w, b)
+    for o in range(2):
+        ref = b[o] + sum(ndimage.correlate(x[i], np.transpose(w[o, :, i].reshape(3, 3, 3), (0, 1, 2)), mode="wrap")
+                         for i in range(3))
+        np.testing.assert_allclose(out[o], ref, atol=1e-11)
+
+
+def test_input_gradient_is_adjoint_of_conv():
+    rng = np.random.default_rng(3)
+    x = rng.standard_normal((4, 6, 6, 6))
+    g = rng.standard_normal((5, 6, 6, 6))
+    w = rng.standard_normal((5, 27, 4))
+    lhs = np.sum(g * C.conv(x, w, np.zeros(5)))
+    rhs = np.sum(C.conv_input_grad(g, w) * x)
+    assert abs(lhs - rhs) < 1e-9 * abs(lhs)
+    gw = C.conv_weight_grad(g, x)
+    assert abs(np.sum(gw * w) - lhs) < 1e-9 * abs(lhs)
+
+
+def test_loss_gradient_matches_central_differences():
+    rng = np.random.default_rng(4)
+    n = 6
+    delta = rng.standard_normal((n, n, n)) * 0.3
+    u_p = rng.standard_normal((n, n, n)) * 5
+    rhat = O.line_of_sight(n, 60.0, (0, 0, 0), (31.0, 17.0, -40.0))
+    target = rng.standard_normal((n, n, n))
+    theta = C.init_params(5)
+    theta[C.N_PARAMS - 1] = 0.3
+    loss, grad = C.loss_and_grad(theta, delta, u_p, rhat, target)
+    idx = rng.choice(np.flatnonzero(np.abs(grad) > 1e-6), 40, replace=False)
+    h = 1e-5
+    for i in idx:
+        tp, tm = theta.copy(), theta.copy()
+        tp[i] += h
+        tm[i] -= h
+        fd = (C.loss_and_grad(tp, delta, u_p, rhat, target)[0] - C.loss_and_grad(tm, delta, u_p, rhat, target)[0]) / (2 * h)
+        assert abs(fd - grad[i]) <= 1e-6 + 1e-5 * abs(grad[i]), i
+
+
+def test_bf16_rounding_matches_torch():
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(6)
+    x = np.concatenate([rng.standard_normal(10000) * 10, [0.0, -0.0, 1.0, 1.00390625, 1.01171875, 3.4e38]])
+    ref = torch.from_numpy(x.astype(np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
+    np.testing.assert_array_equal(C.bf16(x), ref)
+
+
+def test_first_adam_step_moves_by_lr_times_sign():
+    rng = np.random.default_rng(7)
+    theta = rng.standard_normal(100)
+    g = rng.standard_normal(100)
+    g = np.where(np.abs(g) < 0.05, 0.05, g)
+    new, m, v = C.adam_step(theta, np.zeros(100), np.zeros(100), g, 1, 1e-3)
+    np.testing.assert_allclose(new - theta, -1e-3 * np.sign(g), rtol=1e-6)
+
+
+def test_parameter_layout():
+    assert C.N_PARAMS == 16 * 27 * 8 + 16 + 16 * 27 * 16 + 16 + 27 * 16 + 1
+    theta = np.arange(C.N_PARAMS, dtype=np.float64)
+    np.testing.assert_array_equal(C.pack(C.unpack(theta)), theta)
