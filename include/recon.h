@@ -88,7 +88,8 @@ typedef struct {
   double growth;           /* f >= 0 (eq. Nusser)                                                        */
   double smooth_r;         /* R >= 0 [Mpc/h] (Sec. 3.1 smoothing)                                        */
   double mask_tau;         /* mask threshold as a fraction of the mean 27-cell random sum (>= 0)          */
-  uint32_t flags;          /* RECON_NO_RANDOMS | RECON_KEEP_DELTA | RECON_START_BUFFERS                  */
+  uint32_t flags;          /* RECON_NO_RANDOMS | RECON_KEEP_DELTA | RECON_START_BUFFERS (| RECON_CNN_BUFFERS,
+                              recon_cnn.h)                                                               */
   int64_t max_objects;     /* largest catalogue painted in one call that uses the brick-binned deposit
                               (workspace holds 16 B per object for it); larger calls fall back to
                               per-object atomics.  0 disables binning.  Must be < 2^32.                  */
@@ -112,8 +113,9 @@ int recon_paint(recon_plan_t* plan, int which, const float* pos, const float* w,
                 const int64_t* offsets, uint32_t flags);
 
 /* Totals, smoothing, mask, overdensity and its spectrum D_s, and the starting displacement (a
- * synchronisation point: totals are read back).  start: RECON_START_*; net: device pointer to the
- * learned-start network parameters (RECON_START_LEARNED only, layout in recon_cnn.h), else NULL.
+ * synchronisation point: error flags are read back).  start: RECON_START_*; net: device pointer to
+ * the learned-start network parameters (RECON_START_LEARNED only, layout in recon_cnn.h; the plan
+ * needs RECON_KEEP_DELTA | RECON_START_BUFFERS | RECON_CNN_BUFFERS), else NULL.
  * EINVAL when a painted object was invalid or the total random weight is zero. */
 int recon_solve(recon_plan_t* plan, int start, const void* net);
 

@@ -16,6 +16,8 @@
 #include <vector>
 
 #include "../../include/recon.h"
+#include "../../include/recon_cnn.h"
+#include "recon_cnn.hpp"
 #include "recon_kernels.hpp"
 
 using namespace recon;
@@ -31,6 +33,10 @@ struct Layout {
   size_t grid_g = 0, grid_r = 0, mask = 0, w0 = 0, w1 = 0, w2 = 0, ds = 0, dn = 0, psi = 0, delta = 0,
          corr = 0, tw = 0, partials = 0, red = 0, totals = 0, thr = 0, dscal = 0, act = 0, err = 0, total = 0,
          sorted = 0, bcount = 0, bstart = 0, bcursor = 0, bsum = 0, status = 0, tpart = 0;
+  // network buffers
+  size_t a1 = 0, a2 = 0, d1 = 0, d2 = 0, ybuf = 0, dybuf = 0, upbuf = 0, wk1 = 0, wk2 = 0, wk2t = 0, w3 = 0,
+         part_out = 0, part_w1 = 0, part_w2 = 0, g1 = 0, g2 = 0, g3 = 0, grad = 0, lossp = 0, losst = 0;
+  long long nb_conv = 0, nb_w = 0, nb_loss = 0;
   long long nbins = 0, nscan = 0;
 };
 
@@ -46,7 +52,9 @@ bool valid_params(const recon_params_t* p, std::string* why) {
   if (!(p->growth >= 0.0) || !std::isfinite(p->growth)) return fail("growth must be >= 0 and finite");
   if (!(p->smooth_r >= 0.0) || !std::isfinite(p->smooth_r)) return fail("smooth_r must be >= 0 and finite");
   if (!(p->mask_tau >= 0.0) || !std::isfinite(p->mask_tau)) return fail("mask_tau must be >= 0 and finite");
-  if (p->flags & ~(RECON_NO_RANDOMS | RECON_KEEP_DELTA | RECON_START_BUFFERS)) return fail("unknown flag");
+  if (p->flags & ~(RECON_NO_RANDOMS | RECON_KEEP_DELTA | RECON_START_BUFFERS | RECON_CNN_BUFFERS))
+    return fail("unknown flag");
+  if ((p->flags & RECON_CNN_BUFFERS) && p->n < 16) return fail("the network needs n >= 16");
   if (p->max_objects < 0 || p->max_objects >= (1LL << 32)) return fail("max_objects must be in [0, 2^32)");
   return true;
 }
@@ -96,6 +104,32 @@ Layout make_layout(const recon_params_t* p) {
     L.bcursor = take((L.nbins + 2) * 4);
     L.bsum = take(L.nscan * 4);
   }
+  if (p->flags & RECON_CNN_BUFFERS) {
+    using namespace recon::cnn;
+    L.nb_conv = n3 / TPOS;
+    L.nb_w = (n / TY) * (n / TZ);
+    L.nb_loss = 1024;
+    L.a1 = take(b * n3 * CH * 2);
+    L.a2 = take(b * n3 * CH * 2);
+    L.d1 = take(b * n3 * CH * 2);
+    L.d2 = take(b * n3 * CH * 2);
+    L.ybuf = take(b * n3 * 4);
+    L.dybuf = take(b * n3 * 4);
+    L.upbuf = take(b * n3 * 4);
+    L.wk1 = take(CH * K1P * 2);
+    L.wk2 = take(CH * K2 * 2);
+    L.wk2t = take(CH * K2 * 2);
+    L.w3 = take(K2 * 4);
+    L.part_out = take((size_t)b * L.nb_conv * (K2 + 1) * 4);
+    L.part_w1 = take((size_t)b * L.nb_w * CH * (K1P + 1) * 4);
+    L.part_w2 = take((size_t)b * L.nb_w * CH * (K2 + 1) * 4);
+    L.g1 = take(CH * (K1P + 1) * 4);
+    L.g2 = take(CH * (K2 + 1) * 4);
+    L.g3 = take((K2 + 1) * 4);
+    L.grad = take(NPARAM * 4);
+    L.lossp = take(L.nb_loss * 8);
+    L.losst = take(8);
+  }
   L.total = off;
   return L;
 }
@@ -104,11 +138,12 @@ Layout make_layout(const recon_params_t* p) {
 enum KernelId {
   KP_FILL, KP_PAINT, KP_TOTALS, KP_MASK, KP_Z_FWD_GRID, KP_Y_FWD, KP_X_SMOOTH, KP_Y_INV, KP_Z_DELTA, KP_X_START,
   KP_Z_FWD_REAL, KP_Y_FANOUT, KP_Z_ITER, KP_Y_FANIN, KP_X_ITER, KP_REDUCE, KP_Z_FINAL, KP_SHIFT, KP_BIN, KP_SCAN,
-  KP_COUNT
+  KP_CNN_FWD, KP_CNN_BWD, KP_COUNT
 };
 const char* const kKernelNames[KP_COUNT] = {
     "fill", "paint", "totals", "mask", "z_fwd_grid", "y_fwd", "x_smooth", "y_inv", "z_delta", "x_start",
-    "z_fwd_real", "y_fanout", "z_iter", "y_fanin", "x_iter", "reduce", "z_final", "shift", "bin", "scan"};
+    "z_fwd_real", "y_fanout", "z_iter", "y_fanin", "x_iter", "reduce", "z_final", "shift", "bin", "scan",
+    "cnn_fwd", "cnn_bwd"};
 
 struct Profiler {
   bool on = false;
@@ -140,6 +175,12 @@ struct recon_plan_s {
   DeltaScal* dscal = nullptr;
   int *act_fan = nullptr, *act_fin = nullptr, *act_it = nullptr, *err = nullptr;
   float4* sorted = nullptr;
+  unsigned short *a1 = nullptr, *a2 = nullptr, *d1 = nullptr, *d2 = nullptr, *wk1 = nullptr, *wk2 = nullptr,
+                 *wk2t = nullptr;
+  float *ybuf = nullptr, *dybuf = nullptr, *upbuf = nullptr, *w3 = nullptr, *part_out = nullptr,
+        *part_w1 = nullptr, *part_w2 = nullptr, *g1 = nullptr, *g2 = nullptr, *g3 = nullptr, *gradbuf = nullptr;
+  double *lossp = nullptr, *losst = nullptr;
+  const float* net = nullptr;
   unsigned *bcount = nullptr, *bstart = nullptr, *bcursor = nullptr, *bsum = nullptr;
   Geo geo{};
   CicGeo cic{};
@@ -438,6 +479,30 @@ int upload_mask(recon_plan_t* pl, int* dev, std::vector<int>& host) {
   return RECON_OK;
 }
 
+recon::cnn::Geo3 cnn_geo(const recon_plan_t* pl) {
+  recon::cnn::Geo3 g;
+  g.n = pl->n;
+  g.hs = pl->geo.hs;
+  for (int a = 0; a < 3; ++a) g.ds[a] = pl->geo.ds[a];
+  return g;
+}
+
+// Network forward on the plan's batch; out = scale * y.
+int cnn_forward_impl(recon_plan_t* pl, const float* params, const float* delta, const float* up, float* out,
+                     float scale) {
+  using namespace recon::cnn;
+  const dim3 grid((unsigned)pl->L.nb_conv, pl->batch);
+  const Geo3 g = cnn_geo(pl);
+  PROF(pl, KP_CNN_FWD);
+  k_prep_weights<<<64, 256, 0, pl->stream>>>(params, pl->wk1, pl->wk2, pl->wk2t, pl->w3);
+  k_conv16<CIN, K1P, 1, 0><<<grid, 256, 0, pl->stream>>>(nullptr, delta, up, g, pl->wk1, params + OFF_B1, nullptr,
+                                                         pl->a1);
+  k_conv16<CH, K2, 0, 0><<<grid, 256, 0, pl->stream>>>(pl->a1, nullptr, nullptr, g, pl->wk2, params + OFF_B2,
+                                                       nullptr, pl->a2);
+  k_conv_out<<<grid, 256, 0, pl->stream>>>(pl->a2, g, pl->w3, params + OFF_B3, scale, out);
+  return check_launch(pl, "network forward");
+}
+
 double ffta_c(int start, double beta) {
   if (start == RECON_START_FFTA1) return beta / (1.0 + beta);
   if (start == RECON_START_FFTA2) return 3.0 * beta / (7.0 + 3.0 * beta);
@@ -515,6 +580,28 @@ int recon_plan(recon_plan_t** out, const recon_params_t* params, void* workspace
   pl->act_fin = pl->act_fan + pl->batch;
   pl->act_it = pl->act_fan + 2 * pl->batch;
   pl->err = (int*)(w + L.err);
+  if (params->flags & RECON_CNN_BUFFERS) {
+    pl->a1 = (unsigned short*)(w + L.a1);
+    pl->a2 = (unsigned short*)(w + L.a2);
+    pl->d1 = (unsigned short*)(w + L.d1);
+    pl->d2 = (unsigned short*)(w + L.d2);
+    pl->ybuf = (float*)(w + L.ybuf);
+    pl->dybuf = (float*)(w + L.dybuf);
+    pl->upbuf = (float*)(w + L.upbuf);
+    pl->wk1 = (unsigned short*)(w + L.wk1);
+    pl->wk2 = (unsigned short*)(w + L.wk2);
+    pl->wk2t = (unsigned short*)(w + L.wk2t);
+    pl->w3 = (float*)(w + L.w3);
+    pl->part_out = (float*)(w + L.part_out);
+    pl->part_w1 = (float*)(w + L.part_w1);
+    pl->part_w2 = (float*)(w + L.part_w2);
+    pl->g1 = (float*)(w + L.g1);
+    pl->g2 = (float*)(w + L.g2);
+    pl->g3 = (float*)(w + L.g3);
+    pl->gradbuf = (float*)(w + L.grad);
+    pl->lossp = (double*)(w + L.lossp);
+    pl->losst = (double*)(w + L.losst);
+  }
   if (params->max_objects > 0) {
     pl->sorted = (float4*)(w + L.sorted);
     pl->bcount = (unsigned*)(w + L.bcount);
@@ -675,9 +762,11 @@ int recon_solve(recon_plan_t* pl, int start, const void* net) {
   if (start < RECON_START_PLAIN || start > RECON_START_LEARNED) return fail(pl, RECON_EINVAL, "unknown start");
   if (start != RECON_START_PLAIN && !pl->corr)
     return fail(pl, RECON_EINVAL, "non-plain starts need a plan created with RECON_START_BUFFERS");
-  if (start == RECON_START_LEARNED)
-    return fail(pl, RECON_EINVAL, "learned start needs the network library (not linked in this build)");
-  (void)net;
+  if (start == RECON_START_LEARNED) {
+    if (!net) return fail(pl, RECON_EINVAL, "learned start needs the network parameters");
+    if (!pl->delta || !pl->a1)
+      return fail(pl, RECON_EINVAL, "learned start needs RECON_KEEP_DELTA and RECON_CNN_BUFFERS");
+  }
   const Ops* ops = ops_for(pl->n);
   if (pl->state == ST_PAINTED) {
     if (!pl->painted_g) return fail(pl, RECON_ESTATE, "galaxies were not painted");
@@ -712,6 +801,13 @@ int recon_solve(recon_plan_t* pl, int start, const void* net) {
     pl->pending1[b] = 0;
     pl->diverged[b] = 0;
     pl->hist[b].clear();
+  }
+  if (start == RECON_START_LEARNED) {
+    // u_p = Psi_p . r_hat from the fanned-out start, then Delta u = network(delta_s, u_p) into corr
+    RECON_TRY(ops->fanout(pl, nullptr));
+    RECON_TRY(ops->zfinal(pl, nullptr, pl->upbuf, false, nullptr));
+    RECON_TRY(cnn_forward_impl(pl, (const float*)net, pl->delta, pl->upbuf, pl->corr, 1.0f / recon::cnn::S_U));
+    for (int b = 0; b < pl->batch; ++b) pl->st_y[b] = 1;
   }
   pl->state = ST_SOLVED;
   return RECON_OK;
@@ -902,6 +998,66 @@ int recon_get_delta(recon_plan_t* pl, float* out) {
   if (pl->state != ST_SOLVED && pl->state != ST_DELTA) return fail(pl, RECON_ESTATE, "no overdensity yet");
   HIP_TRY(pl, hipMemcpyAsync(out, pl->delta, sizeof(float) * pl->n3 * pl->batch, hipMemcpyDeviceToDevice, pl->stream));
   return RECON_OK;
+}
+
+int recon_cnn_forward(recon_plan_t* pl, const float* params, const float* delta, const float* u_p, float* du_out) {
+  if (!pl) return RECON_EINVAL;
+  if (!pl->a1) return fail(pl, RECON_EINVAL, "plan was created without RECON_CNN_BUFFERS");
+  if (!params || !delta || !u_p || !du_out) return fail(pl, RECON_EINVAL, "NULL pointer");
+  return cnn_forward_impl(pl, params, delta, u_p, du_out, 1.0f / recon::cnn::S_U);
+}
+
+int recon_cnn_train_step(recon_plan_t* pl, float* params, float* adam_m, float* adam_v, int step, float lr,
+                         const float* delta, const float* u_p, const float* target_du, double* loss_out,
+                         float* grad_out) {
+  using namespace recon::cnn;
+  if (!pl) return RECON_EINVAL;
+  if (!pl->a1) return fail(pl, RECON_EINVAL, "plan was created without RECON_CNN_BUFFERS");
+  if (!params || !delta || !u_p || !target_du) return fail(pl, RECON_EINVAL, "NULL pointer");
+  if (lr > 0.f && (!adam_m || !adam_v || step < 1)) return fail(pl, RECON_EINVAL, "Adam needs moments and step >= 1");
+  const long long count = pl->n3 * pl->batch;
+  RECON_TRY(cnn_forward_impl(pl, params, delta, u_p, pl->ybuf, 1.0f));
+  const dim3 grid((unsigned)pl->L.nb_conv, pl->batch);
+  const dim3 gridw((unsigned)pl->L.nb_w, pl->batch);
+  const Geo3 g = cnn_geo(pl);
+  hipStream_t s = pl->stream;
+  {
+    PROF(pl, KP_CNN_BWD);
+    k_loss<<<(unsigned)pl->L.nb_loss, 256, 0, s>>>(pl->ybuf, target_du, count, pl->dybuf, pl->lossp);
+    k_conv_out_bwd<<<grid, 256, 0, s>>>(pl->dybuf, pl->a2, g, pl->w3, pl->d2, pl->part_out);
+    k_wgrad16<CH, K2, 0><<<gridw, 256, 0, s>>>(pl->d2, pl->a1, nullptr, nullptr, g, pl->part_w2);
+    k_conv16<CH, K2, 0, 1><<<grid, 256, 0, s>>>(pl->d2, nullptr, nullptr, g, pl->wk2t, nullptr, pl->a1, pl->d1);
+    k_wgrad16<CIN, K1P, 1><<<gridw, 256, 0, s>>>(pl->d1, nullptr, delta, u_p, g, pl->part_w1);
+    const long long nbo = pl->L.nb_conv * pl->batch, nbw = pl->L.nb_w * pl->batch;
+    k_reduce_cols<<<(K2 + 1 + 255) / 256, 256, 0, s>>>(pl->part_out, nbo, K2 + 1, pl->g3);
+    k_reduce_cols<<<(CH * (K2 + 1) + 255) / 256, 256, 0, s>>>(pl->part_w2, nbw, CH * (K2 + 1), pl->g2);
+    k_reduce_cols<<<(CH * (K1P + 1) + 255) / 256, 256, 0, s>>>(pl->part_w1, nbw, CH * (K1P + 1), pl->g1);
+    float* grad = grad_out ? grad_out : pl->gradbuf;
+    k_assemble_grad<<<(NPARAM + 255) / 256, 256, 0, s>>>(pl->g1, pl->g2, pl->g3, grad);
+    k_reduce_loss<<<1, 256, 0, s>>>(pl->lossp, (int)pl->L.nb_loss, pl->losst);
+    if (lr > 0.f) {
+      const float c1 = (float)(1.0 - std::pow(0.9, step)), c2 = (float)(1.0 - std::pow(0.999, step));
+      k_adam<<<(NPARAM + 255) / 256, 256, 0, s>>>(params, adam_m, adam_v, grad, NPARAM, lr, 0.9f, 0.999f, 1e-8f,
+                                                  c1, c2);
+    }
+  }
+  RECON_TRY(check_launch(pl, "network training step"));
+  double lsum = 0.0;
+  HIP_TRY(pl, hipMemcpyAsync(&lsum, pl->losst, 8, hipMemcpyDeviceToHost, s));
+  HIP_TRY(pl, hipStreamSynchronize(s));
+  if (loss_out) *loss_out = lsum / (double)count;
+  return RECON_OK;
+}
+
+int recon_get_radial(recon_plan_t* pl, float* u_out) {
+  if (!pl || !u_out) return RECON_EINVAL;
+  if (pl->state != ST_SOLVED) return fail(pl, RECON_ESTATE, "no displacement yet");
+  for (int b = 0; b < pl->batch; ++b)
+    if (!pl->psi_valid[b]) return fail(pl, RECON_ESTATE, "displacement not computed; call iterate");
+  long long blocks = (pl->n3 * pl->batch + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  recon::cnn::k_radial<<<(unsigned)blocks, 256, 0, pl->stream>>>(pl->psi, cnn_geo(pl), pl->batch, u_out);
+  return check_launch(pl, "radial component");
 }
 
 int recon_profile_start(recon_plan_t* pl) {

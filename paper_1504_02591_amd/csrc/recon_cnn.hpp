@@ -1,0 +1,416 @@
+// Learned-start network kernels (not part of the paper's method): three periodic
+// 3x3x3 convolutions, channels-last bfloat16 activations, FP32 accumulation.
+//
+//   x0 = [delta_s, S_U u_p, r_x, r_y, r_z, 0, 0, 0]     (assembled on the fly)
+//   a1 = relu(conv(x0; W1, b1))      8 -> 16   BF16 MFMA
+//   a2 = relu(conv(a1; W2, b2))     16 -> 16   BF16 MFMA
+//   y  =      conv(a2; W3, b3)      16 -> 1    VALU
+//   Delta u = y / S_U
+//
+// Parameter vector (FP32, device): W1 [16][27][8], b1 [16], W2 [16][27][16], b2 [16],
+// W3 [1][27][16], b3 [1]; tap t = (dz+1)*9 + (dy+1)*3 + (dx+1), offset (dx, dy, dz).
+//
+// Convolutions are implicit GEMMs on v_mfma_f32_16x16x16bf16_1k: M = 16 output
+// positions (one x row of a 16 x 4 x 4 output tile), N = 16 output channels,
+// K = 27 taps x C_in input channels in blocks of 16.  Operand layout of that
+// instruction: lane l holds A[l%16][4(l/16)+0..3], B[4(l/16)+0..3][l%16], and the
+// result D[4(l/16)+0..3][l%16].
+#pragma once
+
+#include "recon_kernels.hpp"
+
+namespace recon {
+namespace cnn {
+
+constexpr int CIN = 8, CH = 16;
+constexpr float S_U = 0.1f;
+constexpr int OFF_W1 = 0, OFF_B1 = OFF_W1 + CH * 27 * CIN, OFF_W2 = OFF_B1 + CH, OFF_B2 = OFF_W2 + CH * 27 * CH,
+              OFF_W3 = OFF_B2 + CH, OFF_B3 = OFF_W3 + 27 * CH, NPARAM = OFF_B3 + 1;
+constexpr int K1 = 27 * CIN, K1P = 224;      // layer-1 K padded to a multiple of 16
+constexpr int K2 = 27 * CH;                  // 432
+// output tile: 16 (x) by 4 (y) by 4 (z) positions, halo tile 18 x 6 x 6 cells
+constexpr int TX = 16, TY = 4, TZ = 4, HX = TX + 2, HY = TY + 2, HZ = TZ + 2, HCELLS = HX * HY * HZ;
+constexpr int TPOS = TX * TY * TZ;   // 256
+
+typedef short s4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ unsigned short to_bf16(float f) {
+  unsigned u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ float from_bf16(unsigned short h) { return __uint_as_float(((unsigned)h) << 16); }
+
+struct Geo3 {
+  int n;
+  float hs;
+  float ds[3];
+};
+
+// Tile origin of this block: blockIdx.x runs over (x tiles, y tiles, z tiles), blockIdx.y = realisation.
+__device__ __forceinline__ void tile_origin(int n, int& x0, int& y0, int& z0) {
+  const int ntx = n / TX, nty = n / TY;
+  const int t = blockIdx.x;
+  x0 = (t % ntx) * TX;
+  y0 = ((t / ntx) % nty) * TY;
+  z0 = (t / (ntx * nty)) * TZ;
+}
+
+__device__ __forceinline__ long long halo_cell_global(int n, int x0, int y0, int z0, int hc) {
+  const int hx = hc % HX, hy = (hc / HX) % HY, hz = hc / (HX * HY);
+  const long long x = (x0 - 1 + hx) & (n - 1), y = (y0 - 1 + hy) & (n - 1), z = (z0 - 1 + hz) & (n - 1);
+  return (z * n + y) * n + x;
+}
+
+// Stage the halo tile of a channels-last bf16 tensor with C channels into LDS.
+template <int C>
+__device__ __forceinline__ void stage_bf16(unsigned short* tile, const unsigned short* __restrict__ src, int n, int x0,
+                                           int y0, int z0) {
+  constexpr int CH4 = C / 4;
+  for (int e = threadIdx.x; e < HCELLS * CH4; e += 256) {
+    const int hc = e / CH4, q = e % CH4;
+    const long long g = halo_cell_global(n, x0, y0, z0, hc);
+    *(uint2*)(tile + hc * C + 4 * q) = *(const uint2*)(src + g * C + 4 * q);
+  }
+}
+
+// Stage the assembled 8-channel input x0 = [delta, S_U u_p, r_hat, 0, 0, 0].
+__device__ __forceinline__ void stage_x0(unsigned short* tile, const float* __restrict__ delta,
+                                         const float* __restrict__ up, const Geo3& g, int x0, int y0, int z0) {
+  for (int hc = threadIdx.x; hc < HCELLS; hc += 256) {
+    const int hx = hc % HX, hy = (hc / HX) % HY, hz = hc / (HX * HY);
+    const int x = (x0 - 1 + hx) & (g.n - 1), y = (y0 - 1 + hy) & (g.n - 1), z = (z0 - 1 + hz) & (g.n - 1);
+    const long long c = ((long long)z * g.n + y) * g.n + x;
+    const float rx = fmaf(g.hs, (float)x, g.ds[0]), ry = fmaf(g.hs, (float)y, g.ds[1]),
+                rz = fmaf(g.hs, (float)z, g.ds[2]);
+    const float r2 = rx * rx + ry * ry + rz * rz;
+    const float ir = r2 > 0.f ? rsqrtf(r2) : 0.f;
+    unsigned short* t = tile + hc * CIN;
+    t[0] = to_bf16(delta[c]);
+    t[1] = to_bf16(S_U * up[c]);
+    t[2] = to_bf16(rx * ir);
+    t[3] = to_bf16(ry * ir);
+    t[4] = to_bf16(rz * ir);
+    t[5] = 0;
+    t[6] = 0;
+    t[7] = 0;
+  }
+}
+
+// Halo-tile cell of output row (zr, yr), position m, shifted by tap t.
+__device__ __forceinline__ int tap_cell(int zr, int yr, int m, int t) {
+  const int dx = t % 3 - 1, dy = (t / 3) % 3 - 1, dz = t / 9 - 1;
+  return ((zr + 1 + dz) * HY + (yr + 1 + dy)) * HX + (m + 1 + dx);
+}
+
+// Convolution with C input channels and 16 output channels on MFMA.
+//   SRC 0: input is a bf16 tensor [n^3][C];  SRC 1: input is x0 assembled from (delta, u_p) (C = 8).
+//   EPI 0: out = bf16(relu(acc + bias));     EPI 1: out = bf16(acc) where gate > 0, else 0.
+// wk: weights in MFMA layout [16 out][KP] bf16 (KP >= 27 C, zero padded).
+template <int C, int KP, int SRC, int EPI>
+__global__ void __launch_bounds__(256) k_conv16(const unsigned short* __restrict__ in, const float* __restrict__ delta,
+                                                const float* __restrict__ up, Geo3 g, const unsigned short* __restrict__ wk,
+                                                const float* __restrict__ bias, const unsigned short* __restrict__ gate,
+                                                unsigned short* __restrict__ out) {
+  constexpr int KB = KP / 16;
+  __shared__ unsigned short tile[HCELLS * C];
+  const long long n3 = (long long)g.n * g.n * g.n;
+  const int b = blockIdx.y;
+  int x0, y0, z0;
+  tile_origin(g.n, x0, y0, z0);
+  if (SRC == 0) stage_bf16<C>(tile, in + b * n3 * C, g.n, x0, y0, z0);
+  else stage_x0(tile, delta + b * n3, up + b * n3, g, x0, y0, z0);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int m = lane & 15, q = lane >> 4;
+  // B operands (weights) for every K block, kept in registers
+  s4 bw[KB];
+#pragma unroll
+  for (int kb = 0; kb < KB; ++kb) bw[kb] = *(const s4*)(wk + m * KP + kb * 16 + 4 * q);
+  __syncthreads();
+#pragma unroll
+  for (int row = 0; row < 4; ++row) {
+    const int rr = wave * 4 + row, zr = rr / TY, yr = rr % TY;
+    f4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) {
+      const int k = kb * 16 + 4 * q;
+      int t = k / C;
+      if (t > 26) t = 26;                            // padded K: weights are zero there
+      const s4 a = *(const s4*)(tile + tap_cell(zr, yr, m, t) * C + (k % C));
+      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bw[kb], acc, 0, 0, 0);
+    }
+    // lane holds D[pos = 4q + i][channel = m]
+    const long long rowbase = ((long long)(z0 + zr) * g.n + (y0 + yr)) * g.n + x0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const long long cell = b * n3 + rowbase + 4 * q + i;
+      float v = acc[i];
+      if (EPI == 0) v = fmaxf(v + bias[m], 0.f);
+      else v = from_bf16(gate[cell * CH + m]) > 0.f ? v : 0.f;
+      out[cell * CH + m] = to_bf16(v);
+    }
+  }
+}
+
+// Output layer (16 -> 1) on VALU: y = b3 + sum_t sum_i W3[t][i] a2[p + d_t][i]; y_out FP32.
+// scale multiplies the result (1 for training, 1/S_U to write Delta u directly).
+__global__ void __launch_bounds__(256) k_conv_out(const unsigned short* __restrict__ a2, Geo3 g,
+                                                  const float* __restrict__ w3, const float* __restrict__ b3,
+                                                  float scale, float* __restrict__ y_out) {
+  __shared__ unsigned short tile[HCELLS * CH];
+  __shared__ float w[27 * CH];
+  const long long n3 = (long long)g.n * g.n * g.n;
+  const int b = blockIdx.y;
+  int x0, y0, z0;
+  tile_origin(g.n, x0, y0, z0);
+  stage_bf16<CH>(tile, a2 + b * n3 * CH, g.n, x0, y0, z0);
+  for (int i = threadIdx.x; i < 27 * CH; i += 256) w[i] = w3[i];
+  __syncthreads();
+  const int m = threadIdx.x % TX, yr = (threadIdx.x / TX) % TY, zr = threadIdx.x / (TX * TY);
+  float acc = b3[0];
+  for (int t = 0; t < 27; ++t) {
+    const unsigned short* a = tile + tap_cell(zr, yr, m, t) * CH;
+#pragma unroll
+    for (int i = 0; i < CH; ++i) acc = fmaf(w[t * CH + i], from_bf16(a[i]), acc);
+  }
+  const long long cell = ((long long)(z0 + zr) * g.n + (y0 + yr)) * g.n + x0 + m;
+  y_out[b * n3 + cell] = acc * scale;
+}
+
+// Loss residual: r = y - S_U target; dy = 2 r / count; per-block partial of sum r^2.
+__global__ void __launch_bounds__(256) k_loss(const float* __restrict__ y, const float* __restrict__ target,
+                                              long long count, float* __restrict__ dy, double* __restrict__ partial) {
+  double acc = 0.0;
+  const float inv = 2.0f / (float)count;
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < count; i += (long long)gridDim.x * 256) {
+    const float r = y[i] - S_U * target[i];
+    dy[i] = inv * r;
+    acc += (double)r * (double)r;
+  }
+  double t1, t2;
+  block_sum2<256>(acc, 0.0, &t1, &t2);
+  if (threadIdx.x == 0) partial[blockIdx.x] = t1;
+}
+
+// Output-layer backward: dpre2[p][i] = bf16((sum_t W3[t][i] dy[p - d_t]) * [a2[p][i] > 0]),
+// and per-block partials of dW3[t][i] = sum_p dy[p] a2[p + d_t][i] and db3 = sum_p dy[p].
+__global__ void __launch_bounds__(256) k_conv_out_bwd(const float* __restrict__ dy, const unsigned short* __restrict__ a2,
+                                                      Geo3 g, const float* __restrict__ w3,
+                                                      unsigned short* __restrict__ dpre2, float* __restrict__ part) {
+  __shared__ unsigned short tile[HCELLS * CH];
+  __shared__ float dyt[HCELLS];
+  __shared__ float w[27 * CH];
+  const long long n3 = (long long)g.n * g.n * g.n;
+  const int b = blockIdx.y;
+  int x0, y0, z0;
+  tile_origin(g.n, x0, y0, z0);
+  stage_bf16<CH>(tile, a2 + b * n3 * CH, g.n, x0, y0, z0);
+  for (int hc = threadIdx.x; hc < HCELLS; hc += 256) dyt[hc] = dy[b * n3 + halo_cell_global(g.n, x0, y0, z0, hc)];
+  for (int i = threadIdx.x; i < 27 * CH; i += 256) w[i] = w3[i];
+  __syncthreads();
+  {
+    const int m = threadIdx.x % TX, yr = (threadIdx.x / TX) % TY, zr = threadIdx.x / (TX * TY);
+    float d[CH];
+#pragma unroll
+    for (int i = 0; i < CH; ++i) d[i] = 0.f;
+    for (int t = 0; t < 27; ++t) {
+      const float v = dyt[tap_cell(zr, yr, m, 26 - t)];      // dy(p - d_t)
+#pragma unroll
+      for (int i = 0; i < CH; ++i) d[i] = fmaf(w[t * CH + i], v, d[i]);
+    }
+    const int hc = tap_cell(zr, yr, m, 13);
+    const long long cell = b * n3 + ((long long)(z0 + zr) * g.n + (y0 + yr)) * g.n + x0 + m;
+#pragma unroll
+    for (int i = 0; i < CH; ++i) dpre2[cell * CH + i] = to_bf16(from_bf16(tile[hc * CH + i]) > 0.f ? d[i] : 0.f);
+  }
+  // weight partials: entry e = t * 16 + i (432 entries) plus the bias (entry 432)
+  const long long blk = (long long)b * gridDim.x + blockIdx.x;
+  for (int e = threadIdx.x; e < 27 * CH + 1; e += 256) {
+    float acc = 0.f;
+    if (e < 27 * CH) {
+      const int t = e / CH, i = e % CH;
+      for (int p = 0; p < TPOS; ++p) {
+        const int m = p % TX, yr = (p / TX) % TY, zr = p / (TX * TY);
+        acc = fmaf(dyt[tap_cell(zr, yr, m, 13)], from_bf16(tile[tap_cell(zr, yr, m, t) * CH + i]), acc);
+      }
+    } else {
+      for (int p = 0; p < TPOS; ++p) {
+        const int m = p % TX, yr = (p / TX) % TY, zr = p / (TX * TY);
+        acc += dyt[tap_cell(zr, yr, m, 13)];
+      }
+    }
+    part[blk * (27 * CH + 1) + e] = acc;
+  }
+}
+
+// Weight gradient of a 16-output convolution on MFMA:
+//   dW[o][t C + i] = sum_p dpre[p][o] x[p + d_t][i],  db[o] = sum_p dpre[p][o]
+// M = 16 output channels, N = 16 columns (C = 16: the channels of one tap; C = 8: two taps),
+// K = 16 positions per instruction.  One block loops over the x tiles of one (y, z) tile
+// row and writes one partial [16][KP + 1] (bias in the last column).
+template <int C, int KP, int SRC>
+__global__ void __launch_bounds__(256) k_wgrad16(const unsigned short* __restrict__ dpre,
+                                                 const unsigned short* __restrict__ in, const float* __restrict__ delta,
+                                                 const float* __restrict__ up, Geo3 g, float* __restrict__ part) {
+  constexpr int NT = KP / 16;                 // column tiles: C = 16 -> 27 taps, C = 8 -> 14 tap pairs
+  constexpr int TPW = (NT + 3) / 4;           // column tiles per wave
+  __shared__ unsigned short tile[HCELLS * C];
+  __shared__ unsigned short dt[CH][TPOS + 4];   // dpre of the tile, transposed [o][p]
+  const long long n3 = (long long)g.n * g.n * g.n;
+  const int b = blockIdx.y;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int m = lane & 15, q = lane >> 4;
+  f4 acc[TPW];
+#pragma unroll
+  for (int k = 0; k < TPW; ++k) acc[k] = f4{0.f, 0.f, 0.f, 0.f};
+  float bacc = 0.f;
+  const int ntx = g.n / TX, nty = g.n / TY;
+  const int y0 = (blockIdx.x % nty) * TY, z0 = (blockIdx.x / nty) * TZ;
+  for (int xt = 0; xt < ntx; ++xt) {
+    const int x0 = xt * TX;
+    __syncthreads();
+    if (SRC == 0) stage_bf16<C>(tile, in + b * n3 * C, g.n, x0, y0, z0);
+    else stage_x0(tile, delta + b * n3, up + b * n3, g, x0, y0, z0);
+    for (int e = threadIdx.x; e < TPOS * CH / 4; e += 256) {
+      const int p = e / (CH / 4), o4 = e % (CH / 4);
+      const int pm = p % TX, py = (p / TX) % TY, pz = p / (TX * TY);
+      const long long cell = b * n3 + ((long long)(z0 + pz) * g.n + (y0 + py)) * g.n + x0 + pm;
+      const uint2 v = *(const uint2*)(dpre + cell * CH + 4 * o4);
+      dt[4 * o4 + 0][p] = (unsigned short)(v.x & 0xFFFF);
+      dt[4 * o4 + 1][p] = (unsigned short)(v.x >> 16);
+      dt[4 * o4 + 2][p] = (unsigned short)(v.y & 0xFFFF);
+      dt[4 * o4 + 3][p] = (unsigned short)(v.y >> 16);
+    }
+    __syncthreads();
+    if (threadIdx.x < CH) {
+      for (int p = 0; p < TPOS; ++p) bacc += from_bf16(dt[threadIdx.x][p]);
+    }
+#pragma unroll
+    for (int kp = 0; kp < TPOS / 16; ++kp) {
+      // A[o][k] = dpre[p = 16 kp + k][o]: lane row o = m, k = 4q..4q+3
+      const s4 a = *(const s4*)(&dt[m][kp * 16 + 4 * q]);
+      const int p0 = kp * 16 + 4 * q;
+#pragma unroll
+      for (int k = 0; k < TPW; ++k) {
+        const int nt = wave + 4 * k;
+        if (nt < NT) {
+          // B[k][n] = x[p + d_t][i]: lane column n = m
+          const int col = nt * 16 + m;
+          int t = col / C;
+          const int i = col % C;
+          if (t > 26) t = 26;
+          s4 bv;
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const int p = p0 + j;
+            const int pm = p % TX, py = (p / TX) % TY, pz = p / (TX * TY);
+            bv[j] = (short)tile[tap_cell(pz, py, pm, t) * C + i];
+          }
+          acc[k] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bv, acc[k], 0, 0, 0);
+        }
+      }
+    }
+  }
+  // D[o = 4q + r][col = m] for each column tile
+  const long long blk = (long long)b * gridDim.x + blockIdx.x;
+  float* pb = part + blk * (CH * (KP + 1));
+#pragma unroll
+  for (int k = 0; k < TPW; ++k) {
+    const int nt = wave + 4 * k;
+    if (nt < NT) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) pb[(4 * q + r) * (KP + 1) + nt * 16 + m] = acc[k][r];
+    }
+  }
+  if (threadIdx.x < CH) pb[threadIdx.x * (KP + 1) + KP] = bacc;
+}
+
+// out[c] = sum over nb partial rows of in[row][c] (fixed order).
+__global__ void __launch_bounds__(256) k_reduce_cols(const float* __restrict__ part, long long nb, int ncols,
+                                                     float* __restrict__ out) {
+  const int c = blockIdx.x * 256 + threadIdx.x;
+  if (c >= ncols) return;
+  double acc = 0.0;
+  for (long long r = 0; r < nb; ++r) acc += (double)part[r * ncols + c];
+  out[c] = (float)acc;
+}
+
+__global__ void __launch_bounds__(256) k_reduce_loss(const double* __restrict__ part, int nb, double* __restrict__ out) {
+  double a = 0.0;
+  for (int i = threadIdx.x; i < nb; i += 256) a += part[i];
+  double t1, t2;
+  block_sum2<256>(a, 0.0, &t1, &t2);
+  if (threadIdx.x == 0) out[0] = t1;
+}
+
+// Weights in MFMA layouts: wk1 [16][K1P] (k = t*8 + i), wk2 [16][432] (k = t*16 + i),
+// wk2t [16][432] with wk2t[i][t*16 + o] = W2[o][26 - t][i] (flipped taps, transposed
+// channels: the data gradient as a forward convolution), w3 [432] as bf16-rounded FP32.
+__global__ void __launch_bounds__(256) k_prep_weights(const float* __restrict__ th, unsigned short* __restrict__ wk1,
+                                                      unsigned short* __restrict__ wk2, unsigned short* __restrict__ wk2t,
+                                                      float* __restrict__ w3) {
+  for (int e = blockIdx.x * 256 + threadIdx.x; e < CH * K1P + 2 * CH * K2 + K2; e += gridDim.x * 256) {
+    if (e < CH * K1P) {
+      const int o = e / K1P, k = e % K1P;
+      wk1[e] = k < K1 ? to_bf16(th[OFF_W1 + o * K1 + k]) : (unsigned short)0;
+    } else if (e < CH * K1P + CH * K2) {
+      const int f = e - CH * K1P;
+      wk2[f] = to_bf16(th[OFF_W2 + f]);
+    } else if (e < CH * K1P + 2 * CH * K2) {
+      const int f = e - CH * K1P - CH * K2;
+      const int i = f / K2, k = f % K2, t = k / CH, o = k % CH;
+      wk2t[f] = to_bf16(th[OFF_W2 + (o * 27 + (26 - t)) * CH + i]);
+    } else {
+      const int f = e - CH * K1P - 2 * CH * K2;
+      w3[f] = from_bf16(to_bf16(th[OFF_W3 + f]));
+    }
+  }
+}
+
+// Gradient assembly from the reduced partials into the parameter layout.
+__global__ void __launch_bounds__(256) k_assemble_grad(const float* __restrict__ g1, const float* __restrict__ g2,
+                                                       const float* __restrict__ g3, float* __restrict__ grad) {
+  for (int e = blockIdx.x * 256 + threadIdx.x; e < NPARAM; e += gridDim.x * 256) {
+    float v;
+    if (e < OFF_B1) { const int o = e / K1, k = e % K1; v = g1[o * (K1P + 1) + k]; }
+    else if (e < OFF_W2) v = g1[(e - OFF_B1) * (K1P + 1) + K1P];
+    else if (e < OFF_B2) { const int f = e - OFF_W2, o = f / K2, k = f % K2; v = g2[o * (K2 + 1) + k]; }
+    else if (e < OFF_W3) v = g2[(e - OFF_B2) * (K2 + 1) + K2];
+    else v = g3[e - OFF_W3];        // W3 (432) then b3 (entry 432)
+    grad[e] = v;
+  }
+}
+
+// Adam (Kingma & Ba 2015) with bias correction; step counts from 1.
+__global__ void __launch_bounds__(256) k_adam(float* __restrict__ th, float* __restrict__ m, float* __restrict__ v,
+                                              const float* __restrict__ grad, int n, float lr, float b1, float b2,
+                                              float eps, float c1, float c2) {
+  for (int e = blockIdx.x * 256 + threadIdx.x; e < n; e += gridDim.x * 256) {
+    const float gr = grad[e];
+    const float mm = b1 * m[e] + (1.f - b1) * gr;
+    const float vv = b2 * v[e] + (1.f - b2) * gr * gr;
+    m[e] = mm;
+    v[e] = vv;
+    th[e] -= lr * (mm / c1) / (sqrtf(vv / c2) + eps);
+  }
+}
+
+// u = Psi . r_hat from the interleaved displacement.
+__global__ void __launch_bounds__(256) k_radial(const float4* __restrict__ psi4, Geo3 g, int batch,
+                                                float* __restrict__ u) {
+  const long long n3 = (long long)g.n * g.n * g.n;
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n3 * batch; i += (long long)gridDim.x * 256) {
+    const long long c = i % n3;
+    const int x = (int)(c % g.n), y = (int)((c / g.n) % g.n), z = (int)(c / ((long long)g.n * g.n));
+    const float rx = fmaf(g.hs, (float)x, g.ds[0]), ry = fmaf(g.hs, (float)y, g.ds[1]),
+                rz = fmaf(g.hs, (float)z, g.ds[2]);
+    const float r2 = rx * rx + ry * ry + rz * rz;
+    const float ir = r2 > 0.f ? rsqrtf(r2) : 0.f;
+    const float4 p = psi4[i];
+    u[i] = (rx * p.x + ry * p.y + rz * p.z) * ir;
+  }
+}
+
+}  // namespace cnn
+}  // namespace recon

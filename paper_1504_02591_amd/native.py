@@ -20,13 +20,15 @@ RECON_OK, RECON_NOTCONVERGED = 0, 1
 RECON_EINVAL, RECON_ENOMEM, RECON_EDEVICE, RECON_ESTATE, RECON_EDIVERGED = -1, -2, -3, -4, -5
 GAL, RAN = 0, 1
 START_PLAIN, START_FFTA1, START_FFTA2, START_LEARNED = 0, 1, 2, 3
-NO_RANDOMS, KEEP_DELTA, START_BUFFERS = 1, 2, 4
+NO_RANDOMS, KEEP_DELTA, START_BUFFERS, CNN_BUFFERS = 1, 2, 4, 8
+CNN_PARAMS = 10833
 PAINT_ACCUMULATE = 1
 
 EXPORTED = ("recon_workspace_bytes", "recon_plan", "recon_paint", "recon_solve", "recon_iterate",
             "recon_shift", "recon_get_psi", "recon_get_grid", "recon_get_delta", "recon_set_delta",
             "recon_destroy", "recon_strerror", "recon_last_error", "recon_profile_start",
-            "recon_profile_stop", "recon_profile_kernel_name")
+            "recon_profile_stop", "recon_profile_kernel_name", "recon_cnn_forward", "recon_cnn_train_step",
+            "recon_get_radial")
 
 
 class ReconError(RuntimeError):
@@ -76,11 +78,16 @@ def load(path=None):
     lib.recon_strerror.restype = ctypes.c_char_p
     lib.recon_last_error.argtypes = [vp]
     lib.recon_last_error.restype = ctypes.c_char_p
+    lib.recon_cnn_forward.argtypes = [vp, vp, vp, vp, vp]
+    lib.recon_cnn_train_step.argtypes = [vp, vp, vp, vp, ctypes.c_int, ctypes.c_float, vp, vp, vp,
+                                         ctypes.POINTER(dbl), vp]
+    lib.recon_get_radial.argtypes = [vp, vp]
     lib.recon_profile_start.argtypes = [vp]
     lib.recon_profile_stop.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(dbl), ctypes.c_int]
     lib.recon_profile_kernel_name.argtypes = [ctypes.c_int]
     lib.recon_profile_kernel_name.restype = ctypes.c_char_p
-    for name in ("recon_profile_start", "recon_profile_stop", "recon_plan", "recon_paint", "recon_solve", "recon_iterate", "recon_shift",
+    for name in ("recon_cnn_forward", "recon_cnn_train_step", "recon_get_radial",
+                 "recon_profile_start", "recon_profile_stop", "recon_plan", "recon_paint", "recon_solve", "recon_iterate", "recon_shift",
                  "recon_get_psi", "recon_get_grid", "recon_get_delta", "recon_set_delta"):
         getattr(lib, name).restype = ctypes.c_int
     if path is None:
@@ -107,11 +114,12 @@ class Plan:
     """A reconstruction plan: workspace, geometry, and the C-ABI calls on the current stream."""
 
     def __init__(self, n, box_len, observer, bias, growth, smooth_r, origin=(0.0, 0.0, 0.0), batch=1,
-                 mask_tau=0.1, randoms=True, keep_delta=False, start_buffers=False, max_objects=0, device=None):
+                 mask_tau=0.1, randoms=True, keep_delta=False, start_buffers=False, max_objects=0, cnn=False,
+                 device=None):
         self.lib = load()
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
         flags = (0 if randoms else NO_RANDOMS) | (KEEP_DELTA if keep_delta else 0) | \
-                (START_BUFFERS if start_buffers else 0)
+                (START_BUFFERS if start_buffers else 0) | (CNN_BUFFERS if cnn else 0)
         p = Params()
         p.n, p.batch, p.box_len = int(n), int(batch), float(box_len)
         for a in range(3):
@@ -213,6 +221,34 @@ class Plan:
             if counts[i]:
                 out[self.lib.recon_profile_kernel_name(i).decode()] = (int(counts[i]), float(tot[i]))
         return out
+
+    def radial(self):
+        """u = Psi . r_hat of the current displacement, [batch, n, n, n]."""
+        out = torch.empty((self.batch, self.n, self.n, self.n), dtype=torch.float32, device=self.device)
+        self._rc(self.lib.recon_get_radial(self.handle, _ptr(out)))
+        return out
+
+    def cnn_forward(self, params, delta, u_p):
+        """Learned radial correction Delta u for every cell, [batch, n, n, n]."""
+        for t, nm in ((params, "params"), (delta, "delta"), (u_p, "u_p")):
+            _check_dev(t, torch.float32, None, nm, self.device)
+        if params.numel() != CNN_PARAMS or delta.numel() != self.batch * self.n ** 3 or u_p.numel() != delta.numel():
+            raise ValueError("bad network input sizes")
+        out = torch.empty((self.batch, self.n, self.n, self.n), dtype=torch.float32, device=self.device)
+        self._rc(self.lib.recon_cnn_forward(self.handle, _ptr(params), _ptr(delta), _ptr(u_p), _ptr(out)))
+        return out
+
+    def cnn_train_step(self, params, m, v, step, lr, delta, u_p, target_du, grad_out=None):
+        """One loss/gradient evaluation and (lr > 0) Adam update in place; returns the loss."""
+        for t, nm in ((params, "params"), (delta, "delta"), (u_p, "u_p"), (target_du, "target_du")):
+            _check_dev(t, torch.float32, None, nm, self.device)
+        if params.numel() != CNN_PARAMS or target_du.numel() != self.batch * self.n ** 3:
+            raise ValueError("bad network input sizes")
+        loss = ctypes.c_double(0.0)
+        self._rc(self.lib.recon_cnn_train_step(self.handle, _ptr(params), _ptr(m), _ptr(v), int(step), float(lr),
+                                               _ptr(delta), _ptr(u_p), _ptr(target_du), ctypes.byref(loss),
+                                               _ptr(grad_out)))
+        return loss.value
 
     def psi(self):
         out = torch.empty((self.batch, 3, self.n, self.n, self.n), dtype=torch.float32, device=self.device)

@@ -1,0 +1,154 @@
+"""Learned-start network on the GPU vs its FP64 oracle (bf16 rounding emulated at the same points)."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import cnn_oracle as C
+from oracle import recon_oracle as O
+from synth import generators as G
+
+pytestmark = pytest.mark.gpu
+
+
+def dev():
+    return torch.device("cuda", 0)
+
+
+def to_dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(dev())
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / np.linalg.norm(b))
+
+
+def sample(n, seed, box=200.0, observer=(37.0, -60.0, 110.0)):
+    rng = np.random.default_rng(seed)
+    delta = O.smooth(rng.standard_normal((n, n, n)), box, 2.0 * box / n).astype(np.float32)
+    u_p = (O.smooth(rng.standard_normal((n, n, n)), box, 2.0 * box / n) * 40).astype(np.float32)
+    target = (-0.15 * u_p + rng.standard_normal((n, n, n)) * 0.2).astype(np.float32)
+    rhat = O.line_of_sight(n, box, (0, 0, 0), observer)
+    return delta, u_p, target, rhat
+
+
+def params(seed):
+    th = C.init_params(seed)
+    th[-1] = 0.05
+    return th.astype(np.float32)
+
+
+@pytest.mark.parametrize("n", [16, 32])
+def test_forward_matches_oracle(gpu_lib, n):
+    from paper_1504_02591_amd import native
+    box, obs = 200.0, (37.0, -60.0, 110.0)
+    delta, u_p, _, rhat = sample(n, 10 + n, box, obs)
+    th = params(3)
+    plan = native.Plan(n, box, obs, 2.0, 0.7, 0.0, randoms=False, cnn=True)
+    du = plan.cnn_forward(to_dev(th), to_dev(delta), to_dev(u_p))[0].cpu().numpy()
+    plan.close()
+    y, _ = C.forward(th.astype(np.float64), delta.astype(np.float64), u_p.astype(np.float64), rhat, bf16_mode=True)
+    e = rel_l2(du, y / C.S_U)
+    print(f"n={n} forward rel L2 {e:.2e}", flush=True)
+    assert e < 1e-3
+
+
+def test_loss_and_gradient_match_oracle(gpu_lib):
+    from paper_1504_02591_amd import native
+    n, box, obs = 16, 200.0, (37.0, -60.0, 110.0)
+    delta, u_p, target, rhat = sample(n, 5, box, obs)
+    th = params(4)
+    plan = native.Plan(n, box, obs, 2.0, 0.7, 0.0, randoms=False, cnn=True)
+    grad = torch.zeros(native.CNN_PARAMS, dtype=torch.float32, device=dev())
+    loss = plan.cnn_train_step(to_dev(th), None, None, 0, 0.0, to_dev(delta), to_dev(u_p), to_dev(target),
+                               grad_out=grad)
+    plan.close()
+    ref_loss, ref_grad = C.loss_and_grad(th.astype(np.float64), delta.astype(np.float64), u_p.astype(np.float64),
+                                         rhat, target.astype(np.float64), bf16_mode=True)
+    g = grad.cpu().numpy()
+    print(f"loss gpu {loss:.6e} oracle {ref_loss:.6e}", flush=True)
+    assert abs(loss - ref_loss) <= 1e-4 * ref_loss
+    off = 0
+    for name, shp in C.SHAPES:
+        size = int(np.prod(shp))
+        e = rel_l2(g[off:off + size], ref_grad[off:off + size])
+        print(f"grad {name}: rel L2 {e:.2e}", flush=True)
+        assert e < 5e-3, name
+        off += size
+
+
+def test_adam_update_gpu(gpu_lib):
+    from paper_1504_02591_amd import native
+    n, box, obs = 16, 200.0, (37.0, -60.0, 110.0)
+    delta, u_p, target, rhat = sample(n, 6, box, obs)
+    th0 = params(5)
+    th = to_dev(th0)
+    m = torch.zeros_like(th)
+    v = torch.zeros_like(th)
+    grad = torch.zeros_like(th)
+    plan = native.Plan(n, box, obs, 2.0, 0.7, 0.0, randoms=False, cnn=True)
+    for step in (1, 2):
+        before = th.cpu().numpy().astype(np.float64)
+        mb, vb = m.cpu().numpy().astype(np.float64), v.cpu().numpy().astype(np.float64)
+        plan.cnn_train_step(th, m, v, step, 1e-3, to_dev(delta), to_dev(u_p), to_dev(target), grad_out=grad)
+        exp, _, _ = C.adam_step(before, mb, vb, grad.cpu().numpy().astype(np.float64), step, 1e-3)
+        np.testing.assert_allclose(th.cpu().numpy(), exp, rtol=1e-5, atol=1e-7)
+    plan.close()
+
+
+def test_training_reduces_loss(gpu_lib):
+    from paper_1504_02591_amd import native
+    n, box, obs = 32, 300.0, (150.0, 150.0, 150.0)
+    delta, u_p, target, _ = sample(n, 7, box, obs)
+    th = to_dev(params(6))
+    m, v = torch.zeros_like(th), torch.zeros_like(th)
+    plan = native.Plan(n, box, obs, 2.0, 0.7, 0.0, randoms=False, cnn=True)
+    d, u, t = to_dev(delta), to_dev(u_p), to_dev(target)
+    first = plan.cnn_train_step(th, m, v, 1, 3e-3, d, u, t)
+    for step in range(2, 201):
+        last = plan.cnn_train_step(th, m, v, step, 3e-3, d, u, t)
+    plan.close()
+    print(f"loss {first:.4e} -> {last:.4e}", flush=True)
+    assert last < 0.3 * first
+
+
+def ffta2_weights(growth, bias):
+    """Weights whose output is exactly the FFTA-2 correction -c u_p (relu(x) - relu(-x) = x)."""
+    beta = growth / bias
+    c = 3 * beta / (7 + 3 * beta)
+    p = C.unpack(np.zeros(C.N_PARAMS))
+    p["W1"][0, 13, 1] = 1.0
+    p["W1"][1, 13, 1] = -1.0
+    p["W2"][0, 13, 0] = 1.0
+    p["W2"][1, 13, 1] = 1.0
+    p["W3"][0, 13, 0] = -c
+    p["W3"][0, 13, 1] = c
+    return C.pack(p)
+
+
+def test_learned_start_end_to_end(gpu_lib):
+    from paper_1504_02591_amd import native
+    cat = G.lattice_box(32, 500.0, (-500.0, 250.0, 250.0), 0.7, 21, 22, ran_factor=3, bias=1.2, smooth_r=20.0)
+    th = params(8)
+    th[:] = 0.5 * th + 0.5 * ffta2_weights(cat.growth, cat.bias).astype(np.float32)
+    for npass in (1, 3):
+        plan = native.plan_for(cat, keep_delta=True, start_buffers=True, cnn=True)
+        gal, ran = to_dev(cat.gal_pos), to_dev(cat.ran_pos)
+        plan.paint(native.GAL, gal)
+        plan.paint(native.RAN, ran)
+        plan.solve(native.START_LEARNED, to_dev(th))
+        rc, iters, eps = plan.iterate(npass, 0.0)
+        psi = plan.psi()[0].cpu().numpy()
+        plan.close()
+        grid_g = O.paint(cat.gal_pos, None, cat.n, cat.box_len, cat.origin)
+        grid_r = O.paint(cat.ran_pos, None, cat.n, cat.box_len, cat.origin)
+        delta = O.overdensity(grid_g, grid_r, cat.box_len, cat.smooth_r, cat.mask_tau)
+        rhat = O.line_of_sight(cat.n, cat.box_len, cat.origin, cat.observer)
+        plain = O.reconstruct_field(delta, cat.box_len, cat.origin, cat.observer, cat.bias, cat.growth, n_passes=0)
+        u_p = np.sum(plain["psi"] * rhat, axis=0)
+        y, _ = C.forward(th.astype(np.float64), C.bf16(delta), u_p, rhat, bf16_mode=True)
+        ref = O.reconstruct_field(delta, cat.box_len, cat.origin, cat.observer, cat.bias, cat.growth,
+                                  n_passes=npass, start=O.START_LEARNED, start_correction=y / C.S_U)
+        e = rel_l2(psi, ref["psi"])
+        print(f"learned start {npass} passes: psi rel L2 {e:.2e}, eps {eps[0]} vs {ref['eps']}", flush=True)
+        assert e < 1e-4
+        np.testing.assert_allclose(eps[0], ref["eps"], rtol=1e-3, atol=1e-5)
