@@ -118,7 +118,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--start", choices=sorted(START_NAMES), default="plain")
+    ap.add_argument("--starts", default="plain,ffta2,learned",
+                    help="comma-separated starts to time; the last one available is the headline value")
+    ap.add_argument("--weights", default=None, help="learned-start parameters (.npz, key 'params')")
     ap.add_argument("--tol", type=float, default=1e-3)
     ap.add_argument("--max-iter", type=int, default=50)
     ap.add_argument("--n", type=int, default=512, help="grid size (512 is the measured workload)")
@@ -148,37 +150,72 @@ def main():
     ran = torch.from_numpy(cat.ran_pos).to(dev)
     disp_g = torch.empty_like(gal)
     disp_r = torch.empty_like(ran)
-    start = START_NAMES[args.start]
-    plan = native.plan_for(cat, start_buffers=start != 0)
-    passes = []
 
-    def step():
-        plan.paint(native.GAL, gal)
-        plan.paint(native.RAN, ran)
-        plan.solve(start)
-        rc, iters, eps = plan.iterate(args.max_iter, args.tol)
-        plan.shift(native.GAL, gal, out_disp=disp_g)
-        plan.shift(native.RAN, ran, out_disp=disp_r)
-        passes.append(iters[0])
-        return eps[0]
+    starts = [s.strip() for s in args.starts.split(",") if s.strip()]
+    for s in starts:
+        if s not in START_NAMES:
+            sys.exit(f"unknown start {s!r}")
+    net, net_half = None, False
+    if "learned" in starts:
+        from paper_1504_02591_amd import learned
+        wpath = args.weights or learned.WEIGHTS
+        if os.path.exists(wpath):
+            with np.load(wpath, allow_pickle=False) as z:
+                net = torch.from_numpy(np.ascontiguousarray(z["params"], dtype=np.float32)).to(dev)
+                net_half = bool(z["half"]) if "half" in z.files else False
+        else:
+            print(f"[bench] no learned-start weights at {wpath}: learned start skipped", file=sys.stderr, flush=True)
+            starts.remove("learned")
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    print(f"[bench] warmup done ({args.warmup} steps, {passes[-1] if passes else 0} passes)", file=sys.stderr,
-          flush=True)
-    passes.clear()
+    def make_plan(start):
+        lrn = start == START_NAMES["learned"]
+        return native.plan_for(cat, start_buffers=start != 0, keep_delta=lrn, cnn=lrn, cnn_half=lrn and net_half)
+
+    def run(plan, start, steps, passes):
+        eps_last = None
+        for _ in range(steps):
+            plan.paint(native.GAL, gal)
+            plan.paint(native.RAN, ran)
+            plan.solve(start, net if start == START_NAMES["learned"] else None)
+            rc, iters, eps = plan.iterate(args.max_iter, args.tol)
+            plan.shift(native.GAL, gal, out_disp=disp_g)
+            plan.shift(native.RAN, ran, out_disp=disp_r)
+            passes.append(iters[0])
+            eps_last = eps[0]
+        return eps_last  # eps history of the last step
+
+    results = {}
+    for name in starts:
+        start = START_NAMES[name]
+        plan = make_plan(start)
+        passes = []
+        run(plan, start, args.warmup, passes)
+        torch.cuda.synchronize()
+        passes.clear()
+        t0 = time.perf_counter()
+        eps_last = run(plan, start, args.steps, passes)
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        plan.close()
+        results[name] = {"passes": passes[-1], "eps": eps_last, "ms_per_step": round(1e3 * elapsed / args.steps, 3),
+                         "recons_per_s": round(args.steps / elapsed, 3), "elapsed": elapsed}
+        print(f"[bench] {name}: {args.steps} steps in {elapsed:.3f}s, {passes[-1]} passes, eps {eps_last[-1]:.3g}",
+              file=sys.stderr, flush=True)
+    head = starts[-1]
+    elapsed = results[head]["elapsed"]
+    passes = [results[head]["passes"]]
+    eps_last = results[head]["eps"]
+
+    # per-kernel event timing: a separate run of the headline start, so the timed run carries no events
+    prof = {}
     if not args.no_profile:
+        start = START_NAMES[head]
+        plan = make_plan(start)
+        run(plan, start, 1, [])
         plan.profile_start()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    eps_last = None
-    for _ in range(args.steps):
-        eps_last = step()
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    prof = {} if args.no_profile else plan.profile_stop()
-    print(f"[bench] timed {args.steps} steps in {elapsed:.3f}s", file=sys.stderr, flush=True)
+        run(plan, start, args.steps, [])
+        prof = plan.profile_stop()
+        plan.close()
 
     ms_per_step = 1e3 * elapsed / max(args.steps, 1)
     value = args.steps / elapsed
@@ -212,7 +249,7 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        p = int(np.median(passes)) if passes else 1
+        p = results["plain"]["passes"] if "plain" in results else passes[-1]
         t_pass, workers = time_oracle_pass(args.n, cat.box_len, cat.observer, cat.bias, cat.growth, 909)
         cpu = {"value": 1.0 / (t_pass * p), "unit": "recons/s", "cores": workers, "kind": "oracle",
                "sample": f"one FP64 oracle correction pass on a {args.n}^3 field ({t_pass:.2f}s, scipy.fft "
@@ -227,15 +264,14 @@ def main():
         "config": {"workload": f"survey-like {args.n}^3 grid over {cat.box_len:g} Mpc/h, observer at the box "
                                f"centre, {n_gal} galaxies in a 2.5 sr cone shell "
                                f"{cat.info['r_min']:g}-{cat.info['r_max']:g} Mpc/h, {n_ran} randoms (50x), "
-                               f"b=2 f=0.74 R=15, {args.start} start to eps<={args.tol:g}",
-                   "n": args.n, "start": args.start, "tol": args.tol, "passes": passes[-1] if passes else None,
-                   "eps": eps_last},
+                               f"b=2 f=0.74 R=15, {head} start to eps<={args.tol:g}",
+                   "n": args.n, "start": head, "tol": args.tol, "passes": passes[-1], "eps": eps_last},
+        "starts": {k: {kk: vv for kk, vv in v.items() if kk != "elapsed"} for k, v in results.items()},
         "roofline": roofline,
         "copy_GBs": round(copy_gbs, 1),
         "cpu_baseline": cpu,
         "stages": stages,
     }
-    plan.close()
     print(json.dumps(out), flush=True)
 
 

@@ -15,6 +15,9 @@ Network (all convolutions periodic, cross-correlation, taps t = (dz+1)*9 + (dy+1
 Training loss: L = mean_p (y - S_U Delta u*)^2.
 Parameter vector (float32 on the device): W1, b1, W2, b2, W3, b3 in that order.
 
+The network may also run on the (n/2)^3 grid (restrict, forward, prolong): coarse
+nodes are every other fine node, r_hat is taken at the coarse nodes.
+
 bf16=True rounds x0, the weights, a1 and a2 to bfloat16 (round to nearest even)
 where the GPU stores them in bfloat16; sums stay in float64.  Parity unpinned
 against the paper (the paper has no network); pinned here against
@@ -132,6 +135,48 @@ def loss_and_grad(theta, delta, u_p, rhat, target_du, bf16_mode=False):
     g["W1"] = conv_weight_grad(d1, c["x0"])
     g["b1"] = d1.sum(axis=(1, 2, 3))
     return loss, pack(g)
+
+
+def restrict(f):
+    """Full-weighting restriction of a periodic node field [..., n, n, n] to [..., n/2, n/2, n/2].
+
+    Coarse node J sits on fine node 2J; per axis the weights are 1/4, 1/2, 1/4 on
+    fine nodes 2J-1, 2J, 2J+1 (the standard multigrid restriction, exact on linear
+    functions and the adjoint of linear prolongation up to the factor 2^-3).
+    """
+    g = np.asarray(f, dtype=np.float64)
+    for ax in (-3, -2, -1):
+        g = 0.25 * np.roll(g, 1, axis=ax) + 0.5 * g + 0.25 * np.roll(g, -1, axis=ax)
+    return g[..., ::2, ::2, ::2]
+
+
+def prolong(c):
+    """Linear prolongation of a periodic node field [..., m, m, m] to [..., 2m, 2m, 2m].
+
+    Fine node 2J copies coarse node J; fine node 2J+1 takes the mean of coarse nodes J and J+1,
+    axis by axis (trilinear interpolation between coarse nodes).
+    """
+    g = np.asarray(c, dtype=np.float64)
+    for ax in (-3, -2, -1):
+        mid = 0.5 * (g + np.roll(g, -1, axis=ax))
+        shape = list(g.shape)
+        shape[ax] *= 2
+        out = np.empty(shape)
+        sl_even = [slice(None)] * g.ndim
+        sl_odd = [slice(None)] * g.ndim
+        sl_even[ax] = slice(0, None, 2)
+        sl_odd[ax] = slice(1, None, 2)
+        out[tuple(sl_even)] = g
+        out[tuple(sl_odd)] = mid
+        g = out
+    return g
+
+
+def half_grid_correction(theta, delta, u_p, rhat_coarse, bf16_mode=False):
+    """Delta u on the fine grid when the network runs on the (n/2)^3 grid: restrict delta_s and
+    u_p, evaluate the network there (r_hat of the coarse nodes), prolong y / S_U."""
+    y, _ = forward(theta, restrict(delta), restrict(u_p), rhat_coarse, bf16_mode)
+    return prolong(y / S_U)
 
 
 def adam_step(theta, m, v, grad, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):

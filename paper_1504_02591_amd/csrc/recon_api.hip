@@ -35,8 +35,9 @@ struct Layout {
          sorted = 0, bcount = 0, bstart = 0, bcursor = 0, bsum = 0, status = 0, tpart = 0;
   // network buffers
   size_t a1 = 0, a2 = 0, d1 = 0, d2 = 0, ybuf = 0, dybuf = 0, upbuf = 0, wk1 = 0, wk2 = 0, wk2t = 0, w3 = 0,
-         part_out = 0, part_w1 = 0, part_w2 = 0, g1 = 0, g2 = 0, g3 = 0, grad = 0, lossp = 0, losst = 0;
+         part_out = 0, part_w1 = 0, part_w2 = 0, g1 = 0, g2 = 0, g3 = 0, grad = 0, lossp = 0, losst = 0, dc = 0, uc = 0;
   long long nb_conv = 0, nb_w = 0, nb_loss = 0;
+  long long cnn_n = 0;
   long long nbins = 0, nscan = 0;
 };
 
@@ -52,9 +53,11 @@ bool valid_params(const recon_params_t* p, std::string* why) {
   if (!(p->growth >= 0.0) || !std::isfinite(p->growth)) return fail("growth must be >= 0 and finite");
   if (!(p->smooth_r >= 0.0) || !std::isfinite(p->smooth_r)) return fail("smooth_r must be >= 0 and finite");
   if (!(p->mask_tau >= 0.0) || !std::isfinite(p->mask_tau)) return fail("mask_tau must be >= 0 and finite");
-  if (p->flags & ~(RECON_NO_RANDOMS | RECON_KEEP_DELTA | RECON_START_BUFFERS | RECON_CNN_BUFFERS))
+  if (p->flags & ~(RECON_NO_RANDOMS | RECON_KEEP_DELTA | RECON_START_BUFFERS | RECON_CNN_BUFFERS | RECON_CNN_HALF))
     return fail("unknown flag");
-  if ((p->flags & RECON_CNN_BUFFERS) && p->n < 16) return fail("the network needs n >= 16");
+  if ((p->flags & RECON_CNN_HALF) && !(p->flags & RECON_CNN_BUFFERS)) return fail("RECON_CNN_HALF needs RECON_CNN_BUFFERS");
+  if ((p->flags & RECON_CNN_BUFFERS) && p->n < ((p->flags & RECON_CNN_HALF) ? 32 : 16))
+    return fail("the network grid needs at least 16^3 cells");
   if (p->max_objects < 0 || p->max_objects >= (1LL << 32)) return fail("max_objects must be in [0, 2^32)");
   return true;
 }
@@ -106,16 +109,22 @@ Layout make_layout(const recon_params_t* p) {
   }
   if (p->flags & RECON_CNN_BUFFERS) {
     using namespace recon::cnn;
-    L.nb_conv = n3 / TPOS;
-    L.nb_w = (n / TY) * (n / TZ);
+    const long long m = (p->flags & RECON_CNN_HALF) ? n / 2 : n, m3 = m * m * m;   // network grid
+    L.cnn_n = m;
+    L.nb_conv = m3 / TPOS;
+    L.nb_w = (m / TY) * (m / TZ);
     L.nb_loss = 1024;
-    L.a1 = take(b * n3 * CH * 2);
-    L.a2 = take(b * n3 * CH * 2);
-    L.d1 = take(b * n3 * CH * 2);
-    L.d2 = take(b * n3 * CH * 2);
-    L.ybuf = take(b * n3 * 4);
-    L.dybuf = take(b * n3 * 4);
+    L.a1 = take(b * m3 * CH * 2);
+    L.a2 = take(b * m3 * CH * 2);
+    L.d1 = take(b * m3 * CH * 2);
+    L.d2 = take(b * m3 * CH * 2);
+    L.ybuf = take(b * m3 * 4);
+    L.dybuf = take(b * m3 * 4);
     L.upbuf = take(b * n3 * 4);
+    if (p->flags & RECON_CNN_HALF) {
+      L.dc = take(b * m3 * 4);
+      L.uc = take(b * m3 * 4);
+    }
     L.wk1 = take(CH * K1P * 2);
     L.wk2 = take(CH * K2 * 2);
     L.wk2t = take(CH * K2 * 2);
@@ -138,12 +147,12 @@ Layout make_layout(const recon_params_t* p) {
 enum KernelId {
   KP_FILL, KP_PAINT, KP_TOTALS, KP_MASK, KP_Z_FWD_GRID, KP_Y_FWD, KP_X_SMOOTH, KP_Y_INV, KP_Z_DELTA, KP_X_START,
   KP_Z_FWD_REAL, KP_Y_FANOUT, KP_Z_ITER, KP_Y_FANIN, KP_X_ITER, KP_REDUCE, KP_Z_FINAL, KP_SHIFT, KP_BIN, KP_SCAN,
-  KP_CNN_FWD, KP_CNN_BWD, KP_COUNT
+  KP_CNN_FWD, KP_CNN_BWD, KP_RESAMPLE, KP_COUNT
 };
 const char* const kKernelNames[KP_COUNT] = {
     "fill", "paint", "totals", "mask", "z_fwd_grid", "y_fwd", "x_smooth", "y_inv", "z_delta", "x_start",
     "z_fwd_real", "y_fanout", "z_iter", "y_fanin", "x_iter", "reduce", "z_final", "shift", "bin", "scan",
-    "cnn_fwd", "cnn_bwd"};
+    "cnn_fwd", "cnn_bwd", "resample"};
 
 struct Profiler {
   bool on = false;
@@ -178,7 +187,10 @@ struct recon_plan_s {
   unsigned short *a1 = nullptr, *a2 = nullptr, *d1 = nullptr, *d2 = nullptr, *wk1 = nullptr, *wk2 = nullptr,
                  *wk2t = nullptr;
   float *ybuf = nullptr, *dybuf = nullptr, *upbuf = nullptr, *w3 = nullptr, *part_out = nullptr,
-        *part_w1 = nullptr, *part_w2 = nullptr, *g1 = nullptr, *g2 = nullptr, *g3 = nullptr, *gradbuf = nullptr;
+        *part_w1 = nullptr, *part_w2 = nullptr, *g1 = nullptr, *g2 = nullptr, *g3 = nullptr, *gradbuf = nullptr,
+        *dc = nullptr, *uc = nullptr;
+  int cnn_n = 0;                 // network grid: n, or n/2 with RECON_CNN_HALF
+  long long cnn_n3 = 0;
   double *lossp = nullptr, *losst = nullptr;
   const float* net = nullptr;
   unsigned *bcount = nullptr, *bstart = nullptr, *bcursor = nullptr, *bsum = nullptr;
@@ -479,12 +491,30 @@ int upload_mask(recon_plan_t* pl, int* dev, std::vector<int>& host) {
   return RECON_OK;
 }
 
-recon::cnn::Geo3 cnn_geo(const recon_plan_t* pl) {
+// Node geometry of the fine grid (level 0) or of the network grid (every (n / cnn_n)-th node).
+recon::cnn::Geo3 grid_geo(const recon_plan_t* pl, bool network) {
   recon::cnn::Geo3 g;
-  g.n = pl->n;
-  g.hs = pl->geo.hs;
+  const int step = network ? pl->n / pl->cnn_n : 1;
+  g.n = pl->n / step;
+  g.hs = pl->geo.hs * (float)step;
   for (int a = 0; a < 3; ++a) g.ds[a] = pl->geo.ds[a];
   return g;
+}
+recon::cnn::Geo3 cnn_geo(const recon_plan_t* pl) { return grid_geo(pl, true); }
+
+int restrict_impl(recon_plan_t* pl, const float* fine, float* coarse) {
+  const long long m = pl->n / 2;
+  PROF(pl, KP_RESAMPLE);
+  recon::cnn::k_restrict<<<dim3((unsigned)((m * m * m + 255) / 256), pl->batch), 256, 0, pl->stream>>>(fine, pl->n,
+                                                                                                      coarse);
+  return check_launch(pl, "restriction");
+}
+
+int prolong_impl(recon_plan_t* pl, const float* coarse, float scale, float* fine) {
+  PROF(pl, KP_RESAMPLE);
+  recon::cnn::k_prolong<<<dim3((unsigned)((pl->n3 + 255) / 256), pl->batch), 256, 0, pl->stream>>>(coarse, pl->n,
+                                                                                                  scale, fine);
+  return check_launch(pl, "prolongation");
 }
 
 // Network forward on the plan's batch; out = scale * y.
@@ -588,6 +618,12 @@ int recon_plan(recon_plan_t** out, const recon_params_t* params, void* workspace
     pl->ybuf = (float*)(w + L.ybuf);
     pl->dybuf = (float*)(w + L.dybuf);
     pl->upbuf = (float*)(w + L.upbuf);
+    pl->cnn_n = (int)L.cnn_n;
+    pl->cnn_n3 = L.cnn_n * L.cnn_n * L.cnn_n;
+    if (params->flags & RECON_CNN_HALF) {
+      pl->dc = (float*)(w + L.dc);
+      pl->uc = (float*)(w + L.uc);
+    }
     pl->wk1 = (unsigned short*)(w + L.wk1);
     pl->wk2 = (unsigned short*)(w + L.wk2);
     pl->wk2t = (unsigned short*)(w + L.wk2t);
@@ -806,7 +842,15 @@ int recon_solve(recon_plan_t* pl, int start, const void* net) {
     // u_p = Psi_p . r_hat from the fanned-out start, then Delta u = network(delta_s, u_p) into corr
     RECON_TRY(ops->fanout(pl, nullptr));
     RECON_TRY(ops->zfinal(pl, nullptr, pl->upbuf, false, nullptr));
-    RECON_TRY(cnn_forward_impl(pl, (const float*)net, pl->delta, pl->upbuf, pl->corr, 1.0f / recon::cnn::S_U));
+    if (pl->dc) {
+      // network on the (n/2)^3 grid: restrict the inputs, prolong its output
+      RECON_TRY(restrict_impl(pl, pl->delta, pl->dc));
+      RECON_TRY(restrict_impl(pl, pl->upbuf, pl->uc));
+      RECON_TRY(cnn_forward_impl(pl, (const float*)net, pl->dc, pl->uc, pl->ybuf, 1.0f / recon::cnn::S_U));
+      RECON_TRY(prolong_impl(pl, pl->ybuf, 1.0f, pl->corr));
+    } else {
+      RECON_TRY(cnn_forward_impl(pl, (const float*)net, pl->delta, pl->upbuf, pl->corr, 1.0f / recon::cnn::S_U));
+    }
     for (int b = 0; b < pl->batch; ++b) pl->st_y[b] = 1;
   }
   pl->state = ST_SOLVED;
@@ -1015,7 +1059,7 @@ int recon_cnn_train_step(recon_plan_t* pl, float* params, float* adam_m, float* 
   if (!pl->a1) return fail(pl, RECON_EINVAL, "plan was created without RECON_CNN_BUFFERS");
   if (!params || !delta || !u_p || !target_du) return fail(pl, RECON_EINVAL, "NULL pointer");
   if (lr > 0.f && (!adam_m || !adam_v || step < 1)) return fail(pl, RECON_EINVAL, "Adam needs moments and step >= 1");
-  const long long count = pl->n3 * pl->batch;
+  const long long count = pl->cnn_n3 * pl->batch;
   RECON_TRY(cnn_forward_impl(pl, params, delta, u_p, pl->ybuf, 1.0f));
   const dim3 grid((unsigned)pl->L.nb_conv, pl->batch);
   const dim3 gridw((unsigned)pl->L.nb_w, pl->batch);
@@ -1056,8 +1100,20 @@ int recon_get_radial(recon_plan_t* pl, float* u_out) {
     if (!pl->psi_valid[b]) return fail(pl, RECON_ESTATE, "displacement not computed; call iterate");
   long long blocks = (pl->n3 * pl->batch + 255) / 256;
   if (blocks > 65536) blocks = 65536;
-  recon::cnn::k_radial<<<(unsigned)blocks, 256, 0, pl->stream>>>(pl->psi, cnn_geo(pl), pl->batch, u_out);
+  recon::cnn::k_radial<<<(unsigned)blocks, 256, 0, pl->stream>>>(pl->psi, grid_geo(pl, false), pl->batch, u_out);
   return check_launch(pl, "radial component");
+}
+
+int recon_restrict(recon_plan_t* pl, const float* fine, float* coarse) {
+  if (!pl) return RECON_EINVAL;
+  if (!fine || !coarse) return fail(pl, RECON_EINVAL, "NULL pointer");
+  return restrict_impl(pl, fine, coarse);
+}
+
+int recon_prolong(recon_plan_t* pl, const float* coarse, float* fine) {
+  if (!pl) return RECON_EINVAL;
+  if (!coarse || !fine) return fail(pl, RECON_EINVAL, "NULL pointer");
+  return prolong_impl(pl, coarse, 1.0f, fine);
 }
 
 int recon_profile_start(recon_plan_t* pl) {

@@ -412,5 +412,51 @@ __global__ void __launch_bounds__(256) k_radial(const float4* __restrict__ psi4,
   }
 }
 
+// Full-weighting restriction of a periodic n^3 node field to (n/2)^3: coarse node J sits on fine
+// node 2J, weights 1/4, 1/2, 1/4 per axis on fine nodes 2J-1, 2J, 2J+1.  One thread per coarse
+// node, blockIdx.y = realisation.
+__global__ void __launch_bounds__(256) k_restrict(const float* __restrict__ fine, int n, float* __restrict__ coarse) {
+  const int m = n >> 1, msk = n - 1;
+  const long long mc = (long long)m * m * m;
+  const long long i = blockIdx.x * 256LL + threadIdx.x;
+  if (i >= mc) return;
+  const int X = (int)(i % m), Y = (int)((i / m) % m), Z = (int)(i / ((long long)m * m));
+  const float* f = fine + (long long)blockIdx.y * n * n * n;
+  const float w[3] = {0.25f, 0.5f, 0.25f};
+  float acc = 0.f;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const long long z = (2 * Z + c - 1) & msk;
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      const long long row = (z * n + ((2 * Y + b - 1) & msk)) * n;
+      float r = 0.f;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) r = fmaf(w[a], f[row + ((2 * X + a - 1) & msk)], r);
+      acc = fmaf(w[c] * w[b], r, acc);
+    }
+  }
+  coarse[(long long)blockIdx.y * mc + i] = acc;
+}
+
+// Linear prolongation of a periodic (n/2)^3 node field to n^3, times scale: fine node 2J copies
+// coarse node J, fine node 2J+1 takes the mean of coarse J and J+1, axis by axis.
+__global__ void __launch_bounds__(256) k_prolong(const float* __restrict__ coarse, int n, float scale,
+                                                 float* __restrict__ fine) {
+  const int m = n >> 1, mm = m - 1;
+  const long long n3 = (long long)n * n * n;
+  const long long i = blockIdx.x * 256LL + threadIdx.x;
+  if (i >= n3) return;
+  const int x = (int)(i % n), y = (int)((i / n) % n), z = (int)(i / ((long long)n * n));
+  const float* c = coarse + (long long)blockIdx.y * m * m * m;
+  const int x0 = x >> 1, y0 = y >> 1, z0 = z >> 1;
+  const int x1 = (x0 + (x & 1)) & mm, y1 = (y0 + (y & 1)) & mm, z1 = (z0 + (z & 1)) & mm;
+  const long long r00 = ((long long)z0 * m + y0) * m, r01 = ((long long)z0 * m + y1) * m,
+                  r10 = ((long long)z1 * m + y0) * m, r11 = ((long long)z1 * m + y1) * m;
+  const float v = 0.125f * ((c[r00 + x0] + c[r00 + x1]) + (c[r01 + x0] + c[r01 + x1]) +
+                            (c[r10 + x0] + c[r10 + x1]) + (c[r11 + x0] + c[r11 + x1]));
+  fine[(long long)blockIdx.y * n3 + i] = scale * v;
+}
+
 }  // namespace cnn
 }  // namespace recon

@@ -1,0 +1,178 @@
+"""Training and evaluation of the learned starting displacement (recon_cnn.h).
+
+Targets come from the reconstruction itself: for each synthetic survey
+realisation the plain start is iterated to a tight tolerance on the GPU, and the
+network learns the radial correction Delta u* = u_inf - u_p between the
+converged and the plain-start radial displacement.  Training runs entirely in
+the library's own kernels (recon_cnn_train_step: forward, backward and Adam).
+
+By default the network runs on the (n/2)^3 grid (RECON_CNN_HALF): training
+realisations are survey-like catalogues of the 512^3 workload's geometry, solved
+at 512^3, and delta_s, u_p and the target are restricted to the 256^3 network
+grid; inference restricts the 512^3 inputs the same way and prolongs Delta u.
+With --fine the network runs on the solver grid itself.  Test realisations use
+other seeds.
+
+    python -m paper_1504_02591_amd.learned --train 64 --steps 1500 --out weights.npz
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import multiprocessing as mp
+import os
+import sys
+import time
+
+import numpy as np
+import torch
+
+from . import native
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data", "learned_start.npz")
+TRAIN_SEED, TEST_SEED = 50000, 60000
+
+
+def _catalogue(args):
+    from synth import generators as G
+    i, train, n = args
+    base = TRAIN_SEED if train else TEST_SEED
+    cat = G.config2(n=n, scale=n / 512.0, seeds=(base + 3 * i, base + 3 * i + 1, base + 3 * i + 2))
+    return cat
+
+
+def catalogue_pool(workers):
+    """Worker processes for host-side catalogue generation; create before the GPU is touched."""
+    return mp.get_context("fork").Pool(workers)
+
+
+def targets(cat, half=True, tol=1e-6, max_iter=200):
+    """(delta_s, u_p, Delta u*, passes) for one catalogue on the network grid, from the plain start
+    iterated to tol on the GPU; with half=True the fields are restricted to the (n/2)^3 grid."""
+    dev = torch.device("cuda", torch.cuda.current_device())
+    plan = native.plan_for(cat, keep_delta=True)
+    gal = torch.from_numpy(cat.gal_pos).to(dev)
+    ran = torch.from_numpy(cat.ran_pos).to(dev)
+    plan.paint(native.GAL, gal)
+    plan.paint(native.RAN, ran)
+    del gal, ran
+    plan.solve(native.START_PLAIN)
+    plan.iterate(0, 0.0)
+    u_p = plan.radial()
+    rc, iters, eps = plan.iterate(max_iter, tol)
+    u_inf = plan.radial()
+    delta = plan.delta()
+    if half:
+        delta, u_p, u_inf = plan.restrict(delta), plan.restrict(u_p), plan.restrict(u_inf)
+    plan.close()
+    return delta[0].clone(), u_p[0].clone(), (u_inf - u_p)[0].clone(), iters[0]
+
+
+def init_params(seed=0):
+    """He-style random weights (float32), layout W1, b1, W2, b2, W3, b3."""
+    rng = np.random.default_rng(seed)
+    w1 = rng.standard_normal((16, 27, 8)) * np.sqrt(2.0 / (27 * 5))
+    w1[:, :, 5:] = 0.0
+    w2 = rng.standard_normal((16, 27, 16)) * np.sqrt(2.0 / (27 * 16))
+    w3 = rng.standard_normal((1, 27, 16)) * np.sqrt(1.0 / (27 * 16))
+    th = np.concatenate([w1.ravel(), np.zeros(16), w2.ravel(), np.zeros(16), w3.ravel(), np.zeros(1)])
+    assert th.size == native.CNN_PARAMS
+    return th.astype(np.float32)
+
+
+def train(data, geom, steps, lr, seed=0, log_every=50, params=None, state=None, half=True):
+    """Adam on single realisations drawn at random; cosine learning-rate decay.  Returns (params, state, log)."""
+    dev = torch.device("cuda", torch.cuda.current_device())
+    m = data[0][0].shape[-1]
+    plan = native.Plan(2 * m if half else m, geom["box_len"], geom["observer"], geom["bias"], geom["growth"],
+                       geom["smooth_r"], origin=geom["origin"], randoms=False, cnn=True, cnn_half=half)
+    th = torch.from_numpy(init_params(seed) if params is None else params).to(dev)
+    m = torch.zeros_like(th) if state is None else torch.from_numpy(state["m"]).to(dev)
+    v = torch.zeros_like(th) if state is None else torch.from_numpy(state["v"]).to(dev)
+    step0 = 0 if state is None else int(state["step"])
+    rng = np.random.default_rng(seed + 1000 + step0)
+    log = []
+    for s in range(step0 + 1, step0 + steps + 1):
+        k = int(rng.integers(len(data)))
+        d, u, t = data[k][:3]
+        frac = (s - step0 - 1) / max(steps - 1, 1)
+        rate = lr * 0.5 * (1.0 + np.cos(np.pi * frac))
+        loss = plan.cnn_train_step(th, m, v, s, rate, d, u, t)
+        if s % log_every == 0 or s == step0 + 1:
+            log.append((s, loss))
+            print(f"[train] step {s} loss {loss:.5e} lr {rate:.2e}", flush=True)
+    plan.close()
+    state = {"m": m.cpu().numpy(), "v": v.cpu().numpy(), "step": step0 + steps}
+    return th.cpu().numpy(), state, log
+
+
+def passes_to_tol(cat, start, params=None, tol=1e-3, max_iter=60, half=True):
+    dev = torch.device("cuda", torch.cuda.current_device())
+    lrn = start == native.START_LEARNED
+    plan = native.plan_for(cat, keep_delta=lrn, start_buffers=start != native.START_PLAIN, cnn=lrn,
+                           cnn_half=lrn and half)
+    gal = torch.from_numpy(cat.gal_pos).to(dev)
+    ran = torch.from_numpy(cat.ran_pos).to(dev)
+    plan.paint(native.GAL, gal)
+    plan.paint(native.RAN, ran)
+    plan.solve(start, None if params is None else torch.from_numpy(params).to(dev))
+    rc, iters, eps = plan.iterate(max_iter, tol)
+    plan.close()
+    return iters[0], eps[0]
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--train", type=int, default=64, help="training realisations")
+    ap.add_argument("--test", type=int, default=3, help="held-out realisations")
+    ap.add_argument("--steps", type=int, default=1500)
+    ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--n", type=int, default=512, help="solver grid of the realisations")
+    ap.add_argument("--fine", action="store_true", help="network on the solver grid instead of (n/2)^3")
+    ap.add_argument("--workers", type=int, default=8, help="catalogue generation processes")
+    ap.add_argument("--out", default=WEIGHTS)
+    ap.add_argument("--seed", type=int, default=0)
+    args = ap.parse_args()
+    half = not args.fine
+    pool = catalogue_pool(args.workers)          # forked before the GPU is initialised
+    torch.cuda.set_device(0)
+    t0 = time.time()
+    data, geom, passes = [], None, []
+    for k, cat in enumerate(pool.imap(_catalogue, [(i, True, args.n) for i in range(args.train)])):
+        if geom is None:
+            geom = dict(box_len=cat.box_len, observer=cat.observer, bias=cat.bias, growth=cat.growth,
+                        smooth_r=cat.smooth_r, origin=cat.origin)
+        d = targets(cat, half)
+        data.append(d[:3])
+        passes.append(d[3])
+        if (k + 1) % 8 == 0:
+            print(f"[train] {k + 1} targets after {time.time() - t0:.1f}s; plain passes to 1e-6: {passes[-8:]}",
+                  flush=True)
+    tests = list(pool.imap(_catalogue, [(i, False, args.n) for i in range(args.test)]))
+    pool.close()
+    pool.join()
+    t0 = time.time()
+    params, state, log = train(data, geom, args.steps, args.lr, args.seed, half=half)
+    t_train = time.time() - t0
+    print(f"[train] {args.steps} steps in {t_train:.1f}s", flush=True)
+    del data
+    torch.cuda.empty_cache()
+    res = {"plain": [], "ffta2": [], "learned": []}
+    for c in tests:
+        res["plain"].append(passes_to_tol(c, native.START_PLAIN)[0])
+        res["ffta2"].append(passes_to_tol(c, native.START_FFTA2)[0])
+        res["learned"].append(passes_to_tol(c, native.START_LEARNED, params, half=half)[0])
+    print("[train] held-out passes to 1e-3:", json.dumps(res), flush=True)
+    os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
+    np.savez(args.out, params=params, adam_m=state["m"], adam_v=state["v"], step=state["step"],
+             loss=np.array(log, dtype=np.float64), seed=args.seed, train=args.train, n=args.n, half=half,
+             eval=json.dumps(res))
+    print(json.dumps({"out": args.out, "train_seconds": t_train, "final_loss": log[-1][1], "eval": res}), flush=True)
+
+
+if __name__ == "__main__":
+    main()

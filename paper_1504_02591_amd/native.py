@@ -20,7 +20,7 @@ RECON_OK, RECON_NOTCONVERGED = 0, 1
 RECON_EINVAL, RECON_ENOMEM, RECON_EDEVICE, RECON_ESTATE, RECON_EDIVERGED = -1, -2, -3, -4, -5
 GAL, RAN = 0, 1
 START_PLAIN, START_FFTA1, START_FFTA2, START_LEARNED = 0, 1, 2, 3
-NO_RANDOMS, KEEP_DELTA, START_BUFFERS, CNN_BUFFERS = 1, 2, 4, 8
+NO_RANDOMS, KEEP_DELTA, START_BUFFERS, CNN_BUFFERS, CNN_HALF = 1, 2, 4, 8, 16
 CNN_PARAMS = 10833
 PAINT_ACCUMULATE = 1
 
@@ -28,7 +28,7 @@ EXPORTED = ("recon_workspace_bytes", "recon_plan", "recon_paint", "recon_solve",
             "recon_shift", "recon_get_psi", "recon_get_grid", "recon_get_delta", "recon_set_delta",
             "recon_destroy", "recon_strerror", "recon_last_error", "recon_profile_start",
             "recon_profile_stop", "recon_profile_kernel_name", "recon_cnn_forward", "recon_cnn_train_step",
-            "recon_get_radial")
+            "recon_get_radial", "recon_restrict", "recon_prolong")
 
 
 class ReconError(RuntimeError):
@@ -82,11 +82,13 @@ def load(path=None):
     lib.recon_cnn_train_step.argtypes = [vp, vp, vp, vp, ctypes.c_int, ctypes.c_float, vp, vp, vp,
                                          ctypes.POINTER(dbl), vp]
     lib.recon_get_radial.argtypes = [vp, vp]
+    lib.recon_restrict.argtypes = [vp, vp, vp]
+    lib.recon_prolong.argtypes = [vp, vp, vp]
     lib.recon_profile_start.argtypes = [vp]
     lib.recon_profile_stop.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(dbl), ctypes.c_int]
     lib.recon_profile_kernel_name.argtypes = [ctypes.c_int]
     lib.recon_profile_kernel_name.restype = ctypes.c_char_p
-    for name in ("recon_cnn_forward", "recon_cnn_train_step", "recon_get_radial",
+    for name in ("recon_cnn_forward", "recon_cnn_train_step", "recon_get_radial", "recon_restrict", "recon_prolong",
                  "recon_profile_start", "recon_profile_stop", "recon_plan", "recon_paint", "recon_solve", "recon_iterate", "recon_shift",
                  "recon_get_psi", "recon_get_grid", "recon_get_delta", "recon_set_delta"):
         getattr(lib, name).restype = ctypes.c_int
@@ -115,11 +117,11 @@ class Plan:
 
     def __init__(self, n, box_len, observer, bias, growth, smooth_r, origin=(0.0, 0.0, 0.0), batch=1,
                  mask_tau=0.1, randoms=True, keep_delta=False, start_buffers=False, max_objects=0, cnn=False,
-                 device=None):
+                 cnn_half=False, device=None):
         self.lib = load()
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
         flags = (0 if randoms else NO_RANDOMS) | (KEEP_DELTA if keep_delta else 0) | \
-                (START_BUFFERS if start_buffers else 0) | (CNN_BUFFERS if cnn else 0)
+                (START_BUFFERS if start_buffers else 0) | (CNN_BUFFERS if cnn else 0) | (CNN_HALF if cnn_half else 0)
         p = Params()
         p.n, p.batch, p.box_len = int(n), int(batch), float(box_len)
         for a in range(3):
@@ -130,6 +132,7 @@ class Plan:
         p.max_objects = int(max_objects)
         self.params = p
         self.n, self.batch, self.randoms = int(n), int(batch), randoms
+        self.cnn_n = self.n // 2 if cnn_half else self.n     # network grid
         nbytes = self.lib.recon_workspace_bytes(ctypes.byref(p))
         if nbytes == 0:
             raise ReconError(RECON_EINVAL, "invalid parameters")
@@ -228,13 +231,33 @@ class Plan:
         self._rc(self.lib.recon_get_radial(self.handle, _ptr(out)))
         return out
 
+    def restrict(self, fine):
+        """Full-weighting restriction [batch, n, n, n] -> [batch, n/2, n/2, n/2]."""
+        _check_dev(fine, torch.float32, None, "fine", self.device)
+        if fine.numel() != self.batch * self.n ** 3:
+            raise ValueError("fine must hold batch * n^3 values")
+        m = self.n // 2
+        out = torch.empty((self.batch, m, m, m), dtype=torch.float32, device=self.device)
+        self._rc(self.lib.recon_restrict(self.handle, _ptr(fine), _ptr(out)))
+        return out
+
+    def prolong(self, coarse):
+        """Linear prolongation [batch, n/2, n/2, n/2] -> [batch, n, n, n]."""
+        _check_dev(coarse, torch.float32, None, "coarse", self.device)
+        if coarse.numel() != self.batch * (self.n // 2) ** 3:
+            raise ValueError("coarse must hold batch * (n/2)^3 values")
+        out = torch.empty((self.batch, self.n, self.n, self.n), dtype=torch.float32, device=self.device)
+        self._rc(self.lib.recon_prolong(self.handle, _ptr(coarse), _ptr(out)))
+        return out
+
     def cnn_forward(self, params, delta, u_p):
-        """Learned radial correction Delta u for every cell, [batch, n, n, n]."""
+        """Learned radial correction Delta u on the network grid, [batch, m, m, m]."""
         for t, nm in ((params, "params"), (delta, "delta"), (u_p, "u_p")):
             _check_dev(t, torch.float32, None, nm, self.device)
-        if params.numel() != CNN_PARAMS or delta.numel() != self.batch * self.n ** 3 or u_p.numel() != delta.numel():
+        m = self.cnn_n
+        if params.numel() != CNN_PARAMS or delta.numel() != self.batch * m ** 3 or u_p.numel() != delta.numel():
             raise ValueError("bad network input sizes")
-        out = torch.empty((self.batch, self.n, self.n, self.n), dtype=torch.float32, device=self.device)
+        out = torch.empty((self.batch, m, m, m), dtype=torch.float32, device=self.device)
         self._rc(self.lib.recon_cnn_forward(self.handle, _ptr(params), _ptr(delta), _ptr(u_p), _ptr(out)))
         return out
 
@@ -242,7 +265,8 @@ class Plan:
         """One loss/gradient evaluation and (lr > 0) Adam update in place; returns the loss."""
         for t, nm in ((params, "params"), (delta, "delta"), (u_p, "u_p"), (target_du, "target_du")):
             _check_dev(t, torch.float32, None, nm, self.device)
-        if params.numel() != CNN_PARAMS or target_du.numel() != self.batch * self.n ** 3:
+        m3 = self.batch * self.cnn_n ** 3
+        if params.numel() != CNN_PARAMS or any(t.numel() != m3 for t in (delta, u_p, target_du)):
             raise ValueError("bad network input sizes")
         loss = ctypes.c_double(0.0)
         self._rc(self.lib.recon_cnn_train_step(self.handle, _ptr(params), _ptr(m), _ptr(v), int(step), float(lr),

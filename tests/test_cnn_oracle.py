@@ -83,3 +83,52 @@ def test_parameter_layout():
     assert C.N_PARAMS == 16 * 27 * 8 + 16 + 16 * 27 * 16 + 16 + 27 * 16 + 1
     theta = np.arange(C.N_PARAMS, dtype=np.float64)
     np.testing.assert_array_equal(C.pack(C.unpack(theta)), theta)
+
+
+def test_restriction_of_cosines_has_closed_form():
+    # per axis: R cos(theta i) at node 2J = cos(2 theta J) cos^2(theta / 2)
+    n = 16
+    i = np.arange(n)
+    kx, ky, kz = 1, 3, 5
+    th = 2 * np.pi * np.array([kx, ky, kz]) / n
+    f = (np.cos(th[2] * i)[:, None, None] * np.cos(th[1] * i)[None, :, None] * np.cos(th[0] * i)[None, None, :])
+    j = np.arange(n // 2)
+    ref = (np.cos(2 * th[2] * j)[:, None, None] * np.cos(2 * th[1] * j)[None, :, None]
+           * np.cos(2 * th[0] * j)[None, None, :]) * np.prod(np.cos(th / 2) ** 2)
+    np.testing.assert_allclose(C.restrict(f), ref, atol=1e-13)
+    np.testing.assert_allclose(C.restrict(np.full((n, n, n), 2.5)), 2.5, atol=1e-14)
+
+
+def test_prolongation_of_cosines_has_closed_form():
+    # per axis: fine 2J -> cos(phi J); fine 2J+1 -> cos(phi (J + 1/2)) cos(phi / 2)
+    m = 8
+    j = np.arange(m)
+    phi = 2 * np.pi * np.array([2, 1, 3]) / m
+
+    def axis(p):
+        out = np.empty(2 * m)
+        out[0::2] = np.cos(p * j)
+        out[1::2] = np.cos(p * (j + 0.5)) * np.cos(p / 2)
+        return out
+
+    c = np.cos(phi[2] * j)[:, None, None] * np.cos(phi[1] * j)[None, :, None] * np.cos(phi[0] * j)[None, None, :]
+    ref = axis(phi[2])[:, None, None] * axis(phi[1])[None, :, None] * axis(phi[0])[None, None, :]
+    np.testing.assert_allclose(C.prolong(c), ref, atol=1e-13)
+
+
+def test_restriction_is_scaled_adjoint_of_prolongation():
+    rng = np.random.default_rng(8)
+    f = rng.standard_normal((12, 12, 12))
+    g = rng.standard_normal((6, 6, 6))
+    lhs = 8.0 * np.sum(C.restrict(f) * g)
+    rhs = np.sum(f * C.prolong(g))
+    assert abs(lhs - rhs) < 1e-10 * abs(rhs)
+
+
+def test_prolongation_then_restriction_of_smooth_field_is_close():
+    # full weighting of a linear interpolant keeps coarse nodes to second order in k h
+    m = 16
+    j = np.arange(m)
+    c = np.sin(2 * np.pi * j / m)[None, None, :] * np.ones((m, m, 1))
+    rp = C.restrict(C.prolong(c))
+    assert np.max(np.abs(rp - c)) < (2 * np.pi / m) ** 2

@@ -152,3 +152,48 @@ def test_learned_start_end_to_end(gpu_lib):
         print(f"learned start {npass} passes: psi rel L2 {e:.2e}, eps {eps[0]} vs {ref['eps']}", flush=True)
         assert e < 1e-4
         np.testing.assert_allclose(eps[0], ref["eps"], rtol=1e-3, atol=1e-5)
+
+
+def test_restrict_and_prolong_match_oracle(gpu_lib):
+    from paper_1504_02591_amd import native
+    n, b = 32, 2
+    rng = np.random.default_rng(11)
+    f = rng.standard_normal((b, n, n, n)).astype(np.float32)
+    c = rng.standard_normal((b, n // 2, n // 2, n // 2)).astype(np.float32)
+    plan = native.Plan(n, 100.0, (0.0, 0.0, 0.0), 1.0, 0.5, 0.0, batch=b, randoms=False)
+    rc = plan.restrict(to_dev(f)).cpu().numpy()
+    pc = plan.prolong(to_dev(c)).cpu().numpy()
+    plan.close()
+    for i in range(b):
+        np.testing.assert_allclose(rc[i], C.restrict(f[i]), rtol=0, atol=2e-6)
+        np.testing.assert_allclose(pc[i], C.prolong(c[i]), rtol=0, atol=1e-6)
+
+
+@pytest.mark.parametrize("n", [32, 64])
+def test_learned_start_half_grid_end_to_end(gpu_lib, n):
+    from paper_1504_02591_amd import native
+    cat = G.lattice_box(n, 500.0, (-500.0, 250.0, 250.0), 0.7, 23, 24, ran_factor=3, bias=1.2, smooth_r=20.0)
+    th = params(9)
+    th[:] = 0.5 * th + 0.5 * ffta2_weights(cat.growth, cat.bias).astype(np.float32)
+    plan = native.plan_for(cat, keep_delta=True, start_buffers=True, cnn=True, cnn_half=True)
+    gal, ran = to_dev(cat.gal_pos), to_dev(cat.ran_pos)
+    plan.paint(native.GAL, gal)
+    plan.paint(native.RAN, ran)
+    plan.solve(native.START_LEARNED, to_dev(th))
+    rc, iters, eps = plan.iterate(2, 0.0)
+    psi = plan.psi()[0].cpu().numpy()
+    plan.close()
+    grid_g = O.paint(cat.gal_pos, None, cat.n, cat.box_len, cat.origin)
+    grid_r = O.paint(cat.ran_pos, None, cat.n, cat.box_len, cat.origin)
+    delta = O.overdensity(grid_g, grid_r, cat.box_len, cat.smooth_r, cat.mask_tau)
+    rhat = O.line_of_sight(cat.n, cat.box_len, cat.origin, cat.observer)
+    rhat_c = O.line_of_sight(cat.n // 2, cat.box_len, cat.origin, cat.observer)
+    plain = O.reconstruct_field(delta, cat.box_len, cat.origin, cat.observer, cat.bias, cat.growth, n_passes=0)
+    u_p = np.sum(plain["psi"] * rhat, axis=0)
+    du = C.half_grid_correction(th.astype(np.float64), delta, u_p, rhat_c, bf16_mode=True)
+    ref = O.reconstruct_field(delta, cat.box_len, cat.origin, cat.observer, cat.bias, cat.growth,
+                              n_passes=2, start=O.START_LEARNED, start_correction=du)
+    e = rel_l2(psi, ref["psi"])
+    print(f"n={n} half-grid learned start: psi rel L2 {e:.2e}, eps {eps[0]} vs {ref['eps']}", flush=True)
+    assert e < 1e-4
+    np.testing.assert_allclose(eps[0], ref["eps"], rtol=1e-3, atol=1e-5)
