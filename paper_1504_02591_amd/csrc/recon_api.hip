@@ -35,7 +35,8 @@ struct Layout {
          sorted = 0, bcount = 0, bstart = 0, bcursor = 0, bsum = 0, status = 0, tpart = 0;
   // network buffers
   size_t a1 = 0, a2 = 0, d1 = 0, d2 = 0, ybuf = 0, dybuf = 0, upbuf = 0, wk1 = 0, wk2 = 0, wk2t = 0, w3 = 0,
-         part_out = 0, part_w1 = 0, part_w2 = 0, g1 = 0, g2 = 0, g3 = 0, grad = 0, lossp = 0, losst = 0, dc = 0, uc = 0;
+         part_out = 0, part_w1 = 0, part_w2 = 0, g1 = 0, g2 = 0, g3 = 0, grad = 0, lossp = 0, losst = 0, dc = 0, uc = 0,
+         wf1 = 0, wf2 = 0;
   long long nb_conv = 0, nb_w = 0, nb_loss = 0;
   long long cnn_n = 0;
   long long nbins = 0, nscan = 0;
@@ -129,6 +130,8 @@ Layout make_layout(const recon_params_t* p) {
     L.wk2 = take(CH * K2 * 2);
     L.wk2t = take(CH * K2 * 2);
     L.w3 = take(K2 * 4);
+    L.wf1 = take(9 * 64 * 16);
+    L.wf2 = take(9 * 2 * 64 * 16);
     L.part_out = take((size_t)b * L.nb_conv * (K2 + 1) * 4);
     L.part_w1 = take((size_t)b * L.nb_w * CH * (K1P + 1) * 4);
     L.part_w2 = take((size_t)b * L.nb_w * CH * (K2 + 1) * 4);
@@ -189,6 +192,7 @@ struct recon_plan_s {
   float *ybuf = nullptr, *dybuf = nullptr, *upbuf = nullptr, *w3 = nullptr, *part_out = nullptr,
         *part_w1 = nullptr, *part_w2 = nullptr, *g1 = nullptr, *g2 = nullptr, *g3 = nullptr, *gradbuf = nullptr,
         *dc = nullptr, *uc = nullptr;
+  uint4 *wf1 = nullptr, *wf2 = nullptr;
   int cnn_n = 0;                 // network grid: n, or n/2 with RECON_CNN_HALF
   long long cnn_n3 = 0;
   double *lossp = nullptr, *losst = nullptr;
@@ -199,7 +203,7 @@ struct recon_plan_s {
   bool painted_g = false, painted_r = false;
   int state = ST_EMPTY;
   int start = RECON_START_PLAIN;
-  std::vector<int> passes, done, psi_valid, st_y, pending1, diverged;
+  std::vector<int> passes, done, psi_valid, st_y, pending1, diverged, stale_x;
   std::vector<double> num0, den0, s1, s2, norm1;
   std::vector<std::vector<double>> hist;
   std::vector<int> h_fan, h_fin, h_it;
@@ -272,6 +276,7 @@ struct Ops {
   int (*ziter)(recon_plan_t*, int mode, const int*);
   int (*fanin_xiter)(recon_plan_t*, bool first, const int*);
   int (*zfinal)(recon_plan_t*, float4* psi, float* u, bool cross, const int*);
+  int (*refan)(recon_plan_t*, const int*);  // state X again from D_n
   int nb_x, nb_z;
 };
 
@@ -383,6 +388,14 @@ struct SizeOps {
     return finish_start(pl);
   }
 
+  static int refan(recon_plan_t* pl, const int* act) {
+    {
+      PROF(pl, KP_X_START);
+      k_x_refan<N><<<gx(pl), dim3(TX), 0, pl->stream>>>(pl->w0, pl->w1, pl->dn, pl->geo, act, pl->tw);
+    }
+    return check_launch(pl, "x re-fan");
+  }
+
   static int fanout(recon_plan_t* pl, const int* act) {
     {
       PROF(pl, KP_Y_FANOUT);
@@ -401,6 +414,9 @@ struct SizeOps {
       else if (mode == ZI_LEARNED)
         k_z_iter<N, ZI_LEARNED><<<gz(pl), dim3(TZ), 0, s>>>(pl->w0, pl->w1, pl->w2, pl->geo, pl->corr,
                                                                   pl->partials, act, pl->tw);
+      else if (mode == ZI_CROSS)
+        k_z_iter<N, ZI_CROSS><<<gz(pl), dim3(TZ), 0, s>>>(pl->w0, pl->w1, pl->w2, pl->geo, pl->corr,
+                                                                pl->partials, act, pl->tw);
       else
         k_z_iter<N, ZI_PLAIN><<<gz(pl), dim3(TZ), 0, s>>>(pl->w0, pl->w1, pl->w2, pl->geo, nullptr,
                                                                 nullptr, act, pl->tw);
@@ -455,7 +471,7 @@ struct SizeOps {
   }
 
   static const Ops* table() {
-    static const Ops ops = {setup, setup_delta, fanout, ziter, fanin_xiter, zfinal,
+    static const Ops ops = {setup, setup_delta, fanout, ziter, fanin_xiter, zfinal, refan,
                             (int)((N / 2 + 1) * N / WX), (int)(N * (N / (2 * WZ)))};
     return &ops;
   }
@@ -502,18 +518,27 @@ recon::cnn::Geo3 grid_geo(const recon_plan_t* pl, bool network) {
 }
 recon::cnn::Geo3 cnn_geo(const recon_plan_t* pl) { return grid_geo(pl, true); }
 
-int restrict_impl(recon_plan_t* pl, const float* fine, float* coarse) {
+// Restriction of one field (fb == nullptr) or of two fields in one pass.
+int restrict_impl(recon_plan_t* pl, const float* fa, float* ca, const float* fb = nullptr, float* cb = nullptr) {
   const long long m = pl->n / 2;
   PROF(pl, KP_RESAMPLE);
-  recon::cnn::k_restrict<<<dim3((unsigned)((m * m * m + 255) / 256), pl->batch), 256, 0, pl->stream>>>(fine, pl->n,
-                                                                                                      coarse);
+  if (m >= 64) {   // slab kernel: 64 x 4 x 16 coarse nodes per block
+    const dim3 grid((unsigned)((m / 64) * (m / 4) * (m / 16)), pl->batch);
+    if (fb) recon::cnn::k_restrict_slab<2><<<grid, 256, 0, pl->stream>>>(fa, fb, pl->n, ca, cb);
+    else recon::cnn::k_restrict_slab<1><<<grid, 256, 0, pl->stream>>>(fa, fa, pl->n, ca, ca);
+  } else {
+    const dim3 grid((unsigned)((m * m * m + 255) / 256), pl->batch);
+    if (fb) recon::cnn::k_restrict<2><<<grid, 256, 0, pl->stream>>>(fa, fb, pl->n, ca, cb);
+    else recon::cnn::k_restrict<1><<<grid, 256, 0, pl->stream>>>(fa, fa, pl->n, ca, ca);
+  }
   return check_launch(pl, "restriction");
 }
 
 int prolong_impl(recon_plan_t* pl, const float* coarse, float scale, float* fine) {
+  const long long m = pl->n / 2;
   PROF(pl, KP_RESAMPLE);
-  recon::cnn::k_prolong<<<dim3((unsigned)((pl->n3 + 255) / 256), pl->batch), 256, 0, pl->stream>>>(coarse, pl->n,
-                                                                                                  scale, fine);
+  recon::cnn::k_prolong<<<dim3((unsigned)((m * m * m + 255) / 256), pl->batch), 256, 0, pl->stream>>>(coarse, pl->n,
+                                                                                                      scale, fine);
   return check_launch(pl, "prolongation");
 }
 
@@ -525,11 +550,11 @@ int cnn_forward_impl(recon_plan_t* pl, const float* params, const float* delta, 
   const Geo3 g = cnn_geo(pl);
   PROF(pl, KP_CNN_FWD);
   k_prep_weights<<<64, 256, 0, pl->stream>>>(params, pl->wk1, pl->wk2, pl->wk2t, pl->w3);
-  k_conv16<CIN, K1P, 1, 0><<<grid, 256, 0, pl->stream>>>(nullptr, delta, up, g, pl->wk1, params + OFF_B1, nullptr,
-                                                         pl->a1);
-  k_conv16<CH, K2, 0, 0><<<grid, 256, 0, pl->stream>>>(pl->a1, nullptr, nullptr, g, pl->wk2, params + OFF_B2,
-                                                       nullptr, pl->a2);
-  k_conv_out<<<grid, 256, 0, pl->stream>>>(pl->a2, g, pl->w3, params + OFF_B3, scale, out);
+  k_prep_frag<<<(27 * 64 + 255) / 256, 256, 0, pl->stream>>>(params, pl->wf1, pl->wf2);
+  const dim3 gridf((unsigned)(pl->cnn_n3 / (FX * FY * FZ)), pl->batch);
+  k_conv_fwd<CIN, 1><<<gridf, 256, 0, pl->stream>>>(nullptr, delta, up, g, pl->wf1, params + OFF_B1, pl->a1);
+  k_conv_fwd<CH, 0><<<gridf, 256, 0, pl->stream>>>(pl->a1, nullptr, nullptr, g, pl->wf2, params + OFF_B2, pl->a2);
+  k_conv_out_mfma<<<gridf, 256, 0, pl->stream>>>(pl->a2, g, params + OFF_W3, params + OFF_B3, scale, out);
   return check_launch(pl, "network forward");
 }
 
@@ -618,6 +643,8 @@ int recon_plan(recon_plan_t** out, const recon_params_t* params, void* workspace
     pl->ybuf = (float*)(w + L.ybuf);
     pl->dybuf = (float*)(w + L.dybuf);
     pl->upbuf = (float*)(w + L.upbuf);
+    pl->wf1 = (uint4*)(w + L.wf1);
+    pl->wf2 = (uint4*)(w + L.wf2);
     pl->cnn_n = (int)L.cnn_n;
     pl->cnn_n3 = L.cnn_n * L.cnn_n * L.cnn_n;
     if (params->flags & RECON_CNN_HALF) {
@@ -669,6 +696,7 @@ int recon_plan(recon_plan_t** out, const recon_params_t* params, void* workspace
   pl->st_y.assign(pl->batch, 0);
   pl->pending1.assign(pl->batch, 0);
   pl->diverged.assign(pl->batch, 0);
+  pl->stale_x.assign(pl->batch, 0);
   pl->num0.assign(pl->batch, 0.0);
   pl->den0.assign(pl->batch, 0.0);
   pl->s1.assign(pl->batch, 0.0);
@@ -836,6 +864,7 @@ int recon_solve(recon_plan_t* pl, int start, const void* net) {
     pl->st_y[b] = 0;
     pl->pending1[b] = 0;
     pl->diverged[b] = 0;
+    pl->stale_x[b] = 0;
     pl->hist[b].clear();
   }
   if (start == RECON_START_LEARNED) {
@@ -844,8 +873,7 @@ int recon_solve(recon_plan_t* pl, int start, const void* net) {
     RECON_TRY(ops->zfinal(pl, nullptr, pl->upbuf, false, nullptr));
     if (pl->dc) {
       // network on the (n/2)^3 grid: restrict the inputs, prolong its output
-      RECON_TRY(restrict_impl(pl, pl->delta, pl->dc));
-      RECON_TRY(restrict_impl(pl, pl->upbuf, pl->uc));
+      RECON_TRY(restrict_impl(pl, pl->delta, pl->dc, pl->upbuf, pl->uc));
       RECON_TRY(cnn_forward_impl(pl, (const float*)net, pl->dc, pl->uc, pl->ybuf, 1.0f / recon::cnn::S_U));
       RECON_TRY(prolong_impl(pl, pl->ybuf, 1.0f, pl->corr));
     } else {
@@ -919,8 +947,6 @@ int recon_iterate(recon_plan_t* pl, int max_iter, double tol, int32_t* iters_out
     bool any = false;
     for (int b = 0; b < B; ++b) any = any || !pl->done[b];
     if (!any) break;
-    // pending eps_1 first (it also fans out those realisations)
-    RECON_TRY(resolve_pending(true));
     any = false;
     for (int b = 0; b < B; ++b) {
       pl->h_it[b] = pl->done[b] ? 0 : 1;
@@ -935,8 +961,35 @@ int recon_iterate(recon_plan_t* pl, int max_iter, double tol, int32_t* iters_out
     RECON_TRY(ops->fanout(pl, pl->act_fan));
     RECON_TRY(upload_mask(pl, pl->act_it, pl->h_it));
     const bool start_pass = first_pass == 0 && pl->start != RECON_START_PLAIN;
-    const int mode = start_pass ? (pl->start == RECON_START_LEARNED ? ZI_LEARNED : ZI_FFTA) : ZI_PLAIN;
+    // eps_1 of a non-gradient start needs S3 = sum Delta u_1; this pass's z step computes u_1
+    bool cross = false;
+    for (int b = 0; b < B; ++b) cross = cross || (pl->h_it[b] && pl->pending1[b]);
+    const int mode = start_pass ? (pl->start == RECON_START_LEARNED ? ZI_LEARNED : ZI_FFTA)
+                                : (cross ? ZI_CROSS : ZI_PLAIN);
     RECON_TRY(ops->ziter(pl, mode, pl->act_it));
+    if (cross) {
+      HIP_TRY(pl, hipMemcpyAsync(pl->h_red2.data(), pl->red + 2 * B, 16 * B, hipMemcpyDeviceToHost, pl->stream));
+      HIP_TRY(pl, hipStreamSynchronize(pl->stream));
+      bool rest = false;
+      for (int b = 0; b < B; ++b) {
+        if (!pl->h_it[b] || !pl->pending1[b]) continue;
+        pl->pending1[b] = 0;
+        const double s3 = pl->h_red2[2 * b];
+        const double diff2 = pl->num0[b] - 2.0 * (s3 - pl->s1[b]) + pl->s2[b];
+        const double e = pl->den0[b] > 0 ? std::sqrt(std::fmax(diff2, 0.0) / pl->den0[b]) : 0.0;
+        record(b, e, pl->den0[b]);
+        // a realisation that stops here keeps D_1: its z step is dropped and Psi_1 recomputed at the end
+        if (pl->done[b]) {
+          pl->h_it[b] = 0;
+          pl->st_y[b] = 0;
+          pl->psi_valid[b] = 0;
+          pl->stale_x[b] = 1;
+        }
+      }
+      for (int b = 0; b < B; ++b) rest = rest || pl->h_it[b];
+      if (!rest) continue;
+      RECON_TRY(upload_mask(pl, pl->act_it, pl->h_it));
+    }
     RECON_TRY(ops->fanin_xiter(pl, first_pass == 0, pl->act_it));
     HIP_TRY(pl, hipMemcpyAsync(pl->h_red.data(), pl->red, 16 * B, hipMemcpyDeviceToHost, pl->stream));
     if (start_pass) {
@@ -961,6 +1014,19 @@ int recon_iterate(recon_plan_t* pl, int max_iter, double tol, int32_t* iters_out
     }
   }
   RECON_TRY(resolve_pending(true));
+  // realisations stopped inside a pass: state X again from D_n
+  {
+    bool any_stale = false;
+    for (int b = 0; b < B; ++b) {
+      pl->h_fan[b] = pl->stale_x[b];
+      any_stale = any_stale || pl->stale_x[b];
+    }
+    if (any_stale) {
+      RECON_TRY(upload_mask(pl, pl->act_fan, pl->h_fan));
+      RECON_TRY(ops->refan(pl, pl->act_fan));
+      for (int b = 0; b < B; ++b) pl->stale_x[b] = 0;
+    }
+  }
   // displacement of every realisation whose Psi buffer is stale
   bool need = false;
   for (int b = 0; b < B; ++b) {

@@ -153,6 +153,245 @@ __global__ void __launch_bounds__(256) k_conv16(const unsigned short* __restrict
   }
 }
 
+// ---------------------------------------------------------------------------
+// Forward convolution on v_mfma_f32_16x16x32_bf16 (inference and the training forward).
+//
+// Block tile 16 (x) x 8 (y) x 8 (z) output cells, halo 18 x 10 x 10 cells staged once in LDS;
+// each wave owns 16 x 4 x 4 outputs (16 output rows of 16 cells).  The wave walks the 6 x 6 input
+// rows of its halo: an input row's A fragment (16 cells x K = 32) is loaded from LDS once and
+// multiplied into every output row that uses it (up to 9), so one LDS read feeds up to 9 MFMAs.
+// K = 32 of one fragment: C = 16: half 0 = taps dx = -1, 0 (16 channels each), half 1 = dx = +1
+// and 16 zero columns;  C = 8: dx = -1, 0, +1 and 8 zero columns.
+// Operand layout of that instruction: lane l holds A[l%16][8(l/16)+0..7], B[8(l/16)+0..7][l%16],
+// and the result D[4(l/16)+0..3][l%16].
+constexpr int FX = 16, FY = 8, FZ = 8, GX = FX + 2, GY = FY + 2, GZ = FZ + 2, GCELLS = GX * GY * GZ;
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+// Byte offset of the 16-byte half h of halo cell c (C = 16: halves swapped on every other group of
+// four cells so that 8 consecutive lanes reading one half hit distinct banks).
+template <int C>
+__device__ __forceinline__ int frag_off(int c, int h) {
+  if (C == 16) return c * 32 + ((h ^ ((c >> 2) & 1)) << 4);
+  return c * 16;
+}
+
+// Weight fragments: C = 16: wf[(g * 2 + h) * 64 + lane], C = 8: wf[g * 64 + lane], with
+// g = (dz+1)*3 + (dy+1); 8 bf16 per lane in the B layout above.
+__global__ void __launch_bounds__(256) k_prep_frag(const float* __restrict__ th, uint4* __restrict__ wf1,
+                                                   uint4* __restrict__ wf2) {
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= 9 * 64 + 9 * 2 * 64) return;
+  unsigned short v[8];
+  if (e < 9 * 64) {
+    const int g = e / 64, lane = e % 64, o = lane % 16, q = lane / 16;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int t = g * 3 + q;                     // dx = q - 1
+      v[j] = q < 3 ? to_bf16(th[OFF_W1 + (o * 27 + t) * CIN + j]) : (unsigned short)0;
+    }
+    wf1[e] = make_uint4(v[0] | (v[1] << 16), v[2] | (v[3] << 16), v[4] | (v[5] << 16), v[6] | (v[7] << 16));
+  } else {
+    const int f = e - 9 * 64, g = f / 128, h = (f / 64) % 2, lane = f % 64, o = lane % 16, q = lane / 16;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int k = 8 * q + j, ch = k % 16;
+      const int dx = h == 0 ? (k < 16 ? -1 : 0) : 1;
+      const bool zero = h == 1 && k >= 16;
+      v[j] = zero ? (unsigned short)0 : to_bf16(th[OFF_W2 + (o * 27 + g * 3 + dx + 1) * CH + ch]);
+    }
+    wf2[f] = make_uint4(v[0] | (v[1] << 16), v[2] | (v[3] << 16), v[4] | (v[5] << 16), v[6] | (v[7] << 16));
+  }
+}
+
+// Stage the 18 x 10 x 10 halo of a channels-last bf16 tensor into LDS: every thread issues all of
+// its 16-byte loads before the first LDS store so the loads are in flight together.
+template <int C>
+__device__ __forceinline__ void stage_halo(unsigned char* lds, const unsigned short* __restrict__ src, int n, int x0,
+                                           int y0, int z0) {
+  constexpr int CPC = C / 8, TOTAL = GCELLS * CPC, PER = (TOTAL + 255) / 256;
+  const int msk = n - 1;
+  uint4 v[PER];
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int e0 = threadIdx.x + k * 256;
+    const int e = e0 < TOTAL ? e0 : TOTAL - 1;        // tail lanes reload the last chunk
+    const int c = e / CPC, h = e % CPC;
+    const int hx = c % GX, hy = (c / GX) % GY, hz = c / (GX * GY);
+    const long long gc = ((long long)((z0 - 1 + hz) & msk) * n + ((y0 - 1 + hy) & msk)) * n + ((x0 - 1 + hx) & msk);
+    v[k] = *(const uint4*)(src + gc * C + 8 * h);
+  }
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int e = threadIdx.x + k * 256;
+    if (e < TOTAL) *(uint4*)(lds + frag_off<C>(e / CPC, e % CPC)) = v[k];
+  }
+}
+
+//   SRC 0: input is a bf16 tensor [n^3][C];  SRC 1: input is x0 assembled from (delta, u_p), C = 8.
+//   out = bf16(relu(acc + bias)), channels-last [n^3][16].
+template <int C, int SRC>
+__global__ void __launch_bounds__(256) k_conv_fwd(const unsigned short* __restrict__ in,
+                                                     const float* __restrict__ delta, const float* __restrict__ up,
+                                                     Geo3 g, const uint4* __restrict__ wf,
+                                                     const float* __restrict__ bias, unsigned short* __restrict__ out) {
+  constexpr int NH = C == 16 ? 2 : 1;
+  __shared__ __align__(16) unsigned char lds[GCELLS * C * 2];
+  const long long n3 = (long long)g.n * g.n * g.n;
+  const int b = blockIdx.y, msk = g.n - 1;
+  const int nbx = g.n / FX, nby = g.n / FY;
+  const int x0 = (blockIdx.x % nbx) * FX, y0 = ((blockIdx.x / nbx) % nby) * FY, z0 = (blockIdx.x / (nbx * nby)) * FZ;
+  if (SRC == 0) {
+    stage_halo<C>(lds, in + b * n3 * C, g.n, x0, y0, z0);
+  } else {
+    const float* dl = delta + b * n3;
+    const float* ul = up + b * n3;
+    constexpr int PER = (GCELLS + 255) / 256;
+    float dv[PER], uv[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int c = threadIdx.x + k * 256;
+      if (c < GCELLS) {
+        const int hx = c % GX, hy = (c / GX) % GY, hz = c / (GX * GY);
+        const long long gc = ((long long)((z0 - 1 + hz) & msk) * g.n + ((y0 - 1 + hy) & msk)) * g.n + ((x0 - 1 + hx) & msk);
+        dv[k] = dl[gc];
+        uv[k] = ul[gc];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int c = threadIdx.x + k * 256;
+      if (c < GCELLS) {
+        const int hx = c % GX, hy = (c / GX) % GY, hz = c / (GX * GY);
+        const int x = (x0 - 1 + hx) & msk, y = (y0 - 1 + hy) & msk, z = (z0 - 1 + hz) & msk;
+        const float rx = fmaf(g.hs, (float)x, g.ds[0]), ry = fmaf(g.hs, (float)y, g.ds[1]),
+                    rz = fmaf(g.hs, (float)z, g.ds[2]);
+        const float r2 = rx * rx + ry * ry + rz * rz;
+        const float ir = r2 > 0.f ? rsqrtf(r2) : 0.f;
+        const unsigned a0 = to_bf16(dv[k]), a1 = to_bf16(S_U * uv[k]);
+        const unsigned a2 = to_bf16(rx * ir), a3 = to_bf16(ry * ir), a4 = to_bf16(rz * ir);
+        *(uint4*)(lds + c * 16) = make_uint4(a0 | (a1 << 16), a2 | (a3 << 16), a4, 0u);
+      }
+    }
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int m = lane & 15, q = lane >> 4;
+  bf8 bw[9][NH];
+#pragma unroll
+  for (int gi = 0; gi < 9; ++gi)
+#pragma unroll
+    for (int h = 0; h < NH; ++h) bw[gi][h] = __builtin_bit_cast(bf8, wf[(gi * NH + h) * 64 + lane]);
+  __syncthreads();
+  const int wy0 = 4 * (wave & 1), wz0 = 4 * (wave >> 1);
+  f4 acc[4][4];
+#pragma unroll
+  for (int oz = 0; oz < 4; ++oz)
+#pragma unroll
+    for (int oy = 0; oy < 4; ++oy) acc[oz][oy] = f4{0.f, 0.f, 0.f, 0.f};
+  const bf8 zero8 = __builtin_bit_cast(bf8, make_uint4(0u, 0u, 0u, 0u));
+#pragma unroll
+  for (int iz = 0; iz < 6; ++iz) {
+#pragma unroll
+    for (int iy = 0; iy < 6; ++iy) {
+      const int rowc = ((wz0 + iz) * GY + (wy0 + iy)) * GX;
+      bf8 a[NH];
+      if (C == 16) {
+        a[0] = __builtin_bit_cast(bf8, *(const uint4*)(lds + frag_off<C>(rowc + m + (q >> 1), q & 1)));
+        const bf8 t1 = __builtin_bit_cast(bf8, *(const uint4*)(lds + frag_off<C>(rowc + m + 2, q & 1)));
+        a[NH - 1] = q < 2 ? t1 : zero8;
+      } else {
+        const bf8 t0 = __builtin_bit_cast(bf8, *(const uint4*)(lds + frag_off<C>(rowc + m + (q < 3 ? q : 2), 0)));
+        a[0] = q < 3 ? t0 : zero8;
+      }
+#pragma unroll
+      for (int oz = 0; oz < 4; ++oz) {
+        const int dz = iz - 1 - oz;
+        if (dz < -1 || dz > 1) continue;
+#pragma unroll
+        for (int oy = 0; oy < 4; ++oy) {
+          const int dy = iy - 1 - oy;
+          if (dy < -1 || dy > 1) continue;
+          const int gi = (dz + 1) * 3 + (dy + 1);
+#pragma unroll
+          for (int h = 0; h < NH; ++h)
+            acc[oz][oy] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[h], bw[gi][h], acc[oz][oy], 0, 0, 0);
+        }
+      }
+    }
+  }
+  // epilogue: lane (m, q) holds channel m of cells 4q..4q+3 of each output row; channel pairs are
+  // exchanged with the neighbouring lane so every lane stores two packed 32-bit words per row
+  const float bm = bias[m];
+  const bool even = (m & 1) == 0;
+#pragma unroll
+  for (int oz = 0; oz < 4; ++oz) {
+#pragma unroll
+    for (int oy = 0; oy < 4; ++oy) {
+      unsigned mine[4], other[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) mine[i] = to_bf16(fmaxf(acc[oz][oy][i] + bm, 0.f));
+#pragma unroll
+      for (int i = 0; i < 4; ++i) other[i] = (unsigned)__shfl_xor((int)mine[i], 1);
+      const long long row = b * n3 + ((long long)(z0 + wz0 + oz) * g.n + (y0 + wy0 + oy)) * g.n + x0;
+      unsigned* o32 = (unsigned*)out;
+      const int ch2 = m >> 1;                       // channel pair
+      if (even) {
+        o32[(row + 4 * q + 0) * 8 + ch2] = mine[0] | (other[0] << 16);
+        o32[(row + 4 * q + 1) * 8 + ch2] = mine[1] | (other[1] << 16);
+      } else {
+        o32[(row + 4 * q + 2) * 8 + ch2] = other[2] | (mine[2] << 16);
+        o32[(row + 4 * q + 3) * 8 + ch2] = other[3] | (mine[3] << 16);
+      }
+    }
+  }
+}
+
+// Output layer (16 -> 1) on MFMA for the forward pass: with one output channel the N dimension of
+// the instruction runs over the wave's 16 output rows instead.  For input row (iz, iy) the B
+// fragment column n = output row (oz, oy) = (n / 4, n % 4) holds W3 of tap (iz - 1 - oz, iy - 1 - oy, dx)
+// (zero when that row is out of reach), so each A fragment is used once for all 16 output rows.
+__global__ void __launch_bounds__(256) k_conv_out_mfma(const unsigned short* __restrict__ a2, Geo3 g,
+                                                       const float* __restrict__ w3f, const float* __restrict__ b3,
+                                                       float scale, float* __restrict__ y_out) {
+  __shared__ __align__(16) unsigned char lds[GCELLS * CH * 2];
+  __shared__ __align__(16) unsigned short w3b[27 * CH];
+  const long long n3 = (long long)g.n * g.n * g.n;
+  const int b = blockIdx.y, msk = g.n - 1;
+  const int nbx = g.n / FX, nby = g.n / FY;
+  const int x0 = (blockIdx.x % nbx) * FX, y0 = ((blockIdx.x / nbx) % nby) * FY, z0 = (blockIdx.x / (nbx * nby)) * FZ;
+  stage_halo<CH>(lds, a2 + b * n3 * CH, g.n, x0, y0, z0);
+  for (int i = threadIdx.x; i < 27 * CH; i += 256) w3b[i] = to_bf16(w3f[i]);
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int m = lane & 15, q = lane >> 4;
+  const int wy0 = 4 * (wave & 1), wz0 = 4 * (wave >> 1);
+  const int oz = m >> 2, oy = m & 3;                  // output row of B / D column m
+  const bf8 zero8 = __builtin_bit_cast(bf8, make_uint4(0u, 0u, 0u, 0u));
+  f4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int iz = 0; iz < 6; ++iz) {
+#pragma unroll
+    for (int iy = 0; iy < 6; ++iy) {
+      const int rowc = ((wz0 + iz) * GY + (wy0 + iy)) * GX;
+      const bf8 a0 = __builtin_bit_cast(bf8, *(const uint4*)(lds + frag_off<CH>(rowc + m + (q >> 1), q & 1)));
+      const bf8 t1 = __builtin_bit_cast(bf8, *(const uint4*)(lds + frag_off<CH>(rowc + m + 2, q & 1)));
+      const bf8 a1 = q < 2 ? t1 : zero8;
+      const int dz = iz - 1 - oz, dy = iy - 1 - oy;
+      const bool ok = dz >= -1 && dz <= 1 && dy >= -1 && dy <= 1;
+      const int tb = ok ? (dz + 1) * 9 + (dy + 1) * 3 : 0;   // tap of dx = -1
+      // half 0: q < 2 -> dx = -1, q >= 2 -> dx = 0;  half 1: q < 2 -> dx = +1, else zero
+      const bf8 w0 = __builtin_bit_cast(bf8, *(const uint4*)(w3b + (tb + (q >> 1)) * CH + 8 * (q & 1)));
+      const bf8 w1 = __builtin_bit_cast(bf8, *(const uint4*)(w3b + (tb + 2) * CH + 8 * (q & 1)));
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, ok ? w0 : zero8, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, (ok && q < 2) ? w1 : zero8, acc, 0, 0, 0);
+    }
+  }
+  // lane (m, q) holds output row m, cells 4q .. 4q+3
+  const float bb = b3[0];
+  const long long row = b * n3 + ((long long)(z0 + wz0 + oz) * g.n + (y0 + wy0 + oy)) * g.n + x0 + 4 * q;
+  *(float4*)(y_out + row) = make_float4((acc[0] + bb) * scale, (acc[1] + bb) * scale, (acc[2] + bb) * scale,
+                                        (acc[3] + bb) * scale);
+}
+
 // Output layer (16 -> 1) on VALU: y = b3 + sum_t sum_i W3[t][i] a2[p + d_t][i]; y_out FP32.
 // scale multiplies the result (1 for training, 1/S_U to write Delta u directly).
 __global__ void __launch_bounds__(256) k_conv_out(const unsigned short* __restrict__ a2, Geo3 g,
@@ -412,50 +651,138 @@ __global__ void __launch_bounds__(256) k_radial(const float4* __restrict__ psi4,
   }
 }
 
-// Full-weighting restriction of a periodic n^3 node field to (n/2)^3: coarse node J sits on fine
+// Full-weighting restriction of periodic n^3 node fields to (n/2)^3: coarse node J sits on fine
 // node 2J, weights 1/4, 1/2, 1/4 per axis on fine nodes 2J-1, 2J, 2J+1.  One thread per coarse
-// node, blockIdx.y = realisation.
-__global__ void __launch_bounds__(256) k_restrict(const float* __restrict__ fine, int n, float* __restrict__ coarse) {
+// node restricts NF fields, blockIdx.y = realisation.
+template <int NF>
+__global__ void __launch_bounds__(256) k_restrict(const float* __restrict__ fa, const float* __restrict__ fb, int n,
+                                                  float* __restrict__ ca, float* __restrict__ cb) {
   const int m = n >> 1, msk = n - 1;
   const long long mc = (long long)m * m * m;
   const long long i = blockIdx.x * 256LL + threadIdx.x;
   if (i >= mc) return;
   const int X = (int)(i % m), Y = (int)((i / m) % m), Z = (int)(i / ((long long)m * m));
-  const float* f = fine + (long long)blockIdx.y * n * n * n;
+  const long long off = (long long)blockIdx.y * n * n * n;
   const float w[3] = {0.25f, 0.5f, 0.25f};
-  float acc = 0.f;
+  float acc[NF];
+#pragma unroll
+  for (int f = 0; f < NF; ++f) acc[f] = 0.f;
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     const long long z = (2 * Z + c - 1) & msk;
 #pragma unroll
-    for (int b = 0; b < 3; ++b) {
-      const long long row = (z * n + ((2 * Y + b - 1) & msk)) * n;
-      float r = 0.f;
+    for (int bb = 0; bb < 3; ++bb) {
+      const long long row = off + (z * n + ((2 * Y + bb - 1) & msk)) * n;
 #pragma unroll
-      for (int a = 0; a < 3; ++a) r = fmaf(w[a], f[row + ((2 * X + a - 1) & msk)], r);
-      acc = fmaf(w[c] * w[b], r, acc);
+      for (int f = 0; f < NF; ++f) {
+        const float* src = f == 0 ? fa : fb;
+        float r = 0.f;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) r = fmaf(w[a], src[row + ((2 * X + a - 1) & msk)], r);
+        acc[f] = fmaf(w[c] * w[bb], r, acc[f]);
+      }
     }
   }
-  coarse[(long long)blockIdx.y * mc + i] = acc;
+  const long long o = (long long)blockIdx.y * mc + i;
+  ca[o] = acc[0];
+  if (NF > 1) cb[o] = acc[NF - 1];
+}
+
+// The same restriction for n/2 >= 64: a block covers 64 (x) by 4 (y) coarse nodes and marches over
+// 16 coarse z planes, so each fine z plane is filtered once in x and y and shared by the two coarse
+// planes it feeds (the filtered plane 2Z+1 is carried in registers to the next coarse plane).
+template <int NF>
+__global__ void __launch_bounds__(256) k_restrict_slab(const float* __restrict__ fa, const float* __restrict__ fb, int n,
+                                                       float* __restrict__ ca, float* __restrict__ cb) {
+  constexpr int TXW = 64, TYH = 4, ZB = 16;
+  const int m = n >> 1, msk = n - 1;
+  const int nbx = m / TXW, nby = m / TYH;
+  int t = blockIdx.x;
+  const int X = (t % nbx) * TXW + (threadIdx.x % TXW);
+  t /= nbx;
+  const int Y = (t % nby) * TYH + threadIdx.x / TXW;
+  const int Z0 = (t / nby) * ZB;
+  const long long off = (long long)blockIdx.y * n * n * n, mc = (long long)m * m * m;
+  const int xs0 = (2 * X - 1) & msk, xs1 = 2 * X, xs2 = 2 * X + 1;
+  const int ys[3] = {(2 * Y - 1) & msk, 2 * Y, 2 * Y + 1};
+  auto plane = [&](const float* __restrict__ f, int z) {
+    float p = 0.f;
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      const float* r = f + off + ((long long)z * n + ys[b]) * n;
+      const float v = fmaf(0.25f, r[xs0], fmaf(0.5f, r[xs1], 0.25f * r[xs2]));
+      p = fmaf(b == 1 ? 0.5f : 0.25f, v, p);
+    }
+    return p;
+  };
+  float prev[NF];
+#pragma unroll
+  for (int f = 0; f < NF; ++f) prev[f] = plane(f == 0 ? fa : fb, (2 * Z0 - 1) & msk);
+  for (int k = 0; k < ZB; ++k) {
+    const int Z = Z0 + k;
+    const long long o = (long long)blockIdx.y * mc + ((long long)Z * m + Y) * m + X;
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+      const float* src = f == 0 ? fa : fb;
+      const float p0 = plane(src, 2 * Z), p1 = plane(src, 2 * Z + 1);
+      const float v = fmaf(0.25f, prev[f], fmaf(0.5f, p0, 0.25f * p1));
+      prev[f] = p1;
+      (f == 0 ? ca : cb)[o] = v;
+    }
+  }
 }
 
 // Linear prolongation of a periodic (n/2)^3 node field to n^3, times scale: fine node 2J copies
-// coarse node J, fine node 2J+1 takes the mean of coarse J and J+1, axis by axis.
+// coarse node J, fine node 2J+1 takes the mean of coarse J and J+1, axis by axis.  One thread per
+// coarse node writes its 2 x 2 x 2 block of fine nodes.
 __global__ void __launch_bounds__(256) k_prolong(const float* __restrict__ coarse, int n, float scale,
                                                  float* __restrict__ fine) {
   const int m = n >> 1, mm = m - 1;
-  const long long n3 = (long long)n * n * n;
+  const long long mc = (long long)m * m * m;
   const long long i = blockIdx.x * 256LL + threadIdx.x;
-  if (i >= n3) return;
-  const int x = (int)(i % n), y = (int)((i / n) % n), z = (int)(i / ((long long)n * n));
-  const float* c = coarse + (long long)blockIdx.y * m * m * m;
-  const int x0 = x >> 1, y0 = y >> 1, z0 = z >> 1;
-  const int x1 = (x0 + (x & 1)) & mm, y1 = (y0 + (y & 1)) & mm, z1 = (z0 + (z & 1)) & mm;
-  const long long r00 = ((long long)z0 * m + y0) * m, r01 = ((long long)z0 * m + y1) * m,
-                  r10 = ((long long)z1 * m + y0) * m, r11 = ((long long)z1 * m + y1) * m;
-  const float v = 0.125f * ((c[r00 + x0] + c[r00 + x1]) + (c[r01 + x0] + c[r01 + x1]) +
-                            (c[r10 + x0] + c[r10 + x1]) + (c[r11 + x0] + c[r11 + x1]));
-  fine[(long long)blockIdx.y * n3 + i] = scale * v;
+  if (i >= mc) return;
+  const int X = (int)(i % m), Y = (int)((i / m) % m), Z = (int)(i / ((long long)m * m));
+  const float* c = coarse + (long long)blockIdx.y * mc;
+  const int X1 = (X + 1) & mm, Y1 = (Y + 1) & mm, Z1 = (Z + 1) & mm;
+  float v[2][2][2];                                   // [z][y][x] corners J, J+1
+  const long long zr[2] = {(long long)Z * m, (long long)Z1 * m};
+  const int yr[2] = {Y, Y1};
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int bb = 0; bb < 2; ++bb) {
+      const long long r = (zr[a] + yr[bb]) * m;
+      v[a][bb][0] = c[r + X];
+      v[a][bb][1] = c[r + X1];
+    }
+  // x, then y, then z halves
+  float hx[2][2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int bb = 0; bb < 2; ++bb) {
+      hx[a][bb][0] = v[a][bb][0];
+      hx[a][bb][1] = 0.5f * (v[a][bb][0] + v[a][bb][1]);
+    }
+  float hy[2][2][2];                                  // [z corner][ey][ex]
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int ex = 0; ex < 2; ++ex) {
+      hy[a][0][ex] = hx[a][0][ex];
+      hy[a][1][ex] = 0.5f * (hx[a][0][ex] + hx[a][1][ex]);
+    }
+  float* out = fine + (long long)blockIdx.y * n * n * n;
+#pragma unroll
+  for (int ez = 0; ez < 2; ++ez)
+#pragma unroll
+    for (int ey = 0; ey < 2; ++ey) {
+      float o[2];
+#pragma unroll
+      for (int ex = 0; ex < 2; ++ex) o[ex] = scale * (ez ? 0.5f * (hy[0][ey][ex] + hy[1][ey][ex]) : hy[0][ey][ex]);
+      const long long fi = (((long long)(2 * Z + ez) * n) + (2 * Y + ey)) * n + 2 * X;
+      *(float2*)(out + fi) = make_float2(o[0], o[1]);
+    }
 }
 
 }  // namespace cnn

@@ -40,7 +40,7 @@ struct CicGeo {
   float o[3];
 };
 
-enum ZIterMode { ZI_PLAIN = 0, ZI_FFTA = 1, ZI_LEARNED = 2 };
+enum ZIterMode { ZI_PLAIN = 0, ZI_FFTA = 1, ZI_LEARNED = 2, ZI_CROSS = 3 };
 
 // Tile shapes (compile-time tuning knobs): packed z columns, y-pass columns, x-pass rows.
 // Each block runs one radix-8 fragment per thread, (N/8) * tile threads.
@@ -702,7 +702,9 @@ __global__ void __launch_bounds__(ntz<N>()) k_z_delta(float2* __restrict__ a0, c
 // Arrays are updated in place.  Start modes (first pass only):
 //   ZI_FFTA:    u_0 = start_scale * u_p, Delta = u_0 - u_p stored in corr
 //   ZI_LEARNED: u_0 = u_p + corr (corr taken as 0 at the observer)
-// and both accumulate S1 = sum Delta u_p, S2 = sum Delta^2 into partials.
+// and both accumulate S1 = sum Delta u_p, S2 = sum Delta^2 into partials.  On the pass after such
+// a start, ZI_CROSS iterates as ZI_PLAIN and accumulates S3 = sum Delta u_1 (second entry 0), the
+// cross term of ||Psi_1 - Psi_0||^2.
 template <int N, int MODE>
 __global__ void __launch_bounds__(ntz<N>()) k_z_iter(float2* __restrict__ a0, float2* __restrict__ a1,
                                                      float2* __restrict__ a2, Geo g, float* __restrict__ corr,
@@ -743,7 +745,7 @@ __global__ void __launch_bounds__(ntz<N>()) k_z_iter(float2* __restrict__ a0, fl
     }
   }
   // s -> q = u_0 / |r|, so that V_j = q r_j
-  double acc1 = 0.0, acc2 = 0.0;
+  float acc1 = 0.f, acc2 = 0.f;          // 16 terms per thread; block and grid sums in FP64
   if (act) {
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
@@ -763,12 +765,14 @@ __global__ void __launch_bounds__(ntz<N>()) k_z_iter(float2* __restrict__ a0, fl
             u0 = g.start_scale * up;
             dlt = u0 - up;
             corr[cell] = dlt;
+          } else if (MODE == ZI_CROSS) {
+            dlt = r2 > 0.f ? corr[cell] : 0.f;
           } else {
             dlt = r2 > 0.f ? corr[cell] : 0.f;
             u0 = up + dlt;
           }
-          acc1 += (double)dlt * (double)up;
-          acc2 += (double)dlt * (double)dlt;
+          acc1 = fmaf(dlt, up, acc1);
+          if (MODE != ZI_CROSS) acc2 = fmaf(dlt, dlt, acc2);
         }
         const float q = u0 * ir;
         if (h) s1[r] = q; else s0[r] = q;
@@ -777,7 +781,7 @@ __global__ void __launch_bounds__(ntz<N>()) k_z_iter(float2* __restrict__ a0, fl
   }
   if (MODE != ZI_PLAIN) {
     double t1, t2;
-    block_sum2<NT>(acc1, acc2, &t1, &t2);
+    block_sum2<NT>((double)acc1, (double)acc2, &t1, &t2);
     if (threadIdx.x == 0) {
       const long long nb = gridDim.x;
       partials[2 * (b * nb + blockIdx.x) + 0] = t1;
@@ -1094,6 +1098,43 @@ __global__ void __launch_bounds__(ntx<N>()) k_x_start(float2* __restrict__ a0, f
   fft_rr<N, W, false, true>(v, buf, tw);
   if (act) {
     x_store<N>(v, ds, row, j);
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      float k2, dx, dy, dz;
+      int kzi;
+      x_wavenumbers<N>(row, j + r * (N / 8), g.kf, k2, dx, dy, dz, kzi);
+      pr[r] = k2 > 0.f ? v[r] * (g.inv_bn3 / k2) : make_float2(0.f, 0.f);
+      v[r] = mul_i(pr[r]) * dx;
+    }
+  }
+  fft_rr<N, W, true, true>(v, buf, tw);
+  if (act) x_store<N>(v, a0, row, j);
+  fft_rr<N, W, true, true>(pr, buf, tw);
+  if (act) x_store<N>(pr, a1, row, j);
+}
+
+// State X (a0 = X^-1[i k'_x P], a1 = X^-1[P], P = D / (b k^2 N^3)) rebuilt from a stored spectrum D;
+// the tail of k_x_start without its forward transform.
+template <int N>
+__global__ void __launch_bounds__(ntx<N>()) k_x_refan(float2* __restrict__ a0, float2* __restrict__ a1,
+                                                      const float2* __restrict__ d, Geo g,
+                                                      const int* __restrict__ active, const float2* __restrict__ twg) {
+  constexpr int NT = ntx<N>(), W = wx<N>();
+  using L = Lay<N, W, true>;
+  const int b = blockIdx.y;
+  if (active && !active[b]) return;
+  __shared__ float2 buf[L::SIZE];
+  __shared__ float2 tw[N];
+  stage_twiddles<N, NT>(tw, twg);
+  int c, j;
+  frag_coords<N, W, true>(c, j);
+  const bool act = threadIdx.x < L::NTF;
+  const long long cn = (long long)(N / 2 + 1) * N * N;
+  const long long row = (long long)blockIdx.x * W + c;
+  a0 += b * cn; a1 += b * cn; d += b * cn;
+  float2 v[8], pr[8];
+  if (act) {
+    x_load<N>(v, d, row, j);
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
       float k2, dx, dy, dz;

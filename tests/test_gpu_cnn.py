@@ -154,9 +154,10 @@ def test_learned_start_end_to_end(gpu_lib):
         np.testing.assert_allclose(eps[0], ref["eps"], rtol=1e-3, atol=1e-5)
 
 
-def test_restrict_and_prolong_match_oracle(gpu_lib):
+@pytest.mark.parametrize("n", [32, 128])
+def test_restrict_and_prolong_match_oracle(gpu_lib, n):
     from paper_1504_02591_amd import native
-    n, b = 32, 2
+    b = 2
     rng = np.random.default_rng(11)
     f = rng.standard_normal((b, n, n, n)).astype(np.float32)
     c = rng.standard_normal((b, n // 2, n // 2, n // 2)).astype(np.float32)

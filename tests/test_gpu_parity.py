@@ -311,6 +311,23 @@ def test_tolerance_mode_counts_passes(gpu_lib):
     assert g["eps"][-1] <= 1e-3
 
 
+@pytest.mark.parametrize("stop_at", [1, 2])
+def test_start_tolerance_stop_returns_that_pass(gpu_lib, stop_at):
+    # eps_1 of an FFTA start is only known during the next pass: stopping at pass 1 must still
+    # return Psi_1, and stopping at pass 2 Psi_2
+    from paper_1504_02591_amd import native
+    cat = G.lattice_box(32, 500.0, (-500.0, 250.0, 250.0), 0.7, 61, 62, ran_factor=3, bias=1.2, smooth_r=20.0)
+    ref3 = oracle_catalogue_run(cat, 3, start=native.START_FFTA2)
+    e = ref3["eps"]
+    assert e[0] > e[1] > e[2]
+    tol = e[stop_at - 1] * 1.01
+    g = gpu_catalogue_run(native, cat, 10, start=native.START_FFTA2, tol=tol)
+    r = oracle_catalogue_run(cat, stop_at, start=native.START_FFTA2)
+    assert g["rc"] == 0 and g["iters"] == stop_at
+    assert len(g["eps"]) == stop_at
+    compare_full(g, r, f"ffta2 stop at {stop_at}")
+
+
 def test_not_converged_and_resume(gpu_lib):
     from paper_1504_02591_amd import native
     cat = G.lattice_box(32, 500.0, (-500.0, 250.0, 250.0), 0.7, 53, 54, ran_factor=2, bias=1.0, smooth_r=20.0)
