@@ -531,6 +531,50 @@ __device__ __forceinline__ void z_pack_frag(float2* v, const float2* __restrict_
   }
 }
 
+// LDS-direct staging of a z tile: rows kz = 0..N/2 of columns x0 .. x0 + 2 WP - 1 at plane row y
+// land in `stage` as [kz][2 WP] float2 without passing through registers, so the loads of the next
+// array run while the current one is transformed.  Each lane moves 16 bytes; one wave instruction
+// fills one 1 KB chunk (its LDS base is wave-uniform).  Completion: s_waitcnt vmcnt(0), then a barrier.
+template <int N, int WP>
+struct ZStage {
+  static constexpr int ROWB = 2 * WP * 8;             // bytes per kz row
+  static constexpr int LPR = ROWB / 16;               // lanes per row
+  static constexpr int RPC = 64 / LPR;                // rows per 1 KB chunk
+  static constexpr int ROWS = N / 2 + 1;
+  static constexpr int NCH = (ROWS + RPC - 1) / RPC;
+  static constexpr int SIZE = NCH * 128;              // float2 elements
+};
+
+template <int N, int WP, int NT>
+__device__ __forceinline__ void z_stage_issue(float2* stage, const float2* __restrict__ a, int y, int x0) {
+  using S = ZStage<N, WP>;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int q = wave; q < S::NCH; q += NT / 64) {
+    const int m = q * S::RPC + lane / S::LPR;
+    if (m < S::ROWS) {
+      const float2* g = a + ((long long)m * N + y) * N + x0 + 2 * (lane % S::LPR);
+      __builtin_amdgcn_global_load_lds((const void*)g, (__attribute__((address_space(3))) void*)(stage + q * 128),
+                                       16, 0, 0);
+    }
+  }
+}
+
+__device__ __forceinline__ void z_stage_wait() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+// z_pack_frag from a staged tile.
+template <int N, int WP>
+__device__ __forceinline__ void z_pack_stage(float2* v, const float2* stage, int c, int j) {
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    const int k = j + r * (N / 8);
+    const int m = k <= N / 2 ? k : N - k;
+    const float2 A = stage[m * 2 * WP + c], B = stage[m * 2 * WP + c + WP];
+    if (k == 0 || k == N / 2) v[r] = make_float2(A.x, B.x);
+    else if (k < N / 2) v[r] = make_float2(A.x - B.y, A.y + B.x);
+    else v[r] = make_float2(A.x + B.y, B.x - A.y);
+  }
+}
+
 // Split a transformed packed tile (natural order in LDS) into the half spectra of its
 // two real columns and store them.  MULK: multiply by i k'_z.
 template <int N, int WP, int NT, bool MULK>
@@ -716,6 +760,7 @@ __global__ void __launch_bounds__(ntz<N>()) k_z_iter(float2* __restrict__ a0, fl
   if (active && !active[b]) return;
   __shared__ float2 buf[L::SIZE];
   __shared__ float2 tw[N];
+  __shared__ float2 stage[ZStage<N, WP>::SIZE];
   stage_twiddles<N, NT>(tw, twg);
   int y, x0, c, j;
   z_tile_coords<N, WP>(y, x0);
@@ -723,15 +768,23 @@ __global__ void __launch_bounds__(ntz<N>()) k_z_iter(float2* __restrict__ a0, fl
   const bool act = threadIdx.x < L::NTF;
   const long long n3 = (long long)N * N * N, cn = (long long)(N / 2 + 1) * N * N;
   float2* arr[3] = {a0 + b * cn, a1 + b * cn, a2 + b * cn};
+  // each array is staged in LDS by direct loads while the previous one is transformed
+  z_stage_issue<N, WP, NT>(stage, arr[0], y, x0);
   const float ry = los_comp(g, 1, y);
   const float rx0 = los_comp(g, 0, x0 + c), rx1 = los_comp(g, 0, x0 + c + WP);
   float s0[8], s1[8];
 #pragma unroll
   for (int r = 0; r < 8; ++r) { s0[r] = 0.f; s1[r] = 0.f; }
+  z_stage_wait();
+  __syncthreads();
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     float2 v[8];
-    if (act) z_pack_frag<N, WP>(v, arr[a], y, x0, c, j);
+    if (act) z_pack_stage<N, WP>(v, stage, c, j);
+    if (a < 2) {
+      __syncthreads();                                // every thread has read the staged tile
+      z_stage_issue<N, WP, NT>(stage, arr[a + 1], y, x0);
+    }
     fft_rr<N, WP, true, false>(v, buf, tw);
     if (act) {
 #pragma unroll
@@ -742,6 +795,10 @@ __global__ void __launch_bounds__(ntz<N>()) k_z_iter(float2* __restrict__ a0, fl
         s0[r] = fmaf(r0, v[r].x, s0[r]);
         s1[r] = fmaf(r1, v[r].y, s1[r]);
       }
+    }
+    if (a < 2) {
+      z_stage_wait();
+      __syncthreads();                                // the next array is staged
     }
   }
   // s -> q = u_0 / |r|, so that V_j = q r_j
@@ -828,12 +885,25 @@ __global__ void __launch_bounds__(ntz<N>()) k_z_final(const float2* __restrict__
   const bool act = threadIdx.x < L::NTF;
   const long long n3 = (long long)N * N * N, cn = (long long)(N / 2 + 1) * N * N;
   const float2* arr[3] = {a0 + b * cn, a1 + b * cn, a2 + b * cn};
+  // each array is staged in LDS by direct loads while the previous one is transformed
+  __shared__ float2 stage[ZStage<N, WP>::SIZE];
+  z_stage_issue<N, WP, NT>(stage, arr[0], y, x0);
+  z_stage_wait();
+  __syncthreads();
   float2 px[8], py[8], v[8];
-  if (act) z_pack_frag<N, WP>(px, arr[0], y, x0, c, j);
+  if (act) z_pack_stage<N, WP>(px, stage, c, j);
+  __syncthreads();
+  z_stage_issue<N, WP, NT>(stage, arr[1], y, x0);
   fft_rr<N, WP, true, false>(px, buf, tw);
-  if (act) z_pack_frag<N, WP>(py, arr[1], y, x0, c, j);
+  z_stage_wait();
+  __syncthreads();
+  if (act) z_pack_stage<N, WP>(py, stage, c, j);
+  __syncthreads();
+  z_stage_issue<N, WP, NT>(stage, arr[2], y, x0);
   fft_rr<N, WP, true, false>(py, buf, tw);
-  if (act) z_pack_frag<N, WP>(v, arr[2], y, x0, c, j);
+  z_stage_wait();
+  __syncthreads();
+  if (act) z_pack_stage<N, WP>(v, stage, c, j);
   fft_rr<N, WP, true, false>(v, buf, tw);
   const float ry = los_comp(g, 1, y);
   const float rx0 = los_comp(g, 0, x0 + c), rx1 = los_comp(g, 0, x0 + c + WP);
