@@ -54,7 +54,8 @@ bool valid_params(const recon_params_t* p, std::string* why) {
   if (!(p->growth >= 0.0) || !std::isfinite(p->growth)) return fail("growth must be >= 0 and finite");
   if (!(p->smooth_r >= 0.0) || !std::isfinite(p->smooth_r)) return fail("smooth_r must be >= 0 and finite");
   if (!(p->mask_tau >= 0.0) || !std::isfinite(p->mask_tau)) return fail("mask_tau must be >= 0 and finite");
-  if (p->flags & ~(RECON_NO_RANDOMS | RECON_KEEP_DELTA | RECON_START_BUFFERS | RECON_CNN_BUFFERS | RECON_CNN_HALF))
+  if (p->flags & ~(RECON_NO_RANDOMS | RECON_KEEP_DELTA | RECON_START_BUFFERS | RECON_CNN_BUFFERS | RECON_CNN_HALF |
+                   RECON_PASS_GRAPHS))
     return fail("unknown flag");
   if ((p->flags & RECON_CNN_HALF) && !(p->flags & RECON_CNN_BUFFERS)) return fail("RECON_CNN_HALF needs RECON_CNN_BUFFERS");
   if ((p->flags & RECON_CNN_BUFFERS) && p->n < ((p->flags & RECON_CNN_HALF) ? 32 : 16))
@@ -210,8 +211,13 @@ struct recon_plan_s {
   std::vector<double> h_red, h_red2;
   std::string msg;
   Profiler prof;
+  // steady-state pass graph (RECON_PASS_GRAPHS): fan-out, z step, fan-in, x step, norm reduction
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t pass_graph = nullptr;
   ~recon_plan_s() {
     for (hipEvent_t e : prof.pool) (void)hipEventDestroy(e);
+    if (pass_graph) (void)hipGraphExecDestroy(pass_graph);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
   }
 };
 
@@ -556,6 +562,42 @@ int cnn_forward_impl(recon_plan_t* pl, const float* params, const float* delta, 
   k_conv_fwd<CH, 0><<<gridf, 256, 0, pl->stream>>>(pl->a1, nullptr, nullptr, g, pl->wf2, params + OFF_B2, pl->a2);
   k_conv_out_mfma<<<gridf, 256, 0, pl->stream>>>(pl->a2, g, params + OFF_W3, params + OFF_B3, scale, out);
   return check_launch(pl, "network forward");
+}
+
+// Steady-state correction pass as a HIP graph: captured once per plan on a private stream (the
+// plan's buffers, masks and geometry are fixed, so the recorded launches stay valid), then
+// replayed on the plan's stream.  The graph holds kernels only (no memset or copy nodes); the
+// activity masks it reads are uploaded before each replay.
+int pass_graph_launch(recon_plan_t* pl, const Ops* ops) {
+  if (!pl->pass_graph) {
+    if (!pl->cap_stream) HIP_TRY(pl, hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking));
+    hipStream_t keep = pl->stream;
+    pl->stream = pl->cap_stream;
+    hipGraph_t graph = nullptr;
+    int rc = RECON_OK;
+    if (hipStreamBeginCapture(pl->cap_stream, hipStreamCaptureModeRelaxed) != hipSuccess) {
+      pl->stream = keep;
+      return fail(pl, RECON_EDEVICE, "graph capture could not start");
+    }
+    rc = ops->fanout(pl, pl->act_fan);
+    if (rc == RECON_OK) rc = ops->ziter(pl, ZI_PLAIN, pl->act_it);
+    if (rc == RECON_OK) rc = ops->fanin_xiter(pl, false, pl->act_it);
+    const hipError_t ec = hipStreamEndCapture(pl->cap_stream, &graph);
+    pl->stream = keep;
+    if (rc != RECON_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return rc;
+    }
+    if (ec != hipSuccess || !graph) return fail(pl, RECON_EDEVICE, "graph capture failed");
+    const hipError_t ei = hipGraphInstantiate(&pl->pass_graph, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ei != hipSuccess) {
+      pl->pass_graph = nullptr;
+      return fail(pl, RECON_EDEVICE, "graph instantiation failed");
+    }
+  }
+  HIP_TRY(pl, hipGraphLaunch(pl->pass_graph, pl->stream));
+  return RECON_OK;
 }
 
 double ffta_c(int start, double beta) {
@@ -958,7 +1000,6 @@ int recon_iterate(recon_plan_t* pl, int max_iter, double tol, int32_t* iters_out
     for (int b = 0; b < B; ++b)
       if (pl->h_it[b]) { first_pass = pl->passes[b]; break; }
     RECON_TRY(upload_mask(pl, pl->act_fan, pl->h_fan));
-    RECON_TRY(ops->fanout(pl, pl->act_fan));
     RECON_TRY(upload_mask(pl, pl->act_it, pl->h_it));
     const bool start_pass = first_pass == 0 && pl->start != RECON_START_PLAIN;
     // eps_1 of a non-gradient start needs S3 = sum Delta u_1; this pass's z step computes u_1
@@ -966,7 +1007,13 @@ int recon_iterate(recon_plan_t* pl, int max_iter, double tol, int32_t* iters_out
     for (int b = 0; b < B; ++b) cross = cross || (pl->h_it[b] && pl->pending1[b]);
     const int mode = start_pass ? (pl->start == RECON_START_LEARNED ? ZI_LEARNED : ZI_FFTA)
                                 : (cross ? ZI_CROSS : ZI_PLAIN);
-    RECON_TRY(ops->ziter(pl, mode, pl->act_it));
+    const bool steady = mode == ZI_PLAIN && first_pass != 0;
+    if (steady && (pl->p.flags & RECON_PASS_GRAPHS) && !pl->prof.on) {
+      RECON_TRY(pass_graph_launch(pl, ops));
+    } else {
+      RECON_TRY(ops->fanout(pl, pl->act_fan));
+      RECON_TRY(ops->ziter(pl, mode, pl->act_it));
+    }
     if (cross) {
       HIP_TRY(pl, hipMemcpyAsync(pl->h_red2.data(), pl->red + 2 * B, 16 * B, hipMemcpyDeviceToHost, pl->stream));
       HIP_TRY(pl, hipStreamSynchronize(pl->stream));
@@ -990,7 +1037,8 @@ int recon_iterate(recon_plan_t* pl, int max_iter, double tol, int32_t* iters_out
       if (!rest) continue;
       RECON_TRY(upload_mask(pl, pl->act_it, pl->h_it));
     }
-    RECON_TRY(ops->fanin_xiter(pl, first_pass == 0, pl->act_it));
+    if (!(steady && (pl->p.flags & RECON_PASS_GRAPHS) && !pl->prof.on))
+      RECON_TRY(ops->fanin_xiter(pl, first_pass == 0, pl->act_it));
     HIP_TRY(pl, hipMemcpyAsync(pl->h_red.data(), pl->red, 16 * B, hipMemcpyDeviceToHost, pl->stream));
     if (start_pass) {
       HIP_TRY(pl, hipMemcpyAsync(pl->h_red2.data(), pl->red + 2 * B, 16 * B, hipMemcpyDeviceToHost, pl->stream));

@@ -328,6 +328,32 @@ def test_start_tolerance_stop_returns_that_pass(gpu_lib, stop_at):
     compare_full(g, r, f"ffta2 stop at {stop_at}")
 
 
+@pytest.mark.parametrize("batch", [1, 2])
+def test_pass_graph_replays_match_eager(gpu_lib, batch):
+    # the captured steady-state pass, replayed with eager work and synchronisation in between,
+    # must reproduce the eager passes bit for bit
+    from paper_1504_02591_amd import native
+    n, box = 32, 400.0
+    rng = np.random.default_rng(12)
+    delta = np.stack([O.smooth(rng.standard_normal((n, n, n)), box, 25.0) for _ in range(batch)]).astype(np.float32)
+    runs = []
+    for graphs in (False, True):
+        plan = native.Plan(n, box, (30.0, -50.0, 400.0), 1.5, 0.8, 0.0, randoms=False, batch=batch, graphs=graphs)
+        plan.set_delta(to_dev(delta))
+        plan.solve()
+        out = []
+        for _ in range(3):
+            rc, iters, eps = plan.iterate(2, 0.0)
+            psi = plan.psi().cpu().numpy()
+            torch.cuda.synchronize()
+            out.append((list(iters), [list(e) for e in eps], psi))
+        plan.close()
+        runs.append(out)
+    for (ie, ee, pe), (ig, eg, pg) in zip(*runs):
+        assert ie == ig and ee == eg
+        assert np.array_equal(pe, pg)
+
+
 def test_not_converged_and_resume(gpu_lib):
     from paper_1504_02591_amd import native
     cat = G.lattice_box(32, 500.0, (-500.0, 250.0, 250.0), 0.7, 53, 54, ran_factor=2, bias=1.0, smooth_r=20.0)
