@@ -56,7 +56,8 @@ extern "C" {
 #define RECON_ENOMEM (-2)      /* workspace too small */
 #define RECON_EDEVICE (-3)     /* a HIP runtime call or kernel launch failed */
 #define RECON_ESTATE (-4)      /* call out of order */
-#define RECON_EDIVERGED (-5)   /* eps non-finite, rising on two consecutive passes, or ||Psi_n|| > 100 ||Psi_1|| */
+#define RECON_EDIVERGED (-5)   /* eps non-finite, rising on two consecutive passes to above 1e-5, or
+                                  ||Psi_n|| > 100 ||Psi_1|| */
 
 /* catalogue selector */
 #define RECON_GAL 0

@@ -49,8 +49,9 @@ R10 Line of sight r = (x - O)/|x - O| per grid node, r = 0 at the observer.
 R11 The correction term is not re-smoothed (delta_s is already smoothed).
 R12 Convergence: eps_n = ||Psi_n - Psi_{n-1}|| / ||Psi_n|| over all cells and the
     three components; the pass count n counts correction passes (n = 0 is the start).
-    Divergence: eps_n non-finite, eps rising on two consecutive passes, or
-    ||Psi_n|| above 100 ||Psi_1|| (the iteration only converges for beta mu^2 < 1,
+    Divergence: eps_n non-finite, eps rising on two consecutive passes to a value
+    above EPS_FLOOR (rises below it are rounding noise of a converged FP32 iteration),
+    or ||Psi_n|| above 100 ||Psi_1|| (the iteration only converges for beta mu^2 < 1,
     eq. (itpsi) and the remark after it).
 R13 Shift: galaxies move by -Psi - f (Psi.r) r, randoms by -Psi, with Psi
     interpolated to the object by the same CIC stencil.
@@ -58,6 +59,8 @@ R14 FFTA starts with beta in place of f: c = beta/(1+beta) (eq. approx1) or
     3 beta/(7 + 3 beta) (eq. approx2).
 """
 from __future__ import annotations
+
+EPS_FLOOR = 1e-5   # rises of eps below this are not divergence (R12)
 
 import os
 
@@ -366,7 +369,7 @@ def reconstruct_field(delta_s, box_len, origin, observer, bias, growth,
         if not np.isfinite(eps):
             diverged = True
             break
-        if len(eps_hist) >= 3 and eps_hist[-1] > eps_hist[-2] > eps_hist[-3]:
+        if len(eps_hist) >= 3 and eps_hist[-1] > eps_hist[-2] > eps_hist[-3] and eps_hist[-1] > EPS_FLOOR:
             diverged = True
             break
         if passes >= 2 and den > 100.0 * norm1:

@@ -927,6 +927,9 @@ int recon_solve(recon_plan_t* pl, int start, const void* net) {
   return RECON_OK;
 }
 
+// eps rising below this is rounding noise of a converged FP32 iteration, not divergence
+constexpr double kEpsFloor = 1e-5;
+
 int recon_iterate(recon_plan_t* pl, int max_iter, double tol, int32_t* iters_out, double* eps_out) {
   if (!pl) return RECON_EINVAL;
   if (pl->state != ST_SOLVED) return fail(pl, RECON_ESTATE, "solve must precede iterate");
@@ -947,7 +950,8 @@ int recon_iterate(recon_plan_t* pl, int max_iter, double tol, int32_t* iters_out
     const size_t k = h.size();
     const double nrm = std::sqrt(std::fmax(norm2, 0.0));
     if (k == 1) pl->norm1[b] = nrm;
-    if (!std::isfinite(e) || !std::isfinite(nrm) || (k >= 3 && h[k - 1] > h[k - 2] && h[k - 2] > h[k - 3]) ||
+    if (!std::isfinite(e) || !std::isfinite(nrm) ||
+        (k >= 3 && h[k - 1] > h[k - 2] && h[k - 2] > h[k - 3] && h[k - 1] > kEpsFloor) ||
         (k >= 2 && nrm > 100.0 * pl->norm1[b])) {
       pl->diverged[b] = 1;
       pl->done[b] = 1;

@@ -10,6 +10,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "recon_tuning.h"
+
 namespace recon {
 
 constexpr int kThreads = 256;
@@ -193,15 +195,34 @@ __device__ __forceinline__ void last_pass(float2* v, const float2* buf, const fl
   }
 }
 
-// Middle passes between NS = 8 and NS = N/8 (factor N/64 as 2, 4, 8 or 4 x 4).
+// Middle passes between NS = 8 and NS = N/8 (factor N/64).  The split of the factor for 512 and
+// 1024 is a tuning knob (RECON_MID_512: 0 = 8, 1 = 2 x 4, 2 = 4 x 2; RECON_MID_1024: 0 = 4 x 4,
+// 1 = 2 x 8, 2 = 8 x 2), chosen by the autotuner (autotune.py).
 template <int N, int W, bool INV, bool JF>
 __device__ __forceinline__ void middle_passes(float2* buf, const float2* tw) {
   if constexpr (N == 128) lds_pass<N, W, 2, 8, INV, JF>(buf, tw);
   else if constexpr (N == 256) lds_pass<N, W, 4, 8, INV, JF>(buf, tw);
-  else if constexpr (N == 512) lds_pass<N, W, 8, 8, INV, JF>(buf, tw);
-  else if constexpr (N == 1024) {
-    lds_pass<N, W, 4, 8, INV, JF>(buf, tw);
-    lds_pass<N, W, 4, 32, INV, JF>(buf, tw);
+  else if constexpr (N == 512) {
+    if constexpr (RECON_MID_512 == 1) {
+      lds_pass<N, W, 2, 8, INV, JF>(buf, tw);
+      lds_pass<N, W, 4, 16, INV, JF>(buf, tw);
+    } else if constexpr (RECON_MID_512 == 2) {
+      lds_pass<N, W, 4, 8, INV, JF>(buf, tw);
+      lds_pass<N, W, 2, 32, INV, JF>(buf, tw);
+    } else {
+      lds_pass<N, W, 8, 8, INV, JF>(buf, tw);
+    }
+  } else if constexpr (N == 1024) {
+    if constexpr (RECON_MID_1024 == 1) {
+      lds_pass<N, W, 2, 8, INV, JF>(buf, tw);
+      lds_pass<N, W, 8, 16, INV, JF>(buf, tw);
+    } else if constexpr (RECON_MID_1024 == 2) {
+      lds_pass<N, W, 8, 8, INV, JF>(buf, tw);
+      lds_pass<N, W, 2, 64, INV, JF>(buf, tw);
+    } else {
+      lds_pass<N, W, 4, 8, INV, JF>(buf, tw);
+      lds_pass<N, W, 4, 32, INV, JF>(buf, tw);
+    }
   }
 }
 

@@ -42,17 +42,8 @@ struct CicGeo {
 
 enum ZIterMode { ZI_PLAIN = 0, ZI_FFTA = 1, ZI_LEARNED = 2, ZI_CROSS = 3 };
 
-// Tile shapes (compile-time tuning knobs): packed z columns, y-pass columns, x-pass rows.
-// Each block runs one radix-8 fragment per thread, (N/8) * tile threads.
-#ifndef RECON_TILE_Z
-#define RECON_TILE_Z 16
-#endif
-#ifndef RECON_TILE_Y
-#define RECON_TILE_Y 16
-#endif
-#ifndef RECON_TILE_X
-#define RECON_TILE_X 4
-#endif
+// Tile shapes (compile-time tuning knobs from recon_tuning.h): packed z columns, y-pass columns,
+// x-pass rows.  Each block runs one radix-8 fragment per thread, (N/8) * tile threads.
 constexpr int cmin(int a, int b) { return a < b ? a : b; }
 template <int N> constexpr int wz() { return N >= 1024 ? 8 : cmin(N / 2, RECON_TILE_Z); }
 template <int N> constexpr int wy() { return N >= 1024 ? 8 : cmin(N, RECON_TILE_Y); }

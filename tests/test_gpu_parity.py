@@ -354,6 +354,21 @@ def test_pass_graph_replays_match_eager(gpu_lib, batch):
         assert np.array_equal(pe, pg)
 
 
+def test_fixed_passes_past_convergence_do_not_diverge(gpu_lib):
+    # FP32 eps settles at its rounding floor and may rise there; that must not read as divergence
+    from paper_1504_02591_amd import native
+    n, box = 32, 400.0
+    rng = np.random.default_rng(13)
+    delta = O.smooth(rng.standard_normal((n, n, n)), box, 25.0).astype(np.float32)
+    plan = native.Plan(n, box, (200.0, 200.0, -1200.0), 2.0, 0.74, 0.0, randoms=False)
+    plan.set_delta(to_dev(delta))
+    plan.solve()
+    rc, iters, eps = plan.iterate(40, 0.0)
+    plan.close()
+    assert rc == native.RECON_OK and iters[0] == 40
+    assert min(eps[0]) < 1e-5
+
+
 def test_not_converged_and_resume(gpu_lib):
     from paper_1504_02591_amd import native
     cat = G.lattice_box(32, 500.0, (-500.0, 250.0, 250.0), 0.7, 53, 54, ran_factor=2, bias=1.0, smooth_r=20.0)

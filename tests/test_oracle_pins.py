@@ -418,3 +418,14 @@ def test_divergence_beyond_beta_one():
     assert res["diverged"]
     ok = O.reconstruct_field(delta, box, (0, 0, 0), (150.0, 150.0, -3e9), 1.0, 0.9, tol=1e-6, max_iter=400)
     assert not ok["diverged"] and ok["eps"][-1] <= 1e-6
+
+
+def test_rounding_noise_after_convergence_is_not_divergence():
+    """A converged iteration run for a fixed number of passes ends at the rounding floor of eps, where
+    eps may rise by chance; below 1e-5 that is not divergence (R12)."""
+    n, box = 16, 300.0
+    rng = np.random.default_rng(4)
+    delta = O.smooth(rng.standard_normal((n, n, n)), box, 30.0)
+    res = O.reconstruct_field(delta, box, (0, 0, 0), (150.0, 150.0, -3e9), 1.0, 0.5, n_passes=60)
+    assert not res["diverged"] and res["passes"] == 60
+    assert min(res["eps"]) < 1e-12
