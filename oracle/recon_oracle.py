@@ -57,6 +57,10 @@ R13 Shift: galaxies move by -Psi - f (Psi.r) r, randoms by -Psi, with Psi
     interpolated to the object by the same CIC stencil.
 R14 FFTA starts with beta in place of f: c = beta/(1+beta) (eq. approx1) or
     3 beta/(7 + 3 beta) (eq. approx2).
+R15 Lognormal option (Sec. 6, eq. logdelta): the smoothed, masked delta_s is replaced by
+    ln(max(1 + delta_s, 1e-3)) + C, C = -<ln(max(1 + delta_s, 1e-3))> over all cells (masked
+    cells have delta_s = 0 and map to C); the clamp keeps FP32 rounding in empty regions from
+    reaching the logarithm's pole.
 """
 from __future__ import annotations
 
@@ -294,6 +298,19 @@ def overdensity(grid_g, grid_r, box_len, smooth_r, mask_tau=0.1):
 # ---------------------------------------------------------------------------
 # Zel'dovich solve and the iteration (Sec. 2 eq. (Zeldovich), Sec. 5.1 eq. (iterative))
 # ---------------------------------------------------------------------------
+LOG_FLOOR = 1e-3   # lower clamp of 1 + delta_s before the logarithm (R15)
+
+
+def lognormal(delta_s, floor=LOG_FLOOR):
+    """Sec. 6, eq. (logdelta): ln(1 + S*delta) + C with C = -<ln(1 + S*delta)> over all cells.
+
+    delta_s is already smoothed (the paper takes the logarithm of the smoothed field so that it never
+    reaches -1).  1 + delta_s is clamped below at `floor` (R15).
+    """
+    t = np.log(np.maximum(1.0 + np.asarray(delta_s, dtype=np.float64), floor))
+    return t - t.mean()
+
+
 def psi_from_density(dk, n, box_len, bias):
     """Psi_j = IFFT[i k'_j D / (b k^2)], Psi(k=0) = 0 (R1, R7).  Returns (3, n, n, n)."""
     kx, ky, kz, dkx, dky, dkz = wavenumbers(n, box_len)
@@ -426,11 +443,13 @@ def shift(psi, pos, box_len, origin, observer, growth, galaxies):
 # ---------------------------------------------------------------------------
 def reconstruct(gal_pos, gal_w, ran_pos, ran_w, n, box_len, origin, observer,
                 bias, growth, smooth_r, mask_tau=0.1, n_passes=None, tol=None,
-                max_iter=50, start=START_PLAIN, start_correction=None):
-    """Paint -> overdensity -> iteration -> shift, all in FP64 (integer deposit)."""
+                max_iter=50, start=START_PLAIN, start_correction=None, log_transform=False):
+    """Paint -> overdensity (-> lognormal transform) -> iteration -> shift, all in FP64 (integer deposit)."""
     grid_g = paint(gal_pos, gal_w, n, box_len, origin)
     grid_r = None if ran_pos is None else paint(ran_pos, ran_w, n, box_len, origin)
     delta_s = overdensity(grid_g, grid_r, box_len, smooth_r, mask_tau)
+    if log_transform:
+        delta_s = lognormal(delta_s)
     res = reconstruct_field(delta_s, box_len, origin, observer, bias, growth,
                             n_passes=n_passes, tol=tol, max_iter=max_iter,
                             start=start, start_correction=start_correction)

@@ -429,3 +429,28 @@ def test_rounding_noise_after_convergence_is_not_divergence():
     res = O.reconstruct_field(delta, box, (0, 0, 0), (150.0, 150.0, -3e9), 1.0, 0.5, n_passes=60)
     assert not res["diverged"] and res["passes"] == 60
     assert min(res["eps"]) < 1e-12
+
+
+def test_lognormal_of_exponential_field_is_its_exponent():
+    """Sec. 6, eq. (logdelta): if 1 + delta = exp(g) then ln(1 + delta) + C = g - <g>."""
+    rng = np.random.default_rng(21)
+    g = 0.4 * rng.standard_normal((8, 8, 8))
+    out = O.lognormal(np.exp(g) - 1.0)
+    np.testing.assert_allclose(out, g - g.mean(), atol=1e-13)
+    assert abs(out.mean()) < 1e-14
+
+
+def test_lognormal_small_field_second_order():
+    """ln(1 + d) + C = t - <t> with t = d - d^2/2 + d^3/3 + O(d^4) (Taylor series, C = -<ln(1 + d)>)."""
+    rng = np.random.default_rng(22)
+    d = 1e-3 * rng.standard_normal((8, 8, 8))
+    t = d - d ** 2 / 2 + d ** 3 / 3
+    np.testing.assert_allclose(O.lognormal(d), t - t.mean(), atol=2e-10)
+
+
+def test_lognormal_clamps_empty_cells():
+    d = np.full((4, 4, 4), 0.5)
+    d[0, 0, 0] = -1.0          # empty cell: 1 + delta = 0
+    t = np.full(d.shape, np.log(1.5))
+    t[0, 0, 0] = np.log(O.LOG_FLOOR)
+    np.testing.assert_allclose(O.lognormal(d), t - t.mean(), atol=1e-14)
