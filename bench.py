@@ -187,6 +187,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="skip per-kernel event timing")
     ap.add_argument("--no-graphs", action="store_true", help="launch the steady-state pass eagerly")
+    ap.add_argument("--lognormal", action="store_true", help="lognormal transform of delta_s (Sec. 6)")
     ap.add_argument("--batched", type=int, default=0,
                     help="also time B realisations of the batched 256^3 workload in one plan")
     args = ap.parse_args()
@@ -234,7 +235,7 @@ def main():
     def make_plan(start):
         lrn = start == START_NAMES["learned"]
         return native.plan_for(cat, start_buffers=start != 0, keep_delta=lrn, cnn=lrn, cnn_half=lrn and net_half,
-                               graphs=not args.no_graphs)
+                               graphs=not args.no_graphs, lognormal=args.lognormal)
 
     def run(plan, start, steps, passes):
         eps_last = None
@@ -335,7 +336,8 @@ def main():
         "config": {"workload": f"survey-like {args.n}^3 grid over {cat.box_len:g} Mpc/h, observer at the box "
                                f"centre, {n_gal} galaxies in a 2.5 sr cone shell "
                                f"{cat.info['r_min']:g}-{cat.info['r_max']:g} Mpc/h, {n_ran} randoms (50x), "
-                               f"b=2 f=0.74 R=15, {head} start to eps<={args.tol:g}",
+                               f"b=2 f=0.74 R=15, {head} start to eps<={args.tol:g}"
+                               + (", lognormal delta" if args.lognormal else ""),
                    "n": args.n, "start": head, "tol": args.tol, "passes": passes[-1], "eps": eps_last},
         "starts": {k: {kk: vv for kk, vv in v.items() if kk != "elapsed"} for k, v in results.items()},
         "roofline": roofline,

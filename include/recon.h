@@ -75,6 +75,10 @@ extern "C" {
 #define RECON_START_BUFFERS 4u     /* allocate the start-correction field (needed by FFTA / learned)   */
 #define RECON_PASS_GRAPHS 32u      /* replay the steady-state correction pass as one HIP graph (captured
                                       on first use on a private stream; eager while profiling)         */
+#define RECON_LOGNORMAL 64u        /* Sec. 6, eq. (logdelta): start from ln(max(1 + delta_s, 1e-3)) + C,
+                                      C = -<ln(max(1 + delta_s, 1e-3))> over all cells (the kept
+                                      delta_s of RECON_KEEP_DELTA is the transformed field); not applied
+                                      to a field given to recon_set_delta                               */
 
 /* paint flags */
 #define RECON_PAINT_ACCUMULATE 1u  /* add to the grid instead of replacing it */
@@ -91,8 +95,8 @@ typedef struct {
   double growth;           /* f >= 0 (eq. Nusser)                                                        */
   double smooth_r;         /* R >= 0 [Mpc/h] (Sec. 3.1 smoothing)                                        */
   double mask_tau;         /* mask threshold as a fraction of the mean 27-cell random sum (>= 0)          */
-  uint32_t flags;          /* RECON_NO_RANDOMS | RECON_KEEP_DELTA | RECON_START_BUFFERS | RECON_PASS_GRAPHS
-                              (| RECON_CNN_BUFFERS | RECON_CNN_HALF, recon_cnn.h)                        */
+  uint32_t flags;          /* RECON_NO_RANDOMS | RECON_KEEP_DELTA | RECON_START_BUFFERS | RECON_PASS_GRAPHS |
+                              RECON_LOGNORMAL (| RECON_CNN_BUFFERS | RECON_CNN_HALF, recon_cnn.h)        */
   int64_t max_objects;     /* largest catalogue painted in one call that uses the brick-binned deposit
                               (workspace holds 16 B per object for it); larger calls fall back to
                               per-object atomics.  0 disables binning.  Must be < 2^32.                  */

@@ -55,7 +55,7 @@ bool valid_params(const recon_params_t* p, std::string* why) {
   if (!(p->smooth_r >= 0.0) || !std::isfinite(p->smooth_r)) return fail("smooth_r must be >= 0 and finite");
   if (!(p->mask_tau >= 0.0) || !std::isfinite(p->mask_tau)) return fail("mask_tau must be >= 0 and finite");
   if (p->flags & ~(RECON_NO_RANDOMS | RECON_KEEP_DELTA | RECON_START_BUFFERS | RECON_CNN_BUFFERS | RECON_CNN_HALF |
-                   RECON_PASS_GRAPHS))
+                   RECON_PASS_GRAPHS | RECON_LOGNORMAL))
     return fail("unknown flag");
   if ((p->flags & RECON_CNN_HALF) && !(p->flags & RECON_CNN_BUFFERS)) return fail("RECON_CNN_HALF needs RECON_CNN_BUFFERS");
   if ((p->flags & RECON_CNN_BUFFERS) && p->n < ((p->flags & RECON_CNN_HALF) ? 32 : 16))
@@ -303,6 +303,24 @@ int scalars_and_mask(recon_plan_t* pl, int nblk_z) {
   return RECON_OK;
 }
 
+// Lognormal option (RECON_LOGNORMAL): clamp of 1 + delta_s before the logarithm, 0 when off.
+float log_floor(const recon_plan_t* pl) { return (pl->p.flags & RECON_LOGNORMAL) ? 1e-3f : 0.f; }
+
+// C = -<ln(max(1 + delta_s, floor))> added to the kept field (the spectrum needs no change: C only
+// moves the k = 0 mode, which does not enter Psi).
+int log_constant(recon_plan_t* pl, int blocks) {
+  if (!(pl->p.flags & RECON_LOGNORMAL) || !pl->delta) return RECON_OK;
+  {
+    PROF(pl, KP_REDUCE);
+    k_reduce_pairs<<<pl->batch, kThreads, 0, pl->stream>>>(pl->partials, blocks, pl->red + 2 * pl->batch);
+  }
+  RECON_TRY(check_launch(pl, "reduce (log mean)"));
+  long long nb = (pl->n3 * pl->batch + 255) / 256;
+  if (nb > 65536) nb = 65536;
+  k_log_shift<<<(unsigned)nb, 256, 0, pl->stream>>>(pl->delta, pl->n3, pl->batch, pl->red + 2 * pl->batch);
+  return check_launch(pl, "log shift");
+}
+
 template <int N>
 struct SizeOps {
   static constexpr int WZ = wz<N>(), WY = wy<N>(), WX = wx<N>();
@@ -337,9 +355,11 @@ struct SizeOps {
       RECON_TRY(scalars_and_mask(pl, (int)gz(pl).x));
       {
         PROF(pl, KP_Z_DELTA);
-        k_z_delta<N, 2><<<gz(pl), dim3(TZ), 0, s>>>(pl->w0, pl->w1, pl->mask, pl->dscal, pl->delta, pl->tw);
+        k_z_delta<N, 2><<<gz(pl), dim3(TZ), 0, s>>>(pl->w0, pl->w1, pl->mask, pl->dscal, pl->delta,
+                                                    log_floor(pl), pl->partials, pl->tw);
       }
       RECON_TRY(check_launch(pl, "z delta"));
+      RECON_TRY(log_constant(pl, (int)gz(pl).x));
     } else {
       {
         PROF(pl, KP_Z_FWD_GRID);
@@ -364,9 +384,11 @@ struct SizeOps {
       RECON_TRY(scalars_and_mask(pl, (int)gz(pl).x));
       {
         PROF(pl, KP_Z_DELTA);
-        k_z_delta<N, 1><<<gz(pl), dim3(TZ), 0, s>>>(pl->w0, nullptr, nullptr, pl->dscal, pl->delta, pl->tw);
+        k_z_delta<N, 1><<<gz(pl), dim3(TZ), 0, s>>>(pl->w0, nullptr, nullptr, pl->dscal, pl->delta,
+                                                    log_floor(pl), pl->partials, pl->tw);
       }
       RECON_TRY(check_launch(pl, "z delta"));
+      RECON_TRY(log_constant(pl, (int)gz(pl).x));
     }
     return finish_start(pl);
   }

@@ -685,6 +685,7 @@ template <int N, int NA>
 __global__ void __launch_bounds__(ntz<N>()) k_z_delta(float2* __restrict__ a0, const float2* __restrict__ a1,
                                                       const unsigned char* __restrict__ mask,
                                                       const DeltaScal* __restrict__ sc, float* __restrict__ delta_out,
+                                                      float log_floor, double* __restrict__ partials,
                                                       const float2* __restrict__ twg) {
   constexpr int NT = ntz<N>(), WP = wz<N>();
   using L = Lay<N, WP, false>;
@@ -699,6 +700,7 @@ __global__ void __launch_bounds__(ntz<N>()) k_z_delta(float2* __restrict__ a0, c
   const int b = blockIdx.y;
   a0 += b * cn;
   const DeltaScal s = sc[b];
+  double lsum = 0.0;
   float2 gv[8], v[8];
   if (act) z_pack_frag<N, WP>(gv, a0, y, x0, c, j);
   fft_rr<N, WP, true, false>(gv, buf, tw);
@@ -720,6 +722,11 @@ __global__ void __launch_bounds__(ntz<N>()) k_z_delta(float2* __restrict__ a0, c
         d0 = gv[r].x * s.inv_rhobar - 1.f;
         d1 = gv[r].y * s.inv_rhobar - 1.f;
       }
+      if (log_floor > 0.f) {                           // lognormal option: ln(max(1 + delta, floor))
+        d0 = logf(fmaxf(1.f + d0, log_floor));
+        d1 = logf(fmaxf(1.f + d1, log_floor));
+        lsum += (double)d0 + (double)d1;
+      }
       v[r] = make_float2(d0, d1);
       if (delta_out) {
         delta_out[b * n3 + cell] = d0;
@@ -727,8 +734,27 @@ __global__ void __launch_bounds__(ntz<N>()) k_z_delta(float2* __restrict__ a0, c
       }
     }
   }
+  if (log_floor > 0.f) {
+    double t1, t2;
+    block_sum2<NT>(lsum, 0.0, &t1, &t2);
+    if (threadIdx.x == 0) {
+      partials[2 * ((long long)b * gridDim.x + blockIdx.x)] = t1;
+      partials[2 * ((long long)b * gridDim.x + blockIdx.x) + 1] = 0.0;
+    }
+  }
   fft_rl<N, WP, false, false>(v, buf, tw);
   z_unpack_store<N, WP, NT, false>(buf, a0, y, x0, 0.f);
+}
+
+// Lognormal option: add C = -<ln(max(1 + delta, floor))> (sums[2 b] = sum over the n^3 cells of
+// realisation b) to the kept configuration-space field.  Only the k = 0 mode of the spectrum would
+// change, and that mode does not enter Psi, so the spectrum is left alone.
+__global__ void __launch_bounds__(256) k_log_shift(float* __restrict__ delta, long long n3, int batch,
+                                                   const double* __restrict__ sums) {
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n3 * batch; i += (long long)gridDim.x * 256) {
+    const long long b = i / n3;
+    delta[i] += (float)(-sums[2 * b] / (double)n3);
+  }
 }
 
 // One iteration's configuration-space step (step A tail + step B head):

@@ -20,7 +20,7 @@ RECON_OK, RECON_NOTCONVERGED = 0, 1
 RECON_EINVAL, RECON_ENOMEM, RECON_EDEVICE, RECON_ESTATE, RECON_EDIVERGED = -1, -2, -3, -4, -5
 GAL, RAN = 0, 1
 START_PLAIN, START_FFTA1, START_FFTA2, START_LEARNED = 0, 1, 2, 3
-NO_RANDOMS, KEEP_DELTA, START_BUFFERS, CNN_BUFFERS, CNN_HALF, PASS_GRAPHS = 1, 2, 4, 8, 16, 32
+NO_RANDOMS, KEEP_DELTA, START_BUFFERS, CNN_BUFFERS, CNN_HALF, PASS_GRAPHS, LOGNORMAL = 1, 2, 4, 8, 16, 32, 64
 CNN_PARAMS = 10833
 PAINT_ACCUMULATE = 1
 
@@ -117,12 +117,12 @@ class Plan:
 
     def __init__(self, n, box_len, observer, bias, growth, smooth_r, origin=(0.0, 0.0, 0.0), batch=1,
                  mask_tau=0.1, randoms=True, keep_delta=False, start_buffers=False, max_objects=0, cnn=False,
-                 cnn_half=False, graphs=False, device=None):
+                 cnn_half=False, graphs=False, lognormal=False, device=None):
         self.lib = load()
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
         flags = (0 if randoms else NO_RANDOMS) | (KEEP_DELTA if keep_delta else 0) | \
                 (START_BUFFERS if start_buffers else 0) | (CNN_BUFFERS if cnn else 0) | (CNN_HALF if cnn_half else 0) | \
-                (PASS_GRAPHS if graphs else 0)
+                (PASS_GRAPHS if graphs else 0) | (LOGNORMAL if lognormal else 0)
         p = Params()
         p.n, p.batch, p.box_len = int(n), int(batch), float(box_len)
         for a in range(3):

@@ -31,8 +31,8 @@ def rel_l2(a, b):
     return float(np.linalg.norm(np.asarray(a, np.float64) - b) / np.linalg.norm(b))
 
 
-def gpu_catalogue_run(native, cat, n_passes, start=0, keep_delta=True, tol=0.0):
-    plan = native.plan_for(cat, keep_delta=keep_delta, start_buffers=start != 0)
+def gpu_catalogue_run(native, cat, n_passes, start=0, keep_delta=True, tol=0.0, lognormal=False):
+    plan = native.plan_for(cat, keep_delta=keep_delta, start_buffers=start != 0, lognormal=lognormal)
     gal, ran = to_dev(cat.gal_pos), to_dev(cat.ran_pos)
     plan.paint(native.GAL, gal, to_dev(cat.gal_w))
     if ran is not None:
@@ -51,10 +51,10 @@ def gpu_catalogue_run(native, cat, n_passes, start=0, keep_delta=True, tol=0.0):
     return out
 
 
-def oracle_catalogue_run(cat, n_passes, start=0):
+def oracle_catalogue_run(cat, n_passes, start=0, log_transform=False):
     return O.reconstruct(cat.gal_pos, cat.gal_w, cat.ran_pos, cat.ran_w, cat.n, cat.box_len, cat.origin,
                          cat.observer, cat.bias, cat.growth, cat.smooth_r, cat.mask_tau, n_passes=n_passes,
-                         start=start)
+                         start=start, log_transform=log_transform)
 
 
 def compare_full(g, r, label):
@@ -269,6 +269,19 @@ def test_ffta_starts(gpu_lib, start):
         g = gpu_catalogue_run(native, cat, npass, start=start)
         r = oracle_catalogue_run(cat, npass, start=start)
         compare_full(g, r, f"ffta{start}-{npass}")
+
+
+@pytest.mark.parametrize("survey", [False, True])
+def test_lognormal_option_matches_oracle(gpu_lib, survey):
+    # Sec. 6, eq. (logdelta): kept field, Psi, eps and shifts against the oracle's transform
+    from paper_1504_02591_amd import native
+    if survey:
+        cat = G.lattice_box(32, 500.0, (-500.0, 250.0, 250.0), 0.7, 25, 26, ran_factor=3, bias=1.2, smooth_r=20.0)
+    else:
+        cat = G.config3(32)
+    g = gpu_catalogue_run(native, cat, 3, lognormal=True)
+    r = oracle_catalogue_run(cat, 3, log_transform=True)
+    compare_full(g, r, f"lognormal survey={survey}")
 
 
 def test_batched_matches_single_realisations(gpu_lib):
