@@ -57,6 +57,8 @@ R13 Shift: galaxies move by -Psi - f (Psi.r) r, randoms by -Psi, with Psi
     interpolated to the object by the same CIC stencil.
 R14 FFTA starts with beta in place of f: c = beta/(1+beta) (eq. approx1) or
     3 beta/(7 + 3 beta) (eq. approx2).
+R16 NGP option: the paper bins with NGP (Sec. 3.1); node i+1 when the FP32 fraction is >= 1/2.
+    The shift keeps the CIC interpolation of R13.
 R15 Lognormal option (Sec. 6, eq. logdelta): the smoothed, masked delta_s is replaced by
     ln(max(1 + delta_s, 1e-3)) + C, C = -<ln(max(1 + delta_s, 1e-3))> over all cells (masked
     cells have delta_s = 0 and map to C); the clamp keeps FP32 rounding in empty regions from
@@ -226,6 +228,24 @@ def paint(pos, w, n, box_len, origin):
         iz = (i0[:, 2] + dz) % n
         flat = (iz * n + iy) * n + ix
         grid += _bincount_int64(flat, part, n * n * n)
+    return grid.reshape(n, n, n)
+
+
+def paint_ngp(pos, w, n, box_len, origin):
+    """Nearest-grid-point deposit (the paper's binning, Sec. 3.1) in the same fixed point (units 2^-32).
+
+    Node i + 1 (mod n) when the FP32 fraction t = u - floor(u) is at least 1/2, else node i (R16).
+    """
+    pos = np.ascontiguousarray(pos, dtype=np.float32).reshape(-1, 3)
+    m = pos.shape[0]
+    grid = np.zeros(n * n * n, dtype=np.int64)
+    if m == 0:
+        return grid.reshape(n, n, n)
+    i0, _, t = cic_coords(pos, n, box_len, origin)
+    wq = quantise_weights(w, m)
+    ii = np.mod(i0 + (t >= np.float32(0.5)).astype(np.int64), n)
+    flat = (ii[:, 2] * n + ii[:, 1]) * n + ii[:, 0]
+    grid += _bincount_int64(flat, wq, n * n * n)
     return grid.reshape(n, n, n)
 
 
@@ -460,3 +480,21 @@ def reconstruct(gal_pos, gal_w, ran_pos, ran_w, n, box_len, origin, observer,
     if ran_pos is not None:
         res["disp_r"] = shift(res["psi"], ran_pos, box_len, origin, observer, growth, False)
     return res
+
+
+# ---------------------------------------------------------------------------
+# Diagnostics (Sec. 4, Table 1; Sec. 5.2, eq. ratio)
+# ---------------------------------------------------------------------------
+def radial_ratio_stats(psi_ref, psi, rhat, lo=-1.0, hi=3.0):
+    """Mean and standard deviation over grid points of (psi_ref . r) / (psi . r), with ratios
+    above hi or below lo cut as outliers (Sec. 4, Table 1); cells with psi . r = 0 count as outliers.
+    Returns (mean, std, outlier fraction, kept count)."""
+    a = np.sum(np.asarray(psi_ref, dtype=np.float64) * rhat, axis=0).ravel()
+    b = np.sum(np.asarray(psi, dtype=np.float64) * rhat, axis=0).ravel()
+    ok = b != 0
+    ratio = np.where(ok, a / np.where(ok, b, 1.0), np.inf)
+    keep = ok & (ratio >= lo) & (ratio <= hi)
+    r = ratio[keep]
+    if r.size == 0:
+        return 0.0, 0.0, 1.0, 0
+    return float(r.mean()), float(r.std()), float(1.0 - keep.mean()), int(r.size)

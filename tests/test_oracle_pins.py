@@ -454,3 +454,45 @@ def test_lognormal_clamps_empty_cells():
     t = np.full(d.shape, np.log(1.5))
     t[0, 0, 0] = np.log(O.LOG_FLOOR)
     np.testing.assert_allclose(O.lognormal(d), t - t.mean(), atol=1e-14)
+
+
+def test_ngp_deposit_brute_force():
+    """NGP: every object's whole quantised weight on its nearest node (R16), checked object by object."""
+    rng = np.random.default_rng(31)
+    n, box = 8, 100.0
+    pos = (rng.random((300, 3)) * box - 3.0).astype(np.float32)
+    pos[:4] = np.array([[6.25, 0.0, 12.5], [93.75, 99.99, 0.0], [-6.25, 50.0, 18.75], [0.0, 6.2499, 6.2501]],
+                       dtype=np.float32)
+    w = rng.random(300).astype(np.float32) * 3
+    grid = O.paint_ngp(pos, w, n, box, (0.0, 0.0, 0.0))
+    ref = np.zeros((n, n, n), dtype=np.int64)
+    s = np.float32(n / box)
+    for p, wi in zip(pos, w):
+        u = [np.float32(np.float32(p[a]) * s) for a in range(3)]
+        idx = []
+        for a in range(3):
+            f = math.floor(float(u[a]))
+            frac = float(u[a]) - f
+            idx.append((f + (1 if frac >= 0.5 else 0)) % n)
+        ref[idx[2], idx[1], idx[0]] += round(float(wi) * 2 ** 32)
+    np.testing.assert_array_equal(grid, ref)
+    assert grid.sum() == sum(round(float(wi) * 2 ** 32) for wi in w)
+
+
+def test_radial_ratio_stats_hand_values():
+    """Sec. 4, Table 1 statistic: ratio of radial projections, outliers beyond [-1, 3] cut."""
+    n = 4
+    rhat = O.line_of_sight(n, 40.0, (0, 0, 0), (-100.0, 5.0, 7.0))
+    rng = np.random.default_rng(32)
+    psi = rng.standard_normal((3, n, n, n))
+    m, sd, out, cnt = O.radial_ratio_stats(0.5 * psi, psi, rhat)
+    assert abs(m - 0.5) < 1e-14 and sd < 1e-14 and out == 0.0 and cnt == n ** 3
+    ref = psi.copy()
+    u = np.sum(psi * rhat, axis=0)
+    flat = ref.reshape(3, -1)
+    # two cells with ratio 5 (cut), one with ratio -2 (cut), the rest ratio 1
+    for k, fac in ((0, 5.0), (1, 5.0), (2, -2.0)):
+        flat[:, k] += (fac - 1.0) * (u.ravel()[k]) * rhat.reshape(3, -1)[:, k]
+    m, sd, out, cnt = O.radial_ratio_stats(ref, psi, rhat)
+    assert cnt == n ** 3 - 3 and abs(out - 3 / n ** 3) < 1e-15
+    assert abs(m - 1.0) < 1e-12 and sd < 1e-12
