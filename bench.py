@@ -188,6 +188,7 @@ def main():
     ap.add_argument("--no-profile", action="store_true", help="skip per-kernel event timing")
     ap.add_argument("--no-graphs", action="store_true", help="launch the steady-state pass eagerly")
     ap.add_argument("--lognormal", action="store_true", help="lognormal transform of delta_s (Sec. 6)")
+    ap.add_argument("--ngp", action="store_true", help="nearest-grid-point deposit (the paper's binning)")
     ap.add_argument("--batched", type=int, default=0,
                     help="also time B realisations of the batched 256^3 workload in one plan")
     args = ap.parse_args()
@@ -240,8 +241,8 @@ def main():
     def run(plan, start, steps, passes):
         eps_last = None
         for _ in range(steps):
-            plan.paint(native.GAL, gal)
-            plan.paint(native.RAN, ran)
+            plan.paint(native.GAL, gal, ngp=args.ngp)
+            plan.paint(native.RAN, ran, ngp=args.ngp)
             plan.solve(start, net if start == START_NAMES["learned"] else None)
             rc, iters, eps = plan.iterate(args.max_iter, args.tol)
             plan.shift(native.GAL, gal, out_disp=disp_g)
@@ -337,7 +338,7 @@ def main():
                                f"centre, {n_gal} galaxies in a 2.5 sr cone shell "
                                f"{cat.info['r_min']:g}-{cat.info['r_max']:g} Mpc/h, {n_ran} randoms (50x), "
                                f"b=2 f=0.74 R=15, {head} start to eps<={args.tol:g}"
-                               + (", lognormal delta" if args.lognormal else ""),
+                               + (", lognormal delta" if args.lognormal else "") + (", NGP deposit" if args.ngp else ""),
                    "n": args.n, "start": head, "tol": args.tol, "passes": passes[-1], "eps": eps_last},
         "starts": {k: {kk: vv for kk, vv in v.items() if kk != "elapsed"} for k, v in results.items()},
         "roofline": roofline,

@@ -82,6 +82,9 @@ extern "C" {
 
 /* paint flags */
 #define RECON_PAINT_ACCUMULATE 1u  /* add to the grid instead of replacing it */
+#define RECON_PAINT_NGP 2u         /* nearest-grid-point deposit (the paper's binning, Sec. 3.1): the whole
+                                      quantised weight on the nearest node (node i + 1 when the FP32
+                                      fraction is >= 1/2); per-object atomics; the shift stays CIC   */
 
 typedef struct recon_plan_s recon_plan_t;
 
@@ -144,6 +147,14 @@ int recon_get_psi(recon_plan_t* plan, float* psi_out);
 
 /* Copy a deposit grid (device int64 [batch][N^3], units 2^-32 of weight). */
 int recon_get_grid(recon_plan_t* plan, int which, int64_t* out);
+
+/* Diagnostic of Sec. 4 (Table 1): over the grid points of each realisation, the ratio
+ * q = (Psi_ref . r) / (Psi . r) of a reference displacement (e.g. the real-space one) to the current
+ * Psi, both projected on the line of sight; points with Psi . r = 0 or q outside [lo, hi] (the
+ * paper cuts q > 3 and q < -1) are outliers.  psi_ref: device float32 [batch][3][N^3];
+ * stats_out: host double [batch][4] = {mean q, standard deviation, outlier fraction, kept count}.
+ * Needs a computed Psi; synchronises once. */
+int recon_radial_ratio(recon_plan_t* plan, const float* psi_ref, double lo, double hi, double* stats_out);
 
 /* Copy the smoothed masked overdensity delta_s (device float32 [batch][N^3]); needs RECON_KEEP_DELTA. */
 int recon_get_delta(recon_plan_t* plan, float* out);

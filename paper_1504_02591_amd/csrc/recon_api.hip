@@ -804,7 +804,7 @@ int recon_paint(recon_plan_t* pl, int which, const float* pos, const float* w, i
   if (which == RECON_RAN && !pl->randoms) return fail(pl, RECON_EINVAL, "plan was created with RECON_NO_RANDOMS");
   if (n < 0 || (n > 0 && !pos)) return fail(pl, RECON_EINVAL, "bad catalogue pointer or count");
   if (pl->batch > 1 && !offsets && n > 0) return fail(pl, RECON_EINVAL, "offsets are required when batch > 1");
-  if (flags & ~RECON_PAINT_ACCUMULATE) return fail(pl, RECON_EINVAL, "unknown paint flag");
+  if (flags & ~(RECON_PAINT_ACCUMULATE | RECON_PAINT_NGP)) return fail(pl, RECON_EINVAL, "unknown paint flag");
   long long* grid = which == RECON_GAL ? pl->grid_g : pl->grid_r;
   const bool first = which == RECON_GAL ? !pl->painted_g : !pl->painted_r;
   int* errc = pl->err + which;   // invalid-object counter of this grid
@@ -812,7 +812,16 @@ int recon_paint(recon_plan_t* pl, int which, const float* pos, const float* w, i
     RECON_TRY(launch_fill_u64(pl, grid, pl->n3 * pl->batch));
     HIP_TRY(pl, hipMemsetAsync(errc, 0, sizeof(int), pl->stream));
   }
-  if (n > 0 && n <= pl->p.max_objects) {
+  if (n > 0 && (flags & RECON_PAINT_NGP)) {
+    long long blocks = (n + kThreads - 1) / kThreads;
+    if (blocks > 8192) blocks = 8192;
+    {
+      PROF(pl, KP_PAINT);
+      k_paint_ngp<<<(unsigned)blocks, kThreads, 0, pl->stream>>>(pos, w, n, (const long long*)offsets, pl->batch,
+                                                                 (unsigned long long*)grid, pl->cic, errc);
+    }
+    RECON_TRY(check_launch(pl, "paint (NGP)"));
+  } else if (n > 0 && n <= pl->p.max_objects) {
     // brick-binned deposit: count, scan, scatter into brick order, per-brick LDS accumulation
     long long blocks = (n + kThreads - 1) / kThreads;
     if (blocks > 8192) blocks = 8192;
@@ -1173,6 +1182,42 @@ int recon_get_grid(recon_plan_t* pl, int which, int64_t* out) {
   const long long* g = which == RECON_GAL ? pl->grid_g : pl->grid_r;
   if (!g || !(which == RECON_GAL ? pl->painted_g : pl->painted_r)) return fail(pl, RECON_ESTATE, "grid not painted");
   HIP_TRY(pl, hipMemcpyAsync(out, g, sizeof(int64_t) * pl->n3 * pl->batch, hipMemcpyDeviceToDevice, pl->stream));
+  return RECON_OK;
+}
+
+int recon_radial_ratio(recon_plan_t* pl, const float* psi_ref, double lo, double hi, double* stats_out) {
+  if (!pl) return RECON_EINVAL;
+  if (!psi_ref || !stats_out) return fail(pl, RECON_EINVAL, "NULL pointer");
+  if (!(lo <= hi)) return fail(pl, RECON_EINVAL, "need lo <= hi");
+  if (pl->state != ST_SOLVED) return fail(pl, RECON_ESTATE, "no displacement yet");
+  for (int b = 0; b < pl->batch; ++b)
+    if (!pl->psi_valid[b]) return fail(pl, RECON_ESTATE, "displacement not computed; call iterate");
+  constexpr int NT = 256;
+  long long blocks = (pl->n3 + NT - 1) / NT;
+  if (blocks > 1024) blocks = 1024;
+  k_ratio_stats<NT><<<dim3((unsigned)blocks, pl->batch), NT, 0, pl->stream>>>(
+      pl->psi, psi_ref, pl->geo, pl->n, lo, hi, pl->partials, pl->tpart);
+  RECON_TRY(check_launch(pl, "radial ratio"));
+  std::vector<double> part(2 * blocks * pl->batch);
+  std::vector<unsigned long long> cnt(blocks * pl->batch);
+  HIP_TRY(pl, hipMemcpyAsync(part.data(), pl->partials, part.size() * 8, hipMemcpyDeviceToHost, pl->stream));
+  HIP_TRY(pl, hipMemcpyAsync(cnt.data(), pl->tpart, cnt.size() * 8, hipMemcpyDeviceToHost, pl->stream));
+  HIP_TRY(pl, hipStreamSynchronize(pl->stream));
+  for (int b = 0; b < pl->batch; ++b) {
+    double s1 = 0.0, s2 = 0.0;
+    unsigned long long c = 0;
+    for (long long k = 0; k < blocks; ++k) {
+      s1 += part[2 * (b * blocks + k)];
+      s2 += part[2 * (b * blocks + k) + 1];
+      c += cnt[b * blocks + k];
+    }
+    const double mean = c ? s1 / (double)c : 0.0;
+    const double var = c ? std::fmax(s2 / (double)c - mean * mean, 0.0) : 0.0;
+    stats_out[4 * b + 0] = mean;
+    stats_out[4 * b + 1] = std::sqrt(var);
+    stats_out[4 * b + 2] = 1.0 - (double)c / (double)pl->n3;
+    stats_out[4 * b + 3] = (double)c;
+  }
   return RECON_OK;
 }
 

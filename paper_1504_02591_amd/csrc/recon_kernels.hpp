@@ -76,6 +76,40 @@ __device__ __forceinline__ int find_realisation(const long long* __restrict__ of
   return lo;
 }
 
+// Nearest-grid-point deposit in the same fixed point: the whole W_Q goes to node i + 1 when the
+// FP32 fraction is at least 1/2, else to node i (per axis, periodic).
+__global__ void __launch_bounds__(256) k_paint_ngp(const float* __restrict__ pos, const float* __restrict__ w,
+                                                   long long n, const long long* __restrict__ off, int batch,
+                                                   unsigned long long* __restrict__ grid, CicGeo g,
+                                                   int* __restrict__ err) {
+  const long long n3 = (long long)g.n * g.n * g.n;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    bool ok = true;
+    float uu[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      float d = __fsub_rn(pos[3 * i + a], g.o[a]);
+      uu[a] = __fmul_rn(d, g.s);
+      ok = ok && (fabsf(uu[a]) < 1073741824.0f);
+    }
+    const float wv = w ? w[i] : 1.0f;
+    ok = ok && (wv >= 0.0f) && (wv < 64.0f);
+    if (!ok) { atomicAdd(err, 1); continue; }
+    long long ii[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const float fl = floorf(uu[a]);
+      const float t = __fsub_rn(uu[a], fl);
+      ii[a] = ((int)fl + (t >= 0.5f ? 1 : 0)) & (g.n - 1);
+    }
+    const unsigned long long wq = w ? (unsigned long long)__double2ll_rn((double)wv * 4294967296.0)
+                                    : (1ull << 32);
+    const int b = off ? find_realisation(off, batch, i) : 0;
+    if (wq) atomicAdd(grid + (long long)b * n3 + (ii[2] * g.n + ii[1]) * g.n + ii[0], wq);
+  }
+}
+
 // Integer fixed-point CIC deposit.  Seven corners get floor(W_Q c / 2^48) and
 // corner (1,1,1) the remainder, so every object deposits exactly W_Q; integer
 // atomics make the grid independent of the order of the objects.
@@ -956,6 +990,50 @@ __global__ void __launch_bounds__(ntz<N>()) k_z_final(const float2* __restrict__
       partials[2 * ((long long)b * gridDim.x + blockIdx.x)] = t1;
       partials[2 * ((long long)b * gridDim.x + blockIdx.x) + 1] = 0.0;
     }
+  }
+}
+
+// Radial-ratio diagnostic (Sec. 4, Table 1): per cell q = (Psi_ref . r) / (Psi . r); cells with
+// Psi . r != 0 and lo <= q <= hi contribute q and q^2 (FP64 block sums into part[2 blk..]) and
+// one count (cnt[blk]).  psi_ref: planar [b][3][n^3]; blockIdx.y = realisation.
+template <int NT>
+__global__ void __launch_bounds__(NT) k_ratio_stats(const float4* __restrict__ psi4, const float* __restrict__ psi_ref,
+                                                    Geo g, int n, double lo, double hi, double* __restrict__ part,
+                                                    unsigned long long* __restrict__ cnt) {
+  const long long n3 = (long long)n * n * n;
+  const int b = blockIdx.y;
+  double s1 = 0.0, s2 = 0.0;
+  unsigned long long c = 0;
+  for (long long i = blockIdx.x * (long long)NT + threadIdx.x; i < n3; i += (long long)gridDim.x * NT) {
+    const int x = (int)(i % n), y = (int)((i / n) % n), z = (int)(i / ((long long)n * n));
+    const float rx = los_comp(g, 0, x), ry = los_comp(g, 1, y), rz = los_comp(g, 2, z);
+    const float4 p = psi4[b * n3 + i];
+    const float* q = psi_ref + b * 3 * n3;
+    const double a = (double)rx * q[i] + (double)ry * q[n3 + i] + (double)rz * q[2 * n3 + i];
+    const double d = (double)rx * p.x + (double)ry * p.y + (double)rz * p.z;
+    if (d != 0.0) {
+      const double r = a / d;
+      if (r >= lo && r <= hi) {
+        s1 += r;
+        s2 += r * r;
+        ++c;
+      }
+    }
+  }
+  double t1, t2;
+  block_sum2<NT>(s1, s2, &t1, &t2);
+  __shared__ unsigned long long cs[NT / 64];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+  if ((threadIdx.x & 63) == 0) cs[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long tc = 0;
+    for (int k = 0; k < NT / 64; ++k) tc += cs[k];
+    const long long blk = (long long)b * gridDim.x + blockIdx.x;
+    part[2 * blk] = t1;
+    part[2 * blk + 1] = t2;
+    cnt[blk] = tc;
   }
 }
 

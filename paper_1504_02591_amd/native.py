@@ -22,13 +22,13 @@ GAL, RAN = 0, 1
 START_PLAIN, START_FFTA1, START_FFTA2, START_LEARNED = 0, 1, 2, 3
 NO_RANDOMS, KEEP_DELTA, START_BUFFERS, CNN_BUFFERS, CNN_HALF, PASS_GRAPHS, LOGNORMAL = 1, 2, 4, 8, 16, 32, 64
 CNN_PARAMS = 10833
-PAINT_ACCUMULATE = 1
+PAINT_ACCUMULATE, PAINT_NGP = 1, 2
 
 EXPORTED = ("recon_workspace_bytes", "recon_plan", "recon_paint", "recon_solve", "recon_iterate",
             "recon_shift", "recon_get_psi", "recon_get_grid", "recon_get_delta", "recon_set_delta",
             "recon_destroy", "recon_strerror", "recon_last_error", "recon_profile_start",
             "recon_profile_stop", "recon_profile_kernel_name", "recon_cnn_forward", "recon_cnn_train_step",
-            "recon_get_radial", "recon_restrict", "recon_prolong")
+            "recon_get_radial", "recon_restrict", "recon_prolong", "recon_radial_ratio")
 
 
 class ReconError(RuntimeError):
@@ -83,12 +83,14 @@ def load(path=None):
                                          ctypes.POINTER(dbl), vp]
     lib.recon_get_radial.argtypes = [vp, vp]
     lib.recon_restrict.argtypes = [vp, vp, vp]
+    lib.recon_radial_ratio.argtypes = [vp, vp, dbl, dbl, ctypes.POINTER(dbl)]
     lib.recon_prolong.argtypes = [vp, vp, vp]
     lib.recon_profile_start.argtypes = [vp]
     lib.recon_profile_stop.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(dbl), ctypes.c_int]
     lib.recon_profile_kernel_name.argtypes = [ctypes.c_int]
     lib.recon_profile_kernel_name.restype = ctypes.c_char_p
     for name in ("recon_cnn_forward", "recon_cnn_train_step", "recon_get_radial", "recon_restrict", "recon_prolong",
+                 "recon_radial_ratio",
                  "recon_profile_start", "recon_profile_stop", "recon_plan", "recon_paint", "recon_solve", "recon_iterate", "recon_shift",
                  "recon_get_psi", "recon_get_grid", "recon_get_delta", "recon_set_delta"):
         getattr(lib, name).restype = ctypes.c_int
@@ -164,7 +166,7 @@ class Plan:
         msg = self.lib.recon_last_error(self.handle).decode()
         raise ReconError(rc, msg or self.lib.recon_strerror(rc).decode())
 
-    def paint(self, which, pos, w=None, offsets=None, accumulate=False):
+    def paint(self, which, pos, w=None, offsets=None, accumulate=False, ngp=False):
         _check_dev(pos, torch.float32, (3,), "pos", self.device)
         if w is not None:
             _check_dev(w, torch.float32, None, "w", self.device)
@@ -175,7 +177,17 @@ class Plan:
             if offsets.numel() != self.batch + 1:
                 raise ValueError("offsets must have batch + 1 entries")
         return self._rc(self.lib.recon_paint(self.handle, which, _ptr(pos), _ptr(w), pos.shape[0], _ptr(offsets),
-                                             PAINT_ACCUMULATE if accumulate else 0))
+                                             (PAINT_ACCUMULATE if accumulate else 0) | (PAINT_NGP if ngp else 0)))
+
+    def radial_ratio(self, psi_ref, lo=-1.0, hi=3.0):
+        """Table 1 statistic per realisation: (mean, std, outlier fraction, kept count) of
+        (psi_ref . r) / (Psi . r); psi_ref [batch, 3, n, n, n] on the device."""
+        _check_dev(psi_ref, torch.float32, None, "psi_ref", self.device)
+        if psi_ref.numel() != self.batch * 3 * self.n ** 3:
+            raise ValueError("psi_ref must hold batch * 3 * n^3 values")
+        out = (ctypes.c_double * (4 * self.batch))()
+        self._rc(self.lib.recon_radial_ratio(self.handle, _ptr(psi_ref), float(lo), float(hi), out))
+        return [tuple(out[4 * b + k] for k in range(4)) for b in range(self.batch)]
 
     def set_delta(self, delta):
         _check_dev(delta, torch.float32, None, "delta", self.device)

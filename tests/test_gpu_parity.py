@@ -284,6 +284,62 @@ def test_lognormal_option_matches_oracle(gpu_lib, survey):
     compare_full(g, r, f"lognormal survey={survey}")
 
 
+@pytest.mark.parametrize("n", [16, 64])
+def test_ngp_deposit_bitexact(gpu_lib, n):
+    from paper_1504_02591_amd import native
+    rng = np.random.default_rng(40 + n)
+    box = 300.0
+    m = 20000
+    pos = (rng.random((m, 3)) * 1.2 * box - 0.1 * box).astype(np.float32)
+    pos[:3] = np.array([[0.0, 0.0, 0.0], [box / n * 0.5, box / n * 1.5, box - 1e-3], [-box / n * 0.5, 3.0, 7.0]],
+                       dtype=np.float32)
+    w = (rng.random(m) * 5).astype(np.float32)
+    plan = native.Plan(n, box, (0.0, 0.0, -1000.0), 1.0, 0.5, 10.0, randoms=False)
+    plan.paint(native.GAL, to_dev(pos), to_dev(w), ngp=True)
+    grid = plan.grid(native.GAL)[0].cpu().numpy()
+    plan.close()
+    assert np.array_equal(grid, O.paint_ngp(pos, w, n, box, (0.0, 0.0, 0.0)))
+
+
+def test_ngp_reconstruction_matches_oracle(gpu_lib):
+    from paper_1504_02591_amd import native
+    cat = G.lattice_box(32, 500.0, (-500.0, 250.0, 250.0), 0.7, 27, 28, ran_factor=3, bias=1.2, smooth_r=20.0)
+    plan = native.plan_for(cat, keep_delta=True)
+    gal, ran = to_dev(cat.gal_pos), to_dev(cat.ran_pos)
+    plan.paint(native.GAL, gal, ngp=True)
+    plan.paint(native.RAN, ran, ngp=True)
+    plan.solve()
+    rc, iters, eps = plan.iterate(3, 0.0)
+    psi = plan.psi()[0].cpu().numpy()
+    plan.close()
+    gg = O.paint_ngp(cat.gal_pos, None, cat.n, cat.box_len, cat.origin)
+    gr = O.paint_ngp(cat.ran_pos, None, cat.n, cat.box_len, cat.origin)
+    delta = O.overdensity(gg, gr, cat.box_len, cat.smooth_r, cat.mask_tau)
+    ref = O.reconstruct_field(delta, cat.box_len, cat.origin, cat.observer, cat.bias, cat.growth, n_passes=3)
+    assert rel_l2(psi, ref["psi"]) < PSI_TOL
+    np.testing.assert_allclose(eps[0], ref["eps"], rtol=1e-4, atol=1e-6)
+
+
+def test_radial_ratio_statistic_matches_oracle(gpu_lib):
+    # Sec. 4 Table 1 statistic: the lattice's true linear displacement against Psi after one pass
+    from paper_1504_02591_amd import native
+    cat = G.lattice_box(32, 500.0, (-500.0, 250.0, 250.0), 0.7, 29, 30, ran_factor=3, bias=1.0, smooth_r=20.0)
+    _, psi_true = G.linear_field(cat.n, cat.box_len, cat.info["seed_field"])
+    plan = native.plan_for(cat)
+    plan.paint(native.GAL, to_dev(cat.gal_pos))
+    plan.paint(native.RAN, to_dev(cat.ran_pos))
+    plan.solve()
+    plan.iterate(1, 0.0)
+    stats = plan.radial_ratio(to_dev(np.ascontiguousarray(psi_true[None], dtype=np.float32)))[0]
+    plan.close()
+    r = oracle_catalogue_run(cat, 1)
+    rhat = O.line_of_sight(cat.n, cat.box_len, cat.origin, cat.observer)
+    ref = O.radial_ratio_stats(psi_true, r["psi"], rhat)
+    print(f"radial ratio gpu {stats} oracle {ref}", flush=True)
+    assert abs(stats[0] - ref[0]) < 1e-4 and abs(stats[1] - ref[1]) < 1e-4
+    assert abs(stats[3] - ref[3]) <= 2 and abs(stats[2] - ref[2]) <= 2.0 / cat.n ** 3
+
+
 def test_batched_matches_single_realisations(gpu_lib):
     from paper_1504_02591_amd import native
     cats = [G.lattice_box(32, 500.0, (-500.0, 250.0, 250.0), 0.7, 30 + i, 40 + i, ran_factor=2, bias=1.0,
