@@ -10,8 +10,9 @@ By default the network runs on the (n/2)^3 grid (RECON_CNN_HALF): training
 realisations are survey-like catalogues of the 512^3 workload's geometry, solved
 at 512^3, and delta_s, u_p and the target are restricted to the 256^3 network
 grid; inference restricts the 512^3 inputs the same way and prolongs Delta u.
-With --fine the network runs on the solver grid itself.  Test realisations use
-other seeds.
+With --fine the network runs on the solver grid itself.  Every realisation (galaxies
+only) shares one random catalogue, as a survey's realisations share its randoms.  Test
+realisations use other seeds.
 
     python -m paper_1504_02591_amd.learned --train 64 --steps 1500 --out weights.npz
 """
@@ -38,28 +39,48 @@ TRAIN_SEED, TEST_SEED = 50000, 60000
 
 
 def _catalogue(args):
+    """Galaxies of one survey realisation (no randoms: every realisation shares one random catalogue).
+
+    The linear field is drawn on a gen_n^3 grid over the benchmark box; the catalogue is reconstructed
+    on the n^3 grid."""
+    import dataclasses
     from synth import generators as G
-    i, train, n = args
+    i, train, n, gen_n = args
     base = TRAIN_SEED if train else TEST_SEED
-    cat = G.config2(n=n, scale=n / 512.0, seeds=(base + 3 * i, base + 3 * i + 1, base + 3 * i + 2))
-    return cat
+    cat = G.config2(n=gen_n, scale=n / 512.0, seeds=(base + 3 * i, base + 3 * i + 1, base + 3 * i + 2),
+                    ran_factor=0)
+    return dataclasses.replace(cat, n=n)
 
 
-def catalogue_pool(workers):
-    """Worker processes for host-side catalogue generation; create before the GPU is touched."""
-    return mp.get_context("fork").Pool(workers)
+def _randoms(n):
+    """The shared random catalogue (50x the expected galaxy count, same survey mask)."""
+    from synth import generators as G
+    # the randoms depend on the field only through the galaxy count: a coarse field suffices
+    return G.config2(n=64, scale=n / 512.0, seeds=(TRAIN_SEED - 3, TRAIN_SEED - 2, TRAIN_SEED - 1)).ran_pos
 
 
-def targets(cat, half=True, tol=1e-6, max_iter=200):
-    """(delta_s, u_p, Delta u*, passes) for one catalogue on the network grid, from the plain start
-    iterated to tol on the GPU; with half=True the fields are restricted to the (n/2)^3 grid."""
+def _init_worker(threads):
+    from synth import generators as G
+    G.WORKERS = threads
+
+
+def catalogue_pool(workers, threads=None):
+    """Worker processes for host-side catalogue generation (FFT threads split between them);
+    create before the GPU is touched."""
+    t = threads if threads is not None else max(1, 16 // max(workers, 1))
+    return mp.get_context("fork").Pool(workers, initializer=_init_worker, initargs=(t,))
+
+
+def targets(cat, ran, half=True, tol=1e-6, max_iter=200):
+    """(delta_s, u_p, Delta u*, passes) for one galaxy catalogue and the shared randoms (device
+    tensor) on the network grid, from the plain start iterated to tol on the GPU; with half=True
+    the fields are restricted to the (n/2)^3 grid."""
     dev = torch.device("cuda", torch.cuda.current_device())
-    plan = native.plan_for(cat, keep_delta=True)
+    plan = native.plan_for(cat, keep_delta=True, max_objects=max(cat.gal_pos.shape[0], ran.shape[0]))
     gal = torch.from_numpy(cat.gal_pos).to(dev)
-    ran = torch.from_numpy(cat.ran_pos).to(dev)
     plan.paint(native.GAL, gal)
     plan.paint(native.RAN, ran)
-    del gal, ran
+    del gal
     plan.solve(native.START_PLAIN)
     plan.iterate(0, 0.0)
     u_p = plan.radial()
@@ -110,13 +131,12 @@ def train(data, geom, steps, lr, seed=0, log_every=50, params=None, state=None, 
     return th.cpu().numpy(), state, log
 
 
-def passes_to_tol(cat, start, params=None, tol=1e-3, max_iter=60, half=True):
+def passes_to_tol(cat, ran, start, params=None, tol=1e-3, max_iter=60, half=True):
     dev = torch.device("cuda", torch.cuda.current_device())
     lrn = start == native.START_LEARNED
     plan = native.plan_for(cat, keep_delta=lrn, start_buffers=start != native.START_PLAIN, cnn=lrn,
-                           cnn_half=lrn and half)
+                           cnn_half=lrn and half, max_objects=max(cat.gal_pos.shape[0], ran.shape[0]))
     gal = torch.from_numpy(cat.gal_pos).to(dev)
-    ran = torch.from_numpy(cat.ran_pos).to(dev)
     plan.paint(native.GAL, gal)
     plan.paint(native.RAN, ran)
     plan.solve(start, None if params is None else torch.from_numpy(params).to(dev))
@@ -132,27 +152,33 @@ def main():
     ap.add_argument("--steps", type=int, default=1500)
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--n", type=int, default=512, help="solver grid of the realisations")
+    ap.add_argument("--gen-n", type=int, default=256, help="grid of the training realisations' linear fields")
     ap.add_argument("--fine", action="store_true", help="network on the solver grid instead of (n/2)^3")
-    ap.add_argument("--workers", type=int, default=8, help="catalogue generation processes")
+    ap.add_argument("--workers", type=int, default=16, help="catalogue generation processes")
     ap.add_argument("--out", default=WEIGHTS)
     ap.add_argument("--seed", type=int, default=0)
     args = ap.parse_args()
     half = not args.fine
     pool = catalogue_pool(args.workers)          # forked before the GPU is initialised
-    torch.cuda.set_device(0)
     t0 = time.time()
+    # held-out realisations are drawn like the benchmark's (field on the solver grid), in the background
+    test_jobs = [pool.apply_async(_catalogue, ((i, False, args.n, args.n),)) for i in range(args.test)]
+    ran_host = pool.apply_async(_randoms, (args.n,)).get()
+    torch.cuda.set_device(0)
+    ran = torch.from_numpy(ran_host).cuda()
+    print(f"[train] shared randoms: {ran.shape[0]} in {time.time() - t0:.1f}s", flush=True)
     data, geom, passes = [], None, []
-    for k, cat in enumerate(pool.imap(_catalogue, [(i, True, args.n) for i in range(args.train)])):
+    for k, cat in enumerate(pool.imap(_catalogue, [(i, True, args.n, args.gen_n) for i in range(args.train)])):
         if geom is None:
             geom = dict(box_len=cat.box_len, observer=cat.observer, bias=cat.bias, growth=cat.growth,
                         smooth_r=cat.smooth_r, origin=cat.origin)
-        d = targets(cat, half)
+        d = targets(cat, ran, half)
         data.append(d[:3])
         passes.append(d[3])
         if (k + 1) % 8 == 0:
             print(f"[train] {k + 1} targets after {time.time() - t0:.1f}s; plain passes to 1e-6: {passes[-8:]}",
                   flush=True)
-    tests = list(pool.imap(_catalogue, [(i, False, args.n) for i in range(args.test)]))
+    tests = [j.get() for j in test_jobs]
     pool.close()
     pool.join()
     t0 = time.time()
@@ -163,9 +189,9 @@ def main():
     torch.cuda.empty_cache()
     res = {"plain": [], "ffta2": [], "learned": []}
     for c in tests:
-        res["plain"].append(passes_to_tol(c, native.START_PLAIN)[0])
-        res["ffta2"].append(passes_to_tol(c, native.START_FFTA2)[0])
-        res["learned"].append(passes_to_tol(c, native.START_LEARNED, params, half=half)[0])
+        res["plain"].append(passes_to_tol(c, ran, native.START_PLAIN)[0])
+        res["ffta2"].append(passes_to_tol(c, ran, native.START_FFTA2)[0])
+        res["learned"].append(passes_to_tol(c, ran, native.START_LEARNED, params, half=half)[0])
     print("[train] held-out passes to 1e-3:", json.dumps(res), flush=True)
     os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
     np.savez(args.out, params=params, adam_m=state["m"], adam_v=state["v"], step=state["step"],

@@ -273,14 +273,14 @@ def survey(n, box_len, bias, growth, smooth_r, r_min, r_max, omega, n_target, ra
                      smooth_r=smooth_r, info=info)
 
 
-def config2(n=512, scale=1.0, seeds=(201, 202, 203), n_target=7.0e5):
+def config2(n=512, scale=1.0, seeds=(201, 202, 203), n_target=7.0e5, ran_factor=50):
     """Survey-like 512^3 / 3500 Mpc/h box, observer at the centre, cone of 2.5 sr, 1100-1800 Mpc/h.
 
     scale < 1 shrinks the box and the shell together (same cell size when n is scaled too).
     """
     return survey(n, 3500.0 * scale, bias=2.0, growth=0.74, smooth_r=15.0,
                   r_min=1100.0 * scale, r_max=1800.0 * scale, omega=2.5,
-                  n_target=n_target * scale ** 3, ran_factor=50,
+                  n_target=n_target * scale ** 3, ran_factor=ran_factor,
                   seed_field=seeds[0], seed_gal=seeds[1], seed_ran=seeds[2])
 
 
