@@ -34,7 +34,7 @@ struct Layout {
          corr = 0, tw = 0, partials = 0, red = 0, totals = 0, thr = 0, dscal = 0, act = 0, err = 0, total = 0,
          sorted = 0, bcount = 0, bstart = 0, bcursor = 0, bsum = 0, status = 0, tpart = 0;
   // network buffers
-  size_t a1 = 0, a2 = 0, d1 = 0, d2 = 0, ybuf = 0, dybuf = 0, upbuf = 0, wk1 = 0, wk2 = 0, wk2t = 0, w3 = 0,
+  size_t a1 = 0, a2 = 0, d1 = 0, d2 = 0, ybuf = 0, dybuf = 0, upbuf = 0, wk2t = 0, w3 = 0,
          part_out = 0, part_w1 = 0, part_w2 = 0, g1 = 0, g2 = 0, g3 = 0, grad = 0, lossp = 0, losst = 0, dc = 0, uc = 0,
          wf1 = 0, wf2 = 0;
   long long nb_conv = 0, nb_w = 0, nb_loss = 0;
@@ -127,8 +127,6 @@ Layout make_layout(const recon_params_t* p) {
       L.dc = take(b * m3 * 4);
       L.uc = take(b * m3 * 4);
     }
-    L.wk1 = take(CH * K1P * 2);
-    L.wk2 = take(CH * K2 * 2);
     L.wk2t = take(CH * K2 * 2);
     L.w3 = take(K2 * 4);
     L.wf1 = take(9 * 64 * 16);
@@ -188,7 +186,7 @@ struct recon_plan_s {
   DeltaScal* dscal = nullptr;
   int *act_fan = nullptr, *act_fin = nullptr, *act_it = nullptr, *err = nullptr;
   float4* sorted = nullptr;
-  unsigned short *a1 = nullptr, *a2 = nullptr, *d1 = nullptr, *d2 = nullptr, *wk1 = nullptr, *wk2 = nullptr,
+  unsigned short *a1 = nullptr, *a2 = nullptr, *d1 = nullptr, *d2 = nullptr,
                  *wk2t = nullptr;
   float *ybuf = nullptr, *dybuf = nullptr, *upbuf = nullptr, *w3 = nullptr, *part_out = nullptr,
         *part_w1 = nullptr, *part_w2 = nullptr, *g1 = nullptr, *g2 = nullptr, *g3 = nullptr, *gradbuf = nullptr,
@@ -577,7 +575,7 @@ int cnn_forward_impl(recon_plan_t* pl, const float* params, const float* delta, 
   const dim3 grid((unsigned)pl->L.nb_conv, pl->batch);
   const Geo3 g = cnn_geo(pl);
   PROF(pl, KP_CNN_FWD);
-  k_prep_weights<<<64, 256, 0, pl->stream>>>(params, pl->wk1, pl->wk2, pl->wk2t, pl->w3);
+  k_prep_weights<<<32, 256, 0, pl->stream>>>(params, pl->wk2t, pl->w3);
   k_prep_frag<<<(27 * 64 + 255) / 256, 256, 0, pl->stream>>>(params, pl->wf1, pl->wf2);
   const dim3 gridf((unsigned)(pl->cnn_n3 / (FX * FY * FZ)), pl->batch);
   k_conv_fwd<CIN, 1><<<gridf, 256, 0, pl->stream>>>(nullptr, delta, up, g, pl->wf1, params + OFF_B1, pl->a1);
@@ -715,8 +713,6 @@ int recon_plan(recon_plan_t** out, const recon_params_t* params, void* workspace
       pl->dc = (float*)(w + L.dc);
       pl->uc = (float*)(w + L.uc);
     }
-    pl->wk1 = (unsigned short*)(w + L.wk1);
-    pl->wk2 = (unsigned short*)(w + L.wk2);
     pl->wk2t = (unsigned short*)(w + L.wk2t);
     pl->w3 = (float*)(w + L.w3);
     pl->part_out = (float*)(w + L.part_out);

@@ -10,11 +10,13 @@
 // Parameter vector (FP32, device): W1 [16][27][8], b1 [16], W2 [16][27][16], b2 [16],
 // W3 [1][27][16], b3 [1]; tap t = (dz+1)*9 + (dy+1)*3 + (dx+1), offset (dx, dy, dz).
 //
-// Convolutions are implicit GEMMs on v_mfma_f32_16x16x16bf16_1k: M = 16 output
-// positions (one x row of a 16 x 4 x 4 output tile), N = 16 output channels,
-// K = 27 taps x C_in input channels in blocks of 16.  Operand layout of that
-// instruction: lane l holds A[l%16][4(l/16)+0..3], B[4(l/16)+0..3][l%16], and the
-// result D[4(l/16)+0..3][l%16].
+// Forward convolutions (k_conv_fwd, k_conv_out_mfma) are implicit GEMMs on
+// v_mfma_f32_16x16x32_bf16 over 16 x 8 x 8 output tiles (see there).  The training
+// kernels (data gradient k_conv16, weight gradient k_wgrad16) use v_mfma_f32_16x16x16bf16_1k:
+// M = 16 output positions (one x row of a 16 x 4 x 4 output tile), N = 16 output channels,
+// K = 27 taps x C_in input channels in blocks of 16.  Operand layout of that instruction:
+// lane l holds A[l%16][4(l/16)+0..3], B[4(l/16)+0..3][l%16], and the result
+// D[4(l/16)+0..3][l%16].
 #pragma once
 
 #include "recon_kernels.hpp"
@@ -392,31 +394,6 @@ __global__ void __launch_bounds__(256) k_conv_out_mfma(const unsigned short* __r
                                         (acc[3] + bb) * scale);
 }
 
-// Output layer (16 -> 1) on VALU: y = b3 + sum_t sum_i W3[t][i] a2[p + d_t][i]; y_out FP32.
-// scale multiplies the result (1 for training, 1/S_U to write Delta u directly).
-__global__ void __launch_bounds__(256) k_conv_out(const unsigned short* __restrict__ a2, Geo3 g,
-                                                  const float* __restrict__ w3, const float* __restrict__ b3,
-                                                  float scale, float* __restrict__ y_out) {
-  __shared__ unsigned short tile[HCELLS * CH];
-  __shared__ float w[27 * CH];
-  const long long n3 = (long long)g.n * g.n * g.n;
-  const int b = blockIdx.y;
-  int x0, y0, z0;
-  tile_origin(g.n, x0, y0, z0);
-  stage_bf16<CH>(tile, a2 + b * n3 * CH, g.n, x0, y0, z0);
-  for (int i = threadIdx.x; i < 27 * CH; i += 256) w[i] = w3[i];
-  __syncthreads();
-  const int m = threadIdx.x % TX, yr = (threadIdx.x / TX) % TY, zr = threadIdx.x / (TX * TY);
-  float acc = b3[0];
-  for (int t = 0; t < 27; ++t) {
-    const unsigned short* a = tile + tap_cell(zr, yr, m, t) * CH;
-#pragma unroll
-    for (int i = 0; i < CH; ++i) acc = fmaf(w[t * CH + i], from_bf16(a[i]), acc);
-  }
-  const long long cell = ((long long)(z0 + zr) * g.n + (y0 + yr)) * g.n + x0 + m;
-  y_out[b * n3 + cell] = acc * scale;
-}
-
 // Loss residual: r = y - S_U target; dy = 2 r / count; per-block partial of sum r^2.
 __global__ void __launch_bounds__(256) k_loss(const float* __restrict__ y, const float* __restrict__ target,
                                               long long count, float* __restrict__ dy, double* __restrict__ partial) {
@@ -586,23 +563,16 @@ __global__ void __launch_bounds__(256) k_reduce_loss(const double* __restrict__ 
 // Weights in MFMA layouts: wk1 [16][K1P] (k = t*8 + i), wk2 [16][432] (k = t*16 + i),
 // wk2t [16][432] with wk2t[i][t*16 + o] = W2[o][26 - t][i] (flipped taps, transposed
 // channels: the data gradient as a forward convolution), w3 [432] as bf16-rounded FP32.
-__global__ void __launch_bounds__(256) k_prep_weights(const float* __restrict__ th, unsigned short* __restrict__ wk1,
-                                                      unsigned short* __restrict__ wk2, unsigned short* __restrict__ wk2t,
+__global__ void __launch_bounds__(256) k_prep_weights(const float* __restrict__ th, unsigned short* __restrict__ wk2t,
                                                       float* __restrict__ w3) {
-  for (int e = blockIdx.x * 256 + threadIdx.x; e < CH * K1P + 2 * CH * K2 + K2; e += gridDim.x * 256) {
-    if (e < CH * K1P) {
-      const int o = e / K1P, k = e % K1P;
-      wk1[e] = k < K1 ? to_bf16(th[OFF_W1 + o * K1 + k]) : (unsigned short)0;
-    } else if (e < CH * K1P + CH * K2) {
-      const int f = e - CH * K1P;
-      wk2[f] = to_bf16(th[OFF_W2 + f]);
-    } else if (e < CH * K1P + 2 * CH * K2) {
-      const int f = e - CH * K1P - CH * K2;
-      const int i = f / K2, k = f % K2, t = k / CH, o = k % CH;
-      wk2t[f] = to_bf16(th[OFF_W2 + (o * 27 + (26 - t)) * CH + i]);
+  // wk2t: layer-2 weights flipped and transposed for the data gradient, [16 in][27 x 16 out] bf16;
+  // w3: layer-3 weights rounded to bf16 (FP32 storage) for the output-layer backward
+  for (int e = blockIdx.x * 256 + threadIdx.x; e < CH * K2 + K2; e += gridDim.x * 256) {
+    if (e < CH * K2) {
+      const int i = e / K2, k = e % K2, t = k / CH, o = k % CH;
+      wk2t[e] = to_bf16(th[OFF_W2 + (o * 27 + (26 - t)) * CH + i]);
     } else {
-      const int f = e - CH * K1P - 2 * CH * K2;
-      w3[f] = from_bf16(to_bf16(th[OFF_W3 + f]));
+      w3[e - CH * K2] = from_bf16(to_bf16(th[OFF_W3 + e - CH * K2]));
     }
   }
 }

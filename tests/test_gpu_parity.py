@@ -245,6 +245,18 @@ def test_config1_end_to_end(gpu_lib):
     compare_full(g, r, "config1")
 
 
+def test_precision_study_subrun(gpu_lib):
+    # the precision-study geometry (L = 2000, f = 0.76, b = 1, distant observer 5000 Mpc/h from the
+    # centre, lattice of Zel'dovich particles, no randoms) on its 128^3 sub-run: FP32 GPU vs FP64 oracle
+    from paper_1504_02591_amd import native
+    cat = G.config3(128)
+    g = gpu_catalogue_run(native, cat, 6)
+    r = oracle_catalogue_run(cat, 6)
+    e = rel_l2(g["psi"], r["psi"])
+    print(f"precision study 128^3: Psi rel L2 (FP32 GPU vs FP64 oracle) = {e:.3e}", flush=True)
+    compare_full(g, r, "precision-study 128^3")
+
+
 def test_survey_cone_small(gpu_lib):
     from paper_1504_02591_amd import native
     cat = G.config2(n=128, scale=0.25)
