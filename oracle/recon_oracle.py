@@ -57,6 +57,9 @@ R13 Shift: galaxies move by -Psi - f (Psi.r) r, randoms by -Psi, with Psi
     interpolated to the object by the same CIC stencil.
 R14 FFTA starts with beta in place of f: c = beta/(1+beta) (eq. approx1) or
     3 beta/(7 + 3 beta) (eq. approx2).
+R17 Helmholtz split (Sec. 4.1): the projection k_x k_j / k^2 uses the derivative wavenumbers
+    (zero at each axis's Nyquist index, R7) and the full k^2; the k = 0 mode (the mean of Psi.x)
+    goes to the solenoidal part; the solenoidal part is the remainder (Psi.x) x - irrotational.
 R16 NGP option: the paper bins with NGP (Sec. 3.1); node i+1 when the FP32 fraction is >= 1/2.
     The shift keeps the CIC interpolation of R13.
 R15 Lognormal option (Sec. 6, eq. logdelta): the smoothed, masked delta_s is replaced by
@@ -498,3 +501,19 @@ def radial_ratio_stats(psi_ref, psi, rhat, lo=-1.0, hi=3.0):
     if r.size == 0:
         return 0.0, 0.0, 1.0, 0
     return float(r.mean()), float(r.std()), float(1.0 - keep.mean()), int(r.size)
+
+
+def helmholtz_x(psi_x, box_len):
+    """Sec. 4.1, eq. (irrotational) and eq. (solenoidal): split of the plane-parallel RSD field
+    (Psi.x) x into its irrotational part, IFFT[k_x k_j / k^2 FFT(Psi.x)], and the solenoidal
+    remainder (R17).  Returns (irrotational (3,n,n,n), solenoidal (3,n,n,n))."""
+    n = psi_x.shape[0]
+    kx, ky, kz, dkx, dky, dkz = wavenumbers(n, box_len)
+    k2 = kx * kx + ky * ky + kz * kz
+    px = fwd(psi_x)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        proj = np.where(k2 > 0, dkx * px / k2, 0.0)
+    irr = np.stack([inv(d * proj, n) for d in (dkx, dky, dkz)])
+    sol = -irr
+    sol[0] += psi_x
+    return irr, sol

@@ -496,3 +496,36 @@ def test_radial_ratio_stats_hand_values():
     m, sd, out, cnt = O.radial_ratio_stats(ref, psi, rhat)
     assert cnt == n ** 3 - 3 and abs(out - 3 / n ** 3) < 1e-15
     assert abs(m - 1.0) < 1e-12 and sd < 1e-12
+
+
+def test_helmholtz_split_of_plane_wave():
+    """Sec. 4.1: for (Psi.x) x = cos(k.x + p) x the irrotational part is (k_x k_j / k^2) cos(k.x + p)."""
+    n, box = 16, 200.0
+    for modes in [(1, 0, 0), (2, 3, -1), (0, 4, 1)]:
+        f, k0 = G.plane_wave(n, box, modes, 1.0, 0.3)
+        irr, sol = O.helmholtz_x(f, box)
+        kk = float(k0 @ k0)
+        for j in range(3):
+            np.testing.assert_allclose(irr[j], k0[0] * k0[j] / kk * f, atol=1e-12)
+        np.testing.assert_allclose(sol[0], f - irr[0], atol=1e-14)
+
+
+def test_helmholtz_parts_are_curl_and_divergence_free():
+    """curl of the irrotational part and divergence of the solenoidal part vanish (band-limited field)."""
+    n, box = 16, 160.0
+    rng = np.random.default_rng(33)
+    fk = O.fwd(rng.standard_normal((n, n, n)))
+    kx, ky, kz, dkx, dky, dkz = O.wavenumbers(n, box)
+    m = 2 * np.pi / box
+    band = (np.abs(kx) < (n // 2 - 1) * m) & (np.abs(ky) < (n // 2 - 1) * m) & (np.abs(kz) < (n // 2 - 1) * m)
+    f = O.inv(fk * band, n)
+    irr, sol = O.helmholtz_x(f, box)
+    d = (dkx, dky, dkz)
+    ik = [O.fwd(irr[j]) for j in range(3)]
+    sk = [O.fwd(sol[j]) for j in range(3)]
+    scale = np.abs(fk).max()
+    for a, b in ((0, 1), (1, 2), (2, 0)):
+        assert np.abs(d[a] * ik[b] - d[b] * ik[a]).max() < 1e-11 * scale
+    assert np.abs(sum(d[j] * sk[j] for j in range(3))).max() < 1e-11 * scale
+    np.testing.assert_allclose(irr[0] + sol[0], f, atol=1e-13)
+    np.testing.assert_allclose(irr[1] + sol[1], 0.0, atol=1e-13)
