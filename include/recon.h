@@ -156,6 +156,14 @@ int recon_get_grid(recon_plan_t* plan, int which, int64_t* out);
  * Needs a computed Psi; synchronises once. */
 int recon_radial_ratio(recon_plan_t* plan, const float* psi_ref, double lo, double hi, double* stats_out);
 
+/* Diagnostic of Sec. 4.1 (eq. irrotational, eq. solenoidal): split the plane-parallel RSD field
+ * (Psi.x) x of a real field psi_x = Psi.x (device float32 [batch][N^3]) into its irrotational part,
+ * IFFT[k_x k_j / k^2 FFT(psi_x)] (derivative wavenumbers, zero at each axis's Nyquist index; the
+ * k = 0 mode to the solenoidal part), and the solenoidal remainder psi_x x - irrotational.
+ * irr_out, sol_out: device float32 [batch][3][N^3] (sol_out may be NULL).  Uses the plan's transform
+ * buffers: afterwards the plan must be painted (or given delta_s) and solved again. */
+int recon_helmholtz(recon_plan_t* plan, const float* psi_x, float* irr_out, float* sol_out);
+
 /* Copy the smoothed masked overdensity delta_s (device float32 [batch][N^3]); needs RECON_KEEP_DELTA. */
 int recon_get_delta(recon_plan_t* plan, float* out);
 

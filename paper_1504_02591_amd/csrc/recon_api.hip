@@ -281,6 +281,7 @@ struct Ops {
   int (*fanin_xiter)(recon_plan_t*, bool first, const int*);
   int (*zfinal)(recon_plan_t*, float4* psi, float* u, bool cross, const int*);
   int (*refan)(recon_plan_t*, const int*);  // state X again from D_n
+  int (*helm)(recon_plan_t*, const float*);  // fan-out of the Helmholtz projection of a real field
   int nb_x, nb_z;
 };
 
@@ -414,6 +415,18 @@ struct SizeOps {
     return finish_start(pl);
   }
 
+  // z and y forward of the field, then the HELM x start: the plan's fan-out state becomes that of
+  // the irrotational projection (with the opposite sign)
+  static int helm(recon_plan_t* pl, const float* f) {
+    hipStream_t s = pl->stream;
+    k_z_fwd_real<N><<<gz(pl), dim3(TZ), 0, s>>>(f, pl->w0, pl->tw);
+    RECON_TRY(check_launch(pl, "z forward (Helmholtz)"));
+    k_y_plain<N, 1, false><<<gy(pl), dim3(TY), 0, s>>>(pl->w0, nullptr, pl->tw);
+    RECON_TRY(check_launch(pl, "y forward (Helmholtz)"));
+    k_x_start<N, true><<<gx(pl), dim3(TX), 0, s>>>(pl->w0, pl->w1, pl->ds, pl->geo, pl->tw);
+    return check_launch(pl, "x start (Helmholtz)");
+  }
+
   static int refan(recon_plan_t* pl, const int* act) {
     {
       PROF(pl, KP_X_START);
@@ -497,7 +510,7 @@ struct SizeOps {
   }
 
   static const Ops* table() {
-    static const Ops ops = {setup, setup_delta, fanout, ziter, fanin_xiter, zfinal, refan,
+    static const Ops ops = {setup, setup_delta, fanout, ziter, fanin_xiter, zfinal, refan, helm,
                             (int)((N / 2 + 1) * N / WX), (int)(N * (N / (2 * WZ)))};
     return &ops;
   }
@@ -1213,6 +1226,30 @@ int recon_radial_ratio(recon_plan_t* pl, const float* psi_ref, double lo, double
     stats_out[4 * b + 1] = std::sqrt(var);
     stats_out[4 * b + 2] = 1.0 - (double)c / (double)pl->n3;
     stats_out[4 * b + 3] = (double)c;
+  }
+  return RECON_OK;
+}
+
+int recon_helmholtz(recon_plan_t* pl, const float* psi_x, float* irr_out, float* sol_out) {
+  if (!pl) return RECON_EINVAL;
+  if (!psi_x || !irr_out) return fail(pl, RECON_EINVAL, "NULL pointer");
+  const Ops* ops = ops_for(pl->n);
+  RECON_TRY(ops->helm(pl, psi_x));
+  for (int b = 0; b < pl->batch; ++b) pl->h_fan[b] = 1;
+  RECON_TRY(upload_mask(pl, pl->act_fan, pl->h_fan));
+  RECON_TRY(ops->fanout(pl, pl->act_fan));
+  RECON_TRY(upload_mask(pl, pl->act_fin, pl->h_fan));
+  RECON_TRY(ops->zfinal(pl, pl->psi, nullptr, false, pl->act_fin));
+  long long nb = (pl->n3 * pl->batch + 255) / 256;
+  if (nb > 65536) nb = 65536;
+  k_helm_out<<<(unsigned)nb, 256, 0, pl->stream>>>(pl->psi, psi_x, pl->n3, pl->batch, irr_out, sol_out);
+  RECON_TRY(check_launch(pl, "Helmholtz output"));
+  // the transform buffers, D_s and Psi now hold the diagnostic: the reconstruction starts over
+  pl->state = ST_EMPTY;
+  pl->painted_g = pl->painted_r = false;
+  for (int b = 0; b < pl->batch; ++b) {
+    pl->psi_valid[b] = 0;
+    pl->st_y[b] = 0;
   }
   return RECON_OK;
 }

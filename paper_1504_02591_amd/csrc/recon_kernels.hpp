@@ -1243,7 +1243,9 @@ __global__ void __launch_bounds__(ntx<N>()) k_x_smooth(float2* __restrict__ a0, 
 
 // Forward x of the overdensity -> D_s (stored); P = D_s / (b k^2 N^3);
 // a0 <- X^-1[i k'_x P], a1 <- X^-1[P].
-template <int N>
+// HELM: the transformed field F is first multiplied by i k'_x and P = i k'_x F / (k^2 N^3); the
+// fan-out then yields IFFT[-k'_j k'_x F / k^2], minus the irrotational part of (F) x (Sec. 4.1).
+template <int N, bool HELM = false>
 __global__ void __launch_bounds__(ntx<N>()) k_x_start(float2* __restrict__ a0, float2* __restrict__ a1,
                                                       float2* __restrict__ ds, Geo g, const float2* __restrict__ twg) {
   constexpr int NT = ntx<N>(), W = wx<N>();
@@ -1268,7 +1270,8 @@ __global__ void __launch_bounds__(ntx<N>()) k_x_start(float2* __restrict__ a0, f
       float k2, dx, dy, dz;
       int kzi;
       x_wavenumbers<N>(row, j + r * (N / 8), g.kf, k2, dx, dy, dz, kzi);
-      pr[r] = k2 > 0.f ? v[r] * (g.inv_bn3 / k2) : make_float2(0.f, 0.f);
+      if (HELM) v[r] = mul_i(v[r]) * dx;
+      pr[r] = k2 > 0.f ? v[r] * ((HELM ? g.inv_n3 : g.inv_bn3) / k2) : make_float2(0.f, 0.f);
       v[r] = mul_i(pr[r]) * dx;
     }
   }
@@ -1313,6 +1316,26 @@ __global__ void __launch_bounds__(ntx<N>()) k_x_refan(float2* __restrict__ a0, f
   if (act) x_store<N>(v, a0, row, j);
   fft_rr<N, W, true, true>(pr, buf, tw);
   if (act) x_store<N>(pr, a1, row, j);
+}
+
+// Helmholtz split output: irrotational = -Psi (the fan-out of the HELM start), solenoidal =
+// f x - irrotational; planar [b][3][n^3]; sol may be null.
+__global__ void __launch_bounds__(256) k_helm_out(const float4* __restrict__ psi4, const float* __restrict__ f,
+                                                  long long n3, int batch, float* __restrict__ irr,
+                                                  float* __restrict__ sol) {
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n3 * batch; i += (long long)gridDim.x * 256) {
+    const long long b = i / n3, c = i - b * n3;
+    const float4 p = psi4[i];
+    const float ix = -p.x, iy = -p.y, iz = -p.z;
+    irr[(b * 3 + 0) * n3 + c] = ix;
+    irr[(b * 3 + 1) * n3 + c] = iy;
+    irr[(b * 3 + 2) * n3 + c] = iz;
+    if (sol) {
+      sol[(b * 3 + 0) * n3 + c] = f[i] - ix;
+      sol[(b * 3 + 1) * n3 + c] = -iy;
+      sol[(b * 3 + 2) * n3 + c] = -iz;
+    }
+  }
 }
 
 // One iteration's k-space step:

@@ -28,7 +28,7 @@ EXPORTED = ("recon_workspace_bytes", "recon_plan", "recon_paint", "recon_solve",
             "recon_shift", "recon_get_psi", "recon_get_grid", "recon_get_delta", "recon_set_delta",
             "recon_destroy", "recon_strerror", "recon_last_error", "recon_profile_start",
             "recon_profile_stop", "recon_profile_kernel_name", "recon_cnn_forward", "recon_cnn_train_step",
-            "recon_get_radial", "recon_restrict", "recon_prolong", "recon_radial_ratio")
+            "recon_get_radial", "recon_restrict", "recon_prolong", "recon_radial_ratio", "recon_helmholtz")
 
 
 class ReconError(RuntimeError):
@@ -84,13 +84,14 @@ def load(path=None):
     lib.recon_get_radial.argtypes = [vp, vp]
     lib.recon_restrict.argtypes = [vp, vp, vp]
     lib.recon_radial_ratio.argtypes = [vp, vp, dbl, dbl, ctypes.POINTER(dbl)]
+    lib.recon_helmholtz.argtypes = [vp, vp, vp, vp]
     lib.recon_prolong.argtypes = [vp, vp, vp]
     lib.recon_profile_start.argtypes = [vp]
     lib.recon_profile_stop.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(dbl), ctypes.c_int]
     lib.recon_profile_kernel_name.argtypes = [ctypes.c_int]
     lib.recon_profile_kernel_name.restype = ctypes.c_char_p
     for name in ("recon_cnn_forward", "recon_cnn_train_step", "recon_get_radial", "recon_restrict", "recon_prolong",
-                 "recon_radial_ratio",
+                 "recon_radial_ratio", "recon_helmholtz",
                  "recon_profile_start", "recon_profile_stop", "recon_plan", "recon_paint", "recon_solve", "recon_iterate", "recon_shift",
                  "recon_get_psi", "recon_get_grid", "recon_get_delta", "recon_set_delta"):
         getattr(lib, name).restype = ctypes.c_int
@@ -188,6 +189,18 @@ class Plan:
         out = (ctypes.c_double * (4 * self.batch))()
         self._rc(self.lib.recon_radial_ratio(self.handle, _ptr(psi_ref), float(lo), float(hi), out))
         return [tuple(out[4 * b + k] for k in range(4)) for b in range(self.batch)]
+
+    def helmholtz(self, psi_x):
+        """Sec. 4.1 split of (psi_x) x: (irrotational, solenoidal), each [batch, 3, n, n, n].
+        Resets the plan (paint or set_delta and solve again afterwards)."""
+        _check_dev(psi_x, torch.float32, None, "psi_x", self.device)
+        if psi_x.numel() != self.batch * self.n ** 3:
+            raise ValueError("psi_x must hold batch * n^3 values")
+        shape = (self.batch, 3, self.n, self.n, self.n)
+        irr = torch.empty(shape, dtype=torch.float32, device=self.device)
+        sol = torch.empty(shape, dtype=torch.float32, device=self.device)
+        self._rc(self.lib.recon_helmholtz(self.handle, _ptr(psi_x), _ptr(irr), _ptr(sol)))
+        return irr, sol
 
     def set_delta(self, delta):
         _check_dev(delta, torch.float32, None, "delta", self.device)
