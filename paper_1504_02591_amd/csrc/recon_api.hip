@@ -311,7 +311,7 @@ int log_constant(recon_plan_t* pl, int blocks) {
   if (!(pl->p.flags & RECON_LOGNORMAL) || !pl->delta) return RECON_OK;
   {
     PROF(pl, KP_REDUCE);
-    k_reduce_pairs<<<pl->batch, kThreads, 0, pl->stream>>>(pl->partials, blocks, pl->red + 2 * pl->batch);
+    k_reduce_pairs<<<pl->batch, 1024, 0, pl->stream>>>(pl->partials, blocks, pl->red + 2 * pl->batch);
   }
   RECON_TRY(check_launch(pl, "reduce (log mean)"));
   long long nb = (pl->n3 * pl->batch + 255) / 256;
@@ -464,7 +464,7 @@ struct SizeOps {
     if (mode != ZI_PLAIN) {
       {
         PROF(pl, KP_REDUCE);
-        k_reduce_pairs<<<pl->batch, kThreads, 0, s>>>(pl->partials, (int)gz(pl).x, pl->red + 2 * pl->batch);
+        k_reduce_pairs<<<pl->batch, 1024, 0, s>>>(pl->partials, (int)gz(pl).x, pl->red + 2 * pl->batch);
       }
       RECON_TRY(check_launch(pl, "reduce (start sums)"));
     }
@@ -486,7 +486,7 @@ struct SizeOps {
     RECON_TRY(check_launch(pl, "x iteration"));
     {
       PROF(pl, KP_REDUCE);
-      k_reduce_pairs<<<pl->batch, kThreads, 0, s>>>(pl->partials, (int)gx(pl).x, pl->red);
+      k_reduce_pairs<<<pl->batch, 1024, 0, s>>>(pl->partials, (int)gx(pl).x, pl->red);
     }
     return check_launch(pl, "reduce (norm)");
   }
@@ -502,7 +502,7 @@ struct SizeOps {
     if (cross) {
       {
         PROF(pl, KP_REDUCE);
-        k_reduce_pairs<<<pl->batch, kThreads, 0, s>>>(pl->partials, (int)gz(pl).x, pl->red + 2 * pl->batch);
+        k_reduce_pairs<<<pl->batch, 1024, 0, s>>>(pl->partials, (int)gz(pl).x, pl->red + 2 * pl->batch);
       }
       RECON_TRY(check_launch(pl, "reduce (cross sum)"));
     }

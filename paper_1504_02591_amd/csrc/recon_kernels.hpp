@@ -736,11 +736,23 @@ __global__ void __launch_bounds__(ntz<N>()) k_z_delta(float2* __restrict__ a0, c
   const DeltaScal s = sc[b];
   double lsum = 0.0;
   float2 gv[8], v[8];
-  if (act) z_pack_frag<N, WP>(gv, a0, y, x0, c, j);
-  fft_rr<N, WP, true, false>(gv, buf, tw);
   if constexpr (NA == 2) {
-    if (act) z_pack_frag<N, WP>(v, a1 + b * cn, y, x0, c, j);
+    // the second array is staged in LDS by direct loads while the first is transformed
+    __shared__ float2 stage[ZStage<N, WP>::SIZE];
+    z_stage_issue<N, WP, NT>(stage, a0, y, x0);
+    z_stage_wait();
+    __syncthreads();
+    if (act) z_pack_stage<N, WP>(gv, stage, c, j);
+    __syncthreads();
+    z_stage_issue<N, WP, NT>(stage, a1 + b * cn, y, x0);
+    fft_rr<N, WP, true, false>(gv, buf, tw);
+    z_stage_wait();
+    __syncthreads();
+    if (act) z_pack_stage<N, WP>(v, stage, c, j);
     fft_rr<N, WP, true, false>(v, buf, tw);
+  } else {
+    if (act) z_pack_frag<N, WP>(gv, a0, y, x0, c, j);
+    fft_rr<N, WP, true, false>(gv, buf, tw);
   }
   if (act) {
 #pragma unroll
@@ -1410,17 +1422,29 @@ __global__ void __launch_bounds__(ntx<N>()) k_x_iter(float2* __restrict__ a0, fl
 }
 
 // Fixed-order reduction of per-block partial pairs: out[b] = sum over blocks.
-__global__ void __launch_bounds__(256) k_reduce_pairs(const double* __restrict__ partials, int nblk,
-                                                      double* __restrict__ out) {
-  constexpr int NT = kThreads;
+__global__ void __launch_bounds__(1024) k_reduce_pairs(const double* __restrict__ partials, int nblk,
+                                                       double* __restrict__ out) {
+  // one block per realisation; four independent accumulators per thread keep many loads in flight
+  constexpr int NT = 1024;
   const int b = blockIdx.x;
-  double s0 = 0.0, s1 = 0.0;
-  for (int i = threadIdx.x; i < nblk; i += kThreads) {
-    s0 += partials[2 * ((long long)b * nblk + i)];
-    s1 += partials[2 * ((long long)b * nblk + i) + 1];
+  const double2* p = (const double2*)partials + (long long)b * nblk;
+  double s0[4] = {0.0, 0.0, 0.0, 0.0}, s1[4] = {0.0, 0.0, 0.0, 0.0};
+  int i = threadIdx.x;
+  for (; i + 3 * NT < nblk; i += 4 * NT) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const double2 v = p[i + k * NT];
+      s0[k] += v.x;
+      s1[k] += v.y;
+    }
+  }
+  for (; i < nblk; i += NT) {
+    const double2 v = p[i];
+    s0[0] += v.x;
+    s1[0] += v.y;
   }
   double t0, t1;
-  block_sum2<NT>(s0, s1, &t0, &t1);
+  block_sum2<NT>((s0[0] + s0[1]) + (s0[2] + s0[3]), (s1[0] + s1[1]) + (s1[2] + s1[3]), &t0, &t1);
   if (threadIdx.x == 0) { out[2 * b] = t0; out[2 * b + 1] = t1; }
 }
 
