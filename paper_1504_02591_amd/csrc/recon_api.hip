@@ -844,7 +844,7 @@ int recon_paint(recon_plan_t* pl, int which, const float* pos, const float* w, i
     {
       PROF(pl, KP_BIN);
       if (lds_bins)
-        k_bin_count_lds<<<(unsigned)lblocks, 256, 0, pl->stream>>>(pos, w, n, chunk, (const long long*)offsets,
+        k_bin_count_lds<1024><<<(unsigned)lblocks, 1024, 0, pl->stream>>>(pos, w, n, chunk, (const long long*)offsets,
                                                                    pl->batch, pl->cic, pl->bcount, errc);
       else
         k_bin_count<<<(unsigned)blocks, kThreads, 0, pl->stream>>>(pos, w, n, (const long long*)offsets, pl->batch,
@@ -862,7 +862,7 @@ int recon_paint(recon_plan_t* pl, int which, const float* pos, const float* w, i
     {
       PROF(pl, KP_BIN);
       if (lds_bins)
-        k_bin_scatter_lds<<<(unsigned)lblocks, 256, 0, pl->stream>>>(pos, w, n, chunk, (const long long*)offsets,
+        k_bin_scatter_lds<1024><<<(unsigned)lblocks, 1024, 0, pl->stream>>>(pos, w, n, chunk, (const long long*)offsets,
                                                                      pl->batch, pl->cic, pl->bcursor, pl->sorted);
       else
         k_bin_scatter<<<(unsigned)blocks, kThreads, 0, pl->stream>>>(pos, w, n, (const long long*)offsets,

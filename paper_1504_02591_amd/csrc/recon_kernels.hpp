@@ -239,7 +239,8 @@ __global__ void __launch_bounds__(256) k_bin_scatter(const float* __restrict__ p
 // Count with a per-block LDS histogram over the bins of the realisation that owns the
 // chunk's first object; one global atomic per (block, non-empty bin).  Objects whose bin
 // lies outside that window (a chunk crossing realisations) use a direct global atomic.
-__global__ void __launch_bounds__(256) k_bin_count_lds(const float* __restrict__ pos, const float* __restrict__ w,
+template <int NT>
+__global__ void __launch_bounds__(NT) k_bin_count_lds(const float* __restrict__ pos, const float* __restrict__ w,
                                                        long long n, long long chunk,
                                                        const long long* __restrict__ off, int batch, CicGeo g,
                                                        unsigned* __restrict__ counts, int* __restrict__ err) {
@@ -250,9 +251,9 @@ __global__ void __launch_bounds__(256) k_bin_count_lds(const float* __restrict__
   const int nbs = (g.n + kBrick - 1) / kBrick;
   const long long per = (long long)nbs * nbs * nbs;
   const long long base = (off ? (long long)find_realisation(off, batch, lo) : 0LL) * per;
-  for (int i = threadIdx.x; i < kLdsBins; i += 256) hist[i] = 0u;
+  for (int i = threadIdx.x; i < kLdsBins; i += NT) hist[i] = 0u;
   __syncthreads();
-  for (long long i = lo + threadIdx.x; i < hi; i += 256) {
+  for (long long i = lo + threadIdx.x; i < hi; i += NT) {
     int ii[3];
     unsigned long long tau[3];
     if (!cic_locate(pos[3 * i], pos[3 * i + 1], pos[3 * i + 2], w ? w[i] : 1.0f, g, ii, tau)) {
@@ -267,7 +268,7 @@ __global__ void __launch_bounds__(256) k_bin_count_lds(const float* __restrict__
   }
   __syncthreads();
   const long long nb_total = per * batch;
-  for (int i = threadIdx.x; i < kLdsBins; i += 256) {
+  for (int i = threadIdx.x; i < kLdsBins; i += NT) {
     const unsigned c = hist[i];
     if (c && base + i < nb_total) atomicAdd(counts + base + i, c);
   }
@@ -275,7 +276,8 @@ __global__ void __launch_bounds__(256) k_bin_count_lds(const float* __restrict__
 
 // Scatter into brick order: each block reserves one contiguous slot range per non-empty
 // bin of its window, then ranks its objects inside the range with LDS atomics.
-__global__ void __launch_bounds__(256) k_bin_scatter_lds(const float* __restrict__ pos, const float* __restrict__ w,
+template <int NT>
+__global__ void __launch_bounds__(NT) k_bin_scatter_lds(const float* __restrict__ pos, const float* __restrict__ w,
                                                          long long n, long long chunk,
                                                          const long long* __restrict__ off, int batch, CicGeo g,
                                                          unsigned* __restrict__ cursor, float4* __restrict__ sorted) {
@@ -287,9 +289,9 @@ __global__ void __launch_bounds__(256) k_bin_scatter_lds(const float* __restrict
   const long long per = (long long)nbs * nbs * nbs;
   const long long base = (off ? (long long)find_realisation(off, batch, lo) : 0LL) * per;
   const long long nb_total = per * batch;
-  for (int i = threadIdx.x; i < kLdsBins; i += 256) hist[i] = 0u;
+  for (int i = threadIdx.x; i < kLdsBins; i += NT) hist[i] = 0u;
   __syncthreads();
-  for (long long i = lo + threadIdx.x; i < hi; i += 256) {
+  for (long long i = lo + threadIdx.x; i < hi; i += NT) {
     int ii[3];
     unsigned long long tau[3];
     if (!cic_locate(pos[3 * i], pos[3 * i + 1], pos[3 * i + 2], w ? w[i] : 1.0f, g, ii, tau)) continue;
@@ -298,12 +300,12 @@ __global__ void __launch_bounds__(256) k_bin_scatter_lds(const float* __restrict
     if (rel >= 0 && rel < kLdsBins) atomicAdd(&hist[rel], 1u);
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < kLdsBins; i += 256) {
+  for (int i = threadIdx.x; i < kLdsBins; i += NT) {
     const unsigned c = hist[i];
     if (c && base + i < nb_total) hist[i] = atomicAdd(cursor + base + i, c);
   }
   __syncthreads();
-  for (long long i = lo + threadIdx.x; i < hi; i += 256) {
+  for (long long i = lo + threadIdx.x; i < hi; i += NT) {
     int ii[3];
     unsigned long long tau[3];
     const float px = pos[3 * i], py = pos[3 * i + 1], pz = pos[3 * i + 2], wv = w ? w[i] : 1.0f;
