@@ -32,11 +32,13 @@ def algorithmic_bytes(n, n_gal, n_ran, randoms=True, keep_delta=False):
     cn = (n // 2 + 1) * n * n * 8
     na = 2 if randoms else 1
     return {
-        "z_iter": 6 * cn,                       # 3 spectra in, 3 out
-        "y_fanout": 5 * cn,                     # 2 in, 3 out
-        "y_fanin": 5 * cn,                      # 3 in, 2 out
+        "z_iter": 4 * cn,                       # 2 spectra in (combined state), 2 out
+        "y_fanout": 4 * cn,                     # 2 in, 2 out (combined); the output's full form: 2 in, 3 out
+        "y_fanin": 4 * cn,                      # 2 in, 2 out
         "x_iter": 7 * cn,                       # A, B, D_s, D_n in; D_n+1, 2 spectra out
         "z_final": 3 * cn + 3 * n3 * 4,         # 3 spectra in, Psi (3 real fields) out
+        "y_fanout_full": 5 * cn,
+        "z_final_u": 2 * cn + n3 * 4,           # combined state in, u out (learned start)
         "z_fwd_grid": na * (n3 * 8 + cn),       # int64 grids in, spectra out
         "x_smooth": na * 2 * cn,
         "z_delta": na * cn + (n3 if randoms else 0) + cn + (n3 * 4 if keep_delta else 0),
@@ -292,6 +294,12 @@ def main():
         if name == "z_iter" and head != "plain" and per is not None:
             # the start pass and the pass after it also read (or write) the start correction field
             per_step = per * count / args.steps + 2 * args.n ** 3 * 4
+        elif name == "y_fanout":
+            # one full fan-out per reconstruction (the output), the rest combined
+            per_step = (per * (count - args.steps) + ab["y_fanout_full"] * args.steps) / args.steps
+        elif name == "z_final" and head == "learned":
+            # u_p of the start (combined state) plus the output
+            per_step = ab["z_final_u"] + per
         elif name == "paint":
             per_step = 12 * (n_gal + n_ran) + 2 * args.n ** 3 * 8
         elif name == "shift":

@@ -3,8 +3,8 @@
 // One plan owns a caller-provided device workspace carved into the buffers of
 // the pipeline; all kernels run on the plan's stream.  The iteration keeps
 // three complex work arrays (W0..W2) that cycle through
-//   state X (x-inverse output of P_n)  --y_fanout-->  state Y (three displacement
-//   spectra, inverse-transformed along y)  --z_iter, y_fanin, x_iter-->  state X,
+//   state X (x-inverse output of P_n)  --y_fanout-->  state Y (displacement spectra
+//   inverse-transformed along y)  --z_iter, y_fanin, x_iter-->  state X,
 // plus D_s and D_n.  Convergence norms come back as one small device-to-host
 // copy per pass.
 #include <hip/hip_runtime.h>
@@ -28,6 +28,11 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 enum PlanState { ST_EMPTY = 0, ST_PAINTED = 1, ST_DELTA = 2, ST_SOLVED = 3 };
+
+// State Y of a realisation (its displacement spectra inverse-transformed along x and y): absent,
+// full (W0..W2 = Psi_x, Psi_y, Psi_z: what the output needs) or combined (W0 = r_x Psi_x + r_y Psi_y,
+// W2 = Psi_z: what the z iteration needs).  Both fan-outs consume state X.
+enum StateY { SY_NONE = 0, SY_FULL = 1, SY_COMB = 2 };
 
 struct Layout {
   size_t grid_g = 0, grid_r = 0, mask = 0, w0 = 0, w1 = 0, w2 = 0, ds = 0, dn = 0, psi = 0, delta = 0,
@@ -276,11 +281,12 @@ struct ProfScope {
 struct Ops {
   int (*setup)(recon_plan_t*);             // z/y/x/y/z/y/x chain from the painted grids to D_s and state X
   int (*setup_delta)(recon_plan_t*, const float*);
-  int (*fanout)(recon_plan_t*, const int*);
+  int (*fanout)(recon_plan_t*, const int*, bool comb);   // comb: combined state Y for the z iteration
+  int (*combine)(recon_plan_t*, const int*);              // full state Y -> combined state Y
   int (*ziter)(recon_plan_t*, int mode, const int*);
   int (*fanin_xiter)(recon_plan_t*, bool first, const int*);
-  int (*zfinal)(recon_plan_t*, float4* psi, float* u, bool cross, const int*);
-  int (*refan)(recon_plan_t*, const int*);  // state X again from D_n
+  int (*zfinal)(recon_plan_t*, float4* psi, float* u, bool cross, const int*, bool comb);
+  int (*refan)(recon_plan_t*, const int*, const float2* d);  // state X again from the spectrum d
   int (*helm)(recon_plan_t*, const float*);  // fan-out of the Helmholtz projection of a real field
   int nb_x, nb_z;
 };
@@ -427,20 +433,31 @@ struct SizeOps {
     return check_launch(pl, "x start (Helmholtz)");
   }
 
-  static int refan(recon_plan_t* pl, const int* act) {
+  static int refan(recon_plan_t* pl, const int* act, const float2* d) {
     {
       PROF(pl, KP_X_START);
-      k_x_refan<N><<<gx(pl), dim3(TX), 0, pl->stream>>>(pl->w0, pl->w1, pl->dn, pl->geo, act, pl->tw);
+      k_x_refan<N><<<gx(pl), dim3(TX), 0, pl->stream>>>(pl->w0, pl->w1, d, pl->geo, act, pl->tw);
     }
     return check_launch(pl, "x re-fan");
   }
 
-  static int fanout(recon_plan_t* pl, const int* act) {
+  static int fanout(recon_plan_t* pl, const int* act, bool comb) {
     {
       PROF(pl, KP_Y_FANOUT);
-      k_y_fanout<N><<<gy(pl), dim3(TY), 0, pl->stream>>>(pl->w0, pl->w1, pl->w2, pl->geo, act, pl->tw);
+      if (comb)
+        k_y_fanout<N, true><<<gy(pl), dim3(TY), 0, pl->stream>>>(pl->w0, pl->w1, pl->w2, pl->geo, act, pl->tw);
+      else
+        k_y_fanout<N, false><<<gy(pl), dim3(TY), 0, pl->stream>>>(pl->w0, pl->w1, pl->w2, pl->geo, act, pl->tw);
     }
     return check_launch(pl, "y fan-out");
+  }
+
+  static int combine(recon_plan_t* pl, const int* act) {
+    const long long cn = (long long)(N / 2 + 1) * N * N;
+    long long nb = (cn + 255) / 256;
+    if (nb > 8192) nb = 8192;
+    k_y_combine<N><<<dim3((unsigned)nb, pl->batch), 256, 0, pl->stream>>>(pl->w0, pl->w1, pl->geo, act);
+    return check_launch(pl, "y combine");
   }
 
   static int ziter(recon_plan_t* pl, int mode, const int* act) {
@@ -475,7 +492,7 @@ struct SizeOps {
     hipStream_t s = pl->stream;
     {
       PROF(pl, KP_Y_FANIN);
-      k_y_fanin<N><<<gy(pl), dim3(TY), 0, s>>>(pl->w0, pl->w1, pl->w2, pl->geo, act, pl->tw);
+      k_y_fanin<N><<<gy(pl), dim3(TY), 0, s>>>(pl->w0, pl->w1, pl->geo, act, pl->tw);
     }
     RECON_TRY(check_launch(pl, "y fan-in"));
     {
@@ -491,12 +508,17 @@ struct SizeOps {
     return check_launch(pl, "reduce (norm)");
   }
 
-  static int zfinal(recon_plan_t* pl, float4* psi, float* u, bool cross, const int* act) {
+  static int zfinal(recon_plan_t* pl, float4* psi, float* u, bool cross, const int* act, bool comb) {
     hipStream_t s = pl->stream;
+    if (comb && (psi || cross)) return fail(pl, RECON_EINVAL, "internal: the combined state gives u only");
     {
       PROF(pl, KP_Z_FINAL);
-      k_z_final<N><<<gz(pl), dim3(TZ), 0, s>>>(pl->w0, pl->w1, pl->w2, pl->geo, psi, u,
-                                                      cross ? pl->corr : nullptr, pl->partials, act, pl->tw);
+      if (comb)
+        k_z_final<N, true><<<gz(pl), dim3(TZ), 0, s>>>(pl->w0, pl->w1, pl->w2, pl->geo, nullptr, u, nullptr,
+                                                       pl->partials, act, pl->tw);
+      else
+        k_z_final<N, false><<<gz(pl), dim3(TZ), 0, s>>>(pl->w0, pl->w1, pl->w2, pl->geo, psi, u,
+                                                        cross ? pl->corr : nullptr, pl->partials, act, pl->tw);
     }
     RECON_TRY(check_launch(pl, "z final"));
     if (cross) {
@@ -510,7 +532,7 @@ struct SizeOps {
   }
 
   static const Ops* table() {
-    static const Ops ops = {setup, setup_delta, fanout, ziter, fanin_xiter, zfinal, refan, helm,
+    static const Ops ops = {setup, setup_delta, fanout, combine, ziter, fanin_xiter, zfinal, refan, helm,
                             (int)((N / 2 + 1) * N / WX), (int)(N * (N / (2 * WZ)))};
     return &ops;
   }
@@ -612,7 +634,7 @@ int pass_graph_launch(recon_plan_t* pl, const Ops* ops) {
       pl->stream = keep;
       return fail(pl, RECON_EDEVICE, "graph capture could not start");
     }
-    rc = ops->fanout(pl, pl->act_fan);
+    rc = ops->fanout(pl, pl->act_fan, true);
     if (rc == RECON_OK) rc = ops->ziter(pl, ZI_PLAIN, pl->act_it);
     if (rc == RECON_OK) rc = ops->fanin_xiter(pl, false, pl->act_it);
     const hipError_t ec = hipStreamEndCapture(pl->cap_stream, &graph);
@@ -943,7 +965,7 @@ int recon_solve(recon_plan_t* pl, int start, const void* net) {
     pl->passes[b] = 0;
     pl->done[b] = 0;
     pl->psi_valid[b] = 0;
-    pl->st_y[b] = 0;
+    pl->st_y[b] = SY_NONE;
     pl->pending1[b] = 0;
     pl->diverged[b] = 0;
     pl->stale_x[b] = 0;
@@ -951,8 +973,8 @@ int recon_solve(recon_plan_t* pl, int start, const void* net) {
   }
   if (start == RECON_START_LEARNED) {
     // u_p = Psi_p . r_hat from the fanned-out start, then Delta u = network(delta_s, u_p) into corr
-    RECON_TRY(ops->fanout(pl, nullptr));
-    RECON_TRY(ops->zfinal(pl, nullptr, pl->upbuf, false, nullptr));
+    RECON_TRY(ops->fanout(pl, nullptr, true));
+    RECON_TRY(ops->zfinal(pl, nullptr, pl->upbuf, false, nullptr, true));
     if (pl->dc) {
       // network on the (n/2)^3 grid: restrict the inputs, prolong its output
       RECON_TRY(restrict_impl(pl, pl->delta, pl->dc, pl->upbuf, pl->uc));
@@ -961,7 +983,7 @@ int recon_solve(recon_plan_t* pl, int start, const void* net) {
     } else {
       RECON_TRY(cnn_forward_impl(pl, (const float*)net, pl->delta, pl->upbuf, pl->corr, 1.0f / recon::cnn::S_U));
     }
-    for (int b = 0; b < pl->batch; ++b) pl->st_y[b] = 1;
+    for (int b = 0; b < pl->batch; ++b) pl->st_y[b] = SY_COMB;
   }
   pl->state = ST_SOLVED;
   return RECON_OK;
@@ -1000,24 +1022,51 @@ int recon_iterate(recon_plan_t* pl, int max_iter, double tol, int32_t* iters_out
     }
   };
 
-  // resolve eps_1 of a non-gradient start: needs the state-Y fan-out of D_1
+  // full state Y for the realisations marked in h_fin: state X is rebuilt first where it is gone
+  // (a combined state Y, or a pass stopped after its z step) from D_n, or D_s before the first pass
+  auto full_state = [&]() -> int {
+    for (int pick = 0; pick < 2; ++pick) {
+      bool any = false;
+      for (int b = 0; b < B; ++b) {
+        const bool rebuild = pl->h_fin[b] && (pl->stale_x[b] || pl->st_y[b] == SY_COMB);
+        pl->h_fan[b] = (rebuild && (pl->passes[b] == 0) == (pick == 0)) ? 1 : 0;
+        any = any || pl->h_fan[b];
+      }
+      if (!any) continue;
+      RECON_TRY(upload_mask(pl, pl->act_fan, pl->h_fan));
+      RECON_TRY(ops->refan(pl, pl->act_fan, pick == 0 ? pl->ds : pl->dn));
+      for (int b = 0; b < B; ++b)
+        if (pl->h_fan[b]) { pl->stale_x[b] = 0; pl->st_y[b] = SY_NONE; }
+    }
+    bool any = false;
+    for (int b = 0; b < B; ++b) {
+      pl->h_fan[b] = (pl->h_fin[b] && pl->st_y[b] != SY_FULL) ? 1 : 0;
+      any = any || pl->h_fan[b];
+    }
+    if (any) {
+      RECON_TRY(upload_mask(pl, pl->act_fan, pl->h_fan));
+      RECON_TRY(ops->fanout(pl, pl->act_fan, false));
+      for (int b = 0; b < B; ++b)
+        if (pl->h_fan[b]) pl->st_y[b] = SY_FULL;
+    }
+    return RECON_OK;
+  };
+
+  // resolve eps_1 of a non-gradient start: needs the full state Y of D_1
   auto resolve_pending = [&](bool write_psi) -> int {
     bool any = false;
     for (int b = 0; b < B; ++b) {
-      pl->h_fan[b] = (pl->pending1[b] && !pl->st_y[b]) ? 1 : 0;
       pl->h_fin[b] = pl->pending1[b];
       any = any || pl->pending1[b];
     }
     if (!any) return RECON_OK;
-    RECON_TRY(upload_mask(pl, pl->act_fan, pl->h_fan));
-    RECON_TRY(ops->fanout(pl, pl->act_fan));
+    RECON_TRY(full_state());
     RECON_TRY(upload_mask(pl, pl->act_fin, pl->h_fin));
-    RECON_TRY(ops->zfinal(pl, pl->psi, nullptr, true, pl->act_fin));
+    RECON_TRY(ops->zfinal(pl, pl->psi, nullptr, true, pl->act_fin, false));
     HIP_TRY(pl, hipMemcpyAsync(pl->h_red2.data(), pl->red + 2 * B, 16 * B, hipMemcpyDeviceToHost, pl->stream));
     HIP_TRY(pl, hipStreamSynchronize(pl->stream));
     for (int b = 0; b < B; ++b) {
       if (!pl->pending1[b]) continue;
-      pl->st_y[b] = 1;
       pl->psi_valid[b] = 1;
       pl->pending1[b] = 0;
       const double s3 = pl->h_red2[2 * b];
@@ -1034,12 +1083,19 @@ int recon_iterate(recon_plan_t* pl, int max_iter, double tol, int32_t* iters_out
     for (int b = 0; b < B; ++b) any = any || !pl->done[b];
     if (!any) break;
     any = false;
+    bool any_comb = false;
     for (int b = 0; b < B; ++b) {
       pl->h_it[b] = pl->done[b] ? 0 : 1;
-      pl->h_fan[b] = (!pl->done[b] && !pl->st_y[b]) ? 1 : 0;
+      pl->h_fan[b] = (!pl->done[b] && pl->st_y[b] == SY_NONE) ? 1 : 0;
+      pl->h_fin[b] = (!pl->done[b] && pl->st_y[b] == SY_FULL) ? 1 : 0;   // combined in place
       any = any || pl->h_it[b];
+      any_comb = any_comb || pl->h_fin[b];
     }
     if (!any) break;
+    if (any_comb) {
+      RECON_TRY(upload_mask(pl, pl->act_fin, pl->h_fin));
+      RECON_TRY(ops->combine(pl, pl->act_fin));
+    }
     int first_pass = -1;
     for (int b = 0; b < B; ++b)
       if (pl->h_it[b]) { first_pass = pl->passes[b]; break; }
@@ -1055,7 +1111,7 @@ int recon_iterate(recon_plan_t* pl, int max_iter, double tol, int32_t* iters_out
     if (steady && (pl->p.flags & RECON_PASS_GRAPHS) && !pl->prof.on) {
       RECON_TRY(pass_graph_launch(pl, ops));
     } else {
-      RECON_TRY(ops->fanout(pl, pl->act_fan));
+      RECON_TRY(ops->fanout(pl, pl->act_fan, true));
       RECON_TRY(ops->ziter(pl, mode, pl->act_it));
     }
     if (cross) {
@@ -1072,7 +1128,7 @@ int recon_iterate(recon_plan_t* pl, int max_iter, double tol, int32_t* iters_out
         // a realisation that stops here keeps D_1: its z step is dropped and Psi_1 recomputed at the end
         if (pl->done[b]) {
           pl->h_it[b] = 0;
-          pl->st_y[b] = 0;
+          pl->st_y[b] = SY_NONE;
           pl->psi_valid[b] = 0;
           pl->stale_x[b] = 1;
         }
@@ -1090,7 +1146,7 @@ int recon_iterate(recon_plan_t* pl, int max_iter, double tol, int32_t* iters_out
     HIP_TRY(pl, hipStreamSynchronize(pl->stream));
     for (int b = 0; b < B; ++b) {
       if (!pl->h_it[b]) continue;
-      pl->st_y[b] = 0;
+      pl->st_y[b] = SY_NONE;
       pl->psi_valid[b] = 0;
       pl->passes[b] += 1;
       const double num = pl->h_red[2 * b], den = pl->h_red[2 * b + 1];
@@ -1106,33 +1162,19 @@ int recon_iterate(recon_plan_t* pl, int max_iter, double tol, int32_t* iters_out
     }
   }
   RECON_TRY(resolve_pending(true));
-  // realisations stopped inside a pass: state X again from D_n
-  {
-    bool any_stale = false;
-    for (int b = 0; b < B; ++b) {
-      pl->h_fan[b] = pl->stale_x[b];
-      any_stale = any_stale || pl->stale_x[b];
-    }
-    if (any_stale) {
-      RECON_TRY(upload_mask(pl, pl->act_fan, pl->h_fan));
-      RECON_TRY(ops->refan(pl, pl->act_fan));
-      for (int b = 0; b < B; ++b) pl->stale_x[b] = 0;
-    }
-  }
-  // displacement of every realisation whose Psi buffer is stale
+  // displacement of every realisation whose Psi buffer is stale (realisations stopped inside a pass
+  // get state X again from D_n first)
   bool need = false;
   for (int b = 0; b < B; ++b) {
     pl->h_fin[b] = pl->psi_valid[b] ? 0 : 1;
-    pl->h_fan[b] = (pl->h_fin[b] && !pl->st_y[b]) ? 1 : 0;
     need = need || pl->h_fin[b];
   }
   if (need) {
-    RECON_TRY(upload_mask(pl, pl->act_fan, pl->h_fan));
-    RECON_TRY(ops->fanout(pl, pl->act_fan));
+    RECON_TRY(full_state());
     RECON_TRY(upload_mask(pl, pl->act_fin, pl->h_fin));
-    RECON_TRY(ops->zfinal(pl, pl->psi, nullptr, false, pl->act_fin));
+    RECON_TRY(ops->zfinal(pl, pl->psi, nullptr, false, pl->act_fin, false));
     for (int b = 0; b < B; ++b)
-      if (pl->h_fin[b]) { pl->psi_valid[b] = 1; pl->st_y[b] = 1; }
+      if (pl->h_fin[b]) pl->psi_valid[b] = 1;
   }
   HIP_TRY(pl, hipStreamSynchronize(pl->stream));
   bool div = false, notconv = false;
@@ -1237,9 +1279,9 @@ int recon_helmholtz(recon_plan_t* pl, const float* psi_x, float* irr_out, float*
   RECON_TRY(ops->helm(pl, psi_x));
   for (int b = 0; b < pl->batch; ++b) pl->h_fan[b] = 1;
   RECON_TRY(upload_mask(pl, pl->act_fan, pl->h_fan));
-  RECON_TRY(ops->fanout(pl, pl->act_fan));
+  RECON_TRY(ops->fanout(pl, pl->act_fan, false));
   RECON_TRY(upload_mask(pl, pl->act_fin, pl->h_fan));
-  RECON_TRY(ops->zfinal(pl, pl->psi, nullptr, false, pl->act_fin));
+  RECON_TRY(ops->zfinal(pl, pl->psi, nullptr, false, pl->act_fin, false));
   long long nb = (pl->n3 * pl->batch + 255) / 256;
   if (nb > 65536) nb = 65536;
   k_helm_out<<<(unsigned)nb, 256, 0, pl->stream>>>(pl->psi, psi_x, pl->n3, pl->batch, irr_out, sol_out);

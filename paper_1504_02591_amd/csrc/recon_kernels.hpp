@@ -805,10 +805,11 @@ __global__ void __launch_bounds__(256) k_log_shift(float* __restrict__ delta, lo
   }
 }
 
-// One iteration's configuration-space step (step A tail + step B head):
-//   inverse z of the three displacement spectra -> s = sum_j r_j Psi_j
-//   V_j = u r_hat_j = s r_j / |r|^2 -> forward z; the z component is multiplied by i k'_z.
-// Arrays are updated in place.  Start modes (first pass only):
+// One iteration's configuration-space step (step A tail + step B head), on the combined fan-out
+// state a0 = transverse part r_x Psi_x + r_y Psi_y, a2 = Psi_z (z spectra; r the scaled line of sight):
+//   inverse z of both -> s = Psi . r = Z^-1[a0] + r_z Z^-1[a2];  u_p = s / |r|
+//   q = u_0 / |r| (V_j = u_0 r_hat_j = q r_j) -> a0 = Z[q], a1 = i k'_z Z[r_z q]
+// Start modes (first pass only):
 //   ZI_FFTA:    u_0 = start_scale * u_p, Delta = u_0 - u_p stored in corr
 //   ZI_LEARNED: u_0 = u_p + corr (corr taken as 0 at the observer)
 // and both accumulate S1 = sum Delta u_p, S2 = sum Delta^2 into partials.  On the pass after such
@@ -816,7 +817,7 @@ __global__ void __launch_bounds__(256) k_log_shift(float* __restrict__ delta, lo
 // cross term of ||Psi_1 - Psi_0||^2.
 template <int N, int MODE>
 __global__ void __launch_bounds__(ntz<N>()) k_z_iter(float2* __restrict__ a0, float2* __restrict__ a1,
-                                                     float2* __restrict__ a2, Geo g, float* __restrict__ corr,
+                                                     const float2* __restrict__ a2, Geo g, float* __restrict__ corr,
                                                      double* __restrict__ partials, const int* __restrict__ active,
                                                      const float2* __restrict__ twg) {
   constexpr int NT = ntz<N>(), WP = wz<N>();
@@ -832,53 +833,36 @@ __global__ void __launch_bounds__(ntz<N>()) k_z_iter(float2* __restrict__ a0, fl
   frag_coords<N, WP, false>(c, j);
   const bool act = threadIdx.x < L::NTF;
   const long long n3 = (long long)N * N * N, cn = (long long)(N / 2 + 1) * N * N;
-  float2* arr[3] = {a0 + b * cn, a1 + b * cn, a2 + b * cn};
-  // each array is staged in LDS by direct loads while the previous one is transformed
-  z_stage_issue<N, WP, NT>(stage, arr[0], y, x0);
+  a0 += b * cn; a1 += b * cn; a2 += b * cn;
+  // the z component is staged in LDS by direct loads while the transverse part is transformed
+  z_stage_issue<N, WP, NT>(stage, a0, y, x0);
   const float ry = los_comp(g, 1, y);
   const float rx0 = los_comp(g, 0, x0 + c), rx1 = los_comp(g, 0, x0 + c + WP);
-  float s0[8], s1[8];
-#pragma unroll
-  for (int r = 0; r < 8; ++r) { s0[r] = 0.f; s1[r] = 0.f; }
+  float2 s[8], v[8];
   z_stage_wait();
   __syncthreads();
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    float2 v[8];
-    if (act) z_pack_stage<N, WP>(v, stage, c, j);
-    if (a < 2) {
-      __syncthreads();                                // every thread has read the staged tile
-      z_stage_issue<N, WP, NT>(stage, arr[a + 1], y, x0);
-    }
-    fft_rr<N, WP, true, false>(v, buf, tw);
-    if (act) {
-#pragma unroll
-      for (int r = 0; r < 8; ++r) {
-        const float rz = los_comp(g, 2, j + r * (N / 8));
-        const float r0 = a == 0 ? rx0 : (a == 1 ? ry : rz);
-        const float r1 = a == 0 ? rx1 : (a == 1 ? ry : rz);
-        s0[r] = fmaf(r0, v[r].x, s0[r]);
-        s1[r] = fmaf(r1, v[r].y, s1[r]);
-      }
-    }
-    if (a < 2) {
-      z_stage_wait();
-      __syncthreads();                                // the next array is staged
-    }
-  }
-  // s -> q = u_0 / |r|, so that V_j = q r_j
+  if (act) z_pack_stage<N, WP>(s, stage, c, j);
+  __syncthreads();                                  // every thread has read the staged tile
+  z_stage_issue<N, WP, NT>(stage, a2, y, x0);
+  fft_rr<N, WP, true, false>(s, buf, tw);
+  z_stage_wait();
+  __syncthreads();
+  if (act) z_pack_stage<N, WP>(v, stage, c, j);
+  fft_rr<N, WP, true, false>(v, buf, tw);
+  // s = Psi . r (two columns packed as .x / .y) -> q = u_0 / |r|, so that V_j = q r_j
   float acc1 = 0.f, acc2 = 0.f;          // 16 terms per thread; block and grid sums in FP64
   if (act) {
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
       const int z = j + r * (N / 8);
       const float rz = los_comp(g, 2, z);
+      s[r] = make_float2(fmaf(rz, v[r].x, s[r].x), fmaf(rz, v[r].y, s[r].y));
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         const float rx = h ? rx1 : rx0;
         const float r2 = rx * rx + ry * ry + rz * rz;
         const float ir = r2 > 0.f ? rsqrtf(r2) : 0.f;
-        const float up = (h ? s1[r] : s0[r]) * ir;     // u_p = s / |r|
+        const float up = (h ? s[r].y : s[r].x) * ir;     // u_p = Psi . r_hat
         float u0 = up;
         if (MODE != ZI_PLAIN) {
           const long long cell = b * n3 + ((long long)z * N + y) * N + x0 + c + h * WP;
@@ -897,8 +881,9 @@ __global__ void __launch_bounds__(ntz<N>()) k_z_iter(float2* __restrict__ a0, fl
           if (MODE != ZI_CROSS) acc2 = fmaf(dlt, dlt, acc2);
         }
         const float q = u0 * ir;
-        if (h) s1[r] = q; else s0[r] = q;
+        if (h) s[r].y = q; else s[r].x = q;
       }
+      v[r] = s[r] * rz;
     }
   }
   if (MODE != ZI_PLAIN) {
@@ -910,28 +895,19 @@ __global__ void __launch_bounds__(ntz<N>()) k_z_iter(float2* __restrict__ a0, fl
       partials[2 * (b * nb + blockIdx.x) + 1] = t2;
     }
   }
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    float2 v[8];
-    if (act) {
-#pragma unroll
-      for (int r = 0; r < 8; ++r) {
-        const float rz = los_comp(g, 2, j + r * (N / 8));
-        const float r0 = a == 0 ? rx0 : (a == 1 ? ry : rz);
-        const float r1 = a == 0 ? rx1 : (a == 1 ? ry : rz);
-        v[r] = make_float2(s0[r] * r0, s1[r] * r1);
-      }
-    }
-    fft_rl<N, WP, false, false>(v, buf, tw);
-    if (a == 2) z_unpack_store<N, WP, NT, true>(buf, arr[a], y, x0, g.kf);
-    else z_unpack_store<N, WP, NT, false>(buf, arr[a], y, x0, g.kf);
-  }
+  // Z[q] -> a0 and i k'_z Z[r_z q] -> a1; Z[V_x] = r_x Z[q] and Z[V_y] = r_y Z[q] are formed in the
+  // y pass
+  fft_rl<N, WP, false, false>(s, buf, tw);
+  z_unpack_store<N, WP, NT, false>(buf, a0, y, x0, g.kf);
+  fft_rl<N, WP, false, false>(v, buf, tw);
+  z_unpack_store<N, WP, NT, true>(buf, a1, y, x0, g.kf);
 }
 
-// Inverse z of the three displacement spectra: writes Psi interleaved as float4
-// (x, y, z, 0) per cell (when psi4 != null), u = Psi.r_hat (when u_out != null) and
-// accumulates S3 = sum corr * u (when corr != null).
-template <int N>
+// Inverse z of the displacement spectra.  Full state (COMB = false, a0..a2 = Psi_x, Psi_y, Psi_z):
+// writes Psi interleaved as float4 (x, y, z, 0) per cell (when psi4 != null), u = Psi . r_hat (when
+// u_out != null) and accumulates S3 = sum corr * u (when corr != null).  Combined state (COMB = true,
+// a0 = r_x Psi_x + r_y Psi_y, a2 = Psi_z): writes u only (psi4 and corr must be null).
+template <int N, bool COMB>
 __global__ void __launch_bounds__(ntz<N>()) k_z_final(const float2* __restrict__ a0, const float2* __restrict__ a1,
                                                       const float2* __restrict__ a2, Geo g, float4* __restrict__ psi4,
                                                       float* __restrict__ u_out, const float* __restrict__ corr,
@@ -949,23 +925,25 @@ __global__ void __launch_bounds__(ntz<N>()) k_z_final(const float2* __restrict__
   frag_coords<N, WP, false>(c, j);
   const bool act = threadIdx.x < L::NTF;
   const long long n3 = (long long)N * N * N, cn = (long long)(N / 2 + 1) * N * N;
-  const float2* arr[3] = {a0 + b * cn, a1 + b * cn, a2 + b * cn};
+  a0 += b * cn; a1 += b * cn; a2 += b * cn;
   // each array is staged in LDS by direct loads while the previous one is transformed
   __shared__ float2 stage[ZStage<N, WP>::SIZE];
-  z_stage_issue<N, WP, NT>(stage, arr[0], y, x0);
+  z_stage_issue<N, WP, NT>(stage, a0, y, x0);
   z_stage_wait();
   __syncthreads();
   float2 px[8], py[8], v[8];
   if (act) z_pack_stage<N, WP>(px, stage, c, j);
   __syncthreads();
-  z_stage_issue<N, WP, NT>(stage, arr[1], y, x0);
-  fft_rr<N, WP, true, false>(px, buf, tw);
-  z_stage_wait();
-  __syncthreads();
-  if (act) z_pack_stage<N, WP>(py, stage, c, j);
-  __syncthreads();
-  z_stage_issue<N, WP, NT>(stage, arr[2], y, x0);
-  fft_rr<N, WP, true, false>(py, buf, tw);
+  if (!COMB) {
+    z_stage_issue<N, WP, NT>(stage, a1, y, x0);
+    fft_rr<N, WP, true, false>(px, buf, tw);
+    z_stage_wait();
+    __syncthreads();
+    if (act) z_pack_stage<N, WP>(py, stage, c, j);
+    __syncthreads();
+  }
+  z_stage_issue<N, WP, NT>(stage, a2, y, x0);
+  fft_rr<N, WP, true, false>(COMB ? px : py, buf, tw);
   z_stage_wait();
   __syncthreads();
   if (act) z_pack_stage<N, WP>(v, stage, c, j);
@@ -978,26 +956,31 @@ __global__ void __launch_bounds__(ntz<N>()) k_z_final(const float2* __restrict__
     for (int r = 0; r < 8; ++r) {
       const int z = j + r * (N / 8);
       const long long cell = b * n3 + ((long long)z * N + y) * N + x0 + c;
-      if (psi4) {
+      if (!COMB && psi4) {
         psi4[cell] = make_float4(px[r].x, py[r].x, v[r].x, 0.f);
         psi4[cell + WP] = make_float4(px[r].y, py[r].y, v[r].y, 0.f);
       }
-      if (u_out || corr) {
+      if (u_out || (!COMB && corr)) {
         const float rz = los_comp(g, 2, z);
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
           const float rx = h ? rx1 : rx0;
-          const float sx = h ? px[r].y : px[r].x, sy = h ? py[r].y : py[r].x, sz = h ? v[r].y : v[r].x;
           const float r2 = rx * rx + ry * ry + rz * rz;
           const float ir = r2 > 0.f ? rsqrtf(r2) : 0.f;
-          const float u = (rx * sx + ry * sy + rz * sz) * ir;
+          float u;
+          if (COMB) {
+            u = fmaf(rz, h ? v[r].y : v[r].x, h ? px[r].y : px[r].x) * ir;
+          } else {
+            const float sx = h ? px[r].y : px[r].x, sy = h ? py[r].y : py[r].x, sz = h ? v[r].y : v[r].x;
+            u = (rx * sx + ry * sy + rz * sz) * ir;
+          }
           if (u_out) u_out[cell + h * WP] = u;
-          if (corr) acc += (double)corr[cell + h * WP] * (double)u;
+          if (!COMB && corr) acc += (double)corr[cell + h * WP] * (double)u;
         }
       }
     }
   }
-  if (corr) {
+  if (!COMB && corr) {
     double t1, t2;
     block_sum2<NT>(acc, 0.0, &t1, &t2);
     if (threadIdx.x == 0) {
@@ -1110,11 +1093,16 @@ __global__ void __launch_bounds__(nty<N>()) k_y_plain(float2* __restrict__ a0, f
   }
 }
 
-// Inverse y with the displacement fan-out:
+// Inverse y with the displacement fan-out.  Full form (COMB = false), the three displacement
+// components for the output:
 //   a0 <- Y^-1[a0]                    (x component, i k'_x applied in the x pass)
 //   a1 <- Y^-1[i k'_y a1]             (y component)
 //   a2 <- i k'_z Y^-1[a1]             (z component)
-template <int N>
+// Combined form (COMB = true), what the z iteration needs: the scaled line-of-sight components r_x
+// and r_y are constant along a z column, so the transverse part of Psi . r is formed here, before
+// the z transform:
+//   a0 <- r_x Y^-1[a0] + r_y Y^-1[i k'_y a1],   a2 <- i k'_z Y^-1[a1]   (a1 is left as it was)
+template <int N, bool COMB>
 __global__ void __launch_bounds__(nty<N>()) k_y_fanout(float2* __restrict__ a0, float2* __restrict__ a1,
                                                        float2* __restrict__ a2, Geo g, const int* __restrict__ active,
                                                        const float2* __restrict__ twg) {
@@ -1131,17 +1119,34 @@ __global__ void __launch_bounds__(nty<N>()) k_y_fanout(float2* __restrict__ a0, 
   const bool act = threadIdx.x < L::NTF;
   const long long cn = (long long)(N / 2 + 1) * N * N;
   a0 += b * cn; a1 += b * cn; a2 += b * cn;
-  float2 v[8], keep[8];
+  float2 v[8], w[8], keep[8];
   if (act) y_load<N>(v, a0, p, x0, c, j);
   fft_rr<N, W, true, false>(v, buf, tw);
   if (act) {
-    y_store<N>(v, a0, p, x0, c, j);
+    if (COMB) {
+      const float rx = los_comp(g, 0, x0 + c);
+#pragma unroll
+      for (int r = 0; r < 8; ++r) v[r] = v[r] * rx;
+    } else {
+      y_store<N>(v, a0, p, x0, c, j);
+    }
     y_load<N>(keep, a1, p, x0, c, j);
 #pragma unroll
-    for (int r = 0; r < 8; ++r) v[r] = mul_i(keep[r]) * (g.kf * deriv_mode<N>(j + r * (N / 8)));
+    for (int r = 0; r < 8; ++r) w[r] = mul_i(keep[r]) * (g.kf * deriv_mode<N>(j + r * (N / 8)));
   }
-  fft_rr<N, W, true, false>(v, buf, tw);
-  if (act) y_store<N>(v, a1, p, x0, c, j);
+  fft_rr<N, W, true, false>(w, buf, tw);
+  if (act) {
+    if (COMB) {
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        const float ry = los_comp(g, 1, j + r * (N / 8));
+        v[r] = make_float2(fmaf(ry, w[r].x, v[r].x), fmaf(ry, w[r].y, v[r].y));
+      }
+      y_store<N>(v, a0, p, x0, c, j);
+    } else {
+      y_store<N>(w, a1, p, x0, c, j);
+    }
+  }
   fft_rr<N, W, true, false>(keep, buf, tw);
   if (act) {
     const float kz = g.kf * deriv_mode<N>(p);     // p in [0, N/2]; N/2 is the Nyquist plane
@@ -1151,12 +1156,28 @@ __global__ void __launch_bounds__(nty<N>()) k_y_fanout(float2* __restrict__ a0, 
   }
 }
 
-// Forward y with the divergence fan-in:
-//   a0 <- Y[a0]                       (x component; i k'_x applied in the x pass)
-//   a1 <- i k'_y Y[a1] + Y[a2]        (y component plus the z component, already times i k'_z)
+// Full fan-out state -> combined state, in place: a0 <- r_x a0 + r_y a1 (the same arithmetic as the
+// combined fan-out; a2 is shared by both states).  Element-wise over [kz][y][x] spectra.
 template <int N>
-__global__ void __launch_bounds__(nty<N>()) k_y_fanin(float2* __restrict__ a0, float2* __restrict__ a1,
-                                                      const float2* __restrict__ a2, Geo g,
+__global__ void __launch_bounds__(256) k_y_combine(float2* __restrict__ a0, const float2* __restrict__ a1, Geo g,
+                                                   const int* __restrict__ active) {
+  const int b = blockIdx.y;
+  if (active && !active[b]) return;
+  const long long cn = (long long)(N / 2 + 1) * N * N;
+  a0 += b * cn; a1 += b * cn;
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < cn; i += (long long)gridDim.x * 256) {
+    const float rx = los_comp(g, 0, (int)(i % N)), ry = los_comp(g, 1, (int)((i / N) % N));
+    const float2 t = a0[i] * rx, w = a1[i];
+    a0[i] = make_float2(fmaf(ry, w.x, t.x), fmaf(ry, w.y, t.y));
+  }
+}
+
+// Forward y with the divergence fan-in.  In: a0 = Z[q], a1 = i k'_z Z[r_z q] (z spectra of the
+// iteration's q = u / |r| with r the scaled line of sight, so that V_j = q r_j):
+//   a0 <- r_x Y[a0]                   (x component Y Z[V_x]; i k'_x applied in the x pass)
+//   a1 <- i k'_y Y[r_y a0] + Y[a1]    (y component plus the z component)
+template <int N>
+__global__ void __launch_bounds__(nty<N>()) k_y_fanin(float2* __restrict__ a0, float2* __restrict__ a1, Geo g,
                                                       const int* __restrict__ active, const float2* __restrict__ twg) {
   constexpr int NT = nty<N>(), W = wy<N>();
   using L = Lay<N, W, false>;
@@ -1170,19 +1191,25 @@ __global__ void __launch_bounds__(nty<N>()) k_y_fanin(float2* __restrict__ a0, f
   frag_coords<N, W, false>(c, j);
   const bool act = threadIdx.x < L::NTF;
   const long long cn = (long long)(N / 2 + 1) * N * N;
-  a0 += b * cn; a1 += b * cn; a2 += b * cn;
+  a0 += b * cn; a1 += b * cn;
   float2 v[8], keep[8];
-  if (act) y_load<N>(v, a0, p, x0, c, j);
+  if (act) {
+    y_load<N>(v, a0, p, x0, c, j);
+#pragma unroll
+    for (int r = 0; r < 8; ++r) keep[r] = v[r] * los_comp(g, 1, j + r * (N / 8));
+  }
   fft_rr<N, W, false, false>(v, buf, tw);
   if (act) {
+    const float rx = los_comp(g, 0, x0 + c);
+#pragma unroll
+    for (int r = 0; r < 8; ++r) v[r] = v[r] * rx;
     y_store<N>(v, a0, p, x0, c, j);
-    y_load<N>(keep, a1, p, x0, c, j);
   }
   fft_rr<N, W, false, false>(keep, buf, tw);
   if (act) {
 #pragma unroll
     for (int r = 0; r < 8; ++r) keep[r] = mul_i(keep[r]) * (g.kf * deriv_mode<N>(j + r * (N / 8)));
-    y_load<N>(v, a2, p, x0, c, j);
+    y_load<N>(v, a1, p, x0, c, j);
   }
   fft_rr<N, W, false, false>(v, buf, tw);
   if (act) {

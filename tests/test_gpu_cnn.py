@@ -154,6 +154,45 @@ def test_learned_start_end_to_end(gpu_lib):
         np.testing.assert_allclose(eps[0], ref["eps"], rtol=1e-3, atol=1e-5)
 
 
+def test_learned_start_split_calls_equal_one_call(gpu_lib):
+    # solve leaves the combined fan-out of the start; iterate(0) rebuilds state X from D_s for the
+    # output, and the next call starts the learned pass from there: same passes bit for bit.  A call
+    # that ends right after the start pass resolves eps_1 from the output's fan-out instead of the
+    # next pass's z step: the same sum rounded along another path.
+    from paper_1504_02591_amd import native
+    cat = G.lattice_box(32, 500.0, (-500.0, 250.0, 250.0), 0.7, 23, 24, ran_factor=3, bias=1.2, smooth_r=20.0)
+    th = params(9)
+    th[:] = 0.5 * th + 0.5 * ffta2_weights(cat.growth, cat.bias).astype(np.float32)
+    gal, ran = to_dev(cat.gal_pos), to_dev(cat.ran_pos)
+    out = []
+    for split in ((3,), (0, 2, 1), (0, 1, 2)):
+        plan = native.plan_for(cat, keep_delta=True, start_buffers=True, cnn=True)
+        plan.paint(native.GAL, gal)
+        plan.paint(native.RAN, ran)
+        plan.solve(native.START_LEARNED, to_dev(th))
+        eps, psis = [], []
+        for k in split:
+            rc, iters, e = plan.iterate(k, 0.0)
+            eps += list(e[0])
+            psis.append(plan.psi()[0].cpu().numpy())
+        out.append((iters[0], eps, psis))
+        plan.close()
+    (i1, e1, p1), (i2, e2, p2), (i3, e3, p3) = out
+    assert i1 == i2 == i3 == 3
+    assert e1 == e2 and e1[1:] == e3[1:]
+    assert abs(e3[0] - e1[0]) <= 1e-6 * e1[0]
+    assert np.array_equal(p1[-1], p2[-1]) and np.array_equal(p1[-1], p3[-1])
+    # iterate(0) after the learned solve returns the plain start's displacement
+    plain = native.plan_for(cat, keep_delta=True)
+    plain.paint(native.GAL, gal)
+    plain.paint(native.RAN, ran)
+    plain.solve()
+    plain.iterate(0, 0.0)
+    p0 = plain.psi()[0].cpu().numpy()
+    plain.close()
+    assert np.array_equal(p2[0], p0)
+
+
 @pytest.mark.parametrize("n", [32, 128])
 def test_restrict_and_prolong_match_oracle(gpu_lib, n):
     from paper_1504_02591_amd import native

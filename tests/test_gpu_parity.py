@@ -486,6 +486,32 @@ def test_not_converged_and_resume(gpu_lib):
     assert rel_l2(psi, r["psi"]) < PSI_TOL
 
 
+@pytest.mark.parametrize("start", [0, 2])
+@pytest.mark.parametrize("graphs", [False, True])
+def test_split_iterate_calls_equal_one_call(gpu_lib, start, graphs):
+    # a call ends on the full fan-out (Psi written); the next call turns it into the iteration's
+    # combined form, or rebuilds state X when none is left: the passes must be the same bit for bit
+    from paper_1504_02591_amd import native
+    cat = G.lattice_box(32, 500.0, (-500.0, 250.0, 250.0), 0.7, 55, 56, ran_factor=2, bias=1.1, smooth_r=20.0)
+    gal, ran = to_dev(cat.gal_pos), to_dev(cat.ran_pos)
+    out = []
+    for split in ((5,), (0, 2, 3)):
+        plan = native.plan_for(cat, start_buffers=start != 0, graphs=graphs)
+        plan.paint(native.GAL, gal)
+        plan.paint(native.RAN, ran)
+        plan.solve(start)
+        eps = []
+        for k in split:
+            rc, iters, e = plan.iterate(k, 0.0)
+            eps += list(e[0])
+        out.append((iters[0], eps, plan.psi()[0].cpu().numpy()))
+        plan.close()
+    (i1, e1, p1), (i2, e2, p2) = out
+    assert i1 == i2 == 5
+    assert e1 == e2
+    assert np.array_equal(p1, p2)
+
+
 def test_divergence_detected(gpu_lib):
     from paper_1504_02591_amd import native
     n, box = 16, 300.0
