@@ -2,9 +2,10 @@
 
 Knobs (compile-time, see recon_tuning.h): RECON_TILE_Z (packed z column pairs per block),
 RECON_TILE_Y (y-pass columns), RECON_TILE_X (x-pass rows), RECON_MID_512 / RECON_MID_1024
-(split of the middle radix factor).  The search is one knob at a time around the current
-setting: every single-knob variant is compiled (in parallel, on the host), each is timed on the GPU in
-a process of its own on the correction pass of an n^3 field (the dominant cost of a reconstruction),
+(split of the middle radix factor), RECON_Z_TPB (z tiles per block of the z iteration, whose
+next tile is staged while the current one is finished).  The search is one knob at a time around the current setting: every
+single-knob variant is compiled (in parallel, on the host), each is timed on the GPU in a process
+of its own on the correction pass of an n^3 field (the dominant cost of a reconstruction),
 and each knob takes its fastest value.  The combined choice is timed again against the current
 setting and written to recon_tuning.h only if it is faster.
 
@@ -32,6 +33,7 @@ KNOBS = {
     "RECON_TILE_X": [2, 4, 8],
     "RECON_MID_512": [0, 1, 2],
     "RECON_MID_1024": [0, 1, 2],
+    "RECON_Z_TPB": [1, 2, 4, 8],
 }
 
 
@@ -151,7 +153,8 @@ def cmd_write(a):
         note = "fastest per knob"
     lines = ["// Tuning knobs of the transform kernels, written by paper_1504_02591_amd/autotune.py (a -D on the",
              "// compiler command line overrides them).  Tiles: packed z column pairs, y-pass columns, x-pass",
-             "// rows per block; middle radix split of the 512- and 1024-point transforms.",
+             "// rows per block; middle radix split of the 512- and 1024-point transforms; z tiles per block of",
+             "// the z iteration.",
              f"// Chosen on a {meta['n']}^3 correction pass ({note}); ms per pass of each variant:"]
     for name, t in sorted(res.items(), key=lambda kv: kv[1]):
         lines.append(f"//   {name:22s} {t:.4f}")

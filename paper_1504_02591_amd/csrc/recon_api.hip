@@ -331,6 +331,8 @@ struct SizeOps {
   static constexpr int WZ = wz<N>(), WY = wy<N>(), WX = wx<N>();
   static constexpr int TZ = ntz<N>(), TY = nty<N>(), TX = ntx<N>();
   static dim3 gz(const recon_plan_t* pl) { return dim3(N * (N / (2 * WZ)), pl->batch); }
+  template <int MODE>
+  static dim3 gzi(const recon_plan_t* pl) { return dim3(ztiles<N>() / ztpb<N, MODE>(), pl->batch); }
   static dim3 gy(const recon_plan_t* pl) { return dim3((N / 2 + 1) * (N / WY), pl->batch); }
   static dim3 gx(const recon_plan_t* pl) { return dim3((N / 2 + 1) * N / WX, pl->batch); }
 
@@ -465,23 +467,24 @@ struct SizeOps {
     {
       PROF(pl, KP_Z_ITER);
       if (mode == ZI_FFTA)
-        k_z_iter<N, ZI_FFTA><<<gz(pl), dim3(TZ), 0, s>>>(pl->w0, pl->w1, pl->w2, pl->geo, pl->corr,
+        k_z_iter<N, ZI_FFTA><<<gzi<ZI_FFTA>(pl), dim3(TZ), 0, s>>>(pl->w0, pl->w1, pl->w2, pl->geo, pl->corr,
                                                                pl->partials, act, pl->tw);
       else if (mode == ZI_LEARNED)
-        k_z_iter<N, ZI_LEARNED><<<gz(pl), dim3(TZ), 0, s>>>(pl->w0, pl->w1, pl->w2, pl->geo, pl->corr,
+        k_z_iter<N, ZI_LEARNED><<<gzi<ZI_LEARNED>(pl), dim3(TZ), 0, s>>>(pl->w0, pl->w1, pl->w2, pl->geo, pl->corr,
                                                                   pl->partials, act, pl->tw);
       else if (mode == ZI_CROSS)
-        k_z_iter<N, ZI_CROSS><<<gz(pl), dim3(TZ), 0, s>>>(pl->w0, pl->w1, pl->w2, pl->geo, pl->corr,
+        k_z_iter<N, ZI_CROSS><<<gzi<ZI_CROSS>(pl), dim3(TZ), 0, s>>>(pl->w0, pl->w1, pl->w2, pl->geo, pl->corr,
                                                                 pl->partials, act, pl->tw);
       else
-        k_z_iter<N, ZI_PLAIN><<<gz(pl), dim3(TZ), 0, s>>>(pl->w0, pl->w1, pl->w2, pl->geo, nullptr,
+        k_z_iter<N, ZI_PLAIN><<<gzi<ZI_PLAIN>(pl), dim3(TZ), 0, s>>>(pl->w0, pl->w1, pl->w2, pl->geo, nullptr,
                                                                 nullptr, act, pl->tw);
     }
     RECON_TRY(check_launch(pl, "z iteration"));
     if (mode != ZI_PLAIN) {
       {
         PROF(pl, KP_REDUCE);
-        k_reduce_pairs<<<pl->batch, 1024, 0, s>>>(pl->partials, (int)gz(pl).x, pl->red + 2 * pl->batch);
+        // every mode other than the plain one runs one tile per block: the same grid
+        k_reduce_pairs<<<pl->batch, 1024, 0, s>>>(pl->partials, (int)gzi<ZI_FFTA>(pl).x, pl->red + 2 * pl->batch);
       }
       RECON_TRY(check_launch(pl, "reduce (start sums)"));
     }

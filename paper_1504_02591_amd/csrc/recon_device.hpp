@@ -94,16 +94,18 @@ __device__ __forceinline__ void dftR(float2* v) {
 // (NS = N/8) leaves the result in the same fragment layout in registers, so an
 // N = 512 transform costs two LDS exchanges.  Radix-2/4 passes (log2 N not a
 // multiple of 3) sit in the middle; each fragment thread then handles 8/R of them.
-// LDS layouts: column-fast [N][W+1]; row-fast [W][N + N/16] with one pad slot per
-// 16 rows, both free of bank conflicts for the strided pass accesses.
+// LDS layouts: column-fast [N][W+1]; row-fast [W][N + N/8] with one pad slot per 8 rows.  In the
+// row-fast layout a wave holds one column, so its lanes write rows 8 j + r (first pass) and read
+// rows j + (N/8) r: with the pad the first pattern lands on word offsets 18 j, distinct modulo the
+// 64 banks over 32 lanes, and the second is contiguous.
 // ---------------------------------------------------------------------------
 template <int N, int W, bool JF>
 struct Lay {
   static constexpr int LDC = W + 1;
-  static constexpr int LDJ = N + N / 16;
+  static constexpr int LDJ = N + N / 8;
   static constexpr int SIZE = JF ? W * LDJ : N * LDC;
   static constexpr int NTF = (N / 8) * W;   // fragment threads
-  __device__ __forceinline__ static int at(int i, int c) { return JF ? c * LDJ + i + (i >> 4) : i * LDC + c; }
+  __device__ __forceinline__ static int at(int i, int c) { return JF ? c * LDJ + i + (i >> 3) : i * LDC + c; }
 };
 
 // Block size that runs one fragment per thread (at least one wave).

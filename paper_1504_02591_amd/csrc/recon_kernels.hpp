@@ -48,6 +48,10 @@ constexpr int cmin(int a, int b) { return a < b ? a : b; }
 template <int N> constexpr int wz() { return N >= 1024 ? 8 : cmin(N / 2, RECON_TILE_Z); }
 template <int N> constexpr int wy() { return N >= 1024 ? 8 : cmin(N, RECON_TILE_Y); }
 template <int N> constexpr int wx() { return RECON_TILE_X; }
+// z tiles (one y row, 2 wz consecutive x) and tiles per block of the z iteration
+template <int N> constexpr int ztiles() { return N * (N / (2 * wz<N>())); }
+// (the start and cross modes, which hold more live state, take one tile per block)
+template <int N, int MODE> constexpr int ztpb() { return MODE == ZI_PLAIN ? cmin(RECON_Z_TPB, ztiles<N>()) : 1; }
 
 
 __device__ __forceinline__ long long ceil_div_ll(long long a, long long b) { return (a + b - 1) / b; }
@@ -535,11 +539,14 @@ __global__ void __launch_bounds__(256) k_scalars(const unsigned long long* __res
 // over the WP packed columns.
 // ---------------------------------------------------------------------------
 template <int N, int WP>
-__device__ __forceinline__ void z_tile_coords(int& y, int& x0) {
+__device__ __forceinline__ void z_tile_at(int tile, int& y, int& x0) {
   constexpr int TPR = N / (2 * WP);
-  y = blockIdx.x / TPR;
-  x0 = (blockIdx.x % TPR) * 2 * WP;
+  y = tile / TPR;
+  x0 = (tile % TPR) * 2 * WP;
 }
+
+template <int N, int WP>
+__device__ __forceinline__ void z_tile_coords(int& y, int& x0) { z_tile_at<N, WP>(blockIdx.x, y, x0); }
 
 // Packed full-length column element k of the half spectra A (column x0+c) and B
 // (column x0+c+WP): Z(k) = A(k) + i B(k), extended Hermitian-wise for k > N/2; the
@@ -626,6 +633,9 @@ __device__ __forceinline__ void z_unpack_store(const float2* buf, float2* __rest
 
 // Scaled line-of-sight vector of a node: r = (origin + H i - observer) / R0.
 __device__ __forceinline__ float los_comp(const Geo& g, int a, int i) { return fmaf(g.hs, (float)i, g.ds[a]); }
+// |r|^2 with a fixed rounding order, so that every z kernel (and every tiling of one) forms the same
+// value whatever the compiler hoists or contracts
+__device__ __forceinline__ float los_r2(float rx, float ry, float rz) { return fmaf(rz, rz, fmaf(ry, ry, rx * rx)); }
 
 template <int N> constexpr int ntz() { return frag_threads<N, wz<N>()>(); }
 template <int N> constexpr int nty() { return frag_threads<N, wy<N>()>(); }
@@ -820,7 +830,7 @@ __global__ void __launch_bounds__(ntz<N>()) k_z_iter(float2* __restrict__ a0, fl
                                                      const float2* __restrict__ a2, Geo g, float* __restrict__ corr,
                                                      double* __restrict__ partials, const int* __restrict__ active,
                                                      const float2* __restrict__ twg) {
-  constexpr int NT = ntz<N>(), WP = wz<N>();
+  constexpr int NT = ntz<N>(), WP = wz<N>(), TPB = ztpb<N, MODE>();
   using L = Lay<N, WP, false>;
   const int b = blockIdx.y;
   if (active && !active[b]) return;
@@ -828,63 +838,83 @@ __global__ void __launch_bounds__(ntz<N>()) k_z_iter(float2* __restrict__ a0, fl
   __shared__ float2 tw[N];
   __shared__ float2 stage[ZStage<N, WP>::SIZE];
   stage_twiddles<N, NT>(tw, twg);
-  int y, x0, c, j;
-  z_tile_coords<N, WP>(y, x0);
-  frag_coords<N, WP, false>(c, j);
   const bool act = threadIdx.x < L::NTF;
   const long long n3 = (long long)N * N * N, cn = (long long)(N / 2 + 1) * N * N;
   a0 += b * cn; a1 += b * cn; a2 += b * cn;
-  // the z component is staged in LDS by direct loads while the transverse part is transformed
-  z_stage_issue<N, WP, NT>(stage, a0, y, x0);
-  const float ry = los_comp(g, 1, y);
-  const float rx0 = los_comp(g, 0, x0 + c), rx1 = los_comp(g, 0, x0 + c + WP);
-  float2 s[8], v[8];
-  z_stage_wait();
-  __syncthreads();
-  if (act) z_pack_stage<N, WP>(s, stage, c, j);
-  __syncthreads();                                  // every thread has read the staged tile
-  z_stage_issue<N, WP, NT>(stage, a2, y, x0);
-  fft_rr<N, WP, true, false>(s, buf, tw);
-  z_stage_wait();
-  __syncthreads();
-  if (act) z_pack_stage<N, WP>(v, stage, c, j);
-  fft_rr<N, WP, true, false>(v, buf, tw);
-  // s = Psi . r (two columns packed as .x / .y) -> q = u_0 / |r|, so that V_j = q r_j
-  float acc1 = 0.f, acc2 = 0.f;          // 16 terms per thread; block and grid sums in FP64
-  if (act) {
-#pragma unroll
-    for (int r = 0; r < 8; ++r) {
-      const int z = j + r * (N / 8);
-      const float rz = los_comp(g, 2, z);
-      s[r] = make_float2(fmaf(rz, v[r].x, s[r].x), fmaf(rz, v[r].y, s[r].y));
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const float rx = h ? rx1 : rx0;
-        const float r2 = rx * rx + ry * ry + rz * rz;
-        const float ir = r2 > 0.f ? rsqrtf(r2) : 0.f;
-        const float up = (h ? s[r].y : s[r].x) * ir;     // u_p = Psi . r_hat
-        float u0 = up;
-        if (MODE != ZI_PLAIN) {
-          const long long cell = b * n3 + ((long long)z * N + y) * N + x0 + c + h * WP;
-          float dlt;
-          if (MODE == ZI_FFTA) {
-            u0 = g.start_scale * up;
-            dlt = u0 - up;
-            corr[cell] = dlt;
-          } else if (MODE == ZI_CROSS) {
-            dlt = r2 > 0.f ? corr[cell] : 0.f;
-          } else {
-            dlt = r2 > 0.f ? corr[cell] : 0.f;
-            u0 = up + dlt;
-          }
-          acc1 = fmaf(dlt, up, acc1);
-          if (MODE != ZI_CROSS) acc2 = fmaf(dlt, dlt, acc2);
-        }
-        const float q = u0 * ir;
-        if (h) s[r].y = q; else s[r].x = q;
-      }
-      v[r] = s[r] * rz;
+  float acc1 = 0.f, acc2 = 0.f;          // 16 terms per thread and tile; block and grid sums in FP64
+  // TPB tiles per block, strided by the grid; the next tile's transverse part is staged in LDS by
+  // direct loads while the current tile is finished, and the z component while the transverse
+  // part is transformed
+  int tile = blockIdx.x, y, x0;
+  z_tile_at<N, WP>(tile, y, x0);
+  if (tile < ztiles<N>()) z_stage_issue<N, WP, NT>(stage, a0, y, x0);
+#pragma unroll 1
+  for (int t = 0; t < TPB && tile < ztiles<N>(); ++t) {     // block-uniform bound
+    int c, j;
+    frag_coords<N, WP, false>(c, j);
+    const float ry = los_comp(g, 1, y);
+    const float rx0 = los_comp(g, 0, x0 + c), rx1 = los_comp(g, 0, x0 + c + WP);
+    float2 s[8], v[8];
+    z_stage_wait();
+    __syncthreads();
+    if (act) z_pack_stage<N, WP>(s, stage, c, j);
+    __syncthreads();                                  // every thread has read the staged tile
+    z_stage_issue<N, WP, NT>(stage, a2, y, x0);
+    fft_rr<N, WP, true, false>(s, buf, tw);
+    z_stage_wait();
+    __syncthreads();
+    if (act) z_pack_stage<N, WP>(v, stage, c, j);
+    const int next = tile + gridDim.x;
+    int ny = y, nx0 = x0;
+    if (t + 1 < TPB && next < ztiles<N>()) {
+      __syncthreads();
+      z_tile_at<N, WP>(next, ny, nx0);
+      z_stage_issue<N, WP, NT>(stage, a0, ny, nx0);
     }
+    fft_rr<N, WP, true, false>(v, buf, tw);
+    // s = Psi . r (two columns packed as .x / .y) -> q = u_0 / |r|, so that V_j = q r_j
+    if (act) {
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        const int z = j + r * (N / 8);
+        const float rz = los_comp(g, 2, z);
+        s[r] = make_float2(fmaf(rz, v[r].x, s[r].x), fmaf(rz, v[r].y, s[r].y));
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const float rx = h ? rx1 : rx0;
+          const float r2 = los_r2(rx, ry, rz);
+          const float ir = r2 > 0.f ? rsqrtf(r2) : 0.f;
+          const float up = (h ? s[r].y : s[r].x) * ir;     // u_p = Psi . r_hat
+          float u0 = up;
+          if (MODE != ZI_PLAIN) {
+            const long long cell = b * n3 + ((long long)z * N + y) * N + x0 + c + h * WP;
+            float dlt;
+            if (MODE == ZI_FFTA) {
+              u0 = g.start_scale * up;
+              dlt = u0 - up;
+              corr[cell] = dlt;
+            } else if (MODE == ZI_CROSS) {
+              dlt = r2 > 0.f ? corr[cell] : 0.f;
+            } else {
+              dlt = r2 > 0.f ? corr[cell] : 0.f;
+              u0 = up + dlt;
+            }
+            acc1 = fmaf(dlt, up, acc1);
+            if (MODE != ZI_CROSS) acc2 = fmaf(dlt, dlt, acc2);
+          }
+          const float q = u0 * ir;
+          if (h) s[r].y = q; else s[r].x = q;
+        }
+        v[r] = s[r] * rz;
+      }
+    }
+    // Z[q] -> a0 and i k'_z Z[r_z q] -> a1; Z[V_x] = r_x Z[q] and Z[V_y] = r_y Z[q] are formed in
+    // the y pass
+    fft_rl<N, WP, false, false>(s, buf, tw);
+    z_unpack_store<N, WP, NT, false>(buf, a0, y, x0, g.kf);
+    fft_rl<N, WP, false, false>(v, buf, tw);
+    z_unpack_store<N, WP, NT, true>(buf, a1, y, x0, g.kf);
+    tile = next; y = ny; x0 = nx0;
   }
   if (MODE != ZI_PLAIN) {
     double t1, t2;
@@ -895,12 +925,6 @@ __global__ void __launch_bounds__(ntz<N>()) k_z_iter(float2* __restrict__ a0, fl
       partials[2 * (b * nb + blockIdx.x) + 1] = t2;
     }
   }
-  // Z[q] -> a0 and i k'_z Z[r_z q] -> a1; Z[V_x] = r_x Z[q] and Z[V_y] = r_y Z[q] are formed in the
-  // y pass
-  fft_rl<N, WP, false, false>(s, buf, tw);
-  z_unpack_store<N, WP, NT, false>(buf, a0, y, x0, g.kf);
-  fft_rl<N, WP, false, false>(v, buf, tw);
-  z_unpack_store<N, WP, NT, true>(buf, a1, y, x0, g.kf);
 }
 
 // Inverse z of the displacement spectra.  Full state (COMB = false, a0..a2 = Psi_x, Psi_y, Psi_z):
@@ -965,7 +989,7 @@ __global__ void __launch_bounds__(ntz<N>()) k_z_final(const float2* __restrict__
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
           const float rx = h ? rx1 : rx0;
-          const float r2 = rx * rx + ry * ry + rz * rz;
+          const float r2 = los_r2(rx, ry, rz);
           const float ir = r2 > 0.f ? rsqrtf(r2) : 0.f;
           float u;
           if (COMB) {
@@ -1204,12 +1228,12 @@ __global__ void __launch_bounds__(nty<N>()) k_y_fanin(float2* __restrict__ a0, f
 #pragma unroll
     for (int r = 0; r < 8; ++r) v[r] = v[r] * rx;
     y_store<N>(v, a0, p, x0, c, j);
+    y_load<N>(v, a1, p, x0, c, j);                  // in flight during the next transform
   }
   fft_rr<N, W, false, false>(keep, buf, tw);
   if (act) {
 #pragma unroll
     for (int r = 0; r < 8; ++r) keep[r] = mul_i(keep[r]) * (g.kf * deriv_mode<N>(j + r * (N / 8)));
-    y_load<N>(v, a1, p, x0, c, j);
   }
   fft_rr<N, W, false, false>(v, buf, tw);
   if (act) {
