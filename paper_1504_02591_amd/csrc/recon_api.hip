@@ -1226,7 +1226,7 @@ int recon_get_psi(recon_plan_t* pl, float* psi_out) {
     if (!pl->psi_valid[b]) return fail(pl, RECON_ESTATE, "displacement not computed; call iterate");
   long long blocks = (pl->n3 * pl->batch + kThreads - 1) / kThreads;
   if (blocks > 65536) blocks = 65536;
-  k_psi_planar<<<(unsigned)blocks, kThreads, 0, pl->stream>>>(pl->psi, pl->n3, pl->batch, psi_out);
+  k_psi_planar<<<(unsigned)blocks, kThreads, 0, pl->stream>>>(pl->psi, pl->n, pl->batch, psi_out);
   return check_launch(pl, "psi copy");
 }
 
@@ -1287,7 +1287,7 @@ int recon_helmholtz(recon_plan_t* pl, const float* psi_x, float* irr_out, float*
   RECON_TRY(ops->zfinal(pl, pl->psi, nullptr, false, pl->act_fin, false));
   long long nb = (pl->n3 * pl->batch + 255) / 256;
   if (nb > 65536) nb = 65536;
-  k_helm_out<<<(unsigned)nb, 256, 0, pl->stream>>>(pl->psi, psi_x, pl->n3, pl->batch, irr_out, sol_out);
+  k_helm_out<<<(unsigned)nb, 256, 0, pl->stream>>>(pl->psi, psi_x, pl->n, pl->batch, irr_out, sol_out);
   RECON_TRY(check_launch(pl, "Helmholtz output"));
   // the transform buffers, D_s and Psi now hold the diagnostic: the reconstruction starts over
   pl->state = ST_EMPTY;

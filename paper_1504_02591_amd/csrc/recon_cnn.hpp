@@ -605,7 +605,7 @@ __global__ void __launch_bounds__(256) k_adam(float* __restrict__ th, float* __r
   }
 }
 
-// u = Psi . r_hat from the interleaved displacement.
+// u = Psi . r_hat from the interleaved displacement (psi_slot order).
 __global__ void __launch_bounds__(256) k_radial(const float4* __restrict__ psi4, Geo3 g, int batch,
                                                 float* __restrict__ u) {
   const long long n3 = (long long)g.n * g.n * g.n;
@@ -616,7 +616,7 @@ __global__ void __launch_bounds__(256) k_radial(const float4* __restrict__ psi4,
                 rz = fmaf(g.hs, (float)z, g.ds[2]);
     const float r2 = rx * rx + ry * ry + rz * rz;
     const float ir = r2 > 0.f ? rsqrtf(r2) : 0.f;
-    const float4 p = psi4[i];
+    const float4 p = psi4[(i - c) + psi_slot(x, y, z, g.n)];
     u[i] = (rx * p.x + ry * p.y + rz * p.z) * ir;
   }
 }

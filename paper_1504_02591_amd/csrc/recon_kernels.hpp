@@ -42,6 +42,19 @@ struct CicGeo {
 
 enum ZIterMode { ZI_PLAIN = 0, ZI_FFTA = 1, ZI_LEARNED = 2, ZI_CROSS = 3 };
 
+// Storage slot of node (x, y, z) in the displacement buffer (float4 per node): 2 x 2 x 2 bricks, one
+// 128-byte line each, in [z/2][y/2][x/2] order, nodes inside a brick in (z&1, y&1, x&1) order.  The
+// eight nodes of a CIC stencil then span 3.4 lines on average instead of 4.5 in [z][y][x] rows,
+// which is what the random-access shift pays for.
+__device__ __forceinline__ long long psi_slot(int x, int y, int z, int n) {
+  const int h = n >> 1;
+  return ((((long long)(z >> 1) * h + (y >> 1)) * h + (x >> 1)) << 3) | ((z & 1) << 2) | ((y & 1) << 1) | (x & 1);
+}
+// the same for a linear cell index c = (z n + y) n + x
+__device__ __forceinline__ long long psi_slot(long long c, int n) {
+  return psi_slot((int)(c % n), (int)((c / n) % n), (int)(c / ((long long)n * n)), n);
+}
+
 // Tile shapes (compile-time tuning knobs from recon_tuning.h): packed z columns, y-pass columns,
 // x-pass rows.  Each block runs one radix-8 fragment per thread, (N/8) * tile threads.
 constexpr int cmin(int a, int b) { return a < b ? a : b; }
@@ -928,7 +941,7 @@ __global__ void __launch_bounds__(ntz<N>()) k_z_iter(float2* __restrict__ a0, fl
 }
 
 // Inverse z of the displacement spectra.  Full state (COMB = false, a0..a2 = Psi_x, Psi_y, Psi_z):
-// writes Psi interleaved as float4 (x, y, z, 0) per cell (when psi4 != null), u = Psi . r_hat (when
+// writes Psi interleaved as float4 (x, y, z, 0) per node in psi_slot order (when psi4 != null), u = Psi . r_hat (when
 // u_out != null) and accumulates S3 = sum corr * u (when corr != null).  Combined state (COMB = true,
 // a0 = r_x Psi_x + r_y Psi_y, a2 = Psi_z): writes u only (psi4 and corr must be null).
 template <int N, bool COMB>
@@ -981,8 +994,9 @@ __global__ void __launch_bounds__(ntz<N>()) k_z_final(const float2* __restrict__
       const int z = j + r * (N / 8);
       const long long cell = b * n3 + ((long long)z * N + y) * N + x0 + c;
       if (!COMB && psi4) {
-        psi4[cell] = make_float4(px[r].x, py[r].x, v[r].x, 0.f);
-        psi4[cell + WP] = make_float4(px[r].y, py[r].y, v[r].y, 0.f);
+        float4* pb = psi4 + b * n3;
+        pb[psi_slot(x0 + c, y, z, N)] = make_float4(px[r].x, py[r].x, v[r].x, 0.f);
+        pb[psi_slot(x0 + c + WP, y, z, N)] = make_float4(px[r].y, py[r].y, v[r].y, 0.f);
       }
       if (u_out || (!COMB && corr)) {
         const float rz = los_comp(g, 2, z);
@@ -1028,7 +1042,7 @@ __global__ void __launch_bounds__(NT) k_ratio_stats(const float4* __restrict__ p
   for (long long i = blockIdx.x * (long long)NT + threadIdx.x; i < n3; i += (long long)gridDim.x * NT) {
     const int x = (int)(i % n), y = (int)((i / n) % n), z = (int)(i / ((long long)n * n));
     const float rx = los_comp(g, 0, x), ry = los_comp(g, 1, y), rz = los_comp(g, 2, z);
-    const float4 p = psi4[b * n3 + i];
+    const float4 p = psi4[b * n3 + psi_slot(x, y, z, n)];
     const float* q = psi_ref + b * 3 * n3;
     const double a = (double)rx * q[i] + (double)ry * q[n3 + i] + (double)rz * q[2 * n3 + i];
     const double d = (double)rx * p.x + (double)ry * p.y + (double)rz * p.z;
@@ -1058,14 +1072,14 @@ __global__ void __launch_bounds__(NT) k_ratio_stats(const float4* __restrict__ p
   }
 }
 
-// Interleaved displacement (float4 per cell) -> planar [b][3][N^3].
-__global__ void __launch_bounds__(256) k_psi_planar(const float4* __restrict__ psi4, long long n3, int batch,
+// Interleaved displacement (float4 per node, psi_slot order) -> planar [b][3][N^3].
+__global__ void __launch_bounds__(256) k_psi_planar(const float4* __restrict__ psi4, int n, int batch,
                                                     float* __restrict__ out) {
-  const long long total = n3 * batch;
+  const long long n3 = (long long)n * n * n, total = n3 * batch;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
        i += (long long)gridDim.x * blockDim.x) {
-    const float4 v = psi4[i];
     const long long b = i / n3, c = i - b * n3;
+    const float4 v = psi4[b * n3 + psi_slot(c, n)];
     out[(b * 3 + 0) * n3 + c] = v.x;
     out[(b * 3 + 1) * n3 + c] = v.y;
     out[(b * 3 + 2) * n3 + c] = v.z;
@@ -1386,11 +1400,12 @@ __global__ void __launch_bounds__(ntx<N>()) k_x_refan(float2* __restrict__ a0, f
 // Helmholtz split output: irrotational = -Psi (the fan-out of the HELM start), solenoidal =
 // f x - irrotational; planar [b][3][n^3]; sol may be null.
 __global__ void __launch_bounds__(256) k_helm_out(const float4* __restrict__ psi4, const float* __restrict__ f,
-                                                  long long n3, int batch, float* __restrict__ irr,
+                                                  int n, int batch, float* __restrict__ irr,
                                                   float* __restrict__ sol) {
+  const long long n3 = (long long)n * n * n;
   for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n3 * batch; i += (long long)gridDim.x * 256) {
     const long long b = i / n3, c = i - b * n3;
-    const float4 p = psi4[i];
+    const float4 p = psi4[b * n3 + psi_slot(c, n)];
     const float ix = -p.x, iy = -p.y, iz = -p.z;
     irr[(b * 3 + 0) * n3 + c] = ix;
     irr[(b * 3 + 1) * n3 + c] = iy;
@@ -1542,9 +1557,7 @@ __global__ void __launch_bounds__(256) k_shift(const float* __restrict__ pos, lo
     for (int cnr = 0; cnr < 8; ++cnr) {
       const int dx = cnr & 1, dy = (cnr >> 1) & 1, dz = cnr >> 2;
       const float wgt = (dx ? t[0] : 1.f - t[0]) * (dy ? t[1] : 1.f - t[1]) * (dz ? t[2] : 1.f - t[2]);
-      const long long idx = (((long long)((ii[2] + dz) & (cg.n - 1)) * cg.n + ((ii[1] + dy) & (cg.n - 1))) * cg.n) +
-                            ((ii[0] + dx) & (cg.n - 1));
-      const float4 v = pb[idx];
+      const float4 v = pb[psi_slot((ii[0] + dx) & (cg.n - 1), (ii[1] + dy) & (cg.n - 1), (ii[2] + dz) & (cg.n - 1), cg.n)];
       p0 = fmaf(wgt, v.x, p0);
       p1 = fmaf(wgt, v.y, p1);
       p2 = fmaf(wgt, v.z, p2);

@@ -3,13 +3,16 @@
 // rows per block; middle radix split of the 512- and 1024-point transforms; z tiles per block of
 // the z iteration.
 // Chosen on a 512^3 correction pass (fastest per knob); ms per pass of each variant:
-//   base                   2.6144
-//   RECON_TILE_Z=8         2.6168
-//   RECON_TILE_X=2         2.6414
-//   RECON_TILE_X=8         2.6496
-//   RECON_MID_512=2        2.7548
-//   RECON_MID_512=1        2.7652
-//   RECON_TILE_Y=8         2.9666
+//   RECON_Z_TPB=8          2.5736
+//   base                   2.5814
+//   RECON_TILE_X=2         2.5904
+//   RECON_Z_TPB=2          2.5949
+//   RECON_TILE_X=8         2.5954
+//   RECON_Z_TPB=1          2.6240
+//   RECON_TILE_Z=8         2.6522
+//   RECON_MID_512=2        2.7369
+//   RECON_MID_512=1        2.7386
+//   RECON_TILE_Y=8         2.8554
 #pragma once
 #ifndef RECON_TILE_Z
 #define RECON_TILE_Z 16
@@ -27,5 +30,5 @@
 #define RECON_MID_1024 0
 #endif
 #ifndef RECON_Z_TPB
-#define RECON_Z_TPB 4
+#define RECON_Z_TPB 8
 #endif
