@@ -292,8 +292,12 @@ def main():
     for name, (count, tot_ms) in sorted(prof.items(), key=lambda kv: -kv[1][1]):
         per = ab.get(name)
         if name == "z_iter" and head != "plain" and per is not None:
-            # the start pass and the pass after it also read (or write) the start correction field
-            per_step = per * count / args.steps + 2 * args.n ** 3 * 4
+            # the start pass and the pass after it also read (or write) the start correction field;
+            # the learned start's pass reads u_p (one real field) instead of the two state-Y spectra
+            r = args.n ** 3 * 4
+            per_step = per * count / args.steps + 2 * r
+            if head == "learned":
+                per_step += r - per / 2
         elif name == "y_fanout":
             # one full fan-out per reconstruction (the output), the rest combined
             per_step = (per * (count - args.steps) + ab["y_fanout_full"] * args.steps) / args.steps

@@ -471,7 +471,7 @@ struct SizeOps {
                                                                pl->partials, act, pl->tw);
       else if (mode == ZI_LEARNED)
         k_z_iter<N, ZI_LEARNED><<<gzi<ZI_LEARNED>(pl), dim3(TZ), 0, s>>>(pl->w0, pl->w1, pl->w2, pl->geo, pl->corr,
-                                                                  pl->partials, act, pl->tw);
+                                                                  pl->partials, act, pl->tw, pl->upbuf);
       else if (mode == ZI_CROSS)
         k_z_iter<N, ZI_CROSS><<<gzi<ZI_CROSS>(pl), dim3(TZ), 0, s>>>(pl->w0, pl->w1, pl->w2, pl->geo, pl->corr,
                                                                 pl->partials, act, pl->tw);
@@ -1086,30 +1086,34 @@ int recon_iterate(recon_plan_t* pl, int max_iter, double tol, int32_t* iters_out
     for (int b = 0; b < B; ++b) any = any || !pl->done[b];
     if (!any) break;
     any = false;
-    bool any_comb = false;
     for (int b = 0; b < B; ++b) {
       pl->h_it[b] = pl->done[b] ? 0 : 1;
-      pl->h_fan[b] = (!pl->done[b] && pl->st_y[b] == SY_NONE) ? 1 : 0;
-      pl->h_fin[b] = (!pl->done[b] && pl->st_y[b] == SY_FULL) ? 1 : 0;   // combined in place
       any = any || pl->h_it[b];
-      any_comb = any_comb || pl->h_fin[b];
     }
     if (!any) break;
-    if (any_comb) {
-      RECON_TRY(upload_mask(pl, pl->act_fin, pl->h_fin));
-      RECON_TRY(ops->combine(pl, pl->act_fin));
-    }
     int first_pass = -1;
     for (int b = 0; b < B; ++b)
       if (pl->h_it[b]) { first_pass = pl->passes[b]; break; }
-    RECON_TRY(upload_mask(pl, pl->act_fan, pl->h_fan));
-    RECON_TRY(upload_mask(pl, pl->act_it, pl->h_it));
     const bool start_pass = first_pass == 0 && pl->start != RECON_START_PLAIN;
     // eps_1 of a non-gradient start needs S3 = sum Delta u_1; this pass's z step computes u_1
     bool cross = false;
     for (int b = 0; b < B; ++b) cross = cross || (pl->h_it[b] && pl->pending1[b]);
     const int mode = start_pass ? (pl->start == RECON_START_LEARNED ? ZI_LEARNED : ZI_FFTA)
                                 : (cross ? ZI_CROSS : ZI_PLAIN);
+    // the learned start's pass takes u_p from the start's buffer: it needs no state Y
+    const bool need_y = mode != ZI_LEARNED;
+    bool any_comb = false;
+    for (int b = 0; b < B; ++b) {
+      pl->h_fan[b] = (need_y && pl->h_it[b] && pl->st_y[b] == SY_NONE) ? 1 : 0;
+      pl->h_fin[b] = (need_y && pl->h_it[b] && pl->st_y[b] == SY_FULL) ? 1 : 0;   // combined in place
+      any_comb = any_comb || pl->h_fin[b];
+    }
+    if (any_comb) {
+      RECON_TRY(upload_mask(pl, pl->act_fin, pl->h_fin));
+      RECON_TRY(ops->combine(pl, pl->act_fin));
+    }
+    RECON_TRY(upload_mask(pl, pl->act_fan, pl->h_fan));
+    RECON_TRY(upload_mask(pl, pl->act_it, pl->h_it));
     const bool steady = mode == ZI_PLAIN && first_pass != 0;
     if (steady && (pl->p.flags & RECON_PASS_GRAPHS) && !pl->prof.on) {
       RECON_TRY(pass_graph_launch(pl, ops));

@@ -834,7 +834,8 @@ __global__ void __launch_bounds__(256) k_log_shift(float* __restrict__ delta, lo
 //   q = u_0 / |r| (V_j = u_0 r_hat_j = q r_j) -> a0 = Z[q], a1 = i k'_z Z[r_z q]
 // Start modes (first pass only):
 //   ZI_FFTA:    u_0 = start_scale * u_p, Delta = u_0 - u_p stored in corr
-//   ZI_LEARNED: u_0 = u_p + corr (corr taken as 0 at the observer)
+//   ZI_LEARNED: u_0 = u_p + corr (corr taken as 0 at the observer), with u_p read from up_in, the
+//               start's own inverse z step (the same arithmetic), so no inverse transform is redone
 // and both accumulate S1 = sum Delta u_p, S2 = sum Delta^2 into partials.  On the pass after such
 // a start, ZI_CROSS iterates as ZI_PLAIN and accumulates S3 = sum Delta u_1 (second entry 0), the
 // cross term of ||Psi_1 - Psi_0||^2.
@@ -842,7 +843,8 @@ template <int N, int MODE>
 __global__ void __launch_bounds__(ntz<N>()) k_z_iter(float2* __restrict__ a0, float2* __restrict__ a1,
                                                      const float2* __restrict__ a2, Geo g, float* __restrict__ corr,
                                                      double* __restrict__ partials, const int* __restrict__ active,
-                                                     const float2* __restrict__ twg) {
+                                                     const float2* __restrict__ twg,
+                                                     const float* __restrict__ up_in = nullptr) {
   constexpr int NT = ntz<N>(), WP = wz<N>(), TPB = ztpb<N, MODE>();
   using L = Lay<N, WP, false>;
   const int b = blockIdx.y;
@@ -860,7 +862,7 @@ __global__ void __launch_bounds__(ntz<N>()) k_z_iter(float2* __restrict__ a0, fl
   // part is transformed
   int tile = blockIdx.x, y, x0;
   z_tile_at<N, WP>(tile, y, x0);
-  if (tile < ztiles<N>()) z_stage_issue<N, WP, NT>(stage, a0, y, x0);
+  if (MODE != ZI_LEARNED && tile < ztiles<N>()) z_stage_issue<N, WP, NT>(stage, a0, y, x0);
 #pragma unroll 1
   for (int t = 0; t < TPB && tile < ztiles<N>(); ++t) {     // block-uniform bound
     int c, j;
@@ -868,39 +870,42 @@ __global__ void __launch_bounds__(ntz<N>()) k_z_iter(float2* __restrict__ a0, fl
     const float ry = los_comp(g, 1, y);
     const float rx0 = los_comp(g, 0, x0 + c), rx1 = los_comp(g, 0, x0 + c + WP);
     float2 s[8], v[8];
-    z_stage_wait();
-    __syncthreads();
-    if (act) z_pack_stage<N, WP>(s, stage, c, j);
-    __syncthreads();                                  // every thread has read the staged tile
-    z_stage_issue<N, WP, NT>(stage, a2, y, x0);
-    fft_rr<N, WP, true, false>(s, buf, tw);
-    z_stage_wait();
-    __syncthreads();
-    if (act) z_pack_stage<N, WP>(v, stage, c, j);
     const int next = tile + gridDim.x;
     int ny = y, nx0 = x0;
-    if (t + 1 < TPB && next < ztiles<N>()) {
+    if constexpr (MODE != ZI_LEARNED) {
+      z_stage_wait();
       __syncthreads();
-      z_tile_at<N, WP>(next, ny, nx0);
-      z_stage_issue<N, WP, NT>(stage, a0, ny, nx0);
+      if (act) z_pack_stage<N, WP>(s, stage, c, j);
+      __syncthreads();                                // every thread has read the staged tile
+      z_stage_issue<N, WP, NT>(stage, a2, y, x0);
+      fft_rr<N, WP, true, false>(s, buf, tw);
+      z_stage_wait();
+      __syncthreads();
+      if (act) z_pack_stage<N, WP>(v, stage, c, j);
+      if (t + 1 < TPB && next < ztiles<N>()) {
+        __syncthreads();
+        z_tile_at<N, WP>(next, ny, nx0);
+        z_stage_issue<N, WP, NT>(stage, a0, ny, nx0);
+      }
+      fft_rr<N, WP, true, false>(v, buf, tw);
     }
-    fft_rr<N, WP, true, false>(v, buf, tw);
     // s = Psi . r (two columns packed as .x / .y) -> q = u_0 / |r|, so that V_j = q r_j
     if (act) {
 #pragma unroll
       for (int r = 0; r < 8; ++r) {
         const int z = j + r * (N / 8);
         const float rz = los_comp(g, 2, z);
-        s[r] = make_float2(fmaf(rz, v[r].x, s[r].x), fmaf(rz, v[r].y, s[r].y));
+        if (MODE != ZI_LEARNED) s[r] = make_float2(fmaf(rz, v[r].x, s[r].x), fmaf(rz, v[r].y, s[r].y));
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
           const float rx = h ? rx1 : rx0;
           const float r2 = los_r2(rx, ry, rz);
           const float ir = r2 > 0.f ? rsqrtf(r2) : 0.f;
-          const float up = (h ? s[r].y : s[r].x) * ir;     // u_p = Psi . r_hat
+          const long long cell = b * n3 + ((long long)z * N + y) * N + x0 + c + h * WP;
+          // u_p = Psi . r_hat
+          const float up = MODE == ZI_LEARNED ? up_in[cell] : (h ? s[r].y : s[r].x) * ir;
           float u0 = up;
           if (MODE != ZI_PLAIN) {
-            const long long cell = b * n3 + ((long long)z * N + y) * N + x0 + c + h * WP;
             float dlt;
             if (MODE == ZI_FFTA) {
               u0 = g.start_scale * up;
