@@ -37,7 +37,7 @@ enum StateY { SY_NONE = 0, SY_FULL = 1, SY_COMB = 2 };
 struct Layout {
   size_t grid_g = 0, grid_r = 0, mask = 0, w0 = 0, w1 = 0, w2 = 0, ds = 0, dn = 0, psi = 0, delta = 0,
          corr = 0, tw = 0, partials = 0, red = 0, totals = 0, thr = 0, dscal = 0, act = 0, err = 0, total = 0,
-         sorted = 0, bcount = 0, bstart = 0, bcursor = 0, bsum = 0, status = 0, tpart = 0;
+         sorted = 0, bcount = 0, bstart = 0, bcursor = 0, bsum = 0, bvalid = 0, status = 0, tpart = 0;
   // network buffers
   size_t a1 = 0, a2 = 0, d1 = 0, d2 = 0, ybuf = 0, dybuf = 0, upbuf = 0, wk2t = 0, w3 = 0,
          part_out = 0, part_w1 = 0, part_w2 = 0, g1 = 0, g2 = 0, g3 = 0, grad = 0, lossp = 0, losst = 0, dc = 0, uc = 0,
@@ -113,6 +113,7 @@ Layout make_layout(const recon_params_t* p) {
     L.bstart = take((L.nbins + 2) * 4);
     L.bcursor = take((L.nbins + 2) * 4);
     L.bsum = take(L.nscan * 4);
+    L.bvalid = take(2 * L.nbins);
   }
   if (p->flags & RECON_CNN_BUFFERS) {
     using namespace recon::cnn;
@@ -202,6 +203,10 @@ struct recon_plan_s {
   double *lossp = nullptr, *losst = nullptr;
   const float* net = nullptr;
   unsigned *bcount = nullptr, *bstart = nullptr, *bcursor = nullptr, *bsum = nullptr;
+  // brick-sparse integer grids: per-brick validity of each grid, used while sparse_* is set (the
+  // bricks that are not valid are zero and are not read)
+  unsigned char *bvalid_g = nullptr, *bvalid_r = nullptr;
+  bool sparse_g = false, sparse_r = false;
   Geo geo{};
   CicGeo cic{};
   bool painted_g = false, painted_r = false;
@@ -291,15 +296,24 @@ struct Ops {
   int nb_x, nb_z;
 };
 
+// Brick validity of a grid for its readers: null while the grid is dense.
+const unsigned char* valid_of(const recon_plan_t* pl, int which) {
+  if (which == RECON_GAL) return pl->sparse_g ? pl->bvalid_g : nullptr;
+  return pl->sparse_r ? pl->bvalid_r : nullptr;
+}
+
 // Device-side alpha / rho_bar / mask threshold from the totals, then the survey mask.
 int scalars_and_mask(recon_plan_t* pl, int nblk_z) {
   k_scalars<<<pl->batch, 256, 0, pl->stream>>>(pl->tpart, nblk_z, pl->n3, pl->p.mask_tau, pl->randoms ? 1 : 0,
                                                pl->totals, pl->dscal, pl->thr, pl->status);
   RECON_TRY(check_launch(pl, "scalars"));
   if (pl->randoms) {
-    const int nseg = (pl->n + 61) / 62;
-    const unsigned blocks = (unsigned)(nseg * ((pl->n + 3) / 4));
-    {
+    if (const unsigned char* v = valid_of(pl, RECON_RAN)) {
+      PROF(pl, KP_MASK);
+      k_mask_brick<<<(unsigned)pl->L.nbins, 256, 0, pl->stream>>>(pl->grid_r, pl->n, pl->thr, v, pl->mask);
+    } else {
+      const int nseg = (pl->n + 61) / 62;
+      const unsigned blocks = (unsigned)(nseg * ((pl->n + 3) / 4));
       PROF(pl, KP_MASK);
       k_mask_win<<<dim3(blocks, pl->batch), 256, 0, pl->stream>>>(pl->grid_r, pl->n, pl->thr, pl->mask);
     }
@@ -341,7 +355,8 @@ struct SizeOps {
     if (pl->randoms) {
       {
         PROF(pl, KP_Z_FWD_GRID);
-        k_z_fwd_grid<N, 2><<<gz(pl), dim3(TZ), 0, s>>>(pl->grid_g, pl->grid_r, pl->w0, pl->w1, pl->tpart, pl->tw);
+        k_z_fwd_grid<N, 2><<<gz(pl), dim3(TZ), 0, s>>>(pl->grid_g, pl->grid_r, pl->w0, pl->w1, pl->tpart, pl->tw,
+                                                       valid_of(pl, RECON_GAL), valid_of(pl, RECON_RAN));
       }
       RECON_TRY(check_launch(pl, "z forward (grids)"));
       {
@@ -370,7 +385,8 @@ struct SizeOps {
     } else {
       {
         PROF(pl, KP_Z_FWD_GRID);
-        k_z_fwd_grid<N, 1><<<gz(pl), dim3(TZ), 0, s>>>(pl->grid_g, nullptr, pl->w0, nullptr, pl->tpart, pl->tw);
+        k_z_fwd_grid<N, 1><<<gz(pl), dim3(TZ), 0, s>>>(pl->grid_g, nullptr, pl->w0, nullptr, pl->tpart, pl->tw,
+                                                       valid_of(pl, RECON_GAL), nullptr);
       }
       RECON_TRY(check_launch(pl, "z forward (grid)"));
       {
@@ -769,6 +785,8 @@ int recon_plan(recon_plan_t** out, const recon_params_t* params, void* workspace
     pl->bstart = (unsigned*)(w + L.bstart);
     pl->bcursor = (unsigned*)(w + L.bcursor);
     pl->bsum = (unsigned*)(w + L.bsum);
+    pl->bvalid_g = (unsigned char*)(w + L.bvalid);
+    pl->bvalid_r = pl->bvalid_g + L.nbins;
   }
 
   const int n = pl->n;
@@ -842,9 +860,27 @@ int recon_paint(recon_plan_t* pl, int which, const float* pos, const float* w, i
   long long* grid = which == RECON_GAL ? pl->grid_g : pl->grid_r;
   const bool first = which == RECON_GAL ? !pl->painted_g : !pl->painted_r;
   int* errc = pl->err + which;   // invalid-object counter of this grid
-  if (!(flags & RECON_PAINT_ACCUMULATE) || first) {
-    RECON_TRY(launch_fill_u64(pl, grid, pl->n3 * pl->batch));
+  const bool fresh = !(flags & RECON_PAINT_ACCUMULATE) || first;
+  const bool binned = n > 0 && !(flags & RECON_PAINT_NGP) && n <= pl->p.max_objects;
+  // brick-sparse grid: bricks tile the grid and the brick buffers exist
+  const bool can_sparse = pl->L.nbins > 0 && pl->n >= 2 * kBrick;
+  unsigned char* valid = which == RECON_GAL ? pl->bvalid_g : pl->bvalid_r;
+  bool& sparse = which == RECON_GAL ? pl->sparse_g : pl->sparse_r;
+  if (fresh) {
     HIP_TRY(pl, hipMemsetAsync(errc, 0, sizeof(int), pl->stream));
+    if (!(binned && can_sparse)) {
+      RECON_TRY(launch_fill_u64(pl, grid, pl->n3 * pl->batch));
+      sparse = false;
+    }   // else only the bricks the deposit touches are cleared, after the count below
+  } else if (sparse && n > 0 && !binned) {
+    // a deposit that does not go through the bricks adds into a dense grid: clear what is not valid
+    {
+      PROF(pl, KP_FILL);
+      k_brick_prepare<<<(unsigned)pl->L.nbins, 256, 0, pl->stream>>>(pl->bcount, pl->n, 2, valid,
+                                                                     (unsigned long long*)grid);
+    }
+    RECON_TRY(check_launch(pl, "brick densify"));
+    sparse = false;
   }
   if (n > 0 && (flags & RECON_PAINT_NGP)) {
     long long blocks = (n + kThreads - 1) / kThreads;
@@ -855,7 +891,7 @@ int recon_paint(recon_plan_t* pl, int which, const float* pos, const float* w, i
                                                                  (unsigned long long*)grid, pl->cic, errc);
     }
     RECON_TRY(check_launch(pl, "paint (NGP)"));
-  } else if (n > 0 && n <= pl->p.max_objects) {
+  } else if (binned) {
     // brick-binned deposit: count, scan, scatter into brick order, per-brick LDS accumulation
     long long blocks = (n + kThreads - 1) / kThreads;
     if (blocks > 8192) blocks = 8192;
@@ -876,6 +912,16 @@ int recon_paint(recon_plan_t* pl, int which, const float* pos, const float* w, i
                                                                    pl->cic, pl->bcount, errc);
     }
     RECON_TRY(check_launch(pl, "bin count"));
+    if (can_sparse && (fresh || sparse)) {
+      // clear the bricks this deposit touches (new grid), or those of them not held yet (accumulate)
+      {
+        PROF(pl, KP_FILL);
+        k_brick_prepare<<<(unsigned)nb, 256, 0, pl->stream>>>(pl->bcount, pl->n, fresh ? 0 : 1, valid,
+                                                              (unsigned long long*)grid);
+      }
+      RECON_TRY(check_launch(pl, "brick prepare"));
+      sparse = true;
+    }
     {
       PROF(pl, KP_SCAN);
       k_scan_blocks<<<(unsigned)pl->L.nscan, 256, 0, pl->stream>>>(pl->bcount, nb, pl->bsum);
@@ -1239,6 +1285,12 @@ int recon_get_grid(recon_plan_t* pl, int which, int64_t* out) {
   if (which != RECON_GAL && which != RECON_RAN) return fail(pl, RECON_EINVAL, "which must be RECON_GAL or RECON_RAN");
   const long long* g = which == RECON_GAL ? pl->grid_g : pl->grid_r;
   if (!g || !(which == RECON_GAL ? pl->painted_g : pl->painted_r)) return fail(pl, RECON_ESTATE, "grid not painted");
+  if (const unsigned char* v = valid_of(pl, which)) {
+    long long blocks = (pl->n3 * pl->batch + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    k_grid_export<<<(unsigned)blocks, 256, 0, pl->stream>>>(g, v, pl->n, pl->batch, (long long*)out);
+    return check_launch(pl, "grid export");
+  }
   HIP_TRY(pl, hipMemcpyAsync(out, g, sizeof(int64_t) * pl->n3 * pl->batch, hipMemcpyDeviceToDevice, pl->stream));
   return RECON_OK;
 }

@@ -93,6 +93,41 @@ __device__ __forceinline__ int find_realisation(const long long* __restrict__ of
   return lo;
 }
 
+// Integer CIC shares of one object: corner k = (dx, dy, dz) gets floor(W_Q c_k / 2^48) with
+// c_k = a_x a_y a_z, a = 2^16 - tau or tau per axis, for the first seven corners, and corner (1,1,1)
+// the remainder, so the eight shares add up to W_Q exactly.  For a unit weight (W_Q = 2^32) the share
+// is floor(c_k / 2^16); c_k <= 2^48 is formed exactly in FP64 at full rate instead of with 64-bit
+// integer products (the same integers either way).
+__device__ __forceinline__ void cic_shares(unsigned long long wq, const unsigned long long tau[3],
+                                           unsigned long long share[8]) {
+  unsigned long long sum = 0;
+  if (wq == (1ull << 32)) {
+    const double ax[2] = {(double)(65536u - (unsigned)tau[0]), (double)(unsigned)tau[0]};
+    const double ay[2] = {(double)(65536u - (unsigned)tau[1]), (double)(unsigned)tau[1]};
+    const double az[2] = {(double)(65536u - (unsigned)tau[2]), (double)(unsigned)tau[2]};
+#pragma unroll
+    for (int cnr = 0; cnr < 7; ++cnr) {
+      const double c = ax[cnr & 1] * ay[(cnr >> 1) & 1] * az[cnr >> 2];
+      const double f = floor(c * 0x1p-16);
+      share[cnr] = f >= 0x1p32 ? (1ull << 32) : (unsigned long long)(unsigned)f;
+      sum += share[cnr];
+    }
+  } else {
+#pragma unroll
+    for (int cnr = 0; cnr < 7; ++cnr) {
+      const int dx = cnr & 1, dy = (cnr >> 1) & 1, dz = cnr >> 2;
+      const unsigned long long ax = dx ? tau[0] : 65536ull - tau[0];
+      const unsigned long long ay = dy ? tau[1] : 65536ull - tau[1];
+      const unsigned long long az = dz ? tau[2] : 65536ull - tau[2];
+      const unsigned long long c = ax * ay * az;
+      const unsigned long long chi = c >> 24, clo = c & 0xFFFFFFull;
+      share[cnr] = (wq * chi + ((wq * clo) >> 24)) >> 24;
+      sum += share[cnr];
+    }
+  }
+  share[7] = wq - sum;
+}
+
 // Nearest-grid-point deposit in the same fixed point: the whole W_Q goes to node i + 1 when the
 // FP32 fraction is at least 1/2, else to node i (per axis, periodic).
 __global__ void __launch_bounds__(256) k_paint_ngp(const float* __restrict__ pos, const float* __restrict__ w,
@@ -161,26 +196,15 @@ __global__ void __launch_bounds__(256) k_paint(const float* __restrict__ pos, co
                                     : (1ull << 32);
     const int b = off ? find_realisation(off, batch, i) : 0;
     unsigned long long* gb = grid + (long long)b * n3;
-    unsigned long long acc = 0;
+    unsigned long long share[8];
+    cic_shares(wq, tau, share);
 #pragma unroll
     for (int cnr = 0; cnr < 8; ++cnr) {
       const int dx = cnr & 1, dy = (cnr >> 1) & 1, dz = cnr >> 2;
       const long long ix = (ii[0] + dx) & (g.n - 1);
       const long long iy = (ii[1] + dy) & (g.n - 1);
       const long long iz = (ii[2] + dz) & (g.n - 1);
-      unsigned long long share;
-      if (cnr < 7) {
-        const unsigned long long ax = dx ? tau[0] : 65536ull - tau[0];
-        const unsigned long long ay = dy ? tau[1] : 65536ull - tau[1];
-        const unsigned long long az = dz ? tau[2] : 65536ull - tau[2];
-        const unsigned long long c = ax * ay * az;
-        const unsigned long long chi = c >> 24, clo = c & 0xFFFFFFull;
-        share = (wq * chi + ((wq * clo) >> 24)) >> 24;
-        acc += share;
-      } else {
-        share = wq - acc;
-      }
-      if (share) atomicAdd(gb + (iz * g.n + iy) * g.n + ix, share);
+      if (share[cnr]) atomicAdd(gb + (iz * g.n + iy) * g.n + ix, share[cnr]);
     }
   }
 }
@@ -424,23 +448,12 @@ __global__ void __launch_bounds__(256) k_brick_deposit(const float4* __restrict_
     cic_locate(r.x, r.y, r.z, r.w, g, ii, tau);
     const unsigned long long wq = (unsigned long long)__double2ll_rn((double)r.w * 4294967296.0);
     const int lx = ii[0] - bx * kBrick, ly = ii[1] - by * kBrick, lz = ii[2] - bz * kBrick;
-    unsigned long long sum = 0;
+    unsigned long long share[8];
+    cic_shares(wq, tau, share);
 #pragma unroll
     for (int cnr = 0; cnr < 8; ++cnr) {
       const int dx = cnr & 1, dy = (cnr >> 1) & 1, dz = cnr >> 2;
-      unsigned long long share;
-      if (cnr < 7) {
-        const unsigned long long ax = dx ? tau[0] : 65536ull - tau[0];
-        const unsigned long long ay = dy ? tau[1] : 65536ull - tau[1];
-        const unsigned long long az = dz ? tau[2] : 65536ull - tau[2];
-        const unsigned long long c = ax * ay * az;
-        const unsigned long long chi = c >> 24, clo = c & 0xFFFFFFull;
-        share = (wq * chi + ((wq * clo) >> 24)) >> 24;
-        sum += share;
-      } else {
-        share = wq - sum;
-      }
-      if (share) atomicAdd(&acc[((lz + dz) * T + (ly + dy)) * T + (lx + dx)], share);
+      if (share[cnr]) atomicAdd(&acc[((lz + dz) * T + (ly + dy)) * T + (lx + dx)], share[cnr]);
     }
   }
   __syncthreads();
@@ -452,6 +465,68 @@ __global__ void __launch_bounds__(256) k_brick_deposit(const float4* __restrict_
     const long long x = (bx * kBrick + lx) & (g.n - 1), y = (by * kBrick + ly) & (g.n - 1),
                     z = (bz * kBrick + lz) & (g.n - 1);
     atomicAdd(gb + (z * g.n + y) * g.n + x, v);
+  }
+}
+
+// Brick-sparse integer grids.  valid[key] (one byte per 16^3 brick) marks the bricks whose cells are
+// held in memory; every other brick is zero and is neither cleared nor read.  A deposit through the
+// bricks touches brick B when B or one of its seven lower neighbours holds objects (a brick's
+// footprint reaches one cell into its upper neighbours).  Modes, one block per brick:
+//   0 (new grid):   clear the touched bricks, valid = touched
+//   1 (accumulate): clear the touched bricks that are not valid yet, valid |= touched
+//   2 (densify):    clear every brick that is not valid, valid = 1 (before a deposit that does not go
+//                   through the bricks)
+// Requires n to be a multiple of the brick size.
+__global__ void __launch_bounds__(256) k_brick_prepare(const unsigned* __restrict__ count, int n, int mode,
+                                                       unsigned char* __restrict__ valid,
+                                                       unsigned long long* __restrict__ grid) {
+  const int nbs = n / kBrick;
+  const long long per = (long long)nbs * nbs * nbs;
+  const long long key = blockIdx.x;
+  const int b = (int)(key / per);
+  const long long kk = key - (long long)b * per;
+  const int bx = (int)(kk % nbs), by = (int)((kk / nbs) % nbs), bz = (int)(kk / ((long long)nbs * nbs));
+  bool touched = true;
+  if (mode != 2) {
+    touched = false;
+#pragma unroll
+    for (int d = 0; d < 8; ++d) {
+      const int x = (bx - (d & 1) + nbs) % nbs, y = (by - ((d >> 1) & 1) + nbs) % nbs,
+                z = (bz - (d >> 2) + nbs) % nbs;
+      touched = touched || count[(long long)b * per + ((long long)z * nbs + y) * nbs + x] != 0u;
+    }
+  }
+  const bool was = valid[key] != 0;
+  const bool clear = mode == 0 ? touched : (mode == 1 ? (touched && !was) : !was);
+  if (clear) {
+    unsigned long long* gb = grid + (long long)b * n * n * n;
+    for (int i = threadIdx.x; i < kBrick * kBrick * kBrick; i += 256) {
+      const long long x = bx * kBrick + (i % kBrick), y = by * kBrick + (i / kBrick) % kBrick,
+                      z = bz * kBrick + i / (kBrick * kBrick);
+      gb[(z * n + y) * n + x] = 0ull;
+    }
+  }
+  if (threadIdx.x == 0) valid[key] = (unsigned char)(mode == 0 ? touched : (mode == 1 ? (was || touched) : 1));
+}
+
+// Validity of the brick holding cell (x, y, z) of realisation b (null: every brick is valid).
+__device__ __forceinline__ bool brick_valid(const unsigned char* __restrict__ valid, int n, int b, int x, int y,
+                                            int z) {
+  if (!valid) return true;
+  const int nbs = n / kBrick;
+  return valid[(((long long)b * nbs + z / kBrick) * nbs + y / kBrick) * nbs + x / kBrick] != 0;
+}
+
+// Dense copy of a brick-sparse grid (zeros in the bricks that are not valid).
+__global__ void __launch_bounds__(256) k_grid_export(const long long* __restrict__ grid,
+                                                     const unsigned char* __restrict__ valid, int n, int batch,
+                                                     long long* __restrict__ out) {
+  const long long n3 = (long long)n * n * n, total = n3 * batch;
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < total; i += (long long)gridDim.x * 256) {
+    const int b = (int)(i / n3);
+    const long long c = i - b * n3;
+    const int x = (int)(c % n), y = (int)((c / n) % n), z = (int)(c / ((long long)n * n));
+    out[i] = brick_valid(valid, n, b, x, y, z) ? grid[i] : 0;
   }
 }
 
@@ -492,6 +567,87 @@ __global__ void __launch_bounds__(256) k_mask_win(const long long* __restrict__ 
     prev = cur;
     cur = next;
   }
+}
+
+// The same mask on a brick-sparse random grid, one block per 16^3 brick: the 18^3 neighbourhood is
+// staged in LDS (bricks that are not valid read as zero and are not loaded), each thread owns one
+// (x, y) column of the brick and keeps the 3 x 3 sums of the 18 planes in registers, then slides
+// along z.  A brick whose 27 neighbours are all not valid has every window sum 0.
+__global__ void __launch_bounds__(256) k_mask_brick(const long long* __restrict__ gr, int n,
+                                                    const long long* __restrict__ thr,
+                                                    const unsigned char* __restrict__ valid,
+                                                    unsigned char* __restrict__ mask) {
+  constexpr int H = kBrick + 2, H3 = H * H * H, PER = (H3 + 255) / 256;
+  __shared__ __align__(16) long long h[H3];
+  __shared__ int nv[27];
+  __shared__ int any;
+  const int nbs = n / kBrick;
+  const long long per = (long long)nbs * nbs * nbs;
+  const long long key = blockIdx.x;
+  const int b = (int)(key / per);
+  const long long kk = key - (long long)b * per;
+  const int bx = (int)(kk % nbs), by = (int)((kk / nbs) % nbs), bz = (int)(kk / ((long long)nbs * nbs));
+  const long long n2 = (long long)n * n;
+  const long long* g = gr + (long long)b * n2 * n;
+  unsigned char* m = mask + (long long)b * n2 * n;
+  const long long t = thr[b];
+  if (threadIdx.x == 0) any = 0;
+  __syncthreads();
+  if (threadIdx.x < 27) {
+    const int dx = threadIdx.x % 3 - 1, dy = (threadIdx.x / 3) % 3 - 1, dz = threadIdx.x / 9 - 1;
+    const int x = (bx + dx + nbs) % nbs, y = (by + dy + nbs) % nbs, z = (bz + dz + nbs) % nbs;
+    nv[threadIdx.x] = valid[(long long)b * per + ((long long)z * nbs + y) * nbs + x] != 0;
+    if (nv[threadIdx.x]) atomicOr(&any, 1);
+  }
+  __syncthreads();
+  // thread t writes mask row (z, y) = (t / 16, t % 16) of the brick: 16 bytes along x
+  const int rz = threadIdx.x / kBrick, ry = threadIdx.x % kBrick;
+  uint4* row = (uint4*)(m + (long long)(bz * kBrick + rz) * n2 + (long long)(by * kBrick + ry) * n + bx * kBrick);
+  if (!any) {
+    const unsigned v = 0 > t ? 0x01010101u : 0u;
+    *row = make_uint4(v, v, v, v);
+    return;
+  }
+  long long vals[PER];
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int i = threadIdx.x + 256 * k;
+    vals[k] = 0;
+    if (i < H3) {
+      const int lx = i % H, ly = (i / H) % H, lz = i / (H * H);
+      // neighbour brick of this halo cell: -1, 0 or +1 per axis
+      const int ox = lx == 0 ? 0 : (lx == H - 1 ? 2 : 1), oy = ly == 0 ? 0 : (ly == H - 1 ? 2 : 1),
+                oz = lz == 0 ? 0 : (lz == H - 1 ? 2 : 1);
+      if (nv[(oz * 3 + oy) * 3 + ox]) {
+        const long long x = (bx * kBrick + lx - 1 + n) & (n - 1), y = (by * kBrick + ly - 1 + n) & (n - 1),
+                        z = (bz * kBrick + lz - 1 + n) & (n - 1);
+        vals[k] = g[z * n2 + y * n + x];
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < PER; ++k)
+    if (threadIdx.x + 256 * k < H3) h[threadIdx.x + 256 * k] = vals[k];
+  __syncthreads();
+  // thread (tx, ty) owns one (x, y) column: 3 x 3 sums of the 18 planes, then the z window
+  const int tx = threadIdx.x % kBrick, ty = threadIdx.x / kBrick;
+  long long sxy[H];
+#pragma unroll
+  for (int lz = 0; lz < H; ++lz) {
+    long long a = 0;
+#pragma unroll
+    for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+      for (int dx = 0; dx < 3; ++dx) a += h[(lz * H + ty + dy) * H + tx + dx];
+    sxy[lz] = a;
+  }
+  __syncthreads();                                       // h is reused for the mask bytes below
+  unsigned char* mb = (unsigned char*)h;                 // [z][y][x], 16^3 bytes
+#pragma unroll
+  for (int z = 0; z < kBrick; ++z)
+    mb[(z * kBrick + ty) * kBrick + tx] = (sxy[z] + sxy[z + 1] + sxy[z + 2]) > t ? 1 : 0;
+  __syncthreads();
+  *row = ((const uint4*)mb)[threadIdx.x];
 }
 
 // Per-realisation scalars from the exact totals {W_g, W_r, n_occ}:
@@ -660,7 +816,9 @@ template <int N, int NA>
 __global__ void __launch_bounds__(ntz<N>()) k_z_fwd_grid(const long long* __restrict__ g0,
                                                          const long long* __restrict__ g1, float2* __restrict__ o0,
                                                          float2* __restrict__ o1, unsigned long long* __restrict__ tpart,
-                                                         const float2* __restrict__ twg) {
+                                                         const float2* __restrict__ twg,
+                                                         const unsigned char* __restrict__ v0 = nullptr,
+                                                         const unsigned char* __restrict__ v1 = nullptr) {
   constexpr int NT = ntz<N>(), WP = wz<N>();
   using L = Lay<N, WP, false>;
   __shared__ float2 buf[L::SIZE];
@@ -677,12 +835,31 @@ __global__ void __launch_bounds__(ntz<N>()) k_z_fwd_grid(const long long* __rest
 #pragma unroll
   for (int a = 0; a < NA; ++a) {
     const long long* gsrc = (a == 0 ? g0 : g1) + b * n3;
+    // brick-validity of the two columns' bricks along z (brick-sparse grids; null: all valid)
+    const unsigned char* vg = a == 0 ? v0 : v1;
+    constexpr int NBS = N / kBrick;
+    const unsigned char* vb = vg ? vg + (long long)b * NBS * NBS * NBS + (y / kBrick) * NBS : nullptr;
+    if (vb) {
+      // a tile whose bricks are all not valid holds zeros: its half spectra are zero, no transform
+      constexpr int XB = (2 * WP + kBrick - 1) / kBrick;   // bricks across the tile's 2 WP columns
+      int mine = 0;
+      for (int i = threadIdx.x; i < NBS * XB; i += NT) mine |= vb[(i / XB) * NBS * NBS + x0 / kBrick + i % XB];
+      if (!__syncthreads_or(mine)) {
+        float2* out = (a == 0 ? o0 : o1) + b * cn;
+        for (int e = threadIdx.x; e < (N / 2 + 1) * 2 * WP; e += NT)
+          out[((long long)(e / (2 * WP)) * N + y) * N + x0 + e % (2 * WP)] = make_float2(0.f, 0.f);
+        continue;
+      }
+    }
     float2 v[8];
     if (act) {
 #pragma unroll
       for (int r = 0; r < 8; ++r) {
-        const long long base = ((long long)(j + r * (N / 8)) * N + y) * N + x0 + c;
-        const long long q0 = gsrc[base], q1 = gsrc[base + WP];
+        const int z = j + r * (N / 8);
+        const long long base = ((long long)z * N + y) * N + x0 + c;
+        const unsigned char* vz = vb ? vb + (z / kBrick) * NBS * NBS : nullptr;
+        const bool ok0 = !vz || vz[(x0 + c) / kBrick], ok1 = !vz || vz[(x0 + c + WP) / kBrick];
+        const long long q0 = ok0 ? gsrc[base] : 0, q1 = ok1 ? gsrc[base + WP] : 0;
         sums[a] += (unsigned long long)q0 + (unsigned long long)q1;
         if (a == 1) sums[2] += (q0 != 0) + (q1 != 0);
         v[r] = make_float2((float)q0 * unit, (float)q1 * unit);
@@ -762,6 +939,29 @@ __global__ void __launch_bounds__(ntz<N>()) k_z_delta(float2* __restrict__ a0, c
   double lsum = 0.0;
   float2 gv[8], v[8];
   if constexpr (NA == 2) {
+    // a tile outside the survey mask has delta_s = 0 in every cell (also after the lognormal
+    // transform, ln 1 = 0): its spectrum is zero and no transform is needed
+    constexpr int ROW16 = 2 * WP / 16;                   // 16-byte words per z row of the tile
+    int mine = ROW16 == 0;                               // (tiles narrower than 16 bytes: no check)
+    if constexpr (ROW16 > 0) {
+      for (int i = threadIdx.x; i < N * ROW16; i += NT) {
+        const uint4 w4 =
+            *(const uint4*)(mask + b * n3 + ((long long)(i / ROW16) * N + y) * N + x0 + 16 * (i % ROW16));
+        mine |= (w4.x | w4.y | w4.z | w4.w) != 0u;
+      }
+    }
+    if (!__syncthreads_or(mine)) {
+      for (int e = threadIdx.x; e < (N / 2 + 1) * 2 * WP; e += NT)
+        a0[((long long)(e / (2 * WP)) * N + y) * N + x0 + e % (2 * WP)] = make_float2(0.f, 0.f);
+      if (delta_out)
+        for (int e = threadIdx.x; e < N * 2 * WP; e += NT)
+          delta_out[b * n3 + ((long long)(e / (2 * WP)) * N + y) * N + x0 + e % (2 * WP)] = 0.f;
+      if (log_floor > 0.f && threadIdx.x == 0) {
+        partials[2 * ((long long)b * gridDim.x + blockIdx.x)] = 0.0;
+        partials[2 * ((long long)b * gridDim.x + blockIdx.x) + 1] = 0.0;
+      }
+      return;
+    }
     // the second array is staged in LDS by direct loads while the first is transformed
     __shared__ float2 stage[ZStage<N, WP>::SIZE];
     z_stage_issue<N, WP, NT>(stage, a0, y, x0);

@@ -118,6 +118,80 @@ def test_paint_accumulate_equals_single_call(gpu_lib, binned):
     plan.close()
 
 
+@pytest.mark.parametrize("binned", [False, True])
+def test_unit_weight_shares_bitexact(gpu_lib, binned):
+    # unit weights take the FP64 share path (floor(c / 2^16), c <= 2^48); objects exactly on nodes
+    # (c = 2^48 at corner 0), at cell mid-points and just past a node, with and without a weight array
+    from paper_1504_02591_amd import native
+    rng = np.random.default_rng(31)
+    n = 64
+    box = float(n)                                   # cell size 1: integer positions sit on nodes
+    m = 60000
+    pos = (rng.random((m, 3)) * box).astype(np.float32)
+    k = rng.integers(0, n, (3000, 3)).astype(np.float32)
+    pos[:1000] = k[:1000]
+    pos[1000:2000] = k[1000:2000] + 0.5
+    pos[2000:3000] = k[2000:3000] + np.float32(2.0 ** -17)
+    ref = O.paint(pos, None, n, box, (0.0, 0.0, 0.0))
+    plan = native.Plan(n, box, (-100.0, 0.0, 0.0), 1.0, 0.5, 10.0, randoms=False, max_objects=m if binned else 0)
+    plan.paint(native.GAL, to_dev(pos))
+    assert np.array_equal(plan.grid(native.GAL)[0].cpu().numpy(), ref)
+    plan.paint(native.GAL, to_dev(pos), to_dev(np.ones(m, np.float32)))
+    assert np.array_equal(plan.grid(native.GAL)[0].cpu().numpy(), ref)
+    plan.close()
+
+
+def test_sparse_grid_fresh_accumulate_and_densify(gpu_lib):
+    # brick-sparse grids: a new deposit clears only the 16^3 bricks it touches, so bricks holding an
+    # earlier catalogue must read as zero; an accumulating deposit clears the bricks it adds; an
+    # accumulating NGP deposit first makes the grid dense
+    from paper_1504_02591_amd import native
+    rng = np.random.default_rng(41)
+    n, box = 64, 640.0                               # 4 x 4 x 4 bricks of 160 Mpc/h
+    full = (rng.random((50000, 3)) * box).astype(np.float32)
+    clump = (rng.random((20000, 3)) * 60.0 + 200.0).astype(np.float32)
+    edge = (rng.random((5000, 3)) * 8.0 + 472.0).astype(np.float32)    # up to cell 47: footprint into the next brick
+    other = (rng.random((3000, 3)) * box).astype(np.float32)
+    w = (rng.random(5000) * 3).astype(np.float32)
+    plan = native.Plan(n, box, (0.0, 0.0, 0.0), 1.0, 0.5, 10.0, randoms=False, max_objects=50000)
+    plan.paint(native.GAL, to_dev(full))
+    plan.paint(native.GAL, to_dev(clump))
+    ref = O.paint(clump, None, n, box, (0, 0, 0))
+    assert np.array_equal(plan.grid(native.GAL)[0].cpu().numpy(), ref)
+    plan.paint(native.GAL, to_dev(edge), to_dev(w), accumulate=True)
+    ref = ref + O.paint(edge, w, n, box, (0, 0, 0))
+    assert np.array_equal(plan.grid(native.GAL)[0].cpu().numpy(), ref)
+    plan.paint(native.GAL, to_dev(other), accumulate=True, ngp=True)
+    ref = ref + O.paint_ngp(other, None, n, box, (0, 0, 0))
+    assert np.array_equal(plan.grid(native.GAL)[0].cpu().numpy(), ref)
+    plan.paint(native.GAL, to_dev(clump), accumulate=True)
+    ref = ref + O.paint(clump, None, n, box, (0, 0, 0))
+    assert np.array_equal(plan.grid(native.GAL)[0].cpu().numpy(), ref)
+    plan.close()
+
+
+def test_sparse_grids_after_dense_paint_reconstruct(gpu_lib):
+    # grids first filled everywhere by a box-wide catalogue, then the survey catalogues painted anew:
+    # the transforms, totals and mask must see only the bricks the survey deposit touched
+    from paper_1504_02591_amd import native
+    cat = G.config2(n=64, scale=0.125)
+    rng = np.random.default_rng(43)
+    junk = to_dev((rng.random((cat.ran_pos.shape[0], 3)) * cat.box_len + np.asarray(cat.origin)).astype(np.float32))
+    plan = native.plan_for(cat, keep_delta=True)
+    plan.paint(native.GAL, junk)
+    plan.paint(native.RAN, junk)
+    gal, ran = to_dev(cat.gal_pos), to_dev(cat.ran_pos)
+    plan.paint(native.GAL, gal)
+    plan.paint(native.RAN, ran)
+    plan.solve()
+    rc, iters, eps = plan.iterate(3, 0.0)
+    g = dict(eps=eps[0], psi=plan.psi()[0].cpu().numpy(), grid_g=plan.grid(native.GAL)[0].cpu().numpy(),
+             grid_r=plan.grid(native.RAN)[0].cpu().numpy(), disp_g=plan.shift(native.GAL, gal).cpu().numpy(),
+             disp_r=plan.shift(native.RAN, ran).cpu().numpy(), delta=plan.delta()[0].cpu().numpy())
+    plan.close()
+    compare_full(g, oracle_catalogue_run(cat, 3), "sparse grids after a dense paint")
+
+
 def test_binned_deposit_clustered_and_invalid(gpu_lib):
     from paper_1504_02591_amd import native
     rng = np.random.default_rng(9)
@@ -283,11 +357,14 @@ def test_ffta_starts(gpu_lib, start):
         compare_full(g, r, f"ffta{start}-{npass}")
 
 
-@pytest.mark.parametrize("survey", [False, True])
+@pytest.mark.parametrize("survey", [False, True, "cone"])
 def test_lognormal_option_matches_oracle(gpu_lib, survey):
-    # Sec. 6, eq. (logdelta): kept field, Psi, eps and shifts against the oracle's transform
+    # Sec. 6, eq. (logdelta): kept field, Psi, eps and shifts against the oracle's transform; the cone
+    # case has z tiles wholly outside the survey mask (no transform, zero log-mean partials)
     from paper_1504_02591_amd import native
-    if survey:
+    if survey == "cone":
+        cat = G.config2(n=64, scale=0.125)
+    elif survey:
         cat = G.lattice_box(32, 500.0, (-500.0, 250.0, 250.0), 0.7, 25, 26, ran_factor=3, bias=1.2, smooth_r=20.0)
     else:
         cat = G.config3(32)
