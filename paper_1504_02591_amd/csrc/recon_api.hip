@@ -37,7 +37,8 @@ enum StateY { SY_NONE = 0, SY_FULL = 1, SY_COMB = 2 };
 struct Layout {
   size_t grid_g = 0, grid_r = 0, mask = 0, w0 = 0, w1 = 0, w2 = 0, ds = 0, dn = 0, psi = 0, delta = 0,
          corr = 0, tw = 0, partials = 0, red = 0, totals = 0, thr = 0, dscal = 0, act = 0, err = 0, total = 0,
-         sorted = 0, bcount = 0, bstart = 0, bcursor = 0, bsum = 0, bvalid = 0, status = 0, tpart = 0;
+         sorted = 0, bcount = 0, bstart = 0, bcursor = 0, bsum = 0, bvalid = 0, slot = 0, stmp = 0, status = 0,
+         tpart = 0;
   // network buffers
   size_t a1 = 0, a2 = 0, d1 = 0, d2 = 0, ybuf = 0, dybuf = 0, upbuf = 0, wk2t = 0, w3 = 0,
          part_out = 0, part_w1 = 0, part_w2 = 0, g1 = 0, g2 = 0, g3 = 0, grad = 0, lossp = 0, losst = 0, dc = 0, uc = 0,
@@ -109,6 +110,8 @@ Layout make_layout(const recon_params_t* p) {
     L.nbins = b * nbs * nbs * nbs;
     L.nscan = (L.nbins + 256LL * kScanItems - 1) / (256LL * kScanItems);
     L.sorted = take((size_t)p->max_objects * 16);
+    L.slot = take((size_t)p->max_objects * 4);
+    L.stmp = take((size_t)p->max_objects * 16);
     L.bcount = take((L.nbins + 2) * 4);
     L.bstart = take((L.nbins + 2) * 4);
     L.bcursor = take((L.nbins + 2) * 4);
@@ -192,6 +195,14 @@ struct recon_plan_s {
   DeltaScal* dscal = nullptr;
   int *act_fan = nullptr, *act_fin = nullptr, *act_it = nullptr, *err = nullptr;
   float4* sorted = nullptr;
+  // the brick-ordered copy of the catalogue painted last through the bricks: slot of every object
+  // (input order), displacement staging for the shift in brick order, and which call it came from
+  unsigned* slot_of = nullptr;
+  float4* stmp = nullptr;
+  int srt_which = -1;
+  const float* srt_pos = nullptr;
+  long long srt_n = 0;
+  const int64_t* srt_off = nullptr;
   unsigned short *a1 = nullptr, *a2 = nullptr, *d1 = nullptr, *d2 = nullptr,
                  *wk2t = nullptr;
   float *ybuf = nullptr, *dybuf = nullptr, *upbuf = nullptr, *w3 = nullptr, *part_out = nullptr,
@@ -781,6 +792,8 @@ int recon_plan(recon_plan_t** out, const recon_params_t* params, void* workspace
   }
   if (params->max_objects > 0) {
     pl->sorted = (float4*)(w + L.sorted);
+    pl->slot_of = (unsigned*)(w + L.slot);
+    pl->stmp = (float4*)(w + L.stmp);
     pl->bcount = (unsigned*)(w + L.bcount);
     pl->bstart = (unsigned*)(w + L.bstart);
     pl->bcursor = (unsigned*)(w + L.bcursor);
@@ -893,6 +906,7 @@ int recon_paint(recon_plan_t* pl, int which, const float* pos, const float* w, i
     RECON_TRY(check_launch(pl, "paint (NGP)"));
   } else if (binned) {
     // brick-binned deposit: count, scan, scatter into brick order, per-brick LDS accumulation
+    pl->srt_which = -1;   // the sorted copy is being replaced
     long long blocks = (n + kThreads - 1) / kThreads;
     if (blocks > 8192) blocks = 8192;
     const long long nb = pl->L.nbins;
@@ -934,10 +948,12 @@ int recon_paint(recon_plan_t* pl, int which, const float* pos, const float* w, i
       PROF(pl, KP_BIN);
       if (lds_bins)
         k_bin_scatter_lds<1024><<<(unsigned)lblocks, 1024, 0, pl->stream>>>(pos, w, n, chunk, (const long long*)offsets,
-                                                                     pl->batch, pl->cic, pl->bcursor, pl->sorted);
+                                                                     pl->batch, pl->cic, pl->bcursor, pl->sorted,
+                                                                     pl->slot_of);
       else
         k_bin_scatter<<<(unsigned)blocks, kThreads, 0, pl->stream>>>(pos, w, n, (const long long*)offsets,
-                                                                     pl->batch, pl->cic, pl->bcursor, pl->sorted);
+                                                                     pl->batch, pl->cic, pl->bcursor, pl->sorted,
+                                                                     pl->slot_of);
     }
     RECON_TRY(check_launch(pl, "bin scatter"));
     {
@@ -946,6 +962,10 @@ int recon_paint(recon_plan_t* pl, int which, const float* pos, const float* w, i
                                                             (unsigned long long*)grid);
     }
     RECON_TRY(check_launch(pl, "brick deposit"));
+    pl->srt_which = which;
+    pl->srt_pos = pos;
+    pl->srt_n = n;
+    pl->srt_off = offsets;
   } else if (n > 0) {
     long long blocks = (n + kThreads - 1) / kThreads;
     if (blocks > 8192) blocks = 8192;
@@ -1259,6 +1279,20 @@ int recon_shift(recon_plan_t* pl, int which, const float* pos, int64_t n, const 
   HIP_TRY(pl, hipMemsetAsync(pl->err + 2, 0, sizeof(int), pl->stream));
   long long blocks = (n + kThreads - 1) / kThreads;
   if (blocks > 8192) blocks = 8192;
+  if (which == pl->srt_which && pos == pl->srt_pos && n == pl->srt_n && offsets == pl->srt_off) {
+    // the catalogue painted last through the bricks: shift its brick-ordered copy, then reorder
+    const long long nbs = (pl->n + kBrick - 1) / kBrick;
+    {
+      PROF(pl, KP_SHIFT);
+      k_shift_sorted<<<(unsigned)blocks, kThreads, 0, pl->stream>>>(
+          pl->sorted, n, pl->bstart, nbs * nbs * nbs, pl->batch, pl->psi, pl->cic, (float)pl->p.observer[0],
+          (float)pl->p.observer[1], (float)pl->p.observer[2], (float)pl->p.growth, which == RECON_GAL ? 1 : 0,
+          pl->stmp);
+      k_shift_unpermute<<<(unsigned)blocks, kThreads, 0, pl->stream>>>(pl->slot_of, pl->stmp, n, pos, disp_out,
+                                                                       pos_out, pl->err + 2);
+    }
+    return check_launch(pl, "shift (brick order)");
+  }
   {
     PROF(pl, KP_SHIFT);
     k_shift<<<(unsigned)blocks, kThreads, 0, pl->stream>>>(

@@ -128,6 +128,14 @@ __device__ __forceinline__ void cic_shares(unsigned long long wq, const unsigned
   share[7] = wq - sum;
 }
 
+// The rounded value itself, opaque to the compiler: u = fl(fl(x - o) s) stays one rounding, so the
+// fraction t = u - floor(u) is formed from it and never fused into fma(s, x - o, -floor(u)) (which the
+// backend otherwise does in some kernels and not in others).  No instruction is emitted.
+__device__ __forceinline__ float keep_rounded(float v) {
+  asm volatile("" : "+v"(v));
+  return v;
+}
+
 // Nearest-grid-point deposit in the same fixed point: the whole W_Q goes to node i + 1 when the
 // FP32 fraction is at least 1/2, else to node i (per axis, periodic).
 __global__ void __launch_bounds__(256) k_paint_ngp(const float* __restrict__ pos, const float* __restrict__ w,
@@ -142,7 +150,7 @@ __global__ void __launch_bounds__(256) k_paint_ngp(const float* __restrict__ pos
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       float d = __fsub_rn(pos[3 * i + a], g.o[a]);
-      uu[a] = __fmul_rn(d, g.s);
+      uu[a] = keep_rounded(__fmul_rn(d, g.s));
       ok = ok && (fabsf(uu[a]) < 1073741824.0f);
     }
     const float wv = w ? w[i] : 1.0f;
@@ -177,7 +185,7 @@ __global__ void __launch_bounds__(256) k_paint(const float* __restrict__ pos, co
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       float d = __fsub_rn(pos[3 * i + a], g.o[a]);
-      uu[a] = __fmul_rn(d, g.s);
+      uu[a] = keep_rounded(__fmul_rn(d, g.s));
       ok = ok && (fabsf(uu[a]) < 1073741824.0f);   // false for NaN / inf too
     }
     float wv = w ? w[i] : 1.0f;
@@ -226,7 +234,7 @@ __device__ __forceinline__ bool cic_locate(float px, float py, float pz, float w
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     float d = __fsub_rn(pp[a], g.o[a]);
-    uu[a] = __fmul_rn(d, g.s);
+    uu[a] = keep_rounded(__fmul_rn(d, g.s));
     ok = ok && (fabsf(uu[a]) < 1073741824.0f);
   }
   if (!ok) return false;
@@ -264,16 +272,20 @@ __global__ void __launch_bounds__(256) k_bin_count(const float* __restrict__ pos
 __global__ void __launch_bounds__(256) k_bin_scatter(const float* __restrict__ pos, const float* __restrict__ w,
                                                      long long n, const long long* __restrict__ off, int batch,
                                                      CicGeo g, unsigned* __restrict__ cursor,
-                                                     float4* __restrict__ sorted) {
+                                                     float4* __restrict__ sorted, unsigned* __restrict__ slot_of) {
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x) {
     int ii[3];
     unsigned long long tau[3];
     const float px = pos[3 * i], py = pos[3 * i + 1], pz = pos[3 * i + 2], wv = w ? w[i] : 1.0f;
-    if (!cic_locate(px, py, pz, wv, g, ii, tau)) continue;
+    if (!cic_locate(px, py, pz, wv, g, ii, tau)) {
+      slot_of[i] = 0xFFFFFFFFu;   // not in the sorted copy
+      continue;
+    }
     const int b = off ? find_realisation(off, batch, i) : 0;
     const unsigned slot = atomicAdd(cursor + brick_key(ii, g.n, b), 1u);
     sorted[slot] = make_float4(px, py, pz, wv);
+    slot_of[i] = slot;
   }
 }
 
@@ -321,7 +333,8 @@ template <int NT>
 __global__ void __launch_bounds__(NT) k_bin_scatter_lds(const float* __restrict__ pos, const float* __restrict__ w,
                                                          long long n, long long chunk,
                                                          const long long* __restrict__ off, int batch, CicGeo g,
-                                                         unsigned* __restrict__ cursor, float4* __restrict__ sorted) {
+                                                         unsigned* __restrict__ cursor, float4* __restrict__ sorted,
+                                                         unsigned* __restrict__ slot_of) {
   __shared__ unsigned hist[kLdsBins];
   const long long lo = blockIdx.x * chunk;
   if (lo >= n) return;
@@ -350,12 +363,16 @@ __global__ void __launch_bounds__(NT) k_bin_scatter_lds(const float* __restrict_
     int ii[3];
     unsigned long long tau[3];
     const float px = pos[3 * i], py = pos[3 * i + 1], pz = pos[3 * i + 2], wv = w ? w[i] : 1.0f;
-    if (!cic_locate(px, py, pz, wv, g, ii, tau)) continue;
+    if (!cic_locate(px, py, pz, wv, g, ii, tau)) {
+      slot_of[i] = 0xFFFFFFFFu;   // not in the sorted copy
+      continue;
+    }
     const int b = off ? find_realisation(off, batch, i) : 0;
     const long long key = brick_key(ii, g.n, b);
     const long long rel = key - base;
     const unsigned slot = (rel >= 0 && rel < kLdsBins) ? atomicAdd(&hist[rel], 1u) : atomicAdd(cursor + key, 1u);
     sorted[slot] = make_float4(px, py, pz, wv);
+    slot_of[i] = slot;
   }
 }
 
@@ -1725,6 +1742,64 @@ __global__ void __launch_bounds__(1024) k_reduce_pairs(const double* __restrict_
 // Shift: CIC interpolation of Psi at each object with the deposit's stencil.
 //   galaxies: disp = -Psi - f (Psi . r_hat) r_hat;  randoms: disp = -Psi
 // ---------------------------------------------------------------------------
+// CIC interpolation of Psi (float4 per node in psi_slot order) at one valid position, with the deposit's
+// cell index and fractions, and its displacement: galaxies -Psi - f (Psi . r_hat) r_hat, randoms -Psi.
+__device__ __forceinline__ void shift_one(float px, float py, float pz, const float uu[3], const float4* __restrict__ pb,
+                                          const CicGeo& cg, float ox, float oy, float oz, float growth,
+                                          int galaxies, float d[3]) {
+  int ii[3];
+  float t[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    float fl = floorf(uu[a]);
+    t[a] = __fsub_rn(uu[a], fl);
+    ii[a] = ((int)fl) & (cg.n - 1);
+  }
+  // every rounding is spelled out and nothing is contracted, so that the direct and the brick-order
+  // shift give the same bits
+  float p0 = 0.f, p1 = 0.f, p2 = 0.f;
+#pragma unroll
+  for (int cnr = 0; cnr < 8; ++cnr) {
+    const int dx = cnr & 1, dy = (cnr >> 1) & 1, dz = cnr >> 2;
+    const float wx = dx ? t[0] : __fsub_rn(1.f, t[0]), wy = dy ? t[1] : __fsub_rn(1.f, t[1]),
+                wz = dz ? t[2] : __fsub_rn(1.f, t[2]);
+    const float wgt = __fmul_rn(__fmul_rn(wx, wy), wz);
+    const float4 v = pb[psi_slot((ii[0] + dx) & (cg.n - 1), (ii[1] + dy) & (cg.n - 1), (ii[2] + dz) & (cg.n - 1), cg.n)];
+    p0 = fmaf(wgt, v.x, p0);
+    p1 = fmaf(wgt, v.y, p1);
+    p2 = fmaf(wgt, v.z, p2);
+  }
+  float d0 = -p0, d1 = -p1, d2 = -p2;
+  if (galaxies && growth != 0.f) {
+    const float rx = __fsub_rn(px, ox), ry = __fsub_rn(py, oy), rz = __fsub_rn(pz, oz);
+    const float r2 = fmaf(rz, rz, fmaf(ry, ry, __fmul_rn(rx, rx)));
+    if (r2 > 0.f) {
+      const float ir = rsqrtf(r2);
+      const float hx = __fmul_rn(rx, ir), hy = __fmul_rn(ry, ir), hz = __fmul_rn(rz, ir);
+      const float u = __fmul_rn(growth, fmaf(p2, hz, fmaf(p1, hy, __fmul_rn(p0, hx))));
+      d0 = fmaf(-u, hx, d0);
+      d1 = fmaf(-u, hy, d1);
+      d2 = fmaf(-u, hz, d2);
+    }
+  }
+  d[0] = d0;
+  d[1] = d1;
+  d[2] = d2;
+}
+
+// Scaled grid coordinates of a position; false for a non-finite or far position.
+__device__ __forceinline__ bool shift_coords(float px, float py, float pz, const CicGeo& cg, float uu[3]) {
+  const float pp[3] = {px, py, pz};
+  bool ok = true;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    float d = __fsub_rn(pp[a], cg.o[a]);
+    uu[a] = keep_rounded(__fmul_rn(d, cg.s));
+    ok = ok && (fabsf(uu[a]) < 1073741824.0f);
+  }
+  return ok;
+}
+
 __global__ void __launch_bounds__(256) k_shift(const float* __restrict__ pos, long long n,
                                                const long long* __restrict__ off, int batch,
                                                const float4* __restrict__ psi4, CicGeo cg, float ox, float oy,
@@ -1733,60 +1808,76 @@ __global__ void __launch_bounds__(256) k_shift(const float* __restrict__ pos, lo
   const long long n3 = (long long)cg.n * cg.n * cg.n;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x) {
+    const float px = pos[3 * i], py = pos[3 * i + 1], pz = pos[3 * i + 2];
     float uu[3];
-    bool ok = true;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      float d = __fsub_rn(pos[3 * i + a], cg.o[a]);
-      uu[a] = __fmul_rn(d, cg.s);
-      ok = ok && (fabsf(uu[a]) < 1073741824.0f);
-    }
-    if (!ok) {
+    if (!shift_coords(px, py, pz, cg, uu)) {
       atomicAdd(err, 1);
 #pragma unroll
       for (int a = 0; a < 3; ++a) disp[3 * i + a] = 0.f;
       continue;
     }
-    int ii[3];
-    float t[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      float fl = floorf(uu[a]);
-      t[a] = __fsub_rn(uu[a], fl);
-      ii[a] = ((int)fl) & (cg.n - 1);
-    }
     const int b = off ? find_realisation(off, batch, i) : 0;
-    const float4* pb = psi4 + (long long)b * n3;
-    float p0 = 0.f, p1 = 0.f, p2 = 0.f;
-#pragma unroll
-    for (int cnr = 0; cnr < 8; ++cnr) {
-      const int dx = cnr & 1, dy = (cnr >> 1) & 1, dz = cnr >> 2;
-      const float wgt = (dx ? t[0] : 1.f - t[0]) * (dy ? t[1] : 1.f - t[1]) * (dz ? t[2] : 1.f - t[2]);
-      const float4 v = pb[psi_slot((ii[0] + dx) & (cg.n - 1), (ii[1] + dy) & (cg.n - 1), (ii[2] + dz) & (cg.n - 1), cg.n)];
-      p0 = fmaf(wgt, v.x, p0);
-      p1 = fmaf(wgt, v.y, p1);
-      p2 = fmaf(wgt, v.z, p2);
-    }
-    float d0 = -p0, d1 = -p1, d2 = -p2;
-    if (galaxies && growth != 0.f) {
-      const float rx = pos[3 * i] - ox, ry = pos[3 * i + 1] - oy, rz = pos[3 * i + 2] - oz;
-      const float r2 = rx * rx + ry * ry + rz * rz;
-      if (r2 > 0.f) {
-        const float ir = rsqrtf(r2);
-        const float hx = rx * ir, hy = ry * ir, hz = rz * ir;
-        const float u = growth * (p0 * hx + p1 * hy + p2 * hz);
-        d0 -= u * hx;
-        d1 -= u * hy;
-        d2 -= u * hz;
-      }
-    }
-    disp[3 * i] = d0;
-    disp[3 * i + 1] = d1;
-    disp[3 * i + 2] = d2;
+    float d[3];
+    shift_one(px, py, pz, uu, psi4 + (long long)b * n3, cg, ox, oy, oz, growth, galaxies, d);
+    disp[3 * i] = d[0];
+    disp[3 * i + 1] = d[1];
+    disp[3 * i + 2] = d[2];
     if (pos_out) {
-      pos_out[3 * i] = pos[3 * i] + d0;
-      pos_out[3 * i + 1] = pos[3 * i + 1] + d1;
-      pos_out[3 * i + 2] = pos[3 * i + 2] + d2;
+      pos_out[3 * i] = __fadd_rn(px, d[0]);
+      pos_out[3 * i + 1] = __fadd_rn(py, d[1]);
+      pos_out[3 * i + 2] = __fadd_rn(pz, d[2]);
+    }
+  }
+}
+
+// The shift of the catalogue painted last, in the deposit's brick order: slot j of the sorted copy
+// (positions as painted, all valid) gets its displacement in tmp[j]; consecutive slots share a brick,
+// so the displacement gathers stay in cache.  Realisation b owns the slots from
+// start[b * per] to start[(b + 1) * per].
+__global__ void __launch_bounds__(256) k_shift_sorted(const float4* __restrict__ sorted, long long n,
+                                                      const unsigned* __restrict__ start, long long per, int batch,
+                                                      const float4* __restrict__ psi4, CicGeo cg, float ox, float oy,
+                                                      float oz, float growth, int galaxies,
+                                                      float4* __restrict__ tmp) {
+  const long long n3 = (long long)cg.n * cg.n * cg.n;
+  for (long long j = blockIdx.x * (long long)blockDim.x + threadIdx.x; j < n;
+       j += (long long)gridDim.x * blockDim.x) {
+    const float4 r = sorted[j];
+    int b = 0;
+    if (batch > 1) {
+      int lo = 0, hi = batch - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if ((long long)start[mid * per] <= j) lo = mid; else hi = mid - 1;
+      }
+      b = lo;
+    }
+    float uu[3], d[3];
+    shift_coords(r.x, r.y, r.z, cg, uu);
+    shift_one(r.x, r.y, r.z, uu, psi4 + (long long)b * n3, cg, ox, oy, oz, growth, galaxies, d);
+    tmp[j] = make_float4(d[0], d[1], d[2], 0.f);
+  }
+}
+
+// Back to the caller's order: object i takes the displacement of its slot (an object the deposit
+// rejected has no slot: counted in err, displacement 0, as in k_shift).
+__global__ void __launch_bounds__(256) k_shift_unpermute(const unsigned* __restrict__ slot_of,
+                                                         const float4* __restrict__ tmp, long long n,
+                                                         const float* __restrict__ pos, float* __restrict__ disp,
+                                                         float* __restrict__ pos_out, int* __restrict__ err) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    const unsigned s = slot_of[i];
+    float4 d = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (s < n) d = tmp[s];
+    else atomicAdd(err, 1);
+    disp[3 * i] = d.x;
+    disp[3 * i + 1] = d.y;
+    disp[3 * i + 2] = d.z;
+    if (pos_out) {
+      pos_out[3 * i] = __fadd_rn(pos[3 * i], d.x);
+      pos_out[3 * i + 1] = __fadd_rn(pos[3 * i + 1], d.y);
+      pos_out[3 * i + 2] = __fadd_rn(pos[3 * i + 2], d.z);
     }
   }
 }

@@ -474,6 +474,66 @@ def test_batched_matches_single_realisations(gpu_lib):
         np.testing.assert_allclose(eps[i], r["eps"], rtol=1e-4, atol=1e-6)
 
 
+@pytest.mark.parametrize("last", ["gal", "ran"])
+def test_shift_in_brick_order_equals_direct_shift(gpu_lib, last):
+    # the shift of the catalogue painted last (same buffer, count and offsets) runs on the deposit's
+    # brick-ordered copy and is put back in input order; a copy of the positions in another buffer takes
+    # the direct path.  Both must agree bit for bit (galaxies with the RSD term, randoms without), with
+    # the shifted positions, and with the oracle
+    from paper_1504_02591_amd import native
+    cat = G.lattice_box(32, 500.0, (-500.0, 250.0, 250.0), 0.7, 21, 22, ran_factor=3, bias=1.2, smooth_r=20.0)
+    plan = native.plan_for(cat)
+    gal, ran = to_dev(cat.gal_pos), to_dev(cat.ran_pos)
+    order = [(native.RAN, ran), (native.GAL, gal)] if last == "gal" else [(native.GAL, gal), (native.RAN, ran)]
+    for which, pos in order:
+        plan.paint(which, pos)
+    plan.solve()
+    plan.iterate(3, 0.0)
+    which, pos = order[-1]
+    d_sorted, p_sorted = plan.shift(which, pos, want_pos=True)
+    d_direct, p_direct = plan.shift(which, pos.clone(), want_pos=True)
+    plan.close()
+    diff = (d_sorted != d_direct).any(dim=1)
+    if bool(diff.any()):
+        idx = torch.nonzero(diff).flatten()[:5].cpu().numpy()
+        r = oracle_catalogue_run(cat, 3)
+        ref = r["disp_g"] if which == native.GAL else r["disp_r"]
+        print(f"{int(diff.sum())} of {diff.numel()} differ; max |d| {float((d_sorted - d_direct).abs().max()):.3e}; "
+              f"sorted vs oracle {float(np.abs(d_sorted.cpu().numpy() - ref).max()):.3e}, direct vs oracle "
+              f"{float(np.abs(d_direct.cpu().numpy() - ref).max()):.3e}; first {idx} pos {pos[idx].cpu().numpy()} "
+              f"sorted {d_sorted[idx].cpu().numpy()} direct {d_direct[idx].cpu().numpy()}", flush=True)
+    assert torch.equal(d_sorted, d_direct)
+    assert torch.equal(p_sorted, p_direct)
+    r = oracle_catalogue_run(cat, 3)
+    ref = r["disp_g"] if which == native.GAL else r["disp_r"]
+    assert float(np.abs(d_sorted.cpu().numpy() - ref).max()) <= DISP_TOL
+
+
+def test_shift_in_brick_order_batched(gpu_lib):
+    from paper_1504_02591_amd import native
+    cats = [G.lattice_box(32, 500.0, (-500.0, 250.0, 250.0), 0.7, 50 + i, 60 + i, ran_factor=2, bias=1.0,
+                          smooth_r=20.0, n_part=24 + 4 * i) for i in range(3)]
+    gal = to_dev(np.concatenate([c.gal_pos for c in cats]))
+    ran = to_dev(np.concatenate([c.ran_pos for c in cats]))
+    goff = to_dev(np.cumsum([0] + [c.gal_pos.shape[0] for c in cats]).astype(np.int64))
+    roff_np = np.cumsum([0] + [c.ran_pos.shape[0] for c in cats]).astype(np.int64)
+    roff = to_dev(roff_np)
+    c0 = cats[0]
+    plan = native.Plan(32, 500.0, c0.observer, 1.0, 0.7, 20.0, batch=3, max_objects=int(ran.shape[0]))
+    plan.paint(native.GAL, gal, offsets=goff)
+    plan.paint(native.RAN, ran, offsets=roff)
+    plan.solve()
+    plan.iterate(3, 0.0)
+    d_sorted = plan.shift(native.RAN, ran, offsets=roff)
+    d_direct = plan.shift(native.RAN, ran.clone(), offsets=roff.clone())
+    plan.close()
+    assert torch.equal(d_sorted, d_direct)
+    d = d_sorted.cpu().numpy()
+    for i, c in enumerate(cats):
+        r = oracle_catalogue_run(c, 3)
+        assert np.abs(d[roff_np[i]:roff_np[i + 1]] - r["disp_r"]).max() < DISP_TOL
+
+
 # ---------------------------------------------------------------------------
 # Tolerance mode, divergence and errors
 # ---------------------------------------------------------------------------
