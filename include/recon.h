@@ -101,8 +101,9 @@ typedef struct {
   uint32_t flags;          /* RECON_NO_RANDOMS | RECON_KEEP_DELTA | RECON_START_BUFFERS | RECON_PASS_GRAPHS |
                               RECON_LOGNORMAL (| RECON_CNN_BUFFERS | RECON_CNN_HALF, recon_cnn.h)        */
   int64_t max_objects;     /* largest catalogue painted in one call that uses the brick-binned deposit
-                              (workspace holds 16 B per object for it); larger calls fall back to
-                              per-object atomics.  0 disables binning.  Must be < 2^32.                  */
+                              (workspace holds 36 B per object for it: the brick-ordered copy, each
+                              object's slot, the brick-order shift's staging); larger calls fall back
+                              to per-object atomics.  0 disables binning.  Must be < 2^32.             */
 } recon_params_t;
 
 /* Device bytes the workspace must provide for these parameters (0 if the parameters are invalid). */
@@ -138,7 +139,12 @@ int recon_iterate(recon_plan_t* plan, int max_iter, double tol, int32_t* iters_o
 
 /* Move a catalogue back along the displacement (Sec. 1).  disp_out: device float32 [n][3]
  * (galaxies: -Psi - f (Psi.r) r, randoms: -Psi, Psi interpolated with the deposit's stencil);
- * pos_out: device float32 [n][3] receiving pos + disp, or NULL. */
+ * pos_out: device float32 [n][3] receiving pos + disp, or NULL.  When which, pos, n and offsets are
+ * those of the catalogue painted last through the brick-binned deposit (the plan has max_objects >= n
+ * and the paint had no RECON_PAINT_NGP flag), the shift runs on the deposit's brick-ordered copy of
+ * the positions and is put back in input order: the result is bit-identical to the direct shift, but
+ * it uses the positions as they were painted, so a caller that changes pos in between must paint
+ * again (or pass another buffer).  Objects the deposit rejected get a zero displacement. */
 int recon_shift(recon_plan_t* plan, int which, const float* pos, int64_t n, const int64_t* offsets,
                 float* disp_out, float* pos_out);
 
