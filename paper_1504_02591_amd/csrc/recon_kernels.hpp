@@ -1840,8 +1840,15 @@ __global__ void __launch_bounds__(256) k_shift_sorted(const float4* __restrict__
                                                       float oz, float growth, int galaxies,
                                                       float4* __restrict__ tmp) {
   const long long n3 = (long long)cg.n * cg.n * cg.n;
-  for (long long j = blockIdx.x * (long long)blockDim.x + threadIdx.x; j < n;
-       j += (long long)gridDim.x * blockDim.x) {
+  // XCD-aware order: workgroups are dealt to the 8 XCDs round robin, so XCD x (blocks x, x + 8, ...)
+  // takes the x-th eighth of the slots and its L2 holds the displacement bricks those slots need
+  // (gridDim.x is a multiple of 8; the result does not depend on the dispatch order)
+  const long long chunks = (n + 255) / 256, per_x = gridDim.x / 8;
+  const int xcd = blockIdx.x % 8;
+  const long long c_lo = chunks * xcd / 8, c_hi = chunks * (xcd + 1) / 8;
+  for (long long c = c_lo + blockIdx.x / 8; c < c_hi; c += per_x) {
+    const long long j = c * 256 + threadIdx.x;
+    if (j >= n) continue;
     const float4 r = sorted[j];
     int b = 0;
     if (batch > 1) {
