@@ -23,14 +23,39 @@ HBM_PEAK_GBS = 8000.0
 START_NAMES = {"plain": 0, "ffta1": 1, "ffta2": 2, "learned": 3}
 
 
-def algorithmic_bytes(n, n_gal, n_ran, randoms=True, keep_delta=False):
+BRICK = 16
+
+
+def touched_bricks(pos, n, box_len):
+    """16^3 bricks the brick-binned deposit of these objects touches: those holding an object's base cell
+    and their upper neighbours (a brick's stencil footprint reaches one cell into them).  The integer
+    grids are brick-sparse, so these are the bricks that are cleared, written and read back."""
+    import numpy as np
+    nbs = n // BRICK
+    cell = np.floor(pos.astype(np.float64) * (n / box_len)).astype(np.int64) % n
+    b = cell // BRICK
+    occ = np.zeros((nbs, nbs, nbs), dtype=bool)
+    occ[b[:, 2], b[:, 1], b[:, 0]] = True
+    out = np.zeros_like(occ)
+    for dz in (0, 1):
+        for dy in (0, 1):
+            for dx in (0, 1):
+                out |= np.roll(occ, (dz, dy, dx), axis=(0, 1, 2))
+    return int(out.sum())
+
+
+def algorithmic_bytes(n, n_gal, n_ran, randoms=True, keep_delta=False, bricks_g=None, bricks_r=None):
     """Compulsory bytes of one launch of each kernel kind (inputs read once, outputs written once).
 
-    cn = (N/2+1) N^2 complex spectrum elements (8 B), n3 = N^3 cells.
+    cn = (N/2+1) N^2 complex spectrum elements (8 B), n3 = N^3 cells.  The int64 deposit grids are
+    brick-sparse: only the touched bricks (bricks_g, bricks_r; all when None) are written and read.
     """
     n3 = n ** 3
     cn = (n // 2 + 1) * n * n * 8
     na = 2 if randoms else 1
+    nbs3 = (n // BRICK) ** 3
+    gb = (nbs3 if bricks_g is None else bricks_g) * BRICK ** 3 * 8      # galaxy grid bytes held
+    rb = (nbs3 if bricks_r is None else bricks_r) * BRICK ** 3 * 8 if randoms else 0
     return {
         "z_iter": 4 * cn,                       # 2 spectra in (combined state), 2 out
         "y_fanout": 4 * cn,                     # 2 in, 2 out (combined); the output's full form: 2 in, 3 out
@@ -39,12 +64,14 @@ def algorithmic_bytes(n, n_gal, n_ran, randoms=True, keep_delta=False):
         "z_final": 3 * cn + 3 * n3 * 4,         # 3 spectra in, Psi (3 real fields) out
         "y_fanout_full": 5 * cn,
         "z_final_u": 2 * cn + n3 * 4,           # combined state in, u out (learned start)
-        "z_fwd_grid": na * (n3 * 8 + cn),       # int64 grids in, spectra out
+        "z_fwd_grid": gb + rb + na * cn,        # touched bricks of the int64 grids in, spectra out
         "x_smooth": na * 2 * cn,
+        # dense-equivalent: tiles wholly outside the mask skip their spectrum reads
         "z_delta": na * cn + (n3 if randoms else 0) + cn + (n3 * 4 if keep_delta else 0),
         "x_start": cn + 3 * cn,
         "totals": na * n3 * 8,
-        "mask": n3 * 8 + n3,
+        "mask": rb + n3,                        # touched bricks of the random grid in, 1 B per cell out
+        "paint_grids": gb + rb,                 # touched bricks cleared and written (both catalogues)
         "paint": None,                          # per catalogue: 12 B per object + grid written once
         "shift": None,                          # per catalogue: 24 B per object + Psi read once
     }
@@ -287,7 +314,9 @@ def main():
     ms_per_step = 1e3 * elapsed / max(args.steps, 1)
     value = args.steps / elapsed
     n_gal, n_ran = int(gal.shape[0]), int(ran.shape[0])
-    ab = algorithmic_bytes(args.n, n_gal, n_ran)
+    bricks_g = touched_bricks(cat.gal_pos, args.n, cat.box_len)
+    bricks_r = touched_bricks(cat.ran_pos, args.n, cat.box_len)
+    ab = algorithmic_bytes(args.n, n_gal, n_ran, bricks_g=bricks_g, bricks_r=bricks_r)
     stages = {}
     for name, (count, tot_ms) in sorted(prof.items(), key=lambda kv: -kv[1][1]):
         per = ab.get(name)
@@ -305,7 +334,7 @@ def main():
             # u_p of the start (combined state) plus the output
             per_step = ab["z_final_u"] + per
         elif name == "paint":
-            per_step = 12 * (n_gal + n_ran) + 2 * args.n ** 3 * 8
+            per_step = 12 * (n_gal + n_ran) + ab["paint_grids"]
         elif name == "shift":
             per_step = 24 * (n_gal + n_ran) + 2 * 3 * args.n ** 3 * 4
         else:
@@ -350,7 +379,8 @@ def main():
                                f"{cat.info['r_min']:g}-{cat.info['r_max']:g} Mpc/h, {n_ran} randoms (50x), "
                                f"b=2 f=0.74 R=15, {head} start to eps<={args.tol:g}"
                                + (", lognormal delta" if args.lognormal else "") + (", NGP deposit" if args.ngp else ""),
-                   "n": args.n, "start": head, "tol": args.tol, "passes": passes[-1], "eps": eps_last},
+                   "n": args.n, "start": head, "tol": args.tol, "passes": passes[-1], "eps": eps_last,
+                   "touched_bricks": {"galaxies": bricks_g, "randoms": bricks_r, "of": (args.n // BRICK) ** 3}},
         "starts": {k: {kk: vv for kk, vv in v.items() if kk != "elapsed"} for k, v in results.items()},
         "roofline": roofline,
         "copy_GBs": round(copy_gbs, 1),
