@@ -143,6 +143,18 @@ def cmd_time(a):
     print(json.dumps({"choice": choice, "base_ms": res["base"]}), flush=True)
 
 
+def other_knobs():
+    """Knobs in recon_tuning.h that this tuner does not time (the deposit's launch shapes, timed on the
+    survey catalogues), with the comment lines that record their timings: kept as they are."""
+    text = open(TUNING).read()
+    keep = [l for l in text.splitlines() if l.startswith("// Deposit") or l.startswith("//   brick")
+            or l.startswith("//   binning")]
+    for k, v in re.findall(r"#define\s+(RECON_\w+)\s+(\d+)", text):
+        if k not in KNOBS:
+            keep += [f"#ifndef {k}", f"#define {k} {v}", "#endif"]
+    return keep
+
+
 def cmd_write(a):
     meta = json.load(open(os.path.join(a.dir, "result.json")))
     choice, res = meta["choice"], meta["times"]
@@ -161,6 +173,7 @@ def cmd_write(a):
     lines.append("#pragma once")
     for k in KNOBS:
         lines += [f"#ifndef {k}", f"#define {k} {choice[k]}", "#endif"]
+    lines += other_knobs()
     open(TUNING, "w").write("\n".join(lines) + "\n")
     print("\n".join(lines))
 

@@ -914,7 +914,7 @@ int recon_paint(recon_plan_t* pl, int which, const float* pos, const float* w, i
     const long long nbs = (pl->n + kBrick - 1) / kBrick;
     const bool lds_bins = nbs * nbs * nbs <= kLdsBins;
     long long lblocks = (n + 16383) / 16384;
-    if (lblocks > 1024) lblocks = 1024;
+    if (lblocks > RECON_BIN_BLOCKS) lblocks = RECON_BIN_BLOCKS;
     const long long chunk = (n + lblocks - 1) / lblocks;
     {
       PROF(pl, KP_BIN);
@@ -958,7 +958,7 @@ int recon_paint(recon_plan_t* pl, int which, const float* pos, const float* w, i
     RECON_TRY(check_launch(pl, "bin scatter"));
     {
       PROF(pl, KP_PAINT);
-      k_brick_deposit<<<(unsigned)nb, 256, 0, pl->stream>>>(pl->sorted, pl->bstart, pl->cic,
+      k_brick_deposit<RECON_BRICK_NT><<<(unsigned)nb, RECON_BRICK_NT, 0, pl->stream>>>(pl->sorted, pl->bstart, pl->cic,
                                                             (unsigned long long*)grid);
     }
     RECON_TRY(check_launch(pl, "brick deposit"));
