@@ -1281,14 +1281,11 @@ int recon_shift(recon_plan_t* pl, int which, const float* pos, int64_t n, const 
   if (blocks > 8192) blocks = 8192;
   if (which == pl->srt_which && pos == pl->srt_pos && n == pl->srt_n && offsets == pl->srt_off) {
     // the catalogue painted last through the bricks: shift its brick-ordered copy, then reorder
-    const long long nbs = (pl->n + kBrick - 1) / kBrick;
-    const long long sblocks = (blocks + 7) / 8 * 8;   // a multiple of the 8 XCDs
     {
       PROF(pl, KP_SHIFT);
-      k_shift_sorted<<<(unsigned)sblocks, kThreads, 0, pl->stream>>>(
-          pl->sorted, n, pl->bstart, nbs * nbs * nbs, pl->batch, pl->psi, pl->cic, (float)pl->p.observer[0],
-          (float)pl->p.observer[1], (float)pl->p.observer[2], (float)pl->p.growth, which == RECON_GAL ? 1 : 0,
-          pl->stmp);
+      k_shift_brick<512><<<(unsigned)pl->L.nbins, 512, 0, pl->stream>>>(
+          pl->sorted, pl->bstart, pl->psi, pl->cic, (float)pl->p.observer[0], (float)pl->p.observer[1],
+          (float)pl->p.observer[2], (float)pl->p.growth, which == RECON_GAL ? 1 : 0, pl->stmp);
       k_shift_unpermute<<<(unsigned)blocks, kThreads, 0, pl->stream>>>(pl->slot_of, pl->stmp, n, pos, disp_out,
                                                                        pos_out, pl->err + 2);
     }

@@ -1744,11 +1744,13 @@ __global__ void __launch_bounds__(1024) k_reduce_pairs(const double* __restrict_
 // Shift: CIC interpolation of Psi at each object with the deposit's stencil.
 //   galaxies: disp = -Psi - f (Psi . r_hat) r_hat;  randoms: disp = -Psi
 // ---------------------------------------------------------------------------
-// CIC interpolation of Psi (float4 per node in psi_slot order) at one valid position, with the deposit's
-// cell index and fractions, and its displacement: galaxies -Psi - f (Psi . r_hat) r_hat, randoms -Psi.
-__device__ __forceinline__ void shift_one(float px, float py, float pz, const float uu[3], const float4* __restrict__ pb,
-                                          const CicGeo& cg, float ox, float oy, float oz, float growth,
-                                          int galaxies, float d[3]) {
+// CIC interpolation of Psi at one valid position, with the deposit's cell index and fractions, and its
+// displacement: galaxies -Psi - f (Psi . r_hat) r_hat, randoms -Psi.  fetch(ix, iy, iz, ii) returns
+// Psi at the corner ix, iy, iz (wrapped) of base cell ii, from memory or from a staged footprint.
+template <class Fetch>
+__device__ __forceinline__ void shift_one_f(float px, float py, float pz, const float uu[3], Fetch fetch,
+                                            const CicGeo& cg, float ox, float oy, float oz, float growth,
+                                            int galaxies, float d[3]) {
   int ii[3];
   float t[3];
 #pragma unroll
@@ -1766,7 +1768,7 @@ __device__ __forceinline__ void shift_one(float px, float py, float pz, const fl
     const float wx = dx ? t[0] : __fsub_rn(1.f, t[0]), wy = dy ? t[1] : __fsub_rn(1.f, t[1]),
                 wz = dz ? t[2] : __fsub_rn(1.f, t[2]);
     const float wgt = __fmul_rn(__fmul_rn(wx, wy), wz);
-    const float4 v = pb[psi_slot((ii[0] + dx) & (cg.n - 1), (ii[1] + dy) & (cg.n - 1), (ii[2] + dz) & (cg.n - 1), cg.n)];
+    const float4 v = fetch(dx, dy, dz, ii);
     p0 = fmaf(wgt, v.x, p0);
     p1 = fmaf(wgt, v.y, p1);
     p2 = fmaf(wgt, v.z, p2);
@@ -1787,6 +1789,18 @@ __device__ __forceinline__ void shift_one(float px, float py, float pz, const fl
   d[0] = d0;
   d[1] = d1;
   d[2] = d2;
+}
+
+// The same from the displacement in memory (float4 per node in psi_slot order).
+__device__ __forceinline__ void shift_one(float px, float py, float pz, const float uu[3], const float4* __restrict__ pb,
+                                          const CicGeo& cg, float ox, float oy, float oz, float growth,
+                                          int galaxies, float d[3]) {
+  const int m = cg.n - 1, n = cg.n;
+  shift_one_f(px, py, pz, uu,
+              [&](int dx, int dy, int dz, const int ii[3]) {
+                return pb[psi_slot((ii[0] + dx) & m, (ii[1] + dy) & m, (ii[2] + dz) & m, n)];
+              },
+              cg, ox, oy, oz, growth, galaxies, d);
 }
 
 // Scaled grid coordinates of a position; false for a non-finite or far position.
@@ -1832,38 +1846,52 @@ __global__ void __launch_bounds__(256) k_shift(const float* __restrict__ pos, lo
   }
 }
 
-// The shift of the catalogue painted last, in the deposit's brick order: slot j of the sorted copy
-// (positions as painted, all valid) gets its displacement in tmp[j]; consecutive slots share a brick,
-// so the displacement gathers stay in cache.  Realisation b owns the slots from
-// start[b * per] to start[(b + 1) * per].
-__global__ void __launch_bounds__(256) k_shift_sorted(const float4* __restrict__ sorted, long long n,
-                                                      const unsigned* __restrict__ start, long long per, int batch,
-                                                      const float4* __restrict__ psi4, CicGeo cg, float ox, float oy,
-                                                      float oz, float growth, int galaxies,
-                                                      float4* __restrict__ tmp) {
-  const long long n3 = (long long)cg.n * cg.n * cg.n;
-  // XCD-aware order: workgroups are dealt to the 8 XCDs round robin, so XCD x (blocks x, x + 8, ...)
-  // takes the x-th eighth of the slots and its L2 holds the displacement bricks those slots need
-  // (gridDim.x is a multiple of 8; the result does not depend on the dispatch order)
-  const long long chunks = (n + 255) / 256, per_x = gridDim.x / 8;
-  const int xcd = blockIdx.x % 8;
-  const long long c_lo = chunks * xcd / 8, c_hi = chunks * (xcd + 1) / 8;
-  for (long long c = c_lo + blockIdx.x / 8; c < c_hi; c += per_x) {
-    const long long j = c * 256 + threadIdx.x;
-    if (j >= n) continue;
+// The brick-order shift with one block per 16^3 brick: the block stages the displacement at the
+// 18^3 nodes its objects' stencils can reach (the brick's 9^3 2x2x2 node bricks, components stored
+// apart) in LDS, then interpolates every object of the brick from LDS.  Same arithmetic as k_shift.
+template <int NT>
+__global__ void __launch_bounds__(NT) k_shift_brick(const float4* __restrict__ sorted,
+                                                    const unsigned* __restrict__ start,
+                                                    const float4* __restrict__ psi4, CicGeo cg, float ox, float oy,
+                                                    float oz, float growth, int galaxies,
+                                                    float4* __restrict__ tmp) {
+  constexpr int F = kBrick + 2, F3 = F * F * F;
+  __shared__ float px_[F3], py_[F3], pz_[F3];
+  const long long key = blockIdx.x;
+  const unsigned lo = start[key], hi = start[key + 1];
+  if (lo == hi) return;
+  const int n = cg.n, m = n - 1;
+  const int nbs = (n + kBrick - 1) / kBrick;
+  const long long per = (long long)nbs * nbs * nbs;
+  const int b = (int)(key / per);
+  const long long kk = key - (long long)b * per;
+  const int bx = (int)(kk % nbs) * kBrick, by = (int)((kk / nbs) % nbs) * kBrick,
+            bz = (int)(kk / ((long long)nbs * nbs)) * kBrick;
+  const float4* pb = psi4 + (long long)b * n * n * n;
+  // node (lx, ly, lz) of the footprint is grid node (bx + lx, by + ly, bz + lz), wrapped; consecutive
+  // threads take the eight nodes of one 2x2x2 node brick (one 128-byte line) in turn
+  for (int i = threadIdx.x; i < F3; i += NT) {
+    const int q = i >> 3, r = i & 7;
+    const int lx = 2 * (q % (F / 2)) + (r & 1), ly = 2 * ((q / (F / 2)) % (F / 2)) + ((r >> 1) & 1),
+              lz = 2 * (q / ((F / 2) * (F / 2))) + (r >> 2);
+    const float4 v = pb[psi_slot((bx + lx) & m, (by + ly) & m, (bz + lz) & m, n)];
+    const int l = (lz * F + ly) * F + lx;
+    px_[l] = v.x;
+    py_[l] = v.y;
+    pz_[l] = v.z;
+  }
+  __syncthreads();
+  for (unsigned j = lo + threadIdx.x; j < hi; j += NT) {
     const float4 r = sorted[j];
-    int b = 0;
-    if (batch > 1) {
-      int lo = 0, hi = batch - 1;
-      while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if ((long long)start[mid * per] <= j) lo = mid; else hi = mid - 1;
-      }
-      b = lo;
-    }
     float uu[3], d[3];
     shift_coords(r.x, r.y, r.z, cg, uu);
-    shift_one(r.x, r.y, r.z, uu, psi4 + (long long)b * n3, cg, ox, oy, oz, growth, galaxies, d);
+    shift_one_f(r.x, r.y, r.z, uu,
+                [&](int dx, int dy, int dz, const int ii[3]) {
+                  // the base cell lies in this brick (it decided the object's brick)
+                  const int l = ((ii[2] - bz + dz) * F + (ii[1] - by + dy)) * F + (ii[0] - bx + dx);
+                  return make_float4(px_[l], py_[l], pz_[l], 0.f);
+                },
+                cg, ox, oy, oz, growth, galaxies, d);
     tmp[j] = make_float4(d[0], d[1], d[2], 0.f);
   }
 }
