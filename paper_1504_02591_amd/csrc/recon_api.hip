@@ -1286,8 +1286,8 @@ int recon_shift(recon_plan_t* pl, int which, const float* pos, int64_t n, const 
       k_shift_brick<512><<<(unsigned)pl->L.nbins, 512, 0, pl->stream>>>(
           pl->sorted, pl->bstart, pl->psi, pl->cic, (float)pl->p.observer[0], (float)pl->p.observer[1],
           (float)pl->p.observer[2], (float)pl->p.growth, which == RECON_GAL ? 1 : 0, pl->stmp);
-      k_shift_unpermute<<<(unsigned)blocks, kThreads, 0, pl->stream>>>(pl->slot_of, pl->stmp, n, pos, disp_out,
-                                                                       pos_out, pl->err + 2);
+      k_shift_unpermute<<<(unsigned)((blocks + 7) / 8 * 8), kThreads, 0, pl->stream>>>(
+          pl->slot_of, pl->stmp, n, pos, disp_out, pos_out, pl->err + 2);
     }
     return check_launch(pl, "shift (brick order)");
   }

@@ -1897,13 +1897,21 @@ __global__ void __launch_bounds__(NT) k_shift_brick(const float4* __restrict__ s
 }
 
 // Back to the caller's order: object i takes the displacement of its slot (an object the deposit
-// rejected has no slot: counted in err, displacement 0, as in k_shift).
+// rejected has no slot: counted in err, displacement 0, as in k_shift).  Consecutive objects of one
+// scatter chunk have their slots in short runs per brick, so their staged results share lines; the
+// 8 XCDs (workgroups are dealt to them round robin) each take a contiguous eighth of the objects so
+// that those lines are reused in one L2 (gridDim.x is a multiple of 8; the result does not depend on
+// the dispatch order).
 __global__ void __launch_bounds__(256) k_shift_unpermute(const unsigned* __restrict__ slot_of,
                                                          const float4* __restrict__ tmp, long long n,
                                                          const float* __restrict__ pos, float* __restrict__ disp,
                                                          float* __restrict__ pos_out, int* __restrict__ err) {
-  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
-       i += (long long)gridDim.x * blockDim.x) {
+  const long long chunks = (n + 255) / 256, per_x = gridDim.x / 8;
+  const int xcd = blockIdx.x % 8;
+  const long long c_lo = chunks * xcd / 8, c_hi = chunks * (xcd + 1) / 8;
+  for (long long c = c_lo + blockIdx.x / 8; c < c_hi; c += per_x) {
+    const long long i = c * 256 + threadIdx.x;
+    if (i >= n) continue;
     const unsigned s = slot_of[i];
     float4 d = make_float4(0.f, 0.f, 0.f, 0.f);
     if (s < n) d = tmp[s];
