@@ -37,7 +37,7 @@ enum StateY { SY_NONE = 0, SY_FULL = 1, SY_COMB = 2 };
 struct Layout {
   size_t grid_g = 0, grid_r = 0, mask = 0, w0 = 0, w1 = 0, w2 = 0, ds = 0, dn = 0, psi = 0, delta = 0,
          corr = 0, tw = 0, partials = 0, red = 0, totals = 0, thr = 0, dscal = 0, act = 0, err = 0, total = 0,
-         sorted = 0, bcount = 0, bstart = 0, bcursor = 0, bsum = 0, bvalid = 0, slot = 0, stmp = 0, status = 0,
+         sorted = 0, bcount = 0, bstart = 0, bcursor = 0, bsum = 0, bvalid = 0, slot = 0, stmp = 0, bhist = 0, status = 0,
          tpart = 0;
   // network buffers
   size_t a1 = 0, a2 = 0, d1 = 0, d2 = 0, ybuf = 0, dybuf = 0, upbuf = 0, wk2t = 0, w3 = 0,
@@ -116,6 +116,7 @@ Layout make_layout(const recon_params_t* p) {
     L.bstart = take((L.nbins + 2) * 4);
     L.bcursor = take((L.nbins + 2) * 4);
     L.bsum = take(L.nscan * 4);
+    L.bhist = take((size_t)RECON_BIN_BLOCKS * kLdsBins * 4);
     L.bvalid = take(2 * L.nbins);
   }
   if (p->flags & RECON_CNN_BUFFERS) {
@@ -214,6 +215,7 @@ struct recon_plan_s {
   double *lossp = nullptr, *losst = nullptr;
   const float* net = nullptr;
   unsigned *bcount = nullptr, *bstart = nullptr, *bcursor = nullptr, *bsum = nullptr;
+  unsigned* bhist = nullptr;   // per-block LDS histograms of the binning count, reused by the scatter
   // brick-sparse integer grids: per-brick validity of each grid, used while sparse_* is set (the
   // bricks that are not valid are zero and are not read)
   unsigned char *bvalid_g = nullptr, *bvalid_r = nullptr;
@@ -798,6 +800,7 @@ int recon_plan(recon_plan_t** out, const recon_params_t* params, void* workspace
     pl->bstart = (unsigned*)(w + L.bstart);
     pl->bcursor = (unsigned*)(w + L.bcursor);
     pl->bsum = (unsigned*)(w + L.bsum);
+    pl->bhist = (unsigned*)(w + L.bhist);
     pl->bvalid_g = (unsigned char*)(w + L.bvalid);
     pl->bvalid_r = pl->bvalid_g + L.nbins;
   }
@@ -920,7 +923,8 @@ int recon_paint(recon_plan_t* pl, int which, const float* pos, const float* w, i
       PROF(pl, KP_BIN);
       if (lds_bins)
         k_bin_count_lds<1024><<<(unsigned)lblocks, 1024, 0, pl->stream>>>(pos, w, n, chunk, (const long long*)offsets,
-                                                                   pl->batch, pl->cic, pl->bcount, errc);
+                                                                   pl->batch, pl->cic, pl->bcount, errc,
+                                                                   pl->bhist);
       else
         k_bin_count<<<(unsigned)blocks, kThreads, 0, pl->stream>>>(pos, w, n, (const long long*)offsets, pl->batch,
                                                                    pl->cic, pl->bcount, errc);
@@ -949,7 +953,7 @@ int recon_paint(recon_plan_t* pl, int which, const float* pos, const float* w, i
       if (lds_bins)
         k_bin_scatter_lds<1024><<<(unsigned)lblocks, 1024, 0, pl->stream>>>(pos, w, n, chunk, (const long long*)offsets,
                                                                      pl->batch, pl->cic, pl->bcursor, pl->sorted,
-                                                                     pl->slot_of);
+                                                                     pl->slot_of, pl->bhist);
       else
         k_bin_scatter<<<(unsigned)blocks, kThreads, 0, pl->stream>>>(pos, w, n, (const long long*)offsets,
                                                                      pl->batch, pl->cic, pl->bcursor, pl->sorted,

@@ -292,11 +292,14 @@ __global__ void __launch_bounds__(256) k_bin_scatter(const float* __restrict__ p
 // Count with a per-block LDS histogram over the bins of the realisation that owns the
 // chunk's first object; one global atomic per (block, non-empty bin).  Objects whose bin
 // lies outside that window (a chunk crossing realisations) use a direct global atomic.
+// The block's histogram is also stored in bhist[block][bin] (when not null), so that the scatter,
+// which splits the catalogue into the same chunks, need not count again.
 template <int NT>
 __global__ void __launch_bounds__(NT) k_bin_count_lds(const float* __restrict__ pos, const float* __restrict__ w,
                                                        long long n, long long chunk,
                                                        const long long* __restrict__ off, int batch, CicGeo g,
-                                                       unsigned* __restrict__ counts, int* __restrict__ err) {
+                                                       unsigned* __restrict__ counts, int* __restrict__ err,
+                                                       unsigned* __restrict__ bhist) {
   __shared__ unsigned hist[kLdsBins];
   const long long lo = blockIdx.x * chunk;
   if (lo >= n) return;
@@ -324,6 +327,7 @@ __global__ void __launch_bounds__(NT) k_bin_count_lds(const float* __restrict__ 
   for (int i = threadIdx.x; i < kLdsBins; i += NT) {
     const unsigned c = hist[i];
     if (c && base + i < nb_total) atomicAdd(counts + base + i, c);
+    if (bhist) bhist[(long long)blockIdx.x * kLdsBins + i] = c;
   }
 }
 
@@ -334,7 +338,8 @@ __global__ void __launch_bounds__(NT) k_bin_scatter_lds(const float* __restrict_
                                                          long long n, long long chunk,
                                                          const long long* __restrict__ off, int batch, CicGeo g,
                                                          unsigned* __restrict__ cursor, float4* __restrict__ sorted,
-                                                         unsigned* __restrict__ slot_of) {
+                                                         unsigned* __restrict__ slot_of,
+                                                         const unsigned* __restrict__ bhist) {
   __shared__ unsigned hist[kLdsBins];
   const long long lo = blockIdx.x * chunk;
   if (lo >= n) return;
@@ -343,15 +348,20 @@ __global__ void __launch_bounds__(NT) k_bin_scatter_lds(const float* __restrict_
   const long long per = (long long)nbs * nbs * nbs;
   const long long base = (off ? (long long)find_realisation(off, batch, lo) : 0LL) * per;
   const long long nb_total = per * batch;
-  for (int i = threadIdx.x; i < kLdsBins; i += NT) hist[i] = 0u;
-  __syncthreads();
-  for (long long i = lo + threadIdx.x; i < hi; i += NT) {
-    int ii[3];
-    unsigned long long tau[3];
-    if (!cic_locate(pos[3 * i], pos[3 * i + 1], pos[3 * i + 2], w ? w[i] : 1.0f, g, ii, tau)) continue;
-    const int b = off ? find_realisation(off, batch, i) : 0;
-    const long long rel = brick_key(ii, g.n, b) - base;
-    if (rel >= 0 && rel < kLdsBins) atomicAdd(&hist[rel], 1u);
+  if (bhist) {
+    // the count kernel's histogram of this very chunk
+    for (int i = threadIdx.x; i < kLdsBins; i += NT) hist[i] = bhist[(long long)blockIdx.x * kLdsBins + i];
+  } else {
+    for (int i = threadIdx.x; i < kLdsBins; i += NT) hist[i] = 0u;
+    __syncthreads();
+    for (long long i = lo + threadIdx.x; i < hi; i += NT) {
+      int ii[3];
+      unsigned long long tau[3];
+      if (!cic_locate(pos[3 * i], pos[3 * i + 1], pos[3 * i + 2], w ? w[i] : 1.0f, g, ii, tau)) continue;
+      const int b = off ? find_realisation(off, batch, i) : 0;
+      const long long rel = brick_key(ii, g.n, b) - base;
+      if (rel >= 0 && rel < kLdsBins) atomicAdd(&hist[rel], 1u);
+    }
   }
   __syncthreads();
   for (int i = threadIdx.x; i < kLdsBins; i += NT) {
