@@ -24,6 +24,11 @@ START_NAMES = {"plain": 0, "ffta1": 1, "ffta2": 2, "learned": 3}
 
 
 BRICK = 16
+BIN_BLOCKS = 256          # binning blocks (recon_tuning.h RECON_BIN_BLOCKS), 16384 objects each at least
+
+
+def bin_blocks(count):
+    return min(BIN_BLOCKS, (count + 16383) // 16384)
 
 
 def touched_bricks(pos, n, box_len):
@@ -74,6 +79,18 @@ def algorithmic_bytes(n, n_gal, n_ran, randoms=True, keep_delta=False, bricks_g=
         "paint_grids": gb + rb,                 # touched bricks cleared and written (both catalogues)
         "paint": None,                          # per catalogue: 12 B per object + grid written once
         "shift": None,                          # per catalogue: 24 B per object + Psi read once
+        # per reconstruction (all launches of the stage together):
+        "y_fwd_step": (4 if randoms else 2) * cn + 2 * cn,   # y forward of the grids' spectra, then of D_s
+        "y_inv_step": (4 if randoms else 2) * cn,            # y inverse of the smoothed spectra
+        # binning, both catalogues: positions read by the count and by the scatter, brick-ordered copy
+        # (16 B) and slot (4 B) written, each block's 128 KB histogram written and read back
+        "bin_step": 44 * (n_gal + n_ran) + 2 * 131072 * (bin_blocks(n_gal) + bin_blocks(n_ran)),
+        "fill_step": gb + rb + 2 * 4 * nbs3,                  # touched bricks cleared, brick counts zeroed
+        # learned start: full-weighting restriction of delta_s and u_p (R in, R/8 out each), linear
+        # prolongation of the network output (R/8 in, R out); the three layers on (N/2)^3 cells read
+        # delta and u_p (8 B), write and read a1 and a2 (32 B each, bf16 x 16 channels), write Delta u
+        "resample_step": 13.5 * n3,
+        "cnn_fwd_step": (8 + 32 + 32 + 32 + 32 + 4) * n3 // 8,
     }
 
 
@@ -337,6 +354,8 @@ def main():
             per_step = 12 * (n_gal + n_ran) + ab["paint_grids"]
         elif name == "shift":
             per_step = 24 * (n_gal + n_ran) + 2 * 3 * args.n ** 3 * 4
+        elif name + "_step" in ab:
+            per_step = ab[name + "_step"]
         else:
             per_step = None if per is None else per * count / args.steps
         ent = {"launches_per_step": count / args.steps, "ms_per_step": tot_ms / args.steps,
