@@ -1,0 +1,57 @@
+"""Host-side logic around the library (no GPU): the benchmark's byte model for the brick-sparse deposit
+grids and the autotuner's handling of the tuning header."""
+import os
+import sys
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def brute_force_touched(pos, n, box_len, brick=16):
+    """Bricks holding an object's base cell, and their upper neighbours, one object at a time."""
+    nbs = n // brick
+    seen = set()
+    for p in pos.astype(np.float64):
+        c = [int(np.floor(v * n / box_len)) % n for v in p]
+        b = [v // brick for v in c]
+        for dz in (0, 1):
+            for dy in (0, 1):
+                for dx in (0, 1):
+                    seen.add(((b[2] + dz) % nbs, (b[1] + dy) % nbs, (b[0] + dx) % nbs))
+    return len(seen)
+
+
+def test_touched_bricks_matches_brute_force():
+    import bench
+    rng = np.random.default_rng(5)
+    n, box = 64, 640.0
+    clump = rng.random((300, 3)) * 60.0 + 200.0
+    edge = rng.random((50, 3)) * 8.0 + np.array([632.0, 0.0, 300.0])      # wraps in x
+    spread = rng.random((40, 3)) * box
+    for pos in (clump, edge, spread, np.concatenate([clump, edge, spread])):
+        assert bench.touched_bricks(pos, n, box) == brute_force_touched(pos, n, box)
+
+
+def test_sparse_byte_model_counts_only_touched_bricks():
+    import bench
+    dense = bench.algorithmic_bytes(512, 1000, 50000)
+    sparse = bench.algorithmic_bytes(512, 1000, 50000, bricks_g=100, bricks_r=200)
+    brick_bytes = 16 ** 3 * 8
+    cn = 257 * 512 * 512 * 8
+    assert sparse["z_fwd_grid"] == 300 * brick_bytes + 2 * cn
+    assert sparse["mask"] == 200 * brick_bytes + 512 ** 3
+    assert sparse["paint_grids"] == 300 * brick_bytes
+    assert dense["z_fwd_grid"] == 2 * 512 ** 3 * 8 + 2 * cn
+
+
+def test_autotuner_keeps_knobs_it_does_not_time():
+    from paper_1504_02591_amd import autotune
+    kept = autotune.other_knobs()
+    text = "\n".join(kept)
+    for knob in ("RECON_BRICK_NT", "RECON_BIN_BLOCKS"):
+        assert f"#define {knob}" in text
+    for knob in autotune.KNOBS:
+        assert f"#define {knob} " not in text
