@@ -175,6 +175,33 @@ struct Profiler {
 
 }  // namespace
 
+// Small host buffer in pinned memory (hipHostMalloc), for the per-pass read-backs of the convergence
+// sums: the copy is a direct DMA instead of a staged copy into pageable memory.
+struct PinnedDoubles {
+  double* p = nullptr;
+  size_t n = 0;
+  PinnedDoubles() = default;
+  PinnedDoubles(const PinnedDoubles&) = delete;
+  PinnedDoubles& operator=(const PinnedDoubles&) = delete;
+  ~PinnedDoubles() {
+    if (p) (void)hipHostFree(p);
+  }
+  bool assign(size_t count, double v) {
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    n = 0;
+    if (hipHostMalloc((void**)&p, count * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+      p = nullptr;
+      return false;
+    }
+    n = count;
+    for (size_t i = 0; i < count; ++i) p[i] = v;
+    return true;
+  }
+  double* data() { return p; }
+  double& operator[](size_t i) { return p[i]; }
+};
+
 struct recon_plan_s {
   recon_params_t p{};
   hipStream_t stream = nullptr;
@@ -229,7 +256,7 @@ struct recon_plan_s {
   std::vector<double> num0, den0, s1, s2, norm1;
   std::vector<std::vector<double>> hist;
   std::vector<int> h_fan, h_fin, h_it;
-  std::vector<double> h_red, h_red2;
+  PinnedDoubles h_red, h_red2;
   std::string msg;
   Profiler prof;
   // steady-state pass graph (RECON_PASS_GRAPHS): fan-out, z step, fan-in, x step, norm reduction
@@ -838,8 +865,10 @@ int recon_plan(recon_plan_t** out, const recon_params_t* params, void* workspace
   pl->h_fan.assign(pl->batch, 0);
   pl->h_fin.assign(pl->batch, 0);
   pl->h_it.assign(pl->batch, 0);
-  pl->h_red.assign(2 * pl->batch, 0.0);
-  pl->h_red2.assign(2 * pl->batch, 0.0);
+  if (!pl->h_red.assign(2 * pl->batch, 0.0) || !pl->h_red2.assign(2 * pl->batch, 0.0)) {
+    delete pl;
+    return RECON_EDEVICE;
+  }
 
   {
     const Ops* ops = ops_for(n);
