@@ -474,14 +474,16 @@ def test_batched_matches_single_realisations(gpu_lib):
         np.testing.assert_allclose(eps[i], r["eps"], rtol=1e-4, atol=1e-6)
 
 
+@pytest.mark.parametrize("n", [8, 16, 32])
 @pytest.mark.parametrize("last", ["gal", "ran"])
-def test_shift_in_brick_order_equals_direct_shift(gpu_lib, last):
+def test_shift_in_brick_order_equals_direct_shift(gpu_lib, last, n):
     # the shift of the catalogue painted last (same buffer, count and offsets) runs on the deposit's
     # brick-ordered copy and is put back in input order; a copy of the positions in another buffer takes
     # the direct path.  Both must agree bit for bit (galaxies with the RSD term, randoms without), with
     # the shifted positions, and with the oracle
     from paper_1504_02591_amd import native
-    cat = G.lattice_box(32, 500.0, (-500.0, 250.0, 250.0), 0.7, 21, 22, ran_factor=3, bias=1.2, smooth_r=20.0)
+    # n = 8 and 16: one 16^3 brick covers the whole grid and its footprint wraps onto itself
+    cat = G.lattice_box(n, 500.0, (-500.0, 250.0, 250.0), 0.7, 21, 22, ran_factor=3, bias=1.2, smooth_r=20.0)
     plan = native.plan_for(cat)
     gal, ran = to_dev(cat.gal_pos), to_dev(cat.ran_pos)
     order = [(native.RAN, ran), (native.GAL, gal)] if last == "gal" else [(native.GAL, gal), (native.RAN, ran)]
