@@ -1091,6 +1091,12 @@ __global__ void __launch_bounds__(ntz<N>()) k_z_iter(float2* __restrict__ a0, fl
   // part is transformed
   int tile = blockIdx.x, y, x0;
   z_tile_at<N, WP>(tile, y, x0);
+  // With RECON_Z_DEFER the second output of a tile (still in the exchange tile after its transform)
+  // is stored only after the next tile's first array has been packed, so that the stores drain while
+  // the next inverse transform runs instead of delaying the wait for the next tile's staged input;
+  // py < 0: nothing deferred
+  constexpr bool DEFER = RECON_Z_DEFER && MODE != ZI_LEARNED;
+  int py = -1, px0 = 0;
   if (MODE != ZI_LEARNED && tile < ztiles<N>()) z_stage_issue<N, WP, NT>(stage, a0, y, x0);
 #pragma unroll 1
   for (int t = 0; t < TPB && tile < ztiles<N>(); ++t) {     // block-uniform bound
@@ -1106,8 +1112,9 @@ __global__ void __launch_bounds__(ntz<N>()) k_z_iter(float2* __restrict__ a0, fl
       __syncthreads();
       if (act) z_pack_stage<N, WP>(s, stage, c, j);
       __syncthreads();                                // every thread has read the staged tile
+      if (DEFER && py >= 0) z_unpack_store<N, WP, NT, true>(buf, a1, py, px0, g.kf);
       z_stage_issue<N, WP, NT>(stage, a2, y, x0);
-      fft_rr<N, WP, true, false>(s, buf, tw);
+      fft_rr<N, WP, true, false>(s, buf, tw);        // (its first barrier ends the reads of buf above)
       z_stage_wait();
       __syncthreads();
       if (act) z_pack_stage<N, WP>(v, stage, c, j);
@@ -1160,9 +1167,15 @@ __global__ void __launch_bounds__(ntz<N>()) k_z_iter(float2* __restrict__ a0, fl
     fft_rl<N, WP, false, false>(s, buf, tw);
     z_unpack_store<N, WP, NT, false>(buf, a0, y, x0, g.kf);
     fft_rl<N, WP, false, false>(v, buf, tw);
-    z_unpack_store<N, WP, NT, true>(buf, a1, y, x0, g.kf);
+    if (DEFER) {
+      py = y;
+      px0 = x0;
+    } else {
+      z_unpack_store<N, WP, NT, true>(buf, a1, y, x0, g.kf);
+    }
     tile = next; y = ny; x0 = nx0;
   }
+  if (DEFER && py >= 0) z_unpack_store<N, WP, NT, true>(buf, a1, py, px0, g.kf);
   if (MODE != ZI_PLAIN) {
     double t1, t2;
     block_sum2<NT>((double)acc1, (double)acc2, &t1, &t2);

@@ -32,6 +32,9 @@
 #ifndef RECON_Z_TPB
 #define RECON_Z_TPB 8
 #endif
+#ifndef RECON_Z_DEFER
+#define RECON_Z_DEFER 1
+#endif
 // Deposit launch shapes, timed on the 512^3 survey catalogues (ms per reconstruction, both catalogues):
 //   brick accumulation threads per brick  256: 0.640   512: 0.522   1024: 0.585
 //   binning blocks (one 128 KB LDS histogram each)  1024: 1.018   512: 0.951   256: 0.915
