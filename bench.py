@@ -220,7 +220,8 @@ def run_batched(args, cats, torch, native, dev):
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--rounds", type=int, default=5, help="interleaved timing rounds over the starts")
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--starts", default="plain,ffta2,learned",
                     help="comma-separated starts to time; the last one available is the headline value")
@@ -295,23 +296,34 @@ def main():
             eps_last = eps[0]
         return eps_last  # eps history of the last step
 
+    # The starts are timed interleaved: each of `rounds` rounds runs a block of steps of every start
+    # (in an order rotated from round to round), each block bracketed by device synchronisations, so
+    # that clock or thermal drift over the run falls on all starts alike.  Every start runs exactly
+    # args.steps timed steps in total.
+    plans = {name: make_plan(START_NAMES[name]) for name in starts}
+    for name in starts:
+        run(plans[name], START_NAMES[name], args.warmup, [])
+    torch.cuda.synchronize()
+    rounds = max(1, min(args.rounds, args.steps))
+    blocks = [args.steps // rounds + (1 if r < args.steps % rounds else 0) for r in range(rounds)]
+    acc = {name: {"elapsed": 0.0, "passes": [], "eps": None} for name in starts}
+    for r, k in enumerate(blocks):
+        for name in starts[r % len(starts):] + starts[:r % len(starts)]:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            eps = run(plans[name], START_NAMES[name], k, acc[name]["passes"])
+            torch.cuda.synchronize()
+            acc[name]["elapsed"] += time.perf_counter() - t0
+            acc[name]["eps"] = eps
     results = {}
     for name in starts:
-        start = START_NAMES[name]
-        plan = make_plan(start)
-        passes = []
-        run(plan, start, args.warmup, passes)
-        torch.cuda.synchronize()
-        passes.clear()
-        t0 = time.perf_counter()
-        eps_last = run(plan, start, args.steps, passes)
-        torch.cuda.synchronize()
-        elapsed = time.perf_counter() - t0
-        plan.close()
-        results[name] = {"passes": passes[-1], "eps": eps_last, "ms_per_step": round(1e3 * elapsed / args.steps, 3),
+        plans[name].close()
+        elapsed, p_, eps_last = acc[name]["elapsed"], acc[name]["passes"], acc[name]["eps"]
+        results[name] = {"passes": p_[-1], "eps": eps_last, "ms_per_step": round(1e3 * elapsed / args.steps, 3),
                          "recons_per_s": round(args.steps / elapsed, 3), "elapsed": elapsed}
-        print(f"[bench] {name}: {args.steps} steps in {elapsed:.3f}s, {passes[-1]} passes, eps {eps_last[-1]:.3g}",
-              file=sys.stderr, flush=True)
+        print(f"[bench] {name}: {args.steps} steps in {elapsed:.3f}s ({rounds} interleaved rounds), {p_[-1]} passes, "
+              f"eps {eps_last[-1]:.3g}", file=sys.stderr, flush=True)
+    del plans
     head = starts[-1]
     elapsed = results[head]["elapsed"]
     passes = [results[head]["passes"]]
