@@ -253,6 +253,27 @@ __device__ __forceinline__ long long brick_key(const int ii[3], int n, int b) {
   return (long long)b * nbs * nbs * nbs + ((long long)(ii[2] / kBrick) * nbs + ii[1] / kBrick) * nbs + ii[0] / kBrick;
 }
 
+// Objects handled per loop trip by the deposit and shift loops: their loads are issued together so that
+// their latencies overlap (each thread still takes the same objects in the same order).
+constexpr int kObjBatch = 4;
+
+// Positions and weights of objects i0 + u * stride, u < U; an index at or past hi loads object hi - 1
+// instead (in bounds; the caller skips it).  Requires i0 < hi.
+template <int U>
+__device__ __forceinline__ void load_objects(const float* __restrict__ pos, const float* __restrict__ w, long long i0,
+                                             long long stride, long long hi, float px[U], float py[U], float pz[U],
+                                             float wv[U]) {
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    long long i = i0 + (long long)u * stride;
+    if (i >= hi) i = hi - 1;
+    px[u] = pos[3 * i];
+    py[u] = pos[3 * i + 1];
+    pz[u] = pos[3 * i + 2];
+    wv[u] = w ? w[i] : 1.0f;
+  }
+}
+
 __global__ void __launch_bounds__(256) k_bin_count(const float* __restrict__ pos, const float* __restrict__ w,
                                                    long long n, const long long* __restrict__ off, int batch,
                                                    CicGeo g, unsigned* __restrict__ counts, int* __restrict__ err) {
@@ -309,18 +330,26 @@ __global__ void __launch_bounds__(NT) k_bin_count_lds(const float* __restrict__ 
   const long long base = (off ? (long long)find_realisation(off, batch, lo) : 0LL) * per;
   for (int i = threadIdx.x; i < kLdsBins; i += NT) hist[i] = 0u;
   __syncthreads();
-  for (long long i = lo + threadIdx.x; i < hi; i += NT) {
-    int ii[3];
-    unsigned long long tau[3];
-    if (!cic_locate(pos[3 * i], pos[3 * i + 1], pos[3 * i + 2], w ? w[i] : 1.0f, g, ii, tau)) {
-      atomicAdd(err, 1);
-      continue;
+  constexpr int U = kObjBatch;
+  for (long long i0 = lo + threadIdx.x; i0 < hi; i0 += (long long)NT * U) {
+    float px[U], py[U], pz[U], wv[U];
+    load_objects<U>(pos, w, i0, NT, hi, px, py, pz, wv);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const long long i = i0 + (long long)u * NT;
+      if (i >= hi) break;
+      int ii[3];
+      unsigned long long tau[3];
+      if (!cic_locate(px[u], py[u], pz[u], wv[u], g, ii, tau)) {
+        atomicAdd(err, 1);
+        continue;
+      }
+      const int b = off ? find_realisation(off, batch, i) : 0;
+      const long long key = brick_key(ii, g.n, b);
+      const long long rel = key - base;
+      if (rel >= 0 && rel < kLdsBins) atomicAdd(&hist[rel], 1u);
+      else atomicAdd(counts + key, 1u);
     }
-    const int b = off ? find_realisation(off, batch, i) : 0;
-    const long long key = brick_key(ii, g.n, b);
-    const long long rel = key - base;
-    if (rel >= 0 && rel < kLdsBins) atomicAdd(&hist[rel], 1u);
-    else atomicAdd(counts + key, 1u);
   }
   __syncthreads();
   const long long nb_total = per * batch;
@@ -369,20 +398,27 @@ __global__ void __launch_bounds__(NT) k_bin_scatter_lds(const float* __restrict_
     if (c && base + i < nb_total) hist[i] = atomicAdd(cursor + base + i, c);
   }
   __syncthreads();
-  for (long long i = lo + threadIdx.x; i < hi; i += NT) {
-    int ii[3];
-    unsigned long long tau[3];
-    const float px = pos[3 * i], py = pos[3 * i + 1], pz = pos[3 * i + 2], wv = w ? w[i] : 1.0f;
-    if (!cic_locate(px, py, pz, wv, g, ii, tau)) {
-      slot_of[i] = 0xFFFFFFFFu;   // not in the sorted copy
-      continue;
+  constexpr int U = kObjBatch;
+  for (long long i0 = lo + threadIdx.x; i0 < hi; i0 += (long long)NT * U) {
+    float px[U], py[U], pz[U], wv[U];
+    load_objects<U>(pos, w, i0, NT, hi, px, py, pz, wv);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const long long i = i0 + (long long)u * NT;
+      if (i >= hi) break;
+      int ii[3];
+      unsigned long long tau[3];
+      if (!cic_locate(px[u], py[u], pz[u], wv[u], g, ii, tau)) {
+        slot_of[i] = 0xFFFFFFFFu;   // not in the sorted copy
+        continue;
+      }
+      const int b = off ? find_realisation(off, batch, i) : 0;
+      const long long key = brick_key(ii, g.n, b);
+      const long long rel = key - base;
+      const unsigned slot = (rel >= 0 && rel < kLdsBins) ? atomicAdd(&hist[rel], 1u) : atomicAdd(cursor + key, 1u);
+      sorted[slot] = make_float4(px[u], py[u], pz[u], wv[u]);
+      slot_of[i] = slot;
     }
-    const int b = off ? find_realisation(off, batch, i) : 0;
-    const long long key = brick_key(ii, g.n, b);
-    const long long rel = key - base;
-    const unsigned slot = (rel >= 0 && rel < kLdsBins) ? atomicAdd(&hist[rel], 1u) : atomicAdd(cursor + key, 1u);
-    sorted[slot] = make_float4(px, py, pz, wv);
-    slot_of[i] = slot;
   }
 }
 
@@ -470,19 +506,30 @@ __global__ void __launch_bounds__(NT) k_brick_deposit(const float4* __restrict__
   const int bx = (int)(kk % nbs), by = (int)((kk / nbs) % nbs), bz = (int)(kk / ((long long)nbs * nbs));
   for (int i = threadIdx.x; i < T * T * T; i += NT) acc[i] = 0ull;
   __syncthreads();
-  for (unsigned j = lo + threadIdx.x; j < hi; j += NT) {
-    const float4 r = sorted[j];
-    int ii[3];
-    unsigned long long tau[3];
-    cic_locate(r.x, r.y, r.z, r.w, g, ii, tau);
-    const unsigned long long wq = (unsigned long long)__double2ll_rn((double)r.w * 4294967296.0);
-    const int lx = ii[0] - bx * kBrick, ly = ii[1] - by * kBrick, lz = ii[2] - bz * kBrick;
-    unsigned long long share[8];
-    cic_shares(wq, tau, share);
+  constexpr int U = kObjBatch;
+  for (long long j0 = (long long)lo + threadIdx.x; j0 < hi; j0 += (long long)NT * U) {
+    float4 rr[U];
 #pragma unroll
-    for (int cnr = 0; cnr < 8; ++cnr) {
-      const int dx = cnr & 1, dy = (cnr >> 1) & 1, dz = cnr >> 2;
-      if (share[cnr]) atomicAdd(&acc[((lz + dz) * T + (ly + dy)) * T + (lx + dx)], share[cnr]);
+    for (int u = 0; u < U; ++u) {
+      const long long j = j0 + (long long)u * NT;
+      rr[u] = sorted[j < hi ? j : hi - 1];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (j0 + (long long)u * NT >= hi) break;
+      const float4 r = rr[u];
+      int ii[3];
+      unsigned long long tau[3];
+      cic_locate(r.x, r.y, r.z, r.w, g, ii, tau);
+      const unsigned long long wq = (unsigned long long)__double2ll_rn((double)r.w * 4294967296.0);
+      const int lx = ii[0] - bx * kBrick, ly = ii[1] - by * kBrick, lz = ii[2] - bz * kBrick;
+      unsigned long long share[8];
+      cic_shares(wq, tau, share);
+#pragma unroll
+      for (int cnr = 0; cnr < 8; ++cnr) {
+        const int dx = cnr & 1, dy = (cnr >> 1) & 1, dz = cnr >> 2;
+        if (share[cnr]) atomicAdd(&acc[((lz + dz) * T + (ly + dy)) * T + (lx + dx)], share[cnr]);
+      }
     }
   }
   __syncthreads();
@@ -1904,18 +1951,30 @@ __global__ void __launch_bounds__(NT) k_shift_brick(const float4* __restrict__ s
     pz_[l] = v.z;
   }
   __syncthreads();
-  for (unsigned j = lo + threadIdx.x; j < hi; j += NT) {
-    const float4 r = sorted[j];
-    float uu[3], d[3];
-    shift_coords(r.x, r.y, r.z, cg, uu);
-    shift_one_f(r.x, r.y, r.z, uu,
-                [&](int dx, int dy, int dz, const int ii[3]) {
-                  // the base cell lies in this brick (it decided the object's brick)
-                  const int l = ((ii[2] - bz + dz) * F + (ii[1] - by + dy)) * F + (ii[0] - bx + dx);
-                  return make_float4(px_[l], py_[l], pz_[l], 0.f);
-                },
-                cg, ox, oy, oz, growth, galaxies, d);
-    tmp[j] = make_float4(d[0], d[1], d[2], 0.f);
+  constexpr int U = kObjBatch;
+  for (long long j0 = (long long)lo + threadIdx.x; j0 < hi; j0 += (long long)NT * U) {
+    float4 rr[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const long long j = j0 + (long long)u * NT;
+      rr[u] = sorted[j < hi ? j : hi - 1];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const long long j = j0 + (long long)u * NT;
+      if (j >= hi) break;
+      const float4 r = rr[u];
+      float uu[3], d[3];
+      shift_coords(r.x, r.y, r.z, cg, uu);
+      shift_one_f(r.x, r.y, r.z, uu,
+                  [&](int dx, int dy, int dz, const int ii[3]) {
+                    // the base cell lies in this brick (it decided the object's brick)
+                    const int l = ((ii[2] - bz + dz) * F + (ii[1] - by + dy)) * F + (ii[0] - bx + dx);
+                    return make_float4(px_[l], py_[l], pz_[l], 0.f);
+                  },
+                  cg, ox, oy, oz, growth, galaxies, d);
+      tmp[j] = make_float4(d[0], d[1], d[2], 0.f);
+    }
   }
 }
 
@@ -1932,20 +1991,33 @@ __global__ void __launch_bounds__(256) k_shift_unpermute(const unsigned* __restr
   const long long chunks = (n + 255) / 256, per_x = gridDim.x / 8;
   const int xcd = blockIdx.x % 8;
   const long long c_lo = chunks * xcd / 8, c_hi = chunks * (xcd + 1) / 8;
-  for (long long c = c_lo + blockIdx.x / 8; c < c_hi; c += per_x) {
-    const long long i = c * 256 + threadIdx.x;
-    if (i >= n) continue;
-    const unsigned s = slot_of[i];
-    float4 d = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (s < n) d = tmp[s];
-    else atomicAdd(err, 1);
-    disp[3 * i] = d.x;
-    disp[3 * i + 1] = d.y;
-    disp[3 * i + 2] = d.z;
-    if (pos_out) {
-      pos_out[3 * i] = __fadd_rn(pos[3 * i], d.x);
-      pos_out[3 * i + 1] = __fadd_rn(pos[3 * i + 1], d.y);
-      pos_out[3 * i + 2] = __fadd_rn(pos[3 * i + 2], d.z);
+  constexpr int U = kObjBatch;
+  for (long long c0 = c_lo + blockIdx.x / 8; c0 < c_hi; c0 += per_x * U) {
+    // U chunks per trip: their slot and staged-result loads are issued together
+    unsigned sl[U];
+    float4 dd[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const long long i = (c0 + u * per_x) * 256 + threadIdx.x;
+      sl[u] = (c0 + u * per_x < c_hi && i < n) ? slot_of[i] : 0xFFFFFFFFu;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) dd[u] = sl[u] < n ? tmp[sl[u]] : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const long long c = c0 + u * per_x;
+      const long long i = c * 256 + threadIdx.x;
+      if (c >= c_hi || i >= n) continue;
+      const float4 d = dd[u];
+      if (sl[u] >= n) atomicAdd(err, 1);
+      disp[3 * i] = d.x;
+      disp[3 * i + 1] = d.y;
+      disp[3 * i + 2] = d.z;
+      if (pos_out) {
+        pos_out[3 * i] = __fadd_rn(pos[3 * i], d.x);
+        pos_out[3 * i + 1] = __fadd_rn(pos[3 * i + 1], d.y);
+        pos_out[3 * i + 2] = __fadd_rn(pos[3 * i + 2], d.z);
+      }
     }
   }
 }
