@@ -148,7 +148,7 @@ def other_knobs():
     survey catalogues), with the comment lines that record their timings: kept as they are."""
     text = open(TUNING).read()
     keep = [l for l in text.splitlines() if l.startswith("// Deposit") or l.startswith("//   brick")
-            or l.startswith("//   binning")]
+            or l.startswith("//   binning") or l.startswith("//   objects")]
     for k, v in re.findall(r"#define\s+(RECON_\w+)\s+(\d+)", text):
         if k not in KNOBS:
             keep += [f"#ifndef {k}", f"#define {k} {v}", "#endif"]

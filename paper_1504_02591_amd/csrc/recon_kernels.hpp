@@ -255,7 +255,7 @@ __device__ __forceinline__ long long brick_key(const int ii[3], int n, int b) {
 
 // Objects handled per loop trip by the deposit and shift loops: their loads are issued together so that
 // their latencies overlap (each thread still takes the same objects in the same order).
-constexpr int kObjBatch = 4;
+constexpr int kObjBatch = RECON_OBJ_BATCH;
 
 // Positions and weights of objects i0 + u * stride, u < U; an index at or past hi loads object hi - 1
 // instead (in bounds; the caller skips it).  Requires i0 < hi.

@@ -38,9 +38,13 @@
 // Deposit launch shapes, timed on the 512^3 survey catalogues (ms per reconstruction, both catalogues):
 //   brick accumulation threads per brick  256: 0.640   512: 0.522   1024: 0.585
 //   binning blocks (one 128 KB LDS histogram each)  1024: 1.018   512: 0.951   256: 0.915
+//   objects per loop trip (deposit + randoms' shift)  2: 0.512 + 1.025   4: 0.497 + 1.025   8: 0.510 + 1.062
 #ifndef RECON_BRICK_NT
 #define RECON_BRICK_NT 512
 #endif
 #ifndef RECON_BIN_BLOCKS
 #define RECON_BIN_BLOCKS 256
+#endif
+#ifndef RECON_OBJ_BATCH
+#define RECON_OBJ_BATCH 4
 #endif

@@ -51,7 +51,7 @@ def test_autotuner_keeps_knobs_it_does_not_time():
     from paper_1504_02591_amd import autotune
     kept = autotune.other_knobs()
     text = "\n".join(kept)
-    for knob in ("RECON_BRICK_NT", "RECON_BIN_BLOCKS"):
+    for knob in ("RECON_BRICK_NT", "RECON_BIN_BLOCKS", "RECON_OBJ_BATCH"):
         assert f"#define {knob}" in text
     for knob in autotune.KNOBS:
         assert f"#define {knob} " not in text
