@@ -237,7 +237,9 @@ __global__ void __launch_bounds__(256) k_conv_fwd(const unsigned short* __restri
                                                      Geo3 g, const uint4* __restrict__ wf,
                                                      const float* __restrict__ bias, unsigned short* __restrict__ out) {
   constexpr int NH = C == 16 ? 2 : 1;
-  __shared__ __align__(16) unsigned char lds[GCELLS * C * 2];
+  // halo of the input (bf16 channels) during the products, then the output tile (16 channels, bf16)
+  constexpr int LDS_IN = GCELLS * C * 2, LDS_OUT = FX * FY * FZ * 32;
+  __shared__ __align__(16) unsigned char lds[LDS_IN > LDS_OUT ? LDS_IN : LDS_OUT];
   const long long n3 = (long long)g.n * g.n * g.n;
   const int b = blockIdx.y, msk = g.n - 1;
   const int nbx = g.n / FX, nby = g.n / FY;
@@ -321,9 +323,12 @@ __global__ void __launch_bounds__(256) k_conv_fwd(const unsigned short* __restri
     }
   }
   // epilogue: lane (m, q) holds channel m of cells 4q..4q+3 of each output row; channel pairs are
-  // exchanged with the neighbouring lane so every lane stores two packed 32-bit words per row
+  // exchanged with the neighbouring lane and the packed words go to the output tile in LDS
+  // ([cell][16 channels]), from which every lane stores whole 16-byte halves of cells
   const float bm = bias[m];
   const bool even = (m & 1) == 0;
+  __syncthreads();                                  // every wave is done with the halo
+  unsigned* t32 = (unsigned*)lds;
 #pragma unroll
   for (int oz = 0; oz < 4; ++oz) {
 #pragma unroll
@@ -333,18 +338,28 @@ __global__ void __launch_bounds__(256) k_conv_fwd(const unsigned short* __restri
       for (int i = 0; i < 4; ++i) mine[i] = to_bf16(fmaxf(acc[oz][oy][i] + bm, 0.f));
 #pragma unroll
       for (int i = 0; i < 4; ++i) other[i] = (unsigned)__shfl_xor((int)mine[i], 1);
-      const long long row = b * n3 + ((long long)(z0 + wz0 + oz) * g.n + (y0 + wy0 + oy)) * g.n + x0;
-      unsigned* o32 = (unsigned*)out;
+      const int cell0 = ((wz0 + oz) * FY + (wy0 + oy)) * FX + 4 * q;
       const int ch2 = m >> 1;                       // channel pair
       if (even) {
-        o32[(row + 4 * q + 0) * 8 + ch2] = mine[0] | (other[0] << 16);
-        o32[(row + 4 * q + 1) * 8 + ch2] = mine[1] | (other[1] << 16);
+        t32[(cell0 + 0) * 8 + ch2] = mine[0] | (other[0] << 16);
+        t32[(cell0 + 1) * 8 + ch2] = mine[1] | (other[1] << 16);
       } else {
-        o32[(row + 4 * q + 2) * 8 + ch2] = other[2] | (mine[2] << 16);
-        o32[(row + 4 * q + 3) * 8 + ch2] = other[3] | (mine[3] << 16);
+        t32[(cell0 + 2) * 8 + ch2] = other[2] | (mine[2] << 16);
+        t32[(cell0 + 3) * 8 + ch2] = other[3] | (mine[3] << 16);
       }
     }
   }
+  __syncthreads();
+  const uint4* t128 = (const uint4*)lds;
+  uint4* o128 = (uint4*)out;
+#pragma unroll
+  for (int k = 0; k < FX * FY * FZ * 2 / 256; ++k) {
+    const int e = threadIdx.x + k * 256;           // 16-byte half e % 2 of tile cell e / 2
+    const int cell = e >> 1, lx = cell % FX, ly = (cell / FX) % FY, lz = cell / (FX * FY);
+    const long long row = b * n3 + ((long long)(z0 + lz) * g.n + (y0 + ly)) * g.n + x0 + lx;
+    o128[row * 2 + (e & 1)] = t128[e];
+  }
+
 }
 
 // Output layer (16 -> 1) on MFMA for the forward pass: with one output channel the N dimension of
