@@ -147,8 +147,15 @@ def other_knobs():
     """Knobs in recon_tuning.h that this tuner does not time (the deposit's launch shapes, timed on the
     survey catalogues), with the comment lines that record their timings: kept as they are."""
     text = open(TUNING).read()
-    keep = [l for l in text.splitlines() if l.startswith("// Deposit") or l.startswith("//   brick")
-            or l.startswith("//   binning") or l.startswith("//   objects")]
+    lines = text.splitlines()
+    keep = []
+    for i, l in enumerate(lines):         # the comment block that opens with "// Deposit"
+        if l.startswith("// Deposit"):
+            j = i
+            while j < len(lines) and lines[j].startswith("//"):
+                keep.append(lines[j])
+                j += 1
+            break
     for k, v in re.findall(r"#define\s+(RECON_\w+)\s+(\d+)", text):
         if k not in KNOBS:
             keep += [f"#ifndef {k}", f"#define {k} {v}", "#endif"]

@@ -1319,7 +1319,10 @@ int recon_shift(recon_plan_t* pl, int which, const float* pos, int64_t n, const 
       k_shift_brick<512><<<(unsigned)pl->L.nbins, 512, 0, pl->stream>>>(
           pl->sorted, pl->bstart, pl->psi, pl->cic, (float)pl->p.observer[0], (float)pl->p.observer[1],
           (float)pl->p.observer[2], (float)pl->p.growth, which == RECON_GAL ? 1 : 0, pl->stmp);
-      k_shift_unpermute<<<(unsigned)((blocks + 7) / 8 * 8), kThreads, 0, pl->stream>>>(
+      // one trip per block: per XCD, ceil(chunks / 8) chunks of 256 objects in groups of kObjBatch
+      const long long chunks = (n + kThreads - 1) / kThreads;
+      const long long ub = 8 * (((chunks + 7) / 8 + kObjBatch - 1) / kObjBatch);
+      k_shift_unpermute<<<(unsigned)ub, kThreads, 0, pl->stream>>>(
           pl->slot_of, pl->stmp, n, pos, disp_out, pos_out, pl->err + 2);
     }
     return check_launch(pl, "shift (brick order)");

@@ -1981,9 +1981,10 @@ __global__ void __launch_bounds__(NT) k_shift_brick(const float4* __restrict__ s
 // Back to the caller's order: object i takes the displacement of its slot (an object the deposit
 // rejected has no slot: counted in err, displacement 0, as in k_shift).  Consecutive objects of one
 // scatter chunk have their slots in short runs per brick, so their staged results share lines; the
-// 8 XCDs (workgroups are dealt to them round robin) each take a contiguous eighth of the objects so
-// that those lines are reused in one L2 (gridDim.x is a multiple of 8; the result does not depend on
-// the dispatch order).
+// 8 XCDs (workgroups are dealt to them round robin) each take a contiguous eighth of the objects,
+// and a block takes U adjacent 256-object chunks, so that the chunks in flight on one XCD form a
+// single window that moves forward in dispatch order and the lines it gathers are reused in that
+// XCD's L2 (gridDim.x is a multiple of 8; the result does not depend on the dispatch order).
 __global__ void __launch_bounds__(256) k_shift_unpermute(const unsigned* __restrict__ slot_of,
                                                          const float4* __restrict__ tmp, long long n,
                                                          const float* __restrict__ pos, float* __restrict__ disp,
@@ -1992,20 +1993,20 @@ __global__ void __launch_bounds__(256) k_shift_unpermute(const unsigned* __restr
   const int xcd = blockIdx.x % 8;
   const long long c_lo = chunks * xcd / 8, c_hi = chunks * (xcd + 1) / 8;
   constexpr int U = kObjBatch;
-  for (long long c0 = c_lo + blockIdx.x / 8; c0 < c_hi; c0 += per_x * U) {
-    // U chunks per trip: their slot and staged-result loads are issued together
+  for (long long c0 = c_lo + (long long)(blockIdx.x / 8) * U; c0 < c_hi; c0 += per_x * U) {
+    // the U chunks' slot and staged-result loads are issued together
     unsigned sl[U];
     float4 dd[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const long long i = (c0 + u * per_x) * 256 + threadIdx.x;
-      sl[u] = (c0 + u * per_x < c_hi && i < n) ? slot_of[i] : 0xFFFFFFFFu;
+      const long long i = (c0 + u) * 256 + threadIdx.x;
+      sl[u] = (c0 + u < c_hi && i < n) ? slot_of[i] : 0xFFFFFFFFu;
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) dd[u] = sl[u] < n ? tmp[sl[u]] : make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const long long c = c0 + u * per_x;
+      const long long c = c0 + u;
       const long long i = c * 256 + threadIdx.x;
       if (c >= c_hi || i >= n) continue;
       const float4 d = dd[u];

@@ -39,6 +39,8 @@
 //   brick accumulation threads per brick  256: 0.640   512: 0.522   1024: 0.585
 //   binning blocks (one 128 KB LDS histogram each)  1024: 1.018   512: 0.951   256: 0.915
 //   objects per loop trip (deposit + randoms' shift)  2: 0.512 + 1.025   4: 0.497 + 1.025   8: 0.510 + 1.062
+//   reorder after the brick-order shift, chunks of one block (shift stage, both catalogues)
+//     per_x apart: 1.096   adjacent (one trip per block), 2 / 4 / 8 chunks: 0.980 / 0.983 / 0.980
 #ifndef RECON_BRICK_NT
 #define RECON_BRICK_NT 512
 #endif

@@ -55,3 +55,7 @@ def test_autotuner_keeps_knobs_it_does_not_time():
         assert f"#define {knob}" in text
     for knob in autotune.KNOBS:
         assert f"#define {knob} " not in text
+    # the deposit and reorder timings stay with their knobs
+    assert any(l.startswith("// Deposit") for l in kept)
+    assert any("reorder" in l for l in kept)
+    assert not any(l.startswith("//   RECON_") or l.startswith("//   base") for l in kept)
