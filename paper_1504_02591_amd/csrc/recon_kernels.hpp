@@ -1451,40 +1451,40 @@ __global__ void __launch_bounds__(nty<N>()) k_y_fanout(float2* __restrict__ a0, 
   const bool act = threadIdx.x < L::NTF;
   const long long cn = (long long)(N / 2 + 1) * N * N;
   a0 += b * cn; a1 += b * cn; a2 += b * cn;
-  float2 v[8], w[8], keep[8];
-  if (act) y_load<N>(v, a0, p, x0, c, j);
+  // a1 first: once its z component is stored only w is live, so a0 is loaded while w is transformed
+  // and no transform runs with more than two arrays live (97 VGPRs; holding a0 and a1 through the
+  // first transform needs 119)
+  float2 v[8], w[8];
+  {
+    float2 keep[8];
+    if (act) {
+      y_load<N>(keep, a1, p, x0, c, j);
+#pragma unroll
+      for (int r = 0; r < 8; ++r) w[r] = mul_i(keep[r]) * (g.kf * deriv_mode<N>(j + r * (N / 8)));
+    }
+    fft_rr<N, W, true, false>(keep, buf, tw);
+    if (act) {
+      const float kz = g.kf * deriv_mode<N>(p);     // p in [0, N/2]; N/2 is the Nyquist plane
+#pragma unroll
+      for (int r = 0; r < 8; ++r) keep[r] = mul_i(keep[r]) * kz;
+      y_store<N>(keep, a2, p, x0, c, j);
+      y_load<N>(v, a0, p, x0, c, j);               // in flight during the transform of w
+    }
+  }
+  fft_rr<N, W, true, false>(w, buf, tw);
+  if (!COMB && act) y_store<N>(w, a1, p, x0, c, j);
   fft_rr<N, W, true, false>(v, buf, tw);
   if (act) {
     if (COMB) {
       const float rx = los_comp(g, 0, x0 + c);
 #pragma unroll
-      for (int r = 0; r < 8; ++r) v[r] = v[r] * rx;
-    } else {
-      y_store<N>(v, a0, p, x0, c, j);
-    }
-    y_load<N>(keep, a1, p, x0, c, j);
-#pragma unroll
-    for (int r = 0; r < 8; ++r) w[r] = mul_i(keep[r]) * (g.kf * deriv_mode<N>(j + r * (N / 8)));
-  }
-  fft_rr<N, W, true, false>(w, buf, tw);
-  if (act) {
-    if (COMB) {
-#pragma unroll
       for (int r = 0; r < 8; ++r) {
         const float ry = los_comp(g, 1, j + r * (N / 8));
-        v[r] = make_float2(fmaf(ry, w[r].x, v[r].x), fmaf(ry, w[r].y, v[r].y));
+        const float2 t = v[r] * rx;
+        v[r] = make_float2(fmaf(ry, w[r].x, t.x), fmaf(ry, w[r].y, t.y));
       }
-      y_store<N>(v, a0, p, x0, c, j);
-    } else {
-      y_store<N>(w, a1, p, x0, c, j);
     }
-  }
-  fft_rr<N, W, true, false>(keep, buf, tw);
-  if (act) {
-    const float kz = g.kf * deriv_mode<N>(p);     // p in [0, N/2]; N/2 is the Nyquist plane
-#pragma unroll
-    for (int r = 0; r < 8; ++r) keep[r] = mul_i(keep[r]) * kz;
-    y_store<N>(keep, a2, p, x0, c, j);
+    y_store<N>(v, a0, p, x0, c, j);
   }
 }
 
