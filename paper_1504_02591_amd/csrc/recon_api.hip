@@ -256,6 +256,7 @@ struct recon_plan_s {
   std::vector<double> num0, den0, s1, s2, norm1;
   std::vector<std::vector<double>> hist;
   std::vector<int> h_fan, h_fin, h_it;
+  std::vector<int> up_fan, up_fin, up_it;     // what the device masks hold (empty: not yet uploaded)
   PinnedDoubles h_red, h_red2;
   std::string msg;
   Profiler prof;
@@ -622,8 +623,14 @@ int launch_fill_u64(recon_plan_t* pl, void* p, long long count) {
   return check_launch(pl, "fill");
 }
 
+// The device masks are written only here, so an upload whose flags the device copy already holds
+// (the usual case from one pass to the next) is skipped.
 int upload_mask(recon_plan_t* pl, int* dev, std::vector<int>& host) {
+  std::vector<int>& held = dev == pl->act_fan ? pl->up_fan : (dev == pl->act_fin ? pl->up_fin : pl->up_it);
+  if (held == host) return RECON_OK;
+  held.clear();
   HIP_TRY(pl, hipMemcpyAsync(dev, host.data(), sizeof(int) * host.size(), hipMemcpyHostToDevice, pl->stream));
+  held = host;
   return RECON_OK;
 }
 
@@ -1201,11 +1208,12 @@ int recon_iterate(recon_plan_t* pl, int max_iter, double tol, int32_t* iters_out
                                 : (cross ? ZI_CROSS : ZI_PLAIN);
     // the learned start's pass takes u_p from the start's buffer: it needs no state Y
     const bool need_y = mode != ZI_LEARNED;
-    bool any_comb = false;
+    bool any_comb = false, any_fan = false;
     for (int b = 0; b < B; ++b) {
       pl->h_fan[b] = (need_y && pl->h_it[b] && pl->st_y[b] == SY_NONE) ? 1 : 0;
       pl->h_fin[b] = (need_y && pl->h_it[b] && pl->st_y[b] == SY_FULL) ? 1 : 0;   // combined in place
       any_comb = any_comb || pl->h_fin[b];
+      any_fan = any_fan || pl->h_fan[b];
     }
     if (any_comb) {
       RECON_TRY(upload_mask(pl, pl->act_fin, pl->h_fin));
@@ -1217,7 +1225,7 @@ int recon_iterate(recon_plan_t* pl, int max_iter, double tol, int32_t* iters_out
     if (steady && (pl->p.flags & RECON_PASS_GRAPHS) && !pl->prof.on) {
       RECON_TRY(pass_graph_launch(pl, ops));
     } else {
-      RECON_TRY(ops->fanout(pl, pl->act_fan, true));
+      if (any_fan) RECON_TRY(ops->fanout(pl, pl->act_fan, true));
       RECON_TRY(ops->ziter(pl, mode, pl->act_it));
     }
     if (cross) {
