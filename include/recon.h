@@ -132,7 +132,7 @@ int recon_solve(recon_plan_t* plan, int start, const void* net);
 
 /* Run correction passes (Sec. 5.1) until eps_n = ||Psi_n - Psi_{n-1}|| / ||Psi_n|| <= tol for every
  * realisation, or max_iter passes in this call.  tol <= 0 runs exactly max_iter passes.  Synchronises
- * once per pass.  iters_out: host int32 [batch], total passes of each realisation (may be NULL);
+ * once per pass; the transform of the final Psi is left queued on the plan's stream.  iters_out: host int32 [batch], total passes of each realisation (may be NULL);
  * eps_out: host double [batch * max_iter], eps of each pass of this call, NaN-padded (may be NULL).
  * Returns OK, NOTCONVERGED, or EDIVERGED.  May be called again to continue. */
 int recon_iterate(recon_plan_t* plan, int max_iter, double tol, int32_t* iters_out, double* eps_out);

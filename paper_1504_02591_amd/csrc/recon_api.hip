@@ -872,7 +872,7 @@ int recon_plan(recon_plan_t** out, const recon_params_t* params, void* workspace
   pl->h_fan.assign(pl->batch, 0);
   pl->h_fin.assign(pl->batch, 0);
   pl->h_it.assign(pl->batch, 0);
-  if (!pl->h_red.assign(2 * pl->batch, 0.0) || !pl->h_red2.assign(2 * pl->batch, 0.0)) {
+  if (!pl->h_red.assign(4 * pl->batch, 0.0) || !pl->h_red2.assign(2 * pl->batch, 0.0)) {
     delete pl;
     return RECON_EDEVICE;
   }
@@ -1253,10 +1253,9 @@ int recon_iterate(recon_plan_t* pl, int max_iter, double tol, int32_t* iters_out
     }
     if (!(steady && (pl->p.flags & RECON_PASS_GRAPHS) && !pl->prof.on))
       RECON_TRY(ops->fanin_xiter(pl, first_pass == 0, pl->act_it));
-    HIP_TRY(pl, hipMemcpyAsync(pl->h_red.data(), pl->red, 16 * B, hipMemcpyDeviceToHost, pl->stream));
-    if (start_pass) {
-      HIP_TRY(pl, hipMemcpyAsync(pl->h_red2.data(), pl->red + 2 * B, 16 * B, hipMemcpyDeviceToHost, pl->stream));
-    }
+    // the start pass also reads S1, S2 (red[2B..4B)): one copy of both halves
+    HIP_TRY(pl, hipMemcpyAsync(pl->h_red.data(), pl->red, (start_pass ? 32 : 16) * B, hipMemcpyDeviceToHost,
+                               pl->stream));
     HIP_TRY(pl, hipStreamSynchronize(pl->stream));
     for (int b = 0; b < B; ++b) {
       if (!pl->h_it[b]) continue;
@@ -1267,8 +1266,8 @@ int recon_iterate(recon_plan_t* pl, int max_iter, double tol, int32_t* iters_out
       if (start_pass) {
         pl->num0[b] = num * norm_k;
         pl->den0[b] = den * norm_k;
-        pl->s1[b] = pl->h_red2[2 * b];
-        pl->s2[b] = pl->h_red2[2 * b + 1];
+        pl->s1[b] = pl->h_red[2 * B + 2 * b];
+        pl->s2[b] = pl->h_red[2 * B + 2 * b + 1];
         pl->pending1[b] = 1;
       } else {
         record(b, den > 0 ? std::sqrt(num / den) : 0.0, den * norm_k);
@@ -1290,7 +1289,7 @@ int recon_iterate(recon_plan_t* pl, int max_iter, double tol, int32_t* iters_out
     for (int b = 0; b < B; ++b)
       if (pl->h_fin[b]) pl->psi_valid[b] = 1;
   }
-  HIP_TRY(pl, hipStreamSynchronize(pl->stream));
+  // the final displacement transform stays queued on the stream: what follows reads host state only
   bool div = false, notconv = false;
   for (int b = 0; b < B; ++b) {
     if (iters_out) iters_out[b] = pl->passes[b];
