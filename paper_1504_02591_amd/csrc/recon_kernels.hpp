@@ -575,11 +575,13 @@ __global__ void __launch_bounds__(256) k_brick_prepare(const unsigned* __restric
   const bool was = valid[key] != 0;
   const bool clear = mode == 0 ? touched : (mode == 1 ? (touched && !was) : !was);
   if (clear) {
+    // 16-byte stores, two cells each (a brick row starts at an even cell, the grid on 16 bytes)
     unsigned long long* gb = grid + (long long)b * n * n * n;
-    for (int i = threadIdx.x; i < kBrick * kBrick * kBrick; i += 256) {
-      const long long x = bx * kBrick + (i % kBrick), y = by * kBrick + (i / kBrick) % kBrick,
-                      z = bz * kBrick + i / (kBrick * kBrick);
-      gb[(z * n + y) * n + x] = 0ull;
+    constexpr int H = kBrick / 2;
+    for (int i = threadIdx.x; i < H * kBrick * kBrick; i += 256) {
+      const long long x = bx * kBrick + 2 * (i % H), y = by * kBrick + (i / H) % kBrick,
+                      z = bz * kBrick + i / (H * kBrick);
+      *reinterpret_cast<uint4*>(gb + (z * n + y) * n + x) = make_uint4(0u, 0u, 0u, 0u);
     }
   }
   if (threadIdx.x == 0) valid[key] = (unsigned char)(mode == 0 ? touched : (mode == 1 ? (was || touched) : 1));
