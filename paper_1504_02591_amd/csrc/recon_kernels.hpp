@@ -650,7 +650,10 @@ __global__ void __launch_bounds__(256) k_mask_win(const long long* __restrict__ 
 // The same mask on a brick-sparse random grid, one block per 16^3 brick: the 18^3 neighbourhood is
 // staged in LDS (bricks that are not valid read as zero and are not loaded), each thread owns one
 // (x, y) column of the brick and keeps the 3 x 3 sums of the 18 planes in registers, then slides
-// along z.  A brick whose 27 neighbours are all not valid has every window sum 0.
+// along z.  A brick whose 27 neighbours are all not valid has every window sum 0.  Each XCD
+// (workgroups are dealt to the 8 XCDs round robin) takes a contiguous range of bricks, so x-adjacent
+// bricks run together on one L2: their one-cell halo reads and the 16-byte pieces of the 128-byte
+// mask lines they write meet there instead of in HBM.
 __global__ void __launch_bounds__(256) k_mask_brick(const long long* __restrict__ gr, int n,
                                                     const long long* __restrict__ thr,
                                                     const unsigned char* __restrict__ valid,
@@ -661,7 +664,9 @@ __global__ void __launch_bounds__(256) k_mask_brick(const long long* __restrict_
   __shared__ int any;
   const int nbs = n / kBrick;
   const long long per = (long long)nbs * nbs * nbs;
-  const long long key = blockIdx.x;
+  const long long nblk = gridDim.x;                      // one block per brick of the batch
+  const long long key = (nblk & 7) ? (long long)blockIdx.x
+                                   : (long long)(blockIdx.x & 7) * (nblk >> 3) + (blockIdx.x >> 3);
   const int b = (int)(key / per);
   const long long kk = key - (long long)b * per;
   const int bx = (int)(kk % nbs), by = (int)((kk / nbs) % nbs), bz = (int)(kk / ((long long)nbs * nbs));
