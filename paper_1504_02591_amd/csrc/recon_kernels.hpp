@@ -223,6 +223,14 @@ __global__ void __launch_bounds__(256) k_paint(const float* __restrict__ pos, co
 // coalesced flush.  Same integer shares as k_paint, so the grid is identical.
 // ---------------------------------------------------------------------------
 constexpr int kBrick = 16;
+
+// Brick of this block in a launch of one block per brick: each XCD (workgroups are dealt to the 8
+// XCDs round robin) takes a contiguous range of bricks, so x-adjacent bricks, which share halo and
+// output lines, run together on one L2 (identity when the brick count is not a multiple of 8).
+__device__ __forceinline__ long long brick_of_block() {
+  const long long nblk = gridDim.x;
+  return (nblk & 7) ? (long long)blockIdx.x : (long long)(blockIdx.x & 7) * (nblk >> 3) + (blockIdx.x >> 3);
+}
 constexpr int kLdsBins = 32768;   // bins a block histograms in LDS (128 KB)
 
 // Cell coordinate of an object; false for a non-finite / far position or a bad weight.
@@ -496,7 +504,7 @@ __global__ void __launch_bounds__(NT) k_brick_deposit(const float4* __restrict__
                                                       unsigned long long* __restrict__ grid) {
   constexpr int T = kBrick + 1;
   __shared__ unsigned long long acc[T * T * T];
-  const long long key = blockIdx.x;
+  const long long key = brick_of_block();
   const unsigned lo = start[key], hi = start[key + 1];
   if (lo == hi) return;
   const int nbs = (g.n + kBrick - 1) / kBrick;
@@ -650,10 +658,9 @@ __global__ void __launch_bounds__(256) k_mask_win(const long long* __restrict__ 
 // The same mask on a brick-sparse random grid, one block per 16^3 brick: the 18^3 neighbourhood is
 // staged in LDS (bricks that are not valid read as zero and are not loaded), each thread owns one
 // (x, y) column of the brick and keeps the 3 x 3 sums of the 18 planes in registers, then slides
-// along z.  A brick whose 27 neighbours are all not valid has every window sum 0.  Each XCD
-// (workgroups are dealt to the 8 XCDs round robin) takes a contiguous range of bricks, so x-adjacent
-// bricks run together on one L2: their one-cell halo reads and the 16-byte pieces of the 128-byte
-// mask lines they write meet there instead of in HBM.
+// along z.  A brick whose 27 neighbours are all not valid has every window sum 0.  Bricks are
+// taken in XCD ranges (brick_of_block): the one-cell halo reads of x-adjacent bricks and the 16-byte
+// pieces of the 128-byte mask lines they write meet in one L2 instead of in HBM.
 __global__ void __launch_bounds__(256) k_mask_brick(const long long* __restrict__ gr, int n,
                                                     const long long* __restrict__ thr,
                                                     const unsigned char* __restrict__ valid,
@@ -664,9 +671,7 @@ __global__ void __launch_bounds__(256) k_mask_brick(const long long* __restrict_
   __shared__ int any;
   const int nbs = n / kBrick;
   const long long per = (long long)nbs * nbs * nbs;
-  const long long nblk = gridDim.x;                      // one block per brick of the batch
-  const long long key = (nblk & 7) ? (long long)blockIdx.x
-                                   : (long long)(blockIdx.x & 7) * (nblk >> 3) + (blockIdx.x >> 3);
+  const long long key = brick_of_block();
   const int b = (int)(key / per);
   const long long kk = key - (long long)b * per;
   const int bx = (int)(kk % nbs), by = (int)((kk / nbs) % nbs), bz = (int)(kk / ((long long)nbs * nbs));
@@ -1934,7 +1939,7 @@ __global__ void __launch_bounds__(NT) k_shift_brick(const float4* __restrict__ s
                                                     float4* __restrict__ tmp) {
   constexpr int F = kBrick + 2, F3 = F * F * F;
   __shared__ float px_[F3], py_[F3], pz_[F3];
-  const long long key = blockIdx.x;
+  const long long key = brick_of_block();
   const unsigned lo = start[key], hi = start[key + 1];
   if (lo == hi) return;
   const int n = cg.n, m = n - 1;
