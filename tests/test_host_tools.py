@@ -59,3 +59,13 @@ def test_autotuner_keeps_knobs_it_does_not_time():
     assert any(l.startswith("// Deposit") for l in kept)
     assert any("reorder" in l for l in kept)
     assert not any(l.startswith("//   RECON_") or l.startswith("//   base") for l in kept)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The benchmark measures one GPU: asked for more it exits with a message before touching a device."""
+    import subprocess
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=60, cwd=ROOT)
+    assert r.returncode == 2
+    assert "single MI355X" in r.stderr
+    assert r.stdout == ""
