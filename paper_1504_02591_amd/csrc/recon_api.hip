@@ -1119,7 +1119,8 @@ int recon_iterate(recon_plan_t* pl, int max_iter, double tol, int32_t* iters_out
     pl->hist[b].push_back(e);
     const auto& h = pl->hist[b];
     const size_t k = h.size();
-    const double nrm = std::sqrt(std::fmax(norm2, 0.0));
+    // a non-finite norm (a non-finite field) must not be clipped to 0 and read as convergence
+    const double nrm = std::isfinite(norm2) ? std::sqrt(std::fmax(norm2, 0.0)) : NAN;
     if (k == 1) pl->norm1[b] = nrm;
     if (!std::isfinite(e) || !std::isfinite(nrm) ||
         (k >= 3 && h[k - 1] > h[k - 2] && h[k - 2] > h[k - 3] && h[k - 1] > kEpsFloor) ||
@@ -1180,7 +1181,8 @@ int recon_iterate(recon_plan_t* pl, int max_iter, double tol, int32_t* iters_out
       pl->pending1[b] = 0;
       const double s3 = pl->h_red2[2 * b];
       const double diff2 = pl->num0[b] - 2.0 * (s3 - pl->s1[b]) + pl->s2[b];
-      const double e = pl->den0[b] > 0 ? std::sqrt(std::fmax(diff2, 0.0) / pl->den0[b]) : 0.0;
+      const double e = !std::isfinite(diff2) ? NAN
+                       : (pl->den0[b] > 0 ? std::sqrt(std::fmax(diff2, 0.0) / pl->den0[b]) : 0.0);
       record(b, e, pl->den0[b]);
     }
     (void)write_psi;
@@ -1237,7 +1239,8 @@ int recon_iterate(recon_plan_t* pl, int max_iter, double tol, int32_t* iters_out
         pl->pending1[b] = 0;
         const double s3 = pl->h_red2[2 * b];
         const double diff2 = pl->num0[b] - 2.0 * (s3 - pl->s1[b]) + pl->s2[b];
-        const double e = pl->den0[b] > 0 ? std::sqrt(std::fmax(diff2, 0.0) / pl->den0[b]) : 0.0;
+        const double e = !std::isfinite(diff2) ? NAN
+                         : (pl->den0[b] > 0 ? std::sqrt(std::fmax(diff2, 0.0) / pl->den0[b]) : 0.0);
         record(b, e, pl->den0[b]);
         // a realisation that stops here keeps D_1: its z step is dropped and Psi_1 recomputed at the end
         if (pl->done[b]) {

@@ -701,6 +701,24 @@ def test_divergence_detected(gpu_lib):
     plan.close()
 
 
+@pytest.mark.parametrize("start", ["plain", "ffta2"])
+def test_nonfinite_field_reads_as_divergence(gpu_lib, start):
+    # a non-finite overdensity (e.g. from a broken upstream step) must end in EDIVERGED, not in a
+    # clipped convergence norm of 0 that reports a NaN displacement as converged
+    from paper_1504_02591_amd import native
+    n, box = 16, 300.0
+    rng = np.random.default_rng(4)
+    delta = O.smooth(rng.standard_normal((n, n, n)), box, 30.0).astype(np.float32)
+    delta[3, 5, 7] = np.nan
+    plan = native.Plan(n, box, (150.0, 150.0, -500.0), 2.0, 0.7, 0.0, randoms=False, start_buffers=True)
+    plan.set_delta(to_dev(delta))
+    plan.solve(native.START_PLAIN if start == "plain" else native.START_FFTA2)
+    with pytest.raises(native.ReconError) as ei:
+        plan.iterate(10, 1e-3)
+    assert ei.value.code == native.RECON_EDIVERGED
+    plan.close()
+
+
 def test_invalid_inputs_and_order(gpu_lib):
     from paper_1504_02591_amd import native
     plan = native.Plan(16, 100.0, (50.0, 50.0, 50.0), 1.0, 0.5, 10.0)
