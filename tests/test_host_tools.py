@@ -69,3 +69,21 @@ def test_bench_refuses_more_than_one_gpu():
     assert r.returncode == 2
     assert "single MI355X" in r.stderr
     assert r.stdout == ""
+
+
+def test_every_timed_stage_has_a_byte_model():
+    """Each stage the library's event profile reports on the benchmarked path carries algorithmic
+    bytes in the benchmark's model, so its roofline fraction is reported; the exceptions are the
+    tiny reductions and scans and the stages the benchmark never runs (the real-field forward z
+    pass behind recon_set_delta, network training)."""
+    import ctypes
+    import bench
+    from paper_1504_02591_amd import native
+    lib = native.load()
+    lib.recon_profile_kernel_name.restype = ctypes.c_char_p
+    names = [lib.recon_profile_kernel_name(k) for k in range(64)]
+    names = [s.decode() for s in names if s]
+    assert "x_iter" in names and "shift" in names
+    ab = bench.algorithmic_bytes(512, 1000, 50000, bricks_g=100, bricks_r=200)
+    missing = {n for n in names if n not in ab and n + "_step" not in ab}
+    assert missing <= {"reduce", "scan", "z_fwd_real", "cnn_bwd"}, missing
