@@ -79,6 +79,35 @@ def test_first_adam_step_moves_by_lr_times_sign():
     np.testing.assert_allclose(new - theta, -1e-3 * np.sign(g), rtol=1e-6)
 
 
+def test_adam_steps_hand_values():
+    """Pins adam_step past the first step (Kingma & Ba 2015, Algorithm 1): theta_0 = 0.5, lr = 0.01,
+    gradients 0.2, -0.1, 0.4.  By hand:
+      step 1: m = 0.02,   v = 4e-5,         m^ = 0.2,          v^ = 0.04
+      step 2: m = 0.008,  v = 4.996e-5,     m^ = 0.008/0.19,   v^ = 4.996e-5/0.001999
+      step 3: m = 0.0472, v = 2.0991004e-4, m^ = 0.0472/0.271, v^ = 2.0991004e-4/0.002997001
+    and theta_t = theta_{t-1} - lr m^ / (sqrt(v^) + 1e-8)."""
+    theta, m, v = np.array([0.5]), np.zeros(1), np.zeros(1)
+    hand = [(0.02, 4e-5, 0.4900000005),
+            (0.008, 4.996e-5, 0.4873366302718676),
+            (0.0472, 2.0991004e-4, 0.4807555145179949)]
+    for step, (g, (m_e, v_e, th_e)) in enumerate(zip((0.2, -0.1, 0.4), hand), start=1):
+        theta, m, v = C.adam_step(theta, m, v, np.array([g]), step, 0.01)
+        np.testing.assert_allclose(m, m_e, rtol=1e-12)
+        np.testing.assert_allclose(v, v_e, rtol=1e-12)
+        np.testing.assert_allclose(theta, th_e, rtol=1e-12)
+
+
+def test_adam_constant_gradient_moves_by_lr_every_step():
+    """With a constant gradient g the bias-corrected moments are exactly g and g^2 at every step, so
+    each update is lr g / (|g| + eps): a wrong bias-correction power fails from step 2 on."""
+    theta, m, v = np.zeros(3), np.zeros(3), np.zeros(3)
+    g = np.array([0.3, -2.0, 5e-3])
+    for step in range(1, 11):
+        new, m, v = C.adam_step(theta, m, v, g, step, 1e-3)
+        np.testing.assert_allclose(new - theta, -1e-3 * g / (np.abs(g) + 1e-8), rtol=1e-9)
+        theta = new
+
+
 def test_parameter_layout():
     assert C.N_PARAMS == 16 * 27 * 8 + 16 + 16 * 27 * 16 + 16 + 27 * 16 + 1
     theta = np.arange(C.N_PARAMS, dtype=np.float64)

@@ -400,6 +400,58 @@ def test_uniform_lattice_has_zero_overdensity():
     np.testing.assert_allclose(d2, 0.0, atol=1e-12)
 
 
+def _node_lattice(n, box, weight_of_node):
+    """One object on every grid node (box a power of two times n, so every node coordinate and the
+    grid scale are exact in float32 and each object's whole weight lands on its own node)."""
+    h = box / n
+    i = np.arange(n)
+    z, y, x = np.meshgrid(i, i, i, indexing="ij")
+    pos = np.stack([x.ravel() * h, y.ravel() * h, z.ravel() * h], axis=1).astype(np.float32)
+    w = weight_of_node(x.ravel(), y.ravel(), z.ravel()).astype(np.float32)
+    return pos, w
+
+
+def test_overdensity_with_randoms_closed_form():
+    """Pins overdensity() in survey mode (Sec. 2 definition of delta, Sec. 3.2 randoms and mask).
+
+    No smoothing, galaxies of weight 1 + a cos(2 pi m y / L) and randoms of weight 3 on the nodes of
+    the half box x < L/2 only.  The galaxy weights average to 1 over the covered nodes, so the
+    random-to-galaxy normalisation is alpha = 1/3 and delta_s = w_g / (alpha w_r) - 1 = a cos(2 pi m y/L)
+    on the covered nodes, 0 outside the mask.  A denominator of R instead of alpha R, or alpha
+    inverted, gives a cos / 3 or 9 (1 + a cos) - 1 and fails."""
+    n, box, a, m = 16, 128.0, 0.3, 2
+    cover = lambda x, y, z: x < n // 2
+    pos_g, w_g = _node_lattice(n, box, lambda x, y, z: 1.0 + a * np.cos(2 * np.pi * m * y / n))
+    pos_r, w_r = _node_lattice(n, box, lambda x, y, z: np.full(x.shape, 3.0))
+    keep = cover(pos_g[:, 0] / (box / n), None, None)
+    g = O.paint(pos_g[keep], w_g[keep], n, box, (0, 0, 0))
+    r = O.paint(pos_r[keep], w_r[keep], n, box, (0, 0, 0))
+    d = O.overdensity(g, r, box, 0.0, 0.1)
+    i = np.arange(n)
+    z, y, x = np.meshgrid(i, i, i, indexing="ij")
+    expect = np.where(x < n // 2, a * np.cos(2 * np.pi * m * y / n), 0.0)
+    np.testing.assert_allclose(d, expect, rtol=0, atol=2e-7)
+
+
+def test_overdensity_with_randoms_smoothed_plane_wave():
+    """Survey-mode overdensity of a smoothed plane wave (Sec. 3.1 smoothing, Sec. 3.2 separate
+    smoothing of galaxies and randoms): galaxies of weight 1 + a cos(k0 . x) and uniform randoms of
+    weight 3 on every node; smoothing multiplies the wave by exp(-k0^2 R^2 / 2) and leaves the
+    randoms uniform, so delta_s = a exp(-k0^2 R^2/2) cos(k0 . x) everywhere."""
+    n, box, a, R = 16, 128.0, 0.25, 9.0
+    mx, mz = 1, 2
+    pos_g, w_g = _node_lattice(n, box, lambda x, y, z: 1.0 + a * np.cos(2 * np.pi * (mx * x + mz * z) / n))
+    pos_r, w_r = _node_lattice(n, box, lambda x, y, z: np.full(x.shape, 3.0))
+    g = O.paint(pos_g, w_g, n, box, (0, 0, 0))
+    r = O.paint(pos_r, w_r, n, box, (0, 0, 0))
+    d = O.overdensity(g, r, box, R, 0.1)
+    k2 = (2 * np.pi / box) ** 2 * (mx * mx + mz * mz)
+    i = np.arange(n)
+    z, y, x = np.meshgrid(i, i, i, indexing="ij")
+    expect = a * np.exp(-0.5 * k2 * R * R) * np.cos(2 * np.pi * (mx * x + mz * z) / n)
+    np.testing.assert_allclose(d, expect, rtol=0, atol=2e-7)
+
+
 def test_bad_inputs_rejected():
     with pytest.raises(ValueError):
         O.paint(np.array([[np.nan, 0, 0]], np.float32), None, 8, 8.0, (0, 0, 0))
