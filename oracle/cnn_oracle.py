@@ -22,8 +22,15 @@ bf16=True rounds x0, the weights, a1 and a2 to bfloat16 (round to nearest even)
 where the GPU stores them in bfloat16; sums stay in float64.  Parity unpinned
 against the paper (the paper has no network); pinned here against
 scipy.ndimage.correlate and central finite differences.
+
+conv() writes the convolution with array shifts; conv_loops() computes the same
+definition with plain C loops (oracle/cnn_conv.c, built by the repository's build
+step) for grids where the array form is too slow (256^3), and is pinned to conv().
 """
 from __future__ import annotations
+
+import ctypes
+import os
 
 import numpy as np
 
@@ -64,12 +71,18 @@ def init_params(seed):
 
 
 def bf16(x):
-    """Round float64 values to bfloat16 (round to nearest, ties to even), returned as float64."""
-    f = np.asarray(x, dtype=np.float32)
-    u = f.view(np.uint32).astype(np.uint64)
-    lsb = (u >> 16) & 1
-    r = ((u + 0x7FFF + lsb) >> 16) << 16
-    return r.astype(np.uint32).view(np.float32).astype(np.float64)
+    """Round float64 values to bfloat16 (round to nearest, ties to even), returned as float64.
+
+    On the float32 bit pattern u: add 0x7FFF plus the lowest kept bit, clear the 16 dropped bits
+    (uint32 arithmetic, in place)."""
+    u = np.array(x, dtype=np.float32).view(np.uint32)
+    lsb = u >> 16
+    lsb &= 1
+    u += np.uint32(0x7FFF)
+    u += lsb
+    del lsb
+    u &= np.uint32(0xFFFF0000)
+    return u.view(np.float32).astype(np.float64)
 
 
 def shift(f, d):
@@ -85,6 +98,41 @@ def conv(x, w, b):
         xs = shift(x, d)
         out += np.einsum("oi,izyx->ozyx", w[:, t, :], xs)
     return out + b.reshape(-1, 1, 1, 1)
+
+
+_CONV_LIB = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libcnn_conv.so")
+_conv_handle = None
+
+
+def _conv_lib():
+    global _conv_handle
+    if _conv_handle is None:
+        if not os.path.exists(_CONV_LIB):
+            raise RuntimeError(f"{_CONV_LIB} is missing; build it with __graft_entry__.build()")
+        lib = ctypes.CDLL(_CONV_LIB)
+        dp = ctypes.POINTER(ctypes.c_double)
+        lib.conv3_periodic.argtypes = [dp, ctypes.c_int, ctypes.c_int, dp, dp, ctypes.c_int, dp]
+        lib.conv3_periodic.restype = ctypes.c_int
+        _conv_handle = lib
+    return _conv_handle
+
+
+def conv_loops(x, w, b):
+    """conv(x, w, b) by plain FP64 loops in C (same definition; channels moved last for the loops)."""
+    cout, _, cin = w.shape
+    n = x.shape[-1]
+    if x.shape != (cin, n, n, n) or cout > 64:
+        raise ValueError("conv_loops: x must be [C_in, n, n, n] and C_out <= 64")
+    xl = np.ascontiguousarray(np.moveaxis(np.asarray(x, dtype=np.float64), 0, -1))
+    wl = np.ascontiguousarray(w, dtype=np.float64)
+    bl = np.ascontiguousarray(b, dtype=np.float64)
+    out = np.empty((n, n, n, cout))
+    dp = ctypes.POINTER(ctypes.c_double)
+    rc = _conv_lib().conv3_periodic(xl.ctypes.data_as(dp), cin, n, wl.ctypes.data_as(dp), bl.ctypes.data_as(dp),
+                                    cout, out.ctypes.data_as(dp))
+    if rc != 0:
+        raise RuntimeError("conv_loops failed")
+    return np.ascontiguousarray(np.moveaxis(out, -1, 0))
 
 
 def conv_input_grad(g, w):
@@ -106,14 +154,14 @@ def inputs(delta, u_p, rhat):
     return np.stack([delta, S_U * u_p, rhat[0], rhat[1], rhat[2], z, z, z])
 
 
-def forward(theta, delta, u_p, rhat, bf16_mode=False):
+def forward(theta, delta, u_p, rhat, bf16_mode=False, conv_fn=conv):
     """Returns (y, cache); y is the scaled correction S_U * Delta u on the grid."""
     p = unpack(theta)
     q = (lambda a: bf16(a)) if bf16_mode else (lambda a: a)
     x0 = q(inputs(delta, u_p, rhat))
-    a1 = q(np.maximum(conv(x0, q(p["W1"]), p["b1"]), 0.0))
-    a2 = q(np.maximum(conv(a1, q(p["W2"]), p["b2"]), 0.0))
-    y = conv(a2, q(p["W3"]), p["b3"])[0]
+    a1 = q(np.maximum(conv_fn(x0, q(p["W1"]), p["b1"]), 0.0))
+    a2 = q(np.maximum(conv_fn(a1, q(p["W2"]), p["b2"]), 0.0))
+    y = conv_fn(a2, q(p["W3"]), p["b3"])[0]
     return y, dict(x0=x0, a1=a1, a2=a2, p=p, q=q)
 
 
@@ -172,10 +220,10 @@ def prolong(c):
     return g
 
 
-def half_grid_correction(theta, delta, u_p, rhat_coarse, bf16_mode=False):
+def half_grid_correction(theta, delta, u_p, rhat_coarse, bf16_mode=False, conv_fn=conv):
     """Delta u on the fine grid when the network runs on the (n/2)^3 grid: restrict delta_s and
     u_p, evaluate the network there (r_hat of the coarse nodes), prolong y / S_U."""
-    y, _ = forward(theta, restrict(delta), restrict(u_p), rhat_coarse, bf16_mode)
+    y, _ = forward(theta, restrict(delta), restrict(u_p), rhat_coarse, bf16_mode, conv_fn)
     return prolong(y / S_U)
 
 

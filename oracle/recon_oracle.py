@@ -362,14 +362,15 @@ def ffta_coefficient(start, growth, bias):
 
 def reconstruct_field(delta_s, box_len, origin, observer, bias, growth,
                       n_passes=None, tol=None, max_iter=50, start=START_PLAIN,
-                      start_correction=None, rhat=None):
+                      start_correction=None, rhat=None, keep=()):
     """Iterative RSD removal from the smoothed redshift-space overdensity.
 
     delta_s: (n,n,n) float64.  Runs exactly n_passes passes when given, otherwise
     stops at the first n >= 1 with eps_n <= tol (or max_iter).  start selects the
     starting displacement: plain (Psi from delta_s), FFTA-1/FFTA-2, or learned,
     where start_correction is the scalar field Delta added along r-hat.
-    Returns dict(psi=(3,n,n,n), eps=[eps_1..], passes=n, diverged=bool, D=final density spectrum).
+    Returns dict(psi=(3,n,n,n), eps=[eps_1..], passes=n, diverged=bool, D=final density spectrum,
+    psi_at={k: Psi_k for the pass counts k listed in keep}).
     """
     n = delta_s.shape[0]
     if rhat is None:
@@ -390,6 +391,7 @@ def reconstruct_field(delta_s, box_len, origin, observer, bias, growth,
         raise ValueError("unknown start")
 
     eps_hist = []
+    psi_at = {0: psi.copy()} if 0 in keep else {}
     passes = 0
     diverged = False
     norm1 = None
@@ -405,6 +407,8 @@ def reconstruct_field(delta_s, box_len, origin, observer, bias, growth,
         psi = psi_new
         passes += 1
         eps_hist.append(float(eps))
+        if passes in keep:
+            psi_at[passes] = psi.copy()
         norm1 = den if norm1 is None else norm1
         if not np.isfinite(eps):
             diverged = True
@@ -417,7 +421,7 @@ def reconstruct_field(delta_s, box_len, origin, observer, bias, growth,
             break
         if n_passes is None and tol is not None and eps <= tol:
             break
-    return {"psi": psi, "eps": eps_hist, "passes": passes, "diverged": diverged, "D": dk}
+    return {"psi": psi, "eps": eps_hist, "passes": passes, "diverged": diverged, "D": dk, "psi_at": psi_at}
 
 
 # ---------------------------------------------------------------------------

@@ -108,6 +108,17 @@ def test_adam_constant_gradient_moves_by_lr_every_step():
         theta = new
 
 
+@pytest.mark.parametrize("cin,cout", [(8, 16), (16, 16), (16, 1)])
+def test_loop_convolution_equals_array_convolution(cin, cout):
+    """The C loops (conv_loops, used on 256^3 grids) compute the same periodic convolution as conv."""
+    rng = np.random.default_rng(cin * 100 + cout)
+    n = 12
+    x = rng.standard_normal((cin, n, n, n))
+    w = rng.standard_normal((cout, 27, cin))
+    b = rng.standard_normal(cout)
+    np.testing.assert_allclose(C.conv_loops(x, w, b), C.conv(x, w, b), rtol=0, atol=1e-12)
+
+
 def test_parameter_layout():
     assert C.N_PARAMS == 16 * 27 * 8 + 16 + 16 * 27 * 16 + 16 + 27 * 16 + 1
     theta = np.arange(C.N_PARAMS, dtype=np.float64)
