@@ -52,6 +52,8 @@ extern "C" {
 /* return codes */
 #define RECON_OK 0
 #define RECON_NOTCONVERGED 1   /* warning: max_iter reached before the tolerance */
+#define RECON_RESTARTED 2      /* warning: a learned start was rejected and its realisation restarted
+                                  from the plain start (converged otherwise); see recon_iterate   */
 #define RECON_EINVAL (-1)      /* invalid argument or invalid input data (NaN position, bad weight, ...) */
 #define RECON_ENOMEM (-2)      /* workspace too small */
 #define RECON_EDEVICE (-3)     /* a HIP runtime call or kernel launch failed */
@@ -62,6 +64,9 @@ extern "C" {
 /* catalogue selector */
 #define RECON_GAL 0
 #define RECON_RAN 1
+/* recon_shift: or-ed into the catalogue selector when pos, n and offsets are the catalogue painted last
+   through the brick-binned deposit and pos has not changed since that paint */
+#define RECON_SHIFT_AS_PAINTED 256
 
 /* starting displacement */
 #define RECON_START_PLAIN 0    /* Psi_0 from the redshift-space overdensity (Sec. 5.2, first start) */
@@ -134,17 +139,28 @@ int recon_solve(recon_plan_t* plan, int start, const void* net);
  * realisation, or max_iter passes in this call.  tol <= 0 runs exactly max_iter passes.  Synchronises
  * once per pass; the transform of the final Psi is left queued on the plan's stream.  iters_out: host int32 [batch], total passes of each realisation (may be NULL);
  * eps_out: host double [batch * max_iter], eps of each pass of this call, NaN-padded (may be NULL).
- * Returns OK, NOTCONVERGED, or EDIVERGED.  May be called again to continue. */
+ * The plain iteration judges a learned start: a realisation whose learned start gives a non-finite
+ * eps_1, an eps_1 above an upper bound of the plain start's eps_1 (beta/(1 - beta), and a bound from
+ * the same pass's sums: the start is then provably worse than the plain one), or a diverging
+ * iteration restarts once from the plain start (D_0 = D_s) within this call's pass budget; its pass
+ * count and eps history then count from that restart (recon_start_restarts counts restarts).
+ * Returns OK, NOTCONVERGED, RESTARTED (converged after a restart) or EDIVERGED.  May be called again
+ * to continue. */
 int recon_iterate(recon_plan_t* plan, int max_iter, double tol, int32_t* iters_out, double* eps_out);
+
+/* Restarts from the plain start since the last recon_solve: host int32 [batch]. */
+int recon_start_restarts(const recon_plan_t* plan, int32_t* out);
 
 /* Move a catalogue back along the displacement (Sec. 1).  disp_out: device float32 [n][3]
  * (galaxies: -Psi - f (Psi.r) r, randoms: -Psi, Psi interpolated with the deposit's stencil);
- * pos_out: device float32 [n][3] receiving pos + disp, or NULL.  When which, pos, n and offsets are
- * those of the catalogue painted last through the brick-binned deposit (the plan has max_objects >= n
- * and the paint had no RECON_PAINT_NGP flag), the shift runs on the deposit's brick-ordered copy of
- * the positions and is put back in input order: the result is bit-identical to the direct shift, but
- * it uses the positions as they were painted, so a caller that changes pos in between must paint
- * again (or pass another buffer).  Objects the deposit rejected get a zero displacement. */
+ * pos_out: device float32 [n][3] receiving pos + disp, or NULL.  which: RECON_GAL or RECON_RAN,
+ * optionally or-ed with RECON_SHIFT_AS_PAINTED.  With that flag the caller states that pos, n and
+ * offsets are the catalogue painted last through the brick-binned deposit (the plan has
+ * max_objects >= n and the paint had no RECON_PAINT_NGP flag) and that pos is unchanged since: the
+ * shift then runs on the deposit's brick-ordered copy of the positions and puts the results back in
+ * input order, bit-identical to the direct shift; EINVAL when which, pos, n or offsets differ from
+ * that paint's.  Without the flag the positions are read from pos.  Objects the deposit rejected get
+ * a zero displacement. */
 int recon_shift(recon_plan_t* plan, int which, const float* pos, int64_t n, const int64_t* offsets,
                 float* disp_out, float* pos_out);
 

@@ -252,6 +252,9 @@ struct recon_plan_s {
   bool painted_g = false, painted_r = false;
   int state = ST_EMPTY;
   int start = RECON_START_PLAIN;
+  // start of each realisation (a learned start that is rejected restarts from the plain start) and
+  // how often that happened since the solve
+  std::vector<int> start_b, restarts;
   std::vector<int> passes, done, psi_valid, st_y, pending1, diverged, stale_x;
   std::vector<double> num0, den0, s1, s2, norm1;
   std::vector<std::vector<double>> hist;
@@ -863,6 +866,8 @@ int recon_plan(recon_plan_t** out, const recon_params_t* params, void* workspace
   pl->pending1.assign(pl->batch, 0);
   pl->diverged.assign(pl->batch, 0);
   pl->stale_x.assign(pl->batch, 0);
+  pl->start_b.assign(pl->batch, RECON_START_PLAIN);
+  pl->restarts.assign(pl->batch, 0);
   pl->num0.assign(pl->batch, 0.0);
   pl->den0.assign(pl->batch, 0.0);
   pl->s1.assign(pl->batch, 0.0);
@@ -1079,6 +1084,8 @@ int recon_solve(recon_plan_t* pl, int start, const void* net) {
     pl->diverged[b] = 0;
     pl->stale_x[b] = 0;
     pl->hist[b].clear();
+    pl->start_b[b] = start;
+    pl->restarts[b] = 0;
   }
   if (start == RECON_START_LEARNED) {
     // u_p = Psi_p . r_hat from the fanned-out start, then Delta u = network(delta_s, u_p) into corr
@@ -1101,6 +1108,21 @@ int recon_solve(recon_plan_t* pl, int start, const void* net) {
 // eps rising below this is rounding noise of a converged FP32 iteration, not divergence
 constexpr double kEpsFloor = 1e-5;
 
+// Upper bound of the plain start's eps_1 from the sums of a non-gradient start's first pass.  The
+// map from a radial field u to Psi_1 - Psi_0 (Sec. 5.1, eq. iterative) is -beta k' (k' . FFT[u r])/k^2,
+// whose norm is at most beta (|k'|^2 <= k^2, |r| <= 1).  With Psi_p the plain start, Psi_1 the
+// learned start's first iterate and Delta the learned radial correction:
+//   ||Psi_1 - Psi_1^plain|| <= beta ||Delta||,  ||Psi_1^plain - Psi_p|| <= beta ||Psi_p||,
+// so eps_1^plain <= beta / (1 - beta) (beta < 1), and
+//   eps_1^plain <= (||Psi_1 - Psi_p|| + beta ||Delta||) / (||Psi_1|| - beta ||Delta||).
+// num0 = ||Psi_1 - Psi_p||^2, den0 = ||Psi_1||^2, s2 = ||Delta||^2 (configuration-space sums).
+double plain_eps1_bound(double beta, double num0, double den0, double s2) {
+  double bound = beta < 1.0 ? beta / (1.0 - beta) : INFINITY;
+  const double bd = beta * std::sqrt(std::fmax(s2, 0.0)), dn = std::sqrt(std::fmax(den0, 0.0));
+  if (dn > bd) bound = std::fmin(bound, (std::sqrt(std::fmax(num0, 0.0)) + bd) / (dn - bd));
+  return bound;
+}
+
 int recon_iterate(recon_plan_t* pl, int max_iter, double tol, int32_t* iters_out, double* eps_out) {
   if (!pl) return RECON_EINVAL;
   if (pl->state != ST_SOLVED) return fail(pl, RECON_ESTATE, "solve must precede iterate");
@@ -1109,12 +1131,35 @@ int recon_iterate(recon_plan_t* pl, int max_iter, double tol, int32_t* iters_out
   const int B = pl->batch;
   const bool fixed = !(tol > 0.0);
   const double norm_k = 1.0 / (pl->p.bias * pl->p.bias * (double)pl->n3);   // Parseval + 1/b^2
+  const double beta = pl->p.growth / pl->p.bias;
   std::vector<std::vector<double>> call_eps(B);
   for (int b = 0; b < B; ++b) pl->done[b] = pl->diverged[b] ? 1 : 0;
+  bool restarted = false;
+
+  // A rejected learned start: the realisation starts over from the plain start, D_0 = D_s.  Its D_n
+  // becomes D_s (so that a pass reading D_n as the previous iterate starts from the plain start),
+  // its state X is rebuilt from D_s before its next pass, and its history starts again.
+  auto fall_back = [&](int b) -> int {
+    HIP_TRY(pl, hipMemcpyAsync(pl->dn + (size_t)b * pl->cn, pl->ds + (size_t)b * pl->cn, sizeof(float2) * pl->cn,
+                               hipMemcpyDeviceToDevice, pl->stream));
+    pl->start_b[b] = RECON_START_PLAIN;
+    pl->restarts[b] += 1;
+    pl->passes[b] = 0;
+    pl->pending1[b] = 0;
+    pl->diverged[b] = 0;
+    pl->done[b] = 0;
+    pl->psi_valid[b] = 0;
+    pl->st_y[b] = SY_NONE;
+    pl->stale_x[b] = 1;
+    pl->hist[b].clear();
+    call_eps[b].clear();
+    restarted = true;
+    return RECON_OK;
+  };
 
   // norm2 = ||Psi_n||^2.  Divergence: non-finite eps, eps rising twice in a row, or
-  // ||Psi_n|| > 100 ||Psi_1||.
-  auto record = [&](int b, double e, double norm2) {
+  // ||Psi_n|| > 100 ||Psi_1||.  A learned start that diverges falls back to the plain start once.
+  auto record = [&](int b, double e, double norm2) -> int {
     call_eps[b].push_back(e);
     pl->hist[b].push_back(e);
     const auto& h = pl->hist[b];
@@ -1125,21 +1170,38 @@ int recon_iterate(recon_plan_t* pl, int max_iter, double tol, int32_t* iters_out
     if (!std::isfinite(e) || !std::isfinite(nrm) ||
         (k >= 3 && h[k - 1] > h[k - 2] && h[k - 2] > h[k - 3] && h[k - 1] > kEpsFloor) ||
         (k >= 2 && nrm > 100.0 * pl->norm1[b])) {
+      if (pl->start_b[b] == RECON_START_LEARNED) return fall_back(b);
       pl->diverged[b] = 1;
       pl->done[b] = 1;
     } else if (!fixed && e <= tol) {
       pl->done[b] = 1;
     }
+    return RECON_OK;
   };
 
-  // full state Y for the realisations marked in h_fin: state X is rebuilt first where it is gone
-  // (a combined state Y, or a pass stopped after its z step) from D_n, or D_s before the first pass
-  auto full_state = [&]() -> int {
+  // eps_1 of a non-gradient start from the first pass's sums and S3 = sum Delta u_1.  A learned start
+  // whose eps_1 is non-finite, or above the bound of the plain start's eps_1, is rejected: it is
+  // provably a worse start than the plain one.  Returns whether the realisation fell back.
+  auto judge_eps1 = [&](int b, double s3, bool& fell) -> int {
+    fell = false;
+    const double diff2 = pl->num0[b] - 2.0 * (s3 - pl->s1[b]) + pl->s2[b];
+    const double e = !std::isfinite(diff2) ? NAN
+                     : (pl->den0[b] > 0 ? std::sqrt(std::fmax(diff2, 0.0) / pl->den0[b]) : 0.0);
+    if (pl->start_b[b] == RECON_START_LEARNED &&
+        !(e <= plain_eps1_bound(beta, pl->num0[b], pl->den0[b], pl->s2[b]))) {
+      fell = true;
+      return fall_back(b);
+    }
+    return record(b, e, pl->den0[b]);
+  };
+
+  // state X again (from D_s before the first pass, else from D_n) for the realisations marked in
+  // h_fan whose state X is gone
+  auto rebuild_x = [&](const std::vector<int>& want) -> int {
     for (int pick = 0; pick < 2; ++pick) {
       bool any = false;
       for (int b = 0; b < B; ++b) {
-        const bool rebuild = pl->h_fin[b] && (pl->stale_x[b] || pl->st_y[b] == SY_COMB);
-        pl->h_fan[b] = (rebuild && (pl->passes[b] == 0) == (pick == 0)) ? 1 : 0;
+        pl->h_fan[b] = (want[b] && (pl->passes[b] == 0) == (pick == 0)) ? 1 : 0;
         any = any || pl->h_fan[b];
       }
       if (!any) continue;
@@ -1148,6 +1210,15 @@ int recon_iterate(recon_plan_t* pl, int max_iter, double tol, int32_t* iters_out
       for (int b = 0; b < B; ++b)
         if (pl->h_fan[b]) { pl->stale_x[b] = 0; pl->st_y[b] = SY_NONE; }
     }
+    return RECON_OK;
+  };
+
+  // full state Y for the realisations marked in h_fin: state X is rebuilt first where it is gone
+  // (a combined state Y, or a pass stopped after its z step) from D_n, or D_s before the first pass
+  auto full_state = [&]() -> int {
+    std::vector<int> want(B, 0);
+    for (int b = 0; b < B; ++b) want[b] = pl->h_fin[b] && (pl->stale_x[b] || pl->st_y[b] == SY_COMB);
+    RECON_TRY(rebuild_x(want));
     bool any = false;
     for (int b = 0; b < B; ++b) {
       pl->h_fan[b] = (pl->h_fin[b] && pl->st_y[b] != SY_FULL) ? 1 : 0;
@@ -1163,7 +1234,7 @@ int recon_iterate(recon_plan_t* pl, int max_iter, double tol, int32_t* iters_out
   };
 
   // resolve eps_1 of a non-gradient start: needs the full state Y of D_1
-  auto resolve_pending = [&](bool write_psi) -> int {
+  auto resolve_pending = [&]() -> int {
     bool any = false;
     for (int b = 0; b < B; ++b) {
       pl->h_fin[b] = pl->pending1[b];
@@ -1179,30 +1250,38 @@ int recon_iterate(recon_plan_t* pl, int max_iter, double tol, int32_t* iters_out
       if (!pl->pending1[b]) continue;
       pl->psi_valid[b] = 1;
       pl->pending1[b] = 0;
-      const double s3 = pl->h_red2[2 * b];
-      const double diff2 = pl->num0[b] - 2.0 * (s3 - pl->s1[b]) + pl->s2[b];
-      const double e = !std::isfinite(diff2) ? NAN
-                       : (pl->den0[b] > 0 ? std::sqrt(std::fmax(diff2, 0.0) / pl->den0[b]) : 0.0);
-      record(b, e, pl->den0[b]);
+      bool fell = false;
+      RECON_TRY(judge_eps1(b, pl->h_red2[2 * b], fell));
     }
-    (void)write_psi;
     return RECON_OK;
   };
 
   for (int it = 0; it < max_iter; ++it) {
     bool any = false;
-    for (int b = 0; b < B; ++b) any = any || !pl->done[b];
-    if (!any) break;
-    any = false;
     for (int b = 0; b < B; ++b) {
       pl->h_it[b] = pl->done[b] ? 0 : 1;
       any = any || pl->h_it[b];
     }
     if (!any) break;
-    int first_pass = -1;
-    for (int b = 0; b < B; ++b)
-      if (pl->h_it[b]) { first_pass = pl->passes[b]; break; }
-    const bool start_pass = first_pass == 0 && pl->start != RECON_START_PLAIN;
+    // realisations that restarted from the plain start need their state X from D_s first
+    {
+      std::vector<int> want(B, 0);
+      bool stale = false;
+      for (int b = 0; b < B; ++b) {
+        want[b] = pl->h_it[b] && pl->stale_x[b];
+        stale = stale || want[b];
+      }
+      if (stale) RECON_TRY(rebuild_x(want));
+    }
+    // first: every active realisation is before its first pass (the previous iterate is D_s; a
+    // realisation that restarted also holds D_s in D_n).  start_pass: some realisation's first pass
+    // from a non-gradient start (all of a plan's realisations reach it together)
+    bool first = true, start_pass = false;
+    for (int b = 0; b < B; ++b) {
+      if (!pl->h_it[b]) continue;
+      first = first && pl->passes[b] == 0;
+      start_pass = start_pass || (pl->passes[b] == 0 && pl->start_b[b] != RECON_START_PLAIN);
+    }
     // eps_1 of a non-gradient start needs S3 = sum Delta u_1; this pass's z step computes u_1
     bool cross = false;
     for (int b = 0; b < B; ++b) cross = cross || (pl->h_it[b] && pl->pending1[b]);
@@ -1223,8 +1302,9 @@ int recon_iterate(recon_plan_t* pl, int max_iter, double tol, int32_t* iters_out
     }
     RECON_TRY(upload_mask(pl, pl->act_fan, pl->h_fan));
     RECON_TRY(upload_mask(pl, pl->act_it, pl->h_it));
-    const bool steady = mode == ZI_PLAIN && first_pass != 0;
-    if (steady && (pl->p.flags & RECON_PASS_GRAPHS) && !pl->prof.on) {
+    const bool steady = mode == ZI_PLAIN && !first;
+    const bool graph = steady && (pl->p.flags & RECON_PASS_GRAPHS) && !pl->prof.on;
+    if (graph) {
       RECON_TRY(pass_graph_launch(pl, ops));
     } else {
       if (any_fan) RECON_TRY(ops->fanout(pl, pl->act_fan, true));
@@ -1237,25 +1317,24 @@ int recon_iterate(recon_plan_t* pl, int max_iter, double tol, int32_t* iters_out
       for (int b = 0; b < B; ++b) {
         if (!pl->h_it[b] || !pl->pending1[b]) continue;
         pl->pending1[b] = 0;
-        const double s3 = pl->h_red2[2 * b];
-        const double diff2 = pl->num0[b] - 2.0 * (s3 - pl->s1[b]) + pl->s2[b];
-        const double e = !std::isfinite(diff2) ? NAN
-                         : (pl->den0[b] > 0 ? std::sqrt(std::fmax(diff2, 0.0) / pl->den0[b]) : 0.0);
-        record(b, e, pl->den0[b]);
-        // a realisation that stops here keeps D_1: its z step is dropped and Psi_1 recomputed at the end
-        if (pl->done[b]) {
+        bool fell = false;
+        RECON_TRY(judge_eps1(b, pl->h_red2[2 * b], fell));
+        // a realisation that stops here keeps D_1: its z step is dropped and Psi_1 recomputed at the
+        // end; one that restarts from the plain start drops the rest of the pass too
+        if (pl->done[b] || fell) {
           pl->h_it[b] = 0;
-          pl->st_y[b] = SY_NONE;
-          pl->psi_valid[b] = 0;
-          pl->stale_x[b] = 1;
+          if (!fell) {
+            pl->st_y[b] = SY_NONE;
+            pl->psi_valid[b] = 0;
+            pl->stale_x[b] = 1;
+          }
         }
       }
       for (int b = 0; b < B; ++b) rest = rest || pl->h_it[b];
       if (!rest) continue;
       RECON_TRY(upload_mask(pl, pl->act_it, pl->h_it));
     }
-    if (!(steady && (pl->p.flags & RECON_PASS_GRAPHS) && !pl->prof.on))
-      RECON_TRY(ops->fanin_xiter(pl, first_pass == 0, pl->act_it));
+    if (!graph) RECON_TRY(ops->fanin_xiter(pl, first, pl->act_it));
     // the start pass also reads S1, S2 (red[2B..4B)): one copy of both halves
     HIP_TRY(pl, hipMemcpyAsync(pl->h_red.data(), pl->red, (start_pass ? 32 : 16) * B, hipMemcpyDeviceToHost,
                                pl->stream));
@@ -1264,20 +1343,21 @@ int recon_iterate(recon_plan_t* pl, int max_iter, double tol, int32_t* iters_out
       if (!pl->h_it[b]) continue;
       pl->st_y[b] = SY_NONE;
       pl->psi_valid[b] = 0;
+      const bool was_start = pl->passes[b] == 0 && pl->start_b[b] != RECON_START_PLAIN;
       pl->passes[b] += 1;
       const double num = pl->h_red[2 * b], den = pl->h_red[2 * b + 1];
-      if (start_pass) {
+      if (was_start) {
         pl->num0[b] = num * norm_k;
         pl->den0[b] = den * norm_k;
         pl->s1[b] = pl->h_red[2 * B + 2 * b];
         pl->s2[b] = pl->h_red[2 * B + 2 * b + 1];
         pl->pending1[b] = 1;
       } else {
-        record(b, den > 0 ? std::sqrt(num / den) : 0.0, den * norm_k);
+        RECON_TRY(record(b, den > 0 ? std::sqrt(num / den) : 0.0, den * norm_k));
       }
     }
   }
-  RECON_TRY(resolve_pending(true));
+  RECON_TRY(resolve_pending());
   // displacement of every realisation whose Psi buffer is stale (realisations stopped inside a pass
   // get state X again from D_n first)
   bool need = false;
@@ -1306,23 +1386,37 @@ int recon_iterate(recon_plan_t* pl, int max_iter, double tol, int32_t* iters_out
     }
   }
   if (div) return fail(pl, RECON_EDIVERGED, "convergence norm rose twice in a row or became non-finite");
-  return notconv ? RECON_NOTCONVERGED : RECON_OK;
+  if (notconv) return RECON_NOTCONVERGED;
+  if (restarted) return fail(pl, RECON_RESTARTED, "a learned start was rejected; restarted from the plain start");
+  return RECON_OK;
 }
 
-int recon_shift(recon_plan_t* pl, int which, const float* pos, int64_t n, const int64_t* offsets, float* disp_out,
-                float* pos_out) {
+int recon_start_restarts(const recon_plan_t* pl, int32_t* out) {
+  if (!pl || !out) return RECON_EINVAL;
+  for (int b = 0; b < pl->batch; ++b) out[b] = pl->restarts[b];
+  return RECON_OK;
+}
+
+int recon_shift(recon_plan_t* pl, int which_flags, const float* pos, int64_t n, const int64_t* offsets,
+                float* disp_out, float* pos_out) {
   if (!pl) return RECON_EINVAL;
+  const int which = which_flags & ~RECON_SHIFT_AS_PAINTED;
+  const bool as_painted = (which_flags & RECON_SHIFT_AS_PAINTED) != 0;
   if (which != RECON_GAL && which != RECON_RAN) return fail(pl, RECON_EINVAL, "which must be RECON_GAL or RECON_RAN");
   if (pl->state != ST_SOLVED) return fail(pl, RECON_ESTATE, "iterate must precede shift");
   for (int b = 0; b < pl->batch; ++b)
     if (!pl->psi_valid[b]) return fail(pl, RECON_ESTATE, "displacement not computed; call iterate");
   if (n < 0 || (n > 0 && (!pos || !disp_out))) return fail(pl, RECON_EINVAL, "bad catalogue pointers");
   if (pl->batch > 1 && !offsets && n > 0) return fail(pl, RECON_EINVAL, "offsets are required when batch > 1");
+  // the brick-ordered copy is used only when the caller says the catalogue is the one painted last
+  // (unchanged since); the call must then name that paint's catalogue
+  if (as_painted && !(which == pl->srt_which && pos == pl->srt_pos && n == pl->srt_n && offsets == pl->srt_off))
+    return fail(pl, RECON_EINVAL, "RECON_SHIFT_AS_PAINTED: not the catalogue painted last through the bricks");
   if (n == 0) return RECON_OK;
   HIP_TRY(pl, hipMemsetAsync(pl->err + 2, 0, sizeof(int), pl->stream));
   long long blocks = (n + kThreads - 1) / kThreads;
   if (blocks > 8192) blocks = 8192;
-  if (which == pl->srt_which && pos == pl->srt_pos && n == pl->srt_n && offsets == pl->srt_off) {
+  if (as_painted) {
     // the catalogue painted last through the bricks: shift its brick-ordered copy, then reorder
     {
       PROF(pl, KP_SHIFT);

@@ -16,19 +16,21 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_NAME = "librecon.so"
 
-RECON_OK, RECON_NOTCONVERGED = 0, 1
+RECON_OK, RECON_NOTCONVERGED, RECON_RESTARTED = 0, 1, 2
 RECON_EINVAL, RECON_ENOMEM, RECON_EDEVICE, RECON_ESTATE, RECON_EDIVERGED = -1, -2, -3, -4, -5
 GAL, RAN = 0, 1
 START_PLAIN, START_FFTA1, START_FFTA2, START_LEARNED = 0, 1, 2, 3
 NO_RANDOMS, KEEP_DELTA, START_BUFFERS, CNN_BUFFERS, CNN_HALF, PASS_GRAPHS, LOGNORMAL = 1, 2, 4, 8, 16, 32, 64
 CNN_PARAMS = 10833
 PAINT_ACCUMULATE, PAINT_NGP = 1, 2
+SHIFT_AS_PAINTED = 256
 
 EXPORTED = ("recon_workspace_bytes", "recon_plan", "recon_paint", "recon_solve", "recon_iterate",
             "recon_shift", "recon_get_psi", "recon_get_grid", "recon_get_delta", "recon_set_delta",
             "recon_destroy", "recon_strerror", "recon_last_error", "recon_profile_start",
             "recon_profile_stop", "recon_profile_kernel_name", "recon_cnn_forward", "recon_cnn_train_step",
-            "recon_get_radial", "recon_restrict", "recon_prolong", "recon_radial_ratio", "recon_helmholtz")
+            "recon_get_radial", "recon_restrict", "recon_prolong", "recon_radial_ratio", "recon_helmholtz",
+            "recon_start_restarts")
 
 
 class ReconError(RuntimeError):
@@ -67,6 +69,7 @@ def load(path=None):
     lib.recon_paint.argtypes = [vp, ctypes.c_int, vp, vp, i64, vp, u32]
     lib.recon_solve.argtypes = [vp, ctypes.c_int, vp]
     lib.recon_iterate.argtypes = [vp, ctypes.c_int, dbl, ctypes.POINTER(i32), ctypes.POINTER(dbl)]
+    lib.recon_start_restarts.argtypes = [vp, ctypes.POINTER(i32)]
     lib.recon_shift.argtypes = [vp, ctypes.c_int, vp, i64, vp, vp, vp]
     lib.recon_get_psi.argtypes = [vp, vp]
     lib.recon_get_grid.argtypes = [vp, ctypes.c_int, vp]
@@ -90,7 +93,7 @@ def load(path=None):
     lib.recon_profile_stop.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(dbl), ctypes.c_int]
     lib.recon_profile_kernel_name.argtypes = [ctypes.c_int]
     lib.recon_profile_kernel_name.restype = ctypes.c_char_p
-    for name in ("recon_cnn_forward", "recon_cnn_train_step", "recon_get_radial", "recon_restrict", "recon_prolong",
+    for name in ("recon_start_restarts", "recon_cnn_forward", "recon_cnn_train_step", "recon_get_radial", "recon_restrict", "recon_prolong",
                  "recon_radial_ratio", "recon_helmholtz",
                  "recon_profile_start", "recon_profile_stop", "recon_plan", "recon_paint", "recon_solve", "recon_iterate", "recon_shift",
                  "recon_get_psi", "recon_get_grid", "recon_get_delta", "recon_set_delta"):
@@ -105,6 +108,8 @@ def _ptr(t):
 
 
 def _check_dev(t, dtype, shape_tail, name, device):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
     if t.dtype != dtype:
         raise TypeError(f"{name} must be {dtype}")
     if not t.is_contiguous():
@@ -136,6 +141,10 @@ class Plan:
         p.max_objects = int(max_objects)
         self.params = p
         self.n, self.batch, self.randoms = int(n), int(batch), randoms
+        # the catalogue painted last through the brick-binned deposit: (which, pos, pos version, offsets,
+        # offsets version).  The plan keeps the tensors alive, so their memory cannot be handed to
+        # another tensor while the record stands, and the version counters catch in-place changes.
+        self._painted = None
         self.cnn_n = self.n // 2 if cnn_half else self.n     # network grid
         nbytes = self.lib.recon_workspace_bytes(ctypes.byref(p))
         if nbytes == 0:
@@ -150,6 +159,7 @@ class Plan:
         self.handle = h
 
     def close(self):
+        self._painted = None
         if getattr(self, "handle", None):
             torch.cuda.synchronize(self.device)
             self.lib.recon_destroy(self.handle)
@@ -167,18 +177,43 @@ class Plan:
         msg = self.lib.recon_last_error(self.handle).decode()
         raise ReconError(rc, msg or self.lib.recon_strerror(rc).decode())
 
+    def _check_offsets(self, offsets, n):
+        if offsets is None:
+            if self.batch > 1 and n > 0:
+                raise ValueError("offsets are required when batch > 1")
+            return
+        _check_dev(offsets, torch.int64, None, "offsets", self.device)
+        if offsets.numel() != self.batch + 1:
+            raise ValueError("offsets must have batch + 1 entries")
+
     def paint(self, which, pos, w=None, offsets=None, accumulate=False, ngp=False):
+        if which not in (GAL, RAN):
+            raise ValueError("which must be GAL or RAN")
         _check_dev(pos, torch.float32, (3,), "pos", self.device)
         if w is not None:
             _check_dev(w, torch.float32, None, "w", self.device)
             if w.numel() != pos.shape[0]:
                 raise ValueError("w must have one entry per object")
-        if offsets is not None:
-            _check_dev(offsets, torch.int64, None, "offsets", self.device)
-            if offsets.numel() != self.batch + 1:
-                raise ValueError("offsets must have batch + 1 entries")
-        return self._rc(self.lib.recon_paint(self.handle, which, _ptr(pos), _ptr(w), pos.shape[0], _ptr(offsets),
-                                             (PAINT_ACCUMULATE if accumulate else 0) | (PAINT_NGP if ngp else 0)))
+        self._check_offsets(offsets, pos.shape[0])
+        n = pos.shape[0]
+        binned = n > 0 and not ngp and n <= self.params.max_objects
+        if binned:
+            self._painted = None       # the library drops its brick-ordered copy first
+        rc = self._rc(self.lib.recon_paint(self.handle, which, _ptr(pos), _ptr(w), n, _ptr(offsets),
+                                           (PAINT_ACCUMULATE if accumulate else 0) | (PAINT_NGP if ngp else 0)))
+        if binned:
+            self._painted = (which, pos, pos._version, offsets, None if offsets is None else offsets._version)
+        return rc
+
+    def _as_painted(self, which, pos, offsets):
+        # the brick-ordered copy may stand in for pos only when pos is the very tensor painted last,
+        # unchanged since (same object, same version), with the same offsets tensor
+        rec = self._painted
+        if rec is None:
+            return False
+        w0, p0, v0, o0, ov0 = rec
+        return (which == w0 and pos is p0 and pos._version == v0 and offsets is o0
+                and (offsets is None or offsets._version == ov0))
 
     def radial_ratio(self, psi_ref, lo=-1.0, hi=3.0):
         """Table 1 statistic per realisation: (mean, std, outlier fraction, kept count) of
@@ -209,28 +244,46 @@ class Plan:
         return self._rc(self.lib.recon_set_delta(self.handle, _ptr(delta)))
 
     def solve(self, start=START_PLAIN, net=None):
+        if net is not None:
+            _check_dev(net, torch.float32, None, "net", self.device)
+            if net.numel() != CNN_PARAMS:
+                raise ValueError(f"net must hold {CNN_PARAMS} parameters")
         return self._rc(self.lib.recon_solve(self.handle, int(start), _ptr(net)))
 
     def iterate(self, max_iter, tol):
-        """Returns (code, passes per realisation, eps history [batch][<=max_iter])."""
+        """Returns (code, passes per realisation, eps history [batch][<=max_iter]).  The code is
+        RECON_OK, RECON_NOTCONVERGED, or RECON_RESTARTED when a rejected learned start restarted from
+        the plain start (see restarts())."""
         iters = (ctypes.c_int32 * self.batch)()
         eps = (ctypes.c_double * (self.batch * max(max_iter, 1)))()
         rc = self._rc(self.lib.recon_iterate(self.handle, int(max_iter), float(tol), iters, eps),
-                      allow=(RECON_OK, RECON_NOTCONVERGED))
+                      allow=(RECON_OK, RECON_NOTCONVERGED, RECON_RESTARTED))
         hist = []
         for b in range(self.batch):
             row = [eps[b * max_iter + i] for i in range(max_iter)]
             hist.append([e for e in row if not math.isnan(e)])
         return rc, list(iters), hist
 
+    def restarts(self):
+        """Restarts from the plain start of each realisation since the last solve."""
+        out = (ctypes.c_int32 * self.batch)()
+        self._rc(self.lib.recon_start_restarts(self.handle, out))
+        return list(out)
+
     def shift(self, which, pos, offsets=None, want_pos=False, out_disp=None, out_pos=None):
+        if which not in (GAL, RAN):
+            raise ValueError("which must be GAL or RAN")
         _check_dev(pos, torch.float32, (3,), "pos", self.device)
+        self._check_offsets(offsets, pos.shape[0])
         disp = torch.empty_like(pos) if out_disp is None else out_disp
         out = (torch.empty_like(pos) if out_pos is None else out_pos) if want_pos else None
         _check_dev(disp, torch.float32, (3,), "out_disp", self.device)
+        if out is not None:
+            _check_dev(out, torch.float32, (3,), "out_pos", self.device)
         if disp.shape != pos.shape or (out is not None and out.shape != pos.shape):
             raise ValueError("output buffers must match pos")
-        self._rc(self.lib.recon_shift(self.handle, which, _ptr(pos), pos.shape[0], _ptr(offsets), _ptr(disp),
+        sel = which | (SHIFT_AS_PAINTED if self._as_painted(which, pos, offsets) else 0)
+        self._rc(self.lib.recon_shift(self.handle, sel, _ptr(pos), pos.shape[0], _ptr(offsets), _ptr(disp),
                                       _ptr(out)))
         return (disp, out) if want_pos else disp
 
@@ -294,6 +347,14 @@ class Plan:
         m3 = self.batch * self.cnn_n ** 3
         if params.numel() != CNN_PARAMS or any(t.numel() != m3 for t in (delta, u_p, target_du)):
             raise ValueError("bad network input sizes")
+        vecs = ((m, "m"), (v, "v"), (grad_out, "grad_out")) if lr > 0 else ((grad_out, "grad_out"),)
+        if lr > 0 and (m is None or v is None):
+            raise ValueError("an Adam update needs the moment vectors m and v")
+        for t, nm in vecs:
+            if t is not None:
+                _check_dev(t, torch.float32, None, nm, self.device)
+                if t.numel() != CNN_PARAMS:
+                    raise ValueError(f"{nm} must hold {CNN_PARAMS} values")
         loss = ctypes.c_double(0.0)
         self._rc(self.lib.recon_cnn_train_step(self.handle, _ptr(params), _ptr(m), _ptr(v), int(step), float(lr),
                                                _ptr(delta), _ptr(u_p), _ptr(target_du), ctypes.byref(loss),

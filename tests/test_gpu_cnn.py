@@ -237,3 +237,83 @@ def test_learned_start_half_grid_end_to_end(gpu_lib, n):
     print(f"n={n} half-grid learned start: psi rel L2 {e:.2e}, eps {eps[0]} vs {ref['eps']}", flush=True)
     assert e < 1e-4
     np.testing.assert_allclose(eps[0], ref["eps"], rtol=1e-3, atol=1e-5)
+
+
+def _plain_reference(native, cat, tol):
+    plan = native.plan_for(cat)
+    gal, ran = to_dev(cat.gal_pos), to_dev(cat.ran_pos)
+    plan.paint(native.GAL, gal)
+    plan.paint(native.RAN, ran)
+    plan.solve(native.START_PLAIN)
+    rc, iters, eps = plan.iterate(40, tol)
+    psi = plan.psi()[0].cpu().numpy()
+    plan.close()
+    return rc, iters[0], eps[0], psi
+
+
+@pytest.mark.parametrize("kind", ["nan", "garbage"])
+def test_rejected_learned_start_restarts_from_plain(gpu_lib, kind):
+    # the plain iteration judges the learned start (Sec. 5.1 iteration from any start): a network
+    # with a NaN parameter gives a non-finite eps_1, one with huge finite weights an eps_1 above the
+    # plain start's bound beta/(1 - beta); both must restart from D_s and end on the plain result
+    from paper_1504_02591_amd import native
+    cat = G.lattice_box(32, 500.0, (-500.0, 250.0, 250.0), 0.74, 31, 32, ran_factor=3, bias=2.0, smooth_r=20.0)
+    th = params(12)
+    if kind == "nan":
+        th[100] = np.nan
+    else:
+        th *= 40.0
+    tol = 1e-4
+    plan = native.plan_for(cat, keep_delta=True, start_buffers=True, cnn=True)
+    gal, ran = to_dev(cat.gal_pos), to_dev(cat.ran_pos)
+    plan.paint(native.GAL, gal)
+    plan.paint(native.RAN, ran)
+    plan.solve(native.START_LEARNED, to_dev(th))
+    rc, iters, eps = plan.iterate(40, tol)
+    psi = plan.psi()[0].cpu().numpy()
+    restarts = plan.restarts()
+    disp = plan.shift(native.GAL, gal).cpu().numpy()
+    plan.close()
+    rc_p, iters_p, eps_p, psi_p = _plain_reference(native, cat, tol)
+    print(f"{kind} network: rc {rc}, restarts {restarts}, passes {iters[0]} (plain {iters_p}), "
+          f"eps {eps[0]} (plain {eps_p})", flush=True)
+    assert rc == native.RECON_RESTARTED and restarts == [1]
+    assert iters[0] == iters_p
+    np.testing.assert_allclose(eps[0], eps_p, rtol=1e-4, atol=1e-7)
+    assert rel_l2(psi, psi_p) < 1e-6
+    ref = O.reconstruct(cat.gal_pos, None, cat.ran_pos, None, cat.n, cat.box_len, cat.origin, cat.observer,
+                        cat.bias, cat.growth, cat.smooth_r, cat.mask_tau, n_passes=iters_p)
+    assert rel_l2(psi, ref["psi"]) < 1e-5
+    assert np.abs(disp - ref["disp_g"]).max() < 1e-4
+
+
+def test_rejected_learned_start_in_fixed_pass_call(gpu_lib):
+    # a call that ends right after the start pass decides eps_1 from the output's transform; a
+    # rejected start then returns the plain start's displacement and continues from there next call
+    from paper_1504_02591_amd import native
+    cat = G.lattice_box(32, 500.0, (-500.0, 250.0, 250.0), 0.74, 33, 34, ran_factor=3, bias=2.0, smooth_r=20.0)
+    th = params(13)
+    th[7] = np.nan
+    plan = native.plan_for(cat, keep_delta=True, start_buffers=True, cnn=True)
+    gal, ran = to_dev(cat.gal_pos), to_dev(cat.ran_pos)
+    plan.paint(native.GAL, gal)
+    plan.paint(native.RAN, ran)
+    plan.solve(native.START_LEARNED, to_dev(th))
+    rc, iters, eps = plan.iterate(1, 0.0)
+    assert rc == native.RECON_RESTARTED and iters[0] == 0 and eps[0] == []
+    p0 = plan.psi()[0].cpu().numpy()
+    rc, iters, eps = plan.iterate(3, 0.0)
+    p3 = plan.psi()[0].cpu().numpy()
+    plan.close()
+    assert rc == native.RECON_OK and iters[0] == 3
+    plain = native.plan_for(cat)
+    plain.paint(native.GAL, gal)
+    plain.paint(native.RAN, ran)
+    plain.solve()
+    plain.iterate(0, 0.0)
+    q0 = plain.psi()[0].cpu().numpy()
+    rc_q, it_q, eps_q = plain.iterate(3, 0.0)
+    q3 = plain.psi()[0].cpu().numpy()
+    plain.close()
+    assert rel_l2(p0, q0) < 1e-6 and rel_l2(p3, q3) < 1e-6
+    np.testing.assert_allclose(eps[0], eps_q[0], rtol=1e-4, atol=1e-7)
