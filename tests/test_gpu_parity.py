@@ -547,6 +547,41 @@ def test_shift_in_brick_order_equals_direct_shift(gpu_lib, last, n):
     assert float(np.abs(d_sorted.cpu().numpy() - ref).max()) <= DISP_TOL
 
 
+def test_brick_order_shift_needs_the_unchanged_painted_catalogue(gpu_lib):
+    # the deposit's brick-ordered copy stands in for the positions only when the caller passes the very
+    # tensor painted last, unchanged: another catalogue of the same length (whatever its address) and
+    # the painted tensor changed in place both take the direct path; at the C ABI a false claim of
+    # RECON_SHIFT_AS_PAINTED is refused
+    import ctypes
+    from paper_1504_02591_amd import native
+    cat = G.lattice_box(32, 500.0, (-500.0, 250.0, 250.0), 0.7, 41, 42, ran_factor=3, bias=1.2, smooth_r=20.0)
+    plan = native.plan_for(cat)
+    gal, ran = to_dev(cat.gal_pos), to_dev(cat.ran_pos)
+    plan.paint(native.GAL, gal)
+    plan.paint(native.RAN, ran)
+    plan.solve()
+    plan.iterate(2, 0.0)
+    del ran                                            # the plan still holds the painted tensor
+    other = to_dev((cat.ran_pos[::-1] * np.float32(0.97)).copy())
+    d_other = plan.shift(native.RAN, other)
+    d_other_direct = plan.shift(native.RAN, other.clone())
+    assert torch.equal(d_other, d_other_direct)
+    painted = plan._painted[1]
+    painted.mul_(0.99)                                 # changed in place after the paint
+    d_changed = plan.shift(native.RAN, painted)
+    d_changed_direct = plan.shift(native.RAN, painted.clone())
+    assert torch.equal(d_changed, d_changed_direct)
+    disp = torch.empty_like(other)
+    rc = plan.lib.recon_shift(plan.handle, native.RAN | native.SHIFT_AS_PAINTED, ctypes.c_void_p(other.data_ptr()),
+                              other.shape[0], None, ctypes.c_void_p(disp.data_ptr()), None)
+    assert rc == native.RECON_EINVAL
+    plan.close()
+    r = O.reconstruct(cat.gal_pos, None, cat.ran_pos, None, cat.n, cat.box_len, cat.origin, cat.observer,
+                      cat.bias, cat.growth, cat.smooth_r, cat.mask_tau, n_passes=2)
+    ref = O.shift(r["psi"], other.cpu().numpy(), cat.box_len, cat.origin, cat.observer, cat.growth, False)
+    assert np.abs(d_other.cpu().numpy() - ref).max() <= DISP_TOL
+
+
 def test_shift_in_brick_order_batched(gpu_lib):
     from paper_1504_02591_amd import native
     cats = [G.lattice_box(32, 500.0, (-500.0, 250.0, 250.0), 0.7, 50 + i, 60 + i, ran_factor=2, bias=1.0,
