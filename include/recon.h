@@ -120,6 +120,22 @@ size_t recon_workspace_bytes(const recon_params_t* params);
 int recon_plan(recon_plan_t** out, const recon_params_t* params, void* workspace, size_t workspace_bytes,
                void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): a plan whose workspace is the library's own device scratch, a
+ * fixed array of recon_noalloc_limit() bytes (64 MiB) per GPU that each GPU the library runs on holds
+ * until the process ends.  The call allocates no device or pinned memory (it calls no hipMalloc,
+ * hipHostMalloc or hipFree; the plan's host-side record and its read-back buffers are ordinary host
+ * memory).  It takes the scratch of the device current on the calling thread; stream must belong to
+ * that device.  Every no-allocation plan on one GPU shares that GPU's scratch: creating one makes any
+ * earlier one on the same device stale (its calls then return RECON_ESTATE), and calls of two such
+ * plans that overlap in time race on the same memory.  The scratch keeps the last plan's contents;
+ * the plan clears what it needs as a plan on a caller workspace does.  RECON_ENOMEM when the
+ * parameters need more than recon_noalloc_limit() bytes (recon_workspace_bytes tells), RECON_EINVAL for
+ * invalid parameters or RECON_PASS_GRAPHS (graph instantiation may allocate), RECON_EDEVICE when the
+ * scratch address cannot be taken.  Otherwise the plan behaves as one from recon_plan. */
+int recon_plan_noalloc(recon_plan_t** out, const recon_params_t* params, void* stream);
+size_t recon_noalloc_limit(void);
+
 /* Deposit a catalogue (Sec. 3.1 / 3.2 binning; cloud-in-cell in integer fixed point, units 2^-32 of
  * weight, periodic wrap).  pos: device float32 [n][3]; w: device float32 [n] or NULL; offsets: device
  * int64 [batch+1] giving each realisation's object range (NULL when batch == 1).  Objects with a

@@ -11,6 +11,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -175,25 +176,34 @@ struct Profiler {
 
 }  // namespace
 
-// Small host buffer in pinned memory (hipHostMalloc), for the per-pass read-backs of the convergence
-// sums: the copy is a direct DMA instead of a staged copy into pageable memory.
+// Small host buffer for the per-pass read-backs of the convergence sums: pinned memory
+// (hipHostMalloc), so that the copy is a direct DMA instead of a staged copy into pageable memory, or
+// ordinary host memory for a plan that may not call HIP allocation routines.
 struct PinnedDoubles {
   double* p = nullptr;
   size_t n = 0;
+  bool pinned = true;
   PinnedDoubles() = default;
   PinnedDoubles(const PinnedDoubles&) = delete;
   PinnedDoubles& operator=(const PinnedDoubles&) = delete;
-  ~PinnedDoubles() {
-    if (p) (void)hipHostFree(p);
-  }
-  bool assign(size_t count, double v) {
-    if (p) (void)hipHostFree(p);
+  ~PinnedDoubles() { release(); }
+  void release() {
+    if (p) {
+      if (pinned) (void)hipHostFree(p);
+      else delete[] p;
+    }
     p = nullptr;
     n = 0;
-    if (hipHostMalloc((void**)&p, count * sizeof(double), hipHostMallocDefault) != hipSuccess) {
-      p = nullptr;
-      return false;
+  }
+  bool assign(size_t count, double v, bool pin) {
+    release();
+    pinned = pin;
+    if (pin) {
+      if (hipHostMalloc((void**)&p, count * sizeof(double), hipHostMallocDefault) != hipSuccess) p = nullptr;
+    } else {
+      p = new (std::nothrow) double[count];
     }
+    if (!p) return false;
     n = count;
     for (size_t i = 0; i < count; ++i) p[i] = v;
     return true;
@@ -202,8 +212,29 @@ struct PinnedDoubles {
   double& operator[](size_t i) { return p[i]; }
 };
 
+// The library's own device scratch for plans that cannot allocate (recon_plan_noalloc): one array per
+// GPU, held until the process ends.  Host code never uses the symbol itself as an address (there it
+// is only a host-side stand-in); the device address of each GPU's copy comes from
+// hipGetSymbolAddress, taken once per device with that device current.
+constexpr size_t kScratchBytes = 64ull << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+struct ScratchSlot {
+  void* ptr = nullptr;             // device address of this GPU's scratch
+  unsigned long long owner = 0;    // generation of the no-allocation plan that holds it (0: none)
+  unsigned long long next = 0;
+};
+std::mutex g_scratch_mu;
+ScratchSlot g_scratch[kMaxDevices];
+}  // namespace
+
 struct recon_plan_s {
   recon_params_t p{};
+  // a plan on the library's scratch (recon_plan_noalloc): its device and generation; -1 otherwise
+  int scratch_dev = -1;
+  unsigned long long scratch_gen = 0;
   hipStream_t stream = nullptr;
   char* ws = nullptr;
   Layout L;
@@ -757,15 +788,13 @@ const char* recon_strerror(int code) {
 
 const char* recon_last_error(const recon_plan_t* plan) { return plan ? plan->msg.c_str() : "plan is NULL"; }
 
-int recon_plan(recon_plan_t** out, const recon_params_t* params, void* workspace, size_t workspace_bytes,
-               void* stream) {
-  if (!out) return RECON_EINVAL;
-  *out = nullptr;
-  std::string why;
-  if (!valid_params(params, &why)) return RECON_EINVAL;
-  if (!workspace || ((uintptr_t)workspace % kAlign)) return RECON_EINVAL;
-  Layout L = make_layout(params);
-  if (workspace_bytes < L.total) return RECON_ENOMEM;
+}  // extern "C"
+
+namespace {
+
+// A plan over `workspace` (validated by the callers); pinned: read-back buffers in pinned memory.
+int plan_create(recon_plan_t** out, const recon_params_t* params, const Layout& L, void* workspace, void* stream,
+                bool pinned) {
   recon_plan_t* pl = new (std::nothrow) recon_plan_t();
   if (!pl) return RECON_ENOMEM;
   pl->p = *params;
@@ -877,7 +906,7 @@ int recon_plan(recon_plan_t** out, const recon_params_t* params, void* workspace
   pl->h_fan.assign(pl->batch, 0);
   pl->h_fin.assign(pl->batch, 0);
   pl->h_it.assign(pl->batch, 0);
-  if (!pl->h_red.assign(4 * pl->batch, 0.0) || !pl->h_red2.assign(2 * pl->batch, 0.0)) {
+  if (!pl->h_red.assign(4 * pl->batch, 0.0, pinned) || !pl->h_red2.assign(2 * pl->batch, 0.0, pinned)) {
     delete pl;
     return RECON_EDEVICE;
   }
@@ -904,11 +933,83 @@ int recon_plan(recon_plan_t** out, const recon_params_t* params, void* workspace
   return RECON_OK;
 }
 
-void recon_destroy(recon_plan_t* plan) { delete plan; }
+// A plan on the library's scratch is usable while no later recon_plan_noalloc took that scratch.
+int check_scratch_owner(recon_plan_t* pl) {
+  if (pl->scratch_dev < 0) return RECON_OK;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch[pl->scratch_dev].owner != pl->scratch_gen)
+    return fail(pl, RECON_ESTATE, "a later recon_plan_noalloc on this device took the scratch this plan used");
+  return RECON_OK;
+}
+
+}  // namespace
+
+#define CHECK_PLAN(pl)                    \
+  do {                                    \
+    if (!(pl)) return RECON_EINVAL;       \
+    RECON_TRY(check_scratch_owner(pl));   \
+  } while (0)
+
+extern "C" {
+
+int recon_plan(recon_plan_t** out, const recon_params_t* params, void* workspace, size_t workspace_bytes,
+               void* stream) {
+  if (!out) return RECON_EINVAL;
+  *out = nullptr;
+  std::string why;
+  if (!valid_params(params, &why)) return RECON_EINVAL;
+  if (!workspace || ((uintptr_t)workspace % kAlign)) return RECON_EINVAL;
+  Layout L = make_layout(params);
+  if (workspace_bytes < L.total) return RECON_ENOMEM;
+  return plan_create(out, params, L, workspace, stream, true);
+}
+
+size_t recon_noalloc_limit(void) { return kScratchBytes; }
+
+int recon_plan_noalloc(recon_plan_t** out, const recon_params_t* params, void* stream) {
+  if (!out) return RECON_EINVAL;
+  *out = nullptr;
+  std::string why;
+  if (!valid_params(params, &why)) return RECON_EINVAL;
+  if (params->flags & RECON_PASS_GRAPHS) return RECON_EINVAL;   // graph instantiation may allocate
+  const Layout L = make_layout(params);
+  if (L.total > kScratchBytes) return RECON_ENOMEM;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return RECON_EDEVICE;
+  void* ws = nullptr;
+  unsigned long long gen = 0;
+  {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    ScratchSlot& slot = g_scratch[dev];
+    if (!slot.ptr) {
+      // once per device, with that device current: the device address of its copy of the array
+      void* p = nullptr;
+      if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return RECON_EDEVICE;
+      slot.ptr = p;
+    }
+    ws = slot.ptr;
+    gen = ++slot.next;
+    slot.owner = gen;     // earlier no-allocation plans on this device are now stale
+  }
+  const int rc = plan_create(out, params, L, ws, stream, false);
+  if (rc != RECON_OK) return rc;
+  (*out)->scratch_dev = dev;
+  (*out)->scratch_gen = gen;
+  return RECON_OK;
+}
+
+void recon_destroy(recon_plan_t* plan) {
+  if (plan && plan->scratch_dev >= 0) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch[plan->scratch_dev].owner == plan->scratch_gen) g_scratch[plan->scratch_dev].owner = 0;
+  }
+  delete plan;
+}
+
 
 int recon_paint(recon_plan_t* pl, int which, const float* pos, const float* w, int64_t n, const int64_t* offsets,
                 uint32_t flags) {
-  if (!pl) return RECON_EINVAL;
+  CHECK_PLAN(pl);
   if (which != RECON_GAL && which != RECON_RAN) return fail(pl, RECON_EINVAL, "which must be RECON_GAL or RECON_RAN");
   if (which == RECON_RAN && !pl->randoms) return fail(pl, RECON_EINVAL, "plan was created with RECON_NO_RANDOMS");
   if (n < 0 || (n > 0 && !pos)) return fail(pl, RECON_EINVAL, "bad catalogue pointer or count");
@@ -1027,7 +1128,7 @@ int recon_paint(recon_plan_t* pl, int which, const float* pos, const float* w, i
 }
 
 int recon_set_delta(recon_plan_t* pl, const float* delta_s) {
-  if (!pl) return RECON_EINVAL;
+  CHECK_PLAN(pl);
   if (!delta_s) return fail(pl, RECON_EINVAL, "delta_s is NULL");
   const Ops* ops = ops_for(pl->n);
   if (pl->delta) {
@@ -1040,7 +1141,7 @@ int recon_set_delta(recon_plan_t* pl, const float* delta_s) {
 }
 
 int recon_solve(recon_plan_t* pl, int start, const void* net) {
-  if (!pl) return RECON_EINVAL;
+  CHECK_PLAN(pl);
   if (start < RECON_START_PLAIN || start > RECON_START_LEARNED) return fail(pl, RECON_EINVAL, "unknown start");
   if (start != RECON_START_PLAIN && !pl->corr)
     return fail(pl, RECON_EINVAL, "non-plain starts need a plan created with RECON_START_BUFFERS");
@@ -1124,7 +1225,7 @@ double plain_eps1_bound(double beta, double num0, double den0, double s2) {
 }
 
 int recon_iterate(recon_plan_t* pl, int max_iter, double tol, int32_t* iters_out, double* eps_out) {
-  if (!pl) return RECON_EINVAL;
+  CHECK_PLAN(pl);
   if (pl->state != ST_SOLVED) return fail(pl, RECON_ESTATE, "solve must precede iterate");
   if (max_iter < 0) return fail(pl, RECON_EINVAL, "max_iter must be >= 0");
   const Ops* ops = ops_for(pl->n);
@@ -1399,7 +1500,7 @@ int recon_start_restarts(const recon_plan_t* pl, int32_t* out) {
 
 int recon_shift(recon_plan_t* pl, int which_flags, const float* pos, int64_t n, const int64_t* offsets,
                 float* disp_out, float* pos_out) {
-  if (!pl) return RECON_EINVAL;
+  CHECK_PLAN(pl);
   const int which = which_flags & ~RECON_SHIFT_AS_PAINTED;
   const bool as_painted = (which_flags & RECON_SHIFT_AS_PAINTED) != 0;
   if (which != RECON_GAL && which != RECON_RAN) return fail(pl, RECON_EINVAL, "which must be RECON_GAL or RECON_RAN");
@@ -1442,7 +1543,8 @@ int recon_shift(recon_plan_t* pl, int which_flags, const float* pos, int64_t n, 
 }
 
 int recon_get_psi(recon_plan_t* pl, float* psi_out) {
-  if (!pl || !psi_out) return RECON_EINVAL;
+  CHECK_PLAN(pl);
+  if (!psi_out) return fail(pl, RECON_EINVAL, "NULL output pointer");
   if (pl->state != ST_SOLVED) return fail(pl, RECON_ESTATE, "no displacement yet");
   for (int b = 0; b < pl->batch; ++b)
     if (!pl->psi_valid[b]) return fail(pl, RECON_ESTATE, "displacement not computed; call iterate");
@@ -1453,7 +1555,8 @@ int recon_get_psi(recon_plan_t* pl, float* psi_out) {
 }
 
 int recon_get_grid(recon_plan_t* pl, int which, int64_t* out) {
-  if (!pl || !out) return RECON_EINVAL;
+  CHECK_PLAN(pl);
+  if (!out) return fail(pl, RECON_EINVAL, "NULL output pointer");
   if (which != RECON_GAL && which != RECON_RAN) return fail(pl, RECON_EINVAL, "which must be RECON_GAL or RECON_RAN");
   const long long* g = which == RECON_GAL ? pl->grid_g : pl->grid_r;
   if (!g || !(which == RECON_GAL ? pl->painted_g : pl->painted_r)) return fail(pl, RECON_ESTATE, "grid not painted");
@@ -1468,7 +1571,7 @@ int recon_get_grid(recon_plan_t* pl, int which, int64_t* out) {
 }
 
 int recon_radial_ratio(recon_plan_t* pl, const float* psi_ref, double lo, double hi, double* stats_out) {
-  if (!pl) return RECON_EINVAL;
+  CHECK_PLAN(pl);
   if (!psi_ref || !stats_out) return fail(pl, RECON_EINVAL, "NULL pointer");
   if (!(lo <= hi)) return fail(pl, RECON_EINVAL, "need lo <= hi");
   if (pl->state != ST_SOLVED) return fail(pl, RECON_ESTATE, "no displacement yet");
@@ -1504,7 +1607,7 @@ int recon_radial_ratio(recon_plan_t* pl, const float* psi_ref, double lo, double
 }
 
 int recon_helmholtz(recon_plan_t* pl, const float* psi_x, float* irr_out, float* sol_out) {
-  if (!pl) return RECON_EINVAL;
+  CHECK_PLAN(pl);
   if (!psi_x || !irr_out) return fail(pl, RECON_EINVAL, "NULL pointer");
   const Ops* ops = ops_for(pl->n);
   RECON_TRY(ops->helm(pl, psi_x));
@@ -1528,7 +1631,8 @@ int recon_helmholtz(recon_plan_t* pl, const float* psi_x, float* irr_out, float*
 }
 
 int recon_get_delta(recon_plan_t* pl, float* out) {
-  if (!pl || !out) return RECON_EINVAL;
+  CHECK_PLAN(pl);
+  if (!out) return fail(pl, RECON_EINVAL, "NULL output pointer");
   if (!pl->delta) return fail(pl, RECON_EINVAL, "plan was created without RECON_KEEP_DELTA");
   if (pl->state != ST_SOLVED && pl->state != ST_DELTA) return fail(pl, RECON_ESTATE, "no overdensity yet");
   HIP_TRY(pl, hipMemcpyAsync(out, pl->delta, sizeof(float) * pl->n3 * pl->batch, hipMemcpyDeviceToDevice, pl->stream));
@@ -1536,7 +1640,7 @@ int recon_get_delta(recon_plan_t* pl, float* out) {
 }
 
 int recon_cnn_forward(recon_plan_t* pl, const float* params, const float* delta, const float* u_p, float* du_out) {
-  if (!pl) return RECON_EINVAL;
+  CHECK_PLAN(pl);
   if (!pl->a1) return fail(pl, RECON_EINVAL, "plan was created without RECON_CNN_BUFFERS");
   if (!params || !delta || !u_p || !du_out) return fail(pl, RECON_EINVAL, "NULL pointer");
   return cnn_forward_impl(pl, params, delta, u_p, du_out, 1.0f / recon::cnn::S_U);
@@ -1546,7 +1650,7 @@ int recon_cnn_train_step(recon_plan_t* pl, float* params, float* adam_m, float* 
                          const float* delta, const float* u_p, const float* target_du, double* loss_out,
                          float* grad_out) {
   using namespace recon::cnn;
-  if (!pl) return RECON_EINVAL;
+  CHECK_PLAN(pl);
   if (!pl->a1) return fail(pl, RECON_EINVAL, "plan was created without RECON_CNN_BUFFERS");
   if (!params || !delta || !u_p || !target_du) return fail(pl, RECON_EINVAL, "NULL pointer");
   if (lr > 0.f && (!adam_m || !adam_v || step < 1)) return fail(pl, RECON_EINVAL, "Adam needs moments and step >= 1");
@@ -1585,7 +1689,8 @@ int recon_cnn_train_step(recon_plan_t* pl, float* params, float* adam_m, float* 
 }
 
 int recon_get_radial(recon_plan_t* pl, float* u_out) {
-  if (!pl || !u_out) return RECON_EINVAL;
+  CHECK_PLAN(pl);
+  if (!u_out) return fail(pl, RECON_EINVAL, "NULL output pointer");
   if (pl->state != ST_SOLVED) return fail(pl, RECON_ESTATE, "no displacement yet");
   for (int b = 0; b < pl->batch; ++b)
     if (!pl->psi_valid[b]) return fail(pl, RECON_ESTATE, "displacement not computed; call iterate");
@@ -1596,13 +1701,13 @@ int recon_get_radial(recon_plan_t* pl, float* u_out) {
 }
 
 int recon_restrict(recon_plan_t* pl, const float* fine, float* coarse) {
-  if (!pl) return RECON_EINVAL;
+  CHECK_PLAN(pl);
   if (!fine || !coarse) return fail(pl, RECON_EINVAL, "NULL pointer");
   return restrict_impl(pl, fine, coarse);
 }
 
 int recon_prolong(recon_plan_t* pl, const float* coarse, float* fine) {
-  if (!pl) return RECON_EINVAL;
+  CHECK_PLAN(pl);
   if (!coarse || !fine) return fail(pl, RECON_EINVAL, "NULL pointer");
   return prolong_impl(pl, coarse, 1.0f, fine);
 }

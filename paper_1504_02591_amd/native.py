@@ -30,7 +30,7 @@ EXPORTED = ("recon_workspace_bytes", "recon_plan", "recon_paint", "recon_solve",
             "recon_destroy", "recon_strerror", "recon_last_error", "recon_profile_start",
             "recon_profile_stop", "recon_profile_kernel_name", "recon_cnn_forward", "recon_cnn_train_step",
             "recon_get_radial", "recon_restrict", "recon_prolong", "recon_radial_ratio", "recon_helmholtz",
-            "recon_start_restarts")
+            "recon_start_restarts", "recon_plan_noalloc", "recon_noalloc_limit")
 
 
 class ReconError(RuntimeError):
@@ -66,6 +66,10 @@ def load(path=None):
     lib.recon_workspace_bytes.argtypes = [ctypes.POINTER(Params)]
     lib.recon_workspace_bytes.restype = ctypes.c_size_t
     lib.recon_plan.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(Params), vp, ctypes.c_size_t, vp]
+    lib.recon_plan_noalloc.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(Params), vp]
+    lib.recon_plan_noalloc.restype = ctypes.c_int
+    lib.recon_noalloc_limit.argtypes = []
+    lib.recon_noalloc_limit.restype = ctypes.c_size_t
     lib.recon_paint.argtypes = [vp, ctypes.c_int, vp, vp, i64, vp, u32]
     lib.recon_solve.argtypes = [vp, ctypes.c_int, vp]
     lib.recon_iterate.argtypes = [vp, ctypes.c_int, dbl, ctypes.POINTER(i32), ctypes.POINTER(dbl)]
@@ -125,7 +129,9 @@ class Plan:
 
     def __init__(self, n, box_len, observer, bias, growth, smooth_r, origin=(0.0, 0.0, 0.0), batch=1,
                  mask_tau=0.1, randoms=True, keep_delta=False, start_buffers=False, max_objects=0, cnn=False,
-                 cnn_half=False, graphs=False, lognormal=False, device=None):
+                 cnn_half=False, graphs=False, lognormal=False, device=None, noalloc=False):
+        """noalloc=True: the plan runs on the library's own device scratch (recon_plan_noalloc) instead of a
+        workspace allocated here; a later no-allocation plan on the same device makes this one stale."""
         self.lib = load()
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
         flags = (0 if randoms else NO_RANDOMS) | (KEEP_DELTA if keep_delta else 0) | \
@@ -149,11 +155,17 @@ class Plan:
         nbytes = self.lib.recon_workspace_bytes(ctypes.byref(p))
         if nbytes == 0:
             raise ReconError(RECON_EINVAL, "invalid parameters")
-        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         self.stream = torch.cuda.current_stream(self.device)
         h = ctypes.c_void_p()
-        rc = self.lib.recon_plan(ctypes.byref(h), ctypes.byref(p), _ptr(self.workspace), nbytes,
-                                 ctypes.c_void_p(self.stream.cuda_stream))
+        if noalloc:
+            self.workspace = None
+            with torch.cuda.device(self.device):
+                rc = self.lib.recon_plan_noalloc(ctypes.byref(h), ctypes.byref(p),
+                                                 ctypes.c_void_p(self.stream.cuda_stream))
+        else:
+            self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            rc = self.lib.recon_plan(ctypes.byref(h), ctypes.byref(p), _ptr(self.workspace), nbytes,
+                                     ctypes.c_void_p(self.stream.cuda_stream))
         if rc != RECON_OK:
             raise ReconError(rc, self.lib.recon_strerror(rc).decode())
         self.handle = h

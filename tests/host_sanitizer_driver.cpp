@@ -137,6 +137,20 @@ int main() {
   CHECK(recon_plan(&pl, &p, ws, sizeof ws, nullptr) == RECON_ENOMEM);             // far too small
   CHECK(pl == nullptr);
 
+  // the no-allocation plan checks its arguments and its scratch size before any device call
+  CHECK(recon_noalloc_limit() == (size_t)64 << 20);
+  CHECK(recon_plan_noalloc(nullptr, &p, nullptr) == RECON_EINVAL);
+  CHECK(recon_plan_noalloc(&pl, nullptr, nullptr) == RECON_EINVAL);
+  CHECK(pl == nullptr);
+  {
+    recon_params_t q = base(512);                          // 512^3 needs gigabytes
+    CHECK(recon_plan_noalloc(&pl, &q, nullptr) == RECON_ENOMEM);
+    q = base(32);
+    q.flags |= RECON_PASS_GRAPHS;
+    CHECK(recon_plan_noalloc(&pl, &q, nullptr) == RECON_EINVAL);
+    CHECK(pl == nullptr);
+  }
+
   // every entry point rejects a NULL plan
   float f[4] = {0.f, 0.f, 0.f, 0.f};
   int64_t g[2] = {0, 0};
