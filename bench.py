@@ -219,6 +219,100 @@ def run_batched(args, cats, torch, native, dev):
     return res
 
 
+def run_precision(args):
+    """The precision study: the periodic 1024^3 box of 1024^3 Zel'dovich lattice particles (L = 2000 Mpc/h,
+    f = 0.76, b = 1, R = 10 Mpc/h, observer 5000 Mpc/h from the centre, mean-density overdensity) in FP32
+    and with the split-bfloat16 matrix-core radix-8 stage (2 and 3 terms); every variant timed per
+    reconstruction (deposit, solve, passes to eps <= tol, shift of all particles), compared with the FP32
+    result at 1024^3 and with the FP64 oracle on the 128^3 sub-run of the same geometry."""
+    import numpy as np
+    import torch
+    from oracle import recon_oracle as O
+    from paper_1504_02591_amd import native
+    from synth import generators as G
+
+    def log(msg):
+        print(f"[precision] {msg}", file=sys.stderr, flush=True)
+
+    variants = (0, 2, 3)
+    names = {0: "fp32", 2: "split_bf16_2", 3: "split_bf16_3"}
+    out = {"subrun_128": {}, "n1024": {}}
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    # 128^3 sub-run against the FP64 oracle (6 fixed passes)
+    sub = G.config3(128)
+    ref = O.reconstruct(sub.gal_pos, None, None, None, sub.n, sub.box_len, sub.origin, sub.observer, sub.bias,
+                        sub.growth, sub.smooth_r, n_passes=6)
+    gsub = torch.from_numpy(sub.gal_pos).to(dev)
+    for v in variants:
+        plan = native.plan_for(sub, split_terms=v)
+        plan.paint(native.GAL, gsub)
+        plan.solve()
+        plan.iterate(6, 0.0)
+        psi = plan.psi()[0].cpu().numpy().astype(np.float64)
+        plan.close()
+        e = float(np.linalg.norm(psi - ref["psi"]) / np.linalg.norm(ref["psi"]))
+        out["subrun_128"][names[v]] = {"psi_rel_l2_vs_fp64_oracle": e}
+        log(f"128^3 sub-run, {names[v]}: Psi rel L2 vs FP64 oracle {e:.3e}")
+    del gsub
+    # the 1024^3 box
+    t0 = time.perf_counter()
+    cat = G.config3(1024, log=log)
+    log(f"1024^3 lattice: {cat.gal_pos.shape[0]} particles in {time.perf_counter() - t0:.1f}s")
+    gal = torch.from_numpy(cat.gal_pos).to(dev)
+    cat.gal_pos = None
+    disp = torch.empty_like(gal)
+    psi_fp32 = None
+    for v in variants:
+        plan = native.Plan(1024, cat.box_len, cat.observer, cat.bias, cat.growth, cat.smooth_r, randoms=False,
+                           max_objects=int(gal.shape[0]), graphs=True, split_terms=v)
+        log(f"{names[v]}: plan of {plan.workspace.numel() / 1e9:.1f} GB")
+        passes, rcs = [], []
+
+        def step():
+            plan.paint(native.GAL, gal)
+            plan.solve()
+            rc, iters, eps = plan.iterate(args.max_iter, args.tol)
+            plan.shift(native.GAL, gal, out_disp=disp)
+            passes.append(iters[0])
+            rcs.append(rc)
+            return eps[0]
+
+        step()
+        torch.cuda.synchronize()
+        k = max(1, args.steps // 4)
+        t1 = time.perf_counter()
+        for _ in range(k):
+            eps = step()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t1
+        plan.profile_start()
+        step()
+        prof = plan.profile_stop()
+        psi = plan.psi()[0]
+        plan.close()
+        del plan
+        ent = {"ms_per_recon": round(1e3 * el / k, 2), "recons_per_s": round(k / el, 4), "passes": passes[-1],
+               "eps": eps, "return_codes": sorted(set(rcs)),
+               "z_iter_avg_launch_ms": round(prof["z_iter"][1] / prof["z_iter"][0], 4) if "z_iter" in prof else None}
+        if psi_fp32 is None:
+            psi_fp32 = psi
+        else:
+            ent["psi_rel_l2_vs_fp32"] = float((psi - psi_fp32).double().norm() / psi_fp32.double().norm())
+            del psi
+        out["n1024"][names[v]] = ent
+        log(f"1024^3 {names[v]}: {ent}")
+        torch.cuda.empty_cache()
+    res = {"metric": "1024^3 precision study: reconstructions/s (FP32 and split-bf16 radix) and Psi rel L2",
+           "value": out["n1024"]["fp32"]["recons_per_s"], "unit": "recons/s", "n_gpus": 1,
+           "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"periodic 1024^3 grid over 2000 Mpc/h, {int(gal.shape[0])} Zel'dovich lattice "
+                                  f"particles, f=0.76 b=1 R=10, observer 5000 Mpc/h from the centre, mean-density "
+                                  f"overdensity, passes to eps<={args.tol:g}"},
+           "variants": out}
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -238,6 +332,8 @@ def main():
     ap.add_argument("--no-graphs", action="store_true", help="launch the steady-state pass eagerly")
     ap.add_argument("--lognormal", action="store_true", help="lognormal transform of delta_s (Sec. 6)")
     ap.add_argument("--ngp", action="store_true", help="nearest-grid-point deposit (the paper's binning)")
+    ap.add_argument("--precision", action="store_true",
+                    help="run the 1024^3 precision study (FP32 vs split-bf16 radix) instead of the survey workload")
     ap.add_argument("--batched", type=int, default=0,
                     help="also time B realisations of the batched 256^3 workload in one plan")
     args = ap.parse_args()
@@ -246,6 +342,9 @@ def main():
         print("bench.py measures a single MI355X: this build has no multi-GPU path; run with --gpus 1",
               file=sys.stderr, flush=True)
         sys.exit(2)
+    if args.precision:
+        run_precision(args)
+        return
 
     import numpy as np
     from synth import generators as G
@@ -270,21 +369,23 @@ def main():
     for s in starts:
         if s not in START_NAMES:
             sys.exit(f"unknown start {s!r}")
-    net, net_half = None, False
+    net, net_levels = None, 0
     if "learned" in starts:
         from paper_1504_02591_amd import learned
         wpath = args.weights or learned.WEIGHTS
         if os.path.exists(wpath):
             with np.load(wpath, allow_pickle=False) as z:
                 net = torch.from_numpy(np.ascontiguousarray(z["params"], dtype=np.float32)).to(dev)
-                net_half = bool(z["half"]) if "half" in z.files else False
+                net_levels = int(z["levels"]) if "levels" in z.files else (1 if "half" in z.files and bool(z["half"])
+                                                                             else 0)
         else:
             print(f"[bench] no learned-start weights at {wpath}: learned start skipped", file=sys.stderr, flush=True)
             starts.remove("learned")
 
     def make_plan(start):
         lrn = start == START_NAMES["learned"]
-        return native.plan_for(cat, start_buffers=start != 0, keep_delta=lrn, cnn=lrn, cnn_half=lrn and net_half,
+        return native.plan_for(cat, start_buffers=start != 0, keep_delta=lrn, cnn=lrn,
+                               cnn_half=lrn and net_levels == 1, cnn_quarter=lrn and net_levels == 2,
                                graphs=not args.no_graphs, lognormal=args.lognormal)
 
     codes = {}

@@ -84,6 +84,11 @@ extern "C" {
                                       C = -<ln(max(1 + delta_s, 1e-3))> over all cells (the kept
                                       delta_s of RECON_KEEP_DELTA is the transformed field); not applied
                                       to a field given to recon_set_delta                               */
+#define RECON_FFT_SPLITBF16 128u   /* precision study: the last radix-8 stage of every transform of the steady
+                                      correction pass's z step runs on the matrix cores as an 8-point DFT
+                                      GEMM with split-bfloat16 operands (2 terms, 3 products, about
+                                      2^-16 relative per product); n >= 64, other steps stay FP32      */
+#define RECON_FFT_SPLITBF16_X3 256u  /* as RECON_FFT_SPLITBF16 with 3 terms (6 products, about 2^-24)  */
 
 /* paint flags */
 #define RECON_PAINT_ACCUMULATE 1u  /* add to the grid instead of replacing it */
@@ -104,7 +109,8 @@ typedef struct {
   double smooth_r;         /* R >= 0 [Mpc/h] (Sec. 3.1 smoothing)                                        */
   double mask_tau;         /* mask threshold as a fraction of the mean 27-cell random sum (>= 0)          */
   uint32_t flags;          /* RECON_NO_RANDOMS | RECON_KEEP_DELTA | RECON_START_BUFFERS | RECON_PASS_GRAPHS |
-                              RECON_LOGNORMAL (| RECON_CNN_BUFFERS | RECON_CNN_HALF, recon_cnn.h)        */
+                              RECON_LOGNORMAL | RECON_FFT_SPLITBF16[_X3]
+                              (| RECON_CNN_BUFFERS | RECON_CNN_HALF, recon_cnn.h)                        */
   int64_t max_objects;     /* largest catalogue painted in one call that uses the brick-binned deposit
                               (workspace holds 36 B per object for it: the brick-ordered copy, each
                               object's slot, the brick-order shift's staging); larger calls fall back
@@ -214,6 +220,11 @@ int recon_set_delta(recon_plan_t* plan, const float* delta_s);
  * k < min(cap, kinds), clears the record and returns the number of kernel kinds; names come from
  * recon_profile_kernel_name(k). */
 int recon_profile_start(recon_plan_t* plan);
+/* Debug build only (the library compiled with -DRECON_DEBUG, librecon_debug.so): the number of array
+ * indices the device code found outside their array (each such access is skipped), on the current
+ * device since the last reset; synchronises the device; reset != 0 clears the count.  The release
+ * build has no checks and returns -1; -2 on a HIP error. */
+int64_t recon_debug_violations(int reset);
 int recon_profile_stop(recon_plan_t* plan, int32_t* counts, double* total_ms, int cap);
 const char* recon_profile_kernel_name(int kind);
 

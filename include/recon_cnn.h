@@ -17,7 +17,8 @@
  * in that order.  Every call needs a plan created with RECON_CNN_BUFFERS.
  *
  * Network grid: the plan's n^3 grid, or with RECON_CNN_HALF the (n/2)^3 grid of every
- * other node (cell 2 L/n).  Then recon_solve restricts delta_s and u_p by full weighting
+ * other node (cell 2 L/n), or with RECON_CNN_QUARTER the (n/4)^3 grid of every fourth node (the
+ * restriction and prolongation below applied twice).  Then recon_solve restricts delta_s and u_p by full weighting
  * (recon_restrict), evaluates the network with r_hat of the coarse nodes, and prolongs
  * Delta u linearly (recon_prolong) to the n^3 grid.  The network grid needs >= 16^3 cells.
  * recon_cnn_forward and recon_cnn_train_step take and return fields on the network grid.
@@ -34,10 +35,12 @@ extern "C" {
 #define RECON_CNN_PARAMS 10833
 #define RECON_CNN_BUFFERS 8u     /* plan flag: activation, gradient and partial-sum buffers */
 #define RECON_CNN_HALF 16u       /* plan flag (with RECON_CNN_BUFFERS): network on the (n/2)^3 grid */
+#define RECON_CNN_QUARTER 512u   /* plan flag (with RECON_CNN_BUFFERS): network on the (n/4)^3 grid of every
+                                    fourth node: inputs restricted twice, output prolonged twice      */
 
 /* Delta u for every cell of every realisation of the plan.  params: device FP32
  * [RECON_CNN_PARAMS]; delta, u_p, du_out: device FP32 [batch][m^3] on the network grid
- * (m = n, or n/2 with RECON_CNN_HALF). */
+ * (m = n, n/2 with RECON_CNN_HALF, or n/4 with RECON_CNN_QUARTER). */
 int recon_cnn_forward(recon_plan_t* plan, const float* params, const float* delta, const float* u_p, float* du_out);
 
 /* One training step on the plan's batch: loss = mean (y - 0.1 target_du)^2 over all cells,

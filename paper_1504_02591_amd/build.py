@@ -8,10 +8,14 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 SOURCES = [os.path.join(HERE, "csrc", "recon_api.hip")]
 OUTPUT = os.path.join(HERE, "librecon.so")
+# the same library with the device bounds checks compiled in (recon_debug_violations counts them)
+DEBUG_OUTPUT = os.path.join(HERE, "librecon_debug.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
          # no packed FP32 instructions anywhere in the device code
-         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         # roctx ranges named after the pipeline's stages (shown by rocprofv3 --marker-trace)
+         "-L/opt/rocm/lib", "-Wl,-rpath,/opt/rocm/lib", "-lrocprofiler-sdk-roctx"]
 
 
 def build(verbose=False, output=OUTPUT, extra=()):
@@ -31,5 +35,11 @@ def build(verbose=False, output=OUTPUT, extra=()):
     return output
 
 
+def build_debug(verbose=False):
+    """The library with RECON_DEBUG bounds checks, beside the release one."""
+    return build(verbose=verbose, output=DEBUG_OUTPUT, extra=("-DRECON_DEBUG",))
+
+
 if __name__ == "__main__":
     print(build(verbose=True))
+    print(build_debug(verbose=True))

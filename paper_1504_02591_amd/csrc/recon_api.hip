@@ -8,6 +8,7 @@
 // plus D_s and D_n.  Convergence norms come back as one small device-to-host
 // copy per pass.
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <cmath>
 #include <cstring>
@@ -43,11 +44,14 @@ struct Layout {
   // network buffers
   size_t a1 = 0, a2 = 0, d1 = 0, d2 = 0, ybuf = 0, dybuf = 0, upbuf = 0, wk2t = 0, w3 = 0,
          part_out = 0, part_w1 = 0, part_w2 = 0, g1 = 0, g2 = 0, g3 = 0, grad = 0, lossp = 0, losst = 0, dc = 0, uc = 0,
-         wf1 = 0, wf2 = 0;
+         wf1 = 0, wf2 = 0, dh = 0, uh = 0;
   long long nb_conv = 0, nb_w = 0, nb_loss = 0;
   long long cnn_n = 0;
   long long nbins = 0, nscan = 0;
 };
+
+// Coarsening levels of the network grid: 0 (solver grid), 1 (RECON_CNN_HALF), 2 (RECON_CNN_QUARTER).
+int cnn_levels(uint32_t flags) { return (flags & RECON_CNN_QUARTER) ? 2 : ((flags & RECON_CNN_HALF) ? 1 : 0); }
 
 bool valid_params(const recon_params_t* p, std::string* why) {
   auto fail = [&](const char* m) { if (why) *why = m; return false; };
@@ -62,10 +66,16 @@ bool valid_params(const recon_params_t* p, std::string* why) {
   if (!(p->smooth_r >= 0.0) || !std::isfinite(p->smooth_r)) return fail("smooth_r must be >= 0 and finite");
   if (!(p->mask_tau >= 0.0) || !std::isfinite(p->mask_tau)) return fail("mask_tau must be >= 0 and finite");
   if (p->flags & ~(RECON_NO_RANDOMS | RECON_KEEP_DELTA | RECON_START_BUFFERS | RECON_CNN_BUFFERS | RECON_CNN_HALF |
-                   RECON_PASS_GRAPHS | RECON_LOGNORMAL))
+                   RECON_PASS_GRAPHS | RECON_LOGNORMAL | RECON_FFT_SPLITBF16 | RECON_FFT_SPLITBF16_X3 |
+                   RECON_CNN_QUARTER))
     return fail("unknown flag");
-  if ((p->flags & RECON_CNN_HALF) && !(p->flags & RECON_CNN_BUFFERS)) return fail("RECON_CNN_HALF needs RECON_CNN_BUFFERS");
-  if ((p->flags & RECON_CNN_BUFFERS) && p->n < ((p->flags & RECON_CNN_HALF) ? 32 : 16))
+  if ((p->flags & RECON_FFT_SPLITBF16) && (p->flags & RECON_FFT_SPLITBF16_X3))
+    return fail("RECON_FFT_SPLITBF16 and RECON_FFT_SPLITBF16_X3 exclude each other");
+  if ((p->flags & (RECON_CNN_HALF | RECON_CNN_QUARTER)) && !(p->flags & RECON_CNN_BUFFERS))
+    return fail("RECON_CNN_HALF / RECON_CNN_QUARTER need RECON_CNN_BUFFERS");
+  if ((p->flags & RECON_CNN_HALF) && (p->flags & RECON_CNN_QUARTER))
+    return fail("RECON_CNN_HALF and RECON_CNN_QUARTER exclude each other");
+  if ((p->flags & RECON_CNN_BUFFERS) && (p->n >> cnn_levels(p->flags)) < 16)
     return fail("the network grid needs at least 16^3 cells");
   if (p->max_objects < 0 || p->max_objects >= (1LL << 32)) return fail("max_objects must be in [0, 2^32)");
   return true;
@@ -122,7 +132,8 @@ Layout make_layout(const recon_params_t* p) {
   }
   if (p->flags & RECON_CNN_BUFFERS) {
     using namespace recon::cnn;
-    const long long m = (p->flags & RECON_CNN_HALF) ? n / 2 : n, m3 = m * m * m;   // network grid
+    const int lv = cnn_levels(p->flags);
+    const long long m = n >> lv, m3 = m * m * m;   // network grid
     L.cnn_n = m;
     L.nb_conv = m3 / TPOS;
     L.nb_w = (m / TY) * (m / TZ);
@@ -134,9 +145,16 @@ Layout make_layout(const recon_params_t* p) {
     L.ybuf = take(b * m3 * 4);
     L.dybuf = take(b * m3 * 4);
     L.upbuf = take(b * n3 * 4);
-    if (p->flags & RECON_CNN_HALF) {
+    if (lv >= 1) {
+      // restricted inputs on the network grid; with two levels also the (n/2)^3 intermediates
+      // (the second also holds the network output prolonged once)
       L.dc = take(b * m3 * 4);
       L.uc = take(b * m3 * 4);
+    }
+    if (lv == 2) {
+      const long long h3 = (n / 2) * (n / 2) * (n / 2);
+      L.dh = take(b * h3 * 4);
+      L.uh = take(b * h3 * 4);
     }
     L.wk2t = take(CH * K2 * 2);
     L.w3 = take(K2 * 4);
@@ -266,7 +284,7 @@ struct recon_plan_s {
                  *wk2t = nullptr;
   float *ybuf = nullptr, *dybuf = nullptr, *upbuf = nullptr, *w3 = nullptr, *part_out = nullptr,
         *part_w1 = nullptr, *part_w2 = nullptr, *g1 = nullptr, *g2 = nullptr, *g3 = nullptr, *gradbuf = nullptr,
-        *dc = nullptr, *uc = nullptr;
+        *dc = nullptr, *uc = nullptr, *dh = nullptr, *uh = nullptr;
   uint4 *wf1 = nullptr, *wf2 = nullptr;
   int cnn_n = 0;                 // network grid: n, or n/2 with RECON_CNN_HALF
   long long cnn_n3 = 0;
@@ -316,6 +334,15 @@ int check_launch(recon_plan_t* pl, const char* what) {
   if (e != hipSuccess) return fail(pl, RECON_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
   return RECON_OK;
 }
+
+// roctx range over a stage of the pipeline (host side: the enqueueing of its launches, and the waits
+// of the calls that synchronise), named after the hot-path step it covers.
+struct Marker {
+  explicit Marker(const char* m) { roctxRangePushA(m); }
+  ~Marker() { roctxRangePop(); }
+  Marker(const Marker&) = delete;
+  Marker& operator=(const Marker&) = delete;
+};
 
 struct ProfScope {
   recon_plan_t* pl;
@@ -420,8 +447,8 @@ struct SizeOps {
   static constexpr int WZ = wz<N>(), WY = wy<N>(), WX = wx<N>();
   static constexpr int TZ = ntz<N>(), TY = nty<N>(), TX = ntx<N>();
   static dim3 gz(const recon_plan_t* pl) { return dim3(N * (N / (2 * WZ)), pl->batch); }
-  template <int MODE>
-  static dim3 gzi(const recon_plan_t* pl) { return dim3(ztiles<N>() / ztpb<N, MODE>(), pl->batch); }
+  template <int MODE, int SPLIT = 0>
+  static dim3 gzi(const recon_plan_t* pl) { return dim3(ztiles<N>() / ztpb<N, MODE, SPLIT>(), pl->batch); }
   static dim3 gy(const recon_plan_t* pl) { return dim3((N / 2 + 1) * (N / WY), pl->batch); }
   static dim3 gx(const recon_plan_t* pl) { return dim3((N / 2 + 1) * N / WX, pl->batch); }
 
@@ -566,6 +593,12 @@ struct SizeOps {
       else if (mode == ZI_CROSS)
         k_z_iter<N, ZI_CROSS><<<gzi<ZI_CROSS>(pl), dim3(TZ), 0, s>>>(pl->w0, pl->w1, pl->w2, pl->geo, pl->corr,
                                                                 pl->partials, act, pl->tw);
+      else if (N >= 64 && (pl->p.flags & RECON_FFT_SPLITBF16))
+        k_z_iter<N, ZI_PLAIN, N >= 64 ? 2 : 0><<<gzi<ZI_PLAIN, N >= 64 ? 2 : 0>(pl), dim3(TZ), 0, s>>>(
+            pl->w0, pl->w1, pl->w2, pl->geo, nullptr, nullptr, act, pl->tw);
+      else if (N >= 64 && (pl->p.flags & RECON_FFT_SPLITBF16_X3))
+        k_z_iter<N, ZI_PLAIN, N >= 64 ? 3 : 0><<<gzi<ZI_PLAIN, N >= 64 ? 3 : 0>(pl), dim3(TZ), 0, s>>>(
+            pl->w0, pl->w1, pl->w2, pl->geo, nullptr, nullptr, act, pl->tw);
       else
         k_z_iter<N, ZI_PLAIN><<<gzi<ZI_PLAIN>(pl), dim3(TZ), 0, s>>>(pl->w0, pl->w1, pl->w2, pl->geo, nullptr,
                                                                 nullptr, act, pl->tw);
@@ -679,26 +712,31 @@ recon::cnn::Geo3 grid_geo(const recon_plan_t* pl, bool network) {
 }
 recon::cnn::Geo3 cnn_geo(const recon_plan_t* pl) { return grid_geo(pl, true); }
 
-// Restriction of one field (fb == nullptr) or of two fields in one pass.
-int restrict_impl(recon_plan_t* pl, const float* fa, float* ca, const float* fb = nullptr, float* cb = nullptr) {
-  const long long m = pl->n / 2;
+// Restriction of one field (fb == nullptr) or of two fields in one pass, from nf^3 (the plan's grid
+// unless given) to (nf/2)^3.
+int restrict_impl(recon_plan_t* pl, const float* fa, float* ca, const float* fb = nullptr, float* cb = nullptr,
+                  int nf = 0) {
+  if (nf == 0) nf = pl->n;
+  const long long m = nf / 2;
   PROF(pl, KP_RESAMPLE);
   if (m >= 64) {   // slab kernel: 64 x 4 x 16 coarse nodes per block
     const dim3 grid((unsigned)((m / 64) * (m / 4) * (m / 16)), pl->batch);
-    if (fb) recon::cnn::k_restrict_slab<2><<<grid, 256, 0, pl->stream>>>(fa, fb, pl->n, ca, cb);
-    else recon::cnn::k_restrict_slab<1><<<grid, 256, 0, pl->stream>>>(fa, fa, pl->n, ca, ca);
+    if (fb) recon::cnn::k_restrict_slab<2><<<grid, 256, 0, pl->stream>>>(fa, fb, nf, ca, cb);
+    else recon::cnn::k_restrict_slab<1><<<grid, 256, 0, pl->stream>>>(fa, fa, nf, ca, ca);
   } else {
     const dim3 grid((unsigned)((m * m * m + 255) / 256), pl->batch);
-    if (fb) recon::cnn::k_restrict<2><<<grid, 256, 0, pl->stream>>>(fa, fb, pl->n, ca, cb);
-    else recon::cnn::k_restrict<1><<<grid, 256, 0, pl->stream>>>(fa, fa, pl->n, ca, ca);
+    if (fb) recon::cnn::k_restrict<2><<<grid, 256, 0, pl->stream>>>(fa, fb, nf, ca, cb);
+    else recon::cnn::k_restrict<1><<<grid, 256, 0, pl->stream>>>(fa, fa, nf, ca, ca);
   }
   return check_launch(pl, "restriction");
 }
 
-int prolong_impl(recon_plan_t* pl, const float* coarse, float scale, float* fine) {
-  const long long m = pl->n / 2;
+// Prolongation from (nf/2)^3 to nf^3 (the plan's grid unless given).
+int prolong_impl(recon_plan_t* pl, const float* coarse, float scale, float* fine, int nf = 0) {
+  if (nf == 0) nf = pl->n;
+  const long long m = nf / 2;
   PROF(pl, KP_RESAMPLE);
-  recon::cnn::k_prolong<<<dim3((unsigned)((m * m * m + 255) / 256), pl->batch), 256, 0, pl->stream>>>(coarse, pl->n,
+  recon::cnn::k_prolong<<<dim3((unsigned)((m * m * m + 255) / 256), pl->batch), 256, 0, pl->stream>>>(coarse, nf,
                                                                                                       scale, fine);
   return check_launch(pl, "prolongation");
 }
@@ -842,9 +880,13 @@ int plan_create(recon_plan_t** out, const recon_params_t* params, const Layout& 
     pl->wf2 = (uint4*)(w + L.wf2);
     pl->cnn_n = (int)L.cnn_n;
     pl->cnn_n3 = L.cnn_n * L.cnn_n * L.cnn_n;
-    if (params->flags & RECON_CNN_HALF) {
+    if (params->flags & (RECON_CNN_HALF | RECON_CNN_QUARTER)) {
       pl->dc = (float*)(w + L.dc);
       pl->uc = (float*)(w + L.uc);
+    }
+    if (params->flags & RECON_CNN_QUARTER) {
+      pl->dh = (float*)(w + L.dh);
+      pl->uh = (float*)(w + L.uh);
     }
     pl->wk2t = (unsigned short*)(w + L.wk2t);
     pl->w3 = (float*)(w + L.w3);
@@ -1006,7 +1048,6 @@ void recon_destroy(recon_plan_t* plan) {
   delete plan;
 }
 
-
 int recon_paint(recon_plan_t* pl, int which, const float* pos, const float* w, int64_t n, const int64_t* offsets,
                 uint32_t flags) {
   CHECK_PLAN(pl);
@@ -1015,6 +1056,7 @@ int recon_paint(recon_plan_t* pl, int which, const float* pos, const float* w, i
   if (n < 0 || (n > 0 && !pos)) return fail(pl, RECON_EINVAL, "bad catalogue pointer or count");
   if (pl->batch > 1 && !offsets && n > 0) return fail(pl, RECON_EINVAL, "offsets are required when batch > 1");
   if (flags & ~(RECON_PAINT_ACCUMULATE | RECON_PAINT_NGP)) return fail(pl, RECON_EINVAL, "unknown paint flag");
+  Marker mark(which == RECON_GAL ? "a1 deposit (galaxies)" : "a1 deposit (randoms)");
   long long* grid = which == RECON_GAL ? pl->grid_g : pl->grid_r;
   const bool first = which == RECON_GAL ? !pl->painted_g : !pl->painted_r;
   int* errc = pl->err + which;   // invalid-object counter of this grid
@@ -1154,6 +1196,7 @@ int recon_solve(recon_plan_t* pl, int start, const void* net) {
   if (pl->state == ST_PAINTED) {
     if (!pl->painted_g) return fail(pl, RECON_ESTATE, "galaxies were not painted");
     if (pl->randoms && !pl->painted_r) return fail(pl, RECON_ESTATE, "randoms were not painted");
+    Marker mark("a2-a6 totals, smoothing, mask, overdensity, D_s");
     RECON_TRY(ops->setup(pl));
     // one read-back: invalid-object counters and the totals status of every realisation
     std::vector<int> st(pl->batch, 0);
@@ -1189,10 +1232,18 @@ int recon_solve(recon_plan_t* pl, int start, const void* net) {
     pl->restarts[b] = 0;
   }
   if (start == RECON_START_LEARNED) {
+    Marker mark("a7/a11 learned start (u_p, network)");
     // u_p = Psi_p . r_hat from the fanned-out start, then Delta u = network(delta_s, u_p) into corr
     RECON_TRY(ops->fanout(pl, nullptr, true));
     RECON_TRY(ops->zfinal(pl, nullptr, pl->upbuf, false, nullptr, true));
-    if (pl->dc) {
+    if (pl->dh) {
+      // network on the (n/4)^3 grid: restrict the inputs twice, prolong its output twice
+      RECON_TRY(restrict_impl(pl, pl->delta, pl->dh, pl->upbuf, pl->uh));
+      RECON_TRY(restrict_impl(pl, pl->dh, pl->dc, pl->uh, pl->uc, pl->n / 2));
+      RECON_TRY(cnn_forward_impl(pl, (const float*)net, pl->dc, pl->uc, pl->ybuf, 1.0f / recon::cnn::S_U));
+      RECON_TRY(prolong_impl(pl, pl->ybuf, 1.0f, pl->dh, pl->n / 2));
+      RECON_TRY(prolong_impl(pl, pl->dh, 1.0f, pl->corr));
+    } else if (pl->dc) {
       // network on the (n/2)^3 grid: restrict the inputs, prolong its output
       RECON_TRY(restrict_impl(pl, pl->delta, pl->dc, pl->upbuf, pl->uc));
       RECON_TRY(cnn_forward_impl(pl, (const float*)net, pl->dc, pl->uc, pl->ybuf, 1.0f / recon::cnn::S_U));
@@ -1358,6 +1409,7 @@ int recon_iterate(recon_plan_t* pl, int max_iter, double tol, int32_t* iters_out
   };
 
   for (int it = 0; it < max_iter; ++it) {
+    Marker mark("a8 correction pass");
     bool any = false;
     for (int b = 0; b < B; ++b) {
       pl->h_it[b] = pl->done[b] ? 0 : 1;
@@ -1458,6 +1510,7 @@ int recon_iterate(recon_plan_t* pl, int max_iter, double tol, int32_t* iters_out
       }
     }
   }
+  Marker mark_final("a9 final Psi");
   RECON_TRY(resolve_pending());
   // displacement of every realisation whose Psi buffer is stale (realisations stopped inside a pass
   // get state X again from D_n first)
@@ -1514,6 +1567,7 @@ int recon_shift(recon_plan_t* pl, int which_flags, const float* pos, int64_t n, 
   if (as_painted && !(which == pl->srt_which && pos == pl->srt_pos && n == pl->srt_n && offsets == pl->srt_off))
     return fail(pl, RECON_EINVAL, "RECON_SHIFT_AS_PAINTED: not the catalogue painted last through the bricks");
   if (n == 0) return RECON_OK;
+  Marker mark(which == RECON_GAL ? "a10 shift (galaxies)" : "a10 shift (randoms)");
   HIP_TRY(pl, hipMemsetAsync(pl->err + 2, 0, sizeof(int), pl->stream));
   long long blocks = (n + kThreads - 1) / kThreads;
   if (blocks > 8192) blocks = 8192;
@@ -1739,6 +1793,24 @@ int recon_profile_stop(recon_plan_t* pl, int32_t* counts, double* total_ms, int 
     if (total_ms) total_ms[k] = t[k];
   }
   return KP_COUNT;
+}
+
+int64_t recon_debug_violations(int reset) {
+#ifdef RECON_DEBUG
+  if (hipDeviceSynchronize() != hipSuccess) return -2;
+  unsigned long long v = 0;
+  if (hipMemcpyFromSymbol(&v, HIP_SYMBOL(recon::recon_debug_count), sizeof v, 0, hipMemcpyDeviceToHost) != hipSuccess)
+    return -2;
+  if (reset) {
+    const unsigned long long z = 0;
+    if (hipMemcpyToSymbol(HIP_SYMBOL(recon::recon_debug_count), &z, sizeof z, 0, hipMemcpyHostToDevice) != hipSuccess)
+      return -2;
+  }
+  return (int64_t)v;
+#else
+  (void)reset;
+  return -1;
+#endif
 }
 
 const char* recon_profile_kernel_name(int id) {

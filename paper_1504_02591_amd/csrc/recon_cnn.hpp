@@ -4,7 +4,7 @@
 //   x0 = [delta_s, S_U u_p, r_x, r_y, r_z, 0, 0, 0]     (assembled on the fly)
 //   a1 = relu(conv(x0; W1, b1))      8 -> 16   BF16 MFMA
 //   a2 = relu(conv(a1; W2, b2))     16 -> 16   BF16 MFMA
-//   y  =      conv(a2; W3, b3)      16 -> 1    VALU
+//   y  =      conv(a2; W3, b3)      16 -> 1    BF16 MFMA (k_conv_out_mfma)
 //   Delta u = y / S_U
 //
 // Parameter vector (FP32, device): W1 [16][27][8], b1 [16], W2 [16][27][16], b2 [16],

@@ -16,6 +16,20 @@ namespace recon {
 
 constexpr int kThreads = 256;
 
+// Bounds checks of the debug build (-DRECON_DEBUG): an index outside [0, n) of the array it addresses
+// is counted in recon_debug_count and the access is skipped; the release build compiles the checks
+// out (in_bounds is the constant true).  recon_debug_violations() reads the count.
+#ifdef RECON_DEBUG
+__device__ unsigned long long recon_debug_count;
+__device__ __forceinline__ bool in_bounds(long long i, long long n) {
+  if (i >= 0 && i < n) return true;
+  atomicAdd(&recon_debug_count, 1ull);
+  return false;
+}
+#else
+__device__ __forceinline__ constexpr bool in_bounds(long long, long long) { return true; }
+#endif
+
 __host__ __device__ constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n / 2); }
 
 __device__ __forceinline__ float2 operator+(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
@@ -228,9 +242,122 @@ __device__ __forceinline__ void middle_passes(float2* buf, const float2* tw) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Optional radix-8 stage on the matrix cores with split-bfloat16 compensated products (the
+// precision study's DFT-as-GEMM variant; the default transforms are FP32 throughout).
+//
+// A radix-8 butterfly is the product of the 8-point DFT matrix (in real form, 16 x 16) with the 16
+// real inputs of the butterfly after their twiddle factors.  Sixteen butterflies form the 16
+// columns of one v_mfma_f32_16x16x16bf16_1k product.  Operands are split into bfloat16 terms,
+// x = x_1 + x_2 (+ x_3), x_1 = bf16(x), x_2 = bf16(x - x_1), x_3 = bf16(x - x_1 - x_2), and the
+// products whose terms are not both of the smallest order are accumulated in FP32 (TERMS = 2: three
+// products, relative error about 2^-16; TERMS = 3: six products, about 2^-24).
+// Operand layout: lane l holds A[l%16][4(l/16) + 0..3] and B[4(l/16) + 0..3][l%16]; the result is
+// D[4(l/16) + 0..3][l%16].  Lane l therefore feeds complex inputs 2(l/16), 2(l/16) + 1 of butterfly
+// l%16 and receives the complex outputs of the same indices.
+// ---------------------------------------------------------------------------
+typedef short mf_s4 __attribute__((ext_vector_type(4)));
+typedef float mf_f4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ unsigned short bf16_rne(float f) {
+  unsigned u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ float bf16_val(unsigned short h) { return __uint_as_float(((unsigned)h) << 16); }
+
+// Split four values into TERMS bfloat16 operand vectors.
+template <int TERMS>
+__device__ __forceinline__ void bf16_split4(const float* x, mf_s4* t) {
+  float r[4] = {x[0], x[1], x[2], x[3]};
+#pragma unroll
+  for (int k = 0; k < TERMS; ++k) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const unsigned short h = bf16_rne(r[i]);
+      t[k][i] = (short)h;
+      r[i] -= bf16_val(h);
+    }
+  }
+}
+
+// Real form of the 8-point DFT, element (m, kk): output (m/2, re|im), input (kk/2, re|im).
+template <bool INV>
+__device__ __forceinline__ float dft8_real(int m, int kk) {
+  const float s = 0.70710678118654752440f;
+  const float c8[8] = {1.f, s, 0.f, -s, -1.f, -s, 0.f, s};
+  const float s8[8] = {0.f, s, 1.f, s, 0.f, -s, -1.f, -s};
+  const int a = ((m >> 1) * (kk >> 1)) & 7;
+  const float wr = c8[a], wi = INV ? s8[a] : -s8[a];    // omega^(p r), omega = exp(-+ 2 pi i / 8)
+  if ((m & 1) == 0) return (kk & 1) ? -wi : wr;
+  return (kk & 1) ? wr : wi;
+}
+
+// LDS-to-LDS radix-8 Stockham pass (completed sub-transform length NS) on the matrix cores.  Every
+// wave handles the 64 butterflies of its 64 fragment threads, 16 per product.  Needs (N/8) W to be a
+// multiple of 64 (whole waves).
+template <int N, int W, int NS, bool INV, bool JF, int TERMS>
+__device__ __forceinline__ void lds_pass_r8_mfma(float2* buf, const float2* tw) {
+  using L = Lay<N, W, JF>;
+  static_assert(L::NTF % 64 == 0, "the matrix-core radix-8 pass runs whole waves");
+  const int t = threadIdx.x, lane = t & 63, wbase = t - lane, n = lane & 15, q = lane >> 4;
+  float x[4][4];
+  if (t < L::NTF) {
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      int c, j;
+      bfly_coords<N, W, 8, JF>(wbase + 16 * g + n, c, j);
+      const int k = j % NS;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int r = 2 * q + h;
+        float2 v = buf[L::at(j + r * (N / 8), c)];
+        if constexpr (NS > 1) {
+          float2 w = tw[r * k * (N / (NS * 8))];
+          if (INV) w.y = -w.y;
+          v = cmul(v, w);
+        }
+        x[g][2 * h] = v.x;
+        x[g][2 * h + 1] = v.y;
+      }
+    }
+  }
+  __syncthreads();
+  if (t < L::NTF) {
+    float a[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) a[i] = dft8_real<INV>(n, 4 * q + i);
+    mf_s4 at[TERMS];
+    bf16_split4<TERMS>(a, at);
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      mf_s4 bt[TERMS];
+      bf16_split4<TERMS>(x[g], bt);
+      mf_f4 acc = {0.f, 0.f, 0.f, 0.f};
+      // smallest products first
+      if constexpr (TERMS == 3) {
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(at[1], bt[1], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(at[2], bt[0], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(at[0], bt[2], acc, 0, 0, 0);
+      }
+      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(at[1], bt[0], acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(at[0], bt[1], acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(at[0], bt[0], acc, 0, 0, 0);
+      int c, j;
+      bfly_coords<N, W, 8, JF>(wbase + 16 * g + n, c, j);
+      const int k = j % NS;
+      const int idx = (j / NS) * NS * 8 + k;
+      buf[L::at(idx + (2 * q) * NS, c)] = make_float2(acc[0], acc[1]);
+      buf[L::at(idx + (2 * q + 1) * NS, c)] = make_float2(acc[2], acc[3]);
+    }
+  }
+  __syncthreads();
+}
+
 // Length-N FFT of the tile, register fragment in and out.  The caller must place a
-// barrier before its next write to the tile.
-template <int N, int W, bool INV, bool JF>
+// barrier before its next write to the tile.  SPLIT > 0 (N >= 64): the last radix-8 stage runs on
+// the matrix cores with SPLIT bfloat16 terms per operand (lds_pass_r8_mfma).
+template <int N, int W, bool INV, bool JF, int SPLIT = 0>
 __device__ __forceinline__ void fft_rr(float2* v, float2* buf, const float2* tw) {
   using L = Lay<N, W, JF>;
   if constexpr (N == 8) {
@@ -238,6 +365,16 @@ __device__ __forceinline__ void fft_rr(float2* v, float2* buf, const float2* tw)
   } else if constexpr (N < 64) {
     first_pass<N, W, INV, JF>(v, buf);
     lds_pass<N, W, N / 8, 8, INV, JF>(buf, tw);
+    if (threadIdx.x < L::NTF) {
+      int c, j;
+      frag_coords<N, W, JF>(c, j);
+#pragma unroll
+      for (int r = 0; r < 8; ++r) v[r] = buf[L::at(j + r * (N / 8), c)];
+    }
+  } else if constexpr (SPLIT > 0) {
+    first_pass<N, W, INV, JF>(v, buf);
+    middle_passes<N, W, INV, JF>(buf, tw);
+    lds_pass_r8_mfma<N, W, N / 8, INV, JF, SPLIT>(buf, tw);
     if (threadIdx.x < L::NTF) {
       int c, j;
       frag_coords<N, W, JF>(c, j);
@@ -252,7 +389,8 @@ __device__ __forceinline__ void fft_rr(float2* v, float2* buf, const float2* tw)
 }
 
 // Length-N FFT of the tile, register fragment in, natural order in LDS out (ends with a barrier).
-template <int N, int W, bool INV, bool JF>
+// SPLIT as in fft_rr.
+template <int N, int W, bool INV, bool JF, int SPLIT = 0>
 __device__ __forceinline__ void fft_rl(float2* v, float2* buf, const float2* tw) {
   using L = Lay<N, W, JF>;
   if constexpr (N == 8) {
@@ -271,7 +409,8 @@ __device__ __forceinline__ void fft_rl(float2* v, float2* buf, const float2* tw)
   } else {
     first_pass<N, W, INV, JF>(v, buf);
     middle_passes<N, W, INV, JF>(buf, tw);
-    lds_pass<N, W, 8, N / 8, INV, JF>(buf, tw);
+    if constexpr (SPLIT > 0) lds_pass_r8_mfma<N, W, N / 8, INV, JF, SPLIT>(buf, tw);
+    else lds_pass<N, W, 8, N / 8, INV, JF>(buf, tw);
   }
 }
 

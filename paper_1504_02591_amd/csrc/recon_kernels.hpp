@@ -63,8 +63,11 @@ template <int N> constexpr int wy() { return N >= 1024 ? 8 : cmin(N, RECON_TILE_
 template <int N> constexpr int wx() { return RECON_TILE_X; }
 // z tiles (one y row, 2 wz consecutive x) and tiles per block of the z iteration
 template <int N> constexpr int ztiles() { return N * (N / (2 * wz<N>())); }
-// (the start and cross modes, which hold more live state, take one tile per block)
-template <int N, int MODE> constexpr int ztpb() { return MODE == ZI_PLAIN ? cmin(RECON_Z_TPB, ztiles<N>()) : 1; }
+// (the start and cross modes and the matrix-core radix variants, which hold more live state, take one
+// tile per block)
+template <int N, int MODE, int SPLIT = 0> constexpr int ztpb() {
+  return MODE == ZI_PLAIN && SPLIT == 0 ? cmin(RECON_Z_TPB, ztiles<N>()) : 1;
+}
 
 
 __device__ __forceinline__ long long ceil_div_ll(long long a, long long b) { return (a + b - 1) / b; }
@@ -166,7 +169,8 @@ __global__ void __launch_bounds__(256) k_paint_ngp(const float* __restrict__ pos
     const unsigned long long wq = w ? (unsigned long long)__double2ll_rn((double)wv * 4294967296.0)
                                     : (1ull << 32);
     const int b = off ? find_realisation(off, batch, i) : 0;
-    if (wq) atomicAdd(grid + (long long)b * n3 + (ii[2] * g.n + ii[1]) * g.n + ii[0], wq);
+    const long long cell = (ii[2] * g.n + ii[1]) * g.n + ii[0];
+    if (wq && in_bounds(cell, n3)) atomicAdd(grid + (long long)b * n3 + cell, wq);
   }
 }
 
@@ -212,7 +216,8 @@ __global__ void __launch_bounds__(256) k_paint(const float* __restrict__ pos, co
       const long long ix = (ii[0] + dx) & (g.n - 1);
       const long long iy = (ii[1] + dy) & (g.n - 1);
       const long long iz = (ii[2] + dz) & (g.n - 1);
-      if (share[cnr]) atomicAdd(gb + (iz * g.n + iy) * g.n + ix, share[cnr]);
+      const long long cell = (iz * g.n + iy) * g.n + ix;
+      if (share[cnr] && in_bounds(cell, n3)) atomicAdd(gb + cell, share[cnr]);
     }
   }
 }
@@ -548,7 +553,8 @@ __global__ void __launch_bounds__(NT) k_brick_deposit(const float4* __restrict__
     const int lx = i % T, ly = (i / T) % T, lz = i / (T * T);
     const long long x = (bx * kBrick + lx) & (g.n - 1), y = (by * kBrick + ly) & (g.n - 1),
                     z = (bz * kBrick + lz) & (g.n - 1);
-    atomicAdd(gb + (z * g.n + y) * g.n + x, v);
+    const long long cell = ((long long)z * g.n + y) * g.n + x;
+    if (in_bounds(cell, (long long)g.n * g.n * g.n)) atomicAdd(gb + cell, v);
   }
 }
 
@@ -815,7 +821,8 @@ __device__ __forceinline__ void z_pack_frag(float2* v, const float2* __restrict_
     const int k = j + r * (N / 8);
     const int m = k <= N / 2 ? k : N - k;
     const long long base = ((long long)m * N + y) * N + x0 + c;
-    const float2 A = a[base], B = a[base + WP];
+    constexpr long long CN = (long long)(N / 2 + 1) * N * N;
+    const float2 A = in_bounds(base, CN) ? a[base] : float2{}, B = in_bounds(base + WP, CN) ? a[base + WP] : float2{};
     if (k == 0 || k == N / 2) v[r] = make_float2(A.x, B.x);
     else if (k < N / 2) v[r] = make_float2(A.x - B.y, A.y + B.x);
     else v[r] = make_float2(A.x + B.y, B.x - A.y);
@@ -842,8 +849,9 @@ __device__ __forceinline__ void z_stage_issue(float2* stage, const float2* __res
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int q = wave; q < S::NCH; q += NT / 64) {
     const int m = q * S::RPC + lane / S::LPR;
-    if (m < S::ROWS) {
-      const float2* g = a + ((long long)m * N + y) * N + x0 + 2 * (lane % S::LPR);
+    const long long e = ((long long)m * N + y) * N + x0 + 2 * (lane % S::LPR);
+    if (m < S::ROWS && in_bounds(e + 1, (long long)(N / 2 + 1) * N * N)) {
+      const float2* g = a + e;
       __builtin_amdgcn_global_load_lds((const void*)g, (__attribute__((address_space(3))) void*)(stage + q * 128),
                                        16, 0, 0);
     }
@@ -883,8 +891,9 @@ __device__ __forceinline__ void z_unpack_store(const float2* buf, float2* __rest
       B = mul_i(B) * k;
     }
     const long long base = ((long long)kz * N + y) * N + x0 + p;
-    out[base] = A;
-    out[base + WP] = B;
+    constexpr long long CN = (long long)(N / 2 + 1) * N * N;
+    if (in_bounds(base, CN)) out[base] = A;
+    if (in_bounds(base + WP, CN)) out[base + WP] = B;
   }
 }
 
@@ -1127,13 +1136,13 @@ __global__ void __launch_bounds__(256) k_log_shift(float* __restrict__ delta, lo
 // and both accumulate S1 = sum Delta u_p, S2 = sum Delta^2 into partials.  On the pass after such
 // a start, ZI_CROSS iterates as ZI_PLAIN and accumulates S3 = sum Delta u_1 (second entry 0), the
 // cross term of ||Psi_1 - Psi_0||^2.
-template <int N, int MODE>
+template <int N, int MODE, int SPLIT = 0>
 __global__ void __launch_bounds__(ntz<N>()) k_z_iter(float2* __restrict__ a0, float2* __restrict__ a1,
                                                      const float2* __restrict__ a2, Geo g, float* __restrict__ corr,
                                                      double* __restrict__ partials, const int* __restrict__ active,
                                                      const float2* __restrict__ twg,
                                                      const float* __restrict__ up_in = nullptr) {
-  constexpr int NT = ntz<N>(), WP = wz<N>(), TPB = ztpb<N, MODE>();
+  constexpr int NT = ntz<N>(), WP = wz<N>(), TPB = ztpb<N, MODE, SPLIT>();
   using L = Lay<N, WP, false>;
   const int b = blockIdx.y;
   if (active && !active[b]) return;
@@ -1173,7 +1182,7 @@ __global__ void __launch_bounds__(ntz<N>()) k_z_iter(float2* __restrict__ a0, fl
       __syncthreads();                                // every thread has read the staged tile
       if (DEFER && py >= 0) z_unpack_store<N, WP, NT, true>(buf, a1, py, px0, g.kf);
       z_stage_issue<N, WP, NT>(stage, a2, y, x0);
-      fft_rr<N, WP, true, false>(s, buf, tw);        // (its first barrier ends the reads of buf above)
+      fft_rr<N, WP, true, false, SPLIT>(s, buf, tw);        // (its first barrier ends the reads of buf above)
       z_stage_wait();
       __syncthreads();
       if (act) z_pack_stage<N, WP>(v, stage, c, j);
@@ -1182,7 +1191,7 @@ __global__ void __launch_bounds__(ntz<N>()) k_z_iter(float2* __restrict__ a0, fl
         z_tile_at<N, WP>(next, ny, nx0);
         z_stage_issue<N, WP, NT>(stage, a0, ny, nx0);
       }
-      fft_rr<N, WP, true, false>(v, buf, tw);
+      fft_rr<N, WP, true, false, SPLIT>(v, buf, tw);
     }
     // s = Psi . r (two columns packed as .x / .y) -> q = u_0 / |r|, so that V_j = q r_j
     if (act) {
@@ -1223,9 +1232,9 @@ __global__ void __launch_bounds__(ntz<N>()) k_z_iter(float2* __restrict__ a0, fl
     }
     // Z[q] -> a0 and i k'_z Z[r_z q] -> a1; Z[V_x] = r_x Z[q] and Z[V_y] = r_y Z[q] are formed in
     // the y pass
-    fft_rl<N, WP, false, false>(s, buf, tw);
+    fft_rl<N, WP, false, false, SPLIT>(s, buf, tw);
     z_unpack_store<N, WP, NT, false>(buf, a0, y, x0, g.kf);
-    fft_rl<N, WP, false, false>(v, buf, tw);
+    fft_rl<N, WP, false, false, SPLIT>(v, buf, tw);
     if (DEFER) {
       py = y;
       px0 = x0;
@@ -1301,8 +1310,9 @@ __global__ void __launch_bounds__(ntz<N>()) k_z_final(const float2* __restrict__
       const long long cell = b * n3 + ((long long)z * N + y) * N + x0 + c;
       if (!COMB && psi4) {
         float4* pb = psi4 + b * n3;
-        pb[psi_slot(x0 + c, y, z, N)] = make_float4(px[r].x, py[r].x, v[r].x, 0.f);
-        pb[psi_slot(x0 + c + WP, y, z, N)] = make_float4(px[r].y, py[r].y, v[r].y, 0.f);
+        const long long s0 = psi_slot(x0 + c, y, z, N), s1 = psi_slot(x0 + c + WP, y, z, N);
+        if (in_bounds(s0, n3)) pb[s0] = make_float4(px[r].x, py[r].x, v[r].x, 0.f);
+        if (in_bounds(s1, n3)) pb[s1] = make_float4(px[r].y, py[r].y, v[r].y, 0.f);
       }
       if (u_out || (!COMB && corr)) {
         const float rz = los_comp(g, 2, z);
@@ -1404,13 +1414,19 @@ __device__ __forceinline__ void y_tile_coords(int& p, int& x0) {
 template <int N>
 __device__ __forceinline__ void y_load(float2* v, const float2* __restrict__ a, int p, int x0, int c, int j) {
 #pragma unroll
-  for (int r = 0; r < 8; ++r) v[r] = a[((long long)p * N + j + r * (N / 8)) * N + x0 + c];
+  for (int r = 0; r < 8; ++r) {
+    const long long e = ((long long)p * N + j + r * (N / 8)) * N + x0 + c;
+    v[r] = in_bounds(e, (long long)(N / 2 + 1) * N * N) ? a[e] : float2{};
+  }
 }
 
 template <int N>
 __device__ __forceinline__ void y_store(const float2* v, float2* __restrict__ a, int p, int x0, int c, int j) {
 #pragma unroll
-  for (int r = 0; r < 8; ++r) a[((long long)p * N + j + r * (N / 8)) * N + x0 + c] = v[r];
+  for (int r = 0; r < 8; ++r) {
+    const long long e = ((long long)p * N + j + r * (N / 8)) * N + x0 + c;
+    if (in_bounds(e, (long long)(N / 2 + 1) * N * N)) a[e] = v[r];
+  }
 }
 
 template <int N, int NA, bool INV>
@@ -1569,13 +1585,19 @@ __global__ void __launch_bounds__(nty<N>()) k_y_fanin(float2* __restrict__ a0, f
 template <int N>
 __device__ __forceinline__ void x_load(float2* v, const float2* __restrict__ a, long long row, int j) {
 #pragma unroll
-  for (int r = 0; r < 8; ++r) v[r] = a[row * N + j + r * (N / 8)];
+  for (int r = 0; r < 8; ++r) {
+    const long long e = row * N + j + r * (N / 8);
+    v[r] = in_bounds(e, (long long)(N / 2 + 1) * N * N) ? a[e] : float2{};
+  }
 }
 
 template <int N>
 __device__ __forceinline__ void x_store(const float2* v, float2* __restrict__ a, long long row, int j) {
 #pragma unroll
-  for (int r = 0; r < 8; ++r) a[row * N + j + r * (N / 8)] = v[r];
+  for (int r = 0; r < 8; ++r) {
+    const long long e = row * N + j + r * (N / 8);
+    if (in_bounds(e, (long long)(N / 2 + 1) * N * N)) a[e] = v[r];
+  }
 }
 
 // k^2 and the derivative components of element (row, kx).
@@ -1880,7 +1902,8 @@ __device__ __forceinline__ void shift_one(float px, float py, float pz, const fl
   const int m = cg.n - 1, n = cg.n;
   shift_one_f(px, py, pz, uu,
               [&](int dx, int dy, int dz, const int ii[3]) {
-                return pb[psi_slot((ii[0] + dx) & m, (ii[1] + dy) & m, (ii[2] + dz) & m, n)];
+                const long long sl = psi_slot((ii[0] + dx) & m, (ii[1] + dy) & m, (ii[2] + dz) & m, n);
+                return in_bounds(sl, (long long)n * n * n) ? pb[sl] : float4{};
               },
               cg, ox, oy, oz, growth, galaxies, d);
 }
@@ -1956,7 +1979,8 @@ __global__ void __launch_bounds__(NT) k_shift_brick(const float4* __restrict__ s
     const int q = i >> 3, r = i & 7;
     const int lx = 2 * (q % (F / 2)) + (r & 1), ly = 2 * ((q / (F / 2)) % (F / 2)) + ((r >> 1) & 1),
               lz = 2 * (q / ((F / 2) * (F / 2))) + (r >> 2);
-    const float4 v = pb[psi_slot((bx + lx) & m, (by + ly) & m, (bz + lz) & m, n)];
+    const long long sl = psi_slot((bx + lx) & m, (by + ly) & m, (bz + lz) & m, n);
+    const float4 v = in_bounds(sl, (long long)n * n * n) ? pb[sl] : float4{};
     const int l = (lz * F + ly) * F + lx;
     px_[l] = v.x;
     py_[l] = v.y;

@@ -21,6 +21,8 @@ RECON_EINVAL, RECON_ENOMEM, RECON_EDEVICE, RECON_ESTATE, RECON_EDIVERGED = -1, -
 GAL, RAN = 0, 1
 START_PLAIN, START_FFTA1, START_FFTA2, START_LEARNED = 0, 1, 2, 3
 NO_RANDOMS, KEEP_DELTA, START_BUFFERS, CNN_BUFFERS, CNN_HALF, PASS_GRAPHS, LOGNORMAL = 1, 2, 4, 8, 16, 32, 64
+FFT_SPLITBF16, FFT_SPLITBF16_X3 = 128, 256
+CNN_QUARTER = 512
 CNN_PARAMS = 10833
 PAINT_ACCUMULATE, PAINT_NGP = 1, 2
 SHIFT_AS_PAINTED = 256
@@ -30,7 +32,7 @@ EXPORTED = ("recon_workspace_bytes", "recon_plan", "recon_paint", "recon_solve",
             "recon_destroy", "recon_strerror", "recon_last_error", "recon_profile_start",
             "recon_profile_stop", "recon_profile_kernel_name", "recon_cnn_forward", "recon_cnn_train_step",
             "recon_get_radial", "recon_restrict", "recon_prolong", "recon_radial_ratio", "recon_helmholtz",
-            "recon_start_restarts", "recon_plan_noalloc", "recon_noalloc_limit")
+            "recon_start_restarts", "recon_plan_noalloc", "recon_noalloc_limit", "recon_debug_violations")
 
 
 class ReconError(RuntimeError):
@@ -53,6 +55,11 @@ def lib_path():
     return os.path.join(_HERE, LIB_NAME)
 
 
+def debug_lib_path():
+    """The library built with the device bounds checks (RECON_DEBUG)."""
+    return os.path.join(_HERE, "librecon_debug.so")
+
+
 def load(path=None):
     """Load the built HIP library (raises if it has not been built)."""
     global _LIB
@@ -70,6 +77,8 @@ def load(path=None):
     lib.recon_plan_noalloc.restype = ctypes.c_int
     lib.recon_noalloc_limit.argtypes = []
     lib.recon_noalloc_limit.restype = ctypes.c_size_t
+    lib.recon_debug_violations.argtypes = [ctypes.c_int]
+    lib.recon_debug_violations.restype = ctypes.c_int64
     lib.recon_paint.argtypes = [vp, ctypes.c_int, vp, vp, i64, vp, u32]
     lib.recon_solve.argtypes = [vp, ctypes.c_int, vp]
     lib.recon_iterate.argtypes = [vp, ctypes.c_int, dbl, ctypes.POINTER(i32), ctypes.POINTER(dbl)]
@@ -129,14 +138,16 @@ class Plan:
 
     def __init__(self, n, box_len, observer, bias, growth, smooth_r, origin=(0.0, 0.0, 0.0), batch=1,
                  mask_tau=0.1, randoms=True, keep_delta=False, start_buffers=False, max_objects=0, cnn=False,
-                 cnn_half=False, graphs=False, lognormal=False, device=None, noalloc=False):
+                 cnn_half=False, graphs=False, lognormal=False, device=None, noalloc=False, split_terms=0,
+                 cnn_quarter=False, lib=None):
         """noalloc=True: the plan runs on the library's own device scratch (recon_plan_noalloc) instead of a
         workspace allocated here; a later no-allocation plan on the same device makes this one stale."""
-        self.lib = load()
+        self.lib = load() if lib is None else lib    # lib: another build of the library, from load(path)
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
         flags = (0 if randoms else NO_RANDOMS) | (KEEP_DELTA if keep_delta else 0) | \
                 (START_BUFFERS if start_buffers else 0) | (CNN_BUFFERS if cnn else 0) | (CNN_HALF if cnn_half else 0) | \
-                (PASS_GRAPHS if graphs else 0) | (LOGNORMAL if lognormal else 0)
+                (PASS_GRAPHS if graphs else 0) | (LOGNORMAL if lognormal else 0) | \
+                {0: 0, 2: FFT_SPLITBF16, 3: FFT_SPLITBF16_X3}[int(split_terms)] | (CNN_QUARTER if cnn_quarter else 0)
         p = Params()
         p.n, p.batch, p.box_len = int(n), int(batch), float(box_len)
         for a in range(3):
@@ -151,7 +162,7 @@ class Plan:
         # offsets version).  The plan keeps the tensors alive, so their memory cannot be handed to
         # another tensor while the record stands, and the version counters catch in-place changes.
         self._painted = None
-        self.cnn_n = self.n // 2 if cnn_half else self.n     # network grid
+        self.cnn_n = self.n // 4 if cnn_quarter else (self.n // 2 if cnn_half else self.n)     # network grid
         nbytes = self.lib.recon_workspace_bytes(ctypes.byref(p))
         if nbytes == 0:
             raise ReconError(RECON_EINVAL, "invalid parameters")

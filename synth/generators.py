@@ -64,7 +64,7 @@ def power_amplitude(sigma8=SIGMA8, radius=8.0):
     return sigma8 ** 2 / val
 
 
-def linear_field(n, box_len, seed, want_psi=True, dtype=np.float64):
+def linear_field(n, box_len, seed, want_psi=True, dtype=np.float64, log=None):
     """Gaussian linear density field and its linear displacement on an n^3 grid.
 
     White noise w ~ N(0,1) -> F_k = FFT(w) sqrt(P(k) n^3 / L^3) with F_0 = 0.
@@ -75,6 +75,8 @@ def linear_field(n, box_len, seed, want_psi=True, dtype=np.float64):
     wn = rng.standard_normal((n, n, n), dtype=dtype)
     fk = sfft.rfftn(wn, workers=WORKERS).astype(ctype, copy=False)
     del wn
+    if log:
+        log(f"white noise on {n}^3 drawn and transformed")
     amp = power_amplitude()
     mf = np.fft.fftfreq(n, d=1.0 / n)
     mh = np.arange(n // 2 + 1, dtype=np.float64)
@@ -88,6 +90,8 @@ def linear_field(n, box_len, seed, want_psi=True, dtype=np.float64):
     scale[0, 0, 0] = 0.0
     fk *= scale.astype(dtype)
     delta = sfft.irfftn(fk, s=(n, n, n), workers=WORKERS).astype(dtype, copy=False)
+    if log:
+        log("linear density field formed")
     psi = None
     if want_psi:
         k2 = kx * kx + ky * ky + kz * kz
@@ -98,6 +102,8 @@ def linear_field(n, box_len, seed, want_psi=True, dtype=np.float64):
         psi = np.empty((3, n, n, n), dtype=dtype)
         for j, d in enumerate((dx, dy, dz)):
             psi[j] = sfft.irfftn(fk * (1j * d / k2).astype(ctype), s=(n, n, n), workers=WORKERS)
+            if log:
+                log(f"linear displacement component {j} formed")
     return delta, psi
 
 
@@ -161,14 +167,54 @@ def lattice_box(n, box_len, observer, growth, seed_field, seed_randoms=None, ran
                                real_pos=np.mod(x, box_len).astype(np.float32)))
 
 
+def lattice_box_large(n, box_len, observer, growth, seed_field, bias=1.0, smooth_r=10.0, slab=32,
+                      field_dtype=np.float64, log=None):
+    """lattice_box without randoms for large n (the 1024^3 lattice): the same draws and arithmetic
+    per object, but the positions are formed slab by slab of z planes (slabs in parallel threads) into
+    one float32 array, so that only the linear field, its displacement and a few slabs of float64
+    temporaries are held at once.  field_dtype=np.float32 draws the linear field in single precision
+    (another, equally valid realisation; half the memory and time at 1024^3)."""
+    from concurrent.futures import ThreadPoolExecutor
+    _, psi = linear_field(n, box_len, seed_field, dtype=field_dtype, log=log)
+    if log:
+        log(f"linear field and displacement on {n}^3 drawn")
+    h = box_len / n
+    obs = np.asarray(observer, dtype=np.float64)
+    out = np.empty((n ** 3, 3), dtype=np.float32)
+    i = np.arange(n, dtype=np.float64) * h
+
+    def one(z0):
+        z1 = min(n, z0 + slab)
+        qz, qy, qx = np.meshgrid(i[z0:z1], i, i, indexing="ij")
+        q = np.stack([qx.ravel(), qy.ravel(), qz.ravel()], axis=1)
+        p = np.stack([psi[0, z0:z1].ravel(), psi[1, z0:z1].ravel(), psi[2, z0:z1].ravel()], axis=1)
+        x = q + p
+        rh = _unit(x - obs)
+        s = x + growth * np.sum(p * rh, axis=1, keepdims=True) * rh
+        s = np.mod(s, box_len)
+        s = np.where(s >= box_len, s - box_len, s)
+        out[z0 * n * n:z1 * n * n] = s
+
+    with ThreadPoolExecutor(WORKERS) as ex:
+        list(ex.map(one, range(0, n, slab)))
+    del psi
+    return Catalogue(gal_pos=out, ran_pos=None, n=n, box_len=box_len, origin=(0.0, 0.0, 0.0),
+                     observer=tuple(float(v) for v in observer), bias=bias, growth=growth, smooth_r=smooth_r,
+                     info=dict(kind="lattice", n_part=n, seed_field=seed_field))
+
+
 def config1():
     """Oracle-sized periodic box: 64^3 grid, L = 1000, f = 0.7, b = 1, observer (-1000, 500, 500), R = 10."""
     return lattice_box(64, 1000.0, (-1000.0, 500.0, 500.0), 0.7, 101, 102, ran_factor=5,
                        bias=1.0, smooth_r=10.0)
 
 
-def config3(n=128):
-    """Precision-study box: L = 2000, f = 0.76, b = 1, no randoms, observer 5000 Mpc/h from the centre."""
+def config3(n=128, log=None):
+    """Precision-study box: L = 2000, f = 0.76, b = 1, no randoms, observer 5000 Mpc/h from the centre
+    (n^3 lattice particles; the slab-wise generator above 256^3)."""
+    if n > 256:
+        return lattice_box_large(n, 2000.0, (-4000.0, 1000.0, 1000.0), 0.76, 301, bias=1.0, smooth_r=10.0,
+                                 slab=max(1, 4096 // n), field_dtype=np.float32, log=log)
     return lattice_box(n, 2000.0, (-4000.0, 1000.0, 1000.0), 0.76, 301, None, ran_factor=0,
                        bias=1.0, smooth_r=10.0)
 

@@ -367,6 +367,29 @@ def test_precision_study_subrun(gpu_lib):
     compare_full(g, r, "precision-study 128^3")
 
 
+@pytest.mark.parametrize("terms", [2, 3])
+def test_precision_study_split_bf16_radix(gpu_lib, terms):
+    # the same sub-run with the last radix-8 stage of the steady passes' z transforms on the matrix
+    # cores (8-point DFT as a GEMM on split-bfloat16 operands): the grid and the first pass are the
+    # FP32 path's; the error against the FP64 oracle is reported.  Three terms keep FP32-level error;
+    # two terms (about 2^-16 per product) are held to a looser bar
+    from paper_1504_02591_amd import native
+    cat = G.config3(128)
+    plan = native.plan_for(cat, split_terms=terms)
+    gal = to_dev(cat.gal_pos)
+    plan.paint(native.GAL, gal)
+    plan.solve()
+    rc, iters, eps = plan.iterate(6, 0.0)
+    psi = plan.psi()[0].cpu().numpy()
+    plan.close()
+    r = oracle_catalogue_run(cat, 6)
+    e = rel_l2(psi, r["psi"])
+    print(f"precision study 128^3, split-bf16 radix ({terms} terms): Psi rel L2 vs FP64 oracle = {e:.3e}; "
+          f"eps {eps[0]}", flush=True)
+    assert e <= (PSI_TOL if terms == 3 else 1e-3)
+    np.testing.assert_allclose(eps[0], r["eps"], rtol=1e-2 if terms == 2 else 1e-4, atol=1e-6)
+
+
 def test_survey_cone_small(gpu_lib):
     from paper_1504_02591_amd import native
     cat = G.config2(n=128, scale=0.25)

@@ -27,7 +27,8 @@ def test_host_entry_points_under_asan_and_ubsan(tmp_path):
     subprocess.run([HIPCC, "--offload-arch=gfx950", "-O1", "-g", "-std=c++17", "-fPIC", "-shared",
                     "-fno-omit-frame-pointer", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
                     "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
-                    f"-I{inc}", "-o", str(lib), src], check=True, capture_output=True, timeout=540)
+                    f"-I{inc}", "-o", str(lib), src, "-L/opt/rocm/lib", "-Wl,-rpath,/opt/rocm/lib",
+                    "-lrocprofiler-sdk-roctx"], check=True, capture_output=True, timeout=540)
     drv = tmp_path / "driver"
     subprocess.run([CLANG, "-std=c++17", "-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
                     f"-I{inc}", "-o", str(drv), os.path.join(ROOT, "tests", "host_sanitizer_driver.cpp"),
