@@ -221,10 +221,22 @@ def prolong(c):
 
 
 def half_grid_correction(theta, delta, u_p, rhat_coarse, bf16_mode=False, conv_fn=conv):
-    """Delta u on the fine grid when the network runs on the (n/2)^3 grid: restrict delta_s and
-    u_p, evaluate the network there (r_hat of the coarse nodes), prolong y / S_U."""
-    y, _ = forward(theta, restrict(delta), restrict(u_p), rhat_coarse, bf16_mode, conv_fn)
-    return prolong(y / S_U)
+    """Delta u on the fine grid when the network runs on the (n/2)^3 grid (one level)."""
+    return coarse_grid_correction(theta, delta, u_p, rhat_coarse, 1, bf16_mode, conv_fn)
+
+
+def coarse_grid_correction(theta, delta, u_p, rhat_coarse, levels, bf16_mode=False, conv_fn=conv):
+    """Delta u on the fine grid when the network runs on the (n/2^levels)^3 grid: restrict delta_s and
+    u_p levels times, evaluate the network there (r_hat of the coarse nodes), prolong y / S_U levels
+    times."""
+    d, u = delta, u_p
+    for _ in range(levels):
+        d, u = restrict(d), restrict(u)
+    y, _ = forward(theta, d, u, rhat_coarse, bf16_mode, conv_fn)
+    out = y / S_U
+    for _ in range(levels):
+        out = prolong(out)
+    return out
 
 
 def adam_step(theta, m, v, grad, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):

@@ -10,7 +10,8 @@ By default the network runs on the (n/2)^3 grid (RECON_CNN_HALF): training
 realisations are survey-like catalogues of the 512^3 workload's geometry, solved
 at 512^3, and delta_s, u_p and the target are restricted to the 256^3 network
 grid; inference restricts the 512^3 inputs the same way and prolongs Delta u.
-With --fine the network runs on the solver grid itself.  Every realisation (galaxies
+--levels 2 puts it on the (n/4)^3 grid (RECON_CNN_QUARTER, restricted twice),
+--levels 0 on the solver grid itself.  Every realisation (galaxies
 only) shares one random catalogue, as a survey's realisations share its randoms.  Test
 realisations use other seeds.
 
@@ -71,10 +72,19 @@ def catalogue_pool(workers, threads=None):
     return mp.get_context("fork").Pool(workers, initializer=_init_worker, initargs=(t,))
 
 
+def _levels(half):
+    """Coarsening levels of the network grid (True: 1, False: 0, or the level count itself)."""
+    return int(half) if isinstance(half, bool) else int(half)
+
+
+def _plan_flags(levels):
+    return dict(cnn_half=levels == 1, cnn_quarter=levels == 2)
+
+
 def targets(cat, ran, half=True, tol=1e-6, max_iter=200):
     """(delta_s, u_p, Delta u*, passes) for one galaxy catalogue and the shared randoms (device
-    tensor) on the network grid, from the plain start iterated to tol on the GPU; with half=True
-    the fields are restricted to the (n/2)^3 grid."""
+    tensor) on the network grid, from the plain start iterated to tol on the GPU; the fields are
+    restricted half (True = 1, or a level count) times."""
     dev = torch.device("cuda", torch.cuda.current_device())
     plan = native.plan_for(cat, keep_delta=True, max_objects=max(cat.gal_pos.shape[0], ran.shape[0]))
     gal = torch.from_numpy(cat.gal_pos).to(dev)
@@ -87,8 +97,13 @@ def targets(cat, ran, half=True, tol=1e-6, max_iter=200):
     rc, iters, eps = plan.iterate(max_iter, tol)
     u_inf = plan.radial()
     delta = plan.delta()
-    if half:
-        delta, u_p, u_inf = plan.restrict(delta), plan.restrict(u_p), plan.restrict(u_inf)
+    levels = _levels(half)
+    for lv in range(levels):
+        rp = plan if lv == 0 else native.Plan(cat.n >> lv, cat.box_len, cat.observer, cat.bias, cat.growth,
+                                              cat.smooth_r, origin=cat.origin, randoms=False)
+        delta, u_p, u_inf = rp.restrict(delta), rp.restrict(u_p), rp.restrict(u_inf)
+        if lv > 0:
+            rp.close()
     plan.close()
     return delta[0].clone(), u_p[0].clone(), (u_inf - u_p)[0].clone(), iters[0]
 
@@ -105,37 +120,61 @@ def init_params(seed=0):
     return th.astype(np.float32)
 
 
-def train(data, geom, steps, lr, seed=0, log_every=50, params=None, state=None, half=True):
-    """Adam on single realisations drawn at random; cosine learning-rate decay.  Returns (params, state, log)."""
+def train(data, geom, steps, lr, seed=0, log_every=50, params=None, state=None, half=True, total=None):
+    """Adam on single realisations drawn at random; cosine learning-rate decay over `total` steps (default:
+    this call's steps).  Returns (params, state, log).
+
+    The realisation of step s is drawn from a generator seeded by (seed, s) and the rate is a function of s
+    and total, so a run resumed from its saved state (params, Adam moments, step count, total) continues
+    exactly as an uninterrupted run would: the same parameters bit for bit."""
     dev = torch.device("cuda", torch.cuda.current_device())
     m = data[0][0].shape[-1]
-    plan = native.Plan(2 * m if half else m, geom["box_len"], geom["observer"], geom["bias"], geom["growth"],
-                       geom["smooth_r"], origin=geom["origin"], randoms=False, cnn=True, cnn_half=half)
+    levels = _levels(half)
+    plan = native.Plan(m << levels, geom["box_len"], geom["observer"], geom["bias"], geom["growth"],
+                       geom["smooth_r"], origin=geom["origin"], randoms=False, cnn=True, **_plan_flags(levels))
     th = torch.from_numpy(init_params(seed) if params is None else params).to(dev)
     m = torch.zeros_like(th) if state is None else torch.from_numpy(state["m"]).to(dev)
     v = torch.zeros_like(th) if state is None else torch.from_numpy(state["v"]).to(dev)
     step0 = 0 if state is None else int(state["step"])
-    rng = np.random.default_rng(seed + 1000 + step0)
+    if total is None:
+        total = int(state["total"]) if state is not None and "total" in state else step0 + steps
     log = []
     for s in range(step0 + 1, step0 + steps + 1):
-        k = int(rng.integers(len(data)))
+        k = int(np.random.default_rng([seed, s]).integers(len(data)))
         d, u, t = data[k][:3]
-        frac = (s - step0 - 1) / max(steps - 1, 1)
+        frac = min((s - 1) / max(total - 1, 1), 1.0)
         rate = lr * 0.5 * (1.0 + np.cos(np.pi * frac))
         loss = plan.cnn_train_step(th, m, v, s, rate, d, u, t)
         if s % log_every == 0 or s == step0 + 1:
             log.append((s, loss))
             print(f"[train] step {s} loss {loss:.5e} lr {rate:.2e}", flush=True)
     plan.close()
-    state = {"m": m.cpu().numpy(), "v": v.cpu().numpy(), "step": step0 + steps}
+    state = {"m": m.cpu().numpy(), "v": v.cpu().numpy(), "step": step0 + steps, "total": total}
     return th.cpu().numpy(), state, log
+
+
+def save_checkpoint(path, params, state, seed, **extra):
+    """Parameters, Adam moments, step count, schedule length and seed in one .npz (no pickled objects)."""
+    np.savez(path, params=params, adam_m=state["m"], adam_v=state["v"], step=state["step"], total=state["total"],
+             seed=seed, **extra)
+
+
+def load_checkpoint(path):
+    """(params, state, seed) from save_checkpoint's file; train(..., params=params, state=state, seed=seed)
+    continues the run."""
+    with np.load(path, allow_pickle=False) as z:
+        state = {"m": z["adam_m"].copy(), "v": z["adam_v"].copy(), "step": int(z["step"])}
+        if "total" in z.files:
+            state["total"] = int(z["total"])
+        return z["params"].copy(), state, int(z["seed"])
 
 
 def passes_to_tol(cat, ran, start, params=None, tol=1e-3, max_iter=60, half=True):
     dev = torch.device("cuda", torch.cuda.current_device())
     lrn = start == native.START_LEARNED
+    levels = _levels(half) if lrn else 0
     plan = native.plan_for(cat, keep_delta=lrn, start_buffers=start != native.START_PLAIN, cnn=lrn,
-                           cnn_half=lrn and half, max_objects=max(cat.gal_pos.shape[0], ran.shape[0]))
+                           max_objects=max(cat.gal_pos.shape[0], ran.shape[0]), **_plan_flags(levels))
     gal = torch.from_numpy(cat.gal_pos).to(dev)
     plan.paint(native.GAL, gal)
     plan.paint(native.RAN, ran)
@@ -153,12 +192,13 @@ def main():
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--n", type=int, default=512, help="solver grid of the realisations")
     ap.add_argument("--gen-n", type=int, default=256, help="grid of the training realisations' linear fields")
-    ap.add_argument("--fine", action="store_true", help="network on the solver grid instead of (n/2)^3")
+    ap.add_argument("--levels", type=int, default=1, choices=(0, 1, 2),
+                    help="network grid n / 2^levels (0: the solver grid, 1: (n/2)^3, 2: (n/4)^3)")
     ap.add_argument("--workers", type=int, default=16, help="catalogue generation processes")
     ap.add_argument("--out", default=WEIGHTS)
     ap.add_argument("--seed", type=int, default=0)
     args = ap.parse_args()
-    half = not args.fine
+    half = args.levels
     pool = catalogue_pool(args.workers)          # forked before the GPU is initialised
     t0 = time.time()
     # held-out realisations are drawn like the benchmark's (field on the solver grid), in the background
@@ -194,9 +234,9 @@ def main():
         res["learned"].append(passes_to_tol(c, ran, native.START_LEARNED, params, half=half)[0])
     print("[train] held-out passes to 1e-3:", json.dumps(res), flush=True)
     os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
-    np.savez(args.out, params=params, adam_m=state["m"], adam_v=state["v"], step=state["step"],
-             loss=np.array(log, dtype=np.float64), seed=args.seed, train=args.train, n=args.n, half=half,
-             eval=json.dumps(res))
+    save_checkpoint(args.out, params, state, args.seed,
+                    loss=np.array(log, dtype=np.float64), train=args.train, n=args.n, half=half == 1, levels=half,
+                    eval=json.dumps(res))
     print(json.dumps({"out": args.out, "train_seconds": t_train, "final_loss": log[-1][1], "eval": res}), flush=True)
 
 

@@ -209,13 +209,16 @@ def test_restrict_and_prolong_match_oracle(gpu_lib, n):
         np.testing.assert_allclose(pc[i], C.prolong(c[i]), rtol=0, atol=1e-6)
 
 
-@pytest.mark.parametrize("n", [32, 64])
-def test_learned_start_half_grid_end_to_end(gpu_lib, n):
+@pytest.mark.parametrize("n,levels", [(32, 1), (64, 1), (64, 2), (128, 2)])
+def test_learned_start_coarse_grid_end_to_end(gpu_lib, n, levels):
+    # network on the (n/2)^3 (RECON_CNN_HALF) or (n/4)^3 (RECON_CNN_QUARTER) grid: inputs restricted,
+    # output prolonged, level by level
     from paper_1504_02591_amd import native
     cat = G.lattice_box(n, 500.0, (-500.0, 250.0, 250.0), 0.7, 23, 24, ran_factor=3, bias=1.2, smooth_r=20.0)
     th = params(9)
     th[:] = 0.5 * th + 0.5 * ffta2_weights(cat.growth, cat.bias).astype(np.float32)
-    plan = native.plan_for(cat, keep_delta=True, start_buffers=True, cnn=True, cnn_half=True)
+    plan = native.plan_for(cat, keep_delta=True, start_buffers=True, cnn=True, cnn_half=levels == 1,
+                           cnn_quarter=levels == 2)
     gal, ran = to_dev(cat.gal_pos), to_dev(cat.ran_pos)
     plan.paint(native.GAL, gal)
     plan.paint(native.RAN, ran)
@@ -227,14 +230,16 @@ def test_learned_start_half_grid_end_to_end(gpu_lib, n):
     grid_r = O.paint(cat.ran_pos, None, cat.n, cat.box_len, cat.origin)
     delta = O.overdensity(grid_g, grid_r, cat.box_len, cat.smooth_r, cat.mask_tau)
     rhat = O.line_of_sight(cat.n, cat.box_len, cat.origin, cat.observer)
-    rhat_c = O.line_of_sight(cat.n // 2, cat.box_len, cat.origin, cat.observer)
+    rhat_c = O.line_of_sight(cat.n >> levels, cat.box_len, cat.origin, cat.observer)
     plain = O.reconstruct_field(delta, cat.box_len, cat.origin, cat.observer, cat.bias, cat.growth, n_passes=0)
     u_p = np.sum(plain["psi"] * rhat, axis=0)
-    du = C.half_grid_correction(th.astype(np.float64), delta, u_p, rhat_c, bf16_mode=True)
+    du = C.coarse_grid_correction(th.astype(np.float64), delta, u_p, rhat_c, levels, bf16_mode=True,
+                                  conv_fn=C.conv_loops)
     ref = O.reconstruct_field(delta, cat.box_len, cat.origin, cat.observer, cat.bias, cat.growth,
                               n_passes=2, start=O.START_LEARNED, start_correction=du)
     e = rel_l2(psi, ref["psi"])
-    print(f"n={n} half-grid learned start: psi rel L2 {e:.2e}, eps {eps[0]} vs {ref['eps']}", flush=True)
+    print(f"n={n} network grid {n >> levels}^3: learned start psi rel L2 {e:.2e}, eps {eps[0]} vs {ref['eps']}",
+          flush=True)
     assert e < 1e-4
     np.testing.assert_allclose(eps[0], ref["eps"], rtol=1e-3, atol=1e-5)
 
@@ -317,3 +322,27 @@ def test_rejected_learned_start_in_fixed_pass_call(gpu_lib):
     plain.close()
     assert rel_l2(p0, q0) < 1e-6 and rel_l2(p3, q3) < 1e-6
     np.testing.assert_allclose(eps[0], eps_q[0], rtol=1e-4, atol=1e-7)
+
+
+def test_training_resumes_bit_identically(gpu_lib, tmp_path):
+    # a run stopped after half its steps, saved (parameters, Adam moments, step, schedule length, seed)
+    # and resumed from the file ends on the same parameters and moments, bit for bit, as an
+    # uninterrupted run of all the steps
+    from paper_1504_02591_amd import learned
+    geom = dict(box_len=300.0, observer=(150.0, 150.0, 150.0), bias=2.0, growth=0.7, smooth_r=0.0,
+                origin=(0.0, 0.0, 0.0))
+    data = []
+    for i in range(3):
+        delta, u_p, target, _ = sample(32, 80 + i, 300.0, geom["observer"])
+        data.append((to_dev(delta), to_dev(u_p), to_dev(target)))
+    p_full, s_full, _ = learned.train(data, geom, 12, 3e-3, seed=5, half=0, log_every=100)
+    p_a, s_a, _ = learned.train(data, geom, 6, 3e-3, seed=5, half=0, total=12, log_every=100)
+    path = str(tmp_path / "checkpoint.npz")
+    learned.save_checkpoint(path, p_a, s_a, 5)
+    params, state, seed = learned.load_checkpoint(path)
+    assert state["step"] == 6 and state["total"] == 12 and seed == 5
+    p_b, s_b, _ = learned.train(data, geom, 6, 3e-3, seed=seed, half=0, params=params, state=state, log_every=100)
+    assert np.array_equal(p_b, p_full)
+    assert np.array_equal(s_b["m"], s_full["m"]) and np.array_equal(s_b["v"], s_full["v"])
+    assert s_b["step"] == s_full["step"] == 12
+    assert not np.array_equal(p_a, p_full)

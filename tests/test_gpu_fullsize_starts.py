@@ -65,16 +65,17 @@ def oracle_base():
 def weights():
     from paper_1504_02591_amd import learned
     with np.load(learned.WEIGHTS, allow_pickle=False) as z:
-        return np.ascontiguousarray(z["params"], dtype=np.float32), bool(z["half"])
+        levels = int(z["levels"]) if "levels" in z.files else (1 if bool(z["half"]) else 0)
+        return np.ascontiguousarray(z["params"], dtype=np.float32), levels
 
 
-def gpu_run(native, cat, start, chunks, net=None, half=True):
+def gpu_run(native, cat, start, chunks, net=None, levels=1):
     """The benchmark's plan; passes in chunks (one iterate call each), Psi after every chunk, then the
     shift of both catalogues and the deposit grids."""
     dev = torch.device("cuda", 0)
     lrn = start == native.START_LEARNED
     plan = native.plan_for(cat, keep_delta=lrn, start_buffers=start != native.START_PLAIN, cnn=lrn,
-                           cnn_half=lrn and half, graphs=True)
+                           cnn_half=lrn and levels == 1, cnn_quarter=lrn and levels == 2, graphs=True)
     gal = torch.from_numpy(cat.gal_pos).to(dev)
     ran = torch.from_numpy(cat.ran_pos).to(dev)
     plan.paint(native.GAL, gal)
@@ -110,19 +111,20 @@ def check_shifts(g, psi_ref, cat, label):
 def test_learned_start_512_benchmark_configuration(gpu_lib):
     from paper_1504_02591_amd import native
     cat = survey()
-    net, half = weights()
-    assert half, "the committed network runs on the half grid"
-    g = gpu_run(native, cat, native.START_LEARNED, (2, 3), net)
+    net, levels = weights()
+    assert levels >= 1, "the committed network runs on a coarser grid than the solver's"
+    g = gpu_run(native, cat, native.START_LEARNED, (2, 3), net, levels)
     log(f"GPU learned start: eps {g['eps']}, restarts {g['restarts']}")
     assert g["restarts"] == 0
     grid_g, grid_r, delta, rhat, u_p = oracle_base()
     assert np.array_equal(g["grid_g"], grid_g), "galaxy grid not bit-exact"
     assert np.array_equal(g["grid_r"], grid_r), "random grid not bit-exact"
     t0 = time.perf_counter()
-    rhat_c = O.line_of_sight(cat.n // 2, cat.box_len, cat.origin, cat.observer)
-    du = C.half_grid_correction(net.astype(np.float64), delta, u_p, rhat_c, bf16_mode=True, conv_fn=C.conv_loops)
+    rhat_c = O.line_of_sight(cat.n >> levels, cat.box_len, cat.origin, cat.observer)
+    du = C.coarse_grid_correction(net.astype(np.float64), delta, u_p, rhat_c, levels, bf16_mode=True,
+                                  conv_fn=C.conv_loops)
     del rhat_c
-    log(f"oracle network on the 256^3 grid: {time.perf_counter() - t0:.1f}s")
+    log(f"oracle network on the {cat.n >> levels}^3 grid: {time.perf_counter() - t0:.1f}s")
     t0 = time.perf_counter()
     ref = O.reconstruct_field(delta, cat.box_len, cat.origin, cat.observer, cat.bias, cat.growth, n_passes=5,
                               start=O.START_LEARNED, start_correction=du, rhat=rhat, keep=(2,))
@@ -161,7 +163,7 @@ def test_trained_network_saves_passes_on_held_out_realisation(gpu_lib):
     i = 1          # held-out set: seeds 60000 + 3 i .. (training used 50000 + 3 i ..)
     base = learned.TEST_SEED
     cat = G.config2(seeds=(base + 3 * i, base + 3 * i + 1, base + 3 * i + 2))
-    net, half = weights()
+    net, levels = weights()
     dev = torch.device("cuda", 0)
     gal = torch.from_numpy(cat.gal_pos).to(dev)
     ran = torch.from_numpy(cat.ran_pos).to(dev)
@@ -170,7 +172,7 @@ def test_trained_network_saves_passes_on_held_out_realisation(gpu_lib):
                         ("learned", native.START_LEARNED)):
         lrn = start == native.START_LEARNED
         plan = native.plan_for(cat, keep_delta=lrn, start_buffers=start != native.START_PLAIN, cnn=lrn,
-                               cnn_half=lrn and half, graphs=True)
+                               cnn_half=lrn and levels == 1, cnn_quarter=lrn and levels == 2, graphs=True)
         netd = torch.from_numpy(net).to(dev) if lrn else None
         times = []
         for _ in range(3):
