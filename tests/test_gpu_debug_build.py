@@ -54,6 +54,8 @@ def test_debug_build_finds_no_out_of_bounds_index(gpu_lib):
             if a.dtype == np.int64:
                 assert np.array_equal(a, b), k
             else:
-                np.testing.assert_allclose(a, b, rtol=1e-5, atol=1e-6, err_msg=str(k))
+                # the checks change the compiled code around the transforms, so FP32 contractions may differ
+                e = np.linalg.norm(a.astype(np.float64) - b) / max(np.linalg.norm(b.astype(np.float64)), 1e-30)
+                assert e < 1e-6, (k, e)
         print(f"debug build n={cat.n} start {start}: no out-of-bounds index; results as the release build",
               flush=True)

@@ -3,9 +3,9 @@
 Survey-like catalogue on the 512^3 grid over 3500 Mpc/h (observer at the centre, 2.5 sr cone shell
 1100-1800 Mpc/h, about 7e5 galaxies and 3.5e7 randoms, b = 2, f = 0.74, R = 15) in the plan
 configuration the benchmark times: brick-binned deposit, steady-state pass replayed as a HIP graph,
-start buffers, and for the learned start the committed network parameters evaluated on the 256^3
-network grid (two-field slab restriction, BF16 MFMA layers, prolongation), followed by the learned
-start pass and the pass that finishes its eps_1.  Fixed pass counts, against the oracle's plain FP64
+start buffers, and for the learned start the committed network parameters evaluated on their
+network grid (128^3 for the committed quarter-grid network: two-field slab restrictions, BF16 MFMA
+layers, prolongations), followed by the learned start pass and the pass that finishes its eps_1.  Fixed pass counts, against the oracle's plain FP64
 definition of every step (the network with the same bf16 roundings as the kernels).
 
 The gain test runs a held-out realisation (seeds of the network's held-out set, never trained on)
