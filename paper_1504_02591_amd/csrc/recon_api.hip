@@ -82,8 +82,9 @@ bool valid_params(const recon_params_t* p, std::string* why) {
 }
 
 long long max_partial_blocks(int n) {
-  // blocks of the reducing launches: x passes hold RECON_TILE_X rows, z passes >= 2 columns
-  long long xb = (long long)(n / 2 + 1) * n / RECON_TILE_X;
+  // blocks of the reducing launches: x passes hold tile_x rows (per size), z passes >= 2 columns
+  const int tx = n == 256 ? RECON_TILE_X_256 : (n == 1024 ? RECON_TILE_X_1024 : RECON_TILE_X);
+  long long xb = (long long)(n / 2 + 1) * n / tx;
   long long zb = (long long)n * n / 2;
   return xb > zb ? xb : zb;
 }
@@ -599,6 +600,8 @@ struct SizeOps {
       else if (N >= 64 && (pl->p.flags & RECON_FFT_SPLITBF16_X3))
         k_z_iter<N, ZI_PLAIN, N >= 64 ? 3 : 0><<<gzi<ZI_PLAIN, N >= 64 ? 3 : 0>(pl), dim3(TZ), 0, s>>>(
             pl->w0, pl->w1, pl->w2, pl->geo, nullptr, nullptr, act, pl->tw);
+      else if constexpr (N == 512 && RECON_Z_WAVE)
+        k_z_iter_w<N><<<gzi<ZI_PLAIN>(pl), dim3(1024), 0, s>>>(pl->w0, pl->w1, pl->w2, pl->geo, act, pl->tw);
       else
         k_z_iter<N, ZI_PLAIN><<<gzi<ZI_PLAIN>(pl), dim3(TZ), 0, s>>>(pl->w0, pl->w1, pl->w2, pl->geo, nullptr,
                                                                 nullptr, act, pl->tw);

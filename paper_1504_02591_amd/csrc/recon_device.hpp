@@ -414,6 +414,74 @@ __device__ __forceinline__ void fft_rl(float2* v, float2* buf, const float2* tw)
   }
 }
 
+// ---------------------------------------------------------------------------
+// Wave-local transforms of length 512: one column per wave, lane j owning rows j + 64 r (one radix-8
+// fragment), exchanging through the wave's own LDS region (row i at i + i/8, one pad slot per 8 rows),
+// so that no block barrier is needed inside a transform and the waves of a block drift freely between
+// the block's staging barriers.  Three radix-8 Stockham passes: registers -> LDS, LDS -> LDS, and
+// LDS -> registers (wfft_rr) or LDS -> LDS in natural order (wfft_rl).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+__device__ __forceinline__ int wat(int i) { return i + (i >> 3); }
+
+template <bool INV>
+__device__ __forceinline__ void wfft_first(float2* v, float2* reg, int j) {
+  dft8<INV>(v);
+#pragma unroll
+  for (int r = 0; r < 8; ++r) reg[wat(8 * j + r)] = v[r];
+  wave_sync();
+}
+
+template <int NS, bool INV>
+__device__ __forceinline__ void wfft_mid(float2* reg, const float2* tw, int j) {
+  constexpr int N = 512;
+  float2 v[8];
+#pragma unroll
+  for (int r = 0; r < 8; ++r) v[r] = reg[wat(j + r * (N / 8))];
+  wave_sync();                                        // every lane has read before any lane writes
+  const int k = j % NS;
+#pragma unroll
+  for (int r = 1; r < 8; ++r) {
+    float2 w = tw[r * k * (N / (NS * 8))];
+    if (INV) w.y = -w.y;
+    v[r] = cmul(v[r], w);
+  }
+  dft8<INV>(v);
+  const int idx = (j / NS) * NS * 8 + k;
+#pragma unroll
+  for (int r = 0; r < 8; ++r) reg[wat(idx + r * NS)] = v[r];
+  wave_sync();
+}
+
+// register fragment in and out (rows j + 64 r); the region is free again when it returns
+template <bool INV>
+__device__ __forceinline__ void wfft_rr(float2* v, float2* reg, const float2* tw, int j) {
+  wfft_first<INV>(v, reg, j);
+  wfft_mid<8, INV>(reg, tw, j);
+#pragma unroll
+  for (int r = 0; r < 8; ++r) v[r] = reg[wat(j + r * 64)];
+#pragma unroll
+  for (int r = 1; r < 8; ++r) {
+    float2 w = tw[r * j];
+    if (INV) w.y = -w.y;
+    v[r] = cmul(v[r], w);
+  }
+  dft8<INV>(v);
+  wave_sync();                                        // the region's reads are done
+}
+
+// register fragment in, natural order in the region out
+template <bool INV>
+__device__ __forceinline__ void wfft_rl(float2* v, float2* reg, const float2* tw, int j) {
+  wfft_first<INV>(v, reg, j);
+  wfft_mid<8, INV>(reg, tw, j);
+  wfft_mid<64, INV>(reg, tw, j);
+}
+
 template <int N, int NT>
 __device__ __forceinline__ void stage_twiddles(float2* tw_lds, const float2* __restrict__ tw) {
   for (int i = threadIdx.x; i < N; i += NT) tw_lds[i] = tw[i];

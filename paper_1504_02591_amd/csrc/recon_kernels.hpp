@@ -58,15 +58,26 @@ __device__ __forceinline__ long long psi_slot(long long c, int n) {
 // Tile shapes (compile-time tuning knobs from recon_tuning.h): packed z columns, y-pass columns,
 // x-pass rows.  Each block runs one radix-8 fragment per thread, (N/8) * tile threads.
 constexpr int cmin(int a, int b) { return a < b ? a : b; }
-template <int N> constexpr int wz() { return N >= 1024 ? 8 : cmin(N / 2, RECON_TILE_Z); }
-template <int N> constexpr int wy() { return N >= 1024 ? 8 : cmin(N, RECON_TILE_Y); }
-template <int N> constexpr int wx() { return RECON_TILE_X; }
+// Knobs per grid size: the 256^3 and 1024^3 values are tuned on their own (recon_tuning.h), every
+// other size takes the general value.
+template <int N> constexpr int tile_z() { return N == 256 ? RECON_TILE_Z_256 : RECON_TILE_Z; }
+template <int N> constexpr int tile_y() { return N == 256 ? RECON_TILE_Y_256 : RECON_TILE_Y; }
+template <int N> constexpr int tile_x() {
+  return N == 256 ? RECON_TILE_X_256 : (N == 1024 ? RECON_TILE_X_1024 : RECON_TILE_X);
+}
+template <int N> constexpr int z_tpb() {
+  return N == 256 ? RECON_Z_TPB_256 : (N == 1024 ? RECON_Z_TPB_1024 : RECON_Z_TPB);
+}
+// (1024-point columns need 8-column tiles to fit the LDS)
+template <int N> constexpr int wz() { return N >= 1024 ? 8 : cmin(N / 2, tile_z<N>()); }
+template <int N> constexpr int wy() { return N >= 1024 ? 8 : cmin(N, tile_y<N>()); }
+template <int N> constexpr int wx() { return tile_x<N>(); }
 // z tiles (one y row, 2 wz consecutive x) and tiles per block of the z iteration
 template <int N> constexpr int ztiles() { return N * (N / (2 * wz<N>())); }
 // (the start and cross modes and the matrix-core radix variants, which hold more live state, take one
 // tile per block)
 template <int N, int MODE, int SPLIT = 0> constexpr int ztpb() {
-  return MODE == ZI_PLAIN && SPLIT == 0 ? cmin(RECON_Z_TPB, ztiles<N>()) : 1;
+  return MODE == ZI_PLAIN && SPLIT == 0 ? cmin(z_tpb<N>(), ztiles<N>()) : 1;
 }
 
 
@@ -1252,6 +1263,142 @@ __global__ void __launch_bounds__(ntz<N>()) k_z_iter(float2* __restrict__ a0, fl
       partials[2 * (b * nb + blockIdx.x) + 0] = t1;
       partials[2 * (b * nb + blockIdx.x) + 1] = t2;
     }
+  }
+}
+
+// The plain z iteration of k_z_iter with wave-local transforms (N = 512): the wave of packed column
+// c transforms that column in its own LDS region, so the only block barriers of a tile are those
+// of the staging and of the stores (7 per tile instead of about 22).  The staged tile is skewed: row
+// m's 16-byte piece p sits in slot (p - m) mod 16 of the row, so that a wave reading one column down
+// 64 consecutive rows spreads over every bank; the per-wave regions are 577 float2 apart, so that the
+// stores, which read one row of 16 columns at a time, do too.
+template <int N, int WP>
+__device__ __forceinline__ void z_stage_issue_skew(float2* stage, const float2* __restrict__ a, int y, int x0) {
+  using S = ZStage<N, WP>;
+  static_assert(S::LPR == 16, "skewed staging takes rows of 16 pieces");
+  constexpr int NT = 1024;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int q = wave; q < S::NCH; q += NT / 64) {
+    const int m = q * S::RPC + lane / S::LPR;
+    const long long e = ((long long)m * N + y) * N + x0 + 2 * (((lane % S::LPR) + m) & 15);
+    if (m < S::ROWS && in_bounds(e + 1, (long long)(N / 2 + 1) * N * N)) {
+      __builtin_amdgcn_global_load_lds((const void*)(a + e),
+                                       (__attribute__((address_space(3))) void*)(stage + q * 128), 16, 0, 0);
+    }
+  }
+}
+
+template <int N, int WP>
+__device__ __forceinline__ float2 z_stage_at_skew(const float2* stage, int m, int col) {
+  return stage[m * 2 * WP + 2 * (((col >> 1) - m) & 15) + (col & 1)];
+}
+
+// z_pack_stage for the wave layout: column c, rows j + 64 r
+template <int N, int WP>
+__device__ __forceinline__ void z_pack_stage_w(float2* v, const float2* stage, int c, int j) {
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    const int k = j + r * (N / 8);
+    const int m = k <= N / 2 ? k : N - k;
+    const float2 A = z_stage_at_skew<N, WP>(stage, m, c), B = z_stage_at_skew<N, WP>(stage, m, c + WP);
+    if (k == 0 || k == N / 2) v[r] = make_float2(A.x, B.x);
+    else if (k < N / 2) v[r] = make_float2(A.x - B.y, A.y + B.x);
+    else v[r] = make_float2(A.x + B.y, B.x - A.y);
+  }
+}
+
+constexpr int kWaveRegion = 512 + 512 / 8 + 1;   // float2 per wave region
+
+// z_unpack_store from the per-wave regions (column p in region p, natural order)
+template <int N, int WP, int NT, bool MULK>
+__device__ __forceinline__ void z_unpack_store_w(const float2* wreg, float2* __restrict__ out, int y, int x0,
+                                                 float kf) {
+  for (int e = threadIdx.x; e < (N / 2 + 1) * WP; e += NT) {
+    const int p = e % WP, kz = e / WP;
+    const float2 Z = wreg[p * kWaveRegion + wat(kz)];
+    const float2 M = wreg[p * kWaveRegion + wat((N - kz) & (N - 1))];
+    float2 A = make_float2(0.5f * (Z.x + M.x), 0.5f * (Z.y - M.y));
+    float2 B = make_float2(0.5f * (Z.y + M.y), 0.5f * (M.x - Z.x));
+    if (MULK) {
+      const float k = kf * deriv_mode<N>(kz);
+      A = mul_i(A) * k;
+      B = mul_i(B) * k;
+    }
+    const long long base = ((long long)kz * N + y) * N + x0 + p;
+    constexpr long long CN = (long long)(N / 2 + 1) * N * N;
+    if (in_bounds(base, CN)) out[base] = A;
+    if (in_bounds(base + WP, CN)) out[base + WP] = B;
+  }
+}
+
+template <int N>
+__global__ void __launch_bounds__(1024) k_z_iter_w(float2* __restrict__ a0, float2* __restrict__ a1,
+                                                   const float2* __restrict__ a2, Geo g,
+                                                   const int* __restrict__ active, const float2* __restrict__ twg) {
+  static_assert(N == 512, "wave-local z iteration: one radix-8 fragment per lane of a 64-lane wave");
+  constexpr int WP = wz<N>(), NT = 1024, TPB = ztpb<N, ZI_PLAIN>();
+  static_assert(WP == 16 && (N / 8) * WP == NT, "one wave per packed column");
+  const int b = blockIdx.y;
+  if (active && !active[b]) return;
+  __shared__ float2 wreg[WP * kWaveRegion];
+  __shared__ float2 tw[N];
+  __shared__ float2 stage[ZStage<N, WP>::SIZE];
+  stage_twiddles<N, NT>(tw, twg);
+  const long long cn = (long long)(N / 2 + 1) * N * N;
+  a0 += b * cn; a1 += b * cn; a2 += b * cn;
+  int tile = blockIdx.x, y, x0;
+  z_tile_at<N, WP>(tile, y, x0);
+  if (tile < ztiles<N>()) z_stage_issue_skew<N, WP>(stage, a0, y, x0);
+#pragma unroll 1
+  for (int t = 0; t < TPB && tile < ztiles<N>(); ++t) {   // block-uniform bound
+    // the lane's row and column are taken afresh in every tile: the addresses and line-of-sight
+    // components derived from them are recomputed (a few integer and FMA operations) instead of
+    // being held in registers across the loop, which would spill
+    int j = threadIdx.x & 63, c = threadIdx.x >> 6;
+    asm volatile("" : "+v"(j), "+v"(c));
+    float2* reg = wreg + c * kWaveRegion;
+    const float ry = los_comp(g, 1, y);
+    const float rx0 = los_comp(g, 0, x0 + c), rx1 = los_comp(g, 0, x0 + c + WP);
+    const int next = tile + gridDim.x;
+    int ny = y, nx0 = x0;
+    float2 s[8], v[8];
+    z_stage_wait();
+    __syncthreads();                                   // tile staged; the last tile's stores have read
+    z_pack_stage_w<N, WP>(s, stage, c, j);
+    __syncthreads();                                   // every wave has read the staged tile
+    z_stage_issue_skew<N, WP>(stage, a2, y, x0);
+    wfft_rr<true>(s, reg, tw, j);
+    z_stage_wait();
+    __syncthreads();
+    z_pack_stage_w<N, WP>(v, stage, c, j);
+    __syncthreads();
+    if (t + 1 < TPB && next < ztiles<N>()) {
+      z_tile_at<N, WP>(next, ny, nx0);
+      z_stage_issue_skew<N, WP>(stage, a0, ny, nx0);
+    }
+    wfft_rr<true>(v, reg, tw, j);
+    // s = Psi . r (two columns packed as .x / .y) -> q = u / |r|, so that V_j = q r_j
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const float rz = los_comp(g, 2, j + r * (N / 8));
+      s[r] = make_float2(fmaf(rz, v[r].x, s[r].x), fmaf(rz, v[r].y, s[r].y));
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const float r2 = los_r2(h ? rx1 : rx0, ry, rz);
+        const float ir = r2 > 0.f ? rsqrtf(r2) : 0.f;
+        const float q = ((h ? s[r].y : s[r].x) * ir) * ir;
+        if (h) s[r].y = q; else s[r].x = q;
+      }
+      v[r] = s[r] * rz;
+    }
+    wfft_rl<false>(s, reg, tw, j);
+    __syncthreads();                                   // every column of Z[q] is in its region
+    z_unpack_store_w<N, WP, NT, false>(wreg, a0, y, x0, g.kf);
+    __syncthreads();                                   // the regions are free
+    wfft_rl<false>(v, reg, tw, j);
+    __syncthreads();
+    z_unpack_store_w<N, WP, NT, true>(wreg, a1, y, x0, g.kf);
+    tile = next; y = ny; x0 = nx0;
   }
 }
 

@@ -35,6 +35,28 @@
 #ifndef RECON_Z_DEFER
 #define RECON_Z_DEFER 1
 #endif
+#ifndef RECON_Z_WAVE
+#define RECON_Z_WAVE 0
+#endif
+// Per-size knobs (the 256^3 and 1024^3 grids; the general value until tuned at that size)
+#ifndef RECON_TILE_Z_256
+#define RECON_TILE_Z_256 RECON_TILE_Z
+#endif
+#ifndef RECON_TILE_Y_256
+#define RECON_TILE_Y_256 RECON_TILE_Y
+#endif
+#ifndef RECON_TILE_X_256
+#define RECON_TILE_X_256 RECON_TILE_X
+#endif
+#ifndef RECON_Z_TPB_256
+#define RECON_Z_TPB_256 RECON_Z_TPB
+#endif
+#ifndef RECON_TILE_X_1024
+#define RECON_TILE_X_1024 RECON_TILE_X
+#endif
+#ifndef RECON_Z_TPB_1024
+#define RECON_Z_TPB_1024 RECON_Z_TPB
+#endif
 // Deposit launch shapes, timed on the 512^3 survey catalogues (ms per reconstruction, both catalogues):
 //   brick accumulation threads per brick  256: 0.640   512: 0.522   1024: 0.585
 //   binning blocks (one 128 KB LDS histogram each)  1024: 1.018   512: 0.951   256: 0.915

@@ -87,3 +87,36 @@ def test_every_timed_stage_has_a_byte_model():
     ab = bench.algorithmic_bytes(512, 1000, 50000, bricks_g=100, bricks_r=200)
     missing = {n for n in names if n not in ab and n + "_step" not in ab}
     assert missing <= {"reduce", "scan", "z_fwd_real", "cnn_bwd"}, missing
+
+
+def test_autotuner_writes_one_size_and_keeps_the_others(tmp_path, monkeypatch):
+    """Tuning at 256^3 (batch 64) rewrites only the _256 knobs and adds its timing block; the general
+    knobs, their 512^3 timings and the deposit knobs stay."""
+    import argparse
+    import json
+    import shutil
+    from paper_1504_02591_amd import autotune
+    header = tmp_path / "recon_tuning.h"
+    shutil.copy(autotune.TUNING, header)
+    monkeypatch.setattr(autotune, "TUNING", str(header))
+    before = autotune.current()
+    blocks_before = autotune.size_blocks()
+    choice = dict(before)
+    choice["RECON_TILE_X_256"] = 8 if before["RECON_TILE_X_256"] != 8 else 2
+    json.dump({"n": 256, "batch": 64, "base": before, "choice": choice,
+               "times": {"base": 2.0, f"RECON_TILE_X_256={choice['RECON_TILE_X_256']}": 1.9}},
+              open(tmp_path / "result.json", "w"))
+    autotune.cmd_write(argparse.Namespace(dir=str(tmp_path)))
+    after = autotune.current()
+    assert after["RECON_TILE_X_256"] == choice["RECON_TILE_X_256"]
+    for k in autotune.KNOBS:
+        if k != "RECON_TILE_X_256":
+            assert after[k] == before[k], k
+    blocks = autotune.size_blocks()
+    assert 256 in blocks and "batch of 64" in blocks[256][0]
+    for size, lines in blocks_before.items():
+        if size != 256:
+            assert blocks[size] == lines
+    text = header.read_text()
+    for knob in ("RECON_BRICK_NT", "RECON_BIN_BLOCKS", "RECON_OBJ_BATCH"):
+        assert f"#define {knob}" in text
