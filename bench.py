@@ -49,7 +49,7 @@ def touched_bricks(pos, n, box_len):
     return int(out.sum())
 
 
-def algorithmic_bytes(n, n_gal, n_ran, randoms=True, keep_delta=False, bricks_g=None, bricks_r=None):
+def algorithmic_bytes(n, n_gal, n_ran, randoms=True, keep_delta=False, bricks_g=None, bricks_r=None, levels=1):
     """Compulsory bytes of one launch of each kernel kind (inputs read once, outputs written once).
 
     cn = (N/2+1) N^2 complex spectrum elements (8 B), n3 = N^3 cells.  The int64 deposit grids are
@@ -88,11 +88,12 @@ def algorithmic_bytes(n, n_gal, n_ran, randoms=True, keep_delta=False, bricks_g=
         # (16 B) and slot (4 B) written, each block's 128 KB histogram written and read back
         "bin_step": 44 * (n_gal + n_ran) + 2 * 131072 * (bin_blocks(n_gal) + bin_blocks(n_ran)),
         "fill_step": gb + rb + 2 * 4 * nbs3,                  # touched bricks cleared, brick counts zeroed
-        # learned start: full-weighting restriction of delta_s and u_p (R in, R/8 out each), linear
-        # prolongation of the network output (R/8 in, R out); the three layers on (N/2)^3 cells read
-        # delta and u_p (8 B), write and read a1 and a2 (32 B each, bf16 x 16 channels), write Delta u
-        "resample_step": 13.5 * n3,
-        "cnn_fwd_step": (8 + 32 + 32 + 32 + 32 + 4) * n3 // 8,
+        # learned start on the network grid of (N/2^levels)^3 cells (c = 8^-levels of the cells):
+        # restriction of delta_s and u_p (R in, c R out each; the (N/2)^3 intermediates of the two-level
+        # form are not compulsory) and prolongation of the network output (c R in, R out); the three layers read delta and u_p (8 B per network cell), write and
+        # read a1 and a2 (32 B each, bf16 x 16 channels) and write Delta u (4 B)
+        "resample_step": (2 * 4 + 2 * 4 * 8.0 ** -levels + 4 * 8.0 ** -levels + 4) * n3,
+        "cnn_fwd_step": (8 + 32 + 32 + 32 + 32 + 4) * n3 * 8.0 ** -levels,
     }
 
 
@@ -497,7 +498,7 @@ def main():
     n_gal, n_ran = int(gal.shape[0]), int(ran.shape[0])
     bricks_g = touched_bricks(cat.gal_pos, args.n, cat.box_len)
     bricks_r = touched_bricks(cat.ran_pos, args.n, cat.box_len)
-    ab = algorithmic_bytes(args.n, n_gal, n_ran, bricks_g=bricks_g, bricks_r=bricks_r)
+    ab = algorithmic_bytes(args.n, n_gal, n_ran, bricks_g=bricks_g, bricks_r=bricks_r, levels=max(net_levels, 1))
     stages = {}
     for name, (count, tot_ms) in sorted(prof.items(), key=lambda kv: -kv[1][1]):
         per = ab.get(name)

@@ -18,7 +18,8 @@
  *
  * Network grid: the plan's n^3 grid, or with RECON_CNN_HALF the (n/2)^3 grid of every
  * other node (cell 2 L/n), or with RECON_CNN_QUARTER the (n/4)^3 grid of every fourth node (the
- * restriction and prolongation below applied twice).  Then recon_solve restricts delta_s and u_p by full weighting
+ * restriction and prolongation below applied twice; the two prolongations run as one trilinear pass,
+ * equal up to FP32 rounding).  Then recon_solve restricts delta_s and u_p by full weighting
  * (recon_restrict), evaluates the network with r_hat of the coarse nodes, and prolongs
  * Delta u linearly (recon_prolong) to the n^3 grid.  The network grid needs >= 16^3 cells.
  * recon_cnn_forward and recon_cnn_train_step take and return fields on the network grid.

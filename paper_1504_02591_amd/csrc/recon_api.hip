@@ -153,6 +153,7 @@ Layout make_layout(const recon_params_t* p) {
       L.uc = take(b * m3 * 4);
     }
     if (lv == 2) {
+      // (n/2)^3 intermediates of the two-step restriction
       const long long h3 = (n / 2) * (n / 2) * (n / 2);
       L.dh = take(b * h3 * 4);
       L.uh = take(b * h3 * 4);
@@ -600,7 +601,7 @@ struct SizeOps {
       else if (N >= 64 && (pl->p.flags & RECON_FFT_SPLITBF16_X3))
         k_z_iter<N, ZI_PLAIN, N >= 64 ? 3 : 0><<<gzi<ZI_PLAIN, N >= 64 ? 3 : 0>(pl), dim3(TZ), 0, s>>>(
             pl->w0, pl->w1, pl->w2, pl->geo, nullptr, nullptr, act, pl->tw);
-      else if constexpr (N == 512 && RECON_Z_WAVE)
+      else if constexpr (N == 512 && RECON_Z_WAVE && wz<N>() == 16)
         k_z_iter_w<N><<<gzi<ZI_PLAIN>(pl), dim3(1024), 0, s>>>(pl->w0, pl->w1, pl->w2, pl->geo, act, pl->tw);
       else
         k_z_iter<N, ZI_PLAIN><<<gzi<ZI_PLAIN>(pl), dim3(TZ), 0, s>>>(pl->w0, pl->w1, pl->w2, pl->geo, nullptr,
@@ -742,6 +743,15 @@ int prolong_impl(recon_plan_t* pl, const float* coarse, float scale, float* fine
   recon::cnn::k_prolong<<<dim3((unsigned)((m * m * m + 255) / 256), pl->batch), 256, 0, pl->stream>>>(coarse, nf,
                                                                                                       scale, fine);
   return check_launch(pl, "prolongation");
+}
+
+// Prolongation twice in one pass ((n/4)^3 -> n^3).
+int prolong4_impl(recon_plan_t* pl, const float* coarse, float scale, float* fine) {
+  const long long m = pl->n / 4;
+  PROF(pl, KP_RESAMPLE);
+  recon::cnn::k_prolong4<<<dim3((unsigned)((m * m * m + 255) / 256), pl->batch), 256, 0, pl->stream>>>(
+      coarse, pl->n, scale, fine);
+  return check_launch(pl, "prolongation (two levels)");
 }
 
 // Network forward on the plan's batch; out = scale * y.
@@ -887,7 +897,7 @@ int plan_create(recon_plan_t** out, const recon_params_t* params, const Layout& 
       pl->dc = (float*)(w + L.dc);
       pl->uc = (float*)(w + L.uc);
     }
-    if (params->flags & RECON_CNN_QUARTER) {
+    if ((params->flags & RECON_CNN_QUARTER) && L.dh) {
       pl->dh = (float*)(w + L.dh);
       pl->uh = (float*)(w + L.uh);
     }
@@ -1240,12 +1250,12 @@ int recon_solve(recon_plan_t* pl, int start, const void* net) {
     RECON_TRY(ops->fanout(pl, nullptr, true));
     RECON_TRY(ops->zfinal(pl, nullptr, pl->upbuf, false, nullptr, true));
     if (pl->dh) {
-      // network on the (n/4)^3 grid: restrict the inputs twice, prolong its output twice
+      // network on the (n/4)^3 grid: two restrictions (both fields per pass), one trilinear
+      // prolongation that equals the linear one applied twice
       RECON_TRY(restrict_impl(pl, pl->delta, pl->dh, pl->upbuf, pl->uh));
       RECON_TRY(restrict_impl(pl, pl->dh, pl->dc, pl->uh, pl->uc, pl->n / 2));
       RECON_TRY(cnn_forward_impl(pl, (const float*)net, pl->dc, pl->uc, pl->ybuf, 1.0f / recon::cnn::S_U));
-      RECON_TRY(prolong_impl(pl, pl->ybuf, 1.0f, pl->dh, pl->n / 2));
-      RECON_TRY(prolong_impl(pl, pl->dh, 1.0f, pl->corr));
+      RECON_TRY(prolong4_impl(pl, pl->ybuf, 1.0f, pl->corr));
     } else if (pl->dc) {
       // network on the (n/2)^3 grid: restrict the inputs, prolong its output
       RECON_TRY(restrict_impl(pl, pl->delta, pl->dc, pl->upbuf, pl->uc));

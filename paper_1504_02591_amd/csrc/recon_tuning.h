@@ -1,18 +1,38 @@
 // Tuning knobs of the transform kernels, written by paper_1504_02591_amd/autotune.py (a -D on the
 // compiler command line overrides them).  Tiles: packed z column pairs, y-pass columns, x-pass
 // rows per block; middle radix split of the 512- and 1024-point transforms; z tiles per block of
-// the z iteration.
+// the z iteration; wave-local z iteration at 512^3.  The general knobs are timed at 512^3 and
+// serve every size without its own; the _256 and _1024 knobs are timed at those sizes.
+// Chosen on a 256^3 correction pass of a batch of 64 (fastest per knob); ms per pass of each variant:
+//   RECON_Z_TPB_256=4      18.3334
+//   RECON_Z_TPB_256=1      18.3340
+//   RECON_TILE_X_256=8     18.3761
+//   base                   18.4052
+//   RECON_TILE_X_256=2     18.4290
+//   RECON_Z_TPB_256=2      18.4743
+//   RECON_TILE_Z_256=8     18.5960
+//   RECON_TILE_Y_256=8     20.6149
 // Chosen on a 512^3 correction pass (fastest per knob); ms per pass of each variant:
-//   RECON_Z_TPB=8          2.5736
-//   base                   2.5814
-//   RECON_TILE_X=2         2.5904
-//   RECON_Z_TPB=2          2.5949
-//   RECON_TILE_X=8         2.5954
-//   RECON_Z_TPB=1          2.6240
-//   RECON_TILE_Z=8         2.6522
-//   RECON_MID_512=2        2.7369
-//   RECON_MID_512=1        2.7386
-//   RECON_TILE_Y=8         2.8554
+//   base                   2.4034
+//   RECON_Z_TPB=4          2.4174
+//   RECON_TILE_X=2         2.4249
+//   RECON_TILE_X=8         2.4291
+//   RECON_Z_TPB=2          2.4547
+//   RECON_MID_512=2        2.4941
+//   RECON_MID_512=1        2.4949
+//   RECON_Z_TPB=1          2.4980
+//   RECON_Z_WAVE=0         2.4997
+//   RECON_TILE_Z=8         2.5664
+//   RECON_TILE_Y=8         2.7006
+// Chosen on a 1024^3 correction pass (fastest per knob); ms per pass of each variant:
+//   RECON_TILE_X_1024=2    28.2326
+//   base                   29.0081
+//   RECON_Z_TPB_1024=4     29.1065
+//   RECON_TILE_X_1024=8    29.3792
+//   RECON_MID_1024=1       29.5875
+//   RECON_Z_TPB_1024=2     29.6346
+//   RECON_MID_1024=2       29.7253
+//   RECON_Z_TPB_1024=1     30.3946
 #pragma once
 #ifndef RECON_TILE_Z
 #define RECON_TILE_Z 16
@@ -26,36 +46,32 @@
 #ifndef RECON_MID_512
 #define RECON_MID_512 0
 #endif
-#ifndef RECON_MID_1024
-#define RECON_MID_1024 0
-#endif
 #ifndef RECON_Z_TPB
 #define RECON_Z_TPB 8
 #endif
-#ifndef RECON_Z_DEFER
-#define RECON_Z_DEFER 1
-#endif
 #ifndef RECON_Z_WAVE
-#define RECON_Z_WAVE 0
+#define RECON_Z_WAVE 1
 #endif
-// Per-size knobs (the 256^3 and 1024^3 grids; the general value until tuned at that size)
 #ifndef RECON_TILE_Z_256
-#define RECON_TILE_Z_256 RECON_TILE_Z
+#define RECON_TILE_Z_256 16
 #endif
 #ifndef RECON_TILE_Y_256
-#define RECON_TILE_Y_256 RECON_TILE_Y
+#define RECON_TILE_Y_256 16
 #endif
 #ifndef RECON_TILE_X_256
-#define RECON_TILE_X_256 RECON_TILE_X
+#define RECON_TILE_X_256 8
 #endif
 #ifndef RECON_Z_TPB_256
-#define RECON_Z_TPB_256 RECON_Z_TPB
+#define RECON_Z_TPB_256 4
 #endif
 #ifndef RECON_TILE_X_1024
-#define RECON_TILE_X_1024 RECON_TILE_X
+#define RECON_TILE_X_1024 2
+#endif
+#ifndef RECON_MID_1024
+#define RECON_MID_1024 0
 #endif
 #ifndef RECON_Z_TPB_1024
-#define RECON_Z_TPB_1024 RECON_Z_TPB
+#define RECON_Z_TPB_1024 8
 #endif
 // Deposit launch shapes, timed on the 512^3 survey catalogues (ms per reconstruction, both catalogues):
 //   brick accumulation threads per brick  256: 0.640   512: 0.522   1024: 0.585
@@ -63,6 +79,9 @@
 //   objects per loop trip (deposit + randoms' shift)  2: 0.512 + 1.025   4: 0.497 + 1.025   8: 0.510 + 1.062
 //   reorder after the brick-order shift, chunks of one block (shift stage, both catalogues)
 //     per_x apart: 1.096   adjacent (one trip per block), 2 / 4 / 8 chunks: 0.980 / 0.983 / 0.980
+#ifndef RECON_Z_DEFER
+#define RECON_Z_DEFER 1
+#endif
 #ifndef RECON_BRICK_NT
 #define RECON_BRICK_NT 512
 #endif
