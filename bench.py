@@ -155,7 +155,9 @@ def time_oracle_sample(n, tol, max_iter, full=False):
     cat = G.config2(n=n, scale=n / 512.0) if full else G.config2(n=n // 2, scale=0.5, seeds=(911, 912, 913))
     t0 = time.perf_counter()
     res = O.reconstruct(cat.gal_pos, None, cat.ran_pos, None, cat.n, cat.box_len, cat.origin, cat.observer,
-                        cat.bias, cat.growth, cat.smooth_r, cat.mask_tau, tol=tol, max_iter=max_iter)
+                        cat.bias, cat.growth, cat.smooth_r, cat.mask_tau, tol=tol, max_iter=max_iter,
+                        log=(lambda m: print(f"[bench] {m} ({time.perf_counter() - t0:.1f}s)", file=sys.stderr,
+                                             flush=True)) if full else None)
     dt = time.perf_counter() - t0
     return dt, res["passes"], int(cat.gal_pos.shape[0] + cat.ran_pos.shape[0]), O.WORKERS
 

@@ -215,8 +215,9 @@ def _bincount_int64(idx, vals, size):
     return (s_hi.astype(np.int64) << 26) + s_lo.astype(np.int64)
 
 
-def paint(pos, w, n, box_len, origin):
-    """Deterministic fixed-point CIC deposit onto an int64 grid [iz][iy][ix] (units of 2^-32)."""
+def paint(pos, w, n, box_len, origin, log=None):
+    """Deterministic fixed-point CIC deposit onto an int64 grid [iz][iy][ix] (units of 2^-32).
+    log: optional callable taking a progress line per corner."""
     pos = np.ascontiguousarray(pos, dtype=np.float32).reshape(-1, 3)
     m = pos.shape[0]
     grid = np.zeros(n * n * n, dtype=np.int64)
@@ -231,6 +232,8 @@ def paint(pos, w, n, box_len, origin):
         iz = (i0[:, 2] + dz) % n
         flat = (iz * n + iy) * n + ix
         grid += _bincount_int64(flat, part, n * n * n)
+        if log:
+            log(f"oracle deposit of {m} objects: corner ({dx}, {dy}, {dz}) done")
     return grid.reshape(n, n, n)
 
 
@@ -362,7 +365,7 @@ def ffta_coefficient(start, growth, bias):
 
 def reconstruct_field(delta_s, box_len, origin, observer, bias, growth,
                       n_passes=None, tol=None, max_iter=50, start=START_PLAIN,
-                      start_correction=None, rhat=None, keep=()):
+                      start_correction=None, rhat=None, keep=(), log=None):
     """Iterative RSD removal from the smoothed redshift-space overdensity.
 
     delta_s: (n,n,n) float64.  Runs exactly n_passes passes when given, otherwise
@@ -409,6 +412,8 @@ def reconstruct_field(delta_s, box_len, origin, observer, bias, growth,
         eps_hist.append(float(eps))
         if passes in keep:
             psi_at[passes] = psi.copy()
+        if log:
+            log(f"oracle pass {passes}: eps {eps:.3e}")
         norm1 = den if norm1 is None else norm1
         if not np.isfinite(eps):
             diverged = True
@@ -470,16 +475,19 @@ def shift(psi, pos, box_len, origin, observer, growth, galaxies):
 # ---------------------------------------------------------------------------
 def reconstruct(gal_pos, gal_w, ran_pos, ran_w, n, box_len, origin, observer,
                 bias, growth, smooth_r, mask_tau=0.1, n_passes=None, tol=None,
-                max_iter=50, start=START_PLAIN, start_correction=None, log_transform=False):
-    """Paint -> overdensity (-> lognormal transform) -> iteration -> shift, all in FP64 (integer deposit)."""
-    grid_g = paint(gal_pos, gal_w, n, box_len, origin)
-    grid_r = None if ran_pos is None else paint(ran_pos, ran_w, n, box_len, origin)
+                max_iter=50, start=START_PLAIN, start_correction=None, log_transform=False, log=None):
+    """Paint -> overdensity (-> lognormal transform) -> iteration -> shift, all in FP64 (integer deposit).
+    log: optional callable taking one progress line per stage and pass."""
+    grid_g = paint(gal_pos, gal_w, n, box_len, origin, log=log)
+    grid_r = None if ran_pos is None else paint(ran_pos, ran_w, n, box_len, origin, log=log)
     delta_s = overdensity(grid_g, grid_r, box_len, smooth_r, mask_tau)
     if log_transform:
         delta_s = lognormal(delta_s)
+    if log:
+        log("oracle overdensity done")
     res = reconstruct_field(delta_s, box_len, origin, observer, bias, growth,
                             n_passes=n_passes, tol=tol, max_iter=max_iter,
-                            start=start, start_correction=start_correction)
+                            start=start, start_correction=start_correction, log=log)
     res["grid_g"] = grid_g
     res["grid_r"] = grid_r
     res["delta_s"] = delta_s

@@ -1268,7 +1268,7 @@ __global__ void __launch_bounds__(ntz<N>()) k_z_iter(float2* __restrict__ a0, fl
 
 // The plain z iteration of k_z_iter with wave-local transforms (N = 512): the wave of packed column
 // c transforms that column in its own LDS region, so the only block barriers of a tile are those
-// of the staging and of the stores (7 per tile instead of about 22).  The staged tile is skewed: row
+// of the staging and of the stores (6 per tile instead of about 22).  The staged tile is skewed: row
 // m's 16-byte piece p sits in slot (p - m) mod 16 of the row, so that a wave reading one column down
 // 64 consecutive rows spreads over every bank; the per-wave regions are 577 float2 apart, so that the
 // stores, which read one row of 16 columns at a time, do too.
@@ -1349,6 +1349,12 @@ __global__ void __launch_bounds__(1024) k_z_iter_w(float2* __restrict__ a0, floa
   int tile = blockIdx.x, y, x0;
   z_tile_at<N, WP>(tile, y, x0);
   if (tile < ztiles<N>()) z_stage_issue_skew<N, WP>(stage, a0, y, x0);
+  z_stage_wait();
+  __syncthreads();                                     // first tile staged
+  // Waits: the staging waits (vmcnt(0)) also wait for every store a wave has issued.  The next tile's
+  // first array is therefore waited for after the inverse transform of v, not at the top of the loop:
+  // the stores of Z[q] have drained under that transform, and the stores of Z[r_z q], issued after
+  // the wait, drain under the next tile's packing and first transform.
 #pragma unroll 1
   for (int t = 0; t < TPB && tile < ztiles<N>(); ++t) {   // block-uniform bound
     // the lane's row and column are taken afresh in every tile: the addresses and line-of-sight
@@ -1362,8 +1368,6 @@ __global__ void __launch_bounds__(1024) k_z_iter_w(float2* __restrict__ a0, floa
     const int next = tile + gridDim.x;
     int ny = y, nx0 = x0;
     float2 s[8], v[8];
-    z_stage_wait();
-    __syncthreads();                                   // tile staged; the last tile's stores have read
     z_pack_stage_w<N, WP>(s, stage, c, j);
     __syncthreads();                                   // every wave has read the staged tile
     z_stage_issue_skew<N, WP>(stage, a2, y, x0);
@@ -1396,8 +1400,10 @@ __global__ void __launch_bounds__(1024) k_z_iter_w(float2* __restrict__ a0, floa
     z_unpack_store_w<N, WP, NT, false>(wreg, a0, y, x0, g.kf);
     __syncthreads();                                   // the regions are free
     wfft_rl<false>(v, reg, tw, j);
-    __syncthreads();
+    z_stage_wait();
+    __syncthreads();                                   // Z[r_z q] in the regions; the next tile staged
     z_unpack_store_w<N, WP, NT, true>(wreg, a1, y, x0, g.kf);
+    // (the barrier after the next tile's packing orders these reads of the regions before its transforms)
     tile = next; y = ny; x0 = nx0;
   }
 }
