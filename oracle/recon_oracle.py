@@ -378,6 +378,8 @@ def reconstruct_field(delta_s, box_len, origin, observer, bias, growth,
     n = delta_s.shape[0]
     if rhat is None:
         rhat = line_of_sight(n, box_len, origin, observer)
+        if log:
+            log("oracle line of sight done")
     d_s = fwd(delta_s)
     psi_p = psi_from_density(d_s, n, box_len, bias)
     u_p = np.sum(psi_p * rhat, axis=0)
@@ -392,6 +394,8 @@ def reconstruct_field(delta_s, box_len, origin, observer, bias, growth,
         psi = psi_p + np.asarray(start_correction, dtype=np.float64) * rhat
     else:
         raise ValueError("unknown start")
+    if log:
+        log("oracle start done")
 
     eps_hist = []
     psi_at = {0: psi.copy()} if 0 in keep else {}
