@@ -66,6 +66,15 @@ R15 Lognormal option (Sec. 6, eq. logdelta): the smoothed, masked delta_s is rep
     ln(max(1 + delta_s, 1e-3)) + C, C = -<ln(max(1 + delta_s, 1e-3))> over all cells (masked
     cells have delta_s = 0 and map to C); the clamp keeps FP32 rounding in empty regions from
     reaching the logarithm's pole.
+R18 Relaxed iteration option (not in the paper; it changes the path, not the fixed point):
+    D_{n+1} = (1 - w) D_n + w (D_s + f div[(Psi_n.r)r]) with w = 2/(2 + beta).  The pass of
+    Sec. 5.1 maps D_n to D_s + T D_n with T D = -beta G^H P G (D/k^2), where G X = (i k'_j X)_j,
+    G^H its adjoint and P the pointwise projection v -> (v.r) r.  T is similar to
+    -beta (G/|k|)^H P (G/|k|), a symmetric operator with |k'| <= |k| and P a projection, so its
+    eigenvalues are real and lie in [-beta, 0]; those of the relaxed pass, 1 - w + w lambda, lie in
+    [1 - w(1 + beta), 1 - w], whose largest modulus beta/(2 + beta) is the smallest any w gives.
+    The first pass after a non-gradient start (FFTA, learned) has no D_0 to mix with and is the
+    plain pass; every other pass, including the first pass of the plain start (D_0 = D_s), is relaxed.
 """
 from __future__ import annotations
 
@@ -363,15 +372,21 @@ def ffta_coefficient(start, growth, bias):
     return 0.0
 
 
+def relax_weight(growth, bias):
+    """w = 2/(2 + beta) of the relaxed pass (R18): centres the pass's eigenvalue interval on 0."""
+    return 2.0 / (2.0 + growth / bias)
+
+
 def reconstruct_field(delta_s, box_len, origin, observer, bias, growth,
                       n_passes=None, tol=None, max_iter=50, start=START_PLAIN,
-                      start_correction=None, rhat=None, keep=(), log=None):
+                      start_correction=None, rhat=None, keep=(), log=None, relax=None):
     """Iterative RSD removal from the smoothed redshift-space overdensity.
 
     delta_s: (n,n,n) float64.  Runs exactly n_passes passes when given, otherwise
     stops at the first n >= 1 with eps_n <= tol (or max_iter).  start selects the
     starting displacement: plain (Psi from delta_s), FFTA-1/FFTA-2, or learned,
-    where start_correction is the scalar field Delta added along r-hat.
+    where start_correction is the scalar field Delta added along r-hat.  relax: the
+    weight w of the relaxed iteration (R18), None for the paper's pass.
     Returns dict(psi=(3,n,n,n), eps=[eps_1..], passes=n, diverged=bool, D=final density spectrum,
     psi_at={k: Psi_k for the pass counts k listed in keep}).
     """
@@ -406,7 +421,11 @@ def reconstruct_field(delta_s, box_len, origin, observer, bias, growth,
     limit = n_passes if n_passes is not None else max_iter
     while passes < limit:
         u = np.sum(psi * rhat, axis=0)
-        dk = d_s + growth * rsd_divergence(u, rhat, box_len)
+        full = d_s + growth * rsd_divergence(u, rhat, box_len)
+        if relax is None or (passes == 0 and start != START_PLAIN):
+            dk = full
+        else:
+            dk = (1.0 - relax) * dk + relax * full   # dk is D_n here (D_s before the first pass)
         psi_new = psi_from_density(dk, n, box_len, bias)
         num = np.sqrt(np.sum((psi_new - psi) ** 2))
         den = np.sqrt(np.sum(psi_new ** 2))
@@ -479,7 +498,8 @@ def shift(psi, pos, box_len, origin, observer, growth, galaxies):
 # ---------------------------------------------------------------------------
 def reconstruct(gal_pos, gal_w, ran_pos, ran_w, n, box_len, origin, observer,
                 bias, growth, smooth_r, mask_tau=0.1, n_passes=None, tol=None,
-                max_iter=50, start=START_PLAIN, start_correction=None, log_transform=False, log=None):
+                max_iter=50, start=START_PLAIN, start_correction=None, log_transform=False, log=None,
+                relax=None):
     """Paint -> overdensity (-> lognormal transform) -> iteration -> shift, all in FP64 (integer deposit).
     log: optional callable taking one progress line per stage and pass."""
     grid_g = paint(gal_pos, gal_w, n, box_len, origin, log=log)
@@ -491,7 +511,7 @@ def reconstruct(gal_pos, gal_w, ran_pos, ran_w, n, box_len, origin, observer,
         log("oracle overdensity done")
     res = reconstruct_field(delta_s, box_len, origin, observer, bias, growth,
                             n_passes=n_passes, tol=tol, max_iter=max_iter,
-                            start=start, start_correction=start_correction, log=log)
+                            start=start, start_correction=start_correction, log=log, relax=relax)
     res["grid_g"] = grid_g
     res["grid_r"] = grid_r
     res["delta_s"] = delta_s

@@ -218,6 +218,117 @@ def test_fixed_point_independent_of_start(start):
     np.testing.assert_allclose(alt["psi"], ref["psi"], atol=1e-11)
 
 
+# ---------------------------------------------------------------------------
+# Relaxed iteration (R18): same fixed point, per-mode closed form, contraction bound
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("axis", [0, 2])
+def test_relaxed_distant_observer_iterates_closed_form(axis):
+    """Distant observer along an axis: each mode's relaxed pass is the scalar map
+    D -> (1 - w) D + w (D_s - beta mu'^2 D), so D_n = D_inf + (1 - w (1 + beta mu'^2))^n (D_s - D_inf)
+    with D_inf = D_s / (1 + beta mu'^2) (the Kaiser factor of the plain iteration's limit)."""
+    n, box, b, f = 16, 400.0, 2.0, 0.74
+    beta = f / b
+    w = 2.0 / (2.0 + beta)
+    assert O.relax_weight(f, b) == w
+    rng = np.random.default_rng(60 + axis)
+    delta = O.smooth(rng.standard_normal((n, n, n)), box, 20.0)
+    dk_s = O.fwd(delta)
+    m = np.fft.fftfreq(n, d=1.0 / n)
+    mh = np.arange(n // 2 + 1)
+    mlist = [mh.reshape(1, 1, -1), m.reshape(1, -1, 1), m.reshape(-1, 1, 1)]
+    kvec = [np.broadcast_to((2 * np.pi / box) * a, (n, n, n // 2 + 1)) for a in mlist]
+    k2 = kvec[0] ** 2 + kvec[1] ** 2 + kvec[2] ** 2
+    dk = [np.where(np.abs(np.broadcast_to(mm, k2.shape)) == n // 2, 0.0, kk) for mm, kk in zip(mlist, kvec)]
+    with np.errstate(invalid="ignore", divide="ignore"):
+        mu2 = np.where(k2 > 0, dk[axis] ** 2 / k2, 0.0)
+    d_inf = dk_s / (1 + beta * mu2)
+    for npass in (1, 2, 5):
+        res = O.reconstruct_field(delta, box, (0, 0, 0), _far_observer(axis, box), b, f, n_passes=npass, relax=w)
+        dn = d_inf + (1 - w * (1 + beta * mu2)) ** npass * (dk_s - d_inf)
+        with np.errstate(invalid="ignore", divide="ignore"):
+            pot = np.where(k2 > 0, dn / (b * k2), 0.0)
+        for j in range(3):
+            expect = np.fft.irfftn(1j * dk[j] * pot, s=(n, n, n), axes=(0, 1, 2))
+            np.testing.assert_allclose(res["psi"][j], expect, atol=1e-8 * np.abs(expect).max() + 1e-14)
+
+
+@pytest.mark.parametrize("observer", [(31.3, 47.9, 52.1), (-40.0, 130.0, 60.0)])
+def test_relaxed_fixed_point_solves_nusser_davis_equation(observer):
+    """The relaxed passes reach the solution of the discretised eq. (Nusser) found by a dense direct
+    solve (the same system as the plain iteration's pin), in fewer passes."""
+    n, box, b, f = 8, 100.0, 1.5, 0.6
+    rng = np.random.default_rng(41)
+    delta = O.smooth(rng.standard_normal((n, n, n)), box, 12.0)
+    grad, lap = dense_operators(n, box)
+    rh = los_loops(n, box, (0, 0, 0), observer)
+    rvec = [rh[j].ravel() for j in range(3)]
+    radial = sum(np.diag(rvec[i]) @ grad[i] for i in range(3))
+    rsd = sum(grad[j] @ np.diag(rvec[j]) for j in range(3)) @ radial
+    a = -b * lap - f * rsd
+    rhs = delta.ravel() - delta.mean()
+    phi, *_ = np.linalg.lstsq(a, rhs, rcond=None)
+    res = O.reconstruct_field(delta, box, (0, 0, 0), observer, b, f, n_passes=40, relax=O.relax_weight(f, b))
+    assert res["eps"][-1] < 1e-13
+    for j in range(3):
+        np.testing.assert_allclose(res["psi"][j].ravel(), grad[j] @ phi, atol=1e-10)
+
+
+def test_relaxed_pass_contracts_by_beta_over_two_plus_beta():
+    """Wide angle (observer inside the box): with X = D/|k| the pass is symmetric, so the error
+    X_n - X_inf shrinks by at least beta/(2 + beta) per relaxed pass, against at most beta per plain
+    pass, which the slowest mode nearly reaches."""
+    n, box, b, f = 16, 300.0, 1.0, 0.7
+    beta = f / b
+    rng = np.random.default_rng(71)
+    delta = O.smooth(rng.standard_normal((n, n, n)), box, 15.0)
+    obs = (140.3, 160.7, 150.2)
+    m = np.fft.fftfreq(n, d=1.0 / n)
+    mh = np.arange(n // 2 + 1)
+    k2 = sum(((2 * np.pi / box) * a) ** 2 for a in (mh.reshape(1, 1, -1), m.reshape(1, -1, 1), m.reshape(-1, 1, 1)))
+    inv_k = np.where(k2 > 0, 1.0 / np.sqrt(np.where(k2 > 0, k2, 1.0)), 0.0)
+    wgt = np.where((mh == 0) | (mh == n // 2), 1.0, 2.0).reshape(1, 1, -1)
+
+    def xnorm(d):
+        return math.sqrt(float(np.sum(wgt * np.abs(d * inv_k) ** 2)))
+
+    x_inf = O.reconstruct_field(delta, box, (0, 0, 0), obs, b, f, n_passes=120)["D"]
+    for relax, bound in ((O.relax_weight(f, b), beta / (2 + beta)), (None, beta)):
+        errs = [xnorm(O.reconstruct_field(delta, box, (0, 0, 0), obs, b, f, n_passes=p, relax=relax)["D"] - x_inf)
+                for p in range(1, 7)]
+        ratios = [e1 / e0 for e0, e1 in zip(errs, errs[1:])]
+        assert max(ratios) <= bound * (1 + 1e-9), (relax, ratios)
+        if relax is None:
+            assert max(ratios) > 0.5 * beta          # the plain pass is not faster than the bound says
+        else:
+            assert max(ratios) < 0.6 * beta          # the relaxed one is
+
+
+@pytest.mark.parametrize("start", [O.START_FFTA2, O.START_LEARNED])
+def test_relaxed_iteration_after_non_gradient_start(start):
+    """After a non-gradient start the first pass is the plain pass (no D_0 to mix with); the relaxed
+    passes that follow reach the plain iteration's fixed point."""
+    n, box, b, f = 16, 300.0, 2.0, 0.74
+    rng = np.random.default_rng(81)
+    delta = O.smooth(rng.standard_normal((n, n, n)), box, 20.0)
+    corr = 0.1 * O.smooth(rng.standard_normal((n, n, n)), box, 30.0) if start == O.START_LEARNED else None
+    obs = (150.0, 120.0, 170.0)
+    w = O.relax_weight(f, b)
+    one_plain = O.reconstruct_field(delta, box, (0, 0, 0), obs, b, f, n_passes=1, start=start, start_correction=corr)
+    one_relax = O.reconstruct_field(delta, box, (0, 0, 0), obs, b, f, n_passes=1, start=start, start_correction=corr,
+                                    relax=w)
+    np.testing.assert_array_equal(one_relax["psi"], one_plain["psi"])
+    two_plain = O.reconstruct_field(delta, box, (0, 0, 0), obs, b, f, n_passes=2, start=start, start_correction=corr)
+    two_relax = O.reconstruct_field(delta, box, (0, 0, 0), obs, b, f, n_passes=2, start=start, start_correction=corr,
+                                    relax=w)
+    # the second pass mixes: D_2 = (1 - w) D_1 + w (plain pass from D_1)
+    np.testing.assert_allclose(two_relax["D"], (1 - w) * one_plain["D"] + w * two_plain["D"], rtol=0,
+                               atol=1e-12 * np.abs(two_plain["D"]).max())
+    ref = O.reconstruct_field(delta, box, (0, 0, 0), obs, b, f, n_passes=60)
+    alt = O.reconstruct_field(delta, box, (0, 0, 0), obs, b, f, n_passes=30, start=start, start_correction=corr,
+                              relax=w)
+    np.testing.assert_allclose(alt["psi"], ref["psi"], atol=1e-11)
+
+
 def test_ffta_start_changes_only_the_radial_component():
     n, box, b, f = 16, 300.0, 2.0, 0.74
     rng = np.random.default_rng(52)
