@@ -21,6 +21,13 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 START_NAMES = {"plain": 0, "ffta1": 1, "ffta2": 2, "learned": 3}
+RELAXED_SUFFIX = "_relaxed"   # a start name with this suffix runs the relaxed correction pass (RECON_RELAXED)
+
+
+def start_of(name):
+    """(start code, relaxed) of a start name such as 'learned' or 'plain_relaxed'."""
+    relaxed = name.endswith(RELAXED_SUFFIX)
+    return START_NAMES[name[:-len(RELAXED_SUFFIX)] if relaxed else name], relaxed
 
 
 BRICK = 16
@@ -149,7 +156,8 @@ def time_oracle_sample(n, tol, max_iter, full=False):
     """The whole FP64 oracle pipeline (deposit of galaxies and randoms, smoothing, mask, overdensity,
     passes to eps <= tol, shift of both catalogues) on the survey workload shrunk by 2 per axis:
     (n/2)^3 grid over half the box and shell, so the same cell size and 1/8 of the cells and objects;
-    full=True runs the workload itself (n^3, minutes).  Returns (seconds, passes, objects, threads)."""
+    full=True runs the workload itself (n^3, minutes).  Returns (seconds, passes, objects, threads, the
+    catalogue, the oracle's result)."""
     from oracle import recon_oracle as O
     from synth import generators as G
     cat = G.config2(n=n, scale=n / 512.0) if full else G.config2(n=n // 2, scale=0.5, seeds=(911, 912, 913))
@@ -159,7 +167,31 @@ def time_oracle_sample(n, tol, max_iter, full=False):
                         log=(lambda m: print(f"[bench] {m} ({time.perf_counter() - t0:.1f}s)", file=sys.stderr,
                                              flush=True)) if full else None)
     dt = time.perf_counter() - t0
-    return dt, res["passes"], int(cat.gal_pos.shape[0] + cat.ran_pos.shape[0]), O.WORKERS
+    return dt, res["passes"], int(cat.gal_pos.shape[0] + cat.ran_pos.shape[0]), O.WORKERS, cat, res
+
+
+def gpu_error_vs_oracle(cat, ref, torch, native, dev):
+    """The GPU path on the oracle's timed sample (plain start, the oracle's pass count): Psi relative L2
+    error, eps history agreement and the largest displacement difference against the oracle's result."""
+    import numpy as np
+    plan = native.plan_for(cat)
+    gal = torch.from_numpy(cat.gal_pos).to(dev)
+    ran = torch.from_numpy(cat.ran_pos).to(dev)
+    plan.paint(native.GAL, gal)
+    plan.paint(native.RAN, ran)
+    plan.solve()
+    rc, iters, eps = plan.iterate(ref["passes"], 0.0)
+    psi = plan.psi()[0].cpu().numpy().astype(np.float64)
+    dg = plan.shift(native.GAL, gal).cpu().numpy()
+    dr = plan.shift(native.RAN, ran).cpu().numpy()
+    plan.close()
+    e_psi = float(np.linalg.norm(psi - ref["psi"]) / np.linalg.norm(ref["psi"]))
+    e_eps = float(np.max(np.abs(np.asarray(eps[0]) - np.asarray(ref["eps"])) / np.asarray(ref["eps"])))
+    e_disp = float(max(np.abs(dg - ref["disp_g"]).max(), np.abs(dr - ref["disp_r"]).max()))
+    return {"workload": f"the oracle's timed sample ({cat.n}^3, {cat.gal_pos.shape[0] + cat.ran_pos.shape[0]} "
+                        f"objects), plain start, {ref['passes']} passes",
+            "psi_rel_l2": e_psi, "eps_max_rel": e_eps, "disp_max_abs_mpc_h": e_disp,
+            "bar": {"psi_rel_l2": 1e-5, "disp_max_abs_mpc_h": 1e-4}}
 
 
 def _one_fft_thread():
@@ -350,8 +382,9 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--rounds", type=int, default=5, help="interleaved timing rounds over the starts")
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--starts", default="plain,ffta2,learned",
-                    help="comma-separated starts to time; the last one available is the headline value")
+    ap.add_argument("--starts", default="plain_relaxed,learned_relaxed,plain,ffta2,learned",
+                    help="comma-separated starts to time (suffix _relaxed: the relaxed correction pass); the last "
+                         "one available is the headline value")
     ap.add_argument("--weights", default=None, help="learned-start parameters (.npz, key 'params')")
     ap.add_argument("--tol", type=float, default=1e-3)
     ap.add_argument("--max-iter", type=int, default=50)
@@ -409,10 +442,12 @@ def main():
 
     starts = [s.strip() for s in args.starts.split(",") if s.strip()]
     for s in starts:
-        if s not in START_NAMES:
+        try:
+            start_of(s)
+        except KeyError:
             sys.exit(f"unknown start {s!r}")
     net, net_levels = None, 0
-    if "learned" in starts:
+    if any(start_of(s)[0] == START_NAMES["learned"] for s in starts):
         from paper_1504_02591_amd import learned
         wpath = args.weights or learned.WEIGHTS
         if os.path.exists(wpath):
@@ -422,13 +457,14 @@ def main():
                                                                              else 0)
         else:
             print(f"[bench] no learned-start weights at {wpath}: learned start skipped", file=sys.stderr, flush=True)
-            starts.remove("learned")
+            starts = [s for s in starts if start_of(s)[0] != START_NAMES["learned"]]
 
-    def make_plan(start):
+    def make_plan(name):
+        start, relaxed = start_of(name)
         lrn = start == START_NAMES["learned"]
         return native.plan_for(cat, start_buffers=start != 0, keep_delta=lrn, cnn=lrn,
                                cnn_half=lrn and net_levels == 1, cnn_quarter=lrn and net_levels == 2,
-                               graphs=not args.no_graphs, lognormal=args.lognormal)
+                               graphs=not args.no_graphs, lognormal=args.lognormal, relaxed=relaxed)
 
     codes = {}
 
@@ -450,9 +486,9 @@ def main():
     # (in an order rotated from round to round), each block bracketed by device synchronisations, so
     # that clock or thermal drift over the run falls on all starts alike.  Every start runs exactly
     # args.steps timed steps in total.
-    plans = {name: make_plan(START_NAMES[name]) for name in starts}
+    plans = {name: make_plan(name) for name in starts}
     for name in starts:
-        run(plans[name], START_NAMES[name], args.warmup, [])
+        run(plans[name], start_of(name)[0], args.warmup, [])
     torch.cuda.synchronize()
     rounds = max(1, min(args.rounds, args.steps))
     blocks = [args.steps // rounds + (1 if r < args.steps % rounds else 0) for r in range(rounds)]
@@ -461,7 +497,7 @@ def main():
         for name in starts[r % len(starts):] + starts[:r % len(starts)]:
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            eps = run(plans[name], START_NAMES[name], k, acc[name]["passes"])
+            eps = run(plans[name], start_of(name)[0], k, acc[name]["passes"])
             torch.cuda.synchronize()
             acc[name]["elapsed"] += time.perf_counter() - t0
             acc[name]["eps"] = eps
@@ -487,8 +523,8 @@ def main():
     # per-kernel event timing: a separate run of the headline start, so the timed run carries no events
     prof = {}
     if not args.no_profile:
-        start = START_NAMES[head]
-        plan = make_plan(start)
+        start = start_of(head)[0]
+        plan = make_plan(head)
         run(plan, start, 1, [])
         plan.profile_start()
         run(plan, start, args.steps, [])
@@ -504,17 +540,17 @@ def main():
     stages = {}
     for name, (count, tot_ms) in sorted(prof.items(), key=lambda kv: -kv[1][1]):
         per = ab.get(name)
-        if name == "z_iter" and head != "plain" and per is not None:
+        if name == "z_iter" and start_of(head)[0] != START_NAMES["plain"] and per is not None:
             # the start pass and the pass after it also read (or write) the start correction field;
             # the learned start's pass reads u_p (one real field) instead of the two state-Y spectra
             r = args.n ** 3 * 4
             per_step = per * count / args.steps + 2 * r
-            if head == "learned":
+            if start_of(head)[0] == START_NAMES["learned"]:
                 per_step += r - per / 2
         elif name == "y_fanout":
             # one full fan-out per reconstruction (the output), the rest combined
             per_step = (per * (count - args.steps) + ab["y_fanout_full"] * args.steps) / args.steps
-        elif name == "z_final" and head == "learned":
+        elif name == "z_final" and start_of(head)[0] == START_NAMES["learned"]:
             # u_p of the start (combined state) plus the output
             per_step = ab["z_final_u"] + per
         elif name == "paint":
@@ -543,9 +579,13 @@ def main():
                     "traffic": measured_traffic(dom) if args.n == 512 else None,
                     "algorithmic_bytes_per_launch": int(round(per_launch)), "avg_launch_ms": round(avg_s * 1e3, 4)}
 
-    cpu = None
+    cpu = vs_oracle = None
     if not args.no_cpu_baseline:
-        t_s, p_s, m_s, workers = time_oracle_sample(args.n, args.tol, args.max_iter, full=args.cpu_full)
+        t_s, p_s, m_s, workers, s_cat, s_ref = time_oracle_sample(args.n, args.tol, args.max_iter, full=args.cpu_full)
+        vs_oracle = gpu_error_vs_oracle(s_cat, s_ref, torch, native, dev)
+        del s_cat, s_ref
+        print(f"[bench] GPU vs oracle on the sample: psi rel L2 {vs_oracle['psi_rel_l2']:.2e}, displacement "
+              f"{vs_oracle['disp_max_abs_mpc_h']:.2e} Mpc/h", file=sys.stderr, flush=True)
         if args.cpu_full:
             cpu = {"value": 1.0 / t_s, "unit": "recons/s", "cores": workers, "kind": "oracle",
                    "host_cpu_count": os.cpu_count(),
@@ -578,6 +618,9 @@ def main():
                    "touched_bricks": {"galaxies": bricks_g, "randoms": bricks_r, "of": (args.n // BRICK) ** 3}},
         "starts": {k: {kk: vv for kk, vv in v.items() if kk != "elapsed"} for k, v in results.items()},
         "step_return_codes": {str(k): v for k, v in codes.items()},
+        # starts named *_relaxed run the relaxed correction pass, an option beyond the paper (its fixed point)
+        "relaxed_pass": "D_{n+1} = (1 - w) D_n + w (D_s + f div[(Psi_n . r) r]), w = 2/(2 + f/b); the first pass "
+                        "after the learned start is the paper's pass",
         # the paper's own figures for this method (Sec. 5.2, Tables 2-3), as context: correction passes to
         # convergence of the mean radial ratio against the true field on a BOSS DR11 CMASS mock (NGP, 512^3,
         # L = 3500 Mpc/h, R = 10 Mpc/h, b = 1.87) and an N-body box (128^3, L = 768 Mpc/h); no timings or
@@ -587,6 +630,8 @@ def main():
         "roofline": roofline,
         "copy_GBs": round(copy_gbs, 1),
         "cpu_baseline": cpu,
+        # this run's error against the oracle, on the oracle's timed sample (the same catalogue generator)
+        "vs_oracle": vs_oracle,
         "stages": stages,
     }
     if batched:

@@ -89,6 +89,13 @@ extern "C" {
                                       GEMM with split-bfloat16 operands (2 terms, 3 products, about
                                       2^-16 relative per product); n >= 64, other steps stay FP32      */
 #define RECON_FFT_SPLITBF16_X3 256u  /* as RECON_FFT_SPLITBF16 with 3 terms (6 products, about 2^-24)  */
+#define RECON_RELAXED 1024u        /* relaxed correction pass (not in the paper): D_{n+1} = (1 - w) D_n +
+                                      w (D_s + f div[(Psi_n . r) r]) with w = 2/(2 + beta), beta = f/b.
+                                      The pass of Sec. 5.1 has real eigenvalues in [-beta, 0] (the RSD
+                                      term is -beta times a projection seen through k'/|k|), so this w
+                                      shrinks the error by beta/(2 + beta) per pass instead of up to
+                                      beta; the fixed point (eq. Nusser) is the same.  The first pass
+                                      after an FFTA or learned start is the plain pass.                */
 
 /* paint flags */
 #define RECON_PAINT_ACCUMULATE 1u  /* add to the grid instead of replacing it */
@@ -109,7 +116,7 @@ typedef struct {
   double smooth_r;         /* R >= 0 [Mpc/h] (Sec. 3.1 smoothing)                                        */
   double mask_tau;         /* mask threshold as a fraction of the mean 27-cell random sum (>= 0)          */
   uint32_t flags;          /* RECON_NO_RANDOMS | RECON_KEEP_DELTA | RECON_START_BUFFERS | RECON_PASS_GRAPHS |
-                              RECON_LOGNORMAL | RECON_FFT_SPLITBF16[_X3]
+                              RECON_LOGNORMAL | RECON_FFT_SPLITBF16[_X3] | RECON_RELAXED
                               (| RECON_CNN_BUFFERS | RECON_CNN_HALF, recon_cnn.h)                        */
   int64_t max_objects;     /* largest catalogue painted in one call that uses the brick-binned deposit
                               (workspace holds 36 B per object for it: the brick-ordered copy, each

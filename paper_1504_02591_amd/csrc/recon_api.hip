@@ -67,7 +67,7 @@ bool valid_params(const recon_params_t* p, std::string* why) {
   if (!(p->mask_tau >= 0.0) || !std::isfinite(p->mask_tau)) return fail("mask_tau must be >= 0 and finite");
   if (p->flags & ~(RECON_NO_RANDOMS | RECON_KEEP_DELTA | RECON_START_BUFFERS | RECON_CNN_BUFFERS | RECON_CNN_HALF |
                    RECON_PASS_GRAPHS | RECON_LOGNORMAL | RECON_FFT_SPLITBF16 | RECON_FFT_SPLITBF16_X3 |
-                   RECON_CNN_QUARTER))
+                   RECON_CNN_QUARTER | RECON_RELAXED))
     return fail("unknown flag");
   if ((p->flags & RECON_FFT_SPLITBF16) && (p->flags & RECON_FFT_SPLITBF16_X3))
     return fail("RECON_FFT_SPLITBF16 and RECON_FFT_SPLITBF16_X3 exclude each other");
@@ -104,7 +104,7 @@ Layout make_layout(const recon_params_t* p) {
   L.w2 = take(b * cn * 8);
   L.ds = take(b * cn * 8);
   L.dn = take(b * cn * 8);
-  L.psi = take(b * n3 * 16);
+  L.psi = take(b * n3 * 12);
   L.delta = (p->flags & RECON_KEEP_DELTA) ? take(b * n3 * 4) : 0;
   L.corr = (p->flags & RECON_START_BUFFERS) ? take(b * n3 * 4) : 0;
   L.tw = take(n * 8);
@@ -264,7 +264,7 @@ struct recon_plan_s {
   long long *grid_g = nullptr, *grid_r = nullptr;
   unsigned char* mask = nullptr;
   float2 *w0 = nullptr, *w1 = nullptr, *w2 = nullptr, *ds = nullptr, *dn = nullptr, *tw = nullptr;
-  float4* psi = nullptr;
+  float* psi = nullptr;   // planar [batch][3][N^3]
   float *delta = nullptr, *corr = nullptr;
   double *partials = nullptr, *red = nullptr;
   unsigned long long* totals = nullptr;
@@ -393,8 +393,8 @@ struct Ops {
   int (*fanout)(recon_plan_t*, const int*, bool comb);   // comb: combined state Y for the z iteration
   int (*combine)(recon_plan_t*, const int*);              // full state Y -> combined state Y
   int (*ziter)(recon_plan_t*, int mode, const int*);
-  int (*fanin_xiter)(recon_plan_t*, bool first, const int*);
-  int (*zfinal)(recon_plan_t*, float4* psi, float* u, bool cross, const int*, bool comb);
+  int (*fanin_xiter)(recon_plan_t*, bool first, const int*, float omega);
+  int (*zfinal)(recon_plan_t*, float* psi, float* u, bool cross, const int*, bool comb);
   int (*refan)(recon_plan_t*, const int*, const float2* d);  // state X again from the spectrum d
   int (*helm)(recon_plan_t*, const float*);  // fan-out of the Helmholtz projection of a real field
   int nb_x, nb_z;
@@ -424,6 +424,12 @@ int scalars_and_mask(recon_plan_t* pl, int nblk_z) {
     RECON_TRY(check_launch(pl, "mask"));
   }
   return RECON_OK;
+}
+
+// Weight of the relaxed pass (RECON_RELAXED): 2/(2 + beta); 1 (the plain pass) without the flag.
+float relax_weight(const recon_plan_t* pl) {
+  if (!(pl->p.flags & RECON_RELAXED)) return 1.f;
+  return (float)(2.0 / (2.0 + pl->p.growth / pl->p.bias));
 }
 
 // Lognormal option (RECON_LOGNORMAL): clamp of 1 + delta_s before the logarithm, 0 when off.
@@ -619,7 +625,7 @@ struct SizeOps {
     return RECON_OK;
   }
 
-  static int fanin_xiter(recon_plan_t* pl, bool first, const int* act) {
+  static int fanin_xiter(recon_plan_t* pl, bool first, const int* act, float omega) {
     hipStream_t s = pl->stream;
     {
       PROF(pl, KP_Y_FANIN);
@@ -629,7 +635,7 @@ struct SizeOps {
     {
       PROF(pl, KP_X_ITER);
       k_x_iter<N><<<gx(pl), dim3(TX), 0, s>>>(pl->w0, pl->w1, pl->ds, first ? pl->ds : pl->dn, pl->dn,
-                                                     pl->geo, pl->partials, act, pl->tw);
+                                                     pl->geo, pl->partials, act, pl->tw, omega);
     }
     RECON_TRY(check_launch(pl, "x iteration"));
     {
@@ -639,7 +645,7 @@ struct SizeOps {
     return check_launch(pl, "reduce (norm)");
   }
 
-  static int zfinal(recon_plan_t* pl, float4* psi, float* u, bool cross, const int* act, bool comb) {
+  static int zfinal(recon_plan_t* pl, float* psi, float* u, bool cross, const int* act, bool comb) {
     hipStream_t s = pl->stream;
     if (comb && (psi || cross)) return fail(pl, RECON_EINVAL, "internal: the combined state gives u only");
     {
@@ -787,7 +793,7 @@ int pass_graph_launch(recon_plan_t* pl, const Ops* ops) {
     }
     rc = ops->fanout(pl, pl->act_fan, true);
     if (rc == RECON_OK) rc = ops->ziter(pl, ZI_PLAIN, pl->act_it);
-    if (rc == RECON_OK) rc = ops->fanin_xiter(pl, false, pl->act_it);
+    if (rc == RECON_OK) rc = ops->fanin_xiter(pl, false, pl->act_it, relax_weight(pl));
     const hipError_t ec = hipStreamEndCapture(pl->cap_stream, &graph);
     pl->stream = keep;
     if (rc != RECON_OK) {
@@ -866,7 +872,7 @@ int plan_create(recon_plan_t** out, const recon_params_t* params, const Layout& 
   pl->w2 = (float2*)(w + L.w2);
   pl->ds = (float2*)(w + L.ds);
   pl->dn = (float2*)(w + L.dn);
-  pl->psi = (float4*)(w + L.psi);
+  pl->psi = (float*)(w + L.psi);
   pl->delta = (params->flags & RECON_KEEP_DELTA) ? (float*)(w + L.delta) : nullptr;
   pl->corr = (params->flags & RECON_START_BUFFERS) ? (float*)(w + L.corr) : nullptr;
   pl->tw = (float2*)(w + L.tw);
@@ -1500,7 +1506,8 @@ int recon_iterate(recon_plan_t* pl, int max_iter, double tol, int32_t* iters_out
       if (!rest) continue;
       RECON_TRY(upload_mask(pl, pl->act_it, pl->h_it));
     }
-    if (!graph) RECON_TRY(ops->fanin_xiter(pl, first, pl->act_it));
+    // relaxed passes mix with D_n; the first pass after a non-gradient start has no D_0 and is plain
+    if (!graph) RECON_TRY(ops->fanin_xiter(pl, first, pl->act_it, start_pass ? 1.f : relax_weight(pl)));
     // the start pass also reads S1, S2 (red[2B..4B)): one copy of both halves
     HIP_TRY(pl, hipMemcpyAsync(pl->h_red.data(), pl->red, (start_pass ? 32 : 16) * B, hipMemcpyDeviceToHost,
                                pl->stream));
@@ -1615,10 +1622,10 @@ int recon_get_psi(recon_plan_t* pl, float* psi_out) {
   if (pl->state != ST_SOLVED) return fail(pl, RECON_ESTATE, "no displacement yet");
   for (int b = 0; b < pl->batch; ++b)
     if (!pl->psi_valid[b]) return fail(pl, RECON_ESTATE, "displacement not computed; call iterate");
-  long long blocks = (pl->n3 * pl->batch + kThreads - 1) / kThreads;
-  if (blocks > 65536) blocks = 65536;
-  k_psi_planar<<<(unsigned)blocks, kThreads, 0, pl->stream>>>(pl->psi, pl->n, pl->batch, psi_out);
-  return check_launch(pl, "psi copy");
+  // the plan keeps the displacement in the output's layout
+  HIP_TRY(pl, hipMemcpyAsync(psi_out, pl->psi, sizeof(float) * 3 * (size_t)pl->n3 * pl->batch,
+                             hipMemcpyDeviceToDevice, pl->stream));
+  return RECON_OK;
 }
 
 int recon_get_grid(recon_plan_t* pl, int which, int64_t* out) {

@@ -620,8 +620,8 @@ __global__ void __launch_bounds__(256) k_adam(float* __restrict__ th, float* __r
   }
 }
 
-// u = Psi . r_hat from the interleaved displacement (psi_slot order).
-__global__ void __launch_bounds__(256) k_radial(const float4* __restrict__ psi4, Geo3 g, int batch,
+// u = Psi . r_hat from the displacement (planar [b][3][N^3]).
+__global__ void __launch_bounds__(256) k_radial(const float* __restrict__ psi, Geo3 g, int batch,
                                                 float* __restrict__ u) {
   const long long n3 = (long long)g.n * g.n * g.n;
   for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n3 * batch; i += (long long)gridDim.x * 256) {
@@ -631,8 +631,8 @@ __global__ void __launch_bounds__(256) k_radial(const float4* __restrict__ psi4,
                 rz = fmaf(g.hs, (float)z, g.ds[2]);
     const float r2 = rx * rx + ry * ry + rz * rz;
     const float ir = r2 > 0.f ? rsqrtf(r2) : 0.f;
-    const float4 p = psi4[(i - c) + psi_slot(x, y, z, g.n)];
-    u[i] = (rx * p.x + ry * p.y + rz * p.z) * ir;
+    const float* p = psi + 3 * (i - c);
+    u[i] = (rx * p[c] + ry * p[n3 + c] + rz * p[2 * n3 + c]) * ir;
   }
 }
 

@@ -42,18 +42,9 @@ struct CicGeo {
 
 enum ZIterMode { ZI_PLAIN = 0, ZI_FFTA = 1, ZI_LEARNED = 2, ZI_CROSS = 3 };
 
-// Storage slot of node (x, y, z) in the displacement buffer (float4 per node): 2 x 2 x 2 bricks, one
-// 128-byte line each, in [z/2][y/2][x/2] order, nodes inside a brick in (z&1, y&1, x&1) order.  The
-// eight nodes of a CIC stencil then span 3.4 lines on average instead of 4.5 in [z][y][x] rows,
-// which is what the random-access shift pays for.
-__device__ __forceinline__ long long psi_slot(int x, int y, int z, int n) {
-  const int h = n >> 1;
-  return ((((long long)(z >> 1) * h + (y >> 1)) * h + (x >> 1)) << 3) | ((z & 1) << 2) | ((y & 1) << 1) | (x & 1);
-}
-// the same for a linear cell index c = (z n + y) n + x
-__device__ __forceinline__ long long psi_slot(long long c, int n) {
-  return psi_slot((int)(c % n), (int)((c / n) % n), (int)(c / ((long long)n * n)), n);
-}
+// The displacement buffer is planar, [b][3][N^3] floats with x fastest (the layout recon_get_psi
+// hands out): the final z pass then writes whole 128-byte lines (a tile's 32 consecutive x of one
+// component), 12 bytes per node, and the shift reads each component's rows.
 
 // Tile shapes (compile-time tuning knobs from recon_tuning.h): packed z columns, y-pass columns,
 // x-pass rows.  Each block runs one radix-8 fragment per thread, (N/8) * tile threads.
@@ -921,7 +912,7 @@ template <int N> constexpr int ntx() { return frag_threads<N, wx<N>()>(); }
 // Forward z transform of int64 grids (units 2^-32) into half spectra.
 // Also writes the exact totals {sum g0, sum g1, #(g1 != 0)} of the tile to tpart[b][block].
 template <int N, int NA>
-__global__ void __launch_bounds__(ntz<N>()) k_z_fwd_grid(const long long* __restrict__ g0,
+__global__ void __launch_bounds__(ntz<N>(), 8) k_z_fwd_grid(const long long* __restrict__ g0,
                                                          const long long* __restrict__ g1, float2* __restrict__ o0,
                                                          float2* __restrict__ o1, unsigned long long* __restrict__ tpart,
                                                          const float2* __restrict__ twg,
@@ -1409,12 +1400,12 @@ __global__ void __launch_bounds__(1024) k_z_iter_w(float2* __restrict__ a0, floa
 }
 
 // Inverse z of the displacement spectra.  Full state (COMB = false, a0..a2 = Psi_x, Psi_y, Psi_z):
-// writes Psi interleaved as float4 (x, y, z, 0) per node in psi_slot order (when psi4 != null), u = Psi . r_hat (when
-// u_out != null) and accumulates S3 = sum corr * u (when corr != null).  Combined state (COMB = true,
-// a0 = r_x Psi_x + r_y Psi_y, a2 = Psi_z): writes u only (psi4 and corr must be null).
+// writes Psi (planar [b][3][N^3], when psi != null), u = Psi . r_hat (when u_out != null) and accumulates
+// S3 = sum corr * u (when corr != null).  Combined state (COMB = true, a0 = r_x Psi_x + r_y Psi_y,
+// a2 = Psi_z): writes u only (psi and corr must be null).
 template <int N, bool COMB>
 __global__ void __launch_bounds__(ntz<N>()) k_z_final(const float2* __restrict__ a0, const float2* __restrict__ a1,
-                                                      const float2* __restrict__ a2, Geo g, float4* __restrict__ psi4,
+                                                      const float2* __restrict__ a2, Geo g, float* __restrict__ psi,
                                                       float* __restrict__ u_out, const float* __restrict__ corr,
                                                       double* __restrict__ partials, const int* __restrict__ active,
                                                       const float2* __restrict__ twg) {
@@ -1461,11 +1452,17 @@ __global__ void __launch_bounds__(ntz<N>()) k_z_final(const float2* __restrict__
     for (int r = 0; r < 8; ++r) {
       const int z = j + r * (N / 8);
       const long long cell = b * n3 + ((long long)z * N + y) * N + x0 + c;
-      if (!COMB && psi4) {
-        float4* pb = psi4 + b * n3;
-        const long long s0 = psi_slot(x0 + c, y, z, N), s1 = psi_slot(x0 + c + WP, y, z, N);
-        if (in_bounds(s0, n3)) pb[s0] = make_float4(px[r].x, py[r].x, v[r].x, 0.f);
-        if (in_bounds(s1, n3)) pb[s1] = make_float4(px[r].y, py[r].y, v[r].y, 0.f);
+      if (!COMB && psi) {
+        float* pb = psi + 3 * b * n3;
+        const long long c0 = cell - b * n3, c1 = c0 + WP;
+        if (in_bounds(c1, n3)) {
+          pb[c0] = px[r].x;
+          pb[c1] = px[r].y;
+          pb[n3 + c0] = py[r].x;
+          pb[n3 + c1] = py[r].y;
+          pb[2 * n3 + c0] = v[r].x;
+          pb[2 * n3 + c1] = v[r].y;
+        }
       }
       if (u_out || (!COMB && corr)) {
         const float rz = los_comp(g, 2, z);
@@ -1501,7 +1498,7 @@ __global__ void __launch_bounds__(ntz<N>()) k_z_final(const float2* __restrict__
 // Psi . r != 0 and lo <= q <= hi contribute q and q^2 (FP64 block sums into part[2 blk..]) and
 // one count (cnt[blk]).  psi_ref: planar [b][3][n^3]; blockIdx.y = realisation.
 template <int NT>
-__global__ void __launch_bounds__(NT) k_ratio_stats(const float4* __restrict__ psi4, const float* __restrict__ psi_ref,
+__global__ void __launch_bounds__(NT) k_ratio_stats(const float* __restrict__ psi, const float* __restrict__ psi_ref,
                                                     Geo g, int n, double lo, double hi, double* __restrict__ part,
                                                     unsigned long long* __restrict__ cnt) {
   const long long n3 = (long long)n * n * n;
@@ -1511,10 +1508,10 @@ __global__ void __launch_bounds__(NT) k_ratio_stats(const float4* __restrict__ p
   for (long long i = blockIdx.x * (long long)NT + threadIdx.x; i < n3; i += (long long)gridDim.x * NT) {
     const int x = (int)(i % n), y = (int)((i / n) % n), z = (int)(i / ((long long)n * n));
     const float rx = los_comp(g, 0, x), ry = los_comp(g, 1, y), rz = los_comp(g, 2, z);
-    const float4 p = psi4[b * n3 + psi_slot(x, y, z, n)];
+    const float* p = psi + b * 3 * n3;
     const float* q = psi_ref + b * 3 * n3;
     const double a = (double)rx * q[i] + (double)ry * q[n3 + i] + (double)rz * q[2 * n3 + i];
-    const double d = (double)rx * p.x + (double)ry * p.y + (double)rz * p.z;
+    const double d = (double)rx * p[i] + (double)ry * p[n3 + i] + (double)rz * p[2 * n3 + i];
     if (d != 0.0) {
       const double r = a / d;
       if (r >= lo && r <= hi) {
@@ -1538,20 +1535,6 @@ __global__ void __launch_bounds__(NT) k_ratio_stats(const float4* __restrict__ p
     part[2 * blk] = t1;
     part[2 * blk + 1] = t2;
     cnt[blk] = tc;
-  }
-}
-
-// Interleaved displacement (float4 per node, psi_slot order) -> planar [b][3][N^3].
-__global__ void __launch_bounds__(256) k_psi_planar(const float4* __restrict__ psi4, int n, int batch,
-                                                    float* __restrict__ out) {
-  const long long n3 = (long long)n * n * n, total = n3 * batch;
-  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
-       i += (long long)gridDim.x * blockDim.x) {
-    const long long b = i / n3, c = i - b * n3;
-    const float4 v = psi4[b * n3 + psi_slot(c, n)];
-    out[(b * 3 + 0) * n3 + c] = v.x;
-    out[(b * 3 + 1) * n3 + c] = v.y;
-    out[(b * 3 + 2) * n3 + c] = v.z;
   }
 }
 
@@ -1880,14 +1863,14 @@ __global__ void __launch_bounds__(ntx<N>()) k_x_refan(float2* __restrict__ a0, f
 
 // Helmholtz split output: irrotational = -Psi (the fan-out of the HELM start), solenoidal =
 // f x - irrotational; planar [b][3][n^3]; sol may be null.
-__global__ void __launch_bounds__(256) k_helm_out(const float4* __restrict__ psi4, const float* __restrict__ f,
+__global__ void __launch_bounds__(256) k_helm_out(const float* __restrict__ psi, const float* __restrict__ f,
                                                   int n, int batch, float* __restrict__ irr,
                                                   float* __restrict__ sol) {
   const long long n3 = (long long)n * n * n;
   for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n3 * batch; i += (long long)gridDim.x * 256) {
     const long long b = i / n3, c = i - b * n3;
-    const float4 p = psi4[b * n3 + psi_slot(c, n)];
-    const float ix = -p.x, iy = -p.y, iz = -p.z;
+    const float* p = psi + b * 3 * n3;
+    const float ix = -p[c], iy = -p[n3 + c], iz = -p[2 * n3 + c];
     irr[(b * 3 + 0) * n3 + c] = ix;
     irr[(b * 3 + 1) * n3 + c] = iy;
     irr[(b * 3 + 2) * n3 + c] = iz;
@@ -1900,7 +1883,8 @@ __global__ void __launch_bounds__(256) k_helm_out(const float4* __restrict__ psi
 }
 
 // One iteration's k-space step:
-//   div = i k'_x X[a0] + X[a1];  D_{n+1} = D_s + f div  (stored to dnext)
+//   div = i k'_x X[a0] + X[a1];  D_{n+1} = D_s + f div  (stored to dnext); with a relaxation weight
+//   omega != 1, D_{n+1} = D_n + omega (D_s + f div - D_n)
 //   partial sums of  sum w k'^2 |D_{n+1} - D_n|^2 / k^4  and  sum w k'^2 |D_{n+1}|^2 / k^4
 //   (w = 2 inside the halved kz axis) -> convergence norm by Parseval
 //   P = D_{n+1} / (b k^2 N^3);  a0 <- X^-1[i k'_x P],  a1 <- X^-1[P]
@@ -1909,7 +1893,8 @@ template <int N>
 __global__ void __launch_bounds__(ntx<N>()) k_x_iter(float2* __restrict__ a0, float2* __restrict__ a1,
                                                      const float2* __restrict__ ds, const float2* dprev,
                                                      float2* dnext, Geo g, double* __restrict__ partials,
-                                                     const int* __restrict__ active, const float2* __restrict__ twg) {
+                                                     const int* __restrict__ active, const float2* __restrict__ twg,
+                                                     float omega) {
   constexpr int NT = ntx<N>(), W = wx<N>();
   using L = Lay<N, W, true>;
   const int b = blockIdx.y;
@@ -1939,8 +1924,9 @@ __global__ void __launch_bounds__(ntx<N>()) k_x_iter(float2* __restrict__ a0, fl
       const float2 div = mul_i(xa[r]) * dx + v[r];
       const long long idx = row * N + kx;
       const float2 dsv = ds[idx];
-      const float2 dn = make_float2(fmaf(g.growth, div.x, dsv.x), fmaf(g.growth, div.y, dsv.y));
       const float2 dp = dprev[idx];
+      float2 dn = make_float2(fmaf(g.growth, div.x, dsv.x), fmaf(g.growth, div.y, dsv.y));
+      if (omega != 1.f) dn = make_float2(fmaf(omega, dn.x - dp.x, dp.x), fmaf(omega, dn.y - dp.y, dp.y));
       dnext[idx] = dn;
       if (k2 > 0.f) {
         const float wgt = (kzi == 0 || kzi == N / 2) ? 1.f : 2.f;
@@ -2048,15 +2034,16 @@ __device__ __forceinline__ void shift_one_f(float px, float py, float pz, const 
   d[2] = d2;
 }
 
-// The same from the displacement in memory (float4 per node in psi_slot order).
-__device__ __forceinline__ void shift_one(float px, float py, float pz, const float uu[3], const float4* __restrict__ pb,
+// The same from the displacement in memory (planar, one realisation's [3][N^3]).
+__device__ __forceinline__ void shift_one(float px, float py, float pz, const float uu[3], const float* __restrict__ pb,
                                           const CicGeo& cg, float ox, float oy, float oz, float growth,
                                           int galaxies, float d[3]) {
   const int m = cg.n - 1, n = cg.n;
+  const long long n3 = (long long)n * n * n;
   shift_one_f(px, py, pz, uu,
               [&](int dx, int dy, int dz, const int ii[3]) {
-                const long long sl = psi_slot((ii[0] + dx) & m, (ii[1] + dy) & m, (ii[2] + dz) & m, n);
-                return in_bounds(sl, (long long)n * n * n) ? pb[sl] : float4{};
+                const long long c = (((long long)((ii[2] + dz) & m) * n + ((ii[1] + dy) & m)) * n) + ((ii[0] + dx) & m);
+                return in_bounds(c, n3) ? make_float4(pb[c], pb[n3 + c], pb[2 * n3 + c], 0.f) : float4{};
               },
               cg, ox, oy, oz, growth, galaxies, d);
 }
@@ -2076,7 +2063,7 @@ __device__ __forceinline__ bool shift_coords(float px, float py, float pz, const
 
 __global__ void __launch_bounds__(256) k_shift(const float* __restrict__ pos, long long n,
                                                const long long* __restrict__ off, int batch,
-                                               const float4* __restrict__ psi4, CicGeo cg, float ox, float oy,
+                                               const float* __restrict__ psi, CicGeo cg, float ox, float oy,
                                                float oz, float growth, int galaxies, float* __restrict__ disp,
                                                float* __restrict__ pos_out, int* __restrict__ err) {
   const long long n3 = (long long)cg.n * cg.n * cg.n;
@@ -2092,7 +2079,7 @@ __global__ void __launch_bounds__(256) k_shift(const float* __restrict__ pos, lo
     }
     const int b = off ? find_realisation(off, batch, i) : 0;
     float d[3];
-    shift_one(px, py, pz, uu, psi4 + (long long)b * n3, cg, ox, oy, oz, growth, galaxies, d);
+    shift_one(px, py, pz, uu, psi + 3 * (long long)b * n3, cg, ox, oy, oz, growth, galaxies, d);
     disp[3 * i] = d[0];
     disp[3 * i + 1] = d[1];
     disp[3 * i + 2] = d[2];
@@ -2105,12 +2092,12 @@ __global__ void __launch_bounds__(256) k_shift(const float* __restrict__ pos, lo
 }
 
 // The brick-order shift with one block per 16^3 brick: the block stages the displacement at the
-// 18^3 nodes its objects' stencils can reach (the brick's 9^3 2x2x2 node bricks, components stored
-// apart) in LDS, then interpolates every object of the brick from LDS.  Same arithmetic as k_shift.
+// 18^3 nodes its objects' stencils can reach (rows of 18 consecutive x per component) in LDS, then
+// interpolates every object of the brick from LDS.  Same arithmetic as k_shift.
 template <int NT>
 __global__ void __launch_bounds__(NT) k_shift_brick(const float4* __restrict__ sorted,
                                                     const unsigned* __restrict__ start,
-                                                    const float4* __restrict__ psi4, CicGeo cg, float ox, float oy,
+                                                    const float* __restrict__ psi, CicGeo cg, float ox, float oy,
                                                     float oz, float growth, int galaxies,
                                                     float4* __restrict__ tmp) {
   constexpr int F = kBrick + 2, F3 = F * F * F;
@@ -2125,19 +2112,17 @@ __global__ void __launch_bounds__(NT) k_shift_brick(const float4* __restrict__ s
   const long long kk = key - (long long)b * per;
   const int bx = (int)(kk % nbs) * kBrick, by = (int)((kk / nbs) % nbs) * kBrick,
             bz = (int)(kk / ((long long)nbs * nbs)) * kBrick;
-  const float4* pb = psi4 + (long long)b * n * n * n;
+  const long long n3 = (long long)n * n * n;
+  const float* pb = psi + 3 * (long long)b * n3;
   // node (lx, ly, lz) of the footprint is grid node (bx + lx, by + ly, bz + lz), wrapped; consecutive
-  // threads take the eight nodes of one 2x2x2 node brick (one 128-byte line) in turn
-  for (int i = threadIdx.x; i < F3; i += NT) {
-    const int q = i >> 3, r = i & 7;
-    const int lx = 2 * (q % (F / 2)) + (r & 1), ly = 2 * ((q / (F / 2)) % (F / 2)) + ((r >> 1) & 1),
-              lz = 2 * (q / ((F / 2) * (F / 2))) + (r >> 2);
-    const long long sl = psi_slot((bx + lx) & m, (by + ly) & m, (bz + lz) & m, n);
-    const float4 v = in_bounds(sl, (long long)n * n * n) ? pb[sl] : float4{};
-    const int l = (lz * F + ly) * F + lx;
-    px_[l] = v.x;
-    py_[l] = v.y;
-    pz_[l] = v.z;
+  // threads take consecutive x of one row
+  for (int l = threadIdx.x; l < F3; l += NT) {
+    const int lx = l % F, ly = (l / F) % F, lz = l / (F * F);
+    const long long c = (((long long)((bz + lz) & m) * n + ((by + ly) & m)) * n) + ((bx + lx) & m);
+    const bool ok = in_bounds(c, n3);
+    px_[l] = ok ? pb[c] : 0.f;
+    py_[l] = ok ? pb[n3 + c] : 0.f;
+    pz_[l] = ok ? pb[2 * n3 + c] : 0.f;
   }
   __syncthreads();
   constexpr int U = kObjBatch;

@@ -23,6 +23,7 @@ START_PLAIN, START_FFTA1, START_FFTA2, START_LEARNED = 0, 1, 2, 3
 NO_RANDOMS, KEEP_DELTA, START_BUFFERS, CNN_BUFFERS, CNN_HALF, PASS_GRAPHS, LOGNORMAL = 1, 2, 4, 8, 16, 32, 64
 FFT_SPLITBF16, FFT_SPLITBF16_X3 = 128, 256
 CNN_QUARTER = 512
+RELAXED = 1024
 CNN_PARAMS = 10833
 PAINT_ACCUMULATE, PAINT_NGP = 1, 2
 SHIFT_AS_PAINTED = 256
@@ -139,7 +140,7 @@ class Plan:
     def __init__(self, n, box_len, observer, bias, growth, smooth_r, origin=(0.0, 0.0, 0.0), batch=1,
                  mask_tau=0.1, randoms=True, keep_delta=False, start_buffers=False, max_objects=0, cnn=False,
                  cnn_half=False, graphs=False, lognormal=False, device=None, noalloc=False, split_terms=0,
-                 cnn_quarter=False, lib=None):
+                 cnn_quarter=False, relaxed=False, lib=None):
         """noalloc=True: the plan runs on the library's own device scratch (recon_plan_noalloc) instead of a
         workspace allocated here; a later no-allocation plan on the same device makes this one stale."""
         self.lib = load() if lib is None else lib    # lib: another build of the library, from load(path)
@@ -147,7 +148,8 @@ class Plan:
         flags = (0 if randoms else NO_RANDOMS) | (KEEP_DELTA if keep_delta else 0) | \
                 (START_BUFFERS if start_buffers else 0) | (CNN_BUFFERS if cnn else 0) | (CNN_HALF if cnn_half else 0) | \
                 (PASS_GRAPHS if graphs else 0) | (LOGNORMAL if lognormal else 0) | \
-                {0: 0, 2: FFT_SPLITBF16, 3: FFT_SPLITBF16_X3}[int(split_terms)] | (CNN_QUARTER if cnn_quarter else 0)
+                {0: 0, 2: FFT_SPLITBF16, 3: FFT_SPLITBF16_X3}[int(split_terms)] | (CNN_QUARTER if cnn_quarter else 0) | \
+                (RELAXED if relaxed else 0)
         p = Params()
         p.n, p.batch, p.box_len = int(n), int(batch), float(box_len)
         for a in range(3):

@@ -43,7 +43,7 @@ int main() {
                                 RECON_KEEP_DELTA | RECON_START_BUFFERS,
                                 RECON_KEEP_DELTA | RECON_START_BUFFERS | RECON_CNN_BUFFERS,
                                 RECON_KEEP_DELTA | RECON_START_BUFFERS | RECON_CNN_BUFFERS | RECON_CNN_HALF,
-                                RECON_PASS_GRAPHS | RECON_LOGNORMAL};
+                                RECON_PASS_GRAPHS | RECON_LOGNORMAL | RECON_RELAXED};
   const int batches[] = {1, 2, 7, 256};
   const int64_t objects[] = {0, 1000, (1LL << 32) - 1};
   for (int n = 8; n <= 1024; n *= 2)

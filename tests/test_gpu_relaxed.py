@@ -1,0 +1,238 @@
+"""The relaxed correction pass (RECON_RELAXED) against the FP64 oracle.
+
+D_{n+1} = (1 - w) D_n + w (D_s + f div[(Psi_n . r) r]), w = 2/(2 + beta): the same fixed point as the
+pass of Sec. 5.1 (eq. Nusser), reached with the error shrinking by beta/(2 + beta) per pass.  The
+oracle's relaxed iteration is pinned on the CPU (per-mode closed form for a distant observer, the
+dense direct solve of the discretised equation, the contraction bound); here the GPU path is checked
+against it: random fields at several sizes with near observers, the distant-observer closed form,
+survey catalogues end to end (grids bit-exact, Psi, eps, shifts), the FFTA-2 and learned starts
+(whose first pass is the plain pass), graph replays, and the pass counts to eps <= 1e-3.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import cnn_oracle as C
+from oracle import recon_oracle as O
+from synth import generators as G
+
+pytestmark = pytest.mark.gpu
+
+PSI_TOL = 1e-5
+DISP_TOL = 1e-4
+
+
+def to_dev(a):
+    return None if a is None else torch.from_numpy(np.ascontiguousarray(a)).to(torch.device("cuda", 0))
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / np.linalg.norm(b))
+
+
+def w_of(b, f):
+    return O.relax_weight(f, b)
+
+
+@pytest.mark.parametrize("n,observer", [(16, (-80.0, 130.0, 60.0)), (64, (-300.0, 100.0, 250.0)),
+                                        (256, (-50.0, 210.0, 190.0))])
+def test_relaxed_random_field_iterates_match_oracle(gpu_lib, n, observer):
+    from paper_1504_02591_amd import native
+    box, b, f = 400.0, 1.5, 0.6
+    rng = np.random.default_rng(300 + n)
+    delta = O.smooth(rng.standard_normal((n, n, n)), box, 2.5 * box / n).astype(np.float32)
+    for npass in (1, 3):
+        plan = native.Plan(n, box, observer, b, f, 0.0, randoms=False, relaxed=True)
+        plan.set_delta(to_dev(delta))
+        plan.solve()
+        rc, iters, eps = plan.iterate(npass, 0.0)
+        psi = plan.psi()[0].cpu().numpy()
+        plan.close()
+        ref = O.reconstruct_field(delta.astype(np.float64), box, (0, 0, 0), observer, b, f, n_passes=npass,
+                                  relax=w_of(b, f))
+        e = rel_l2(psi, ref["psi"])
+        print(f"relaxed n={n} passes={npass}: psi rel L2 {e:.2e}, eps {eps[0]} vs {ref['eps']}", flush=True)
+        assert iters[0] == npass
+        assert e < PSI_TOL
+        np.testing.assert_allclose(eps[0], ref["eps"], rtol=1e-4, atol=1e-6)
+
+
+def test_relaxed_distant_observer_closed_form_gpu(gpu_lib):
+    """Per mode D_n = D_inf + (1 - w (1 + beta mu'^2))^n (D_s - D_inf), D_inf = D_s / (1 + beta mu'^2)."""
+    from paper_1504_02591_amd import native
+    n, box, b, f = 32, 400.0, 2.0, 0.74
+    beta, w = f / b, w_of(2.0, 0.74)
+    rng = np.random.default_rng(37)
+    delta = O.smooth(rng.standard_normal((n, n, n)), box, 30.0).astype(np.float32)
+    obs = [box / 2] * 3
+    obs[1] -= 1e9 * box
+    plan = native.Plan(n, box, obs, b, f, 0.0, randoms=False, relaxed=True)
+    plan.set_delta(to_dev(delta))
+    plan.solve()
+    plan.iterate(3, 0.0)
+    psi = plan.psi()[0].cpu().numpy()
+    plan.close()
+    m = np.fft.fftfreq(n, d=1.0 / n)
+    kk = [(2 * np.pi / box) * m.reshape(1, 1, -1), (2 * np.pi / box) * m.reshape(1, -1, 1),
+          (2 * np.pi / box) * m.reshape(-1, 1, 1)]
+    mm = [m.reshape(1, 1, -1), m.reshape(1, -1, 1), m.reshape(-1, 1, 1)]
+    dk = [np.where(np.abs(a) == n // 2, 0.0, k) for a, k in zip(mm, kk)]
+    k2 = kk[0] ** 2 + kk[1] ** 2 + kk[2] ** 2
+    with np.errstate(invalid="ignore", divide="ignore"):
+        mu2 = np.where(k2 > 0, dk[1] ** 2 / k2, 0.0)
+        ds = np.fft.fftn(delta.astype(np.float64))
+        d_inf = ds / (1 + beta * mu2)
+        dn = d_inf + (1 - w * (1 + beta * mu2)) ** 3 * (ds - d_inf)
+        pot = np.where(k2 > 0, dn / (b * k2), 0.0)
+    expect = np.stack([np.real(np.fft.ifftn(1j * dk[j] * pot)) for j in range(3)])
+    assert rel_l2(psi, expect) < PSI_TOL
+
+
+def catalogue_run(native, cat, n_passes, start=0, net=None, levels=0, tol=0.0, graphs=False):
+    lrn = start == native.START_LEARNED
+    plan = native.plan_for(cat, keep_delta=True, start_buffers=start != 0, cnn=lrn,
+                           cnn_half=lrn and levels == 1, cnn_quarter=lrn and levels == 2, relaxed=True,
+                           graphs=graphs)
+    gal, ran = to_dev(cat.gal_pos), to_dev(cat.ran_pos)
+    plan.paint(native.GAL, gal)
+    plan.paint(native.RAN, ran)
+    plan.solve(start, None if net is None else to_dev(net))
+    rc, iters, eps = plan.iterate(n_passes, tol)
+    out = dict(rc=rc, iters=iters[0], eps=eps[0], psi=plan.psi()[0].cpu().numpy(), restarts=plan.restarts()[0],
+               grid_g=plan.grid(native.GAL)[0].cpu().numpy(), grid_r=plan.grid(native.RAN)[0].cpu().numpy(),
+               disp_g=plan.shift(native.GAL, gal).cpu().numpy(), disp_r=plan.shift(native.RAN, ran).cpu().numpy())
+    plan.close()
+    return out
+
+
+def compare(g, r, cat, label):
+    assert np.array_equal(g["grid_g"], r["grid_g"]), f"{label}: galaxy grid not bit-exact"
+    assert np.array_equal(g["grid_r"], r["grid_r"]), f"{label}: random grid not bit-exact"
+    e_psi = rel_l2(g["psi"], r["psi"])
+    e_dg = float(np.abs(g["disp_g"] - r["disp_g"]).max())
+    e_dr = float(np.abs(g["disp_r"] - r["disp_r"]).max())
+    print(f"{label}: psi rel L2 {e_psi:.2e}, displacement galaxies {e_dg:.2e} randoms {e_dr:.2e}, "
+          f"eps {g['eps']} vs {r['eps']}", flush=True)
+    assert e_psi <= PSI_TOL and e_dg <= DISP_TOL and e_dr <= DISP_TOL
+    np.testing.assert_allclose(g["eps"], r["eps"], rtol=1e-4, atol=1e-6)
+
+
+def test_relaxed_survey_cone_end_to_end(gpu_lib):
+    from paper_1504_02591_amd import native
+    cat = G.config2(n=128, scale=0.25)
+    g = catalogue_run(native, cat, 4)
+    r = O.reconstruct(cat.gal_pos, None, cat.ran_pos, None, cat.n, cat.box_len, cat.origin, cat.observer,
+                      cat.bias, cat.growth, cat.smooth_r, cat.mask_tau, n_passes=4, relax=w_of(cat.bias, cat.growth))
+    compare(g, r, cat, "relaxed survey 128^3, 4 passes")
+
+
+def test_relaxed_ffta2_start(gpu_lib):
+    """The pass after the FFTA-2 start is the plain pass, the later ones are relaxed."""
+    from paper_1504_02591_amd import native
+    cat = G.lattice_box(32, 500.0, (-500.0, 250.0, 250.0), 0.7, 21, 22, ran_factor=3, bias=1.2, smooth_r=20.0)
+    for npass in (1, 2, 4):
+        g = catalogue_run(native, cat, npass, start=native.START_FFTA2)
+        r = O.reconstruct(cat.gal_pos, None, cat.ran_pos, None, cat.n, cat.box_len, cat.origin, cat.observer,
+                          cat.bias, cat.growth, cat.smooth_r, cat.mask_tau, n_passes=npass, start=O.START_FFTA2,
+                          relax=w_of(cat.bias, cat.growth))
+        compare(g, r, cat, f"relaxed FFTA-2, {npass} passes")
+
+
+def committed_network():
+    from paper_1504_02591_amd import learned
+    with np.load(learned.WEIGHTS, allow_pickle=False) as z:
+        levels = int(z["levels"]) if "levels" in z.files else (1 if bool(z["half"]) else 0)
+        return np.ascontiguousarray(z["params"], dtype=np.float32), levels
+
+
+def test_relaxed_learned_start_committed_network(gpu_lib):
+    """Survey geometry at 128^3 (the solver grid's cell size of the benchmark), the committed network on
+    its coarse grid, 1 and 3 passes: the first pass is the plain pass from the learned start."""
+    from paper_1504_02591_amd import native
+    cat = G.config2(n=128, scale=0.25, seeds=(81, 82, 83))
+    net, levels = committed_network()
+    grid_g = O.paint(cat.gal_pos, None, cat.n, cat.box_len, cat.origin)
+    grid_r = O.paint(cat.ran_pos, None, cat.n, cat.box_len, cat.origin)
+    delta = O.overdensity(grid_g, grid_r, cat.box_len, cat.smooth_r, cat.mask_tau)
+    rhat = O.line_of_sight(cat.n, cat.box_len, cat.origin, cat.observer)
+    u_p = np.sum(O.reconstruct_field(delta, cat.box_len, cat.origin, cat.observer, cat.bias, cat.growth,
+                                     n_passes=0)["psi"] * rhat, axis=0)
+    du = C.coarse_grid_correction(net.astype(np.float64), delta, u_p,
+                                  O.line_of_sight(cat.n >> levels, cat.box_len, cat.origin, cat.observer), levels,
+                                  bf16_mode=True, conv_fn=C.conv_loops)
+    for npass in (1, 3):
+        g = catalogue_run(native, cat, npass, start=native.START_LEARNED, net=net, levels=levels)
+        assert g["restarts"] == 0
+        r = O.reconstruct_field(delta, cat.box_len, cat.origin, cat.observer, cat.bias, cat.growth, n_passes=npass,
+                                start=O.START_LEARNED, start_correction=du, rhat=rhat,
+                                relax=w_of(cat.bias, cat.growth))
+        r["grid_g"], r["grid_r"] = grid_g, grid_r
+        r["disp_g"] = O.shift(r["psi"], cat.gal_pos, cat.box_len, cat.origin, cat.observer, cat.growth, True)
+        r["disp_r"] = O.shift(r["psi"], cat.ran_pos, cat.box_len, cat.origin, cat.observer, cat.growth, False)
+        # the network's bf16 ties make the learned start's tolerance that of the learned-start tests: a tie
+        # rounded the other way changes the correction by one bf16 ulp at a coarse node, which moves nearby
+        # objects by up to a few 1e-4 Mpc/h after the first pass; the passes after it damp that (by about
+        # beta/(2 + beta) each), so the displacement bar is checked after the third
+        e = rel_l2(g["psi"], r["psi"])
+        e_dg = float(np.abs(g["disp_g"] - r["disp_g"]).max())
+        e_dr = float(np.abs(g["disp_r"] - r["disp_r"]).max())
+        print(f"relaxed learned start, {npass} passes: psi rel L2 {e:.2e}, eps {g['eps']} vs {r['eps']}, "
+              f"displacement galaxies {e_dg:.2e} randoms {e_dr:.2e}", flush=True)
+        assert e < 1e-4
+        np.testing.assert_allclose(g["eps"], r["eps"], rtol=1e-3, atol=1e-5)
+        if npass >= 3:
+            assert e < PSI_TOL
+            assert e_dg <= DISP_TOL and e_dr <= DISP_TOL
+
+
+def test_relaxed_graph_replays_equal_eager(gpu_lib):
+    from paper_1504_02591_amd import native
+    cat = G.config2(n=64, scale=0.125, seeds=(91, 92, 93))
+    eager = catalogue_run(native, cat, 5, graphs=False)
+    graph = catalogue_run(native, cat, 5, graphs=True)
+    assert eager["eps"] == graph["eps"]
+    assert np.array_equal(eager["psi"], graph["psi"])
+
+
+def test_relaxed_needs_fewer_passes_to_tolerance(gpu_lib):
+    """Survey catalogue at 128^3: passes to eps <= 1e-3 with the relaxed pass against the paper's pass,
+    and the relaxed result is at least as close to the fixed point (the oracle's converged Psi)."""
+    from paper_1504_02591_amd import native
+    cat = G.config2(n=128, scale=0.25)
+    relaxed = catalogue_run(native, cat, 30, tol=1e-3)
+    plan = native.plan_for(cat)
+    gal, ran = to_dev(cat.gal_pos), to_dev(cat.ran_pos)
+    plan.paint(native.GAL, gal)
+    plan.paint(native.RAN, ran)
+    plan.solve()
+    rc, iters, eps = plan.iterate(30, 1e-3)
+    plain_psi = plan.psi()[0].cpu().numpy()
+    plan.close()
+    ref = O.reconstruct(cat.gal_pos, None, cat.ran_pos, None, cat.n, cat.box_len, cat.origin, cat.observer,
+                        cat.bias, cat.growth, cat.smooth_r, cat.mask_tau, n_passes=40)
+    e_relaxed, e_plain = rel_l2(relaxed["psi"], ref["psi"]), rel_l2(plain_psi, ref["psi"])
+    print(f"passes to 1e-3: relaxed {relaxed['iters']} (error {e_relaxed:.2e}), plain {iters[0]} "
+          f"(error {e_plain:.2e})", flush=True)
+    assert relaxed["rc"] == native.RECON_OK and rc == native.RECON_OK
+    assert relaxed["iters"] <= iters[0] - 2
+    assert e_relaxed <= e_plain
+
+
+def test_relaxed_full_size_pass_matches_oracle(gpu_lib):
+    """512^3, the benchmarked launch configuration: two relaxed passes from a survey-like field."""
+    from paper_1504_02591_amd import native
+    n, box, b, f = 512, 3500.0, 2.0, 0.74
+    obs = (1750.0, 1750.0, 1750.0)
+    delta, _ = G.linear_field(n, box, 78, want_psi=False, dtype=np.float32)
+    delta = delta.astype(np.float32)
+    plan = native.Plan(n, box, obs, b, f, 15.0, randoms=False, relaxed=True, graphs=True)
+    plan.set_delta(to_dev(delta))
+    plan.solve()
+    rc, iters, eps = plan.iterate(2, 0.0)
+    psi = plan.psi()[0].cpu().numpy()
+    plan.close()
+    ref = O.reconstruct_field(delta.astype(np.float64), box, (0, 0, 0), obs, b, f, n_passes=2, relax=w_of(b, f))
+    e = rel_l2(psi, ref["psi"])
+    print(f"512^3 two relaxed passes: psi rel L2 {e:.2e}, eps {eps[0]} vs {ref['eps']}", flush=True)
+    assert e < PSI_TOL
+    np.testing.assert_allclose(eps[0], ref["eps"], rtol=1e-4, atol=1e-6)
