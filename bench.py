@@ -56,11 +56,16 @@ def touched_bricks(pos, n, box_len):
     return int(out.sum())
 
 
-def algorithmic_bytes(n, n_gal, n_ran, randoms=True, keep_delta=False, bricks_g=None, bricks_r=None, levels=1):
+def algorithmic_bytes(n, n_gal, n_ran, randoms=True, keep_delta=False, bricks_g=None, bricks_r=None, levels=1,
+                      tiles=None):
     """Compulsory bytes of one launch of each kernel kind (inputs read once, outputs written once).
 
     cn = (N/2+1) N^2 complex spectrum elements (8 B), n3 = N^3 cells.  The int64 deposit grids are
     brick-sparse: only the touched bricks (bricks_g, bricks_r; all when None) are written and read.
+    tiles = (galaxy-grid tiles with data, random-grid tiles with data, tiles inside the mask, tiles) of
+    the setup transforms (recon_tile_counts; all tiles when None): the forward z pass writes, and the
+    forward y pass reads, only the grid tiles with data; the inverse y pass writes, the overdensity
+    step reads and writes, and the y pass of D_s reads only the tiles inside the mask.
     """
     n3 = n ** 3
     cn = (n // 2 + 1) * n * n * 8
@@ -68,6 +73,10 @@ def algorithmic_bytes(n, n_gal, n_ran, randoms=True, keep_delta=False, bricks_g=
     nbs3 = (n // BRICK) ** 3
     gb = (nbs3 if bricks_g is None else bricks_g) * BRICK ** 3 * 8      # galaxy grid bytes held
     rb = (nbs3 if bricks_r is None else bricks_r) * BRICK ** 3 * 8 if randoms else 0
+    if tiles is None:
+        fg, fr, fm = 1.0, (1.0 if randoms else 0.0), 1.0
+    else:
+        fg, fr, fm = tiles[0] / tiles[3], tiles[1] / tiles[3], tiles[2] / tiles[3]
     return {
         "z_iter": 4 * cn,                       # 2 spectra in (combined state), 2 out
         "y_fanout": 4 * cn,                     # 2 in, 2 out (combined); the output's full form: 2 in, 3 out
@@ -76,21 +85,25 @@ def algorithmic_bytes(n, n_gal, n_ran, randoms=True, keep_delta=False, bricks_g=
         "z_final": 3 * cn + 3 * n3 * 4,         # 3 spectra in, Psi (3 real fields) out
         "y_fanout_full": 5 * cn,
         "z_final_u": 2 * cn + n3 * 4,           # combined state in, u out (learned start)
-        "z_fwd_grid": gb + rb + na * cn,        # touched bricks of the int64 grids in, spectra out
+        "z_fwd_grid": gb + rb + (fg + fr) * cn,  # touched bricks of the int64 grids in, their tiles' spectra out
         "x_smooth": na * 2 * cn,
-        # dense-equivalent: tiles wholly outside the mask skip their spectrum reads
-        "z_delta": na * cn + (n3 if randoms else 0) + cn + (n3 * 4 if keep_delta else 0),
+        # inside the mask's tiles: the smoothed spectra and the mask in, the overdensity's spectrum out; the
+        # kept delta_s is written whole
+        "z_delta": (fm * (2 * cn + n3 + cn) if randoms else 2 * cn) + (n3 * 4 if keep_delta else 0),
         "x_start": cn + 3 * cn,
         "totals": na * n3 * 8,
-        "mask": rb + n3,                        # touched bricks of the random grid in, 1 B per cell out
+        # touched bricks of the random grid in, 1 B per cell out; the mask read again for its tile flags
+        "mask": rb + 2 * n3 if randoms else 0,
         "paint_grids": gb + rb,                 # touched bricks cleared and written (both catalogues)
         "paint": None,                          # per catalogue: 12 B per object + grid written once
         # per catalogue: 24 B per object (position in, displacement out) + the three Psi components at the
         # nodes the objects' stencils reach (the touched bricks) read once
         "shift": None,
         # per reconstruction (all launches of the stage together):
-        "y_fwd_step": (4 if randoms else 2) * cn + 2 * cn,   # y forward of the grids' spectra, then of D_s
-        "y_inv_step": (4 if randoms else 2) * cn,            # y inverse of the smoothed spectra
+        # y forward of the grids' spectra (tiles with data in, whole spectra out), then of delta_s
+        "y_fwd_step": (fg + fr) * cn + na * cn + (fm if randoms else 1.0) * cn + cn,
+        # y inverse of the smoothed spectra (whole spectra in, the mask's tiles out)
+        "y_inv_step": na * cn * (1.0 + (fm if randoms else 1.0)),
         # binning, both catalogues: positions read by the count and by the scatter, brick-ordered copy
         # (16 B) and slot (4 B) written, each block's 128 KB histogram written and read back
         "bin_step": 44 * (n_gal + n_ran) + 2 * 131072 * (bin_blocks(n_gal) + bin_blocks(n_ran)),
@@ -521,7 +534,7 @@ def main():
     eps_last = results[head]["eps"]
 
     # per-kernel event timing: a separate run of the headline start, so the timed run carries no events
-    prof = {}
+    prof, tiles = {}, None
     if not args.no_profile:
         start = start_of(head)[0]
         plan = make_plan(head)
@@ -529,6 +542,7 @@ def main():
         plan.profile_start()
         run(plan, start, args.steps, [])
         prof = plan.profile_stop()
+        tiles = plan.tile_counts()[0]
         plan.close()
 
     ms_per_step = 1e3 * elapsed / max(args.steps, 1)
@@ -536,7 +550,8 @@ def main():
     n_gal, n_ran = int(gal.shape[0]), int(ran.shape[0])
     bricks_g = touched_bricks(cat.gal_pos, args.n, cat.box_len)
     bricks_r = touched_bricks(cat.ran_pos, args.n, cat.box_len)
-    ab = algorithmic_bytes(args.n, n_gal, n_ran, bricks_g=bricks_g, bricks_r=bricks_r, levels=max(net_levels, 1))
+    ab = algorithmic_bytes(args.n, n_gal, n_ran, bricks_g=bricks_g, bricks_r=bricks_r, levels=max(net_levels, 1),
+                           tiles=tiles, keep_delta=start_of(head)[0] == START_NAMES["learned"])
     stages = {}
     for name, (count, tot_ms) in sorted(prof.items(), key=lambda kv: -kv[1][1]):
         per = ab.get(name)
@@ -615,7 +630,9 @@ def main():
                                f"b=2 f=0.74 R=15, {head} start to eps<={args.tol:g}"
                                + (", lognormal delta" if args.lognormal else "") + (", NGP deposit" if args.ngp else ""),
                    "n": args.n, "start": head, "tol": args.tol, "passes": passes[-1], "eps": eps_last,
-                   "touched_bricks": {"galaxies": bricks_g, "randoms": bricks_r, "of": (args.n // BRICK) ** 3}},
+                   "touched_bricks": {"galaxies": bricks_g, "randoms": bricks_r, "of": (args.n // BRICK) ** 3},
+                   "setup_tiles": None if tiles is None else {"galaxy_grid": tiles[0], "random_grid": tiles[1],
+                                                               "inside_mask": tiles[2], "of": tiles[3]}},
         "starts": {k: {kk: vv for kk, vv in v.items() if kk != "elapsed"} for k, v in results.items()},
         "step_return_codes": {str(k): v for k, v in codes.items()},
         # starts named *_relaxed run the relaxed correction pass, an option beyond the paper (its fixed point)

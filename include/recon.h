@@ -180,6 +180,13 @@ int recon_iterate(recon_plan_t* plan, int max_iter, double tol, int32_t* iters_o
 /* Restarts from the plain start since the last recon_solve: host int32 [batch]. */
 int recon_start_restarts(const recon_plan_t* plan, int32_t* out);
 
+/* Sparsity of the last recon_solve's transforms (Sec. 3.2: the survey occupies part of the box), for
+ * byte accounting: the setup transforms work on z tiles (one y row, a few consecutive x, every z) and
+ * skip tiles with nothing to transform.  out: host int64 [batch][4] = {tiles of the galaxy grid that
+ * hold data, the same for the random grid (0 without randoms), tiles with any cell inside the survey
+ * mask (all tiles without randoms), tiles per realisation}.  ESTATE before a solve; synchronises. */
+int recon_tile_counts(recon_plan_t* plan, int64_t* out);
+
 /* Move a catalogue back along the displacement (Sec. 1).  disp_out: device float32 [n][3]
  * (galaxies: -Psi - f (Psi.r) r, randoms: -Psi, Psi interpolated with the deposit's stencil);
  * pos_out: device float32 [n][3] receiving pos + disp, or NULL.  which: RECON_GAL or RECON_RAN,

@@ -40,7 +40,7 @@ struct Layout {
   size_t grid_g = 0, grid_r = 0, mask = 0, w0 = 0, w1 = 0, w2 = 0, ds = 0, dn = 0, psi = 0, delta = 0,
          corr = 0, tw = 0, partials = 0, red = 0, totals = 0, thr = 0, dscal = 0, act = 0, err = 0, total = 0,
          sorted = 0, bcount = 0, bstart = 0, bcursor = 0, bsum = 0, bvalid = 0, slot = 0, stmp = 0, bhist = 0, status = 0,
-         tpart = 0;
+         tpart = 0, zflag = 0, mflag = 0;
   // network buffers
   size_t a1 = 0, a2 = 0, d1 = 0, d2 = 0, ybuf = 0, dybuf = 0, upbuf = 0, wk2t = 0, w3 = 0,
          part_out = 0, part_w1 = 0, part_w2 = 0, g1 = 0, g2 = 0, g3 = 0, grad = 0, lossp = 0, losst = 0, dc = 0, uc = 0,
@@ -117,6 +117,9 @@ Layout make_layout(const recon_params_t* p) {
   L.dscal = take(b * sizeof(DeltaScal));
   L.act = take(b * 4 * 4);
   L.err = take(16);
+  // tile flags of the setup transforms (one byte per z tile; n^2 bytes bound the tile count)
+  L.zflag = take((size_t)(randoms ? 2 : 1) * b * n * n);
+  L.mflag = randoms ? take((size_t)b * n * n) : 0;
   if (p->max_objects > 0) {
     const long long nbs = (n + kBrick - 1) / kBrick;
     L.nbins = b * nbs * nbs * nbs;
@@ -297,6 +300,9 @@ struct recon_plan_s {
   // brick-sparse integer grids: per-brick validity of each grid, used while sparse_* is set (the
   // bricks that are not valid are zero and are not read)
   unsigned char *bvalid_g = nullptr, *bvalid_r = nullptr;
+  // z-tile flags of the setup: grid tiles written by the forward z pass ([arrays][batch][tiles]) and
+  // tiles with any cell inside the survey mask ([batch][tiles])
+  unsigned char *zflag = nullptr, *mflag = nullptr;
   bool sparse_g = false, sparse_r = false;
   Geo geo{};
   CicGeo cic{};
@@ -407,19 +413,35 @@ const unsigned char* valid_of(const recon_plan_t* pl, int which) {
 }
 
 // Device-side alpha / rho_bar / mask threshold from the totals, then the survey mask.
-int scalars_and_mask(recon_plan_t* pl, int nblk_z) {
+int launch_fill_u64(recon_plan_t* pl, void* p, long long count);
+
+// Scalars, and with randoms the survey mask and its z-tile flags (pl->mflag; tile width tw = 2 wz).
+int scalars_and_mask(recon_plan_t* pl, int nblk_z, int tw) {
   k_scalars<<<pl->batch, 256, 0, pl->stream>>>(pl->tpart, nblk_z, pl->n3, pl->p.mask_tau, pl->randoms ? 1 : 0,
                                                pl->totals, pl->dscal, pl->thr, pl->status);
   RECON_TRY(check_launch(pl, "scalars"));
   if (pl->randoms) {
-    if (const unsigned char* v = valid_of(pl, RECON_RAN)) {
+    const unsigned char* v = valid_of(pl, RECON_RAN);
+    if (v && tw % kBrick == 0) {
+      // the brick mask sets the flags of the tiles it writes into
+      RECON_TRY(launch_fill_u64(pl, pl->mflag, ((long long)pl->batch * nblk_z + 7) / 8));
       PROF(pl, KP_MASK);
-      k_mask_brick<<<(unsigned)pl->L.nbins, 256, 0, pl->stream>>>(pl->grid_r, pl->n, pl->thr, v, pl->mask);
+      k_mask_brick<<<(unsigned)pl->L.nbins, 256, 0, pl->stream>>>(pl->grid_r, pl->n, pl->thr, v, pl->mask, pl->mflag,
+                                                                 tw);
     } else {
-      const int nseg = (pl->n + 61) / 62;
-      const unsigned blocks = (unsigned)(nseg * ((pl->n + 3) / 4));
+      {
+        PROF(pl, KP_MASK);
+        if (v) {
+          k_mask_brick<<<(unsigned)pl->L.nbins, 256, 0, pl->stream>>>(pl->grid_r, pl->n, pl->thr, v, pl->mask);
+        } else {
+          const int nseg = (pl->n + 61) / 62;
+          const unsigned blocks = (unsigned)(nseg * ((pl->n + 3) / 4));
+          k_mask_win<<<dim3(blocks, pl->batch), 256, 0, pl->stream>>>(pl->grid_r, pl->n, pl->thr, pl->mask);
+        }
+      }
+      RECON_TRY(check_launch(pl, "mask"));
       PROF(pl, KP_MASK);
-      k_mask_win<<<dim3(blocks, pl->batch), 256, 0, pl->stream>>>(pl->grid_r, pl->n, pl->thr, pl->mask);
+      k_mask_tiles<<<dim3((unsigned)nblk_z, pl->batch), 256, 0, pl->stream>>>(pl->mask, pl->n, tw, pl->mflag);
     }
     RECON_TRY(check_launch(pl, "mask"));
   }
@@ -466,12 +488,15 @@ struct SizeOps {
       {
         PROF(pl, KP_Z_FWD_GRID);
         k_z_fwd_grid<N, 2><<<gz(pl), dim3(TZ), 0, s>>>(pl->grid_g, pl->grid_r, pl->w0, pl->w1, pl->tpart, pl->tw,
-                                                       valid_of(pl, RECON_GAL), valid_of(pl, RECON_RAN));
+                                                       valid_of(pl, RECON_GAL), valid_of(pl, RECON_RAN), pl->zflag);
       }
       RECON_TRY(check_launch(pl, "z forward (grids)"));
+      // the mask (from the random grid and the totals) and its tile flags come first, so that the
+      // inverse y pass can skip the rows the overdensity step will not read
+      RECON_TRY(scalars_and_mask(pl, (int)gz(pl).x, 2 * WZ));
       {
         PROF(pl, KP_Y_FWD);
-        k_y_plain<N, 2, false><<<gy(pl), dim3(TY), 0, s>>>(pl->w0, pl->w1, pl->tw);
+        k_y_plain<N, 2, false><<<gy(pl), dim3(TY), 0, s>>>(pl->w0, pl->w1, pl->tw, pl->zflag);
       }
       RECON_TRY(check_launch(pl, "y forward"));
       {
@@ -481,27 +506,27 @@ struct SizeOps {
       RECON_TRY(check_launch(pl, "x smooth"));
       {
         PROF(pl, KP_Y_INV);
-        k_y_plain<N, 2, true><<<gy(pl), dim3(TY), 0, s>>>(pl->w0, pl->w1, pl->tw);
+        k_y_plain<N, 2, true><<<gy(pl), dim3(TY), 0, s>>>(pl->w0, pl->w1, pl->tw, pl->mflag);
       }
       RECON_TRY(check_launch(pl, "y inverse"));
-      RECON_TRY(scalars_and_mask(pl, (int)gz(pl).x));
       {
         PROF(pl, KP_Z_DELTA);
         k_z_delta<N, 2><<<gz(pl), dim3(TZ), 0, s>>>(pl->w0, pl->w1, pl->mask, pl->dscal, pl->delta,
-                                                    log_floor(pl), pl->partials, pl->tw);
+                                                    log_floor(pl), pl->partials, pl->tw, pl->mflag);
       }
       RECON_TRY(check_launch(pl, "z delta"));
       RECON_TRY(log_constant(pl, (int)gz(pl).x));
+      return finish_start(pl, pl->mflag);
     } else {
       {
         PROF(pl, KP_Z_FWD_GRID);
         k_z_fwd_grid<N, 1><<<gz(pl), dim3(TZ), 0, s>>>(pl->grid_g, nullptr, pl->w0, nullptr, pl->tpart, pl->tw,
-                                                       valid_of(pl, RECON_GAL), nullptr);
+                                                       valid_of(pl, RECON_GAL), nullptr, pl->zflag);
       }
       RECON_TRY(check_launch(pl, "z forward (grid)"));
       {
         PROF(pl, KP_Y_FWD);
-        k_y_plain<N, 1, false><<<gy(pl), dim3(TY), 0, s>>>(pl->w0, nullptr, pl->tw);
+        k_y_plain<N, 1, false><<<gy(pl), dim3(TY), 0, s>>>(pl->w0, nullptr, pl->tw, pl->zflag);
       }
       RECON_TRY(check_launch(pl, "y forward"));
       {
@@ -514,7 +539,7 @@ struct SizeOps {
         k_y_plain<N, 1, true><<<gy(pl), dim3(TY), 0, s>>>(pl->w0, nullptr, pl->tw);
       }
       RECON_TRY(check_launch(pl, "y inverse"));
-      RECON_TRY(scalars_and_mask(pl, (int)gz(pl).x));
+      RECON_TRY(scalars_and_mask(pl, (int)gz(pl).x, 2 * WZ));
       {
         PROF(pl, KP_Z_DELTA);
         k_z_delta<N, 1><<<gz(pl), dim3(TZ), 0, s>>>(pl->w0, nullptr, nullptr, pl->dscal, pl->delta,
@@ -523,14 +548,16 @@ struct SizeOps {
       RECON_TRY(check_launch(pl, "z delta"));
       RECON_TRY(log_constant(pl, (int)gz(pl).x));
     }
-    return finish_start(pl);
+    return finish_start(pl, nullptr);
   }
 
-  static int finish_start(recon_plan_t* pl) {
+  // y and x forward of the overdensity's z spectrum (rows of the z tiles flagged 0 in mflag, when
+  // given, were not written and are zero), D_s, and the fan-out state X of the plain start
+  static int finish_start(recon_plan_t* pl, const unsigned char* mflag) {
     hipStream_t s = pl->stream;
     {
       PROF(pl, KP_Y_FWD);
-      k_y_plain<N, 1, false><<<gy(pl), dim3(TY), 0, s>>>(pl->w0, nullptr, pl->tw);
+      k_y_plain<N, 1, false><<<gy(pl), dim3(TY), 0, s>>>(pl->w0, nullptr, pl->tw, mflag);
     }
     RECON_TRY(check_launch(pl, "y forward (delta)"));
     {
@@ -546,7 +573,7 @@ struct SizeOps {
       k_z_fwd_real<N><<<gz(pl), dim3(TZ), 0, pl->stream>>>(d, pl->w0, pl->tw);
     }
     RECON_TRY(check_launch(pl, "z forward (delta)"));
-    return finish_start(pl);
+    return finish_start(pl, nullptr);
   }
 
   // z and y forward of the field, then the HELM x start: the plan's fan-out state becomes that of
@@ -867,6 +894,8 @@ int plan_create(recon_plan_t** out, const recon_params_t* params, const Layout& 
   pl->grid_g = (long long*)(w + L.grid_g);
   pl->grid_r = pl->randoms ? (long long*)(w + L.grid_r) : nullptr;
   pl->mask = pl->randoms ? (unsigned char*)(w + L.mask) : nullptr;
+  pl->zflag = (unsigned char*)(w + L.zflag);
+  pl->mflag = pl->randoms ? (unsigned char*)(w + L.mflag) : nullptr;
   pl->w0 = (float2*)(w + L.w0);
   pl->w1 = (float2*)(w + L.w1);
   pl->w2 = (float2*)(w + L.w2);
@@ -1568,6 +1597,33 @@ int recon_iterate(recon_plan_t* pl, int max_iter, double tol, int32_t* iters_out
 int recon_start_restarts(const recon_plan_t* pl, int32_t* out) {
   if (!pl || !out) return RECON_EINVAL;
   for (int b = 0; b < pl->batch; ++b) out[b] = pl->restarts[b];
+  return RECON_OK;
+}
+
+int recon_tile_counts(recon_plan_t* pl, int64_t* out) {
+  CHECK_PLAN(pl);
+  if (!out) return fail(pl, RECON_EINVAL, "NULL output pointer");
+  if (pl->state != ST_SOLVED) return fail(pl, RECON_ESTATE, "no solve yet");
+  const long long nt = ops_for(pl->n)->nb_z;   // z tiles per realisation
+  const int na = pl->randoms ? 2 : 1;
+  std::vector<unsigned char> z((size_t)na * pl->batch * nt), m(pl->randoms ? (size_t)pl->batch * nt : 0);
+  HIP_TRY(pl, hipMemcpyAsync(z.data(), pl->zflag, z.size(), hipMemcpyDeviceToHost, pl->stream));
+  if (pl->randoms) HIP_TRY(pl, hipMemcpyAsync(m.data(), pl->mflag, m.size(), hipMemcpyDeviceToHost, pl->stream));
+  HIP_TRY(pl, hipStreamSynchronize(pl->stream));
+  for (int b = 0; b < pl->batch; ++b) {
+    int64_t c[3] = {0, 0, 0};
+    for (long long t = 0; t < nt; ++t) {
+      c[0] += z[(size_t)b * nt + t];
+      if (pl->randoms) {
+        c[1] += z[((size_t)pl->batch + b) * nt + t];
+        c[2] += m[(size_t)b * nt + t];
+      }
+    }
+    out[4 * b + 0] = c[0];
+    out[4 * b + 1] = pl->randoms ? c[1] : 0;
+    out[4 * b + 2] = pl->randoms ? c[2] : nt;
+    out[4 * b + 3] = nt;
+  }
   return RECON_OK;
 }
 

@@ -668,11 +668,14 @@ __global__ void __launch_bounds__(256) k_mask_win(const long long* __restrict__ 
 // (x, y) column of the brick and keeps the 3 x 3 sums of the 18 planes in registers, then slides
 // along z.  A brick whose 27 neighbours are all not valid has every window sum 0.  Bricks are
 // taken in XCD ranges (brick_of_block): the one-cell halo reads of x-adjacent bricks and the 16-byte
-// pieces of the 128-byte mask lines they write meet in one L2 instead of in HBM.
+// pieces of the 128-byte mask lines they write meet in one L2 instead of in HBM.  With mflag (zeroed
+// before the launch), a row of the brick with any cell inside the mask sets the flag of its z tile
+// (one y row, tw consecutive x, every z; tw a multiple of the brick size).
 __global__ void __launch_bounds__(256) k_mask_brick(const long long* __restrict__ gr, int n,
                                                     const long long* __restrict__ thr,
                                                     const unsigned char* __restrict__ valid,
-                                                    unsigned char* __restrict__ mask) {
+                                                    unsigned char* __restrict__ mask,
+                                                    unsigned char* __restrict__ mflag = nullptr, int tw = 0) {
   constexpr int H = kBrick + 2, H3 = H * H * H, PER = (H3 + 255) / 256;
   __shared__ __align__(16) long long h[H3];
   __shared__ int nv[27];
@@ -699,9 +702,13 @@ __global__ void __launch_bounds__(256) k_mask_brick(const long long* __restrict_
   // thread t writes mask row (z, y) = (t / 16, t % 16) of the brick: 16 bytes along x
   const int rz = threadIdx.x / kBrick, ry = threadIdx.x % kBrick;
   uint4* row = (uint4*)(m + (long long)(bz * kBrick + rz) * n2 + (long long)(by * kBrick + ry) * n + bx * kBrick);
+  unsigned char* fl = mflag ? mflag + (long long)b * n * (n / tw) + (long long)(by * kBrick + ry) * (n / tw) +
+                                    bx * kBrick / tw
+                            : nullptr;
   if (!any) {
     const unsigned v = 0 > t ? 0x01010101u : 0u;
     *row = make_uint4(v, v, v, v);
+    if (fl && v) *fl = 1;
     return;
   }
   long long vals[PER];
@@ -743,7 +750,9 @@ __global__ void __launch_bounds__(256) k_mask_brick(const long long* __restrict_
   for (int z = 0; z < kBrick; ++z)
     mb[(z * kBrick + ty) * kBrick + tx] = (sxy[z] + sxy[z + 1] + sxy[z + 2]) > t ? 1 : 0;
   __syncthreads();
-  *row = ((const uint4*)mb)[threadIdx.x];
+  const uint4 w4 = ((const uint4*)mb)[threadIdx.x];
+  *row = w4;
+  if (fl && (w4.x | w4.y | w4.z | w4.w)) *fl = 1;      // every writer stores the same value
 }
 
 // Per-realisation scalars from the exact totals {W_g, W_r, n_occ}:
@@ -796,6 +805,35 @@ __global__ void __launch_bounds__(256) k_scalars(const unsigned long long* __res
     thr[b] = th;
     status[b] = st;
   }
+}
+
+// Mask-tile flags: mflag[b][tile] = 1 when any cell of z tile `tile` (one y row, tw consecutive x,
+// every z) lies inside the survey mask.  One block per tile; 16-byte words when the tile row is a
+// multiple of 16 bytes, bytes otherwise.
+__global__ void __launch_bounds__(256) k_mask_tiles(const unsigned char* __restrict__ mask, int n, int tw,
+                                                    unsigned char* __restrict__ mflag) {
+  const long long n3 = (long long)n * n * n;
+  const int b = blockIdx.y, tpr = n / tw;
+  const int y = blockIdx.x / tpr, x0 = (blockIdx.x % tpr) * tw;
+  const unsigned char* m = mask + b * n3;
+  int mine = 0;
+  if (tw % 16 == 0) {
+    const int row16 = tw / 16;
+    for (int i = threadIdx.x; i < n * row16; i += 256) {
+      const long long e = ((long long)(i / row16) * n + y) * n + x0 + 16 * (i % row16);
+      if (in_bounds(e + 15, n3)) {
+        const uint4 w4 = *(const uint4*)(m + e);
+        mine |= (w4.x | w4.y | w4.z | w4.w) != 0u;
+      }
+    }
+  } else {
+    for (int i = threadIdx.x; i < n * tw; i += 256) {
+      const long long e = ((long long)(i / tw) * n + y) * n + x0 + i % tw;
+      if (in_bounds(e, n3)) mine |= m[e] != 0;
+    }
+  }
+  mine = __syncthreads_or(mine);
+  if (threadIdx.x == 0) mflag[(long long)b * gridDim.x + blockIdx.x] = mine ? 1 : 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -912,12 +950,16 @@ template <int N> constexpr int ntx() { return frag_threads<N, wx<N>()>(); }
 // Forward z transform of int64 grids (units 2^-32) into half spectra.
 // Also writes the exact totals {sum g0, sum g1, #(g1 != 0)} of the tile to tpart[b][block].
 template <int N, int NA>
+// With tile flags (zflag != null, [NA][batch][z tiles]): a tile whose bricks are all not valid gets
+// flag 0 and its zero half spectra are not written (the forward y pass reads such rows as zeros);
+// every other tile gets flag 1.
 __global__ void __launch_bounds__(ntz<N>(), 8) k_z_fwd_grid(const long long* __restrict__ g0,
                                                          const long long* __restrict__ g1, float2* __restrict__ o0,
                                                          float2* __restrict__ o1, unsigned long long* __restrict__ tpart,
                                                          const float2* __restrict__ twg,
                                                          const unsigned char* __restrict__ v0 = nullptr,
-                                                         const unsigned char* __restrict__ v1 = nullptr) {
+                                                         const unsigned char* __restrict__ v1 = nullptr,
+                                                         unsigned char* __restrict__ zflag = nullptr) {
   constexpr int NT = ntz<N>(), WP = wz<N>();
   using L = Lay<N, WP, false>;
   __shared__ float2 buf[L::SIZE];
@@ -944,12 +986,17 @@ __global__ void __launch_bounds__(ntz<N>(), 8) k_z_fwd_grid(const long long* __r
       int mine = 0;
       for (int i = threadIdx.x; i < NBS * XB; i += NT) mine |= vb[(i / XB) * NBS * NBS + x0 / kBrick + i % XB];
       if (!__syncthreads_or(mine)) {
-        float2* out = (a == 0 ? o0 : o1) + b * cn;
-        for (int e = threadIdx.x; e < (N / 2 + 1) * 2 * WP; e += NT)
-          out[((long long)(e / (2 * WP)) * N + y) * N + x0 + e % (2 * WP)] = make_float2(0.f, 0.f);
+        if (zflag) {
+          if (threadIdx.x == 0) zflag[((long long)a * gridDim.y + b) * gridDim.x + blockIdx.x] = 0;
+        } else {
+          float2* out = (a == 0 ? o0 : o1) + b * cn;
+          for (int e = threadIdx.x; e < (N / 2 + 1) * 2 * WP; e += NT)
+            out[((long long)(e / (2 * WP)) * N + y) * N + x0 + e % (2 * WP)] = make_float2(0.f, 0.f);
+        }
         continue;
       }
     }
+    if (zflag && threadIdx.x == 0) zflag[((long long)a * gridDim.y + b) * gridDim.x + blockIdx.x] = 1;
     float2 v[8];
     if (act) {
 #pragma unroll
@@ -1021,7 +1068,8 @@ __global__ void __launch_bounds__(ntz<N>()) k_z_delta(float2* __restrict__ a0, c
                                                       const unsigned char* __restrict__ mask,
                                                       const DeltaScal* __restrict__ sc, float* __restrict__ delta_out,
                                                       float log_floor, double* __restrict__ partials,
-                                                      const float2* __restrict__ twg) {
+                                                      const float2* __restrict__ twg,
+                                                      const unsigned char* __restrict__ mflag = nullptr) {
   constexpr int NT = ntz<N>(), WP = wz<N>();
   using L = Lay<N, WP, false>;
   __shared__ float2 buf[L::SIZE];
@@ -1038,20 +1086,11 @@ __global__ void __launch_bounds__(ntz<N>()) k_z_delta(float2* __restrict__ a0, c
   double lsum = 0.0;
   float2 gv[8], v[8];
   if constexpr (NA == 2) {
-    // a tile outside the survey mask has delta_s = 0 in every cell (also after the lognormal
-    // transform, ln 1 = 0): its spectrum is zero and no transform is needed
-    constexpr int ROW16 = 2 * WP / 16;                   // 16-byte words per z row of the tile
-    int mine = ROW16 == 0;                               // (tiles narrower than 16 bytes: no check)
-    if constexpr (ROW16 > 0) {
-      for (int i = threadIdx.x; i < N * ROW16; i += NT) {
-        const uint4 w4 =
-            *(const uint4*)(mask + b * n3 + ((long long)(i / ROW16) * N + y) * N + x0 + 16 * (i % ROW16));
-        mine |= (w4.x | w4.y | w4.z | w4.w) != 0u;
-      }
-    }
-    if (!__syncthreads_or(mine)) {
-      for (int e = threadIdx.x; e < (N / 2 + 1) * 2 * WP; e += NT)
-        a0[((long long)(e / (2 * WP)) * N + y) * N + x0 + e % (2 * WP)] = make_float2(0.f, 0.f);
+    // a tile outside the survey mask (mask-tile flag 0) has delta_s = 0 in every cell (also after the
+    // lognormal transform, ln 1 = 0): its spectrum is zero and no transform is needed; it is not
+    // written either (the forward y pass reads such rows as zeros), nor were its inputs (the inverse
+    // y pass skipped them).  Without flags every tile is transformed.
+    if (mflag && !mflag[(long long)b * gridDim.x + blockIdx.x]) {
       if (delta_out)
         for (int e = threadIdx.x; e < N * 2 * WP; e += NT)
           delta_out[b * n3 + ((long long)(e / (2 * WP)) * N + y) * N + x0 + e % (2 * WP)] = 0.f;
@@ -1565,13 +1604,22 @@ __device__ __forceinline__ void y_store(const float2* v, float2* __restrict__ a,
   }
 }
 
+// Row flags (flag != null): one byte per z tile (one y row, 2 wz consecutive x), [NA][batch][z tiles]
+// for the forward pass, [batch][z tiles] shared by both arrays for the inverse one.  Forward: rows
+// (y, x) whose z tile has flag 0 were not written by the z pass and are read as zeros.  Inverse:
+// such rows are not stored (the z pass that follows does not read them).
+
 template <int N, int NA, bool INV>
 __global__ void __launch_bounds__(nty<N>()) k_y_plain(float2* __restrict__ a0, float2* __restrict__ a1,
-                                                      const float2* __restrict__ twg) {
-  constexpr int NT = nty<N>(), W = wy<N>();
+                                                      const float2* __restrict__ twg,
+                                                      const unsigned char* __restrict__ flag = nullptr) {
+  constexpr int NT = nty<N>(), W = wy<N>(), NZT = N / (2 * wz<N>());
+  static_assert((2 * wz<N>()) % W == 0, "a y tile lies inside one z tile");
+  constexpr int NF = INV ? 1 : NA;                     // flag sets: per array (forward) or shared (inverse)
   using L = Lay<N, W, false>;
   __shared__ float2 buf[L::SIZE];
   __shared__ float2 tw[N];
+  __shared__ unsigned char live[NF][N];                // the tile's row flags, staged with the twiddles
   stage_twiddles<N, NT>(tw, twg);
   int p, x0, c, j;
   y_tile_coords<N, W>(p, x0);
@@ -1579,13 +1627,35 @@ __global__ void __launch_bounds__(nty<N>()) k_y_plain(float2* __restrict__ a0, f
   const bool act = threadIdx.x < L::NTF;
   const long long cn = (long long)(N / 2 + 1) * N * N;
   const int b = blockIdx.y;
+  if (flag) {
+    for (int i = threadIdx.x; i < NF * N; i += NT) {
+      const int f = i / N, yy = i % N;
+      live[f][yy] = flag[((long long)f * gridDim.y + b) * N * NZT + (long long)yy * NZT + x0 / (2 * wz<N>())];
+    }
+    __syncthreads();
+  }
 #pragma unroll
   for (int a = 0; a < NA; ++a) {
     float2* arr = (a == 0 ? a0 : a1) + b * cn;
+    const unsigned char* lv = live[INV ? 0 : a];
     float2 v[8];
-    if (act) y_load<N>(v, arr, p, x0, c, j);
+    if (act) {
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        const int yy = j + r * (N / 8);
+        const long long e = ((long long)p * N + yy) * N + x0 + c;
+        v[r] = (in_bounds(e, cn) && (INV || !flag || lv[yy])) ? arr[e] : float2{};
+      }
+    }
     fft_rr<N, W, INV, false>(v, buf, tw);
-    if (act) y_store<N>(v, arr, p, x0, c, j);
+    if (act) {
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        const int yy = j + r * (N / 8);
+        const long long e = ((long long)p * N + yy) * N + x0 + c;
+        if (in_bounds(e, cn) && (!INV || !flag || lv[yy])) arr[e] = v[r];
+      }
+    }
   }
 }
 

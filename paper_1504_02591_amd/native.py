@@ -33,7 +33,8 @@ EXPORTED = ("recon_workspace_bytes", "recon_plan", "recon_paint", "recon_solve",
             "recon_destroy", "recon_strerror", "recon_last_error", "recon_profile_start",
             "recon_profile_stop", "recon_profile_kernel_name", "recon_cnn_forward", "recon_cnn_train_step",
             "recon_get_radial", "recon_restrict", "recon_prolong", "recon_radial_ratio", "recon_helmholtz",
-            "recon_start_restarts", "recon_plan_noalloc", "recon_noalloc_limit", "recon_debug_violations")
+            "recon_start_restarts", "recon_plan_noalloc", "recon_noalloc_limit", "recon_debug_violations",
+            "recon_tile_counts")
 
 
 class ReconError(RuntimeError):
@@ -84,6 +85,7 @@ def load(path=None):
     lib.recon_solve.argtypes = [vp, ctypes.c_int, vp]
     lib.recon_iterate.argtypes = [vp, ctypes.c_int, dbl, ctypes.POINTER(i32), ctypes.POINTER(dbl)]
     lib.recon_start_restarts.argtypes = [vp, ctypes.POINTER(i32)]
+    lib.recon_tile_counts.argtypes = [vp, ctypes.POINTER(i64)]
     lib.recon_shift.argtypes = [vp, ctypes.c_int, vp, i64, vp, vp, vp]
     lib.recon_get_psi.argtypes = [vp, vp]
     lib.recon_get_grid.argtypes = [vp, ctypes.c_int, vp]
@@ -107,7 +109,7 @@ def load(path=None):
     lib.recon_profile_stop.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(dbl), ctypes.c_int]
     lib.recon_profile_kernel_name.argtypes = [ctypes.c_int]
     lib.recon_profile_kernel_name.restype = ctypes.c_char_p
-    for name in ("recon_start_restarts", "recon_cnn_forward", "recon_cnn_train_step", "recon_get_radial", "recon_restrict", "recon_prolong",
+    for name in ("recon_start_restarts", "recon_tile_counts", "recon_cnn_forward", "recon_cnn_train_step", "recon_get_radial", "recon_restrict", "recon_prolong",
                  "recon_radial_ratio", "recon_helmholtz",
                  "recon_profile_start", "recon_profile_stop", "recon_plan", "recon_paint", "recon_solve", "recon_iterate", "recon_shift",
                  "recon_get_psi", "recon_get_grid", "recon_get_delta", "recon_set_delta"):
@@ -288,6 +290,13 @@ class Plan:
             row = [eps[b * max_iter + i] for i in range(max_iter)]
             hist.append([e for e in row if not math.isnan(e)])
         return rc, list(iters), hist
+
+    def tile_counts(self):
+        """Per realisation: (galaxy-grid tiles with data, random-grid tiles with data, tiles inside the mask,
+        tiles), the z tiles of the last solve's transforms."""
+        out = (ctypes.c_int64 * (4 * self.batch))()
+        self._rc(self.lib.recon_tile_counts(self.handle, out))
+        return [tuple(out[4 * b:4 * b + 4]) for b in range(self.batch)]
 
     def restarts(self):
         """Restarts from the plain start of each realisation since the last solve."""

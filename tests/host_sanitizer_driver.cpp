@@ -161,6 +161,10 @@ int main() {
   CHECK(recon_iterate(nullptr, 3, 1e-3, c, d) == RECON_EINVAL);
   CHECK(recon_shift(nullptr, RECON_RAN, f, 1, nullptr, f, nullptr) == RECON_EINVAL);
   CHECK(recon_get_psi(nullptr, f) == RECON_EINVAL);
+  {
+    int64_t tc[4];
+    CHECK(recon_tile_counts(nullptr, tc) == RECON_EINVAL);
+  }
   CHECK(recon_get_grid(nullptr, RECON_GAL, g) == RECON_EINVAL);
   CHECK(recon_get_delta(nullptr, f) == RECON_EINVAL);
   CHECK(recon_set_delta(nullptr, f) == RECON_EINVAL);

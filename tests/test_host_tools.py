@@ -42,7 +42,13 @@ def test_sparse_byte_model_counts_only_touched_bricks():
     brick_bytes = 16 ** 3 * 8
     cn = 257 * 512 * 512 * 8
     assert sparse["z_fwd_grid"] == 300 * brick_bytes + 2 * cn
-    assert sparse["mask"] == 200 * brick_bytes + 512 ** 3
+    assert sparse["mask"] == 200 * brick_bytes + 2 * 512 ** 3
+    # setup tiles: only the grid tiles with data are written by the forward z pass, only the mask's
+    # tiles are read and written by the overdensity step
+    tiles = (1000, 2000, 1500, 8192)
+    tiled = bench.algorithmic_bytes(512, 1000, 50000, bricks_g=100, bricks_r=200, tiles=tiles)
+    assert tiled["z_fwd_grid"] == 300 * brick_bytes + (3000 / 8192) * cn
+    assert tiled["z_delta"] == (1500 / 8192) * (3 * cn + 512 ** 3)
     assert sparse["paint_grids"] == 300 * brick_bytes
     assert dense["z_fwd_grid"] == 2 * 512 ** 3 * 8 + 2 * cn
 
