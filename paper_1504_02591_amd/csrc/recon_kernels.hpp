@@ -1959,8 +1959,14 @@ __global__ void __launch_bounds__(256) k_helm_out(const float* __restrict__ psi,
 //   (w = 2 inside the halved kz axis) -> convergence norm by Parseval
 //   P = D_{n+1} / (b k^2 N^3);  a0 <- X^-1[i k'_x P],  a1 <- X^-1[P]
 // dprev and dnext may be the same buffer (element-wise in place).
+// RECON_X_WAVES > 0: occupancy hint (waves per SIMD) for the x iteration, which bounds its registers
+#if RECON_X_WAVES > 0
+#define RECON_X_ITER_BOUNDS(N) __launch_bounds__(ntx<N>(), RECON_X_WAVES)
+#else
+#define RECON_X_ITER_BOUNDS(N) __launch_bounds__(ntx<N>())
+#endif
 template <int N>
-__global__ void __launch_bounds__(ntx<N>()) k_x_iter(float2* __restrict__ a0, float2* __restrict__ a1,
+__global__ void RECON_X_ITER_BOUNDS(N) k_x_iter(float2* __restrict__ a0, float2* __restrict__ a1,
                                                      const float2* __restrict__ ds, const float2* dprev,
                                                      float2* dnext, Geo g, double* __restrict__ partials,
                                                      const int* __restrict__ active, const float2* __restrict__ twg,
@@ -2162,15 +2168,16 @@ __global__ void __launch_bounds__(256) k_shift(const float* __restrict__ pos, lo
 }
 
 // The brick-order shift with one block per 16^3 brick: the block stages the displacement at the
-// 18^3 nodes its objects' stencils can reach (rows of 18 consecutive x per component) in LDS, then
-// interpolates every object of the brick from LDS.  Same arithmetic as k_shift.
+// 17^3 nodes its objects' stencils can reach (base cells 0..15 of the brick and their upper corners;
+// rows of 17 consecutive x per component) in LDS, then interpolates every object of the brick from
+// LDS.  Same arithmetic as k_shift.
 template <int NT>
 __global__ void __launch_bounds__(NT) k_shift_brick(const float4* __restrict__ sorted,
                                                     const unsigned* __restrict__ start,
                                                     const float* __restrict__ psi, CicGeo cg, float ox, float oy,
                                                     float oz, float growth, int galaxies,
                                                     float4* __restrict__ tmp) {
-  constexpr int F = kBrick + 2, F3 = F * F * F;
+  constexpr int F = kBrick + 1, F3 = F * F * F;
   __shared__ float px_[F3], py_[F3], pz_[F3];
   const long long key = brick_of_block();
   const unsigned lo = start[key], hi = start[key + 1];

@@ -79,6 +79,9 @@
 //   objects per loop trip (deposit + randoms' shift)  2: 0.512 + 1.025   4: 0.497 + 1.025   8: 0.510 + 1.062
 //   reorder after the brick-order shift, chunks of one block (shift stage, both catalogues)
 //     per_x apart: 1.096   adjacent (one trip per block), 2 / 4 / 8 chunks: 0.980 / 0.983 / 0.980
+#ifndef RECON_X_WAVES
+#define RECON_X_WAVES 0
+#endif
 #ifndef RECON_Z_DEFER
 #define RECON_Z_DEFER 1
 #endif
