@@ -236,3 +236,35 @@ def test_relaxed_full_size_pass_matches_oracle(gpu_lib):
     print(f"512^3 two relaxed passes: psi rel L2 {e:.2e}, eps {eps[0]} vs {ref['eps']}", flush=True)
     assert e < PSI_TOL
     np.testing.assert_allclose(eps[0], ref["eps"], rtol=1e-4, atol=1e-6)
+
+
+def test_relaxed_batched_to_tolerance_matches_single_realisations(gpu_lib):
+    """Three realisations in one plan, relaxed passes to eps <= 1e-3 with per-realisation convergence:
+    each realisation's pass count, eps history and Psi as the oracle's relaxed iteration gives them."""
+    from paper_1504_02591_amd import native
+    cats = [G.lattice_box(32, 500.0, (-500.0, 250.0, 250.0), 0.7, 50 + i, 60 + i, ran_factor=2, bias=1.0,
+                          smooth_r=20.0, n_part=24 + 4 * i) for i in range(3)]
+    gal = np.concatenate([c.gal_pos for c in cats])
+    ran = np.concatenate([c.ran_pos for c in cats])
+    goff = np.cumsum([0] + [c.gal_pos.shape[0] for c in cats]).astype(np.int64)
+    roff = np.cumsum([0] + [c.ran_pos.shape[0] for c in cats]).astype(np.int64)
+    c0 = cats[0]
+    plan = native.Plan(32, 500.0, c0.observer, 1.0, 0.7, 20.0, batch=3, max_objects=ran.shape[0], relaxed=True,
+                       graphs=True)
+    plan.paint(native.GAL, to_dev(gal), offsets=to_dev(goff))
+    plan.paint(native.RAN, to_dev(ran), offsets=to_dev(roff))
+    plan.solve()
+    rc, iters, eps = plan.iterate(20, 1e-3)
+    psi = plan.psi().cpu().numpy()
+    plan.close()
+    assert rc == native.RECON_OK
+    for i, c in enumerate(cats):
+        # the oracle run for the GPU's pass count; it must cross the tolerance at that very pass (within
+        # FP32 rounding of eps)
+        r = O.reconstruct(c.gal_pos, None, c.ran_pos, None, c.n, c.box_len, c.origin, c.observer, c.bias, c.growth,
+                          c.smooth_r, c.mask_tau, n_passes=iters[i], relax=w_of(c.bias, c.growth))
+        print(f"realisation {i}: {iters[i]} relaxed passes, eps {eps[i]} vs {r['eps']}", flush=True)
+        assert r["eps"][-1] <= 1e-3 * (1 + 1e-3)
+        assert iters[i] == 1 or r["eps"][-2] > 1e-3 * (1 - 1e-3)
+        assert rel_l2(psi[i], r["psi"]) < PSI_TOL
+        np.testing.assert_allclose(eps[i], r["eps"], rtol=1e-4, atol=1e-6)
