@@ -81,3 +81,49 @@ def test_tile_counts_mean_density_box(gpu_lib):
     tg, tr, tm, nt = plan.tile_counts()[0]
     plan.close()
     assert (tg, tr, tm) == (nt, 0, nt)
+
+
+def test_batched_surveys_with_different_footprints(gpu_lib):
+    """Two survey realisations whose cones point different ways share one plan: each has its own tile
+    flags (counts as formed on the host) and its own overdensity, Psi, eps and shifts as the oracle's."""
+    from paper_1504_02591_amd import native
+    n, s = 64, 64 / 512.0
+    cats = [G.survey(n, 3500.0 * s, bias=2.0, growth=0.74, smooth_r=15.0, r_min=1100.0 * s, r_max=1800.0 * s,
+                     omega=2.5, n_target=7.0e5 * s ** 3, ran_factor=20, seed_field=301 + 3 * i, seed_gal=302 + 3 * i,
+                     seed_ran=303 + 3 * i, axis=ax) for i, ax in enumerate([(1.0, 1.0, 1.0), (-1.0, 0.4, 0.2)])]
+    dev = torch.device("cuda", 0)
+    gal = np.concatenate([c.gal_pos for c in cats])
+    ran = np.concatenate([c.ran_pos for c in cats])
+    goff = np.cumsum([0] + [c.gal_pos.shape[0] for c in cats]).astype(np.int64)
+    roff = np.cumsum([0] + [c.ran_pos.shape[0] for c in cats]).astype(np.int64)
+    c0 = cats[0]
+    plan = native.Plan(n, c0.box_len, c0.observer, c0.bias, c0.growth, c0.smooth_r, origin=c0.origin, batch=2,
+                       mask_tau=c0.mask_tau, max_objects=ran.shape[0], keep_delta=True)
+    to = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    plan.paint(native.GAL, to(gal), offsets=to(goff))
+    plan.paint(native.RAN, to(ran), offsets=to(roff))
+    plan.solve()
+    tiles = plan.tile_counts()
+    rc, iters, eps = plan.iterate(3, 0.0)
+    psi = plan.psi().cpu().numpy()
+    delta = plan.delta().cpu().numpy()
+    disp = plan.shift(native.GAL, to(gal), offsets=to(goff)).cpu().numpy()
+    grid_g, grid_r = plan.grid(native.GAL).cpu().numpy(), plan.grid(native.RAN).cpu().numpy()
+    plan.close()
+    assert tiles[0][:3] != tiles[1][:3]
+    for i, c in enumerate(cats):
+        tg, tr, tm, nt = tiles[i]
+        tw = n * n // nt
+        r = O.reconstruct(c.gal_pos, None, c.ran_pos, None, n, c.box_len, c.origin, c.observer, c.bias, c.growth,
+                          c.smooth_r, c.mask_tau, n_passes=3)
+        assert np.array_equal(grid_g[i], r["grid_g"]) and np.array_equal(grid_r[i], r["grid_r"])
+        assert tg == live_tiles_from_bricks(touched_bricks(c.gal_pos, n, c.box_len, c.origin), n, tw)
+        assert tr == live_tiles_from_bricks(touched_bricks(c.ran_pos, n, c.box_len, c.origin), n, tw)
+        assert tm == mask_tiles(O.survey_mask(r["grid_r"], c.mask_tau), n, tw)
+        e_d = float(np.linalg.norm(delta[i] - r["delta_s"]) / np.linalg.norm(r["delta_s"]))
+        e_p = float(np.linalg.norm(psi[i] - r["psi"]) / np.linalg.norm(r["psi"]))
+        e_s = float(np.abs(disp[goff[i]:goff[i + 1]] - r["disp_g"]).max())
+        print(f"realisation {i}: tiles {tiles[i]}, delta rel L2 {e_d:.2e}, psi rel L2 {e_p:.2e}, "
+              f"displacement {e_s:.2e}", flush=True)
+        assert e_d < 1e-5 and e_p < 1e-5 and e_s < 1e-4
+        np.testing.assert_allclose(eps[i], r["eps"], rtol=1e-4, atol=1e-6)
