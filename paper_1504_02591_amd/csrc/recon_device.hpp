@@ -30,6 +30,35 @@ __device__ __forceinline__ bool in_bounds(long long i, long long n) {
 __device__ __forceinline__ constexpr bool in_bounds(long long, long long) { return true; }
 #endif
 
+// Streaming accesses of the transform passes.  Each pass reads and writes its spectra once, and a
+// spectrum (539 MB at 512^3) is far larger than the caches, so the accesses may carry the
+// non-temporal hint: RECON_STREAM bit 0 for stores, bit 1 for loads (the staging loads of the z
+// passes included); 0 keeps plain accesses.
+typedef float recon_v2f __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void st_stream(float2* p, float2 v) {
+#if RECON_STREAM & 1
+  __builtin_nontemporal_store(recon_v2f{v.x, v.y}, reinterpret_cast<recon_v2f*>(p));
+#else
+  *p = v;
+#endif
+}
+__device__ __forceinline__ float2 ld_stream(const float2* p) {
+#if RECON_STREAM & 2
+  const recon_v2f t = __builtin_nontemporal_load(reinterpret_cast<const recon_v2f*>(p));
+  return make_float2(t.x, t.y);
+#else
+  return *p;
+#endif
+}
+__device__ __forceinline__ void st_stream(float* p, float v) {
+#if RECON_STREAM & 1
+  __builtin_nontemporal_store(v, p);
+#else
+  *p = v;
+#endif
+}
+constexpr int kStageCachePolicy = (RECON_STREAM & 2) ? 2 : 0;   // the nt bit of the staging loads
+
 __host__ __device__ constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n / 2); }
 
 __device__ __forceinline__ float2 operator+(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }

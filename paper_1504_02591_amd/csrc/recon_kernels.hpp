@@ -893,7 +893,7 @@ __device__ __forceinline__ void z_stage_issue(float2* stage, const float2* __res
     if (m < S::ROWS && in_bounds(e + 1, (long long)(N / 2 + 1) * N * N)) {
       const float2* g = a + e;
       __builtin_amdgcn_global_load_lds((const void*)g, (__attribute__((address_space(3))) void*)(stage + q * 128),
-                                       16, 0, 0);
+                                       16, 0, kStageCachePolicy);
     }
   }
 }
@@ -932,8 +932,8 @@ __device__ __forceinline__ void z_unpack_store(const float2* buf, float2* __rest
     }
     const long long base = ((long long)kz * N + y) * N + x0 + p;
     constexpr long long CN = (long long)(N / 2 + 1) * N * N;
-    if (in_bounds(base, CN)) out[base] = A;
-    if (in_bounds(base + WP, CN)) out[base + WP] = B;
+    if (in_bounds(base, CN)) st_stream(out + base, A);
+    if (in_bounds(base + WP, CN)) st_stream(out + base + WP, B);
   }
 }
 
@@ -1313,7 +1313,8 @@ __device__ __forceinline__ void z_stage_issue_skew(float2* stage, const float2* 
     const long long e = ((long long)m * N + y) * N + x0 + 2 * (((lane % S::LPR) + m) & 15);
     if (m < S::ROWS && in_bounds(e + 1, (long long)(N / 2 + 1) * N * N)) {
       __builtin_amdgcn_global_load_lds((const void*)(a + e),
-                                       (__attribute__((address_space(3))) void*)(stage + q * 128), 16, 0, 0);
+                                       (__attribute__((address_space(3))) void*)(stage + q * 128), 16, 0,
+                                       kStageCachePolicy);
     }
   }
 }
@@ -1356,8 +1357,8 @@ __device__ __forceinline__ void z_unpack_store_w(const float2* wreg, float2* __r
     }
     const long long base = ((long long)kz * N + y) * N + x0 + p;
     constexpr long long CN = (long long)(N / 2 + 1) * N * N;
-    if (in_bounds(base, CN)) out[base] = A;
-    if (in_bounds(base + WP, CN)) out[base + WP] = B;
+    if (in_bounds(base, CN)) st_stream(out + base, A);
+    if (in_bounds(base + WP, CN)) st_stream(out + base + WP, B);
   }
 }
 
@@ -1495,12 +1496,12 @@ __global__ void __launch_bounds__(ntz<N>()) k_z_final(const float2* __restrict__
         float* pb = psi + 3 * b * n3;
         const long long c0 = cell - b * n3, c1 = c0 + WP;
         if (in_bounds(c1, n3)) {
-          pb[c0] = px[r].x;
-          pb[c1] = px[r].y;
-          pb[n3 + c0] = py[r].x;
-          pb[n3 + c1] = py[r].y;
-          pb[2 * n3 + c0] = v[r].x;
-          pb[2 * n3 + c1] = v[r].y;
+          st_stream(pb + c0, px[r].x);
+          st_stream(pb + c1, px[r].y);
+          st_stream(pb + n3 + c0, py[r].x);
+          st_stream(pb + n3 + c1, py[r].y);
+          st_stream(pb + 2 * n3 + c0, v[r].x);
+          st_stream(pb + 2 * n3 + c1, v[r].y);
         }
       }
       if (u_out || (!COMB && corr)) {
@@ -1591,7 +1592,7 @@ __device__ __forceinline__ void y_load(float2* v, const float2* __restrict__ a, 
 #pragma unroll
   for (int r = 0; r < 8; ++r) {
     const long long e = ((long long)p * N + j + r * (N / 8)) * N + x0 + c;
-    v[r] = in_bounds(e, (long long)(N / 2 + 1) * N * N) ? a[e] : float2{};
+    v[r] = in_bounds(e, (long long)(N / 2 + 1) * N * N) ? ld_stream(a + e) : float2{};
   }
 }
 
@@ -1600,7 +1601,7 @@ __device__ __forceinline__ void y_store(const float2* v, float2* __restrict__ a,
 #pragma unroll
   for (int r = 0; r < 8; ++r) {
     const long long e = ((long long)p * N + j + r * (N / 8)) * N + x0 + c;
-    if (in_bounds(e, (long long)(N / 2 + 1) * N * N)) a[e] = v[r];
+    if (in_bounds(e, (long long)(N / 2 + 1) * N * N)) st_stream(a + e, v[r]);
   }
 }
 
@@ -1644,7 +1645,7 @@ __global__ void __launch_bounds__(nty<N>()) k_y_plain(float2* __restrict__ a0, f
       for (int r = 0; r < 8; ++r) {
         const int yy = j + r * (N / 8);
         const long long e = ((long long)p * N + yy) * N + x0 + c;
-        v[r] = (in_bounds(e, cn) && (INV || !flag || lv[yy])) ? arr[e] : float2{};
+        v[r] = (in_bounds(e, cn) && (INV || !flag || lv[yy])) ? ld_stream(arr + e) : float2{};
       }
     }
     fft_rr<N, W, INV, false>(v, buf, tw);
@@ -1653,7 +1654,7 @@ __global__ void __launch_bounds__(nty<N>()) k_y_plain(float2* __restrict__ a0, f
       for (int r = 0; r < 8; ++r) {
         const int yy = j + r * (N / 8);
         const long long e = ((long long)p * N + yy) * N + x0 + c;
-        if (in_bounds(e, cn) && (!INV || !flag || lv[yy])) arr[e] = v[r];
+        if (in_bounds(e, cn) && (!INV || !flag || lv[yy])) st_stream(arr + e, v[r]);
       }
     }
   }
@@ -1793,7 +1794,7 @@ __device__ __forceinline__ void x_load(float2* v, const float2* __restrict__ a, 
 #pragma unroll
   for (int r = 0; r < 8; ++r) {
     const long long e = row * N + j + r * (N / 8);
-    v[r] = in_bounds(e, (long long)(N / 2 + 1) * N * N) ? a[e] : float2{};
+    v[r] = in_bounds(e, (long long)(N / 2 + 1) * N * N) ? ld_stream(a + e) : float2{};
   }
 }
 
@@ -1802,7 +1803,7 @@ __device__ __forceinline__ void x_store(const float2* v, float2* __restrict__ a,
 #pragma unroll
   for (int r = 0; r < 8; ++r) {
     const long long e = row * N + j + r * (N / 8);
-    if (in_bounds(e, (long long)(N / 2 + 1) * N * N)) a[e] = v[r];
+    if (in_bounds(e, (long long)(N / 2 + 1) * N * N)) st_stream(a + e, v[r]);
   }
 }
 
