@@ -50,13 +50,6 @@ __device__ __forceinline__ float2 ld_stream(const float2* p) {
   return *p;
 #endif
 }
-__device__ __forceinline__ void st_stream(float* p, float v) {
-#if RECON_STREAM & 1
-  __builtin_nontemporal_store(v, p);
-#else
-  *p = v;
-#endif
-}
 constexpr int kStageCachePolicy = (RECON_STREAM & 2) ? 2 : 0;   // the nt bit of the staging loads
 
 __host__ __device__ constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n / 2); }

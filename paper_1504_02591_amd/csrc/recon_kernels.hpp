@@ -1496,12 +1496,12 @@ __global__ void __launch_bounds__(ntz<N>()) k_z_final(const float2* __restrict__
         float* pb = psi + 3 * b * n3;
         const long long c0 = cell - b * n3, c1 = c0 + WP;
         if (in_bounds(c1, n3)) {
-          st_stream(pb + c0, px[r].x);
-          st_stream(pb + c1, px[r].y);
-          st_stream(pb + n3 + c0, py[r].x);
-          st_stream(pb + n3 + c1, py[r].y);
-          st_stream(pb + 2 * n3 + c0, v[r].x);
-          st_stream(pb + 2 * n3 + c1, v[r].y);
+          pb[c0] = px[r].x;
+          pb[c1] = px[r].y;
+          pb[n3 + c0] = py[r].x;
+          pb[n3 + c1] = py[r].y;
+          pb[2 * n3 + c0] = v[r].x;
+          pb[2 * n3 + c1] = v[r].y;
         }
       }
       if (u_out || (!COMB && corr)) {
