@@ -42,13 +42,17 @@ __device__ __forceinline__ void st_stream(float2* p, float2 v) {
   *p = v;
 #endif
 }
+// HINT = false keeps a plain load: the y passes' loads at tiles of fewer than 16 columns (rows of
+// 64-byte segments, half a line) ran slower with the hint.
+template <bool HINT = true>
 __device__ __forceinline__ float2 ld_stream(const float2* p) {
 #if RECON_STREAM & 2
-  const recon_v2f t = __builtin_nontemporal_load(reinterpret_cast<const recon_v2f*>(p));
-  return make_float2(t.x, t.y);
-#else
-  return *p;
+  if constexpr (HINT) {
+    const recon_v2f t = __builtin_nontemporal_load(reinterpret_cast<const recon_v2f*>(p));
+    return make_float2(t.x, t.y);
+  }
 #endif
+  return *p;
 }
 constexpr int kStageCachePolicy = (RECON_STREAM & 2) ? 2 : 0;   // the nt bit of the staging loads
 

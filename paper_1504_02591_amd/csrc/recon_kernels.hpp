@@ -1587,12 +1587,15 @@ __device__ __forceinline__ void y_tile_coords(int& p, int& x0) {
   x0 = (blockIdx.x % (N / W)) * W;
 }
 
+// Non-temporal loads in the y passes only where a tile row is a whole 128-byte line (16 columns).
+template <int N> constexpr bool y_hint() { return wy<N>() >= 16; }
+
 template <int N>
 __device__ __forceinline__ void y_load(float2* v, const float2* __restrict__ a, int p, int x0, int c, int j) {
 #pragma unroll
   for (int r = 0; r < 8; ++r) {
     const long long e = ((long long)p * N + j + r * (N / 8)) * N + x0 + c;
-    v[r] = in_bounds(e, (long long)(N / 2 + 1) * N * N) ? ld_stream(a + e) : float2{};
+    v[r] = in_bounds(e, (long long)(N / 2 + 1) * N * N) ? ld_stream<y_hint<N>()>(a + e) : float2{};
   }
 }
 
@@ -1645,7 +1648,7 @@ __global__ void __launch_bounds__(nty<N>()) k_y_plain(float2* __restrict__ a0, f
       for (int r = 0; r < 8; ++r) {
         const int yy = j + r * (N / 8);
         const long long e = ((long long)p * N + yy) * N + x0 + c;
-        v[r] = (in_bounds(e, cn) && (INV || !flag || lv[yy])) ? ld_stream(arr + e) : float2{};
+        v[r] = (in_bounds(e, cn) && (INV || !flag || lv[yy])) ? ld_stream<y_hint<N>()>(arr + e) : float2{};
       }
     }
     fft_rr<N, W, INV, false>(v, buf, tw);

@@ -83,6 +83,9 @@
 // the 512^3 survey reconstruction (plain start, 6 passes, ms per reconstruction): 0: 20.30 / 20.46,
 // 1: 19.71, 2: 19.96, 3: 19.41 / 19.45 (two runs; Psi bit-identical).  The same hint on the deposit's
 // scattered brick-ordered copy made the binning 2.4x slower (0.79 -> 1.92 ms) and is not used.
+// At 1024^3 (y tiles of 8 columns: half-line row segments) hinted loads made the y passes slower
+// (fan-out 6.25 -> 7.05 ms, fan-in 5.88 -> 6.90 ms) while the z and x passes gained (8.80 -> 8.32,
+// 6.09 -> 5.95 ms): the y passes hint their loads only at tiles of 16 columns or more.
 #ifndef RECON_X_WAVES
 #define RECON_X_WAVES 0
 #endif
