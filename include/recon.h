@@ -161,7 +161,8 @@ int recon_paint(recon_plan_t* plan, int which, const float* pos, const float* w,
  * synchronisation point: error flags are read back).  start: RECON_START_*; net: device pointer to
  * the learned-start network parameters (RECON_START_LEARNED only, layout in recon_cnn.h; the plan
  * needs RECON_KEEP_DELTA | RECON_START_BUFFERS | RECON_CNN_BUFFERS), else NULL.
- * EINVAL when a painted object was invalid or the total random weight is zero. */
+ * EINVAL when a painted object was invalid, or the total galaxy weight or the total random weight
+ * of a realisation is zero (the overdensity is then undefined). */
 int recon_solve(recon_plan_t* plan, int start, const void* net);
 
 /* Run correction passes (Sec. 5.1) until eps_n = ||Psi_n - Psi_{n-1}|| / ||Psi_n|| <= tol for every

@@ -317,11 +317,16 @@ def overdensity(grid_g, grid_r, box_len, smooth_r, mask_tau=0.1):
     unit = 2.0 ** -WEIGHT_BITS
     g = smooth(grid_g.astype(np.float64) * unit, box_len, smooth_r)
     if grid_r is None:
-        rho_bar = float(np.sum(grid_g, dtype=np.int64)) * unit / float(n ** 3)
+        w_g = int(np.sum(grid_g, dtype=np.int64))
+        if w_g <= 0:
+            raise ValueError("total galaxy weight is zero")     # rho_bar = 0: delta undefined
+        rho_bar = float(w_g) * unit / float(n ** 3)
         return g / rho_bar - 1.0
     t = totals(grid_g, grid_r)
     if t["alpha"] is None:
         raise ValueError("total random weight is zero")
+    if t["W_g"] <= 0:
+        raise ValueError("total galaxy weight is zero")         # alpha = 0: delta undefined
     r = smooth(grid_r.astype(np.float64) * unit, box_len, smooth_r)
     m = survey_mask(grid_r, mask_tau) & (r > 0)
     ar = t["alpha"] * r

@@ -777,6 +777,56 @@ def test_nonfinite_field_reads_as_divergence(gpu_lib, start):
     plan.close()
 
 
+def test_zero_galaxy_weight_is_refused(gpu_lib):
+    """A realisation without galaxy weight has no overdensity (alpha = W_g/W_r = 0, or rho_bar = 0
+    without randoms; Sec. 2, Sec. 3.2): recon_solve returns EINVAL, as the oracle raises.  An empty
+    catalogue, one of zero weights, and an empty realisation inside a batch; the plan then takes a
+    valid catalogue and matches the oracle."""
+    from paper_1504_02591_amd import native
+    rng = np.random.default_rng(11)
+    n, box, obs = 16, 160.0, (80.0, 80.0, 80.0)
+    gal = (rng.random((150, 3)) * box).astype(np.float32)
+    ran = (rng.random((3000, 3)) * box).astype(np.float32)
+    empty = to_dev(np.zeros((0, 3), np.float32))
+
+    def refused(plan):
+        with pytest.raises(native.ReconError) as ei:
+            plan.solve()
+        assert ei.value.code == native.RECON_EINVAL and "galaxy weight" in str(ei.value)
+
+    plan = native.Plan(n, box, obs, 1.0, 0.5, 10.0, max_objects=ran.shape[0])
+    plan.paint(native.GAL, empty)
+    plan.paint(native.RAN, to_dev(ran))
+    refused(plan)
+    plan.paint(native.GAL, to_dev(gal), to_dev(np.zeros(gal.shape[0], np.float32)))
+    plan.paint(native.RAN, to_dev(ran))
+    refused(plan)
+    plan.paint(native.GAL, to_dev(gal))
+    plan.paint(native.RAN, to_dev(ran))
+    plan.solve()
+    plan.iterate(2, 0.0)
+    psi = plan.psi()[0].cpu().numpy()
+    plan.close()
+    r = O.reconstruct(gal, None, ran, None, n, box, (0.0, 0.0, 0.0), obs, 1.0, 0.5, 10.0, 0.1, n_passes=2)
+    assert rel_l2(psi, r["psi"]) < PSI_TOL
+    with pytest.raises(ValueError, match="galaxy weight"):
+        O.reconstruct(gal[:0], None, ran, None, n, box, (0.0, 0.0, 0.0), obs, 1.0, 0.5, 10.0, 0.1, n_passes=2)
+
+    # batch of 2, realisation 0 without galaxies (offsets 0, 0, 150), the binned deposit
+    plan = native.Plan(n, box, obs, 1.0, 0.5, 10.0, batch=2, max_objects=2 * ran.shape[0])
+    plan.paint(native.GAL, to_dev(gal), offsets=to_dev(np.array([0, 0, gal.shape[0]], np.int64)))
+    plan.paint(native.RAN, to_dev(np.concatenate([ran, ran])),
+               offsets=to_dev(np.array([0, ran.shape[0], 2 * ran.shape[0]], np.int64)))
+    refused(plan)
+    plan.close()
+
+    # mean-density mode (no randoms): rho_bar = 0
+    plan = native.Plan(n, box, obs, 1.0, 0.5, 10.0, randoms=False)
+    plan.paint(native.GAL, empty)
+    refused(plan)
+    plan.close()
+
+
 def test_invalid_inputs_and_order(gpu_lib):
     from paper_1504_02591_amd import native
     plan = native.Plan(16, 100.0, (50.0, 50.0, 50.0), 1.0, 0.5, 10.0)

@@ -550,6 +550,27 @@ def test_uniform_lattice_has_zero_overdensity():
     np.testing.assert_allclose(d2, 0.0, atol=1e-12)
 
 
+def test_zero_weight_catalogues_are_refused():
+    """delta = (G - alpha R)/(alpha R) needs alpha = W_g/W_r > 0, and G/rho_bar - 1 needs rho_bar > 0
+    (Sec. 2, Sec. 3.2): a realisation with no galaxy weight, or no random weight, has no overdensity."""
+    n, box = 16, 160.0
+    rng = np.random.default_rng(3)
+    pos = (rng.random((200, 3)) * box).astype(np.float32)
+    g = O.paint(pos, None, n, box, (0, 0, 0))
+    r = O.paint(pos, None, n, box, (0, 0, 0))
+    empty = O.paint(np.zeros((0, 3), np.float32), None, n, box, (0, 0, 0))
+    weightless = O.paint(pos, np.zeros(pos.shape[0], np.float32), n, box, (0, 0, 0))
+    assert not empty.any() and not weightless.any()
+    for gal in (empty, weightless):
+        with pytest.raises(ValueError, match="galaxy weight"):
+            O.overdensity(gal, r, box, 10.0)
+        with pytest.raises(ValueError, match="galaxy weight"):
+            O.overdensity(gal, None, box, 10.0)
+    with pytest.raises(ValueError, match="random weight"):
+        O.overdensity(g, empty, box, 10.0)
+    assert np.isfinite(O.overdensity(g, r, box, 10.0)).all()
+
+
 def _node_lattice(n, box, weight_of_node):
     """One object on every grid node (box a power of two times n, so every node coordinate and the
     grid scale are exact in float32 and each object's whole weight lands on its own node)."""
