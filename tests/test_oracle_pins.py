@@ -550,6 +550,29 @@ def test_uniform_lattice_has_zero_overdensity():
     np.testing.assert_allclose(d2, 0.0, atol=1e-12)
 
 
+def test_translated_box_gives_the_same_reconstruction():
+    """Moving the box origin, the observer and every object by one vector changes nothing the method
+    computes (the deposit sees x - origin, the line of sight cell - observer).  Positions on a 1/64
+    lattice and an offset of whole units keep every translated coordinate exact in float32, so the
+    grids must agree bit for bit and Psi and the shifts to rounding."""
+    n, box = 16, 160.0
+    rng = np.random.default_rng(21)
+    gal = (np.floor(rng.random((400, 3)) * box * 64) / 64).astype(np.float32)
+    ran = (np.floor(rng.random((4000, 3)) * box * 64) / 64).astype(np.float32)
+    obs = np.array([70.0, 95.0, 60.0])
+    off = np.array([-1024.0, 512.0, 256.0])
+    a = O.reconstruct(gal, None, ran, None, n, box, (0.0, 0.0, 0.0), tuple(obs), 2.0, 0.7, 15.0, 0.1,
+                      n_passes=3)
+    b = O.reconstruct((gal + off).astype(np.float32), None, (ran + off).astype(np.float32), None, n, box,
+                      tuple(off), tuple(obs + off), 2.0, 0.7, 15.0, 0.1, n_passes=3)
+    assert np.array_equal((gal + off).astype(np.float32) - off.astype(np.float32), gal)
+    assert np.array_equal(a["grid_g"], b["grid_g"]) and np.array_equal(a["grid_r"], b["grid_r"])
+    np.testing.assert_allclose(b["psi"], a["psi"], rtol=0, atol=1e-12 * np.abs(a["psi"]).max())
+    np.testing.assert_allclose(b["disp_g"], a["disp_g"], rtol=0, atol=1e-9)
+    np.testing.assert_allclose(b["eps"], a["eps"], rtol=1e-10)
+    assert np.abs(a["psi"]).max() > 0.1
+
+
 def test_zero_weight_catalogues_are_refused():
     """delta = (G - alpha R)/(alpha R) needs alpha = W_g/W_r > 0, and G/rho_bar - 1 needs rho_bar > 0
     (Sec. 2, Sec. 3.2): a realisation with no galaxy weight, or no random weight, has no overdensity."""
