@@ -777,6 +777,54 @@ def test_nonfinite_field_reads_as_divergence(gpu_lib, start):
     plan.close()
 
 
+@pytest.mark.parametrize("mask_tau", [0.0, 0.6])
+def test_mask_threshold(gpu_lib, mask_tau):
+    """The survey end to end at other mask thresholds (tau = 0: every cell whose 27-cell window holds
+    random weight, 37,523 cells at 64^3; 0.6: a tighter footprint, 22,691 cells; the default 0.1 gives
+    29,972): grids, mask (through delta), Psi, eps and shifts against the oracle."""
+    from paper_1504_02591_amd import native
+    cat = G.config2(n=64, scale=0.125)
+    plan = native.Plan(cat.n, cat.box_len, cat.observer, cat.bias, cat.growth, cat.smooth_r, origin=cat.origin,
+                       mask_tau=mask_tau, max_objects=cat.ran_pos.shape[0], keep_delta=True)
+    gal, ran = to_dev(cat.gal_pos), to_dev(cat.ran_pos)
+    plan.paint(native.GAL, gal)
+    plan.paint(native.RAN, ran)
+    plan.solve()
+    rc, iters, eps = plan.iterate(3, 0.0)
+    tiles = plan.tile_counts()[0]
+    g = dict(eps=eps[0], psi=plan.psi()[0].cpu().numpy(), grid_g=plan.grid(native.GAL)[0].cpu().numpy(),
+             grid_r=plan.grid(native.RAN)[0].cpu().numpy(), disp_g=plan.shift(native.GAL, gal).cpu().numpy(),
+             disp_r=plan.shift(native.RAN, ran).cpu().numpy(), delta=plan.delta()[0].cpu().numpy())
+    plan.close()
+    r = O.reconstruct(cat.gal_pos, None, cat.ran_pos, None, cat.n, cat.box_len, cat.origin, cat.observer,
+                      cat.bias, cat.growth, cat.smooth_r, mask_tau, n_passes=3)
+    mask = O.survey_mask(r["grid_r"], mask_tau)
+    print(f"tau={mask_tau}: {int(np.count_nonzero(mask))} cells inside the mask, mask tiles {tiles[2]} of "
+          f"{tiles[3]}", flush=True)
+    tw = cat.n * cat.n // tiles[3]                     # z tile: one y row, tw consecutive x
+    assert tiles[2] == int(mask.any(axis=0).reshape(cat.n, -1, tw).any(axis=2).sum())
+    compare_full(g, r, f"tau={mask_tau}")
+
+
+def test_no_smoothing_mean_density(gpu_lib):
+    """R = 0 (S(k) = 1) on the Zel'dovich lattice box without randoms (delta = G/rho_bar - 1 straight
+    from the CIC grid): grid, delta, Psi, eps and the shift against the oracle."""
+    from paper_1504_02591_amd import native
+    cat = G.config3(n=64)
+    plan = native.Plan(cat.n, cat.box_len, cat.observer, cat.bias, cat.growth, 0.0, origin=cat.origin,
+                       randoms=False, max_objects=cat.gal_pos.shape[0], keep_delta=True)
+    gal = to_dev(cat.gal_pos)
+    plan.paint(native.GAL, gal)
+    plan.solve()
+    rc, iters, eps = plan.iterate(3, 0.0)
+    g = dict(eps=eps[0], psi=plan.psi()[0].cpu().numpy(), grid_g=plan.grid(native.GAL)[0].cpu().numpy(),
+             disp_g=plan.shift(native.GAL, gal).cpu().numpy(), delta=plan.delta()[0].cpu().numpy())
+    plan.close()
+    r = O.reconstruct(cat.gal_pos, None, None, None, cat.n, cat.box_len, cat.origin, cat.observer, cat.bias,
+                      cat.growth, 0.0, cat.mask_tau, n_passes=3)
+    compare_full(g, r, "R=0, mean density")
+
+
 def test_box_origin_offset_matches_oracle(gpu_lib):
     """A survey whose box does not start at the coordinate origin: objects, observer and box origin
     moved by one vector (the translated positions rounded to float32 as a caller would hold them).
