@@ -449,6 +449,27 @@ def test_ngp_deposit_bitexact(gpu_lib, n):
     assert np.array_equal(grid, O.paint_ngp(pos, w, n, box, (0.0, 0.0, 0.0)))
 
 
+def test_ngp_deposit_batched_ragged(gpu_lib):
+    """The NGP deposit over a batch of three realisations with ragged offsets (the middle one empty,
+    the others of different sizes, weighted): each realisation's grid bit for bit, the empty one all
+    zeros."""
+    from paper_1504_02591_amd import native
+    rng = np.random.default_rng(77)
+    n, box = 32, 320.0
+    parts = [(rng.random((5000, 3)) * box).astype(np.float32), np.zeros((0, 3), np.float32),
+             (rng.random((1700, 3)) * 80.0 + 100.0).astype(np.float32)]
+    ws = [(rng.random(p.shape[0]) * 3).astype(np.float32) for p in parts]
+    pos, w = np.concatenate(parts), np.concatenate(ws)
+    off = np.cumsum([0] + [p.shape[0] for p in parts]).astype(np.int64)
+    plan = native.Plan(n, box, (160.0, 160.0, 160.0), 1.0, 0.5, 10.0, batch=3, randoms=False)
+    plan.paint(native.GAL, to_dev(pos), to_dev(w), offsets=to_dev(off), ngp=True)
+    grids = plan.grid(native.GAL).cpu().numpy()
+    plan.close()
+    for i, (p, wi) in enumerate(zip(parts, ws)):
+        assert np.array_equal(grids[i], O.paint_ngp(p, wi, n, box, (0.0, 0.0, 0.0))), f"realisation {i}"
+    assert not grids[1].any() and grids[0].any() and grids[2].any()
+
+
 def test_ngp_reconstruction_matches_oracle(gpu_lib):
     from paper_1504_02591_amd import native
     cat = G.lattice_box(32, 500.0, (-500.0, 250.0, 250.0), 0.7, 27, 28, ran_factor=3, bias=1.2, smooth_r=20.0)
@@ -565,6 +586,7 @@ def test_shift_in_brick_order_equals_direct_shift(gpu_lib, last, n):
               f"sorted {d_sorted[idx].cpu().numpy()} direct {d_direct[idx].cpu().numpy()}", flush=True)
     assert torch.equal(d_sorted, d_direct)
     assert torch.equal(p_sorted, p_direct)
+    assert torch.equal(p_sorted, pos + d_sorted)     # the shifted position is fl32(x + d)
     r = oracle_catalogue_run(cat, 3)
     ref = r["disp_g"] if which == native.GAL else r["disp_r"]
     assert float(np.abs(d_sorted.cpu().numpy() - ref).max()) <= DISP_TOL
