@@ -1147,7 +1147,7 @@ int recon_paint(recon_plan_t* pl, int which, const float* pos, const float* w, i
     const long long nb = pl->L.nbins;
     RECON_TRY(launch_fill_u64(pl, pl->bcount, (nb + 2) / 2));
     const long long nbs = (pl->n + kBrick - 1) / kBrick;
-    const bool lds_bins = nbs * nbs * nbs <= kLdsBins;
+    const bool lds_bins = RECON_BIN_WINDOW || nbs * nbs * nbs <= kLdsBins;   // windows above 512^3
     long long lblocks = (n + 16383) / 16384;
     if (lblocks > RECON_BIN_BLOCKS) lblocks = RECON_BIN_BLOCKS;
     const long long chunk = (n + lblocks - 1) / lblocks;

@@ -330,6 +330,27 @@ __global__ void __launch_bounds__(256) k_bin_scatter(const float* __restrict__ p
 // lies outside that window (a chunk crossing realisations) use a direct global atomic.
 // The block's histogram is also stored in bhist[block][bin] (when not null), so that the scatter,
 // which splits the catalogue into the same chunks, need not count again.
+// First brick key of the LDS window of the binning block that takes objects [lo, ...): the block's
+// realisation when all of its bricks fit (every size up to 512^3); above that, kLdsBins bricks centred
+// on the brick of the chunk's first object, inside its realisation, so that a catalogue stored in
+// spatial order (a lattice formed plane by plane) keeps each block's objects in its window.  Objects
+// outside the window go to global atomics; the count and the scatter take the same window.
+__device__ __forceinline__ long long bin_window(const float* __restrict__ pos, long long lo,
+                                                const long long* __restrict__ off, int batch, const CicGeo& g) {
+  const int nbs = (g.n + kBrick - 1) / kBrick;
+  const long long per = (long long)nbs * nbs * nbs;
+  const int b = off ? find_realisation(off, batch, lo) : 0;
+  const long long rb = (long long)b * per;
+  if (per <= kLdsBins) return rb;
+  int ii[3];
+  unsigned long long tau[3];
+  if (!cic_locate(pos[3 * lo], pos[3 * lo + 1], pos[3 * lo + 2], 1.0f, g, ii, tau)) return rb;
+  long long base = brick_key(ii, g.n, b) - kLdsBins / 2;
+  if (base < rb) base = rb;
+  if (base > rb + per - kLdsBins) base = rb + per - kLdsBins;
+  return base;
+}
+
 template <int NT>
 __global__ void __launch_bounds__(NT) k_bin_count_lds(const float* __restrict__ pos, const float* __restrict__ w,
                                                        long long n, long long chunk,
@@ -342,7 +363,7 @@ __global__ void __launch_bounds__(NT) k_bin_count_lds(const float* __restrict__ 
   const long long hi = lo + chunk < n ? lo + chunk : n;
   const int nbs = (g.n + kBrick - 1) / kBrick;
   const long long per = (long long)nbs * nbs * nbs;
-  const long long base = (off ? (long long)find_realisation(off, batch, lo) : 0LL) * per;
+  const long long base = bin_window(pos, lo, off, batch, g);
   for (int i = threadIdx.x; i < kLdsBins; i += NT) hist[i] = 0u;
   __syncthreads();
   constexpr int U = kObjBatch;
@@ -390,7 +411,7 @@ __global__ void __launch_bounds__(NT) k_bin_scatter_lds(const float* __restrict_
   const long long hi = lo + chunk < n ? lo + chunk : n;
   const int nbs = (g.n + kBrick - 1) / kBrick;
   const long long per = (long long)nbs * nbs * nbs;
-  const long long base = (off ? (long long)find_realisation(off, batch, lo) : 0LL) * per;
+  const long long base = bin_window(pos, lo, off, batch, g);
   const long long nb_total = per * batch;
   if (bhist) {
     // the count kernel's histogram of this very chunk
